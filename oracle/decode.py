@@ -1,0 +1,80 @@
+"""Anchor -> neural Gaussian decoding (Sec. 3.3, Eq. 8 and Eq. 9).
+
+Test infrastructure (see the package docstring).
+
+Each anchor v carries a position x_v, a 32-d feature f_v and k offsets O_vi.
+Its k Gaussians are decoded by five separate two-layer MLPs (opacity, colour,
+scale, rotation, low-dimensional feature), each fed with the anchor feature
+and the unit direction from the camera centre to the anchor (Eq. 8). The
+feature decoder F_d is Linear -> SoftPlus -> Linear with a 32-wide hidden
+layer (appendix, MLP details); the other four use ReLU as in Scaffold-GS.
+"""
+from __future__ import annotations
+
+from typing import Dict
+
+import torch
+import torch.nn.functional as F
+
+F64 = torch.float64
+
+# (head name, values per Gaussian, hidden activation)
+HEAD_ORDER = (
+    ("opacity", 1, "relu"),
+    ("rgb", 3, "relu"),
+    ("scale", 3, "relu"),
+    ("rot", 4, "relu"),
+    ("feat", 16, "softplus"),
+)
+
+
+def _bf16(x: torch.Tensor) -> torch.Tensor:
+    """Round to bfloat16 (nearest-even, via float32) and return as float64."""
+    return x.to(torch.float32).to(torch.bfloat16).to(F64)
+
+
+def decode(xyz: torch.Tensor, feat: torch.Tensor, off: torch.Tensor,
+           weights: Dict[str, Dict[str, torch.Tensor]], cam_center: torch.Tensor,
+           k: int, l_o: float = 1.0, l_s: float = 0.02, precision: str = "fp64"):
+    """Decode anchors into Gaussians.
+
+    xyz (A,3), feat (A,32), off (A*k,3) row n = v*k+i; weights[head] =
+    {W1 (32,35), b1 (32), W2 (k*m,32), b2 (k*m)}; cam_center (3,).
+    precision 'bf16' rounds the feature-part operands of layer 1 and both
+    operands of layer 2 to bfloat16 (what the matrix-core variant feeds its
+    MFMAs); sums, biases, the view-direction part and activations stay exact.
+
+    Returns dict of (N, c) float64 tensors: mean, scale, rot, opacity (N,),
+    rgb, [feat].
+    """
+    A = xyz.shape[0]
+    D = xyz - cam_center[None, :]
+    dist = torch.linalg.norm(D, dim=1, keepdim=True)
+    delta = D / dist
+    out = {}
+    for name, m, act in HEAD_ORDER:
+        if name not in weights:
+            continue
+        w = weights[name]
+        W1, b1, W2, b2 = w["W1"], w["b1"], w["W2"], w["b2"]
+        nf = feat.shape[1]
+        if precision == "bf16":
+            Z = _bf16(feat) @ _bf16(W1[:, :nf]).T + delta @ W1[:, nf:].T + b1
+        else:
+            Z = torch.cat([feat, delta], 1) @ W1.T + b1
+        H = torch.relu(Z) if act == "relu" else F.softplus(Z, beta=1.0, threshold=1e9)
+        if precision == "bf16":
+            Y = _bf16(H) @ _bf16(W2).T + b2
+        else:
+            Y = H @ W2.T + b2
+        mh = W2.shape[0] // k
+        out[name] = Y.reshape(A * k, mh)
+    g = {}
+    g["mean"] = xyz.repeat_interleave(k, dim=0) + l_o * off
+    g["opacity"] = torch.sigmoid(out["opacity"][:, 0])
+    g["rgb"] = torch.sigmoid(out["rgb"])
+    g["scale"] = l_s * torch.sigmoid(out["scale"])
+    g["rot"] = out["rot"]
+    if "feat" in out:
+        g["feat"] = out["feat"]
+    return g

@@ -1,0 +1,48 @@
+"""Render options and the readings taken where the paper is silent.
+
+Test infrastructure (see the package docstring).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Tuple
+
+
+@dataclass
+class RenderOpts:
+    tile: int = 16                 # square screen tiles (pixels per side)
+    n_feat: int = 16               # low-dimensional feature channels N_l (0 = none)
+    alpha_min: float = 1.0 / 255.0  # a Gaussian with alpha below this is skipped
+    alpha_max: float = 0.99         # alpha is clamped to at most this
+    T_min: float = 1e-4             # compositing stops before T would fall below this
+    dilation: float = 0.3           # added to the 2D covariance diagonal (px^2)
+    znear: float = 0.2              # camera-space depth below which a Gaussian is culled
+    fov_clamp: float = 1.3          # Jacobian evaluated with x/z clamped to +-fov_clamp*W/(2 fx); 0 = off
+    bg: Tuple[float, float, float] = field(default=(0.0, 0.0, 0.0))
+
+
+# Each reading: where the paper is silent, ambiguous or garbled, and what is taken.
+READINGS = (
+    "Eq.2 writes the 4x4 pose inverse around a 3x3 covariance: W is read as the rotation of T_wc^-1.",
+    "Eq.3 names the opacity sum 'accumulated transmittance'; the rendered 'alpha' is that sum, "
+    "sum_i sigma_i prod_{j<i}(1-sigma_j), which equals 1 - T_final.",
+    "sigma_i of Eq.3 is alpha_i = min(alpha_max, o_i exp(-1/2 d^T Sigma'^-1 d)).",
+    "Unstated constants follow the vanilla 3DGS rasteriser the paper says it follows: alpha_min 1/255, "
+    "alpha_max 0.99, T_min 1e-4, dilation 0.3 px^2, znear 0.2, Jacobian clamp 1.3, 16x16 tiles.",
+    "Termination is exclusive: the Gaussian that would take T below T_min is not composited, and the "
+    "pixel stops there.",
+    "Footprint is the exact axis-aligned box of the ellipse where alpha >= alpha_min, so tiled "
+    "compositing equals per-pixel brute force and does not depend on the tile size.",
+    "Pixel (px, py) is evaluated at the integer point (px, py); cx = (W-1)/2 in the workloads.",
+    "z_i is the camera-space depth of the Gaussian centre; rendered depth is not normalised by alpha; "
+    "background is zero unless bg is set (colour only).",
+    "Gaussians at exactly equal float32 depth in one tile are ordered by ascending index.",
+    "Quaternions are (w, x, y, z), normalised inside the projection; gradients are w.r.t. the raw input.",
+    "Five separate head MLPs in->32->k*m (opacity, colour, scale, rotation with ReLU; feature with "
+    "SoftPlus); outputs: opacity=sigmoid, colour=sigmoid, scale=l_s*sigmoid, rotation raw, feature raw.",
+    "Decoder input is [anchor feature (32), unit view direction (3)] (35 wide); mean = x_v + l_o*O_vi.",
+    "Pose gradient is w.r.t. xi=(rho,phi) under T_cw <- Exp(xi) T_cw and includes the camera-centre "
+    "path through the decoder's view direction.",
+    "A Gaussian is culled when o <= alpha_min (no pixel can reach alpha_min), when t_z <= znear, "
+    "when det(Sigma') <= 0, or when its tile rectangle is empty.",
+)

@@ -1,0 +1,108 @@
+"""Pins for the oracle's anchor decoder (Sec. 3.3, Eq. 8 and Eq. 9).
+
+Special cases with closed forms: zero second layers give act(b2); selector
+first layers expose the input order, the sign of the view direction and the
+hidden activation of each head; means are anchor + scaled offset; the
+bfloat16 mode stays within the rounding bound of its operands.
+"""
+import math
+
+import numpy as np
+import torch
+
+import synth
+from oracle import decode, HEAD_ORDER
+
+F64 = torch.float64
+
+
+def _tens(sc):
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64))
+    w = {h: {k: t(v) for k, v in d.items()} for h, d in sc.weights.items()}
+    return t(sc.xyz.T), t(sc.feat), t(sc.off.T), w
+
+
+def _sig(x):
+    return 1 / (1 + np.exp(-x))
+
+
+def test_zero_second_layer_gives_bias_activations():
+    sc = synth.tiny_anchor_scene(1, 7, k=3, n_feat=5)
+    xyz, feat, off, w = _tens(sc)
+    for h in w:
+        w[h]["W2"] = torch.zeros_like(w[h]["W2"])
+    g = decode(xyz, feat, off, w, torch.tensor([0.1, -0.2, 0.3], dtype=F64), sc.k, sc.l_o, sc.l_s)
+    k = sc.k
+    b = {h: sc.weights[h]["b2"].astype(np.float64).reshape(k, -1) for h in sc.weights}
+    A = sc.n_anchors
+    np.testing.assert_allclose(g["opacity"].numpy(), np.tile(_sig(b["opacity"][:, 0]), A), rtol=1e-12)
+    np.testing.assert_allclose(g["rgb"].numpy(), np.tile(_sig(b["rgb"]), (A, 1)), rtol=1e-12)
+    np.testing.assert_allclose(g["scale"].numpy(), np.tile(sc.l_s * _sig(b["scale"]), (A, 1)), rtol=1e-12)
+    np.testing.assert_allclose(g["rot"].numpy(), np.tile(b["rot"], (A, 1)), rtol=1e-12)
+    np.testing.assert_allclose(g["feat"].numpy(), np.tile(b["feat"], (A, 1)), rtol=1e-12)
+    np.testing.assert_allclose(g["mean"].numpy(),
+                               np.repeat(sc.xyz.T.astype(np.float64), k, 0) + sc.l_o * sc.off.T, rtol=1e-12)
+
+
+def test_selector_weights_expose_direction_and_activation():
+    """First layer picks input column j (a feature, or a direction component);
+    second layer averages the hidden units. Opacity = sigmoid(act(x_j) + b).
+    The camera sits at the origin so the direction of anchor v is x_v/|x_v|."""
+    k = 2
+    xyz = torch.tensor([[3.0, 0.0, 0.0], [-2.0, 0.0, 0.0], [0.0, 0.0, 5.0]], dtype=F64)
+    feat = torch.zeros((3, 32), dtype=F64)
+    feat[:, 7] = torch.tensor([0.4, -0.9, 1.3])
+    off = torch.zeros((3 * k, 3), dtype=F64)
+    cases = [(32, "opacity"), (34, "opacity"), (7, "opacity"), (32, "feat"), (7, "feat")]
+    for col, head in cases:
+        w = {}
+        for name, m, _ in HEAD_ORDER:
+            mm = 2 if name == "feat" else m
+            W1 = torch.zeros((32, 35), dtype=F64)
+            W1[:, col] = 1.0
+            w[name] = dict(W1=W1, b1=torch.zeros(32, dtype=F64),
+                           W2=torch.full((k * mm, 32), 1.0 / 32, dtype=F64),
+                           b2=torch.full((k * mm,), 0.25, dtype=F64))
+        g = decode(xyz, feat, off, w, torch.zeros(3, dtype=F64), k)
+        if col >= 32:
+            x = (xyz / xyz.norm(dim=1, keepdim=True))[:, col - 32].numpy()
+        else:
+            x = feat[:, col].numpy()
+        relu = np.maximum(x, 0)
+        softplus = np.log1p(np.exp(x))
+        if head == "opacity":
+            np.testing.assert_allclose(g["opacity"].numpy(), np.repeat(_sig(relu + 0.25), k), rtol=1e-12)
+        else:
+            np.testing.assert_allclose(g["feat"].numpy(), np.repeat(softplus + 0.25, k)[:, None]
+                                       * np.ones((1, 2)), rtol=1e-12)
+
+
+def test_view_direction_follows_camera_centre():
+    """Moving the camera along +x by 10 m flips the x direction of an anchor
+    at the origin: a ReLU selector on direction-x then passes 0 instead of 1."""
+    k = 1
+    xyz = torch.zeros((1, 3), dtype=F64)
+    feat = torch.zeros((1, 32), dtype=F64)
+    off = torch.zeros((1, 3), dtype=F64)
+    w = {}
+    for name, m, _ in HEAD_ORDER[:4]:
+        W1 = torch.zeros((32, 35), dtype=F64)
+        W1[:, 32] = 1.0
+        w[name] = dict(W1=W1, b1=torch.zeros(32, dtype=F64), W2=torch.full((m, 32), 1 / 32, dtype=F64),
+                       b2=torch.zeros(m, dtype=F64))
+    g_neg = decode(xyz, feat, off, w, torch.tensor([10.0, 0, 0], dtype=F64), k)   # dir = -x
+    g_pos = decode(xyz, feat, off, w, torch.tensor([-10.0, 0, 0], dtype=F64), k)  # dir = +x
+    assert abs(g_neg["opacity"].item() - 0.5) < 1e-15
+    assert abs(g_pos["opacity"].item() - _sig(1.0)) < 1e-15
+
+
+def test_bf16_mode_within_operand_rounding():
+    sc = synth.tiny_anchor_scene(3, 40, k=10, n_feat=16)
+    xyz, feat, off, w = _tens(sc)
+    c = torch.tensor([0.0, 0.0, -0.5], dtype=F64)
+    g64 = decode(xyz, feat, off, w, c, sc.k, sc.l_o, sc.l_s)
+    g16 = decode(xyz, feat, off, w, c, sc.k, sc.l_o, sc.l_s, precision="bf16")
+    for key in ("opacity", "rgb", "scale", "rot", "feat"):
+        d = (g16[key] - g64[key]).abs().max().item()
+        assert 0 < d < 2e-2, (key, d)
+    assert torch.equal(g16["mean"], g64["mean"])
