@@ -1,0 +1,240 @@
+/*
+ * asgs.h - C ABI of libasgs, the MI355X (gfx950) anchor-Gaussian render hot path.
+ *
+ * The library computes, for one or more camera views:
+ *   decode          anchors -> k neural Gaussians each through five two-layer
+ *                   head MLPs (UP-SLAM Sec. 3.3, Eq. 8 and Eq. 9; MLP details
+ *                   in the appendix);
+ *   render_forward  EWA projection of the Gaussians (Sec. 3.1, Eq. 2), tile
+ *                   binning with a device radix sort on (tile, depth) keys, and
+ *                   front-to-back alpha compositing of colour, depth, the opacity
+ *                   sum (Eq. 3) and the low-dimensional feature (Eq. 10);
+ *   render_backward the vector-Jacobian product of render_forward w.r.t. the
+ *                   Gaussian parameters and the SE(3) camera pose;
+ *   decode_backward the vector-Jacobian product of decode w.r.t. anchors, the
+ *                   head-MLP parameters and (through the view direction) the
+ *                   camera pose.
+ *
+ * Conventions (shared by every call):
+ *  - Every array argument is a DEVICE pointer owned by the caller, except the
+ *    structs themselves, which live in host memory and are read before the
+ *    call returns. The library never allocates or frees device memory: scratch
+ *    and the forward->backward context are caller buffers sized by the
+ *    *_size queries.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL = the null stream) except asgs_render_count and asgs_ctx_status,
+ *    which synchronise that stream to read a device counter.
+ *  - Status: every call returns an asgs_status. Arguments are validated on
+ *    the host before anything is launched, so a failing call launches
+ *    nothing. asgs_last_error() gives a thread-local message for the last
+ *    failing call on the calling thread.
+ *  - Layouts: per-Gaussian attributes are planes [c][n] (structure of
+ *    arrays, n contiguous). Images are planes [c][H][W] per view, views
+ *    packed back to back: view v starts at element (sum of H*W over views
+ *    before v) * c of each output array.
+ *  - Pixel (px, py) is evaluated at the integer point (px, py). Quaternions
+ *    are (w, x, y, z), normalised inside the projection. T_wc is the 3x4
+ *    row-major camera-to-world pose; the world-to-camera rotation is taken as
+ *    the transpose of its rotation block.
+ *  - Pose gradients are w.r.t. the twist xi = (rho, phi) of the left
+ *    perturbation T_cw <- Exp(xi) T_cw, T_cw = T_wc^-1, evaluated at xi = 0.
+ */
+#ifndef ASGS_H
+#define ASGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASGS_ABI_VERSION 1
+#define ASGS_MAX_VIEWS 64      /* views per call */
+#define ASGS_MAX_K 16          /* Gaussians per anchor */
+
+typedef enum asgs_status {
+  ASGS_OK = 0,
+  ASGS_E_INVALID = 1,      /* null pointer, bad size, misaligned (< 16 B) array, non-finite pose */
+  ASGS_E_WORKSPACE = 2,    /* caller buffer too small; the message states the bytes needed */
+  ASGS_E_CAPACITY = 3,     /* more tile/Gaussian intersections than the context holds */
+  ASGS_E_DEVICE = 4,       /* a HIP runtime error; the message holds hipGetErrorString */
+  ASGS_E_UNSUPPORTED = 5   /* valid but not built: n_feat not 0/16, tile != 16, k > 16 ... */
+} asgs_status;
+
+int asgs_abi_version(void);
+const char* asgs_status_string(int status);
+/* Thread-local message of the last failing call on this thread (never NULL). */
+const char* asgs_last_error(void);
+
+/* Pinhole camera, one per view. */
+typedef struct asgs_camera {
+  int32_t width, height;   /* pixels, 1..16384 each */
+  float fx, fy, cx, cy;    /* focal lengths and principal point, pixels */
+  float T_wc[12];          /* row-major 3x4 camera-to-world pose (Sec. 3.1) */
+} asgs_camera;
+
+/* Rasteriser constants. asgs_render_opts_default fills the values the paper's
+ * vanilla-3DGS framework uses (Sec. 3.1). */
+typedef struct asgs_render_opts {
+  int32_t tile;            /* screen tile side in pixels; must be 16 */
+  int32_t n_feat;          /* low-dimensional feature channels N_l: 0 or 16 */
+  float alpha_min;         /* 1/255: alpha below this is skipped */
+  float alpha_max;         /* 0.99: alpha is clamped to this */
+  float T_min;             /* 1e-4: stop before transmittance falls below this */
+  float dilation;          /* 0.3 px^2 added to the 2D covariance diagonal */
+  float znear;             /* 0.2: cull Gaussians with camera depth <= znear */
+  float fov_clamp;         /* 1.3: Jacobian x/z clamp, in units of W/(2 fx); 0 = off */
+  float bg[3];             /* background colour (colour channels only) */
+  int32_t reserved;        /* must be 0 */
+} asgs_render_opts;
+
+void asgs_render_opts_default(asgs_render_opts* opts);
+
+/* Gaussians of every view of a call. Field f of view v is at
+ * ptr_f + v * view_stride[f] (elements); stride 0 shares one array across
+ * views (e.g. the means, which do not depend on the view). Field order of
+ * view_stride: mean, scale, rot, opacity, rgb, feat. */
+typedef struct asgs_gaussians {
+  int64_t n;               /* Gaussians per view, 1 .. 2^26 */
+  float* mean;             /* [3][n] world position */
+  float* scale;            /* [3][n] linear scale (s of Sigma = R S S^T R^T) */
+  float* rot;              /* [4][n] quaternion (w,x,y,z), any norm > 0 */
+  float* opacity;          /* [n]    opacity in (0, 1) */
+  float* rgb;              /* [3][n] colour */
+  float* feat;             /* [n_feat][n] low-dimensional feature, NULL if n_feat == 0 */
+  int64_t view_stride[6];
+} asgs_gaussians;
+
+/* Rendered maps of all views, packed (see Layouts above). */
+typedef struct asgs_images {
+  float* rgb;              /* [3][H][W] colour + T_final * bg */
+  float* depth;            /* [H][W] sum of w_i z_i, z = camera depth (not normalised) */
+  float* feat;             /* [n_feat][H][W], NULL if n_feat == 0 */
+  float* alpha;            /* [H][W] opacity sum of Eq. 3 = 1 - T_final */
+} asgs_images;
+
+/* ---------------------------------------------------------------------------
+ * Rendering
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of a render context for n_views cameras, n_gauss Gaussians per view
+ * and at most `capacity` tile/Gaussian intersections (all views together).
+ * Pure host arithmetic. */
+int asgs_render_ctx_size(const asgs_camera* cams, int32_t n_views, int64_t n_gauss,
+                         const asgs_render_opts* opts, int64_t capacity, size_t* bytes);
+
+/* Runs the projection of all views into `ctx` and returns the exact number of
+ * tile/Gaussian intersections in *n_isect (the value to size a context for).
+ * Synchronises `stream`. The context needs capacity >= 0 for this call. */
+int asgs_render_count(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                      const asgs_render_opts* opts, void* ctx, size_t ctx_bytes,
+                      int64_t* n_isect, void* stream);
+
+/* Forward render of n_views views (Eq. 2, Eq. 3, Eq. 10) into `out`.
+ * `ctx` (asgs_render_ctx_size bytes, 256-byte aligned) receives everything
+ * render_backward needs and stays valid until the caller reuses it. If the
+ * intersections exceed the context's capacity, the excess is dropped, the
+ * context records the overflow (asgs_ctx_status) and the images are
+ * incomplete; the call itself cannot see this without a synchronisation. */
+int asgs_render_forward(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                        const asgs_render_opts* opts, const asgs_images* out,
+                        void* ctx, size_t ctx_bytes, void* stream);
+
+/* Backward of render_forward for the same cams, g, opts and ctx. d_out holds
+ * dL/d(outputs) in the output layout (d_out->alpha may be NULL = zero; feat
+ * must be given when n_feat > 0). d_g receives dL/d(every field of g),
+ * overwritten, with the same view strides as g except that a stride of 0 is
+ * not allowed (each view gets its own gradient). d_pose, if not NULL,
+ * receives [n_views][6] dL/d(rho, phi), overwritten. */
+int asgs_render_backward(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                         const asgs_render_opts* opts, const asgs_images* d_out,
+                         const asgs_gaussians* d_g, float* d_pose, void* ctx,
+                         size_t ctx_bytes, void* stream);
+
+/* Reads the context header: intersections of the last forward/count, number
+ * of visible (view, Gaussian) pairs, and a non-zero overflow flag if the
+ * capacity was exceeded. Synchronises `stream`. */
+int asgs_ctx_status(const void* ctx, void* stream, int64_t* n_isect, int64_t* n_visible,
+                    int32_t* overflow);
+
+/* Internal arrays of a context after render_forward, for inspection:
+ *  ASGS_CTX_PAIR_TILE   uint32[I]   tile key of each sorted intersection
+ *                                   (view tile offset + ty * tiles_x + tx)
+ *  ASGS_CTX_PAIR_GAUSS  uint32[I]   view * n + gaussian of each sorted intersection
+ *  ASGS_CTX_TILE_RANGE  uint32[T][2] [start, end) of each tile key
+ *  ASGS_CTX_RECT        int16[V*n][4] tx0, tx1, ty0, ty1 (empty rect: tx0 > tx1)
+ *  ASGS_CTX_NCONTRIB    uint32[P]   per pixel: list position + 1 of the last
+ *                                   composited Gaussian of its tile
+ *  ASGS_CTX_TFINAL      float[P]    per pixel final transmittance
+ * cams/n_views/n_gauss/opts/ctx_bytes must be those of the forward call.
+ * `*ptr` is a device pointer inside ctx and `*count` its element count
+ * (for the pair arrays: the capacity; read I from asgs_ctx_status). */
+enum {
+  ASGS_CTX_PAIR_TILE = 1,
+  ASGS_CTX_PAIR_GAUSS = 2,
+  ASGS_CTX_TILE_RANGE = 3,
+  ASGS_CTX_RECT = 4,
+  ASGS_CTX_NCONTRIB = 5,
+  ASGS_CTX_TFINAL = 6
+};
+int asgs_ctx_array(const asgs_camera* cams, int32_t n_views, int64_t n_gauss,
+                   const asgs_render_opts* opts, void* ctx, size_t ctx_bytes, int32_t which,
+                   void** ptr, int64_t* count);
+
+/* ---------------------------------------------------------------------------
+ * Anchor decoding (Sec. 3.3, Eq. 8 and Eq. 9)
+ *
+ * Each anchor v has a position x_v, a 32-d feature f_v and k offsets O_vi.
+ * Input X_v = [f_v (32), delta_v (3)], delta_v = (x_v - c)/|x_v - c|, c the
+ * camera centre of the view. Five heads h in the order opacity(m=1),
+ * rgb(3), scale(3), rot(4), feat(n_feat): Y_h = W2_h act_h(W1_h X + b1_h) + b2_h,
+ * act = ReLU for the first four, SoftPlus for feat; W1_h is [32][35], W2_h is
+ * [k*m_h][32]. Gaussian n = v*k + i gets opacity sigmoid(Y[i]), rgb
+ * sigmoid(Y[3i..]), scale l_s * sigmoid(Y[3i..]), rot Y[4i..], feat
+ * Y[16i..], mean x_v + l_o * O_vi.
+ *
+ * Parameters of all heads live in one float array, per head in the order
+ * above: W1 (32*35, row-major), b1 (32), W2 (k*m*32, row-major), b2 (k*m).
+ * ------------------------------------------------------------------------- */
+
+typedef struct asgs_decoder {
+  int64_t n_anchors;       /* A >= 1 */
+  int32_t k;               /* Gaussians per anchor, 1..16 */
+  int32_t n_feat;          /* 0 or 16 (feature head present when 16) */
+  int32_t precision;       /* 0 = FP32, 1 = BF16 operands on matrix cores, FP32 accumulation */
+  float l_o;               /* offset scale (metres) */
+  float l_s;               /* scale bound (metres) */
+  int32_t reserved;        /* must be 0 */
+} asgs_decoder;
+
+/* Number of floats of the packed head parameters. */
+int asgs_decode_param_count(const asgs_decoder* d, int64_t* count);
+
+/* Decode anchors for n_views cameras. anchor_xyz [3][A], anchor_feat [A][32],
+ * anchor_off [3][A*k]; out->n must be A*k. out view strides apply per view;
+ * the mean field is written for view 0 only (it does not depend on the view)
+ * and must be non-NULL there. */
+int asgs_decode(const asgs_decoder* d, const float* anchor_xyz, const float* anchor_feat,
+                const float* anchor_off, const float* params, const asgs_camera* cams,
+                int32_t n_views, const asgs_gaussians* out, void* stream);
+
+/* Bytes of scratch asgs_decode_backward needs. */
+int asgs_decode_workspace_size(const asgs_decoder* d, int32_t n_views, size_t* bytes);
+
+/* Backward of asgs_decode: d_g holds dL/d(decoded Gaussians) per view (the
+ * mean gradient is summed over views). Writes (overwrites) d_xyz [3][A],
+ * d_feat [A][32], d_off [3][A*k], d_params (packed like params); ADDS the
+ * camera-centre term of the pose gradient to d_pose [n_views][6] if not
+ * NULL (render_backward writes the rest of it). */
+int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const float* anchor_feat,
+                         const float* anchor_off, const float* params, const asgs_camera* cams,
+                         int32_t n_views, const asgs_gaussians* d_g, float* d_xyz, float* d_feat,
+                         float* d_off, float* d_params, float* d_pose, void* work,
+                         size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASGS_H */

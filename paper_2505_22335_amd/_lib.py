@@ -1,0 +1,252 @@
+"""ctypes binding of libasgs (include/asgs.h): argument marshalling only.
+
+Every array is a torch tensor on the GPU (float32 unless stated); the binding
+passes its data pointer and the current HIP stream and checks the returned
+status. If the library is missing this module raises on import: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Dict, Optional, Sequence
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libasgs.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "asgs.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libasgs.so not built at {LIB_PATH}: run python -m paper_2505_22335_amd.build")
+lib = C.CDLL(LIB_PATH)
+
+OK, E_INVALID, E_WORKSPACE, E_CAPACITY, E_DEVICE, E_UNSUPPORTED = range(6)
+MAX_VIEWS = 64
+CTX_PAIR_TILE, CTX_PAIR_GAUSS, CTX_TILE_RANGE, CTX_RECT, CTX_NCONTRIB, CTX_TFINAL = range(1, 7)
+
+
+class AsgsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib.asgs_last_error().decode()
+        super().__init__(f"{where}: {lib.asgs_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("T_wc", C.c_float * 12)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("n_feat", C.c_int32), ("alpha_min", C.c_float),
+                ("alpha_max", C.c_float), ("T_min", C.c_float), ("dilation", C.c_float),
+                ("znear", C.c_float), ("fov_clamp", C.c_float), ("bg", C.c_float * 3),
+                ("reserved", C.c_int32)]
+
+
+class Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("scale", C.c_void_p), ("rot", C.c_void_p),
+                ("opacity", C.c_void_p), ("rgb", C.c_void_p), ("feat", C.c_void_p),
+                ("view_stride", C.c_int64 * 6)]
+
+
+class Images(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("feat", C.c_void_p), ("alpha", C.c_void_p)]
+
+
+class Decoder(C.Structure):
+    _fields_ = [("n_anchors", C.c_int64), ("k", C.c_int32), ("n_feat", C.c_int32),
+                ("precision", C.c_int32), ("l_o", C.c_float), ("l_s", C.c_float),
+                ("reserved", C.c_int32)]
+
+
+P = C.c_void_p
+_sigs = {
+    "asgs_abi_version": (C.c_int, []),
+    "asgs_status_string": (C.c_char_p, [C.c_int]),
+    "asgs_last_error": (C.c_char_p, []),
+    "asgs_render_opts_default": (None, [C.POINTER(RenderOpts)]),
+    "asgs_render_ctx_size": (C.c_int, [C.POINTER(Camera), C.c_int32, C.c_int64, C.POINTER(RenderOpts),
+                                       C.c_int64, C.POINTER(C.c_size_t)]),
+    "asgs_render_count": (C.c_int, [C.POINTER(Camera), C.c_int32, C.POINTER(Gaussians), C.POINTER(RenderOpts),
+                                    P, C.c_size_t, C.POINTER(C.c_int64), P]),
+    "asgs_render_forward": (C.c_int, [C.POINTER(Camera), C.c_int32, C.POINTER(Gaussians),
+                                      C.POINTER(RenderOpts), C.POINTER(Images), P, C.c_size_t, P]),
+    "asgs_render_backward": (C.c_int, [C.POINTER(Camera), C.c_int32, C.POINTER(Gaussians),
+                                       C.POINTER(RenderOpts), C.POINTER(Images), C.POINTER(Gaussians), P, P,
+                                       C.c_size_t, P]),
+    "asgs_ctx_status": (C.c_int, [P, P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "asgs_ctx_array": (C.c_int, [C.POINTER(Camera), C.c_int32, C.c_int64, C.POINTER(RenderOpts), P,
+                                 C.c_size_t, C.c_int32, C.POINTER(P), C.POINTER(C.c_int64)]),
+    "asgs_decode_param_count": (C.c_int, [C.POINTER(Decoder), C.POINTER(C.c_int64)]),
+    "asgs_decode": (C.c_int, [C.POINTER(Decoder), P, P, P, P, C.POINTER(Camera), C.c_int32,
+                              C.POINTER(Gaussians), P]),
+    "asgs_decode_workspace_size": (C.c_int, [C.POINTER(Decoder), C.c_int32, C.POINTER(C.c_size_t)]),
+    "asgs_decode_backward": (C.c_int, [C.POINTER(Decoder), P, P, P, P, C.POINTER(Camera), C.c_int32,
+                                       C.POINTER(Gaussians), P, P, P, P, P, P, C.c_size_t, P]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def declared_functions() -> list:
+    """Function names declared in include/asgs.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(asgs_[a-z_0-9]+)\s*\(", txt)))
+
+
+def check(status: int, where: str):
+    if status != OK:
+        raise AsgsError(status, where)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# Struct builders
+# ---------------------------------------------------------------------------
+
+def make_cameras(cams: Sequence) -> "C.Array":
+    """Objects with width, height, fx, fy, cx, cy, T_wc (3x4) -> Camera[]."""
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].width, arr[i].height = int(c.width), int(c.height)
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        T = [float(x) for row in c.T_wc for x in row]
+        for k in range(12):
+            arr[i].T_wc[k] = T[k]
+    return arr
+
+
+def make_opts(n_feat: int = 16, **kw) -> RenderOpts:
+    o = RenderOpts()
+    lib.asgs_render_opts_default(C.byref(o))
+    o.n_feat = n_feat
+    for k, v in kw.items():
+        if k == "bg":
+            for i in range(3):
+                o.bg[i] = float(v[i])
+        else:
+            setattr(o, k, v)
+    return o
+
+
+FIELDS = ("mean", "scale", "rot", "opacity", "rgb", "feat")
+
+
+def make_gaussians(g: Dict[str, "object"], n: int) -> Gaussians:
+    """g maps field -> tensor of shape [c][n] (one view) or [V][c][n] (per
+    view). A 2D/1D tensor is shared by every view (stride 0)."""
+    s = Gaussians()
+    s.n = n
+    for i, f in enumerate(FIELDS):
+        t = g.get(f)
+        if t is None:
+            setattr(s, f, None)
+            s.view_stride[i] = 0
+            continue
+        per_view = (t.dim() == 3) or (f == "opacity" and t.dim() == 2)
+        setattr(s, f, t.data_ptr())
+        s.view_stride[i] = t[0].numel() if per_view else 0
+    return s
+
+
+def make_images(img: Dict[str, "object"]) -> Images:
+    s = Images()
+    s.rgb, s.depth, s.feat, s.alpha = (_ptr(img.get(k)) for k in ("rgb", "depth", "feat", "alpha"))
+    return s
+
+
+# ---------------------------------------------------------------------------
+# Calls
+# ---------------------------------------------------------------------------
+
+def render_ctx_size(cams, n_gauss: int, opts: RenderOpts, capacity: int) -> int:
+    b = C.c_size_t()
+    ca = make_cameras(cams)
+    check(lib.asgs_render_ctx_size(ca, len(cams), n_gauss, C.byref(opts), capacity, C.byref(b)),
+          "asgs_render_ctx_size")
+    return b.value
+
+
+def render_count(cams, g: Gaussians, opts: RenderOpts, ctx, stream=None) -> int:
+    n = C.c_int64()
+    ca = make_cameras(cams)
+    check(lib.asgs_render_count(ca, len(cams), C.byref(g), C.byref(opts), ctx.data_ptr(), ctx.numel(),
+                                C.byref(n), _stream(stream)), "asgs_render_count")
+    return n.value
+
+
+def render_forward(cams, g: Gaussians, opts: RenderOpts, out: Images, ctx, stream=None):
+    ca = make_cameras(cams)
+    check(lib.asgs_render_forward(ca, len(cams), C.byref(g), C.byref(opts), C.byref(out), ctx.data_ptr(),
+                                  ctx.numel(), _stream(stream)), "asgs_render_forward")
+
+
+def render_backward(cams, g: Gaussians, opts: RenderOpts, dout: Images, dg: Gaussians, d_pose, ctx,
+                    stream=None):
+    ca = make_cameras(cams)
+    check(lib.asgs_render_backward(ca, len(cams), C.byref(g), C.byref(opts), C.byref(dout), C.byref(dg),
+                                   _ptr(d_pose), ctx.data_ptr(), ctx.numel(), _stream(stream)),
+          "asgs_render_backward")
+
+
+def ctx_status(ctx, stream=None):
+    ni, nv, ov = C.c_int64(), C.c_int64(), C.c_int32()
+    check(lib.asgs_ctx_status(ctx.data_ptr(), _stream(stream), C.byref(ni), C.byref(nv), C.byref(ov)),
+          "asgs_ctx_status")
+    return ni.value, nv.value, ov.value
+
+
+def ctx_array(cams, n_gauss: int, opts: RenderOpts, ctx, which: int):
+    p, n = C.c_void_p(), C.c_int64()
+    ca = make_cameras(cams)
+    check(lib.asgs_ctx_array(ca, len(cams), n_gauss, C.byref(opts), ctx.data_ptr(), ctx.numel(), which,
+                             C.byref(p), C.byref(n)), "asgs_ctx_array")
+    return p.value, n.value
+
+
+def make_decoder(n_anchors: int, k: int, n_feat: int = 16, precision: int = 0, l_o: float = 1.0,
+                 l_s: float = 0.02) -> Decoder:
+    d = Decoder()
+    d.n_anchors, d.k, d.n_feat, d.precision, d.l_o, d.l_s, d.reserved = n_anchors, k, n_feat, precision, l_o, l_s, 0
+    return d
+
+
+def decode_param_count(d: Decoder) -> int:
+    n = C.c_int64()
+    check(lib.asgs_decode_param_count(C.byref(d), C.byref(n)), "asgs_decode_param_count")
+    return n.value
+
+
+def decode_workspace_size(d: Decoder, n_views: int) -> int:
+    b = C.c_size_t()
+    check(lib.asgs_decode_workspace_size(C.byref(d), n_views, C.byref(b)), "asgs_decode_workspace_size")
+    return b.value
+
+
+def decode(d: Decoder, xyz, feat, off, params, cams, out: Gaussians, stream=None):
+    ca = make_cameras(cams)
+    check(lib.asgs_decode(C.byref(d), xyz.data_ptr(), feat.data_ptr(), off.data_ptr(), params.data_ptr(), ca,
+                          len(cams), C.byref(out), _stream(stream)), "asgs_decode")
+
+
+def decode_backward(d: Decoder, xyz, feat, off, params, cams, dg: Gaussians, d_xyz, d_feat, d_off, d_params,
+                    d_pose, work, stream=None):
+    ca = make_cameras(cams)
+    check(lib.asgs_decode_backward(C.byref(d), xyz.data_ptr(), feat.data_ptr(), off.data_ptr(),
+                                   params.data_ptr(), ca, len(cams), C.byref(dg), d_xyz.data_ptr(),
+                                   d_feat.data_ptr(), d_off.data_ptr(), d_params.data_ptr(), _ptr(d_pose),
+                                   work.data_ptr(), work.numel(), _stream(stream)), "asgs_decode_backward")

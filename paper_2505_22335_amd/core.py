@@ -1,0 +1,191 @@
+"""Tensor-level wrappers over the C ABI: device buffers, contexts, packing.
+
+Torch is used for device memory and streams only; every step of the path runs
+in libasgs kernels.
+"""
+from __future__ import annotations
+
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+HEADS = (("opacity", 1), ("rgb", 3), ("scale", 3), ("rot", 4), ("feat", 16))
+
+
+def _dev(x, device="cuda"):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float32).contiguous()
+    return torch.as_tensor(x, dtype=torch.float32, device=device).contiguous()
+
+
+def gaussians_to_device(planes: Dict[str, object], device="cuda") -> Dict[str, torch.Tensor]:
+    """[c][n] float arrays (numpy or tensors) -> contiguous float32 device tensors."""
+    return {k: _dev(v, device) for k, v in planes.items() if v is not None}
+
+
+def pack_params(weights: Dict[str, Dict[str, object]], k: int, n_feat: int = 16, device="cuda") -> torch.Tensor:
+    """Head weights {head: {W1, b1, W2, b2}} -> the packed parameter vector of
+    the decoder ABI (per head in order opacity, rgb, scale, rot, feat: W1
+    row-major, b1, W2 row-major, b2)."""
+    parts = []
+    for name, m in HEADS:
+        if name == "feat" and n_feat == 0:
+            continue
+        w = weights[name]
+        for key in ("W1", "b1", "W2", "b2"):
+            parts.append(_dev(w[key], device).reshape(-1))
+    return torch.cat(parts)
+
+
+def unpack_params(flat: torch.Tensor, k: int, n_feat: int = 16) -> Dict[str, Dict[str, torch.Tensor]]:
+    out, o = {}, 0
+    for name, m in HEADS:
+        if name == "feat":
+            if n_feat == 0:
+                continue
+            m = n_feat
+        shapes = dict(W1=(32, 35), b1=(32,), W2=(k * m, 32), b2=(k * m,))
+        out[name] = {}
+        for key in ("W1", "b1", "W2", "b2"):
+            sz = 1
+            for d in shapes[key]:
+                sz *= d
+            out[name][key] = flat[o:o + sz].reshape(shapes[key])
+            o += sz
+    return out
+
+
+class RenderContext:
+    """Caller-owned context of the render path for a fixed set of cameras
+    (one resolution) and Gaussian count. Grows its device buffer when the
+    intersection count needs it."""
+
+    def __init__(self, cams: Sequence, n_gauss: int, n_feat: int = 16, capacity: int = 0,
+                 device="cuda", **opt_kw):
+        self.cams = list(cams)
+        self.V = len(self.cams)
+        self.H, self.W = int(self.cams[0].height), int(self.cams[0].width)
+        for c in self.cams:
+            if int(c.height) != self.H or int(c.width) != self.W:
+                raise ValueError("RenderContext needs one resolution for all views")
+        self.n = int(n_gauss)
+        self.nf = int(n_feat)
+        self.opts = L.make_opts(n_feat, **opt_kw)
+        self.device = device
+        self.ctx = None
+        self.capacity = 0
+        self.ensure(max(int(capacity), 1))
+
+    def set_cameras(self, cams: Sequence):
+        cams = list(cams)
+        if len(cams) != self.V:
+            raise ValueError("number of views is fixed per context")
+        self.cams = cams
+
+    def ensure(self, capacity: int):
+        if capacity <= self.capacity and self.ctx is not None:
+            return
+        nbytes = L.render_ctx_size(self.cams, self.n, self.opts, int(capacity))
+        self.ctx = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.capacity = int(capacity)
+
+    def count(self, g: Dict[str, torch.Tensor]) -> int:
+        return L.render_count(self.cams, L.make_gaussians(g, self.n), self.opts, self.ctx)
+
+    def fit(self, g: Dict[str, torch.Tensor], slack: float = 1.25) -> int:
+        """Size the context for g (one synchronising count pass)."""
+        need = self.count(g)
+        if need > self.capacity:
+            self.ensure(int(need * slack) + 1024)
+        return need
+
+    def new_images(self) -> Dict[str, torch.Tensor]:
+        V, H, W = self.V, self.H, self.W
+        kw = dict(dtype=torch.float32, device=self.device)
+        img = dict(rgb=torch.empty((V, 3, H, W), **kw), depth=torch.empty((V, H, W), **kw),
+                   alpha=torch.empty((V, H, W), **kw))
+        if self.nf:
+            img["feat"] = torch.empty((V, self.nf, H, W), **kw)
+        return img
+
+    def forward(self, g: Dict[str, torch.Tensor], out: Optional[Dict[str, torch.Tensor]] = None):
+        out = out if out is not None else self.new_images()
+        L.render_forward(self.cams, L.make_gaussians(g, self.n), self.opts, L.make_images(out), self.ctx)
+        return out
+
+    def new_grads(self) -> Dict[str, torch.Tensor]:
+        V, n = self.V, self.n
+        kw = dict(dtype=torch.float32, device=self.device)
+        dg = dict(mean=torch.empty((V, 3, n), **kw), scale=torch.empty((V, 3, n), **kw),
+                  rot=torch.empty((V, 4, n), **kw), opacity=torch.empty((V, n), **kw),
+                  rgb=torch.empty((V, 3, n), **kw))
+        if self.nf:
+            dg["feat"] = torch.empty((V, self.nf, n), **kw)
+        return dg
+
+    def backward(self, g: Dict[str, torch.Tensor], dimg: Dict[str, torch.Tensor], pose: bool = True,
+                 dg: Optional[Dict[str, torch.Tensor]] = None):
+        dg = dg if dg is not None else self.new_grads()
+        d_pose = torch.empty((self.V, 6), dtype=torch.float32, device=self.device) if pose else None
+        L.render_backward(self.cams, L.make_gaussians(g, self.n), self.opts, L.make_images(dimg),
+                          L.make_gaussians(dg, self.n), d_pose, self.ctx)
+        return dg, d_pose
+
+    def status(self):
+        return L.ctx_status(self.ctx)
+
+    def array(self, which: int, dtype, count: Optional[int] = None, width: int = 1) -> torch.Tensor:
+        """Copy of an internal context array (see asgs_ctx_array)."""
+        ptr, n = L.ctx_array(self.cams, self.n, self.opts, self.ctx, which)
+        if count is not None:
+            n = count
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        base = self.ctx.data_ptr()
+        off = ptr - base
+        raw = self.ctx[off:off + n * width * itemsize]
+        return raw.view(dtype).reshape(n, width) if width > 1 else raw.view(dtype).clone()
+
+
+class Decoder:
+    """Device-resident decoder parameters plus its workspace."""
+
+    def __init__(self, n_anchors: int, k: int, n_feat: int = 16, precision: int = 0, l_o: float = 1.0,
+                 l_s: float = 0.02, device="cuda"):
+        self.desc = L.make_decoder(n_anchors, k, n_feat, precision, l_o, l_s)
+        self.A, self.k, self.nf = n_anchors, k, n_feat
+        self.n = n_anchors * k
+        self.n_params = L.decode_param_count(self.desc)
+        self.device = device
+        self.work = None
+        self.work_views = 0
+
+    def set_precision(self, precision: int):
+        self.desc.precision = precision
+
+    def decode(self, xyz, feat, off, params, cams, out: Optional[Dict[str, torch.Tensor]] = None):
+        V = len(cams)
+        kw = dict(dtype=torch.float32, device=self.device)
+        if out is None:
+            out = dict(mean=torch.empty((3, self.n), **kw), scale=torch.empty((V, 3, self.n), **kw),
+                       rot=torch.empty((V, 4, self.n), **kw), opacity=torch.empty((V, self.n), **kw),
+                       rgb=torch.empty((V, 3, self.n), **kw))
+            if self.nf:
+                out["feat"] = torch.empty((V, self.nf, self.n), **kw)
+        L.decode(self.desc, xyz, feat, off, params, cams, L.make_gaussians(out, self.n))
+        return out
+
+    def backward(self, xyz, feat, off, params, cams, dg: Dict[str, torch.Tensor], d_pose=None):
+        V = len(cams)
+        need = L.decode_workspace_size(self.desc, V)
+        if self.work is None or self.work.numel() < need:
+            self.work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        kw = dict(dtype=torch.float32, device=self.device)
+        d_xyz = torch.empty((3, self.A), **kw)
+        d_feat = torch.empty((self.A, 32), **kw)
+        d_off = torch.empty((3, self.n), **kw)
+        d_params = torch.empty((self.n_params,), **kw)
+        L.decode_backward(self.desc, xyz, feat, off, params, cams, L.make_gaussians(dg, self.n), d_xyz, d_feat,
+                          d_off, d_params, d_pose, self.work)
+        return d_xyz, d_feat, d_off, d_params

@@ -1,0 +1,492 @@
+// Host side of the libasgs C ABI: argument validation, context layout,
+// launch sequencing and error reporting. Nothing here allocates device memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <initializer_list>
+#include <string>
+
+#include "internal.h"
+
+namespace asgs {
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ASGS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return ASGS_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int check_opts(const asgs_render_opts* o) {
+  if (!o) return fail(ASGS_E_INVALID, "opts is NULL");
+  if (o->tile != kTile) return fail(ASGS_E_UNSUPPORTED, "tile must be %d (got %d)", kTile, o->tile);
+  if (o->n_feat != 0 && o->n_feat != 16)
+    return fail(ASGS_E_UNSUPPORTED, "n_feat must be 0 or 16 (got %d)", o->n_feat);
+  if (!(o->alpha_min > 0.f && o->alpha_min < 1.f) || !(o->alpha_max > o->alpha_min && o->alpha_max < 1.f) ||
+      !(o->T_min > 0.f && o->T_min < 1.f) || !(o->dilation >= 0.f) || !(o->znear > 0.f) ||
+      !(o->fov_clamp >= 0.f) || !isfinite(o->bg[0]) || !isfinite(o->bg[1]) || !isfinite(o->bg[2]))
+    return fail(ASGS_E_INVALID, "render options out of range");
+  if (o->reserved != 0) return fail(ASGS_E_INVALID, "opts.reserved must be 0");
+  return ASGS_OK;
+}
+
+// Validates the cameras and fills the device view table (host copy).
+int make_views(const asgs_camera* cams, int32_t n_views, float fov_clamp, ViewDev* out, int* total_tiles,
+               int* total_pix) {
+  if (!cams) return fail(ASGS_E_INVALID, "cams is NULL");
+  if (n_views < 1 || n_views > ASGS_MAX_VIEWS)
+    return fail(ASGS_E_INVALID, "n_views must be in 1..%d (got %d)", ASGS_MAX_VIEWS, n_views);
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const asgs_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+      return fail(ASGS_E_INVALID, "view %d: size %dx%d out of range", v, c.width, c.height);
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.fx) || !isfinite(c.fy) || !isfinite(c.cx) ||
+        !isfinite(c.cy))
+      return fail(ASGS_E_INVALID, "view %d: bad intrinsics", v);
+    for (int k = 0; k < 12; ++k)
+      if (!isfinite(c.T_wc[k])) return fail(ASGS_E_INVALID, "view %d: non-finite T_wc", v);
+    ViewDev& V = out[v];
+    memset(&V, 0, sizeof(V));
+    double Rwc[9], ctr[3];
+    for (int r = 0; r < 3; ++r) {
+      for (int k = 0; k < 3; ++k) Rwc[r * 3 + k] = c.T_wc[r * 4 + k];
+      ctr[r] = c.T_wc[r * 4 + 3];
+    }
+    for (int r = 0; r < 3; ++r) {
+      double tr = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        V.R[r * 3 + k] = (float)Rwc[k * 3 + r];  // R_cw = R_wc^T
+        tr -= Rwc[k * 3 + r] * ctr[k];
+      }
+      V.t[r] = (float)tr;
+      V.cc[r] = (float)ctr[r];
+    }
+    V.fx = c.fx;
+    V.fy = c.fy;
+    V.cx = c.cx;
+    V.cy = c.cy;
+    V.limx = fov_clamp > 0.f ? (float)((double)fov_clamp * c.width / (2.0 * c.fx)) : 3.0e38f;
+    V.limy = fov_clamp > 0.f ? (float)((double)fov_clamp * c.height / (2.0 * c.fy)) : 3.0e38f;
+    V.W = c.width;
+    V.H = c.height;
+    V.TX = (c.width + kTile - 1) / kTile;
+    V.TY = (c.height + kTile - 1) / kTile;
+    V.tile_base = (int32_t)tiles;
+    V.pix_base = (int32_t)pix;
+    tiles += (int64_t)V.TX * V.TY;
+    pix += (int64_t)c.width * c.height;
+  }
+  if (pix > (int64_t)1 << 30) return fail(ASGS_E_INVALID, "too many pixels in one call");
+  *total_tiles = (int)tiles;
+  *total_pix = (int)pix;
+  return ASGS_OK;
+}
+
+int check_gauss(const asgs_gaussians* g, int nf, int n_views, bool allow_shared, const char* name) {
+  if (!g) return fail(ASGS_E_INVALID, "%s is NULL", name);
+  if (g->n < 1 || g->n > ((int64_t)1 << 26)) return fail(ASGS_E_INVALID, "%s: n out of range", name);
+  float* const ptrs[6] = {g->mean, g->scale, g->rot, g->opacity, g->rgb, g->feat};
+  const char* names[6] = {"mean", "scale", "rot", "opacity", "rgb", "feat"};
+  for (int f = 0; f < 6; ++f) {
+    if (f == 5 && nf == 0) continue;
+    if (!ptrs[f]) return fail(ASGS_E_INVALID, "%s.%s is NULL", name, names[f]);
+    if (!aligned16(ptrs[f])) return fail(ASGS_E_INVALID, "%s.%s not 16-byte aligned", name, names[f]);
+    if (g->view_stride[f] < 0) return fail(ASGS_E_INVALID, "%s.%s: negative view stride", name, names[f]);
+    if (n_views > 1 && g->view_stride[f] == 0 && !allow_shared)
+      return fail(ASGS_E_INVALID, "%s.%s: views may not share a gradient array", name, names[f]);
+  }
+  return ASGS_OK;
+}
+
+struct Prep {
+  ViewDev views[ASGS_MAX_VIEWS];
+  int total_tiles = 0, total_pix = 0;
+  RenderConst rc;
+  CtxLayout L;
+};
+
+int prepare(const asgs_camera* cams, int32_t n_views, int64_t n, const asgs_render_opts* opts,
+            int64_t capacity, Prep& P) {
+  int st = check_opts(opts);
+  if (st) return st;
+  st = make_views(cams, n_views, opts->fov_clamp, P.views, &P.total_tiles, &P.total_pix);
+  if (st) return st;
+  if (n < 1 || n > ((int64_t)1 << 26)) return fail(ASGS_E_INVALID, "n_gauss out of range");
+  if (n * n_views > ((int64_t)1 << 31)) return fail(ASGS_E_INVALID, "too many Gaussians in one call");
+  if (capacity < 0 || capacity > ((int64_t)1 << 31)) return fail(ASGS_E_INVALID, "capacity out of range");
+  RenderConst& rc = P.rc;
+  rc.alpha_min = opts->alpha_min;
+  rc.alpha_max = opts->alpha_max;
+  rc.T_min = opts->T_min;
+  rc.dilation = opts->dilation;
+  rc.znear = opts->znear;
+  for (int c = 0; c < 3; ++c) rc.bg[c] = opts->bg[c];
+  rc.n_views = n_views;
+  rc.nf = opts->n_feat;
+  rc.n = n;
+  rc.nv = n * n_views;
+  rc.total_tiles = P.total_tiles;
+  rc.total_pix = P.total_pix;
+  rc.cap = capacity;
+  P.L = ctx_layout(n, n_views, P.total_tiles, P.total_pix, opts->n_feat, capacity);
+  return ASGS_OK;
+}
+
+int check_ctx(const Prep& P, const void* ctx, size_t ctx_bytes) {
+  if (!ctx) return fail(ASGS_E_INVALID, "ctx is NULL");
+  if ((reinterpret_cast<uintptr_t>(ctx) & 255u) != 0) return fail(ASGS_E_INVALID, "ctx not 256-byte aligned");
+  if (ctx_bytes < P.L.total)
+    return fail(ASGS_E_WORKSPACE, "render context needs %zu bytes (got %zu)", P.L.total, ctx_bytes);
+  return ASGS_OK;
+}
+
+// Projection, depth sort and intersection count (shared by count and forward).
+int run_front(const Prep& P, const asgs_gaussians* g, char* ctx, hipStream_t s) {
+  launch_set_views(P.views, P.rc.n_views, reinterpret_cast<ViewDev*>(ctx + P.L.views),
+                   reinterpret_cast<CtxHeader*>(ctx + P.L.hdr), s);
+  launch_project(P.rc, *g, P.L, ctx, s);
+  launch_depth_sort(P.rc, P.L, ctx, s);
+  launch_duplicate(P.rc, P.L, ctx, s);
+  return check_launch("projection/sort launch");
+}
+
+}  // namespace
+
+int chan_stride(int nf) { return 4 + nf; }
+int gslot_stride(int nf) { return 6 + 4 + nf; }
+
+CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int nf, int64_t cap) {
+  CtxLayout L;
+  memset(&L, 0, sizeof(L));
+  const int64_t nv = n * n_views;
+  const int64_t capc = cap > 0 ? cap : 1;
+  L.nv = nv;
+  L.cap = cap;
+  L.total_tiles = total_tiles;
+  L.total_pix = total_pix;
+  L.cs = chan_stride(nf);
+  L.gs = gslot_stride(nf);
+  const int64_t maxitems = nv > capc ? nv : capc;
+  L.nblk_hist = (int32_t)((maxitems + kSortItems - 1) / kSortItems);
+  int passes = 1;
+  while (passes < 4 && ((int64_t)1 << (8 * passes)) < total_tiles) ++passes;
+  L.tile_passes = passes;
+  L.pose_blocks = (int32_t)((n + 255) / 256);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + (bytes > 0 ? bytes : 1));
+    return at;
+  };
+  L.hdr = take(sizeof(CtxHeader));
+  L.views = take(sizeof(ViewDev) * ASGS_MAX_VIEWS);
+  L.geom = take((size_t)nv * kGeomStride * sizeof(float));
+  L.chan = take((size_t)nv * L.cs * sizeof(float));
+  L.rect = take((size_t)nv * 8);
+  L.ntiles = take((size_t)nv * 4);
+  L.rank = take((size_t)nv * 4);
+  L.dkey0 = take((size_t)nv * 4);
+  L.dkeyA = take((size_t)nv * 4);
+  L.dvalA = take((size_t)nv * 4);
+  L.dkeyB = take((size_t)nv * 4);
+  L.dvalB = take((size_t)nv * 4);
+  L.toff = take((size_t)(nv + 1) * 4);
+  L.bsum = take((size_t)((nv + kScanItems - 1) / kScanItems + 1) * 4);
+  L.pkeyA = take((size_t)capc * 4);
+  L.pvalA = take((size_t)capc * 4);
+  L.pkeyB = take((size_t)capc * 4);
+  L.pvalB = take((size_t)capc * 4);
+  L.dupgid = take((size_t)capc * 4);
+  L.pairgid = take((size_t)capc * 4);
+  L.ranges = take((size_t)total_tiles * 8);
+  L.hist = take((size_t)kRadixBins * L.nblk_hist * 4);
+  L.tfinal = take((size_t)total_pix * 4);
+  L.ncontrib = take((size_t)total_pix * 4);
+  L.gslot = take((size_t)capc * L.gs * sizeof(float));
+  L.posepart = take((size_t)n_views * L.pose_blocks * 6 * sizeof(float));
+  L.total = o;
+  const bool odd = (L.tile_passes % 2) == 1;
+  L.pkey_fin = odd ? L.pkeyB : L.pkeyA;
+  L.pval_fin = odd ? L.pvalB : L.pvalA;
+  return L;
+}
+
+}  // namespace asgs
+
+using namespace asgs;
+
+extern "C" {
+
+int asgs_abi_version(void) { return ASGS_ABI_VERSION; }
+
+const char* asgs_status_string(int status) {
+  switch (status) {
+    case ASGS_OK: return "ok";
+    case ASGS_E_INVALID: return "invalid argument";
+    case ASGS_E_WORKSPACE: return "workspace too small";
+    case ASGS_E_CAPACITY: return "intersection capacity exceeded";
+    case ASGS_E_DEVICE: return "device error";
+    case ASGS_E_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* asgs_last_error(void) { return g_err.c_str(); }
+
+void asgs_render_opts_default(asgs_render_opts* o) {
+  if (!o) return;
+  o->tile = 16;
+  o->n_feat = 16;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->T_min = 1e-4f;
+  o->dilation = 0.3f;
+  o->znear = 0.2f;
+  o->fov_clamp = 1.3f;
+  o->bg[0] = o->bg[1] = o->bg[2] = 0.f;
+  o->reserved = 0;
+}
+
+int asgs_render_ctx_size(const asgs_camera* cams, int32_t n_views, int64_t n_gauss, const asgs_render_opts* opts,
+                         int64_t capacity, size_t* bytes) {
+  if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
+  Prep P;
+  const int st = prepare(cams, n_views, n_gauss, opts, capacity, P);
+  if (st) return st;
+  *bytes = P.L.total;
+  return ASGS_OK;
+}
+
+int asgs_render_count(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                      const asgs_render_opts* opts, void* ctx, size_t ctx_bytes, int64_t* n_isect, void* stream) {
+  if (!n_isect) return fail(ASGS_E_INVALID, "n_isect is NULL");
+  if (!g) return fail(ASGS_E_INVALID, "g is NULL");
+  Prep P;
+  int st = prepare(cams, n_views, g->n, opts, 0, P);
+  if (st) return st;
+  if ((st = check_gauss(g, opts->n_feat, n_views, true, "g"))) return st;
+  if ((st = check_ctx(P, ctx, ctx_bytes))) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* c = static_cast<char*>(ctx);
+  if ((st = run_front(P, g, c, s))) return st;
+  CtxHeader h;
+  hipError_t e = hipMemcpyAsync(&h, c + P.L.hdr, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ASGS_E_DEVICE, "count readback: %s", hipGetErrorString(e));
+  *n_isect = (int64_t)h.n_isect;
+  return ASGS_OK;
+}
+
+int asgs_render_forward(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                        const asgs_render_opts* opts, const asgs_images* out, void* ctx, size_t ctx_bytes,
+                        void* stream) {
+  if (!g) return fail(ASGS_E_INVALID, "g is NULL");
+  if (!out || !out->rgb || !out->depth || !out->alpha || (opts && opts->n_feat > 0 && !out->feat))
+    return fail(ASGS_E_INVALID, "output images missing");
+  Prep P;
+  int st = prepare(cams, n_views, g->n, opts, 0, P);
+  if (st) return st;
+  if ((st = check_gauss(g, opts->n_feat, n_views, true, "g"))) return st;
+  if (!ctx) return fail(ASGS_E_INVALID, "ctx is NULL");
+  // the capacity is whatever the given context bytes hold
+  {
+    const CtxLayout L0 = ctx_layout(g->n, n_views, P.total_tiles, P.total_pix, opts->n_feat, 0);
+    if (ctx_bytes < L0.total)
+      return fail(ASGS_E_WORKSPACE, "render context needs at least %zu bytes (got %zu)", L0.total, ctx_bytes);
+    int64_t lo = 0, hi = (int64_t)1 << 31;
+    while (lo < hi) {  // largest capacity whose layout fits
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (ctx_layout(g->n, n_views, P.total_tiles, P.total_pix, opts->n_feat, mid).total <= ctx_bytes)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    P.rc.cap = lo;
+    P.L = ctx_layout(g->n, n_views, P.total_tiles, P.total_pix, opts->n_feat, lo);
+  }
+  if ((st = check_ctx(P, ctx, ctx_bytes))) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* c = static_cast<char*>(ctx);
+  if ((st = run_front(P, g, c, s))) return st;
+  launch_tile_sort(P.rc, P.L, c, s);
+  launch_blend_forward(P.rc, P.L, c, *out, s);
+  return check_launch("render_forward launch");
+}
+
+int asgs_render_backward(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                         const asgs_render_opts* opts, const asgs_images* d_out, const asgs_gaussians* d_g,
+                         float* d_pose, void* ctx, size_t ctx_bytes, void* stream) {
+  if (!g) return fail(ASGS_E_INVALID, "g is NULL");
+  if (!d_out || !d_out->rgb || !d_out->depth || (opts && opts->n_feat > 0 && !d_out->feat))
+    return fail(ASGS_E_INVALID, "upstream gradients missing");
+  Prep P;
+  int st = prepare(cams, n_views, g->n, opts, 0, P);
+  if (st) return st;
+  if ((st = check_gauss(g, opts->n_feat, n_views, true, "g"))) return st;
+  if ((st = check_gauss(d_g, opts->n_feat, n_views, false, "d_g"))) return st;
+  if (d_g->n != g->n) return fail(ASGS_E_INVALID, "d_g.n != g.n");
+  if (!ctx) return fail(ASGS_E_INVALID, "ctx is NULL");
+  {
+    int64_t lo = 0, hi = (int64_t)1 << 31;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (ctx_layout(g->n, n_views, P.total_tiles, P.total_pix, opts->n_feat, mid).total <= ctx_bytes)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    P.rc.cap = lo;
+    P.L = ctx_layout(g->n, n_views, P.total_tiles, P.total_pix, opts->n_feat, lo);
+  }
+  if ((st = check_ctx(P, ctx, ctx_bytes))) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* c = static_cast<char*>(ctx);
+  launch_blend_backward(P.rc, P.L, c, *d_out, s);
+  launch_project_backward(P.rc, *g, *d_g, d_pose, P.L, c, s);
+  return check_launch("render_backward launch");
+}
+
+int asgs_ctx_status(const void* ctx, void* stream, int64_t* n_isect, int64_t* n_visible, int32_t* overflow) {
+  if (!ctx) return fail(ASGS_E_INVALID, "ctx is NULL");
+  CtxHeader h;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&h, ctx, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ASGS_E_DEVICE, "ctx readback: %s", hipGetErrorString(e));
+  if (n_isect) *n_isect = (int64_t)h.n_isect;
+  if (n_visible) *n_visible = (int64_t)h.n_visible;
+  if (overflow) *overflow = (int32_t)h.overflow;
+  return ASGS_OK;
+}
+
+int asgs_ctx_array(const asgs_camera* cams, int32_t n_views, int64_t n_gauss, const asgs_render_opts* opts,
+                   void* ctx, size_t ctx_bytes, int32_t which, void** ptr, int64_t* count) {
+  if (!ptr || !count) return fail(ASGS_E_INVALID, "ptr/count is NULL");
+  Prep P;
+  int st = prepare(cams, n_views, n_gauss, opts, 0, P);
+  if (st) return st;
+  if (!ctx) return fail(ASGS_E_INVALID, "ctx is NULL");
+  int64_t lo = 0, hi = (int64_t)1 << 31;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (ctx_layout(n_gauss, n_views, P.total_tiles, P.total_pix, opts->n_feat, mid).total <= ctx_bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const CtxLayout L = ctx_layout(n_gauss, n_views, P.total_tiles, P.total_pix, opts->n_feat, lo);
+  if (L.total > ctx_bytes) return fail(ASGS_E_WORKSPACE, "ctx too small");
+  char* c = static_cast<char*>(ctx);
+  switch (which) {
+    case ASGS_CTX_PAIR_TILE: *ptr = c + L.pkey_fin; *count = lo; break;
+    case ASGS_CTX_PAIR_GAUSS: *ptr = c + L.pairgid; *count = lo; break;
+    case ASGS_CTX_TILE_RANGE: *ptr = c + L.ranges; *count = L.total_tiles; break;
+    case ASGS_CTX_RECT: *ptr = c + L.rect; *count = L.nv; break;
+    case ASGS_CTX_NCONTRIB: *ptr = c + L.ncontrib; *count = L.total_pix; break;
+    case ASGS_CTX_TFINAL: *ptr = c + L.tfinal; *count = L.total_pix; break;
+    default: return fail(ASGS_E_INVALID, "unknown context array %d", which);
+  }
+  return ASGS_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+
+static int check_decoder(const asgs_decoder* d) {
+  if (!d) return fail(ASGS_E_INVALID, "decoder is NULL");
+  if (d->n_anchors < 1 || d->n_anchors > ((int64_t)1 << 24)) return fail(ASGS_E_INVALID, "n_anchors out of range");
+  if (d->k < 1 || d->k > ASGS_MAX_K) return fail(ASGS_E_UNSUPPORTED, "k must be in 1..%d", ASGS_MAX_K);
+  if (d->n_feat != 0 && d->n_feat != 16) return fail(ASGS_E_UNSUPPORTED, "n_feat must be 0 or 16");
+  if (d->precision != 0 && d->precision != 1) return fail(ASGS_E_INVALID, "precision must be 0 or 1");
+  if (!isfinite(d->l_o) || !(d->l_s > 0.f) || !isfinite(d->l_s)) return fail(ASGS_E_INVALID, "bad l_o/l_s");
+  if (d->reserved != 0) return fail(ASGS_E_INVALID, "decoder.reserved must be 0");
+  return ASGS_OK;
+}
+
+static int check_ptrs(std::initializer_list<const void*> ps, const char* what) {
+  for (const void* p : ps) {
+    if (!p) return fail(ASGS_E_INVALID, "%s: NULL pointer", what);
+    if (!aligned16(p)) return fail(ASGS_E_INVALID, "%s: pointer not 16-byte aligned", what);
+  }
+  return ASGS_OK;
+}
+
+int asgs_decode_param_count(const asgs_decoder* d, int64_t* count) {
+  int st = check_decoder(d);
+  if (st) return st;
+  if (!count) return fail(ASGS_E_INVALID, "count is NULL");
+  *count = decode_const(*d, 1).n_params;
+  return ASGS_OK;
+}
+
+int asgs_decode_workspace_size(const asgs_decoder* d, int32_t n_views, size_t* bytes) {
+  int st = check_decoder(d);
+  if (st) return st;
+  if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
+  if (n_views < 1 || n_views > ASGS_MAX_VIEWS) return fail(ASGS_E_INVALID, "n_views out of range");
+  *bytes = decode_workspace_bytes(decode_const(*d, n_views));
+  return ASGS_OK;
+}
+
+static int decode_common(const asgs_decoder* d, const float* xyz, const float* feat, const float* off,
+                         const float* params, const asgs_camera* cams, int32_t n_views, ViewDev* views) {
+  int st = check_decoder(d);
+  if (st) return st;
+  if ((st = check_ptrs({xyz, feat, off, params}, "decode inputs"))) return st;
+  int tt, tp;
+  return make_views(cams, n_views, 0.f, views, &tt, &tp);
+}
+
+int asgs_decode(const asgs_decoder* d, const float* anchor_xyz, const float* anchor_feat, const float* anchor_off,
+                const float* params, const asgs_camera* cams, int32_t n_views, const asgs_gaussians* out,
+                void* stream) {
+  ViewDev views[ASGS_MAX_VIEWS];
+  int st = decode_common(d, anchor_xyz, anchor_feat, anchor_off, params, cams, n_views, views);
+  if (st) return st;
+  if (d->precision != 0) return fail(ASGS_E_UNSUPPORTED, "BF16 decode is not built");
+  if ((st = check_gauss(out, d->n_feat, n_views, true, "out"))) return st;
+  if (out->n != d->n_anchors * d->k) return fail(ASGS_E_INVALID, "out.n must be n_anchors * k");
+  const DecodeConst dc = decode_const(*d, n_views);
+  launch_decode(dc, anchor_xyz, anchor_feat, anchor_off, params, views, *out,
+                reinterpret_cast<hipStream_t>(stream));
+  return check_launch("decode launch");
+}
+
+int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const float* anchor_feat,
+                         const float* anchor_off, const float* params, const asgs_camera* cams, int32_t n_views,
+                         const asgs_gaussians* d_g, float* d_xyz, float* d_feat, float* d_off, float* d_params,
+                         float* d_pose, void* work, size_t work_bytes, void* stream) {
+  ViewDev views[ASGS_MAX_VIEWS];
+  int st = decode_common(d, anchor_xyz, anchor_feat, anchor_off, params, cams, n_views, views);
+  if (st) return st;
+  if ((st = check_gauss(d_g, d->n_feat, n_views, true, "d_g"))) return st;
+  if (d_g->n != d->n_anchors * d->k) return fail(ASGS_E_INVALID, "d_g.n must be n_anchors * k");
+  if ((st = check_ptrs({d_xyz, d_feat, d_off, d_params, work}, "decode_backward outputs"))) return st;
+  const DecodeConst dc = decode_const(*d, n_views);
+  const size_t need = decode_workspace_bytes(dc);
+  if (work_bytes < need) return fail(ASGS_E_WORKSPACE, "decode workspace needs %zu bytes (got %zu)", need, work_bytes);
+  launch_decode_backward(dc, anchor_xyz, anchor_feat, anchor_off, params, views, *d_g, d_xyz, d_feat, d_off,
+                         d_params, d_pose, work, reinterpret_cast<hipStream_t>(stream));
+  return check_launch("decode_backward launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Internal declarations shared by the libasgs translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "asgs.h"
+
+namespace asgs {
+
+constexpr int kTile = 16;            // screen tile side (pixels)
+constexpr int kTilePix = kTile * kTile;
+constexpr int kGeomStride = 8;       // floats per 2D geometry record: u v A B | C o - -
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortIPT = 8;          // items per thread per radix block
+constexpr int kSortItems = kSortThreads * kSortIPT;
+constexpr int kScanThreads = 256;
+constexpr int kScanIPT = 8;
+constexpr int kScanItems = kScanThreads * kScanIPT;
+constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
+
+// Device view table entry (128 bytes).
+struct ViewDev {
+  float R[9];        // world->camera rotation (transpose of the T_wc rotation block), row-major
+  float t[3];        // world->camera translation
+  float fx, fy, cx, cy;
+  float limx, limy;  // Jacobian clamp limits on x/z and y/z (huge when off)
+  float cc[3];       // camera centre in world coordinates
+  int32_t W, H, TX, TY;
+  int32_t tile_base; // first global tile key of this view
+  int32_t pix_base;  // first pixel of this view in the packed image planes
+  int32_t pad[5];
+};
+static_assert(sizeof(ViewDev) == 128, "ViewDev size");
+
+// Scalars every render kernel needs.
+struct RenderConst {
+  float alpha_min, alpha_max, T_min, dilation, znear;
+  float bg[3];
+  int32_t n_views;
+  int32_t nf;          // feature channels (0 or 16)
+  int64_t n;           // Gaussians per view
+  int64_t nv;          // n * n_views
+  int32_t total_tiles;
+  int32_t total_pix;
+  int64_t cap;         // intersection capacity
+};
+
+// Header at the start of every render context (device memory).
+struct CtxHeader {
+  unsigned long long n_isect;     // intersections of the last forward/count (may exceed cap)
+  unsigned long long n_visible;   // visible (view, Gaussian) pairs
+  uint32_t overflow;
+  uint32_t counters[15];          // last-block-done counters of the multi-block kernels
+  uint32_t magic;
+  uint32_t pad[31];
+};
+
+enum Counter { kCntDepth0 = 0, kCntScan = 4, kCntTile0 = 5, kCntPose = 9 };
+
+// Byte layout of a render context; every array 256-byte aligned.
+struct CtxLayout {
+  size_t hdr, views, geom, chan, rect, ntiles, rank, dkey0, dkeyA, dvalA, dkeyB, dvalB,
+      toff, bsum, pkeyA, pvalA, pkeyB, pvalB, dupgid, pairgid, ranges, hist, tfinal, ncontrib,
+      gslot, posepart, pkey_fin, pval_fin;
+  size_t total;
+  int64_t nv, cap;
+  int32_t total_tiles, total_pix, cs, gs, nblk_hist, tile_passes, pose_blocks;
+};
+
+int chan_stride(int nf);   // floats per channel record: rgb, depth, feat
+int gslot_stride(int nf);  // floats per per-pair gradient slot
+CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int nf, int64_t cap);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (each defined next to its kernels). All asynchronous.
+// ---------------------------------------------------------------------------
+void launch_set_views(const ViewDev* host_views, int n_views, ViewDev* dev_views,
+                      CtxHeader* hdr, hipStream_t s);
+void launch_project(const RenderConst& rc, const asgs_gaussians& g, const CtxLayout& L,
+                    char* ctx, hipStream_t s);
+void launch_depth_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
+void launch_duplicate(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
+void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
+void launch_blend_forward(const RenderConst& rc, const CtxLayout& L, char* ctx,
+                          const asgs_images& out, hipStream_t s);
+void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx,
+                           const asgs_images& dout, hipStream_t s);
+void launch_project_backward(const RenderConst& rc, const asgs_gaussians& g,
+                             const asgs_gaussians& dg, float* d_pose, const CtxLayout& L,
+                             char* ctx, hipStream_t s);
+
+struct DecodeConst {
+  int64_t A;
+  int32_t k, nf, n_views, precision;
+  float l_o, l_s;
+  int64_t head_off[5];   // float offset of each head's W1 in the packed params
+  int32_t head_m[5];     // values per Gaussian of each head (0 = absent)
+  int64_t n_params;
+};
+DecodeConst decode_const(const asgs_decoder& d, int n_views);
+size_t decode_workspace_bytes(const DecodeConst& dc);
+void launch_decode(const DecodeConst& dc, const float* xyz, const float* feat, const float* off,
+                   const float* params, const ViewDev* host_views, const asgs_gaussians& out,
+                   hipStream_t s);
+void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float* feat,
+                            const float* off, const float* params, const ViewDev* host_views,
+                            const asgs_gaussians& dg, float* d_xyz, float* d_feat, float* d_off,
+                            float* d_params, float* d_pose, void* work, hipStream_t s);
+
+}  // namespace asgs
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+#define ASGS_DEV __device__ __forceinline__
+
+namespace asgs {
+
+template <typename T>
+ASGS_DEV T* ctx_ptr(char* ctx, size_t off) { return reinterpret_cast<T*>(ctx + off); }
+
+// Alpha of a Gaussian at a pixel. The same instruction sequence is used by
+// the forward and the backward so both take identical skip/stop decisions.
+ASGS_DEV float eval_power(float u, float v, float A, float B, float C, float px, float py,
+                          float& dx, float& dy) {
+  dx = u - px;
+  dy = v - py;
+  const float q = fmaf(C * dy, dy, A * dx * dx);
+  return fmaf(-0.5f, q, -(B * dx) * dy);
+}
+
+}  // namespace asgs

@@ -1,0 +1,171 @@
+"""GPU parity of the render path (projection, binning/sort, blend, backward)
+against the FP64 oracle, through the C ABI.
+
+Images: max |x - ref| / max |ref| <= 1e-4 per channel group; gradients
+<= 1e-3 per tensor. Pixels with a compositing decision within the guard band
+of its threshold (computed by the oracle in FP64) are excluded from image
+comparisons and get zero upstream gradient, on both sides. Tile lists and
+sort order are compared bit for bit (Gaussian ids and ranges), except for
+Gaussians whose footprint radius is within the guard band of an integer.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import (GRAD_TOL, IMG_TOL, guard_mask, log, oracle_opts, rel_err, to_np, upstream)
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2505_22335_amd as P
+    from paper_2505_22335_amd import _lib as L
+
+
+def _gpu_render(scene, cams, nf, G=None, **kw):
+    g = P.gaussians_to_device(scene.arrays())
+    rc = P.RenderContext(cams, scene.n, n_feat=nf, **kw)
+    rc.fit(g)
+    out = rc.forward(g)
+    res = dict(out={k: to_np(v) for k, v in out.items()}, rc=rc, g=g)
+    if G is not None:
+        V = len(cams)
+        dimg = {k: torch.as_tensor(np.stack([G[k]] * V)).cuda() if not isinstance(G[k], list) else
+                torch.as_tensor(np.stack(G[k])).cuda() for k in G}
+        dg, dpose = rc.backward(g, dimg)
+        torch.cuda.synchronize()
+        res["dg"] = {k: to_np(v) for k, v in dg.items()}
+        res["dpose"] = to_np(dpose)
+    torch.cuda.synchronize()
+    return res
+
+
+def _check_lists(rc, ref, n_views=1):
+    """GPU tile lists equal the oracle's, except entries of flagged Gaussians."""
+    ni, nvis, ov = rc.status()
+    assert ov == 0
+    gid = rc.array(L.CTX_PAIR_GAUSS, torch.int32, count=ni).cpu().numpy().astype(np.int64)
+    rng = rc.array(L.CTX_TILE_RANGE, torch.int32, width=2).cpu().numpy().astype(np.int64)
+    flagged = set(np.flatnonzero(ref["proj"]["margin_r"] < 1e-4).tolist())
+    assert len(flagged) < 0.01 * len(ref["proj"]["margin_r"]) + 3
+    mism = 0
+    for t in range(ref["ranges"].shape[0]):
+        s, e = ref["ranges"][t]
+        a = [x for x in ref["gids"][s:e] if x not in flagged]
+        gs, ge = rng[t]
+        b = [x for x in gid[gs:ge] if x not in flagged]
+        if a != b:
+            mism += 1
+    return mism, ni
+
+
+@pytest.mark.parametrize("bg", [(0.0, 0.0, 0.0), (0.2, 0.5, 1.0)])
+def test_c1_forward_backward(bg):
+    sc, cam, tgt = synth.c1()
+    log("case c1", bg)
+    nf = 0
+    ref = oracle.render_scene(sc, cam, oracle_opts(nf, bg=bg), with_margins=True, keep_lists=True)
+    keep = guard_mask(ref["margins"])
+    log("guard-band pixels excluded:", int((~keep).sum()), "of", keep.size)
+    assert (~keep).sum() < 0.01 * keep.size
+    G = upstream(3, cam.height, cam.width, nf)
+    for k in G:
+        G[k] = G[k] * keep
+    res = _gpu_render(sc, [cam], nf, G=G, bg=bg)
+    out = res["out"]
+    e_rgb = rel_err(out["rgb"][0], ref["rgb"], keep)
+    e_d = rel_err(out["depth"][0], ref["depth"], keep)
+    e_a = rel_err(out["alpha"][0], ref["alpha"], keep)
+    log("c1 image errors rgb %.2e depth %.2e alpha %.2e" % (e_rgb, e_d, e_a))
+    assert e_rgb <= IMG_TOL and e_d <= IMG_TOL and e_a <= IMG_TOL
+    mism, ni = _check_lists(res["rc"], ref)
+    log("c1 intersections", ni, "oracle", len(ref["gids"]), "tile-list mismatches", mism)
+    assert ni == len(ref["gids"]) and mism == 0
+    _, gr = oracle.render_scene(sc, cam, oracle_opts(nf, bg=bg), grad_out=G, pose_grad=True)
+    for k in ("mean", "scale", "rot", "opacity", "rgb"):
+        e = rel_err(res["dg"][k][0], gr["gauss"][k])
+        log("c1 grad", k, "%.2e" % e)
+        assert e <= GRAD_TOL, k
+    e = rel_err(res["dpose"][0], gr["pose"])
+    log("c1 pose grad %.2e" % e, res["dpose"][0], gr["pose"])
+    assert e <= GRAD_TOL
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tiny_scene_features_ragged(seed):
+    """Small image that is not a multiple of the tile size, 16-d features."""
+    nf = 16
+    sc = synth.tiny_scene(200 + seed, 300, n_feat=nf, logs_mu=-2.6)
+    cam = synth.Camera(75, 53, 60.0, 60.0, 37.0, 26.0, np.eye(3, 4, dtype=np.float32))
+    log("case tiny", seed)
+    ref = oracle.render_scene(sc, cam, oracle_opts(nf), with_margins=True, keep_lists=True)
+    keep = guard_mask(ref["margins"])
+    G = upstream(10 + seed, cam.height, cam.width, nf)
+    for k in G:
+        G[k] = G[k] * keep
+    res = _gpu_render(sc, [cam], nf, G=G)
+    out = res["out"]
+    for k in ("rgb", "depth", "alpha", "feat"):
+        e = rel_err(out[k][0], ref[k], keep)
+        log("tiny", k, "%.2e" % e)
+        assert e <= IMG_TOL, k
+    mism, ni = _check_lists(res["rc"], ref)
+    assert ni == len(ref["gids"]) and mism == 0
+    _, gr = oracle.render_scene(sc, cam, oracle_opts(nf), grad_out=G, pose_grad=True)
+    for k in ("mean", "scale", "rot", "opacity", "rgb", "feat"):
+        e = rel_err(res["dg"][k][0], gr["gauss"][k])
+        log("tiny grad", k, "%.2e" % e)
+        assert e <= GRAD_TOL, k
+    assert rel_err(res["dpose"][0], gr["pose"]) <= GRAD_TOL
+
+
+def test_multiview_batch_equals_single():
+    """Three views in one call give the same images and gradients as one call
+    per view (results are per view; the batch shares one sort)."""
+    nf = 16
+    sc = synth.tiny_scene(300, 400, n_feat=nf, logs_mu=-2.6)
+    base = np.eye(3, 4, dtype=np.float32)
+    cams = [synth.Camera(64, 48, 60.0, 60.0, 31.5, 23.5,
+                         synth.perturb_pose(base, [0.05 * v, -0.02 * v, 0.0], [0.0, 0.03 * v, 0.01 * v]))
+            for v in range(3)]
+    log("case multiview")
+    rng = np.random.default_rng(5)
+    G = dict(rgb=[rng.normal(size=(3, 48, 64)).astype(np.float32) for _ in cams],
+             depth=[rng.normal(size=(48, 64)).astype(np.float32) for _ in cams],
+             alpha=[rng.normal(size=(48, 64)).astype(np.float32) for _ in cams],
+             feat=[rng.normal(size=(nf, 48, 64)).astype(np.float32) for _ in cams])
+    batch = _gpu_render(sc, cams, nf, G=G)
+    for v, cam in enumerate(cams):
+        Gv = {k: G[k][v] for k in G}
+        one = _gpu_render(sc, [cam], nf, G=Gv)
+        for k in ("rgb", "depth", "alpha", "feat"):
+            assert np.array_equal(batch["out"][k][v], one["out"][k][0]), (v, k)
+        for k in ("mean", "scale", "rot", "opacity", "rgb", "feat"):
+            assert np.array_equal(batch["dg"][k][v], one["dg"][k][0]), (v, k)
+        np.testing.assert_allclose(batch["dpose"][v], one["dpose"][0], rtol=1e-6, atol=1e-9)
+
+
+def test_empty_and_offscreen():
+    """All Gaussians behind the camera or off screen: zero images, zero grads."""
+    sc = synth.tiny_scene(400, 50)
+    sc.mean[2] = -sc.mean[2]  # behind the camera
+    cam = synth.Camera(40, 30, 40.0, 40.0, 19.5, 14.5, np.eye(3, 4, dtype=np.float32))
+    G = upstream(1, 30, 40, 0)
+    res = _gpu_render(sc, [cam], 0, G=G)
+    assert np.all(res["out"]["rgb"] == 0) and np.all(res["out"]["alpha"] == 0)
+    assert all(np.all(v == 0) for v in res["dg"].values())
+    assert np.all(res["dpose"] == 0)
+    ni, nvis, ov = res["rc"].status()
+    assert ni == 0 and nvis == 0
+
+
+def test_capacity_overflow_is_reported():
+    sc, cam, _ = synth.c1()
+    g = P.gaussians_to_device(sc.arrays())
+    rc = P.RenderContext([cam], sc.n, n_feat=0, capacity=1000)
+    out = rc.forward(g)
+    ni, nvis, ov = rc.status()
+    assert ov == 1 and ni > 1000
+    need = rc.count(g)
+    assert need == ni
