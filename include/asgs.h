@@ -233,6 +233,29 @@ int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const f
                          float* d_off, float* d_params, float* d_pose, void* work,
                          size_t work_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Timing hook (for measurement tools; off by default)
+ *
+ * While a kernel class is enabled, each launch of it made by this library is
+ * bracketed by two hipEvents recorded on the launch stream. asgs_profile_read
+ * waits for those events and returns the summed elapsed time and the number of
+ * launches since the class was last enabled. Process-wide, thread-safe.
+ * ------------------------------------------------------------------------- */
+enum {
+  ASGS_K_PROJECT = 0,      /* projection (one kernel) */
+  ASGS_K_SORT = 1,         /* depth sort, duplication, tile sort, ranges (several kernels) */
+  ASGS_K_BLEND_FWD = 2,    /* forward compositing (one kernel) */
+  ASGS_K_BLEND_BWD = 3,    /* backward compositing (one kernel) */
+  ASGS_K_PROJECT_BWD = 4,  /* projection backward + pose reduction (one kernel) */
+  ASGS_K_DECODE = 5,       /* decoder forward (one kernel) */
+  ASGS_K_DECODE_BWD = 6,   /* decoder backward + parameter reduction (two kernels) */
+  ASGS_K_NUM = 7
+};
+/* Enable the classes whose bit (1 << class) is set in mask; 0 disables all.
+ * Clears earlier measurements. */
+int asgs_profile_enable(uint32_t mask);
+int asgs_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

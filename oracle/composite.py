@@ -22,7 +22,7 @@ F64 = torch.float64
 
 
 def composite_tile(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, with_margins=False,
-                   impact_T=1e-3):
+                   impact_T=1e-3, z32=None):
     """Composite K depth-ordered Gaussians over P pixels, vectorised.
 
     u, v, A, B, C, o: (K,) tensors; chans: (K, Cc) tensors (colour, depth,
@@ -37,7 +37,7 @@ def composite_tile(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, with_margi
         out = (z, torch.zeros(P, dtype=F64), torch.ones(P, dtype=F64), np.zeros(P, np.int64))
         if with_margins:
             return out + (dict(alpha=np.full(P, np.inf), clamp=np.full(P, np.inf),
-                               term=np.full(P, np.inf)),)
+                               term=np.full(P, np.inf), tie=np.full(P, np.inf)),)
         return out
     dx = u[:, None] - px[None, :]
     dy = v[:, None] - py[None, :]
@@ -74,7 +74,17 @@ def composite_tile(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, with_margi
         m_alpha = np.where(reached, np.abs(alpha.numpy() - opts.alpha_min) / opts.alpha_min, np.inf)
         m_clamp = np.where(reached & vn, np.abs(raw.numpy() - opts.alpha_max) / opts.alpha_max, np.inf)
         m_term = np.where(reached & vn, np.abs(T_after.numpy() - opts.T_min) / opts.T_min, np.inf)
-        margins = dict(alpha=m_alpha.min(0), clamp=m_clamp.min(0), term=m_term.min(0))
+        margins = dict(alpha=m_alpha.min(0), clamp=m_clamp.min(0), term=m_term.min(0),
+                       tie=np.full(P, np.inf))
+        if z32 is not None and K > 1:
+            # depth order of two neighbours both composited at a pixel, in
+            # float32 ulps: a near tie may be ordered either way by a float32
+            # depth computed with different rounding
+            zf = np.asarray(z32, np.float32)
+            gap = (zf[1:].astype(np.float64) - zf[:-1]) / np.spacing(zf[:-1]).astype(np.float64)
+            both = (reached & vn)[1:] & (reached & vn)[:-1]
+            m_tie = np.where(both, gap[:, None], np.inf)
+            margins["tie"] = m_tie.min(0)
     return acc, alpha_sum, T_final, n_contrib, margins
 
 

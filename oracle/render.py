@@ -84,7 +84,7 @@ def render(g: Dict[str, torch.Tensor], R_cw, t_cw, cam, opts: RenderOpts, grad_o
     asum = np.zeros(H * W)
     Tfin = np.ones(H * W)
     ncon = np.zeros(H * W, np.int64)
-    marg = {k: np.full(H * W, np.inf) for k in ("alpha", "clamp", "term")}
+    marg = {k: np.full(H * W, np.inf) for k in ("alpha", "clamp", "term", "tie")}
     if grad_out is not None:
         Gimg = [np.asarray(grad_out["rgb"], np.float64).reshape(3, -1),
                 np.asarray(grad_out["depth"], np.float64).reshape(1, -1)]
@@ -112,7 +112,7 @@ def render(g: Dict[str, torch.Tensor], R_cw, t_cw, cam, opts: RenderOpts, grad_o
         ids = torch.as_tensor(gids[s:e])
         args = [x[ids] for x in lv]
         res = composite_tile(*args, torch.as_tensor(pxs, dtype=F64), torch.as_tensor(pys, dtype=F64),
-                             opts, with_margins=with_margins, impact_T=impact_T)
+                             opts, with_margins=with_margins, impact_T=impact_T, z32=p["z32"][gids[s:e]])
         a_, s_, T_, n_ = res[:4]
         acc[pix] = a_.detach().numpy()
         asum[pix] = s_.detach().numpy()

@@ -22,6 +22,7 @@ lib = C.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_WORKSPACE, E_CAPACITY, E_DEVICE, E_UNSUPPORTED = range(6)
 MAX_VIEWS = 64
+K_PROJECT, K_SORT, K_BLEND_FWD, K_BLEND_BWD, K_PROJECT_BWD, K_DECODE, K_DECODE_BWD = range(7)
 CTX_PAIR_TILE, CTX_PAIR_GAUSS, CTX_TILE_RANGE, CTX_RECT, CTX_NCONTRIB, CTX_TFINAL = range(1, 7)
 
 
@@ -84,6 +85,8 @@ _sigs = {
     "asgs_decode_workspace_size": (C.c_int, [C.POINTER(Decoder), C.c_int32, C.POINTER(C.c_size_t)]),
     "asgs_decode_backward": (C.c_int, [C.POINTER(Decoder), P, P, P, P, C.POINTER(Camera), C.c_int32,
                                        C.POINTER(Gaussians), P, P, P, P, P, P, C.c_size_t, P]),
+    "asgs_profile_enable": (C.c_int, [C.c_uint32]),
+    "asgs_profile_read": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 for _name, (_res, _args) in _sigs.items():
     _f = getattr(lib, _name)
@@ -250,3 +253,13 @@ def decode_backward(d: Decoder, xyz, feat, off, params, cams, dg: Gaussians, d_x
                                    params.data_ptr(), ca, len(cams), C.byref(dg), d_xyz.data_ptr(),
                                    d_feat.data_ptr(), d_off.data_ptr(), d_params.data_ptr(), _ptr(d_pose),
                                    work.data_ptr(), work.numel(), _stream(stream)), "asgs_decode_backward")
+
+
+def profile_enable(mask: int):
+    check(lib.asgs_profile_enable(mask), "asgs_profile_enable")
+
+
+def profile_read(kernel_class: int):
+    ms, n = C.c_double(), C.c_int64()
+    check(lib.asgs_profile_read(kernel_class, C.byref(ms), C.byref(n)), "asgs_profile_read")
+    return ms.value, n.value

@@ -1,6 +1,7 @@
 """Build libasgs.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2505_22335_amd.build   (or build() from Python).
+Usage: python paper_2505_22335_amd/build.py   (run as a file: importing the
+package loads the library this script builds).
 Every source is compiled on each call; objects go to _build/ at the repo root.
 """
 from __future__ import annotations

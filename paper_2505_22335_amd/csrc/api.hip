@@ -6,7 +6,9 @@
 #include <string.h>
 
 #include <initializer_list>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -31,6 +33,37 @@ int check_launch(const char* what) {
   if (e != hipSuccess) return fail(ASGS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
   return ASGS_OK;
 }
+
+// ---- timing hook -----------------------------------------------------------
+struct ProfEvent {
+  int cls;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+uint32_t g_prof_mask = 0;
+std::vector<ProfEvent> g_prof;
+
+// Brackets one launch sequence of class `cls` with events when enabled.
+struct ProfScope {
+  hipEvent_t b = nullptr;
+  hipStream_t s;
+  ProfScope(int cls, hipStream_t st) : s(st) {
+    if (!(__atomic_load_n(&g_prof_mask, __ATOMIC_RELAXED) & (1u << cls))) return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back({cls, a, b});
+  }
+  ~ProfScope() {
+    if (b) (void)hipEventRecord(b, s);
+  }
+};
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -164,9 +197,15 @@ int check_ctx(const Prep& P, const void* ctx, size_t ctx_bytes) {
 int run_front(const Prep& P, const asgs_gaussians* g, char* ctx, hipStream_t s) {
   launch_set_views(P.views, P.rc.n_views, reinterpret_cast<ViewDev*>(ctx + P.L.views),
                    reinterpret_cast<CtxHeader*>(ctx + P.L.hdr), s);
-  launch_project(P.rc, *g, P.L, ctx, s);
-  launch_depth_sort(P.rc, P.L, ctx, s);
-  launch_duplicate(P.rc, P.L, ctx, s);
+  {
+    ProfScope ps(ASGS_K_PROJECT, s);
+    launch_project(P.rc, *g, P.L, ctx, s);
+  }
+  {
+    ProfScope ps(ASGS_K_SORT, s);
+    launch_depth_sort(P.rc, P.L, ctx, s);
+    launch_duplicate(P.rc, P.L, ctx, s);
+  }
   return check_launch("projection/sort launch");
 }
 
@@ -328,8 +367,14 @@ int asgs_render_forward(const asgs_camera* cams, int32_t n_views, const asgs_gau
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* c = static_cast<char*>(ctx);
   if ((st = run_front(P, g, c, s))) return st;
-  launch_tile_sort(P.rc, P.L, c, s);
-  launch_blend_forward(P.rc, P.L, c, *out, s);
+  {
+    ProfScope ps(ASGS_K_SORT, s);
+    launch_tile_sort(P.rc, P.L, c, s);
+  }
+  {
+    ProfScope ps(ASGS_K_BLEND_FWD, s);
+    launch_blend_forward(P.rc, P.L, c, *out, s);
+  }
   return check_launch("render_forward launch");
 }
 
@@ -361,8 +406,14 @@ int asgs_render_backward(const asgs_camera* cams, int32_t n_views, const asgs_ga
   if ((st = check_ctx(P, ctx, ctx_bytes))) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* c = static_cast<char*>(ctx);
-  launch_blend_backward(P.rc, P.L, c, *d_out, s);
-  launch_project_backward(P.rc, *g, *d_g, d_pose, P.L, c, s);
+  {
+    ProfScope ps(ASGS_K_BLEND_BWD, s);
+    launch_blend_backward(P.rc, P.L, c, *d_out, s);
+  }
+  {
+    ProfScope ps(ASGS_K_PROJECT_BWD, s);
+    launch_project_backward(P.rc, *g, *d_g, d_pose, P.L, c, s);
+  }
   return check_launch("render_backward launch");
 }
 
@@ -466,8 +517,11 @@ int asgs_decode(const asgs_decoder* d, const float* anchor_xyz, const float* anc
   if ((st = check_gauss(out, d->n_feat, n_views, true, "out"))) return st;
   if (out->n != d->n_anchors * d->k) return fail(ASGS_E_INVALID, "out.n must be n_anchors * k");
   const DecodeConst dc = decode_const(*d, n_views);
-  launch_decode(dc, anchor_xyz, anchor_feat, anchor_off, params, views, *out,
-                reinterpret_cast<hipStream_t>(stream));
+  {
+    ProfScope ps(ASGS_K_DECODE, reinterpret_cast<hipStream_t>(stream));
+    launch_decode(dc, anchor_xyz, anchor_feat, anchor_off, params, views, *out,
+                  reinterpret_cast<hipStream_t>(stream));
+  }
   return check_launch("decode launch");
 }
 
@@ -484,9 +538,44 @@ int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const f
   const DecodeConst dc = decode_const(*d, n_views);
   const size_t need = decode_workspace_bytes(dc);
   if (work_bytes < need) return fail(ASGS_E_WORKSPACE, "decode workspace needs %zu bytes (got %zu)", need, work_bytes);
-  launch_decode_backward(dc, anchor_xyz, anchor_feat, anchor_off, params, views, *d_g, d_xyz, d_feat, d_off,
-                         d_params, d_pose, work, reinterpret_cast<hipStream_t>(stream));
+  {
+    ProfScope ps(ASGS_K_DECODE_BWD, reinterpret_cast<hipStream_t>(stream));
+    launch_decode_backward(dc, anchor_xyz, anchor_feat, anchor_off, params, views, *d_g, d_xyz, d_feat, d_off,
+                           d_params, d_pose, work, reinterpret_cast<hipStream_t>(stream));
+  }
   return check_launch("decode_backward launch");
+}
+
+int asgs_profile_enable(uint32_t mask) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& e : g_prof) {
+    (void)hipEventSynchronize(e.b);
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  g_prof.clear();
+  __atomic_store_n(&g_prof_mask, mask & ((1u << ASGS_K_NUM) - 1u), __ATOMIC_RELAXED);
+  return ASGS_OK;
+}
+
+int asgs_profile_read(int32_t kernel_class, double* total_ms, int64_t* launches) {
+  if (kernel_class < 0 || kernel_class >= ASGS_K_NUM) return fail(ASGS_E_INVALID, "bad kernel class");
+  if (!total_ms || !launches) return fail(ASGS_E_INVALID, "NULL output");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& e : g_prof) {
+    if (e.cls != kernel_class) continue;
+    hipError_t err = hipEventSynchronize(e.b);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e.a, e.b);
+    if (err != hipSuccess) return fail(ASGS_E_DEVICE, "profile read: %s", hipGetErrorString(err));
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return ASGS_OK;
 }
 
 }  // extern "C"

@@ -11,9 +11,10 @@ from oracle import RenderOpts
 
 IMG_TOL = 1e-4     # images: max |x - ref| / max |ref| per channel group
 GRAD_TOL = 1e-3    # gradients: per parameter tensor
-EPS_ALPHA = 2e-5   # guard band: relative distance of alpha to alpha_min
-EPS_CLAMP = 2e-5   # ... of o exp(power) to alpha_max (gradient-only decision)
+EPS_ALPHA = 2e-4   # guard band: relative distance of alpha to alpha_min (FP32 alpha error reaches ~5e-5)
+EPS_CLAMP = 2e-4   # ... of o exp(power) to alpha_max (gradient-only decision)
 EPS_TERM = 2e-4    # ... of T to T_min
+TIE_ULPS = 16      # ... depth gap of two composited neighbours, in float32 ulps
 
 
 def log(*a):
@@ -33,7 +34,24 @@ def rel_err(x, ref, mask=None):
 
 def guard_mask(margins):
     """Pixels whose every compositing decision is clear of its threshold."""
-    return (margins["alpha"] > EPS_ALPHA) & (margins["clamp"] > EPS_CLAMP) & (margins["term"] > EPS_TERM)
+    return ((margins["alpha"] > EPS_ALPHA) & (margins["clamp"] > EPS_CLAMP) & (margins["term"] > EPS_TERM)
+            & (margins["tie"] > TIE_ULPS))
+
+
+def tie_flagged(ref):
+    """Gaussians with a tile-list neighbour within TIE_ULPS float32 ulps of depth."""
+    z32 = ref["proj"]["z32"]
+    gids, rng = ref["gids"], ref["ranges"]
+    out = set()
+    for s, e in rng:
+        if e - s < 2:
+            continue
+        z = z32[gids[s:e]]
+        gap = (z[1:].astype(np.float64) - z[:-1]) / np.spacing(z[:-1]).astype(np.float64)
+        for j in np.flatnonzero(gap <= TIE_ULPS):
+            out.add(int(gids[s + j]))
+            out.add(int(gids[s + j + 1]))
+    return out
 
 
 def upstream(seed, H, W, nf):

@@ -1,0 +1,163 @@
+"""GPU parity of the anchor decoder (forward and backward) and of the whole
+decode -> render -> backward path against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle.geometry import camera_center, pose_cw
+from tests.gpu_util import GRAD_TOL, IMG_TOL, guard_mask, log, oracle_opts, rel_err, to_np, upstream
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2505_22335_amd as P
+    from paper_2505_22335_amd.pipeline import AnchorRenderer, anchors_to_device
+
+DEC_TOL = 1e-5  # decoded attributes and decoder gradients, FP32 vs FP64
+
+
+def _oracle_decode(sc, cams, grads=None):
+    """Oracle decode per view; with grads (per view dict of [c][n] arrays),
+    also the VJP w.r.t. anchors, weights and each view's pose twist."""
+    t = lambda a: torch.as_tensor(np.asarray(a, np.float64)).clone().requires_grad_(grads is not None)
+    xyz, feat, off = t(sc.xyz.T), t(sc.feat), t(sc.off.T)
+    W = {h: {k: t(v) for k, v in w.items()} for h, w in sc.weights.items()}
+    outs, xis = [], []
+    for v, cam in enumerate(cams):
+        xi = torch.zeros(6, dtype=torch.float64, requires_grad=grads is not None)
+        R, tc = pose_cw(np.asarray(cam.T_wc, np.float64), xi)
+        g = oracle.decode(xyz, feat, off, W, camera_center(R, tc), sc.k, sc.l_o, sc.l_s)
+        outs.append(g)
+        xis.append(xi)
+    if grads is None:
+        return [{k: v.detach().numpy().T for k, v in g.items()} for g in outs], None
+    loss = 0
+    for g, G in zip(outs, grads):
+        for k, v in g.items():
+            loss = loss + (v * torch.as_tensor(np.asarray(G[k], np.float64).T.copy())).sum()
+    loss.backward()
+    gr = dict(xyz=xyz.grad.numpy().T, feat=feat.grad.numpy(), off=off.grad.numpy().T,
+              weights={h: {k: v.grad.numpy() for k, v in w.items()} for h, w in W.items()},
+              pose=np.stack([x.grad.numpy() for x in xis]))
+    return [{k: v.detach().numpy().T for k, v in g.items()} for g in outs], gr
+
+
+def _cams_tiny(nv):
+    base = np.eye(3, 4, dtype=np.float32)
+    return [synth.Camera(48, 40, 50.0, 50.0, 23.5, 19.5,
+                         synth.perturb_pose(base, [0.1 * v, -0.05, 0.02 * v], [0.01, -0.02 * v, 0.03]))
+            for v in range(nv)]
+
+
+@pytest.mark.parametrize("k,nf,nv", [(10, 16, 1), (3, 16, 2), (7, 0, 3)])
+def test_decode_forward_backward(k, nf, nv):
+    sc = synth.tiny_anchor_scene(50 + k, 77, k=k, n_feat=nf)
+    cams = _cams_tiny(nv)
+    log("case decode", k, nf, nv)
+    a = anchors_to_device(sc)
+    dec = P.Decoder(a.A, k, nf, 0, a.l_o, a.l_s)
+    out = dec.decode(a.xyz, a.feat, a.off, a.params, cams)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(k)
+    G = []
+    for v in range(nv):
+        Gv = {f: rng.normal(size=out[f][v].shape if f != "mean" else out["mean"].shape).astype(np.float32)
+              for f in out}
+        G.append(Gv)
+    ref, gr = _oracle_decode(sc, cams, G)
+    for v in range(nv):
+        for f in ("opacity", "rgb", "scale", "rot") + (("feat",) if nf else ()):
+            e = rel_err(to_np(out[f][v]), ref[v][f])
+            assert e <= DEC_TOL, (v, f, e)
+    assert rel_err(to_np(out["mean"]), ref[0]["mean"]) <= 1e-6
+    dg = {f: torch.as_tensor(np.stack([G[v][f] for v in range(nv)])).cuda() for f in out}
+    d_pose = torch.zeros((nv, 6), device="cuda")
+    d_xyz, d_feat, d_off, d_params = dec.backward(a.xyz, a.feat, a.off, a.params, cams, dg, d_pose=d_pose)
+    torch.cuda.synchronize()
+    for name, x, r in (("xyz", d_xyz, gr["xyz"]), ("feat", d_feat, gr["feat"]), ("off", d_off, gr["off"])):
+        e = rel_err(to_np(x), r)
+        log("decode grad", name, "%.2e" % e)
+        assert e <= DEC_TOL, name
+    W = P.unpack_params(d_params, k, nf)
+    for h in W:
+        for key in W[h]:
+            e = rel_err(to_np(W[h][key]), gr["weights"][h][key])
+            assert e <= DEC_TOL, (h, key, e)
+    e = rel_err(to_np(d_pose), gr["pose"])
+    log("decode pose term %.2e" % e)
+    assert e <= DEC_TOL
+
+
+def _e2e(sc, cam, nf, G_seed=7):
+    ref = oracle.render_scene(sc, cam, oracle_opts(nf), with_margins=True)
+    keep = guard_mask(ref["margins"])
+    log("guard-band pixels excluded:", int((~keep).sum()), "of", keep.size)
+    G = upstream(G_seed, cam.height, cam.width, nf)
+    for key in G:
+        G[key] = G[key] * keep
+    a = anchors_to_device(sc)
+    r = AnchorRenderer(a, [cam])
+    r.fit()
+    img = r.forward()
+    dimg = {key: torch.as_tensor(G[key][None]).cuda() for key in G}
+    grads = r.backward(dimg)
+    torch.cuda.synchronize()
+    return ref, keep, G, img, grads, r
+
+
+def test_end_to_end_room_small():
+    """Config-2 room and camera, 2000 anchors (k=10), 640x480, 16-d features."""
+    sc, cam, _ = synth.c2("shell", 2000, seed=12)
+    log("case e2e small")
+    ref, keep, G, img, grads, r = _e2e(sc, cam, 16)
+    for key in ("rgb", "depth", "alpha", "feat"):
+        e = rel_err(to_np(img[key][0]), ref[key], keep)
+        log("e2e", key, "%.2e" % e)
+        assert e <= IMG_TOL, key
+    _, gr = oracle.render_scene(sc, cam, oracle_opts(16), grad_out=G, pose_grad=True)
+    for f in ("mean", "scale", "rot", "opacity", "rgb", "feat"):
+        e = rel_err(to_np(grads["d_gauss"][f][0]), gr["gauss"][f])
+        log("e2e d_gauss", f, "%.2e" % e)
+        assert e <= GRAD_TOL, f
+    for name in ("xyz", "feat", "off"):
+        e = rel_err(to_np(grads["d_" + name]), gr["anchor"][name])
+        log("e2e d_anchor", name, "%.2e" % e)
+        assert e <= GRAD_TOL, name
+    W = P.unpack_params(grads["d_params"], sc.k, 16)
+    for h in W:
+        for key in W[h]:
+            e = rel_err(to_np(W[h][key]), gr["weights"][h][key])
+            assert e <= GRAD_TOL, (h, key, e)
+    e = rel_err(to_np(grads["d_pose"][0]), gr["pose"])
+    log("e2e pose %.2e" % e, to_np(grads["d_pose"][0]), gr["pose"])
+    assert e <= GRAD_TOL
+
+
+@pytest.mark.slow
+def test_end_to_end_config2_full():
+    """Config 2 at full size: 20k anchors x 10 = 200k Gaussians, 640x480."""
+    sc, cam, _ = synth.c2()
+    log("case e2e c2 full")
+    ref, keep, G, img, grads, r = _e2e(sc, cam, 16)
+    ni, nvis, ov = r.rc.status()
+    log("c2 intersections", ni, "visible", nvis)
+    for key in ("rgb", "depth", "alpha", "feat"):
+        e = rel_err(to_np(img[key][0]), ref[key], keep)
+        log("c2", key, "%.2e" % e)
+        assert e <= IMG_TOL, key
+    _, gr = oracle.render_scene(sc, cam, oracle_opts(16), grad_out=G, pose_grad=True)
+    for name in ("xyz", "feat", "off"):
+        e = rel_err(to_np(grads["d_" + name]), gr["anchor"][name])
+        log("c2 d_anchor", name, "%.2e" % e)
+        assert e <= GRAD_TOL, name
+    W = P.unpack_params(grads["d_params"], sc.k, 16)
+    for h in W:
+        for key in W[h]:
+            e = rel_err(to_np(W[h][key]), gr["weights"][h][key])
+            log("c2 d_param", h, key, "%.2e" % e)
+            assert e <= GRAD_TOL, (h, key, e)
+    e = rel_err(to_np(grads["d_pose"][0]), gr["pose"])
+    log("c2 pose %.2e" % e)
+    assert e <= GRAD_TOL

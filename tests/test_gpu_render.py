@@ -14,7 +14,8 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import (GRAD_TOL, IMG_TOL, guard_mask, log, oracle_opts, rel_err, to_np, upstream)
+from tests.gpu_util import (GRAD_TOL, IMG_TOL, guard_mask, log, oracle_opts, rel_err, tie_flagged, to_np,
+                            upstream)
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +48,8 @@ def _check_lists(rc, ref, n_views=1):
     assert ov == 0
     gid = rc.array(L.CTX_PAIR_GAUSS, torch.int32, count=ni).cpu().numpy().astype(np.int64)
     rng = rc.array(L.CTX_TILE_RANGE, torch.int32, width=2).cpu().numpy().astype(np.int64)
-    flagged = set(np.flatnonzero(ref["proj"]["margin_r"] < 1e-4).tolist())
-    assert len(flagged) < 0.01 * len(ref["proj"]["margin_r"]) + 3
+    flagged = set(np.flatnonzero(ref["proj"]["margin_r"] < 1e-4).tolist()) | tie_flagged(ref)
+    assert len(flagged) < 0.02 * len(ref["proj"]["margin_r"]) + 3
     mism = 0
     for t in range(ref["ranges"].shape[0]):
         s, e = ref["ranges"][t]
