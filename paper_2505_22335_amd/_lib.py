@@ -16,8 +16,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libasgs.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "asgs.h")
 
+# torch ships its own HIP runtime under the same soname as the system one; it
+# must be the first loaded so that torch's allocations and this library share
+# one runtime (otherwise whichever loads second sees no device).
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libasgs.so not built at {LIB_PATH}: run python -m paper_2505_22335_amd.build")
+    raise ImportError(f"libasgs.so not built at {LIB_PATH}: run python paper_2505_22335_amd/build.py")
 lib = C.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_WORKSPACE, E_CAPACITY, E_DEVICE, E_UNSUPPORTED = range(6)

@@ -10,9 +10,9 @@
 // The backward replays each pixel's list back to front from its last
 // composited Gaussian, recovering T_k = T_{k+1} / (1 - alpha_k). Per list entry
 // the 26 gradient values (u, v, conic, opacity, channels) of the 256 pixels are
-// summed with wave-wide DPP reductions (skipped by ballot when no lane of the
-// wave touches the Gaussian), combined across the four waves in LDS and
-// written once to the entry's gradient slot; no global atomics. The
+// summed over each 16-lane row with DPP (skipped by ballot when no lane of the
+// wave touches the Gaussian), the 16 row sums of the workgroup are combined in
+// LDS and written once to the entry's gradient slot; no global atomics. The
 // projection backward then sums each Gaussian's slots.
 #include "internal.h"
 
@@ -25,17 +25,14 @@ ASGS_DEV float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
 }
 
-// Sum over the 64 lanes of a wave; valid in every lane. All lanes must be active.
-ASGS_DEV float wave_sum(float x) {
+// Sum over each row of 16 lanes; every lane of a row receives its row's sum.
+// All lanes must be active.
+ASGS_DEV float row_sum(float x) {
   x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
   x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
   x += dpp<0x124>(x);  // row_ror:4
   x += dpp<0x128>(x);  // row_ror:8
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
-  return (r0 + r1) + (r2 + r3);
+  return x;
 }
 
 ASGS_DEV int find_view(const ViewDev* views, int n_views, int tile) {
@@ -88,9 +85,14 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
     __syncthreads();
     const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
     if (!done) {
+      float4 n0 = sg[0], n1 = sg[1];
       for (int j = 0; j < cnt; ++j) {
-        const float4 g0 = sg[2 * j];
-        const float4 g1 = sg[2 * j + 1];
+        // geometry of the next entry is read before this one is evaluated
+        const float4 g0 = n0;
+        const float4 g1 = n1;
+        const int jn = j + 1 < cnt ? j + 1 : j;
+        n0 = sg[2 * jn];
+        n1 = sg[2 * jn + 1];
         float dx, dy;
         const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
         if (power > 0.f) continue;
@@ -132,7 +134,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   ctx_ptr<uint32_t>(ctx, L.ncontrib)[pb + pix] = last;
 }
 
-constexpr int kBwdBatch = 64;
+constexpr int kBwdBatch = 16;
 
 template <int NF>
 __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const ViewDev* __restrict__ views,
@@ -160,9 +162,12 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
   float* gslot = ctx_ptr<float>(ctx, L.gslot);
 
+  constexpr int NR = NW * 4;  // 16-lane rows per workgroup
   __shared__ float4 sg[kBwdBatch * 2];
   __shared__ float4 sc[kBwdBatch * CS4];
-  __shared__ float part[NW][kBwdBatch][GS];
+  // row partials, row index innermost (+1 pad) so the four row leaders of a
+  // wave hit four different banks
+  __shared__ float part[kBwdBatch][GS][NR + 1];
   __shared__ uint32_t smax;
 
   const size_t HW = (size_t)V.W * V.H;
@@ -228,7 +233,8 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
           if (alpha >= amin) {
             contrib = true;
             const float oma = 1.f - alpha;
-            T = T / oma;
+            const float ioma = __builtin_amdgcn_rcpf(oma);
+            T = T * ioma;
             const float w = alpha * T;
             float dotg = 0.f;
 #pragma unroll
@@ -241,7 +247,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
             }
 #pragma unroll
             for (int c = 0; c < CS; ++c) gv[6 + c] = w * G[c];
-            const float dalpha = T * dotg - (sacc + GT * Tf) / oma;
+            const float dalpha = T * dotg - (sacc + GT * Tf) * ioma;
             sacc = fmaf(w, dotg, sacc);
             if (raw < amax) {
               const float dp = dalpha * alpha;
@@ -255,14 +261,15 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
           }
         }
       }
+      const int row = wv * 4 + (lane >> 4);
       if (__ballot(contrib) != 0ull) {
 #pragma unroll
         for (int c = 0; c < GS; ++c) {
-          const float s = wave_sum(gv[c]);
-          if (lane == 0) part[wv][jj][c] = s;
+          const float s = row_sum(gv[c]);
+          if ((lane & 15) == 0) part[jj][c][row] = s;
         }
-      } else if (lane < GS) {
-        part[wv][jj][lane] = 0.f;
+      } else if ((lane & 15) < GS) {
+        for (int c = lane & 15; c < GS; c += 16) part[jj][c][row] = 0.f;
       }
     }
     __syncthreads();
@@ -270,7 +277,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
       const int jj = e / GS, c = e - jj * GS;
       float s = 0.f;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) s += part[w][jj][c];
+      for (int r = 0; r < NR; ++r) s += part[jj][c][r];
       gslot[(size_t)pslot[rg.x + lo + jj] * GS + c] = s;
     }
   }

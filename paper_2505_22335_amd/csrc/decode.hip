@@ -25,8 +25,6 @@ namespace {
 
 constexpr int kDecThreads = 320;
 constexpr int kFwdAnchors = 32;     // anchors per forward workgroup
-constexpr int kBwdAnchors = 16;     // anchors per backward batch
-constexpr int kDecBatches = 8;      // batches per workgroup in the backward
 constexpr int kIn = 35;
 constexpr int kHid = 32;
 constexpr int kHeads = 5;
@@ -181,212 +179,383 @@ ASGS_DEV float act_grad(int h, float y, float l_s) {
   }
 }
 
-__global__ void __launch_bounds__(kDecThreads) k_decode_bwd(DecodeConst dc, HeadTable ht, DecodeViews dv,
-                                                            const float* __restrict__ xyz,
-                                                            const float* __restrict__ feat,
-                                                            const float* __restrict__ off,
-                                                            const float* __restrict__ params,
-                                                            asgs_gaussians dg, float* d_xyz, float* d_feat,
-                                                            float* d_off, float* part, float* dcpart) {
-  constexpr int kDecAnchors = kBwdAnchors;
+// ---------------------------------------------------------------------------
+// Backward, per view, in three stages over a workspace holding, per anchor,
+// X (36 floats: input + pad), H (160 hidden activations), dY (second-layer
+// output gradients, row stride RP) and dZ (160 first-layer pre-activation
+// gradients):
+//   prep : recompute X, H and Y; dY = dL/d(decoded) * act'(Y)
+//   mid  : dH = W2^T dY, dZ = dH * act'(Z) (from H: ReLU -> H > 0, SoftPlus ->
+//          1 - exp(-H)), dX = W1^T dZ -> anchor feature and direction
+//          gradients, camera-centre partial sums
+//   wgrad: per chunk of anchors, dW2 = dY^T H, dW1 = dZ^T X and the bias sums,
+//          one partial per workgroup (summed over views), then a fixed-order
+//          reduction over workgroups.
+// ---------------------------------------------------------------------------
+struct DecWork {
+  float* X;
+  float* H;
+  float* dY;
+  float* dZ;
+  float* part;    // [nblk_w][n_params]
+  float* dcpart;  // [nblk_m][n_views][3]
+  int32_t RP;     // row stride of dY
+  int32_t nblk_w, nblk_m;
+};
+
+constexpr int kMidAnchors = 16;
+
+// Workgroup partials of the parameter gradients are stored chunk-major: for
+// every run of 64 parameters, the 64-float segments of all workgroups are
+// contiguous, so the reduction of one run reads one contiguous region.
+ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
+constexpr int kWChunk = 64;     // anchors per weight-gradient workgroup
+constexpr int kWThreads = 1024;
+constexpr int kWSub = 16;       // anchors staged in LDS at a time
+
+__global__ void __launch_bounds__(kDecThreads) k_dec_bwd_prep(DecodeConst dc, HeadTable ht, DecodeViews dv,
+                                                              const float* __restrict__ xyz,
+                                                              const float* __restrict__ feat,
+                                                              const float* __restrict__ params,
+                                                              asgs_gaussians dg, int view, DecWork w) {
+  constexpr int kDecAnchors = kFwdAnchors;
   __shared__ float X[kDecAnchors][kIn + 1];
   __shared__ float H[kDecAnchors * kHeads][kHid + 1];
-  __shared__ float Zs[kDecAnchors * kHeads][kHid + 1];
-  __shared__ float dZ[kDecAnchors * kHeads][kHid + 1];
-  __shared__ float dY[kDecAnchors][kMaxRows + 1];
   __shared__ float dist[kDecAnchors];
-  __shared__ float dXs[kDecAnchors][kIn + 1];
-  __shared__ float dcs[3][kDecThreads / 64];
+  const int64_t a0 = (int64_t)blockIdx.x * kDecAnchors;
+  const int64_t A = dc.A;
+  const int k = dc.k;
+  const int64_t n = A * k;
+  load_inputs<kDecAnchors>(xyz, feat, A, a0, dv.c[view], X, dist);
+  __syncthreads();
+  layer1<kDecAnchors>(params, ht, X, H, nullptr);
+  __syncthreads();
+  const int t = threadIdx.x;
+  for (int e = t; e < kDecAnchors * 36; e += kDecThreads) {
+    const int a = e / 36, c = e % 36;
+    if (a0 + a < A) w.X[(a0 + a) * 36 + c] = X[a][c];
+  }
+  for (int e = t; e < kDecAnchors * 160; e += kDecThreads) {
+    const int a = e / 160, j = e % 160;
+    if (a0 + a < A) w.H[(a0 + a) * 160 + j] = j < ht.nunits ? H[a * kHeads + j / kHid][j % kHid] : 0.f;
+  }
+  for (int o = t; o < ht.nrows; o += kDecThreads) {
+    const int h = row_head(ht, o);
+    const int oh = o - ht.row0[h];
+    const int m = ht.m[h];
+    const int i = oh / m, comp = oh - i * m;
+    const float* W2 = params + ht.off[h] + kHid * kIn + kHid + oh * kHid;
+    const float b2 = params[ht.off[h] + kHid * kIn + kHid + k * m * kHid + oh];
+    float wr[kHid];
+#pragma unroll
+    for (int c = 0; c < kHid; ++c) wr[c] = W2[c];
+    const float* plane = out_plane(dg, view, h, comp, n);
+    for (int a = 0; a < kDecAnchors; ++a) {
+      if (a0 + a >= A) break;
+      float y = b2;
+#pragma unroll
+      for (int c = 0; c < kHid; ++c) y = fmaf(wr[c], H[a * kHeads + h][c], y);
+      w.dY[(a0 + a) * w.RP + o] = plane[(a0 + a) * k + i] * act_grad(h, y, dc.l_s);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kDecThreads) k_dec_bwd_mid(DecodeConst dc, HeadTable ht, DecodeViews dv,
+                                                             const float* __restrict__ xyz,
+                                                             const float* __restrict__ params, int view,
+                                                             DecWork w, float* d_xyz, float* d_feat) {
+  __shared__ float sdY[kMidAnchors][kMaxRows + 4];
+  __shared__ float sdZ[kMidAnchors][160 + 4];
+  __shared__ float sdX[kMidAnchors][kIn + 1];
+  __shared__ float red[3][kDecThreads / 64];
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int64_t A = dc.A;
   const int k = dc.k;
-  const int64_t n = A * k;
+  const int64_t a0 = (int64_t)blockIdx.x * kMidAnchors;
   const int nrows = ht.nrows;
-  // per-thread weight-gradient accumulators: second-layer rows o0 = t, o1 = t + 320
-  float gW2a[kHid], gW2b[kHid], gb2a = 0.f, gb2b = 0.f;
+  for (int e = t; e < kMidAnchors * nrows; e += kDecThreads) {
+    const int a = e / nrows, o = e - a * nrows;
+    sdY[a][o] = (a0 + a < A) ? w.dY[(a0 + a) * w.RP + o] : 0.f;
+  }
+  __syncthreads();
+  // dZ for hidden unit j of head uh, anchors of half `half`
+  {
+    const int j = t % 160, half = t / 160;
+    if (j < ht.nunits && half < 2) {
+      const int uh = j / kHid, ujj = j % kHid;
+      const int rows = k * ht.m[uh];
+      const int r0 = ht.row0[uh];
+      const float* W2c = params + ht.off[uh] + kHid * kIn + kHid + ujj;
+      constexpr int NA = kMidAnchors / 2;
+      float dh[NA];
 #pragma unroll
-  for (int c = 0; c < kHid; ++c) { gW2a[c] = 0.f; gW2b[c] = 0.f; }
-  // first-layer unit j = t % 160 over the anchors of half t / 160
-  float gW1[kIn], gb1 = 0.f;
+      for (int q = 0; q < NA; ++q) dh[q] = 0.f;
+      for (int oh = 0; oh < rows; ++oh) {
+        const float wgt = W2c[oh * kHid];
 #pragma unroll
-  for (int c = 0; c < kIn; ++c) gW1[c] = 0.f;
-  const int j = t % 160, half = t / 160;
-  const bool has_unit = j < ht.nunits && half < 2;
-  const int uh = j / kHid, ujj = j % kHid;
-
-  for (int bt = 0; bt < kDecBatches; ++bt) {
-    const int64_t a0 = ((int64_t)blockIdx.x * kDecBatches + bt) * kDecAnchors;
-    if (a0 >= A) break;
-    for (int view = 0; view < dc.n_views; ++view) {
-      __syncthreads();
-      load_inputs<kDecAnchors>(xyz, feat, A, a0, dv.c[view], X, dist);
-      __syncthreads();
-      layer1<kDecAnchors>(params, ht, X, H, Zs);
-      __syncthreads();
-      // second layer: recompute y, form dL/dy, accumulate dW2, db2
-      for (int r = 0; r < 2; ++r) {
-        const int o = t + r * kDecThreads;
-        if (o >= nrows) break;
-        const int h = row_head(ht, o);
-        const int oh = o - ht.row0[h];
-        const int m = ht.m[h];
-        const int i = oh / m, comp = oh - i * m;
-        const float* W2 = params + ht.off[h] + kHid * kIn + kHid + oh * kHid;
-        const float b2 = params[ht.off[h] + kHid * kIn + kHid + k * m * kHid + oh];
-        const float* plane = out_plane(dg, view, h, comp, n);
-        for (int a = 0; a < kDecAnchors; ++a) {
-          float g = 0.f;
-          if (a0 + a < A) {
-            float y = b2;
-#pragma unroll
-            for (int c = 0; c < kHid; ++c) y = fmaf(W2[c], H[a * kHeads + h][c], y);
-            g = plane[(a0 + a) * k + i] * act_grad(h, y, dc.l_s);
-          }
-          dY[a][o] = g;
-          if (r == 0) {
-            gb2a += g;
-#pragma unroll
-            for (int c = 0; c < kHid; ++c) gW2a[c] = fmaf(g, H[a * kHeads + h][c], gW2a[c]);
-          } else {
-            gb2b += g;
-#pragma unroll
-            for (int c = 0; c < kHid; ++c) gW2b[c] = fmaf(g, H[a * kHeads + h][c], gW2b[c]);
-          }
-        }
+        for (int q = 0; q < NA; ++q) dh[q] = fmaf(wgt, sdY[half * NA + q][r0 + oh], dh[q]);
       }
-      __syncthreads();
-      // dH = W2^T dY, dZ = dH * act'(Z); accumulate dW1, db1
-      if (has_unit) {
-        const int m = ht.m[uh];
-        const int rows = k * m;
-        const float* W2c = params + ht.off[uh] + kHid * kIn + kHid + ujj;  // column ujj, stride 32
-        for (int a = half * (kDecAnchors / 2); a < (half + 1) * (kDecAnchors / 2); ++a) {
-          float dh = 0.f;
-          const int r0 = ht.row0[uh];
-          for (int oh = 0; oh < rows; ++oh) dh = fmaf(W2c[oh * kHid], dY[a][r0 + oh], dh);
-          const float z = Zs[a * kHeads + uh][ujj];
-          const float dz = (uh == 4) ? dh * sigm(z) : (z > 0.f ? dh : 0.f);
-          dZ[a * kHeads + uh][ujj] = dz;
-          if (a0 + a < A) {
-            gb1 += dz;
 #pragma unroll
-            for (int c = 0; c < kIn; ++c) gW1[c] = fmaf(dz, X[a][c], gW1[c]);
-          }
-        }
-      }
-      __syncthreads();
-      // dX = W1^T dZ over the present heads
-      for (int e = t; e < kDecAnchors * kIn; e += kDecThreads) {
-        const int a = e / kIn, c = e - a * kIn;
-        float s = 0.f;
-        for (int h = 0; h < kHeads; ++h) {
-          if (ht.m[h] == 0) continue;
-          const float* W1 = params + ht.off[h] + c;
-          for (int jj = 0; jj < kHid; ++jj) s = fmaf(W1[jj * kIn], dZ[a * kHeads + h][jj], s);
-        }
-        dXs[a][c] = s;
-      }
-      __syncthreads();
-      // anchor feature / position gradients and the camera-centre term
-      float dcl[3] = {0.f, 0.f, 0.f};
-      for (int e = t; e < kDecAnchors * 32; e += kDecThreads) {
-        const int a = e / 32, c = e % 32;
+      for (int q = 0; q < NA; ++q) {
+        const int a = half * NA + q;
+        float dz = 0.f;
         if (a0 + a < A) {
-          float* p = &d_feat[(a0 + a) * 32 + c];
-          *p = (view == 0 ? 0.f : *p) + dXs[a][c];
+          const float hv = w.H[(a0 + a) * 160 + j];
+          dz = (uh == 4) ? dh[q] * (1.f - expf(-hv)) : (hv > 0.f ? dh[q] : 0.f);
+          w.dZ[(a0 + a) * 160 + j] = dz;
         }
-      }
-      if (t < kDecAnchors && a0 + t < A) {
-        const int a = t;
-        const float d = dist[a];
-        const float* del = &X[a][32];
-        const float* gd = &dXs[a][32];
-        const float pr = del[0] * gd[0] + del[1] * gd[1] + del[2] * gd[2];
-        for (int c = 0; c < 3; ++c) {
-          const float dD = (gd[c] - del[c] * pr) / d;
-          float* p = &d_xyz[c * A + a0 + a];
-          *p = (view == 0 ? 0.f : *p) + dD;
-          dcl[c] = -dD;
-        }
-      }
-      for (int c = 0; c < 3; ++c) {
-        float x = dcl[c];
-        for (int o2 = 32; o2 > 0; o2 >>= 1) x += __shfl_xor(x, o2);
-        if (lane == 0) dcs[c][wv] = x;
-      }
-      __syncthreads();
-      if (t < 3) {
-        float s = 0.f;
-        for (int w = 0; w < kDecThreads / 64; ++w) s += dcs[t][w];
-        float* p = &dcpart[((int64_t)blockIdx.x * dc.n_views + view) * 3 + t];
-        *p = (bt == 0 ? 0.f : *p) + s;
+        sdZ[a][j] = dz;
       }
     }
-    // mean gradients (summed over views): d_off = l_o dmu, d_xyz += sum_i dmu
-    __syncthreads();
-    for (int e = t; e < kDecAnchors * 3; e += kDecThreads) {
-      const int a = e / 3, c = e % 3;
-      if (a0 + a >= A) continue;
-      float sx = 0.f;
-      for (int i = 0; i < k; ++i) {
-        const int64_t gn = (a0 + a) * k + i;
-        float s = 0.f;
-        for (int view = 0; view < dc.n_views; ++view) s += dg.mean[view * dg.view_stride[0] + c * n + gn];
-        d_off[c * n + gn] = dc.l_o * s;
-        sx += s;
-      }
-      d_xyz[c * A + a0 + a] += sx;
+  }
+  __syncthreads();
+  // dX = W1^T dZ
+  for (int e = t; e < kMidAnchors * kIn; e += kDecThreads) {
+    const int a = e / kIn, c = e - a * kIn;
+    float sx = 0.f;
+    for (int h = 0; h < kHeads; ++h) {
+      if (ht.m[h] == 0) continue;
+      const float* W1 = params + ht.off[h] + c;
+#pragma unroll 8
+      for (int jj = 0; jj < kHid; ++jj) sx = fmaf(W1[jj * kIn], sdZ[a][h * kHid + jj], sx);
+    }
+    sdX[a][c] = sx;
+  }
+  __syncthreads();
+  for (int e = t; e < kMidAnchors * 32; e += kDecThreads) {
+    const int a = e / 32, c = e % 32;
+    if (a0 + a < A) {
+      float* p = &d_feat[(a0 + a) * 32 + c];
+      *p = (view == 0 ? 0.f : *p) + sdX[a][c];
     }
   }
-  // workgroup partials of the weight gradients, packed like the parameters
-  float* P = part + (int64_t)blockIdx.x * dc.n_params;
-  for (int r = 0; r < 2; ++r) {
-    const int o = t + r * kDecThreads;
-    if (o >= nrows) break;
-    const int h = row_head(ht, o);
-    const int oh = o - ht.row0[h];
-    const int m = ht.m[h];
-    float* W2p = P + ht.off[h] + kHid * kIn + kHid + oh * kHid;
-#pragma unroll
-    for (int c = 0; c < kHid; ++c) W2p[c] = r == 0 ? gW2a[c] : gW2b[c];
-    P[ht.off[h] + kHid * kIn + kHid + k * m * kHid + oh] = r == 0 ? gb2a : gb2b;
+  float dcl[3] = {0.f, 0.f, 0.f};
+  if (t < kMidAnchors && a0 + t < A) {
+    const int64_t a = a0 + t;
+    float D[3];
+    for (int c = 0; c < 3; ++c) D[c] = xyz[c * A + a] - dv.c[view][c];
+    const float d = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    float del[3];
+    for (int c = 0; c < 3; ++c) del[c] = D[c] / d;
+    const float* gd = &sdX[t][32];
+    const float pr = del[0] * gd[0] + del[1] * gd[1] + del[2] * gd[2];
+    for (int c = 0; c < 3; ++c) {
+      const float dD = (gd[c] - del[c] * pr) / d;
+      float* p = &d_xyz[c * A + a];
+      *p = (view == 0 ? 0.f : *p) + dD;
+      dcl[c] = -dD;
+    }
   }
-  // two threads share each first-layer unit: combine through LDS
-  __syncthreads();
-  static_assert(kBwdAnchors * (kMaxRows + 1) >= 160 * (kIn + 1), "dY too small for reuse");
-  float* comb = &dY[0][0];  // reuse: 160 x 36 floats
-  if (has_unit && half == 1) {
-#pragma unroll
-    for (int c = 0; c < kIn; ++c) comb[j * (kIn + 1) + c] = gW1[c];
-    comb[j * (kIn + 1) + kIn] = gb1;
+  for (int c = 0; c < 3; ++c) {
+    float x = dcl[c];
+    for (int o2 = 32; o2 > 0; o2 >>= 1) x += __shfl_xor(x, o2);
+    if (lane == 0) red[c][wv] = x;
   }
   __syncthreads();
-  if (has_unit && half == 0) {
-    float* W1p = P + ht.off[uh] + ujj * kIn;
-#pragma unroll
-    for (int c = 0; c < kIn; ++c) W1p[c] = gW1[c] + comb[j * (kIn + 1) + c];
-    P[ht.off[uh] + kHid * kIn + ujj] = gb1 + comb[j * (kIn + 1) + kIn];
+  if (t < 3) {
+    float sum = 0.f;
+    for (int q = 0; q < kDecThreads / 64; ++q) sum += red[t][q];
+    w.dcpart[((int64_t)blockIdx.x * dc.n_views + view) * 3 + t] = sum;
   }
 }
 
-// Fixed-order reduction of the workgroup partials; adds -R_cw dL/dc to the
-// translation part of the pose gradient.
-__global__ void k_decode_reduce(DecodeConst dc, DecodeViews dv, const float* part, const float* dcpart,
-                                int nblk, float* d_params, float* d_pose) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < dc.n_params) {
+// Mean gradients summed over views: d_off = l_o dmu, d_xyz += sum_i dmu.
+__global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, float* d_off) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t A = dc.A;
+  const int k = dc.k;
+  const int64_t n = A * k;
+  if (e >= A * 3) return;
+  const int c = (int)(e / A);
+  const int64_t a = e - c * A;
+  float sx = 0.f;
+  for (int i = 0; i < k; ++i) {
+    const int64_t gn = a * k + i;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * dc.n_params + p];
-    d_params[p] = s;
-  } else if (d_pose && p < dc.n_params + dc.n_views * 3) {
-    const int e = (int)(p - dc.n_params);
-    const int view = e / 3, r = e % 3;
-    float g[3] = {0.f, 0.f, 0.f};
-    for (int b = 0; b < nblk; ++b)
-      for (int c = 0; c < 3; ++c) g[c] += dcpart[((int64_t)b * dc.n_views + view) * 3 + c];
-    const float* R = dv.R[view];
-    d_pose[view * 6 + r] += -(R[r * 3 + 0] * g[0] + R[r * 3 + 1] * g[1] + R[r * 3 + 2] * g[2]);
+    for (int view = 0; view < dc.n_views; ++view) s += dg.mean[view * dg.view_stride[0] + c * n + gn];
+    d_off[c * n + gn] = dc.l_o * s;
+    sx += s;
+  }
+  d_xyz[c * A + a] += sx;
+}
+
+// Weight gradients of one view, accumulated into per-workgroup partials.
+// Tasks: dW2 rows x 16-column halves, dW1 units x 12-column thirds of the
+// 36-wide (padded) input, and the bias sums.
+__global__ void __launch_bounds__(kWThreads) k_dec_bwd_wgrad(DecodeConst dc, HeadTable ht, int view, DecWork w) {
+  __shared__ float sY[kWSub][kMaxRows + 4];
+  __shared__ float sH[kWSub][160];
+  __shared__ float sZ[kWSub][160];
+  __shared__ float sX[kWSub][36];
+  constexpr int TPT = 2;   // tile tasks per thread (max): 2 * 432 + 3 * 160 <= 2 * 1024
+  const int t = threadIdx.x;
+  const int64_t A = dc.A;
+  const int nrows = ht.nrows, nunits = ht.nunits;
+  const int t2 = nrows * 2;         // dW2 tasks
+  const int t1 = nunits * 3;        // dW1 tasks
+  const int tt = t2 + t1;
+  const int nb = nrows + nunits;    // bias tasks
+  float acc[TPT][16];
+#pragma unroll
+  for (int q = 0; q < TPT; ++q)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[q][c] = 0.f;
+  float bacc[1] = {0.f};  // bias tasks: nrows + nunits <= 432 + 160 <= 1024
+  const int64_t c0 = (int64_t)blockIdx.x * kWChunk;
+  for (int64_t s0 = c0; s0 < c0 + kWChunk && s0 < A; s0 += kWSub) {
+    __syncthreads();
+    for (int e = t; e < kWSub * nrows; e += kWThreads) {
+      const int a = e / nrows, o = e - a * nrows;
+      sY[a][o] = (s0 + a < A) ? w.dY[(s0 + a) * w.RP + o] : 0.f;
+    }
+    for (int e = t; e < kWSub * 160; e += kWThreads) {
+      const int a = e / 160, j = e - a * 160;
+      const bool ok = s0 + a < A;
+      sH[a][j] = ok ? w.H[(s0 + a) * 160 + j] : 0.f;
+      sZ[a][j] = ok ? w.dZ[(s0 + a) * 160 + j] : 0.f;
+    }
+    for (int e = t; e < kWSub * 36; e += kWThreads) {
+      const int a = e / 36, c = e - a * 36;
+      sX[a][c] = (s0 + a < A) ? w.X[(s0 + a) * 36 + c] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int task = t + q * kWThreads;
+      if (task < t2) {
+        const int o = task >> 1, half = task & 1;
+        const int hseg = row_head(ht, o) * kHid + half * 16;
+        for (int a = 0; a < kWSub; ++a) {
+          const float g = sY[a][o];
+          const float4* hp = reinterpret_cast<const float4*>(&sH[a][hseg]);
+#pragma unroll
+          for (int c4 = 0; c4 < 4; ++c4) {
+            const float4 hv = hp[c4];
+            acc[q][4 * c4 + 0] = fmaf(g, hv.x, acc[q][4 * c4 + 0]);
+            acc[q][4 * c4 + 1] = fmaf(g, hv.y, acc[q][4 * c4 + 1]);
+            acc[q][4 * c4 + 2] = fmaf(g, hv.z, acc[q][4 * c4 + 2]);
+            acc[q][4 * c4 + 3] = fmaf(g, hv.w, acc[q][4 * c4 + 3]);
+          }
+        }
+      } else if (task < tt) {
+        const int u = (task - t2) / 3, third = (task - t2) % 3;
+        for (int a = 0; a < kWSub; ++a) {
+          const float g = sZ[a][u];
+          const float4* xp = reinterpret_cast<const float4*>(&sX[a][third * 12]);
+#pragma unroll
+          for (int c4 = 0; c4 < 3; ++c4) {
+            const float4 xv = xp[c4];
+            acc[q][4 * c4 + 0] = fmaf(g, xv.x, acc[q][4 * c4 + 0]);
+            acc[q][4 * c4 + 1] = fmaf(g, xv.y, acc[q][4 * c4 + 1]);
+            acc[q][4 * c4 + 2] = fmaf(g, xv.z, acc[q][4 * c4 + 2]);
+            acc[q][4 * c4 + 3] = fmaf(g, xv.w, acc[q][4 * c4 + 3]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 1; ++q) {
+      const int b = t + q * kWThreads;
+      if (b < nrows) {
+        for (int a = 0; a < kWSub; ++a) bacc[q] += sY[a][b];
+      } else if (b < nb) {
+        for (int a = 0; a < kWSub; ++a) bacc[q] += sZ[a][b - nrows];
+      }
+    }
+  }
+  // write (view 0) or accumulate (later views) this workgroup's partial
+  float* P = w.part;
+  const int64_t bk = blockIdx.x, nbk = w.nblk_w;
+  const bool add = view > 0;
+  const int k = dc.k;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int task = t + q * kWThreads;
+    if (task < t2) {
+      const int o = task >> 1, half = task & 1;
+      const int h = row_head(ht, o);
+      const int oh = o - ht.row0[h];
+      const int64_t pi = ht.off[h] + kHid * kIn + kHid + oh * kHid + half * 16;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        float* dst = P + part_index(pi + c, bk, nbk);
+        *dst = (add ? *dst : 0.f) + acc[q][c];
+      }
+    } else if (task < tt) {
+      const int u = (task - t2) / 3, third = (task - t2) % 3;
+      const int h = u / kHid, jj = u % kHid;
+      const int64_t pi = ht.off[h] + jj * kIn + third * 12;
+#pragma unroll
+      for (int c = 0; c < 12; ++c)
+        if (third * 12 + c < kIn) {
+          float* dst = P + part_index(pi + c, bk, nbk);
+          *dst = (add ? *dst : 0.f) + acc[q][c];
+        }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 1; ++q) {
+    const int b = t + q * kWThreads;
+    float* dst = nullptr;
+    if (b < nrows) {
+      const int h = row_head(ht, b);
+      const int oh = b - ht.row0[h];
+      dst = P + part_index(ht.off[h] + kHid * kIn + kHid + k * ht.m[h] * kHid + oh, bk, nbk);
+    } else if (b < nb) {
+      const int u = b - nrows;
+      dst = P + part_index(ht.off[u / kHid] + kHid * kIn + (u % kHid), bk, nbk);
+    }
+    if (dst) *dst = (add ? *dst : 0.f) + bacc[q];
+  }
+}
+
+// Fixed-order reduction of the workgroup partials: 64 parameters per
+// workgroup, four threads per parameter (each a strided quarter of the
+// partials, four independent sums), combined in LDS. The extra workgroup
+// adds -R_cw dL/dc to the translation part of the pose gradient.
+__global__ void __launch_bounds__(256) k_decode_reduce(DecodeConst dc, DecodeViews dv, DecWork w, float* d_params,
+                                                       float* d_pose) {
+  __shared__ float red[4][64];
+  const int t = threadIdx.x;
+  const int pl = t & 63, q = t >> 6;
+  const int64_t p = (int64_t)blockIdx.x * 64 + pl;
+  const int64_t nparam_blocks = (dc.n_params + 63) / 64;
+  if ((int64_t)blockIdx.x < nparam_blocks) {
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    if (p < dc.n_params) {
+      int b = q;
+      for (; b + 12 < w.nblk_w; b += 16) {
+        s0 += w.part[part_index(p, b, w.nblk_w)];
+        s1 += w.part[part_index(p, b + 4, w.nblk_w)];
+        s2 += w.part[part_index(p, b + 8, w.nblk_w)];
+        s3 += w.part[part_index(p, b + 12, w.nblk_w)];
+      }
+      for (; b < w.nblk_w; b += 4) s0 += w.part[part_index(p, b, w.nblk_w)];
+    }
+    red[q][pl] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (q == 0 && p < dc.n_params) d_params[p] = (red[0][pl] + red[1][pl]) + (red[2][pl] + red[3][pl]);
+    return;
+  }
+  if (!d_pose) return;
+  // camera-centre gradient: every thread sums a strided share of the
+  // per-workgroup partials, then a block reduction per (view, component)
+  for (int view = 0; view < dc.n_views; ++view) {
+    float g[3];
+    for (int c = 0; c < 3; ++c) {
+      float acc = 0.f;
+      for (int b = t; b < w.nblk_m; b += blockDim.x) acc += w.dcpart[((int64_t)b * dc.n_views + view) * 3 + c];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      __syncthreads();
+      if ((t & 63) == 0) red[t >> 6][0] = acc;
+      __syncthreads();
+      g[c] = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    }
+    if (t < 3) {
+      const float* R = dv.R[view];
+      d_pose[view * 6 + t] += -(R[t * 3 + 0] * g[0] + R[t * 3 + 1] * g[1] + R[t * 3 + 2] * g[2]);
+    }
   }
 }
 
@@ -415,9 +584,29 @@ DecodeViews decode_views(const ViewDev* hv, int n_views) {
   return dv;
 }
 
-int64_t bwd_blocks(const DecodeConst& dc) {
-  const int64_t per = (int64_t)kBwdAnchors * kDecBatches;
-  return (dc.A + per - 1) / per;
+struct WorkSizes {
+  int64_t RP, nblk_w, nblk_m;
+  size_t X, H, dY, dZ, part, dcpart, total;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WorkSizes work_sizes(const DecodeConst& dc) {
+  WorkSizes z;
+  int64_t rows = 0;
+  for (int h = 0; h < kHeads; ++h) rows += (int64_t)dc.k * dc.head_m[h];
+  z.RP = (rows + 3) / 4 * 4;
+  z.nblk_w = (dc.A + kWChunk - 1) / kWChunk;
+  z.nblk_m = (dc.A + kMidAnchors - 1) / kMidAnchors;
+  size_t o = 0;
+  z.X = o; o = a256(o + (size_t)dc.A * 36 * 4);
+  z.H = o; o = a256(o + (size_t)dc.A * 160 * 4);
+  z.dY = o; o = a256(o + (size_t)dc.A * z.RP * 4);
+  z.dZ = o; o = a256(o + (size_t)dc.A * 160 * 4);
+  z.part = o; o = a256(o + (size_t)z.nblk_w * ((dc.n_params + 63) / 64 * 64) * 4);
+  z.dcpart = o; o = a256(o + (size_t)z.nblk_m * dc.n_views * 3 * 4);
+  z.total = o;
+  return z;
 }
 
 }  // namespace
@@ -442,10 +631,7 @@ DecodeConst decode_const(const asgs_decoder& d, int n_views) {
   return dc;
 }
 
-size_t decode_workspace_bytes(const DecodeConst& dc) {
-  const int64_t nb = bwd_blocks(dc);
-  return (size_t)(nb * dc.n_params + nb * dc.n_views * 3) * sizeof(float) + 256;
-}
+size_t decode_workspace_bytes(const DecodeConst& dc) { return work_sizes(dc).total; }
 
 void launch_decode(const DecodeConst& dc, const float* xyz, const float* feat, const float* off,
                    const float* params, const ViewDev* host_views, const asgs_gaussians& out, hipStream_t s) {
@@ -459,16 +645,33 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
                             const float* params, const ViewDev* host_views, const asgs_gaussians& dg,
                             float* d_xyz, float* d_feat, float* d_off, float* d_params, float* d_pose,
                             void* work, hipStream_t s) {
+  (void)off;
   const HeadTable ht = head_table(dc);
   const DecodeViews dv = decode_views(host_views, dc.n_views);
-  const int64_t nb = bwd_blocks(dc);
-  float* part = reinterpret_cast<float*>(work);
-  float* dcpart = part + nb * dc.n_params;
-  hipLaunchKernelGGL(k_decode_bwd, dim3((unsigned)nb), dim3(kDecThreads), 0, s, dc, ht, dv, xyz, feat, off,
-                     params, dg, d_xyz, d_feat, d_off, part, dcpart);
-  const int64_t tot = dc.n_params + dc.n_views * 3;
-  hipLaunchKernelGGL(k_decode_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, dc, dv, part,
-                     dcpart, (int)nb, d_params, d_pose);
+  const WorkSizes z = work_sizes(dc);
+  char* wb = reinterpret_cast<char*>(work);
+  DecWork w;
+  w.X = reinterpret_cast<float*>(wb + z.X);
+  w.H = reinterpret_cast<float*>(wb + z.H);
+  w.dY = reinterpret_cast<float*>(wb + z.dY);
+  w.dZ = reinterpret_cast<float*>(wb + z.dZ);
+  w.part = reinterpret_cast<float*>(wb + z.part);
+  w.dcpart = reinterpret_cast<float*>(wb + z.dcpart);
+  w.RP = (int32_t)z.RP;
+  w.nblk_w = (int32_t)z.nblk_w;
+  w.nblk_m = (int32_t)z.nblk_m;
+  const unsigned gp = (unsigned)((dc.A + kFwdAnchors - 1) / kFwdAnchors);
+  for (int view = 0; view < dc.n_views; ++view) {
+    hipLaunchKernelGGL(k_dec_bwd_prep, dim3(gp), dim3(kDecThreads), 0, s, dc, ht, dv, xyz, feat, params, dg,
+                       view, w);
+    hipLaunchKernelGGL(k_dec_bwd_mid, dim3((unsigned)z.nblk_m), dim3(kDecThreads), 0, s, dc, ht, dv, xyz,
+                       params, view, w, d_xyz, d_feat);
+    hipLaunchKernelGGL(k_dec_bwd_wgrad, dim3((unsigned)z.nblk_w), dim3(kWThreads), 0, s, dc, ht, view, w);
+  }
+  hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,
+                     d_off);
+  const unsigned nrb = (unsigned)((dc.n_params + 63) / 64) + 1;
+  hipLaunchKernelGGL(k_decode_reduce, dim3(nrb), dim3(256), 0, s, dc, dv, w, d_params, d_pose);
 }
 
 }  // namespace asgs

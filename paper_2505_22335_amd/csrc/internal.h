@@ -15,7 +15,7 @@ constexpr int kGeomStride = 8;       // floats per 2D geometry record: u v A B |
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
-constexpr int kSortIPT = 8;          // items per thread per radix block
+constexpr int kSortIPT = 4;          // items per thread per radix block
 constexpr int kSortItems = kSortThreads * kSortIPT;
 constexpr int kScanThreads = 256;
 constexpr int kScanIPT = 8;

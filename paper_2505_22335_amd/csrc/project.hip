@@ -355,10 +355,9 @@ __global__ void __launch_bounds__(256) k_project_backward(RenderConst rc, asgs_g
       pose[5] = tx * dt1 - ty * dt0 + (Q[1] - Q[3]);
     }
   }
-  // block reduction of the pose partials, then the last block sums the
+  // block reduction of the pose partials; k_pose_reduce then sums the
   // per-block partials of every view in a fixed order
   __shared__ float red[6][256 / 64];
-  __shared__ bool is_last;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -373,26 +372,24 @@ __global__ void __launch_bounds__(256) k_project_backward(RenderConst rc, asgs_g
     const int k = threadIdx.x;
     part[((int64_t)view * nbx + blockIdx.x) * 6 + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
   }
-  if (d_pose == nullptr) return;
-  __threadfence();
-  __syncthreads();
-  unsigned int* cnt = &ctx_ptr<CtxHeader>(ctx, L.hdr)->counters[kCntPose];
-  if (threadIdx.x == 0) {
-    const unsigned int prev = atomicAdd(cnt, 1u);
-    is_last = (prev == gridDim.x * gridDim.y - 1);
+}
+
+// Fixed-order sum of the per-block pose partials of each view.
+__global__ void __launch_bounds__(256) k_pose_reduce(int n_views, int nbx, const float* __restrict__ part,
+                                                     float* d_pose) {
+  __shared__ float fin[256 / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int vv = 0; vv < n_views; ++vv) {
+    for (int k = 0; k < 6; ++k) {
+      float acc = 0.f;
+      for (int bx = threadIdx.x; bx < nbx; bx += blockDim.x) acc += part[((int64_t)vv * nbx + bx) * 6 + k];
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      __syncthreads();
+      if (lane == 0) fin[wv] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) d_pose[vv * 6 + k] = (fin[0] + fin[1]) + (fin[2] + fin[3]);
+    }
   }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  for (int t = threadIdx.x; t < rc.n_views * 6; t += blockDim.x) {
-    const int vv = t / 6, k = t % 6;
-    float acc = 0.f;
-    for (int bx = 0; bx < nbx; ++bx)
-      acc += __hip_atomic_load(&part[((int64_t)vv * nbx + bx) * 6 + k], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    d_pose[vv * 6 + k] = acc;
-  }
-  if (threadIdx.x == 0) *cnt = 0u;
 }
 
 }  // namespace
@@ -426,6 +423,9 @@ void launch_project_backward(const RenderConst& rc, const asgs_gaussians& g, con
     hipLaunchKernelGGL(k_project_backward<16>, grid, dim3(256), 0, s, rc, g, dg, d_pose, views, ctx, L);
   else
     hipLaunchKernelGGL(k_project_backward<0>, grid, dim3(256), 0, s, rc, g, dg, d_pose, views, ctx, L);
+  if (d_pose)
+    hipLaunchKernelGGL(k_pose_reduce, dim3(1), dim3(256), 0, s, rc.n_views, (int)grid.x,
+                       reinterpret_cast<const float*>(ctx + L.posepart), d_pose);
 }
 
 }  // namespace asgs

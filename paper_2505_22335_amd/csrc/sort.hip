@@ -10,10 +10,13 @@
 // result equals a stable LSD sort of the full keys of the Gaussian-major
 // list.
 //
-// Each pass is two kernels: an upsweep (per-block 256-bin digit histogram;
-// the last block to finish scans all histograms, digit-major) and a stable
-// scatter (wave ballots find lanes with equal digits; ranks follow item
-// order within a wave, across the block's waves, and across blocks).
+// Each pass is two kernels: an upsweep (per-block 256-bin digit histogram,
+// stored block-major) and a stable scatter. Every scatter block derives its
+// own digit offsets from the histograms (digit totals over all blocks plus
+// the counts of the blocks before it), so no grid-wide fence or extra scan
+// launch is needed. Within a block, wave ballots find lanes with equal
+// digits; ranks follow item order within a wave, across the block's waves
+// and across its rounds.
 #include "internal.h"
 
 namespace asgs {
@@ -46,75 +49,24 @@ ASGS_DEV uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Exclusive scan of data[0..len) in place by one block of kScanThreads,
-// through device-coherent loads; returns the total.
-ASGS_DEV uint64_t block_exclusive_scan_global(uint32_t* data, uint64_t len) {
-  __shared__ unsigned long long part[kScanThreads];
-  const int t = threadIdx.x;
-  const uint64_t chunk = (len + kScanThreads - 1) / kScanThreads;
-  const uint64_t lo = t * chunk;
-  const uint64_t hi = lo + chunk < len ? lo + chunk : len;
-  unsigned long long s = 0;
-  for (uint64_t i = lo; i < hi; ++i)
-    s += __hip_atomic_load(&data[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  part[t] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the per-thread sums
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    unsigned long long v = t >= off ? part[t - off] : 0ull;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  unsigned long long run = t > 0 ? part[t - 1] : 0ull;
-  const unsigned long long total = part[kScanThreads - 1];
-  for (uint64_t i = lo; i < hi; ++i) {
-    const uint32_t v = __hip_atomic_load(&data[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    data[i] = (uint32_t)run;
-    run += v;
-  }
-  return total;
-}
-
-// Marks this block done; returns true in every thread of the last block.
-ASGS_DEV bool last_block_done(unsigned int* counter) {
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned int prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (last) __threadfence();
-  return last;
-}
-
 __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(RadixArgs a) {
   __shared__ uint32_t lh[kRadixBins];
   const uint64_t n = item_count(a);
   const uint64_t nb = (n + kSortItems - 1) / kSortItems;
   const uint64_t b = blockIdx.x;
+  if (b >= nb) return;
   lh[threadIdx.x] = 0u;
   __syncthreads();
-  if (b < nb) {
 #pragma unroll
-    for (int r = 0; r < kSortIPT; ++r) {
-      const uint64_t idx = b * kSortItems + (uint64_t)r * kSortThreads + threadIdx.x;
-      if (idx < n) {
-        const uint32_t k = a.keys_in[idx];
-        if (!a.filter || k != kInvalidKey) atomicAdd(&lh[(k >> a.shift) & (kRadixBins - 1)], 1u);
-      }
+  for (int r = 0; r < kSortIPT; ++r) {
+    const uint64_t idx = b * kSortItems + (uint64_t)r * kSortThreads + threadIdx.x;
+    if (idx < n) {
+      const uint32_t k = a.keys_in[idx];
+      if (!a.filter || k != kInvalidKey) atomicAdd(&lh[(k >> a.shift) & (kRadixBins - 1)], 1u);
     }
   }
   __syncthreads();
-  if (b < nb) a.hist[(uint64_t)threadIdx.x * nb + b] = lh[threadIdx.x];
-  if (!last_block_done(a.counter)) return;
-  const uint64_t total = block_exclusive_scan_global(a.hist, (uint64_t)kRadixBins * nb);
-  if (threadIdx.x == 0) {
-    if (a.total_out) *a.total_out = total;
-    *a.counter = 0u;
-  }
+  a.hist[b * kRadixBins + threadIdx.x] = lh[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(RadixArgs a) {
@@ -127,7 +79,28 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(RadixArgs a) {
   if (b >= nb) return;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
-  base[t] = a.hist[(uint64_t)t * nb + b];
+  // digit offsets of this block: exclusive scan of the digit totals over all
+  // blocks, plus the counts of digit t in the blocks before this one
+  {
+    uint32_t tot = 0u, pre = 0u;
+    for (uint64_t bb = 0; bb < nb; ++bb) {
+      const uint32_t c = a.hist[bb * kRadixBins + t];
+      tot += c;
+      pre += bb < b ? c : 0u;
+    }
+    run[t] = tot;
+    __syncthreads();
+    for (int off = 1; off < kRadixBins; off <<= 1) {
+      const uint32_t v = t >= off ? run[t - off] : 0u;
+      __syncthreads();
+      run[t] += v;
+      __syncthreads();
+    }
+    base[t] = run[t] - tot + pre;
+    if (b == 0 && t == kRadixBins - 1 && a.total_out) *a.total_out = run[t];
+    __syncthreads();
+  }
+  (void)lane;
   run[t] = 0u;
   for (int r = 0; r < kSortIPT; ++r) {
     const uint64_t idx = b * kSortItems + (uint64_t)r * kSortThreads + t;
@@ -179,6 +152,7 @@ void radix_pass(const RadixArgs& a, uint64_t max_items, hipStream_t s) {
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kScanThreads) k_dup_upsweep(RenderConst rc, char* ctx, CtxLayout L) {
   __shared__ unsigned long long red[kScanThreads / 64];
+  (void)rc;
   CtxHeader* hdr = ctx_ptr<CtxHeader>(ctx, L.hdr);
   const uint64_t m = __hip_atomic_load(&hdr->n_visible, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint64_t nb = (m + kScanItems - 1) / kScanItems;
@@ -200,13 +174,6 @@ __global__ void __launch_bounds__(kScanThreads) k_dup_upsweep(RenderConst rc, ch
     unsigned long long tot = 0;
     for (int w = 0; w < kScanThreads / 64; ++w) tot += red[w];
     bsum[b] = (uint32_t)tot;
-  }
-  if (!last_block_done(&hdr->counters[kCntScan])) return;
-  const uint64_t total = block_exclusive_scan_global(bsum, nb);
-  if (threadIdx.x == 0) {
-    hdr->n_isect = total;
-    hdr->overflow = total > (uint64_t)rc.cap ? 1u : 0u;
-    hdr->counters[kCntScan] = 0u;
   }
 }
 
@@ -236,6 +203,32 @@ __global__ void __launch_bounds__(kScanThreads) k_dup_emit(RenderConst rc, const
     cnt[r] = j < m ? ntiles[ids[j]] : 0u;
     mine += cnt[r];
   }
+  // sums of the blocks before this one (and, in block 0, of all blocks)
+  __shared__ unsigned long long bred[kScanThreads / 64];
+  __shared__ unsigned long long bbase, btotal;
+  {
+    unsigned long long pre = 0, tot = 0;
+    for (uint64_t bb = threadIdx.x; bb < nb; bb += kScanThreads) {
+      const uint32_t v = bsum[bb];
+      tot += v;
+      pre += bb < b ? v : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
+    if ((threadIdx.x & 63) == 0) bred[threadIdx.x >> 6] = pre;
+    __syncthreads();
+    if (threadIdx.x == 0) bbase = bred[0] + bred[1] + bred[2] + bred[3];
+    __syncthreads();
+    if (b == 0) {
+      for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+      if ((threadIdx.x & 63) == 0) bred[threadIdx.x >> 6] = tot;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        btotal = bred[0] + bred[1] + bred[2] + bred[3];
+        hdr->n_isect = btotal;
+        hdr->overflow = btotal > (uint64_t)rc.cap ? 1u : 0u;
+      }
+    }
+  }
   tsum[threadIdx.x] = mine;
   __syncthreads();
   for (int off = 1; off < kScanThreads; off <<= 1) {
@@ -244,7 +237,7 @@ __global__ void __launch_bounds__(kScanThreads) k_dup_emit(RenderConst rc, const
     tsum[threadIdx.x] += v;
     __syncthreads();
   }
-  uint64_t off = (uint64_t)bsum[b] + (threadIdx.x > 0 ? tsum[threadIdx.x - 1] : 0u);
+  uint64_t off = bbase + (threadIdx.x > 0 ? tsum[threadIdx.x - 1] : 0u);
   const uint64_t cap = (uint64_t)rc.cap;
   for (int r = 0; r < kScanIPT; ++r) {
     const uint64_t j = j0 + r;
@@ -306,7 +299,7 @@ void launch_depth_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hip
     a.shift = 8 * p;
     a.filter = p == 0;
     a.hist = reinterpret_cast<uint32_t*>(ctx + L.hist);
-    a.counter = &hdr->counters[kCntDepth0 + p];
+      a.counter = nullptr;
     a.total_out = p == 0 ? &hdr->n_visible : nullptr;
     radix_pass(a, (uint64_t)rc.nv, s);
   }
@@ -334,7 +327,7 @@ void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipS
     a.shift = 8 * p;
     a.filter = 0;
     a.hist = reinterpret_cast<uint32_t*>(ctx + L.hist);
-    a.counter = &hdr->counters[kCntTile0 + p];
+    a.counter = nullptr;
     a.total_out = nullptr;
     radix_pass(a, (uint64_t)rc.cap, s);
   }
