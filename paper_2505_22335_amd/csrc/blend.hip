@@ -8,32 +8,15 @@
 // (rgb, z, feature). The workgroup leaves as soon as every pixel has stopped.
 //
 // The backward replays each pixel's list back to front from its last
-// composited Gaussian, recovering T_k = T_{k+1} / (1 - alpha_k). Per list entry
-// the 26 gradient values (u, v, conic, opacity, channels) of the 256 pixels are
-// summed over each 16-lane row with DPP (skipped by ballot when no lane of the
-// wave touches the Gaussian), the 16 row sums of the workgroup are combined in
-// LDS and written once to the entry's gradient slot; no global atomics. The
-// projection backward then sums each Gaussian's slots.
+// composited Gaussian, recovering T_k = T_{k+1} / (1 - alpha_k), and sums each
+// entry's gradient over the tile's pixels on the matrix cores (see
+// k_blend_bwd); every entry's gradient slot is written once, without global
+// atomics. The projection backward then sums each Gaussian's slots.
 #include "internal.h"
 
 namespace asgs {
 
 namespace {
-
-template <int CTRL>
-ASGS_DEV float dpp(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-
-// Sum over each row of 16 lanes; every lane of a row receives its row's sum.
-// All lanes must be active.
-ASGS_DEV float row_sum(float x) {
-  x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp<0x124>(x);  // row_ror:4
-  x += dpp<0x128>(x);  // row_ror:8
-  return x;
-}
 
 ASGS_DEV int find_view(const ViewDev* views, int n_views, int tile) {
   int v = 0;
@@ -134,8 +117,27 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   ctx_ptr<uint32_t>(ctx, L.ncontrib)[pb + pix] = last;
 }
 
-constexpr int kBwdBatch = 16;
+constexpr int kBwdBatch = 16;  // list entries per MFMA tile (M = 16)
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+ASGS_DEV f4v mfma4(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// Backward compositing, one workgroup per tile, one pixel per thread.
+//
+// Per list entry k and pixel p the gradient contributions are
+//   dL/dc_k      += w_kp G_p                 (w = alpha T, G = upstream channel gradients)
+//   dL/dpower_kp  = dL/dalpha_kp * alpha_kp  (0 when alpha is clamped)
+//   dL/do_k      += dL/dpower_kp / o_k
+//   dL/du_k       = -sum_p dpow (A dx + B dy), ...  with dx = u - px, dy = v - py
+// so the per-entry sums over the tile's pixels are dot products of two
+// per-pixel coefficients (w, dpow) with fixed per-pixel features: the
+// channel gradients G_p and the moments (1, lx, ly, lx^2, lx ly, ly^2) of the
+// tile-local pixel coordinates, from which the conic and position gradients
+// follow in closed form. Each wave writes its 64 pixels' coefficients for 16
+// entries to LDS and contracts them on the matrix cores (16x16x4 FP32 MFMA,
+// K = pixels); the four waves' 16x26 partials are summed in LDS and written
+// once to each entry's gradient slot.
 template <int NF>
 __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const ViewDev* __restrict__ views,
                                                         char* ctx, CtxLayout L, asgs_images dout) {
@@ -143,6 +145,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   constexpr int CS4 = CS / 4;
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
+  constexpr int CP = 17;          // padded row of 16 coefficients
   const int tile = blockIdx.x;
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
@@ -150,8 +153,9 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   const int ty = lt / V.TX, tx = lt - ty * V.TX;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
-  const int px = tx * kTile + (t & (kTile - 1));
-  const int py = ty * kTile + (t / kTile);
+  const int x0 = tx * kTile, y0 = ty * kTile;
+  const int px = x0 + (t & (kTile - 1));
+  const int py = y0 + (t / kTile);
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
@@ -162,16 +166,14 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
   float* gslot = ctx_ptr<float>(ctx, L.gslot);
 
-  constexpr int NR = NW * 4;  // 16-lane rows per workgroup
   __shared__ float4 sg[kBwdBatch * 2];
   __shared__ float4 sc[kBwdBatch * CS4];
-  // row partials, row index innermost (+1 pad) so the four row leaders of a
-  // wave hit four different banks
-  __shared__ float part[kBwdBatch][GS][NR + 1];
+  __shared__ float cw[NW][64 * CP];     // w of (pixel, entry), per wave
+  __shared__ float cp[NW][64 * CP];     // dL/dpower of (pixel, entry), per wave
+  __shared__ float part[NW][kBwdBatch][32];
   __shared__ uint32_t smax;
 
   const size_t HW = (size_t)V.W * V.H;
-  const size_t pix = (size_t)py * V.W + px;
   const size_t pb = (size_t)V.pix_base;
   float Tf = 1.f;
   uint32_t last = 0;
@@ -180,6 +182,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   for (int c = 0; c < CS; ++c) G[c] = 0.f;
   float GT = 0.f;
   if (inside) {
+    const size_t pix = (size_t)py * V.W + px;
     Tf = ctx_ptr<const float>(ctx, L.tfinal)[pb + pix];
     last = ctx_ptr<const uint32_t>(ctx, L.ncontrib)[pb + pix];
     for (int c = 0; c < 3; ++c) G[c] = dout.rgb[3 * pb + c * HW + pix];
@@ -189,6 +192,34 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
     const float ga = dout.alpha ? dout.alpha[pb + pix] : 0.f;
     GT = rc.bg[0] * G[0] + rc.bg[1] * G[1] + rc.bg[2] * G[2] - ga;
   }
+  // B operands of the MFMAs: K-step s covers pixels 4s..4s+3 of this wave;
+  // lane l supplies feature (l % 16) of pixel 4s + l / 16.
+  const int fcol = lane & 15;
+  float bG0[16], bG1[16], bM[16];
+#pragma unroll
+  for (int s4 = 0; s4 < 16; ++s4) {
+    const int q = 64 * wv + 4 * s4 + (lane >> 4);  // tile-local pixel
+    const int lx = q & 15, ly = q >> 4;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool in = gx < V.W && gy < V.H;
+    const size_t pix = (size_t)gy * V.W + gx;
+    float g0 = 0.f, g1 = 0.f;
+    if (in) {
+      const int c0 = fcol;
+      if (c0 < CS) {
+        g0 = c0 < 3 ? dout.rgb[3 * pb + c0 * HW + pix]
+                    : (c0 == 3 ? dout.depth[pb + pix] : dout.feat[NF * pb + (c0 - 4) * HW + pix]);
+      }
+      const int c1 = 16 + fcol;
+      if (c1 < CS) g1 = dout.feat[NF * pb + (c1 - 4) * HW + pix];
+    }
+    bG0[s4] = g0;
+    bG1[s4] = g1;
+    const float fx = (float)lx, fy = (float)ly;
+    bM[s4] = fcol == 0 ? 1.f : fcol == 1 ? fx : fcol == 2 ? fy : fcol == 3 ? fx * fx
+             : fcol == 4 ? fx * fy : fcol == 5 ? fy * fy : 0.f;
+  }
+
   if (t == 0) smax = 0u;
   __syncthreads();
   atomicMax(&smax, last);
@@ -203,6 +234,8 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   float T = Tf;
   float sacc = 0.f;  // sum over later Gaussians of w_l (G . c_l)
   const float amin = rc.alpha_min, amax = rc.alpha_max;
+  float* mycw = &cw[wv][lane * CP];
+  float* mycp = &cp[wv][lane * CP];
   for (int hi = (int)nproc; hi > 0; hi -= kBwdBatch) {
     const int lo = hi - kBwdBatch > 0 ? hi - kBwdBatch : 0;
     const int cnt = hi - lo;
@@ -215,13 +248,9 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
       for (int c = 0; c < CS4; ++c) sc[t * CS4 + c] = chan4[(size_t)gid * CS4 + c];
     }
     __syncthreads();
-    for (int jj = cnt - 1; jj >= 0; --jj) {
-      const int pos = lo + jj;
-      float gv[GS];
-#pragma unroll
-      for (int c = 0; c < GS; ++c) gv[c] = 0.f;
-      bool contrib = false;
-      if ((uint32_t)pos < last) {
+    for (int jj = kBwdBatch - 1; jj >= 0; --jj) {
+      float wgt = 0.f, dpow = 0.f;
+      if (jj < cnt && (uint32_t)(lo + jj) < last) {
         const float4 g0 = sg[2 * jj];
         const float4 g1 = sg[2 * jj + 1];
         float dx, dy;
@@ -231,11 +260,9 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
           const float raw = g1.y * e;
           const float alpha = fminf(amax, raw);
           if (alpha >= amin) {
-            contrib = true;
-            const float oma = 1.f - alpha;
-            const float ioma = __builtin_amdgcn_rcpf(oma);
+            const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
             T = T * ioma;
-            const float w = alpha * T;
+            wgt = alpha * T;
             float dotg = 0.f;
 #pragma unroll
             for (int c4 = 0; c4 < CS4; ++c4) {
@@ -245,40 +272,61 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
               dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
               dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
             }
-#pragma unroll
-            for (int c = 0; c < CS; ++c) gv[6 + c] = w * G[c];
             const float dalpha = T * dotg - (sacc + GT * Tf) * ioma;
-            sacc = fmaf(w, dotg, sacc);
-            if (raw < amax) {
-              const float dp = dalpha * alpha;
-              gv[0] = -dp * (g0.z * dx + g0.w * dy);
-              gv[1] = -dp * (g0.w * dx + g1.x * dy);
-              gv[2] = -0.5f * dp * dx * dx;
-              gv[3] = -dp * dx * dy;
-              gv[4] = -0.5f * dp * dy * dy;
-              gv[5] = dalpha * e;
-            }
+            sacc = fmaf(wgt, dotg, sacc);
+            dpow = raw < amax ? dalpha * alpha : 0.f;
           }
         }
       }
-      const int row = wv * 4 + (lane >> 4);
-      if (__ballot(contrib) != 0ull) {
-#pragma unroll
-        for (int c = 0; c < GS; ++c) {
-          const float s = row_sum(gv[c]);
-          if ((lane & 15) == 0) part[jj][c][row] = s;
-        }
-      } else if ((lane & 15) < GS) {
-        for (int c = lane & 15; c < GS; c += 16) part[jj][c][row] = 0.f;
-      }
+      mycw[jj] = wgt;
+      mycp[jj] = dpow;
     }
     __syncthreads();
-    for (int e = t; e < cnt * GS; e += kTilePix) {
-      const int jj = e / GS, c = e - jj * GS;
-      float s = 0.f;
+    // contract this wave's 64 pixels: C[entry][feature]
+    f4v c1 = {0.f, 0.f, 0.f, 0.f}, c2 = c1, c3 = c1;
+    const float* acw = &cw[wv][0];
+    const float* acp = &cp[wv][0];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) s += part[jj][c][r];
-      gslot[(size_t)pslot[rg.x + lo + jj] * GS + c] = s;
+    for (int s4 = 0; s4 < 16; ++s4) {
+      const int q = 4 * s4 + (lane >> 4);
+      const float aw = acw[q * CP + fcol];
+      const float ap = acp[q * CP + fcol];
+      c1 = mfma4(aw, bG0[s4], c1);
+      if (CS > 16) c2 = mfma4(aw, bG1[s4], c2);
+      c3 = mfma4(ap, bM[s4], c3);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = 4 * (lane >> 4) + r;
+      if (fcol < CS) part[wv][e][fcol] = c1[r];
+      if (CS > 16 && fcol < CS - 16) part[wv][e][16 + fcol] = c2[r];
+      if (fcol < 6) part[wv][e][20 + fcol] = c3[r];
+    }
+    __syncthreads();
+    for (int q = t; q < cnt * GS; q += kTilePix) {
+      const int e = q / GS, c = q - e * GS;
+      float val;
+      if (c >= 6) {
+        const int f = c - 6;
+        val = (part[0][e][f] + part[1][e][f]) + (part[2][e][f] + part[3][e][f]);
+      } else {
+        float M[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+          M[m] = (part[0][e][20 + m] + part[1][e][20 + m]) + (part[2][e][20 + m] + part[3][e][20 + m]);
+        const float4 g0 = sg[2 * e];
+        const float4 g1 = sg[2 * e + 1];
+        const float uu = g0.x - (float)x0, vv = g0.y - (float)y0;  // tile-local centre
+        const float Sdx = uu * M[0] - M[1];
+        const float Sdy = vv * M[0] - M[2];
+        if (c == 0) val = -(g0.z * Sdx + g0.w * Sdy);
+        else if (c == 1) val = -(g0.w * Sdx + g1.x * Sdy);
+        else if (c == 2) val = -0.5f * (uu * uu * M[0] - 2.f * uu * M[1] + M[3]);
+        else if (c == 3) val = -(uu * vv * M[0] - uu * M[2] - vv * M[1] + M[4]);
+        else if (c == 4) val = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
+        else val = M[0] / g1.y;
+      }
+      gslot[(size_t)pslot[rg.x + lo + e] * GS + c] = val;
     }
   }
 }
