@@ -202,7 +202,9 @@ typedef struct asgs_decoder {
   int64_t n_anchors;       /* A >= 1 */
   int32_t k;               /* Gaussians per anchor, 1..16 */
   int32_t n_feat;          /* 0 or 16 (feature head present when 16) */
-  int32_t precision;       /* 0 = FP32, 1 = BF16 operands on matrix cores, FP32 accumulation */
+  int32_t precision;       /* 0 = FP32; 1 = forward with BF16 operands on the matrix cores and FP32
+                              accumulation (n_anchors * k <= 2^27, else ASGS_E_UNSUPPORTED). The
+                              backward always recomputes and differentiates in FP32. */
   float l_o;               /* offset scale (metres) */
   float l_s;               /* scale bound (metres) */
   int32_t reserved;        /* must be 0 */
@@ -248,7 +250,7 @@ enum {
   ASGS_K_BLEND_BWD = 3,    /* backward compositing (one kernel) */
   ASGS_K_PROJECT_BWD = 4,  /* projection backward + pose reduction (one kernel) */
   ASGS_K_DECODE = 5,       /* decoder forward (one kernel) */
-  ASGS_K_DECODE_BWD = 6,   /* decoder backward + parameter reduction (two kernels) */
+  ASGS_K_DECODE_BWD = 6,   /* decoder backward + parameter reduction (several kernels) */
   ASGS_K_NUM = 7
 };
 /* Enable the classes whose bit (1 << class) is set in mask; 0 disables all.

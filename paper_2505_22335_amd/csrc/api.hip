@@ -468,6 +468,8 @@ static int check_decoder(const asgs_decoder* d) {
   if (d->k < 1 || d->k > ASGS_MAX_K) return fail(ASGS_E_UNSUPPORTED, "k must be in 1..%d", ASGS_MAX_K);
   if (d->n_feat != 0 && d->n_feat != 16) return fail(ASGS_E_UNSUPPORTED, "n_feat must be 0 or 16");
   if (d->precision != 0 && d->precision != 1) return fail(ASGS_E_INVALID, "precision must be 0 or 1");
+  if (d->precision == 1 && d->n_anchors * d->k > ((int64_t)1 << 27))
+    return fail(ASGS_E_UNSUPPORTED, "BF16 decode supports at most 2^27 Gaussians (n_anchors * k)");
   if (!isfinite(d->l_o) || !(d->l_s > 0.f) || !isfinite(d->l_s)) return fail(ASGS_E_INVALID, "bad l_o/l_s");
   if (d->reserved != 0) return fail(ASGS_E_INVALID, "decoder.reserved must be 0");
   return ASGS_OK;
@@ -513,7 +515,6 @@ int asgs_decode(const asgs_decoder* d, const float* anchor_xyz, const float* anc
   ViewDev views[ASGS_MAX_VIEWS];
   int st = decode_common(d, anchor_xyz, anchor_feat, anchor_off, params, cams, n_views, views);
   if (st) return st;
-  if (d->precision != 0) return fail(ASGS_E_UNSUPPORTED, "BF16 decode is not built");
   if ((st = check_gauss(out, d->n_feat, n_views, true, "out"))) return st;
   if (out->n != d->n_anchors * d->k) return fail(ASGS_E_INVALID, "out.n must be n_anchors * k");
   const DecodeConst dc = decode_const(*d, n_views);

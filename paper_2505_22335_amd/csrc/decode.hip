@@ -10,69 +10,24 @@
 // FP32 path: a workgroup decodes 32 anchors of one view. The first layer of
 // all heads (160 hidden units) runs with one hidden unit per thread and its
 // weight row in registers, broadcasting anchor inputs from LDS; the second
-// layer runs with one output row per thread over the 32 hidden activations
-// held in LDS. The backward recomputes the forward per anchor batch, keeps
-// per-thread weight-gradient accumulators across the batches of a
-// workgroup, writes one partial per workgroup and reduces the partials in a
-// fixed order (deterministic, no atomics).
+// layer runs with one output row per thread over the hidden activations held
+// in LDS; many small workgroups keep the SIMDs busy. The BF16 path runs on the
+// matrix cores (decode_mfma.hip). The backward (FP32) recomputes the forward,
+// then forms dL/dH from the second-layer weights, dL/dZ through the
+// activations, dL/dX from the first layer, and the weight gradients as
+// per-workgroup outer-product sums reduced in a fixed order (deterministic,
+// no atomics).
 #include <math.h>
 
-#include "internal.h"
+#include "decode_shared.h"
 
 namespace asgs {
 
 namespace {
 
 constexpr int kDecThreads = 320;
-constexpr int kFwdAnchors = 32;     // anchors per forward workgroup
-constexpr int kIn = 35;
-constexpr int kHid = 32;
-constexpr int kHeads = 5;
-constexpr int kMaxRows = ASGS_MAX_K * 27;  // second-layer rows (k * (1+3+3+4+16))
+constexpr int kFwdAnchors = 32;     // anchors per FP32 forward workgroup
 
-struct DecodeViews {
-  float c[ASGS_MAX_VIEWS][3];
-  float R[ASGS_MAX_VIEWS][9];
-};
-
-struct HeadTable {
-  int32_t off[kHeads];      // packed offset of W1 of head h
-  int32_t m[kHeads];        // values per Gaussian (0 = absent)
-  int32_t row0[kHeads + 1]; // first second-layer row of head h (prefix over k*m)
-  int32_t nunits;           // 32 * number of present heads
-  int32_t nrows;
-};
-
-ASGS_DEV float sigm(float y) { return 1.f / (1.f + expf(-y)); }
-ASGS_DEV float softplus(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
-
-// Which head a hidden unit j / output row o belongs to (heads present are a
-// prefix of the fixed order since only the feature head is optional).
-ASGS_DEV int row_head(const HeadTable& ht, int o) {
-  int h = 0;
-  while (h + 1 < kHeads && o >= ht.row0[h + 1]) ++h;
-  return h;
-}
-
-// Output plane pointer and element for head h, Gaussian n, component comp.
-ASGS_DEV float* out_plane(const asgs_gaussians& g, int view, int h, int comp, int64_t n) {
-  switch (h) {
-    case 0: return g.opacity + view * g.view_stride[3];
-    case 1: return g.rgb + view * g.view_stride[4] + comp * n;
-    case 2: return g.scale + view * g.view_stride[1] + comp * n;
-    case 3: return g.rot + view * g.view_stride[2] + comp * n;
-    default: return g.feat + view * g.view_stride[5] + comp * n;
-  }
-}
-
-ASGS_DEV float out_act(int h, float y, float l_s) {
-  switch (h) {
-    case 0:
-    case 1: return sigm(y);
-    case 2: return l_s * sigm(y);
-    default: return y;
-  }
-}
 
 // Load the 32 features and the view direction of anchors a0.. into X.
 template <int kDecAnchors>
@@ -169,16 +124,6 @@ __global__ void __launch_bounds__(kDecThreads) k_decode_fwd(DecodeConst dc, Head
   }
 }
 
-// Gradient of the decoded value of head h w.r.t. its pre-activation y.
-ASGS_DEV float act_grad(int h, float y, float l_s) {
-  switch (h) {
-    case 0:
-    case 1: { const float s = sigm(y); return s * (1.f - s); }
-    case 2: { const float s = sigm(y); return l_s * s * (1.f - s); }
-    default: return 1.f;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Backward, per view, in three stages over a workspace holding, per anchor,
 // X (36 floats: input + pad), H (160 hidden activations), dY (second-layer
@@ -192,17 +137,6 @@ ASGS_DEV float act_grad(int h, float y, float l_s) {
 //          one partial per workgroup (summed over views), then a fixed-order
 //          reduction over workgroups.
 // ---------------------------------------------------------------------------
-struct DecWork {
-  float* X;
-  float* H;
-  float* dY;
-  float* dZ;
-  float* part;    // [nblk_w][n_params]
-  float* dcpart;  // [nblk_m][n_views][3]
-  int32_t RP;     // row stride of dY
-  int32_t nblk_w, nblk_m;
-};
-
 constexpr int kMidAnchors = 16;
 
 // Workgroup partials of the parameter gradients are stored chunk-major: for
@@ -637,6 +571,10 @@ void launch_decode(const DecodeConst& dc, const float* xyz, const float* feat, c
                    const float* params, const ViewDev* host_views, const asgs_gaussians& out, hipStream_t s) {
   const HeadTable ht = head_table(dc);
   const DecodeViews dv = decode_views(host_views, dc.n_views);
+  if (dc.precision == 1) {
+    launch_decode_mfma(dc, ht, dv, xyz, feat, off, params, out, s);
+    return;
+  }
   dim3 grid((unsigned)((dc.A + kFwdAnchors - 1) / kFwdAnchors), (unsigned)dc.n_views);
   hipLaunchKernelGGL(k_decode_fwd, grid, dim3(kDecThreads), 0, s, dc, ht, dv, xyz, feat, off, params, out);
 }

@@ -161,3 +161,59 @@ def test_end_to_end_config2_full():
     e = rel_err(to_np(grads["d_pose"][0]), gr["pose"])
     log("c2 pose %.2e" % e)
     assert e <= GRAD_TOL
+
+
+def test_decode_bf16_matches_bf16_emulation():
+    """BF16 matrix-core decode equals the oracle's bfloat16 emulation (same
+    operand rounding, exact products, float64 sums) up to FP32 accumulation
+    and rare operand-rounding flips; its error against the FP64 decode is
+    logged."""
+    sc = synth.tiny_anchor_scene(91, 300, k=10, n_feat=16)
+    cams = _cams_tiny(2)
+    a = anchors_to_device(sc)
+    dec = P.Decoder(a.A, 10, 16, 1, a.l_o, a.l_s)
+    out = dec.decode(a.xyz, a.feat, a.off, a.params, cams)
+    torch.cuda.synchronize()
+    t = lambda x: torch.as_tensor(np.asarray(x, np.float64))
+    W = {h: {k: t(v) for k, v in w.items()} for h, w in sc.weights.items()}
+    for v, cam in enumerate(cams):
+        R, tc = pose_cw(np.asarray(cam.T_wc, np.float64))
+        c = camera_center(R, tc)
+        g16 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s, precision="bf16")
+        g64 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s)
+        for f in ("opacity", "rgb", "scale", "rot", "feat"):
+            x = to_np(out[f][v])
+            e16 = rel_err(x, g16[f].numpy().T)
+            e64 = rel_err(x, g64[f].numpy().T)
+            log("bf16 decode", v, f, "vs bf16 emulation %.2e" % e16, "vs fp64 %.2e" % e64)
+            assert e16 <= 2e-3, (f, e16)
+            assert e64 <= 3e-2, (f, e64)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", [1, 0])
+def test_config3_error_report(precision):
+    """Config 3: 100k anchors x 10 = 1M Gaussians at 640x480. Rendered maps
+    with the BF16 (1) or FP32 (0) decoder against the FP64 oracle; max and mean
+    errors are logged (the BF16 path's stated error), FP32 must meet 1e-4."""
+    sc, cam, _ = synth.c3()
+    log("case config3 precision", precision)
+    ref = oracle.render_scene(sc, cam, oracle_opts(16), with_margins=True)
+    keep = guard_mask(ref["margins"])
+    r = AnchorRenderer(anchors_to_device(sc), [cam], precision=precision)
+    r.fit()
+    img = r.forward()
+    torch.cuda.synchronize()
+    ni, nvis, ov = r.rc.status()
+    log("config3 intersections", ni, "visible", nvis, "guard-excluded", int((~keep).sum()))
+    for key in ("rgb", "depth", "feat", "alpha"):
+        x = to_np(img[key][0]).astype(np.float64)
+        refk = ref[key]
+        d = np.abs(x - refk)[..., keep]
+        scale = np.abs(refk).max()
+        log("config3 %s precision=%d max_abs %.3e mean_abs %.3e max_rel %.3e mean_rel %.3e" %
+            (key, precision, d.max(), d.mean(), d.max() / scale, d.mean() / scale))
+        if precision == 0:
+            assert d.max() / scale <= IMG_TOL, key
+        else:
+            assert d.max() / scale <= 5e-2, key
