@@ -22,14 +22,23 @@ F64 = torch.float64
 
 
 def composite_tile(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, with_margins=False,
-                   impact_T=1e-3, z32=None):
+                   impact_T=1e-3, z32=None, frozen=None, structure_out=None):
     """Composite K depth-ordered Gaussians over P pixels, vectorised.
 
     u, v, A, B, C, o: (K,) tensors; chans: (K, Cc) tensors (colour, depth,
     feature...); px, py: (P,) float64 pixel coordinates. Returns
     (acc (P,Cc), alpha_sum (P,), T_final (P,), n_contrib (P,) numpy int) and,
     if requested, a dict of per-pixel decision margins for the guard band.
+
+    frozen = (keep, clamped), two (K,P) boolean arrays, replaces the three
+    compositing decisions (skip below alpha_min, clamp at alpha_max, stop
+    below T_min) by the given ones, so that the outputs are a smooth function
+    of the inputs near the point where the decisions were taken
+    (frozen-structure finite differences). With structure_out (a list), the
+    decisions of this call are appended to it in that form.
     """
+    if frozen is not None:
+        return _composite_frozen(u, v, A, B, C, o, chans, px, py, opts, frozen)
     K = u.shape[0]
     P = px.shape[0]
     if K == 0:
@@ -59,6 +68,8 @@ def composite_tile(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, with_margi
     kn = keep.numpy()
     idx = np.arange(1, K + 1)[:, None]
     n_contrib = np.max(np.where(kn, idx, 0), axis=0)
+    if structure_out is not None:
+        structure_out.append((kn.copy(), (raw >= opts.alpha_max).detach().numpy()))
     if not with_margins:
         return acc, alpha_sum, T_final, n_contrib
     # Guard-band margins: relative distance of each decision to its threshold,
@@ -86,6 +97,27 @@ def composite_tile(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, with_margi
             m_tie = np.where(both, gap[:, None], np.inf)
             margins["tie"] = m_tie.min(0)
     return acc, alpha_sum, T_final, n_contrib, margins
+
+
+def _composite_frozen(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, frozen):
+    """Eq. 3 / Eq. 10 with the per-(Gaussian, pixel) decisions given."""
+    keep = torch.as_tensor(np.asarray(frozen[0], bool))
+    clamped = torch.as_tensor(np.asarray(frozen[1], bool))
+    P = px.shape[0]
+    dx = u[:, None] - px[None, :]
+    dy = v[:, None] - py[None, :]
+    power = -0.5 * (A[:, None] * dx * dx + C[:, None] * dy * dy) - B[:, None] * dx * dy
+    raw = o[:, None] * torch.exp(power)
+    alpha = torch.where(clamped, torch.full_like(raw, opts.alpha_max), raw)
+    a = torch.where(keep, alpha, torch.zeros_like(alpha))
+    om = 1.0 - a
+    T_after = torch.cumprod(om, 0)
+    T_before = torch.cat([torch.ones((1, P), dtype=F64), T_after[:-1]], 0)
+    w = a * T_before
+    acc = w.T @ chans
+    idx = np.arange(1, keep.shape[0] + 1)[:, None]
+    n_contrib = np.max(np.where(keep.numpy(), idx, 0), axis=0)
+    return acc, w.sum(0), om.prod(0), n_contrib
 
 
 def composite_bruteforce(u, v, A, B, C, o, z, chans, width, height, opts: RenderOpts):

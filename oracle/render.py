@@ -54,7 +54,7 @@ class Leaves:
 
 
 def render(g: Dict[str, torch.Tensor], R_cw, t_cw, cam, opts: RenderOpts, grad_out=None,
-           with_margins=False, impact_T=1e-3, keep_lists=False):
+           with_margins=False, impact_T=1e-3, keep_lists=False, structure=None, keep_structure=False):
     """Render one view of Gaussians g ((N,c) float64 tensors).
 
     cam: object with width, height, fx, fy, cx, cy. grad_out: optional dict of
@@ -64,6 +64,11 @@ def render(g: Dict[str, torch.Tensor], R_cw, t_cw, cam, opts: RenderOpts, grad_o
 
     Returns a dict of numpy images (rgb, depth, feat, alpha, T_final,
     n_contrib) plus the projection and tile lists.
+
+    keep_structure returns, under 'structure', the tile lists and every
+    compositing decision of this evaluation; passing that back as structure
+    evaluates the same lists with the same decisions at other inputs
+    (frozen-structure finite differences).
     """
     W, H = cam.width, cam.height
     p = project(g["mean"], g["scale"], g["rot"], g["opacity"], R_cw, t_cw, W, H,
@@ -78,7 +83,11 @@ def render(g: Dict[str, torch.Tensor], R_cw, t_cw, cam, opts: RenderOpts, grad_o
     src2d = [p[k] for k in names2d] + [g["opacity"], chans]
     lv = [s.detach().clone().requires_grad_(grad_out is not None) for s in src2d]
     TX, TY = p["tiles_xy"]
-    tiles, gids, ranges = bin_and_sort(p["rect"], p["z32"], p["visible"], TX, TY)
+    if structure is not None:
+        tiles, gids, ranges = structure["tiles"], structure["gids"], structure["ranges"]
+    else:
+        tiles, gids, ranges = bin_and_sort(p["rect"], p["z32"], p["visible"], TX, TY)
+    decisions = {}
 
     acc = np.zeros((H * W, Cc))
     asum = np.zeros(H * W)
@@ -111,14 +120,20 @@ def render(g: Dict[str, torch.Tensor], R_cw, t_cw, cam, opts: RenderOpts, grad_o
             continue
         ids = torch.as_tensor(gids[s:e])
         args = [x[ids] for x in lv]
+        sink = [] if keep_structure else None
         res = composite_tile(*args, torch.as_tensor(pxs, dtype=F64), torch.as_tensor(pys, dtype=F64),
-                             opts, with_margins=with_margins, impact_T=impact_T, z32=p["z32"][gids[s:e]])
+                             opts, with_margins=with_margins and structure is None, impact_T=impact_T,
+                             z32=p["z32"][gids[s:e]],
+                             frozen=None if structure is None else structure["decisions"][t],
+                             structure_out=sink)
+        if keep_structure:
+            decisions[t] = sink[0]
         a_, s_, T_, n_ = res[:4]
         acc[pix] = a_.detach().numpy()
         asum[pix] = s_.detach().numpy()
         Tfin[pix] = T_.detach().numpy()
         ncon[pix] = n_
-        if with_margins:
+        if with_margins and structure is None:
             for k in marg:
                 marg[k][pix] = res[4][k]
         if grad_out is not None:
@@ -146,19 +161,22 @@ def render(g: Dict[str, torch.Tensor], R_cw, t_cw, cam, opts: RenderOpts, grad_o
         out["margins"] = {k: v.reshape(H, W) for k, v in marg.items()}
     if keep_lists:
         out["tiles"], out["gids"], out["ranges"] = tiles, gids, ranges
+    if keep_structure:
+        out["structure"] = dict(tiles=tiles, gids=gids, ranges=ranges, decisions=decisions)
     return out
 
 
 def render_scene(scene, cam, opts: RenderOpts, grad_out=None, pose_grad=False,
                  precision="fp64", with_margins=False, impact_T=1e-3, keep_lists=False,
-                 xi0=None):
+                 xi0=None, structure=None, keep_structure=False):
     """Evaluate a plain scene (synth.PlainScene) or an anchor scene
     (synth.AnchorScene) at camera cam (synth.Camera).
 
     With grad_out, returns (images, grads) where grads holds numpy gradients
     of every input: Gaussian planes ([c][n] like the inputs), anchor inputs,
     head weights, the decoded Gaussians (anchor scenes) and 'pose' (6,) =
-    dL/dxi. xi0 optionally evaluates at Exp(xi0) T_cw (finite differences).
+    dL/dxi. xi0 optionally evaluates at Exp(xi0) T_cw (finite differences);
+    structure / keep_structure as in render.
     """
     need = grad_out is not None
     xi = torch.zeros(6, dtype=F64, requires_grad=need and pose_grad)
@@ -181,7 +199,8 @@ def render_scene(scene, cam, opts: RenderOpts, grad_out=None, pose_grad=False,
         g = gaussians_from_plain(scene, need)
         lv.gauss = g
     out = render(g, R_cw, t_cw, cam, opts, grad_out=grad_out, with_margins=with_margins,
-                 impact_T=impact_T, keep_lists=keep_lists)
+                 impact_T=impact_T, keep_lists=keep_lists, structure=structure,
+                 keep_structure=keep_structure)
     out["gauss"] = {k: v.detach().numpy().T.copy() for k, v in g.items()}
     if not need:
         return out
