@@ -228,7 +228,10 @@ int asgs_decode_workspace_size(const asgs_decoder* d, int32_t n_views, size_t* b
  * mean gradient is summed over views). Writes (overwrites) d_xyz [3][A],
  * d_feat [A][32], d_off [3][A*k], d_params (packed like params); ADDS the
  * camera-centre term of the pose gradient to d_pose [n_views][6] if not
- * NULL (render_backward writes the rest of it). */
+ * NULL (render_backward writes the rest of it). Pose-only mode: with
+ * d_xyz, d_feat, d_off and d_params all NULL only the camera-centre term is
+ * computed (d_pose required); the parameter-gradient kernels are skipped.
+ * Any other mix of NULL outputs is ASGS_E_INVALID. */
 int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const float* anchor_feat,
                          const float* anchor_off, const float* params, const asgs_camera* cams,
                          int32_t n_views, const asgs_gaussians* d_g, float* d_xyz, float* d_feat,

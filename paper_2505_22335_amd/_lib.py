@@ -14,7 +14,8 @@ from typing import Dict, Optional, Sequence
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libasgs.so")
-HEADER = os.path.join(os.path.dirname(PKG), "include", "asgs.h")
+INCLUDE = os.path.join(os.path.dirname(PKG), "include")
+HEADERS = [os.path.join(INCLUDE, h) for h in ("asgs.h", "asgs_serve.h")]
 
 # torch ships its own HIP runtime under the same soname as the system one; it
 # must be the first loaded so that torch's allocations and this library share
@@ -100,11 +101,14 @@ for _name, (_res, _args) in _sigs.items():
 
 
 def declared_functions() -> list:
-    """Function names declared in include/asgs.h."""
-    with open(HEADER) as f:
-        txt = f.read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(asgs_[a-z_0-9]+)\s*\(", txt)))
+    """Function names declared in the public headers (include/*.h)."""
+    names = set()
+    for h in HEADERS:
+        with open(h) as f:
+            txt = f.read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(asgs_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 def check(status: int, where: str):
@@ -255,8 +259,8 @@ def decode_backward(d: Decoder, xyz, feat, off, params, cams, dg: Gaussians, d_x
                     d_pose, work, stream=None):
     ca = make_cameras(cams)
     check(lib.asgs_decode_backward(C.byref(d), xyz.data_ptr(), feat.data_ptr(), off.data_ptr(),
-                                   params.data_ptr(), ca, len(cams), C.byref(dg), d_xyz.data_ptr(),
-                                   d_feat.data_ptr(), d_off.data_ptr(), d_params.data_ptr(), _ptr(d_pose),
+                                   params.data_ptr(), ca, len(cams), C.byref(dg), _ptr(d_xyz),
+                                   _ptr(d_feat), _ptr(d_off), _ptr(d_params), _ptr(d_pose),
                                    work.data_ptr(), work.numel(), _stream(stream)), "asgs_decode_backward")
 
 

@@ -15,8 +15,8 @@
 namespace asgs {
 
 namespace {
-
 thread_local std::string g_err = "no error";
+}  // namespace
 
 int fail(int status, const char* fmt, ...) {
   char buf[512];
@@ -27,6 +27,8 @@ int fail(int status, const char* fmt, ...) {
   g_err = buf;
   return status;
 }
+
+namespace {
 
 int check_launch(const char* what) {
   const hipError_t e = hipGetLastError();
@@ -535,7 +537,13 @@ int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const f
   if (st) return st;
   if ((st = check_gauss(d_g, d->n_feat, n_views, true, "d_g"))) return st;
   if (d_g->n != d->n_anchors * d->k) return fail(ASGS_E_INVALID, "d_g.n must be n_anchors * k");
-  if ((st = check_ptrs({d_xyz, d_feat, d_off, d_params, work}, "decode_backward outputs"))) return st;
+  const bool pose_only = !d_xyz && !d_feat && !d_off && !d_params;
+  if (pose_only) {
+    if (!d_pose) return fail(ASGS_E_INVALID, "decode_backward: pose-only mode (no anchor outputs) needs d_pose");
+    if ((st = check_ptrs({work}, "decode_backward workspace"))) return st;
+  } else if ((st = check_ptrs({d_xyz, d_feat, d_off, d_params, work}, "decode_backward outputs"))) {
+    return st;
+  }
   const DecodeConst dc = decode_const(*d, n_views);
   const size_t need = decode_workspace_bytes(dc);
   if (work_bytes < need) return fail(ASGS_E_WORKSPACE, "decode workspace needs %zu bytes (got %zu)", need, work_bytes);

@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(kDecThreads) k_dec_bwd_mid(DecodeConst dc, Hea
     sdX[a][c] = sx;
   }
   __syncthreads();
-  for (int e = t; e < kMidAnchors * 32; e += kDecThreads) {
+  for (int e = t; d_feat && e < kMidAnchors * 32; e += kDecThreads) {
     const int a = e / 32, c = e % 32;
     if (a0 + a < A) {
       float* p = &d_feat[(a0 + a) * 32 + c];
@@ -276,8 +276,10 @@ __global__ void __launch_bounds__(kDecThreads) k_dec_bwd_mid(DecodeConst dc, Hea
     const float pr = del[0] * gd[0] + del[1] * gd[1] + del[2] * gd[2];
     for (int c = 0; c < 3; ++c) {
       const float dD = (gd[c] - del[c] * pr) / d;
-      float* p = &d_xyz[c * A + a];
-      *p = (view == 0 ? 0.f : *p) + dD;
+      if (d_xyz) {
+        float* p = &d_xyz[c * A + a];
+        *p = (view == 0 ? 0.f : *p) + dD;
+      }
       dcl[c] = -dD;
     }
   }
@@ -450,11 +452,12 @@ __global__ void __launch_bounds__(kWThreads) k_dec_bwd_wgrad(DecodeConst dc, Hea
 // adds -R_cw dL/dc to the translation part of the pose gradient.
 __global__ void __launch_bounds__(256) k_decode_reduce(DecodeConst dc, DecodeViews dv, DecWork w, float* d_params,
                                                        float* d_pose) {
+  // without d_params only the camera-centre term is reduced (one block)
   __shared__ float red[4][64];
   const int t = threadIdx.x;
   const int pl = t & 63, q = t >> 6;
   const int64_t p = (int64_t)blockIdx.x * 64 + pl;
-  const int64_t nparam_blocks = (dc.n_params + 63) / 64;
+  const int64_t nparam_blocks = d_params ? (dc.n_params + 63) / 64 : 0;
   if ((int64_t)blockIdx.x < nparam_blocks) {
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     if (p < dc.n_params) {
@@ -604,11 +607,13 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
                        view, w);
     hipLaunchKernelGGL(k_dec_bwd_mid, dim3((unsigned)z.nblk_m), dim3(kDecThreads), 0, s, dc, ht, dv, xyz,
                        params, view, w, d_xyz, d_feat);
-    hipLaunchKernelGGL(k_dec_bwd_wgrad, dim3((unsigned)z.nblk_w), dim3(kWThreads), 0, s, dc, ht, view, w);
+    if (d_params)
+      hipLaunchKernelGGL(k_dec_bwd_wgrad, dim3((unsigned)z.nblk_w), dim3(kWThreads), 0, s, dc, ht, view, w);
   }
-  hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,
-                     d_off);
-  const unsigned nrb = (unsigned)((dc.n_params + 63) / 64) + 1;
+  if (d_xyz)
+    hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,
+                       d_off);
+  const unsigned nrb = d_params ? (unsigned)((dc.n_params + 63) / 64) + 1 : 1u;
   hipLaunchKernelGGL(k_decode_reduce, dim3(nrb), dim3(256), 0, s, dc, dv, w, d_params, d_pose);
 }
 

@@ -50,6 +50,9 @@ struct RenderConst {
 };
 
 // Header at the start of every render context (device memory).
+// Record an error message for asgs_last_error (calling thread) and return status.
+int fail(int status, const char* fmt, ...);
+
 struct CtxHeader {
   unsigned long long n_isect;     // intersections of the last forward/count (may exceed cap)
   unsigned long long n_visible;   // visible (view, Gaussian) pairs
