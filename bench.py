@@ -64,6 +64,125 @@ def cpu_baseline(sc, cam, G, budget_s=30.0):
                       f"({dt:.1f} s, torch CPU threads={threads})"}
 
 
+def serving_c5(warmup_s=2.0, measure_s=20.0, burst_s=1.0, seed=5, log=None):
+    """The serving mix on the 500k-Gaussian room: Poisson tracking requests
+    (one 640x480 view, weighted L1 on rgb/depth/features, pose gradient) at
+    300/s and mapping requests (4..16 keyframes at 640x480 or 320x240, anchor
+    and MLP gradients) at 20/s, replayed against three server configurations:
+    batched with the BF16 decoder, batched with the FP32 decoder, and FP32 one
+    request at a time on one stream. Also the saturation throughput of each
+    (a burst of burst_s seconds of requests all arriving at once)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_22335_amd.pipeline import AnchorRenderer, anchors_to_device
+    from paper_2505_22335_amd.serve import MAP, TRACK, RequestSpec, Server, latency_summary, poisson_arrivals
+
+    sc, poses = synth.c5()
+    a = anchors_to_device(sc)
+    full = [synth.camera_c2(T) for T in poses]
+    half = [synth.camera_half(T) for T in poses]
+
+    def prerender(cams):
+        out = ([], [], [])
+        for i in range(0, len(cams), 16):
+            r = AnchorRenderer(a, cams[i:i + 16])
+            r.fit()
+            img = r.forward()
+            for v in range(img["rgb"].shape[0]):
+                out[0].append(img["rgb"][v].clone())
+                out[1].append(img["depth"][v].clone())
+                out[2].append(img["feat"][v].clone())
+            del r, img
+        torch.cuda.synchronize()
+        return out
+    tf, th = prerender(full), prerender(half)
+    rng = np.random.default_rng(seed)
+    weight = torch.as_tensor(rng.uniform(size=(480, 640)), dtype=torch.float32).cuda()
+
+    def jitter(cam, r):
+        u, e = r.normal(size=3), r.normal(size=3)
+        return cam.copy_with(synth.perturb_pose(cam.T_wc, 0.01 * u / np.linalg.norm(u),
+                                                0.0087 * e / np.linalg.norm(e)))
+
+    T_end = warmup_s + measure_s
+    t_tr = poisson_arrivals(rng, 300.0, T_end)
+    t_mp = poisson_arrivals(rng, 20.0, T_end)
+    events = sorted([(t, TRACK) for t in t_tr] + [(t, MAP) for t in t_mp])
+    A, n, npar = a.A, a.A * a.k, a.params.numel()
+    d_pose_tr = torch.empty((len(t_tr), 6), device="cuda")
+    loss_tr = torch.empty(len(t_tr), device="cuda")
+    ring = [dict(d_pose=torch.empty((16, 6), device="cuda"), loss=torch.empty(16, device="cuda"),
+                 d_xyz=torch.empty((3, A), device="cuda"), d_feat=torch.empty((A, 32), device="cuda"),
+                 d_off=torch.empty((3, n), device="cuda"), d_params=torch.empty(npar, device="cuda"))
+            for _ in range(8)]
+    specs, kinds, mpix = [], [], []
+    it = im = 0
+    for t, kind in events:
+        r = np.random.default_rng([seed, len(specs)])
+        if kind == TRACK:
+            i = int(t * 30.0) % 64
+            specs.append(RequestSpec(TRACK, [jitter(full[i], r)], [tf[0][i]], [tf[1][i]], target_feat=[tf[2][i]],
+                                     weight=weight, d_pose=d_pose_tr[it:it + 1], loss=loss_tr[it:it + 1],
+                                     arrival=float(t)))
+            it += 1
+            mpix.append(0.3072)
+        else:
+            B = int(r.integers(4, 17))
+            small = r.random() < 0.5
+            idx = r.choice(64, B, replace=False)
+            cams, tg = (half, th) if small else (full, tf)
+            o = ring[im % len(ring)]
+            specs.append(RequestSpec(MAP, [jitter(cams[j], r) for j in idx], [tg[0][j] for j in idx],
+                                     [tg[1][j] for j in idx], target_feat=[tg[2][j] for j in idx],
+                                     d_pose=o["d_pose"][:B], loss=o["loss"][:B], d_xyz=o["d_xyz"],
+                                     d_feat=o["d_feat"], d_off=o["d_off"], d_params=o["d_params"], arrival=float(t)))
+            im += 1
+            mpix.append(B * (0.0768 if small else 0.3072))
+        kinds.append(kind)
+    kinds, mpix = np.array(kinds), np.array(mpix)
+    arr = np.array([s.arrival for s in specs])
+    offered = float(mpix[arr >= warmup_s].sum() / measure_s)
+    modes = {"served_bf16": dict(precision=1, n_streams=3, max_batch_views=16),
+             "served_fp32": dict(precision=0, n_streams=3, max_batch_views=16),
+             "fifo_fp32": dict(precision=0, n_streams=1, max_batch_views=1, fifo=True)}
+    out = {"workload": "50k anchors x10 = 500k Gaussians; Poisson tracking 300/s (640x480, pose grad) + "
+                       "mapping 20/s (4-16 keyframes, 640x480 or 320x240, anchor/MLP grads)",
+           "warmup_s": warmup_s, "measure_s": measure_s, "requests": len(specs),
+           "offered_mpix_s": round(offered, 1), "modes": {}}
+    burst = [i for i in range(len(specs)) if arr[i] < burst_s]
+    for name, kw in modes.items():
+        with Server(a, arena_bytes=32 << 30, **kw) as srv:
+            res = srv.replay(specs)
+            st = srv.stats()
+        done = np.array([r.done for r in res]) - res[0].arrival + arr[0]
+        ok = np.array([r.status == 0 for r in res])
+        win = arr >= warmup_s
+        span = done[win].max() - warmup_s
+        summ = latency_summary(res, kinds, t_from=warmup_s)
+        # saturation: the first burst_s seconds of requests, all at once
+        bspecs = [specs[i] for i in burst]
+        saved = [s.arrival for s in bspecs]
+        for s_ in bspecs:
+            s_.arrival = 0.0
+        with Server(a, arena_bytes=32 << 30, **kw) as srv:
+            t0 = Server.clock()
+            bres = srv.replay(bspecs)
+        for s_, t in zip(bspecs, saved):
+            s_.arrival = t
+        makespan = max(r.done for r in bres) - t0
+        out["modes"][name] = {
+            "throughput_mpix_s": round(float(mpix[win & ok].sum() / span), 1),
+            "saturation_mpix_s": round(float(mpix[burst].sum() / makespan), 1),
+            "latency": summ, "batches": int(st.batches), "mean_batch_views": round(st.batch_views / max(st.batches, 1), 2),
+            "max_in_flight": int(st.max_in_flight), "arena_peak_gib": round(st.arena_peak / 2 ** 30, 2),
+            "reruns": int(st.reruns), "failed": int(st.failed)}
+        if log:
+            log(name, json.dumps(out["modes"][name]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +195,9 @@ def main():
     ap.add_argument("--breakdown", action="store_true", help="also time every kernel class (untimed pass)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="measured seconds of the serving mix (after 1 s warm-up; 0 = skip)")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving mix (2 s warm-up)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the hot path is not sharded across GPUs in this build "
@@ -89,6 +211,11 @@ def main():
     from paper_2505_22335_amd import _lib as L
     from paper_2505_22335_amd.pipeline import AnchorRenderer, anchors_to_device
 
+    if args.serve_only:
+        res = serving_c5(warmup_s=2.0, measure_s=args.serve_seconds or 20.0,
+                         log=lambda *m: print(*m, file=sys.stderr, flush=True))
+        print(json.dumps({"metric": "p50/p99 request latency, serving mix", "serving": res}), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     sc, cam, _ = synth.c2(wl["mode"], wl["anchors"], seed=wl["seed"])
     cams = [cam] if args.views == 1 else [
@@ -182,6 +309,8 @@ def main():
             br[nm] = entry
         L.profile_enable(0)
         res["kernels"] = br
+    if args.serve_seconds > 0:
+        res["serving"] = serving_c5(warmup_s=1.0, measure_s=args.serve_seconds)
     if not args.no_cpu_baseline:
         g_rng = np.random.default_rng(7)  # seeded upstream gradient of the frame's shape
         G = {"rgb": g_rng.normal(size=(3, H, W)), "depth": g_rng.normal(size=(H, W)),
