@@ -67,7 +67,10 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
-    if (!done) {
+    // Every lane walks the whole batch with predicated updates; the channel
+    // accumulation is skipped only when no lane of the wave takes the entry
+    // (a wave-uniform branch), and the wave leaves once all its pixels stop.
+    if (__ballot(!done)) {
       float4 n0 = sg[0], n1 = sg[1];
       for (int j = 0; j < cnt; ++j) {
         // geometry of the next entry is read before this one is evaluated
@@ -78,25 +81,26 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
         n1 = sg[2 * jn + 1];
         float dx, dy;
         const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
-        if (power > 0.f) continue;
         const float alpha = fminf(amax, g1.y * __expf(power));
-        if (alpha < amin) continue;
+        const bool take = !done && power <= 0.f && alpha >= amin;
         const float Tn = T * (1.f - alpha);
-        if (Tn < tmin) {
-          done = true;
-          break;
-        }
-        const float w = alpha * T;
+        const bool stop = take && Tn < tmin;
+        const bool use = take && !stop;
+        done = done || stop;
+        if (__ballot(use)) {
+          const float w = use ? alpha * T : 0.f;
 #pragma unroll
-        for (int c4 = 0; c4 < CS4; ++c4) {
-          const float4 v = sc[j * CS4 + c4];
-          acc[4 * c4 + 0] = fmaf(w, v.x, acc[4 * c4 + 0]);
-          acc[4 * c4 + 1] = fmaf(w, v.y, acc[4 * c4 + 1]);
-          acc[4 * c4 + 2] = fmaf(w, v.z, acc[4 * c4 + 2]);
-          acc[4 * c4 + 3] = fmaf(w, v.w, acc[4 * c4 + 3]);
+          for (int c4 = 0; c4 < CS4; ++c4) {
+            const float4 v = sc[j * CS4 + c4];
+            acc[4 * c4 + 0] = fmaf(w, v.x, acc[4 * c4 + 0]);
+            acc[4 * c4 + 1] = fmaf(w, v.y, acc[4 * c4 + 1]);
+            acc[4 * c4 + 2] = fmaf(w, v.z, acc[4 * c4 + 2]);
+            acc[4 * c4 + 3] = fmaf(w, v.w, acc[4 * c4 + 3]);
+          }
+          T = use ? Tn : T;
+          last = use ? base - rg.x + (uint32_t)j + 1u : last;
         }
-        T = Tn;
-        last = base - rg.x + (uint32_t)j + 1u;
+        if (__ballot(!done) == 0) break;
       }
     }
   }
@@ -249,33 +253,35 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
     }
     __syncthreads();
     for (int jj = kBwdBatch - 1; jj >= 0; --jj) {
+      // predicated like the forward: stale entries past cnt compute garbage
+      // that the selects discard
+      const float4 g0 = sg[2 * jj];
+      const float4 g1 = sg[2 * jj + 1];
+      float dx, dy;
+      const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
+      const float raw = g1.y * __expf(power);
+      const float alpha = fminf(amax, raw);
+      const bool use = jj < cnt && (uint32_t)(lo + jj) < last && power <= 0.f && alpha >= amin;
       float wgt = 0.f, dpow = 0.f;
-      if (jj < cnt && (uint32_t)(lo + jj) < last) {
-        const float4 g0 = sg[2 * jj];
-        const float4 g1 = sg[2 * jj + 1];
-        float dx, dy;
-        const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
-        if (power <= 0.f) {
-          const float e = __expf(power);
-          const float raw = g1.y * e;
-          const float alpha = fminf(amax, raw);
-          if (alpha >= amin) {
-            const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
-            T = T * ioma;
-            wgt = alpha * T;
-            float dotg = 0.f;
+      if (__ballot(use)) {
+        const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
+        const float Tk = T * ioma;
+        float dotg = 0.f;
 #pragma unroll
-            for (int c4 = 0; c4 < CS4; ++c4) {
-              const float4 v = sc[jj * CS4 + c4];
-              dotg = fmaf(G[4 * c4 + 0], v.x, dotg);
-              dotg = fmaf(G[4 * c4 + 1], v.y, dotg);
-              dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
-              dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
-            }
-            const float dalpha = T * dotg - (sacc + GT * Tf) * ioma;
-            sacc = fmaf(wgt, dotg, sacc);
-            dpow = raw < amax ? dalpha * alpha : 0.f;
-          }
+        for (int c4 = 0; c4 < CS4; ++c4) {
+          const float4 v = sc[jj * CS4 + c4];
+          dotg = fmaf(G[4 * c4 + 0], v.x, dotg);
+          dotg = fmaf(G[4 * c4 + 1], v.y, dotg);
+          dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
+          dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
+        }
+        const float w_ = alpha * Tk;
+        const float dalpha = Tk * dotg - (sacc + GT * Tf) * ioma;
+        if (use) {
+          T = Tk;
+          wgt = w_;
+          sacc = fmaf(w_, dotg, sacc);
+          dpow = raw < amax ? dalpha * alpha : 0.f;
         }
       }
       mycw[jj] = wgt;

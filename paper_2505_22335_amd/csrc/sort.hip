@@ -10,13 +10,12 @@
 // result equals a stable LSD sort of the full keys of the Gaussian-major
 // list.
 //
-// Each pass is two kernels: an upsweep (per-block 256-bin digit histogram,
-// stored block-major) and a stable scatter. Every scatter block derives its
-// own digit offsets from the histograms (digit totals over all blocks plus
-// the counts of the blocks before it), so no grid-wide fence or extra scan
-// launch is needed. Within a block, wave ballots find lanes with equal
-// digits; ranks follow item order within a wave, across the block's waves
-// and across its rounds.
+// Each pass is three kernels: an upsweep (per-block 256-bin digit histogram,
+// stored block-major), a one-workgroup scan that turns the histograms into
+// every block's digit offsets in place (digit totals over all blocks plus the
+// counts of the blocks before it), and a stable scatter. Within a block, wave
+// ballots find lanes with equal digits; ranks follow item order within a
+// wave, across the block's waves and across its rounds.
 #include "internal.h"
 
 namespace asgs {
@@ -33,7 +32,7 @@ struct RadixArgs {
   uint64_t count_cap;
   int32_t shift;
   int32_t filter;                          // drop keys equal to kInvalidKey
-  uint32_t* hist;                          // [256][nb] digit-major
+  uint32_t* hist;                          // [nb][256] block-major histograms, then offsets
   unsigned int* counter;                   // last-block counter (0 between uses)
   unsigned long long* total_out;           // nullptr or: number of kept items
 };
@@ -69,6 +68,57 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(RadixArgs a) {
   a.hist[b * kRadixBins + threadIdx.x] = lh[threadIdx.x];
 }
 
+constexpr int kScanGroups = 4;  // block ranges per digit in the offset scan
+
+// Histograms -> per-block digit offsets, in place. Thread (g, d) owns digit d
+// over the g-th quarter of the blocks; every histogram entry is read and then
+// overwritten by its owner only.
+__global__ void __launch_bounds__(kRadixBins * kScanGroups) k_radix_scan(RadixArgs a) {
+  __shared__ uint32_t part[kScanGroups][kRadixBins];
+  __shared__ uint32_t dbase[kRadixBins];
+  __shared__ uint32_t wsum[kRadixBins / 64];
+  const uint64_t n = item_count(a);
+  const int nb = (int)((n + kSortItems - 1) / kSortItems);
+  const int d = threadIdx.x & (kRadixBins - 1), g = threadIdx.x / kRadixBins;
+  const int per = (nb + kScanGroups - 1) / kScanGroups;
+  const int b0 = g * per, b1 = min(nb, b0 + per);
+  uint32_t* h = a.hist;
+  uint32_t s = 0u;
+#pragma unroll 8
+  for (int b = b0; b < b1; ++b) s += h[b * kRadixBins + d];
+  part[g][d] = s;
+  __syncthreads();
+  // exclusive scan of the digit totals over the 256 digits (group 0: four waves)
+  uint32_t tot = 0u, incl = 0u;
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < kScanGroups; ++q) tot += part[q][d];
+    incl = tot;
+    const int lane = d & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[d >> 6] = incl;
+  }
+  __syncthreads();
+  if (g == 0) {
+    for (int w = 0; w < (d >> 6); ++w) incl += wsum[w];
+    dbase[d] = incl - tot;
+    if (d == kRadixBins - 1 && a.total_out) *a.total_out = incl;
+  }
+  __syncthreads();
+  uint32_t run = dbase[d];
+  for (int q = 0; q < g; ++q) run += part[q][d];
+#pragma unroll 8
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t c = h[b * kRadixBins + d];
+    h[b * kRadixBins + d] = run;
+    run += c;
+  }
+}
+
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(RadixArgs a) {
   __shared__ uint32_t base[kRadixBins];
   __shared__ uint32_t run[kRadixBins];
@@ -79,27 +129,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(RadixArgs a) {
   if (b >= nb) return;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
-  // digit offsets of this block: exclusive scan of the digit totals over all
-  // blocks, plus the counts of digit t in the blocks before this one
-  {
-    uint32_t tot = 0u, pre = 0u;
-    for (uint64_t bb = 0; bb < nb; ++bb) {
-      const uint32_t c = a.hist[bb * kRadixBins + t];
-      tot += c;
-      pre += bb < b ? c : 0u;
-    }
-    run[t] = tot;
-    __syncthreads();
-    for (int off = 1; off < kRadixBins; off <<= 1) {
-      const uint32_t v = t >= off ? run[t - off] : 0u;
-      __syncthreads();
-      run[t] += v;
-      __syncthreads();
-    }
-    base[t] = run[t] - tot + pre;
-    if (b == 0 && t == kRadixBins - 1 && a.total_out) *a.total_out = run[t];
-    __syncthreads();
-  }
+  base[t] = a.hist[b * kRadixBins + t];  // this block's digit offsets (k_radix_scan)
   (void)lane;
   run[t] = 0u;
   for (int r = 0; r < kSortIPT; ++r) {
@@ -143,6 +173,7 @@ void radix_pass(const RadixArgs& a, uint64_t max_items, hipStream_t s) {
   const unsigned nblk = (unsigned)((max_items + kSortItems - 1) / kSortItems);
   const unsigned g = nblk > 0 ? nblk : 1;
   hipLaunchKernelGGL(k_radix_upsweep, dim3(g), dim3(kSortThreads), 0, s, a);
+  hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kRadixBins * kScanGroups), 0, s, a);
   hipLaunchKernelGGL(k_radix_scatter, dim3(g), dim3(kSortThreads), 0, s, a);
 }
 
