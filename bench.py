@@ -48,6 +48,23 @@ def algorithmic_bytes(I, nvis, N, A, P, nf=16):
     }
 
 
+def measured_traffic(path=os.path.join(ROOT, "profiles", "blend_bwd_c2s_traffic.md")):
+    """HBM bytes per blend-backward launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when it is missing or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(path).read()
+        sha = re.search(r"source_sha256: ([0-9a-f]{64})", txt).group(1)
+        src = re.search(r"source: (\S+)", txt).group(1)
+        val = float(re.search(r"traffic_bytes_per_launch: ([0-9.]+)", txt).group(1))
+        cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    return val if cur == sha else None
+
+
 def cpu_baseline(sc, cam, G, budget_s=30.0):
     """The FP64 oracle's forward + backward of the same frame on the host."""
     import torch
@@ -288,7 +305,8 @@ def main():
                    "intersections": I, "visible": nvis},
         "roofline": {"bound": "hbm", "kernel": "blend backward (k_blend_bwd)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic() if args.workload == "c2s" and V == 1 else None,
                      "avg_ms": round(dom_ms, 5), "launches": bb_n,
                      "algorithmic_bytes": int(ab["blend_bwd"])},
         "wall_s": round(wall, 3),

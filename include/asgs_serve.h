@@ -5,7 +5,7 @@
  * current pose estimate and follow the pose gradient of the photometric,
  * depth and feature residuals, UP-SLAM Sec. 3.4) and a mapping thread (per
  * keyframe window: render several keyframes and follow the gradients of the
- * anchors and decoder MLPs, Sec. 3.5). This server runs both kinds of work as
+ * anchors and decoder MLPs, Sec. 3.3). This server runs both kinds of work as
  * requests against one scene that stays resident in HBM:
  *
  *  - ASGS_REQ_TRACK: one view; returns the SE(3) pose gradient (and loss) of

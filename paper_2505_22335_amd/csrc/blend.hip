@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   for (int c = 0; c < CS; ++c) acc[c] = 0.f;
   uint32_t last = 0;
   bool done = !inside;
-  const float amin = rc.alpha_min, amax = rc.alpha_max, tmin = rc.T_min;
+  const float amax = rc.alpha_max, tmin = rc.T_min;
   for (uint32_t base = rg.x; base < rg.y; base += kTilePix) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t p = base + t;
@@ -81,8 +81,10 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
         n1 = sg[2 * jn + 1];
         float dx, dy;
         const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
+        // alpha >= alpha_min  <=>  power >= ln(alpha_min / o) (record slot 6)
+        const bool take = !done && power <= 0.f && power >= g1.z;
+        if (!__ballot(take)) continue;
         const float alpha = fminf(amax, g1.y * __expf(power));
-        const bool take = !done && power <= 0.f && alpha >= amin;
         const float Tn = T * (1.f - alpha);
         const bool stop = take && Tn < tmin;
         const bool use = take && !stop;
@@ -100,7 +102,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
           T = use ? Tn : T;
           last = use ? base - rg.x + (uint32_t)j + 1u : last;
         }
-        if (__ballot(!done) == 0) break;
+        if (__ballot(stop) && __ballot(!done) == 0) break;
       }
     }
   }
@@ -170,11 +172,14 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
   float* gslot = ctx_ptr<float>(ctx, L.gslot);
 
-  __shared__ float4 sg[kBwdBatch * 2];
-  __shared__ float4 sc[kBwdBatch * CS4];
+  constexpr int kRecF4 = 2 + CS4;  // float4 per list entry: geometry (2) + channels
+  constexpr int kRound = 32;       // list entries staged per round (two MFMA batches)
+  constexpr int kPer = (kRound * kRecF4 + kTilePix - 1) / kTilePix;
+  constexpr int PS = GS;           // row of a partial-sum entry
+  __shared__ float4 srec[kRound * kRecF4];
   __shared__ float cw[NW][64 * CP];     // w of (pixel, entry), per wave
   __shared__ float cp[NW][64 * CP];     // dL/dpower of (pixel, entry), per wave
-  __shared__ float part[NW][kBwdBatch][32];
+  __shared__ float part[2][NW][kBwdBatch][PS];
   __shared__ uint32_t smax;
 
   const size_t HW = (size_t)V.W * V.H;
@@ -237,103 +242,133 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   }
   float T = Tf;
   float sacc = 0.f;  // sum over later Gaussians of w_l (G . c_l)
-  const float amin = rc.alpha_min, amax = rc.alpha_max;
+  const float amax = rc.alpha_max;
   float* mycw = &cw[wv][lane * CP];
   float* mycp = &cp[wv][lane * CP];
-  for (int hi = (int)nproc; hi > 0; hi -= kBwdBatch) {
-    const int lo = hi - kBwdBatch > 0 ? hi - kBwdBatch : 0;
-    const int cnt = hi - lo;
-    __syncthreads();
-    if (t < cnt) {
-      const uint32_t gid = pairgid[rg.x + lo + t];
-      sg[2 * t] = geom[2 * (size_t)gid];
-      sg[2 * t + 1] = geom[2 * (size_t)gid + 1];
+  // Records are staged in rounds of kRound entries, walking the list from the
+  // back; the global loads of the next round are issued before the current
+  // round is processed and land in LDS at the start of the next round.
+  float4 stage[kPer];
+  auto fetch = [&](int lo_r, int cnt_r) {
 #pragma unroll
-      for (int c = 0; c < CS4; ++c) sc[t * CS4 + c] = chan4[(size_t)gid * CS4 + c];
-    }
-    __syncthreads();
-    for (int jj = kBwdBatch - 1; jj >= 0; --jj) {
-      // predicated like the forward: stale entries past cnt compute garbage
-      // that the selects discard
-      const float4 g0 = sg[2 * jj];
-      const float4 g1 = sg[2 * jj + 1];
-      float dx, dy;
-      const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
-      const float raw = g1.y * __expf(power);
-      const float alpha = fminf(amax, raw);
-      const bool use = jj < cnt && (uint32_t)(lo + jj) < last && power <= 0.f && alpha >= amin;
-      float wgt = 0.f, dpow = 0.f;
-      if (__ballot(use)) {
-        const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
-        const float Tk = T * ioma;
-        float dotg = 0.f;
-#pragma unroll
-        for (int c4 = 0; c4 < CS4; ++c4) {
-          const float4 v = sc[jj * CS4 + c4];
-          dotg = fmaf(G[4 * c4 + 0], v.x, dotg);
-          dotg = fmaf(G[4 * c4 + 1], v.y, dotg);
-          dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
-          dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
-        }
-        const float w_ = alpha * Tk;
-        const float dalpha = Tk * dotg - (sacc + GT * Tf) * ioma;
-        if (use) {
-          T = Tk;
-          wgt = w_;
-          sacc = fmaf(w_, dotg, sacc);
-          dpow = raw < amax ? dalpha * alpha : 0.f;
-        }
+    for (int k = 0; k < kPer; ++k) {
+      const int e = t + k * kTilePix;
+      const int ent = e / kRecF4, f = e - ent * kRecF4;
+      if (ent < cnt_r) {
+        const uint32_t gid = pairgid[rg.x + lo_r + ent];
+        stage[k] = f < 2 ? geom[2 * (size_t)gid + f] : chan4[(size_t)gid * CS4 + (f - 2)];
       }
-      mycw[jj] = wgt;
-      mycp[jj] = dpow;
+    }
+  };
+  int rhi = (int)nproc;
+  int rlo = rhi - kRound > 0 ? rhi - kRound : 0;
+  if (rhi > 0) fetch(rlo, rhi - rlo);
+  int pbuf = 0;
+  while (rhi > 0) {
+    __syncthreads();  // every reader of the previous round is done
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = t + k * kTilePix;
+      if (e / kRecF4 < rhi - rlo) srec[e] = stage[k];
     }
     __syncthreads();
-    // contract this wave's 64 pixels: C[entry][feature]
-    f4v c1 = {0.f, 0.f, 0.f, 0.f}, c2 = c1, c3 = c1;
-    const float* acw = &cw[wv][0];
-    const float* acp = &cp[wv][0];
+    const int nrhi = rlo, nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
+    if (nrhi > 0) fetch(nrlo, nrhi - nrlo);
+    for (int hi = rhi; hi > rlo; hi -= kBwdBatch) {
+      const int lo = hi - kBwdBatch > rlo ? hi - kBwdBatch : rlo;
+      const int cnt = hi - lo;
+      const float4* rec = &srec[(lo - rlo) * kRecF4];
+      for (int jj = kBwdBatch - 1; jj >= 0; --jj) {
+        // predicated like the forward: entries past cnt compute garbage that
+        // the selects discard
+        const float4 g0 = rec[jj * kRecF4];
+        const float4 g1 = rec[jj * kRecF4 + 1];
+        float wgt = 0.f, dpow = 0.f;
+        // same alpha threshold as the forward
+        float dx, dy;
+        const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
+        const bool use = jj < cnt && (uint32_t)(lo + jj) < last && power <= 0.f && power >= g1.z;
+        if (__ballot(use)) {
+          const float raw = g1.y * __expf(power);
+          const float alpha = fminf(amax, raw);
+          const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
+          const float Tk = T * ioma;
+          float dotg = 0.f;
 #pragma unroll
-    for (int s4 = 0; s4 < 16; ++s4) {
-      const int q = 4 * s4 + (lane >> 4);
-      const float aw = acw[q * CP + fcol];
-      const float ap = acp[q * CP + fcol];
-      c1 = mfma4(aw, bG0[s4], c1);
-      if (CS > 16) c2 = mfma4(aw, bG1[s4], c2);
-      c3 = mfma4(ap, bM[s4], c3);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = 4 * (lane >> 4) + r;
-      if (fcol < CS) part[wv][e][fcol] = c1[r];
-      if (CS > 16 && fcol < CS - 16) part[wv][e][16 + fcol] = c2[r];
-      if (fcol < 6) part[wv][e][20 + fcol] = c3[r];
-    }
-    __syncthreads();
-    for (int q = t; q < cnt * GS; q += kTilePix) {
-      const int e = q / GS, c = q - e * GS;
-      float val;
-      if (c >= 6) {
-        const int f = c - 6;
-        val = (part[0][e][f] + part[1][e][f]) + (part[2][e][f] + part[3][e][f]);
-      } else {
-        float M[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m)
-          M[m] = (part[0][e][20 + m] + part[1][e][20 + m]) + (part[2][e][20 + m] + part[3][e][20 + m]);
-        const float4 g0 = sg[2 * e];
-        const float4 g1 = sg[2 * e + 1];
-        const float uu = g0.x - (float)x0, vv = g0.y - (float)y0;  // tile-local centre
-        const float Sdx = uu * M[0] - M[1];
-        const float Sdy = vv * M[0] - M[2];
-        if (c == 0) val = -(g0.z * Sdx + g0.w * Sdy);
-        else if (c == 1) val = -(g0.w * Sdx + g1.x * Sdy);
-        else if (c == 2) val = -0.5f * (uu * uu * M[0] - 2.f * uu * M[1] + M[3]);
-        else if (c == 3) val = -(uu * vv * M[0] - uu * M[2] - vv * M[1] + M[4]);
-        else if (c == 4) val = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
-        else val = M[0] / g1.y;
+          for (int c4 = 0; c4 < CS4; ++c4) {
+            const float4 v = rec[jj * kRecF4 + 2 + c4];
+            dotg = fmaf(G[4 * c4 + 0], v.x, dotg);
+            dotg = fmaf(G[4 * c4 + 1], v.y, dotg);
+            dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
+            dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
+          }
+          const float w_ = alpha * Tk;
+          const float dalpha = Tk * dotg - (sacc + GT * Tf) * ioma;
+          if (use) {
+            T = Tk;
+            wgt = w_;
+            sacc = fmaf(w_, dotg, sacc);
+            dpow = raw < amax ? dalpha * alpha : 0.f;
+          }
+        }
+        mycw[jj] = wgt;
+        mycp[jj] = dpow;
       }
-      gslot[(size_t)pslot[rg.x + lo + e] * GS + c] = val;
+      // the coefficients are read back by other lanes of this wave only
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // contract this wave's 64 pixels: C[entry][feature]
+      f4v c1 = {0.f, 0.f, 0.f, 0.f}, c2 = c1, c3 = c1;
+      const float* acw = &cw[wv][0];
+      const float* acp = &cp[wv][0];
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int q = 4 * s4 + (lane >> 4);
+        const float aw = acw[q * CP + fcol];
+        const float ap = acp[q * CP + fcol];
+        c1 = mfma4(aw, bG0[s4], c1);
+        if (CS > 16) c2 = mfma4(aw, bG1[s4], c2);
+        c3 = mfma4(ap, bM[s4], c3);
+      }
+      float (*pt)[kBwdBatch][PS] = part[pbuf];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = 4 * (lane >> 4) + r;
+        if (fcol < CS) pt[wv][e][6 + fcol] = c1[r];
+        if (CS > 16 && fcol < CS - 16) pt[wv][e][6 + 16 + fcol] = c2[r];
+        if (fcol < 6) pt[wv][e][fcol] = c3[r];
+      }
+      __syncthreads();
+      // partial sums of the four waves -> one gradient slot per entry; the
+      // other buffer is written by the next batch meanwhile
+      for (int q = t; q < cnt * GS; q += kTilePix) {
+        const int e = q / GS, c = q - e * GS;
+        float val;
+        if (c >= 6) {
+          val = (pt[0][e][c] + pt[1][e][c]) + (pt[2][e][c] + pt[3][e][c]);
+        } else {
+          float M[6];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) M[m] = (pt[0][e][m] + pt[1][e][m]) + (pt[2][e][m] + pt[3][e][m]);
+          const float4 g0 = rec[e * kRecF4];
+          const float4 g1 = rec[e * kRecF4 + 1];
+          const float uu = g0.x - (float)x0, vv = g0.y - (float)y0;  // tile-local centre
+          const float Sdx = uu * M[0] - M[1];
+          const float Sdy = vv * M[0] - M[2];
+          if (c == 0) val = -(g0.z * Sdx + g0.w * Sdy);
+          else if (c == 1) val = -(g0.w * Sdx + g1.x * Sdy);
+          else if (c == 2) val = -0.5f * (uu * uu * M[0] - 2.f * uu * M[1] + M[3]);
+          else if (c == 3) val = -(uu * vv * M[0] - uu * M[2] - vv * M[1] + M[4]);
+          else if (c == 4) val = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
+          else val = M[0] / g1.y;
+        }
+        gslot[(size_t)pslot[rg.x + lo + e] * GS + c] = val;
+      }
+      pbuf ^= 1;
     }
+    rhi = nrhi;
+    rlo = nrlo;
   }
 }
 

@@ -125,176 +125,21 @@ __global__ void __launch_bounds__(kDecThreads) k_decode_fwd(DecodeConst dc, Head
 }
 
 // ---------------------------------------------------------------------------
-// Backward, per view, in three stages over a workspace holding, per anchor,
+// Backward, per view, in two stages over a workspace holding, per anchor,
 // X (36 floats: input + pad), H (160 hidden activations), dY (second-layer
 // output gradients, row stride RP) and dZ (160 first-layer pre-activation
 // gradients):
-//   prep : recompute X, H and Y; dY = dL/d(decoded) * act'(Y)
-//   mid  : dH = W2^T dY, dZ = dH * act'(Z) (from H: ReLU -> H > 0, SoftPlus ->
-//          1 - exp(-H)), dX = W1^T dZ -> anchor feature and direction
-//          gradients, camera-centre partial sums
+//   tile : on the matrix cores (decode_bwd_mfma.hip): recompute X, H, Y;
+//          dY = dL/d(decoded) * act'(Y), dH = W2^T dY, dZ = dH * act'(Z),
+//          dX = W1^T dZ -> anchor feature and direction gradients,
+//          camera-centre partial sums
 //   wgrad: per chunk of anchors, dW2 = dY^T H, dW1 = dZ^T X and the bias sums,
 //          one partial per workgroup (summed over views), then a fixed-order
 //          reduction over workgroups.
 // ---------------------------------------------------------------------------
-constexpr int kMidAnchors = 16;
-
-// Workgroup partials of the parameter gradients are stored chunk-major: for
-// every run of 64 parameters, the 64-float segments of all workgroups are
-// contiguous, so the reduction of one run reads one contiguous region.
-ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
 constexpr int kWChunk = 64;     // anchors per weight-gradient workgroup
 constexpr int kWThreads = 1024;
 constexpr int kWSub = 16;       // anchors staged in LDS at a time
-
-__global__ void __launch_bounds__(kDecThreads) k_dec_bwd_prep(DecodeConst dc, HeadTable ht, DecodeViews dv,
-                                                              const float* __restrict__ xyz,
-                                                              const float* __restrict__ feat,
-                                                              const float* __restrict__ params,
-                                                              asgs_gaussians dg, int view, DecWork w) {
-  constexpr int kDecAnchors = kFwdAnchors;
-  __shared__ float X[kDecAnchors][kIn + 1];
-  __shared__ float H[kDecAnchors * kHeads][kHid + 1];
-  __shared__ float dist[kDecAnchors];
-  const int64_t a0 = (int64_t)blockIdx.x * kDecAnchors;
-  const int64_t A = dc.A;
-  const int k = dc.k;
-  const int64_t n = A * k;
-  load_inputs<kDecAnchors>(xyz, feat, A, a0, dv.c[view], X, dist);
-  __syncthreads();
-  layer1<kDecAnchors>(params, ht, X, H, nullptr);
-  __syncthreads();
-  const int t = threadIdx.x;
-  for (int e = t; e < kDecAnchors * 36; e += kDecThreads) {
-    const int a = e / 36, c = e % 36;
-    if (a0 + a < A) w.X[(a0 + a) * 36 + c] = X[a][c];
-  }
-  for (int e = t; e < kDecAnchors * 160; e += kDecThreads) {
-    const int a = e / 160, j = e % 160;
-    if (a0 + a < A) w.H[(a0 + a) * 160 + j] = j < ht.nunits ? H[a * kHeads + j / kHid][j % kHid] : 0.f;
-  }
-  for (int o = t; o < ht.nrows; o += kDecThreads) {
-    const int h = row_head(ht, o);
-    const int oh = o - ht.row0[h];
-    const int m = ht.m[h];
-    const int i = oh / m, comp = oh - i * m;
-    const float* W2 = params + ht.off[h] + kHid * kIn + kHid + oh * kHid;
-    const float b2 = params[ht.off[h] + kHid * kIn + kHid + k * m * kHid + oh];
-    float wr[kHid];
-#pragma unroll
-    for (int c = 0; c < kHid; ++c) wr[c] = W2[c];
-    const float* plane = out_plane(dg, view, h, comp, n);
-    for (int a = 0; a < kDecAnchors; ++a) {
-      if (a0 + a >= A) break;
-      float y = b2;
-#pragma unroll
-      for (int c = 0; c < kHid; ++c) y = fmaf(wr[c], H[a * kHeads + h][c], y);
-      w.dY[(a0 + a) * w.RP + o] = plane[(a0 + a) * k + i] * act_grad(h, y, dc.l_s);
-    }
-  }
-}
-
-__global__ void __launch_bounds__(kDecThreads) k_dec_bwd_mid(DecodeConst dc, HeadTable ht, DecodeViews dv,
-                                                             const float* __restrict__ xyz,
-                                                             const float* __restrict__ params, int view,
-                                                             DecWork w, float* d_xyz, float* d_feat) {
-  __shared__ float sdY[kMidAnchors][kMaxRows + 4];
-  __shared__ float sdZ[kMidAnchors][160 + 4];
-  __shared__ float sdX[kMidAnchors][kIn + 1];
-  __shared__ float red[3][kDecThreads / 64];
-  const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
-  const int64_t A = dc.A;
-  const int k = dc.k;
-  const int64_t a0 = (int64_t)blockIdx.x * kMidAnchors;
-  const int nrows = ht.nrows;
-  for (int e = t; e < kMidAnchors * nrows; e += kDecThreads) {
-    const int a = e / nrows, o = e - a * nrows;
-    sdY[a][o] = (a0 + a < A) ? w.dY[(a0 + a) * w.RP + o] : 0.f;
-  }
-  __syncthreads();
-  // dZ for hidden unit j of head uh, anchors of half `half`
-  {
-    const int j = t % 160, half = t / 160;
-    if (j < ht.nunits && half < 2) {
-      const int uh = j / kHid, ujj = j % kHid;
-      const int rows = k * ht.m[uh];
-      const int r0 = ht.row0[uh];
-      const float* W2c = params + ht.off[uh] + kHid * kIn + kHid + ujj;
-      constexpr int NA = kMidAnchors / 2;
-      float dh[NA];
-#pragma unroll
-      for (int q = 0; q < NA; ++q) dh[q] = 0.f;
-      for (int oh = 0; oh < rows; ++oh) {
-        const float wgt = W2c[oh * kHid];
-#pragma unroll
-        for (int q = 0; q < NA; ++q) dh[q] = fmaf(wgt, sdY[half * NA + q][r0 + oh], dh[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const int a = half * NA + q;
-        float dz = 0.f;
-        if (a0 + a < A) {
-          const float hv = w.H[(a0 + a) * 160 + j];
-          dz = (uh == 4) ? dh[q] * (1.f - expf(-hv)) : (hv > 0.f ? dh[q] : 0.f);
-          w.dZ[(a0 + a) * 160 + j] = dz;
-        }
-        sdZ[a][j] = dz;
-      }
-    }
-  }
-  __syncthreads();
-  // dX = W1^T dZ
-  for (int e = t; e < kMidAnchors * kIn; e += kDecThreads) {
-    const int a = e / kIn, c = e - a * kIn;
-    float sx = 0.f;
-    for (int h = 0; h < kHeads; ++h) {
-      if (ht.m[h] == 0) continue;
-      const float* W1 = params + ht.off[h] + c;
-#pragma unroll 8
-      for (int jj = 0; jj < kHid; ++jj) sx = fmaf(W1[jj * kIn], sdZ[a][h * kHid + jj], sx);
-    }
-    sdX[a][c] = sx;
-  }
-  __syncthreads();
-  for (int e = t; d_feat && e < kMidAnchors * 32; e += kDecThreads) {
-    const int a = e / 32, c = e % 32;
-    if (a0 + a < A) {
-      float* p = &d_feat[(a0 + a) * 32 + c];
-      *p = (view == 0 ? 0.f : *p) + sdX[a][c];
-    }
-  }
-  float dcl[3] = {0.f, 0.f, 0.f};
-  if (t < kMidAnchors && a0 + t < A) {
-    const int64_t a = a0 + t;
-    float D[3];
-    for (int c = 0; c < 3; ++c) D[c] = xyz[c * A + a] - dv.c[view][c];
-    const float d = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-    float del[3];
-    for (int c = 0; c < 3; ++c) del[c] = D[c] / d;
-    const float* gd = &sdX[t][32];
-    const float pr = del[0] * gd[0] + del[1] * gd[1] + del[2] * gd[2];
-    for (int c = 0; c < 3; ++c) {
-      const float dD = (gd[c] - del[c] * pr) / d;
-      if (d_xyz) {
-        float* p = &d_xyz[c * A + a];
-        *p = (view == 0 ? 0.f : *p) + dD;
-      }
-      dcl[c] = -dD;
-    }
-  }
-  for (int c = 0; c < 3; ++c) {
-    float x = dcl[c];
-    for (int o2 = 32; o2 > 0; o2 >>= 1) x += __shfl_xor(x, o2);
-    if (lane == 0) red[c][wv] = x;
-  }
-  __syncthreads();
-  if (t < 3) {
-    float sum = 0.f;
-    for (int q = 0; q < kDecThreads / 64; ++q) sum += red[t][q];
-    w.dcpart[((int64_t)blockIdx.x * dc.n_views + view) * 3 + t] = sum;
-  }
-}
 
 // Mean gradients summed over views: d_off = l_o dmu, d_xyz += sum_i dmu.
 __global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, float* d_off) {
@@ -534,7 +379,7 @@ WorkSizes work_sizes(const DecodeConst& dc) {
   for (int h = 0; h < kHeads; ++h) rows += (int64_t)dc.k * dc.head_m[h];
   z.RP = (rows + 3) / 4 * 4;
   z.nblk_w = (dc.A + kWChunk - 1) / kWChunk;
-  z.nblk_m = (dc.A + kMidAnchors - 1) / kMidAnchors;
+  z.nblk_m = (dc.A + kBwdTileAnchors - 1) / kBwdTileAnchors;
   size_t o = 0;
   z.X = o; o = a256(o + (size_t)dc.A * 36 * 4);
   z.H = o; o = a256(o + (size_t)dc.A * 160 * 4);
@@ -601,12 +446,8 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
   w.RP = (int32_t)z.RP;
   w.nblk_w = (int32_t)z.nblk_w;
   w.nblk_m = (int32_t)z.nblk_m;
-  const unsigned gp = (unsigned)((dc.A + kFwdAnchors - 1) / kFwdAnchors);
   for (int view = 0; view < dc.n_views; ++view) {
-    hipLaunchKernelGGL(k_dec_bwd_prep, dim3(gp), dim3(kDecThreads), 0, s, dc, ht, dv, xyz, feat, params, dg,
-                       view, w);
-    hipLaunchKernelGGL(k_dec_bwd_mid, dim3((unsigned)z.nblk_m), dim3(kDecThreads), 0, s, dc, ht, dv, xyz,
-                       params, view, w, d_xyz, d_feat);
+    launch_dec_bwd_tile(dc, ht, dv, xyz, feat, params, dg, view, w, d_xyz, d_feat, s);
     if (d_params)
       hipLaunchKernelGGL(k_dec_bwd_wgrad, dim3((unsigned)z.nblk_w), dim3(kWThreads), 0, s, dc, ht, view, w);
   }

@@ -72,17 +72,24 @@ struct DecWork {
   float* dY;
   float* dZ;
   float* part;    // per-workgroup parameter-gradient partials (chunk-major, see part_index)
-  float* dcpart;  // [nblk_m][n_views][3]
+  float* dcpart;  // [nblk_m][n_views][3], one row per backward workgroup
   int32_t RP;     // row stride of dY
   int32_t nblk_w, nblk_m;
 };
 
 
+// Workgroup partials of the parameter gradients are stored chunk-major: for
+// every run of 64 parameters, the 64-float segments of all workgroups are
+// contiguous, so the reduction of one run reads one contiguous region.
+ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
+
+constexpr int kBwdTileAnchors = 64;  // anchors per workgroup of the MFMA decoder backward (4 waves x 16)
+
+void launch_dec_bwd_tile(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
+                         const float* feat, const float* params, const asgs_gaussians& dg, int view,
+                         const DecWork& w, float* d_xyz, float* d_feat, hipStream_t s);
 void launch_decode_mfma(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                         const float* feat, const float* off, const float* params, const asgs_gaussians& out,
                         hipStream_t s);
-void launch_decode_prep_mfma(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
-                             const float* feat, const float* params, const asgs_gaussians& dg, int view,
-                             const DecWork& w, hipStream_t s);
 
 }  // namespace asgs

@@ -185,7 +185,9 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
     return;
   }
   geom[2 * gid] = make_float4(u, v, A, B);
-  geom[2 * gid + 1] = make_float4(C, o, 0.f, 0.f);
+  // slot 6: the power at which o exp(power) reaches alpha_min, so that the
+  // blend kernels test alpha >= alpha_min without an exponential
+  geom[2 * gid + 1] = make_float4(C, o, logf(rc.alpha_min / o), 0.f);
   const float* rgb = g.rgb + view * g.view_stride[4];
   float* ch = chan + gid * CS;
   ch[0] = rgb[i];

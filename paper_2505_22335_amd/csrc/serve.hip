@@ -1,5 +1,5 @@
 // Request loop over a resident anchor scene: continuous batching of tracking
-// and mapping renders (UP-SLAM Sec. 3.4 tracking, Sec. 3.5 mapping), with
+// and mapping renders (UP-SLAM Sec. 3.4 tracking, Sec. 3.3 mapping), with
 // admission by device memory and overlap of batches on several HIP streams.
 // Semantics and ABI: asgs_serve.h.
 #include <hip/hip_runtime.h>
