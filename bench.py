@@ -1,7 +1,7 @@
 """Throughput of the anchor-Gaussian hot path on one MI355X.
 
 One step = decode (anchor MLPs) -> render forward (project, bin/sort, blend) ->
-L1 loss gradient (PyTorch) -> render backward -> decode backward, for one batch
+L1 loss gradient -> render backward -> decode backward, for one batch
 of views of a synthetic scene resident in HBM. Prints one JSON line.
 
 Default workload: 20k anchors x 10 = 200k Gaussians on the shell of a
@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="measured seconds of the serving mix (after 1 s warm-up; 0 = skip)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving mix (2 s warm-up)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one step into a HIP graph and time its replays (checked bitwise against the eager step)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the hot path is not sharded across GPUs in this build "
@@ -226,6 +228,7 @@ def main():
 
     import synth
     from paper_2505_22335_amd import _lib as L
+    from paper_2505_22335_amd.core import l1_loss_grad
     from paper_2505_22335_amd.pipeline import AnchorRenderer, anchors_to_device
 
     if args.serve_only:
@@ -251,9 +254,8 @@ def main():
 
     def step():
         img = r.forward()
-        for k in dimg:  # L1 loss gradient, mean over each output
-            torch.sign(torch.sub(img[k], tgt[k]), out=dimg[k])
-            dimg[k].mul_(scale[k])
+        # L1 loss gradient, mean over each output (one fused library kernel)
+        l1_loss_grad(img, tgt, dimg, scale)
         r.backward(dimg)
 
     if args.copy_probe_mb:
@@ -268,18 +270,39 @@ def main():
     I, nvis, ov = r.rc.status()
     if ov:
         raise RuntimeError("intersection capacity exceeded")
-    L.profile_enable(1 << L.K_BLEND_BWD)
+    run = step
+    if args.graph:
+        # The whole step (every library kernel and the loss ops) captured once
+        # into a HIP graph and replayed: same work, no per-launch host cost.
+        # A replay must reproduce the eager step bitwise.
+        ref = {k: v.clone() for k, v in r.images.items()}
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in ref:
+            if not torch.equal(ref[k], r.images[k]):
+                raise RuntimeError(f"graph replay differs from the eager step ({k})")
+        run = graph.replay
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        step()
+        run()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
+    # the dominant kernel's mean launch time: HIP events recorded on its launch
+    # stream around every blend-backward launch of the same number of steps,
+    # launched from the host (a graph replay carries no per-launch events)
+    L.profile_enable(1 << L.K_BLEND_BWD)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     bb_ms, bb_n = L.profile_read(L.K_BLEND_BWD)
     L.profile_enable(0)
     N, A, P = r.a.A * r.a.k, r.a.A, V * H * W
@@ -310,6 +333,7 @@ def main():
                      "avg_ms": round(dom_ms, 5), "launches": bb_n,
                      "algorithmic_bytes": int(ab["blend_bwd"])},
         "wall_s": round(wall, 3),
+        "launch": "hip-graph" if args.graph else "host",
     }
     if args.breakdown:
         L.profile_enable((1 << L.K_NUM) - 1 if hasattr(L, "K_NUM") else 0x7F)

@@ -239,6 +239,33 @@ int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const f
                          size_t work_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Weighted L1 residual of rendered maps (the photometric, depth and feature
+ * residual of the tracking and mapping losses, UP-SLAM Eq. 4 and Sec. 3.4)
+ * and its gradient, in one pass. For view v, pixel p, channel group g (rgb,
+ * depth, feat, alpha) with a target:
+ *   loss[v] += scale[g] * w_p * |x - x*|,   grad = scale[g] * w_p * sign(x - x*)
+ * with sign(0) = 0 and w_p = weight[p] (1 when weight is NULL). Maps,
+ * targets and gradients are packed like asgs_images for n_views views of
+ * width x height; a group whose target is NULL contributes nothing and its
+ * gradient plane (if not NULL) is zeroed; NULL gradient planes are not
+ * written. loss (NULL or device [n_views]) needs work of
+ * asgs_l1_loss_work_size bytes; without loss, work may be NULL.
+ * ------------------------------------------------------------------------- */
+typedef struct asgs_l1_targets {
+  const float* rgb;     /* [n_views][3][H][W] or NULL */
+  const float* depth;   /* [n_views][H][W] or NULL */
+  const float* feat;    /* [n_views][n_feat][H][W] or NULL */
+  const float* alpha;   /* [n_views][H][W] or NULL */
+  const float* weight;  /* [H][W] per-pixel weight shared by the views, or NULL */
+  float scale[4];       /* multipliers of the rgb, depth, feat and alpha terms */
+} asgs_l1_targets;
+
+int asgs_l1_loss_work_size(int32_t n_views, size_t* bytes);
+int asgs_l1_loss(int32_t n_views, int32_t width, int32_t height, int32_t n_feat, const asgs_images* maps,
+                 const asgs_l1_targets* targets, const asgs_images* grad, float* loss, void* work,
+                 size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Timing hook (for measurement tools; off by default)
  *
  * While a kernel class is enabled, each launch of it made by this library is

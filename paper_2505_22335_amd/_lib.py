@@ -67,6 +67,11 @@ class Decoder(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class L1Targets(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("feat", C.c_void_p), ("alpha", C.c_void_p),
+                ("weight", C.c_void_p), ("scale", C.c_float * 4)]
+
+
 P = C.c_void_p
 _sigs = {
     "asgs_abi_version": (C.c_int, []),
@@ -91,6 +96,9 @@ _sigs = {
     "asgs_decode_workspace_size": (C.c_int, [C.POINTER(Decoder), C.c_int32, C.POINTER(C.c_size_t)]),
     "asgs_decode_backward": (C.c_int, [C.POINTER(Decoder), P, P, P, P, C.POINTER(Camera), C.c_int32,
                                        C.POINTER(Gaussians), P, P, P, P, P, P, C.c_size_t, P]),
+    "asgs_l1_loss_work_size": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "asgs_l1_loss": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Images), C.POINTER(L1Targets),
+                               C.POINTER(Images), P, P, C.c_size_t, P]),
     "asgs_profile_enable": (C.c_int, [C.c_uint32]),
     "asgs_profile_read": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
@@ -262,6 +270,19 @@ def decode_backward(d: Decoder, xyz, feat, off, params, cams, dg: Gaussians, d_x
                                    params.data_ptr(), ca, len(cams), C.byref(dg), _ptr(d_xyz),
                                    _ptr(d_feat), _ptr(d_off), _ptr(d_params), _ptr(d_pose),
                                    work.data_ptr(), work.numel(), _stream(stream)), "asgs_decode_backward")
+
+
+def l1_loss_work_size(n_views: int) -> int:
+    b = C.c_size_t()
+    check(lib.asgs_l1_loss_work_size(n_views, C.byref(b)), "asgs_l1_loss_work_size")
+    return b.value
+
+
+def l1_loss(n_views: int, width: int, height: int, n_feat: int, maps: Images, targets: L1Targets, grad: Images,
+            loss=None, work=None, stream=None):
+    check(lib.asgs_l1_loss(n_views, width, height, n_feat, C.byref(maps), C.byref(targets), C.byref(grad),
+                           _ptr(loss), _ptr(work), 0 if work is None else work.numel(), _stream(stream)),
+          "asgs_l1_loss")
 
 
 def profile_enable(mask: int):

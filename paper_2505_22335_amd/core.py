@@ -189,3 +189,25 @@ class Decoder:
         L.decode_backward(self.desc, xyz, feat, off, params, cams, L.make_gaussians(dg, self.n), d_xyz, d_feat,
                           d_off, d_params, d_pose, self.work)
         return d_xyz, d_feat, d_off, d_params
+
+
+def l1_loss_grad(maps: Dict[str, torch.Tensor], targets: Dict[str, torch.Tensor], grad: Dict[str, torch.Tensor],
+                 scale: Dict[str, float], weight: Optional[torch.Tensor] = None,
+                 loss: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+    """Weighted L1 residual of packed maps (V, C, H, W) against targets in
+    one library kernel (asgs_l1_loss): writes sign gradients times scale into
+    grad and, with loss (a (V,) tensor), the per-view loss."""
+    rgb = maps["rgb"]
+    V, H, W = rgb.shape[0], rgb.shape[-2], rgb.shape[-1]
+    nf = maps["feat"].shape[1] if "feat" in maps else 0
+    t = L.L1Targets()
+    for k in ("rgb", "depth", "feat", "alpha"):
+        setattr(t, k, L._ptr(targets.get(k)))
+    t.weight = L._ptr(weight)
+    for i, k in enumerate(("rgb", "depth", "feat", "alpha")):
+        t.scale[i] = float(scale.get(k, 0.0))
+    work = None
+    if loss is not None:
+        work = torch.empty(L.l1_loss_work_size(V), dtype=torch.uint8, device=rgb.device)
+    L.l1_loss(V, W, H, nf, L.make_images(maps), t, L.make_images(grad), loss, work)
+    return loss

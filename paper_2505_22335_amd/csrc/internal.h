@@ -18,7 +18,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortIPT = 4;          // items per thread per radix block
 constexpr int kSortItems = kSortThreads * kSortIPT;
 constexpr int kScanThreads = 256;
-constexpr int kScanIPT = 8;
+constexpr int kScanIPT = 1;   // one visible Gaussian per thread: enough blocks to fill the GPU
 constexpr int kScanItems = kScanThreads * kScanIPT;
 constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
 
@@ -95,6 +95,24 @@ void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx,
 void launch_project_backward(const RenderConst& rc, const asgs_gaussians& g,
                              const asgs_gaussians& dg, float* d_pose, const CtxLayout& L,
                              char* ctx, hipStream_t s);
+
+// Weighted L1 residual of packed maps (loss.hip). Groups: 0 rgb (3), 1 depth
+// (1), 2 feature (nf), 3 opacity sum (1).
+constexpr int kL1Blocks = 512;  // blocks per view of the loss kernel
+struct L1Views {
+  const float* t[4][ASGS_MAX_VIEWS];  // targets per group and view ([C][H][W]); NULL = no term
+  const float* w[ASGS_MAX_VIEWS];     // per-pixel weights per view; NULL = 1
+};
+struct L1Args {
+  const float* x[4];  // rendered maps per group, packed [V][C][HW]
+  float* g[4];        // gradient maps per group (packed like x), NULL = not written
+  float* partial;     // [V][kL1Blocks] partial sums, or NULL (no loss value)
+  float* loss;        // [V] or NULL
+  int64_t HW;
+  int32_t nf, n_views;
+  float s[4];         // scale of each group's term
+};
+void launch_l1_loss(const L1Args& a, const L1Views& tv, hipStream_t s);
 
 struct DecodeConst {
   int64_t A;

@@ -25,85 +25,9 @@
 namespace {
 
 using asgs::fail;
-
-constexpr int kLossThreads = 256;
-constexpr int kLossBlocks = 64;  // per view
-
-struct LossArgs {
-  const float* trgb[ASGS_MAX_VIEWS];
-  const float* tdepth[ASGS_MAX_VIEWS];
-  const float* tfeat[ASGS_MAX_VIEWS];
-  const float* weight[ASGS_MAX_VIEWS];
-  const float* rgb;    // [V][3][HW]
-  const float* depth;  // [V][HW]
-  const float* feat;   // [V][nf][HW]
-  float* grgb;
-  float* gdepth;
-  float* gfeat;
-  float* partial;  // [V][kLossBlocks]
-  int64_t HW;
-  int32_t nf;
-  float s_rgb, s_depth, s_feat;  // 1/(3HW), 1/HW, 1/(nf HW)
-};
-
-__device__ __forceinline__ float sgn(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
-
-// Weighted L1 residual of one batch: gradient maps and per-block loss sums.
-__global__ void __launch_bounds__(kLossThreads) k_l1_loss(LossArgs a) {
-  __shared__ float red[kLossThreads / 64];
-  const int v = blockIdx.y;
-  const int64_t HW = a.HW;
-  const float* w = a.weight[v];
-  const float* tr = a.trgb[v];
-  const float* td = a.tdepth[v];
-  const float* tf = a.tfeat[v];
-  const float* xr = a.rgb + (int64_t)v * 3 * HW;
-  const float* xd = a.depth + (int64_t)v * HW;
-  const float* xf = a.feat + (int64_t)v * a.nf * HW;
-  float* gr = a.grgb + (int64_t)v * 3 * HW;
-  float* gd = a.gdepth + (int64_t)v * HW;
-  float* gf = a.gfeat + (int64_t)v * a.nf * HW;
-  float acc = 0.f;
-  for (int64_t p = (int64_t)blockIdx.x * kLossThreads + threadIdx.x; p < HW; p += (int64_t)gridDim.x * kLossThreads) {
-    const float wp = w ? w[p] : 1.f;
-    float lr = 0.f;
-    for (int c = 0; c < 3; ++c) {
-      const float d = xr[c * HW + p] - tr[c * HW + p];
-      gr[c * HW + p] = wp * sgn(d) * a.s_rgb;
-      lr += fabsf(d);
-    }
-    const float dd = xd[p] - td[p];
-    gd[p] = wp * sgn(dd) * a.s_depth;
-    float lf = 0.f;
-    for (int c = 0; c < a.nf; ++c) {
-      if (tf) {
-        const float d = xf[c * HW + p] - tf[c * HW + p];
-        gf[c * HW + p] = wp * sgn(d) * a.s_feat;
-        lf += fabsf(d);
-      } else {
-        gf[c * HW + p] = 0.f;
-      }
-    }
-    acc += wp * (lr * a.s_rgb + fabsf(dd) * a.s_depth + lf * a.s_feat);
-  }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float s = 0.f;
-    for (int q = 0; q < kLossThreads / 64; ++q) s += red[q];
-    a.partial[v * kLossBlocks + blockIdx.x] = s;
-  }
-}
-
-// Per-view loss: fixed-order sum of the block partials.
-__global__ void k_l1_loss_sum(const float* partial, float* loss, int n_views) {
-  const int v = threadIdx.x;
-  if (v >= n_views) return;
-  float s = 0.f;
-  for (int b = 0; b < kLossBlocks; ++b) s += partial[v * kLossBlocks + b];
-  loss[v] = s;
-}
+using asgs::L1Args;
+using asgs::L1Views;
+using asgs::launch_l1_loss;
 
 double now_s() {
   using namespace std::chrono;
@@ -249,7 +173,7 @@ BatchLayout layout(const Server& S, const Batch& b, int64_t capacity) {
   L.dg = take(L.dg_stride * V);
   L.dpose = take((uint64_t)V * 6 * 4);
   L.loss = take((uint64_t)V * 4);
-  L.partial = take((uint64_t)V * kLossBlocks * 4);
+  L.partial = take((uint64_t)V * asgs::kL1Blocks * 4);
   asgs_decoder d = S.dec;
   (void)asgs_decode_workspace_size(&d, (int32_t)V, &L.work_bytes);
   L.work = take(L.work_bytes);
@@ -322,33 +246,39 @@ int run_batch(Server& S, Batch& b, const BatchLayout& L) {
   dimg.depth = db + (int64_t)V * 3 * HW;
   dimg.feat = nf ? db + (int64_t)V * 4 * HW : nullptr;
   dimg.alpha = nullptr;
-  LossArgs la{};
+  L1Args la{};
+  L1Views tv{};
   {
     int v = 0;
     for (Req* r : b.reqs) {
       for (int j = 0; j < r->r.n_views; ++j, ++v) {
-        la.trgb[v] = r->trgb[j];
-        la.tdepth[v] = r->tdepth[j];
-        la.tfeat[v] = r->tfeat.empty() ? nullptr : r->tfeat[j];
-        la.weight[v] = r->r.weight;
+        tv.t[0][v] = r->trgb[j];
+        tv.t[1][v] = r->tdepth[j];
+        tv.t[2][v] = r->tfeat.empty() ? nullptr : r->tfeat[j];
+        tv.t[3][v] = nullptr;
+        tv.w[v] = r->r.weight;
       }
     }
   }
-  la.rgb = img.rgb;
-  la.depth = img.depth;
-  la.feat = img.feat ? img.feat : img.rgb;
-  la.grgb = dimg.rgb;
-  la.gdepth = dimg.depth;
-  la.gfeat = dimg.feat ? dimg.feat : dimg.rgb;
+  la.x[0] = img.rgb;
+  la.x[1] = img.depth;
+  la.x[2] = img.feat;
+  la.x[3] = nullptr;
+  la.g[0] = dimg.rgb;
+  la.g[1] = dimg.depth;
+  la.g[2] = dimg.feat;
+  la.g[3] = nullptr;
+  float* loss = reinterpret_cast<float*>(p + L.loss);
   la.partial = reinterpret_cast<float*>(p + L.partial);
+  la.loss = loss;
   la.HW = HW;
   la.nf = nf;
-  la.s_rgb = (float)(1.0 / (3.0 * (double)HW));
-  la.s_depth = (float)(1.0 / (double)HW);
-  la.s_feat = nf ? (float)(1.0 / ((double)nf * (double)HW)) : 0.f;
-  hipLaunchKernelGGL(k_l1_loss, dim3(kLossBlocks, V), dim3(kLossThreads), 0, s, la);
-  float* loss = reinterpret_cast<float*>(p + L.loss);
-  hipLaunchKernelGGL(k_l1_loss_sum, dim3(1), dim3(64), 0, s, la.partial, loss, V);
+  la.n_views = V;
+  la.s[0] = (float)(1.0 / (3.0 * (double)HW));
+  la.s[1] = (float)(1.0 / (double)HW);
+  la.s[2] = nf ? (float)(1.0 / ((double)nf * (double)HW)) : 0.f;
+  la.s[3] = 0.f;
+  launch_l1_loss(la, tv, s);
   if ((st = hip_check(hipGetLastError(), "loss kernels"))) return st;
   asgs_gaussians dg = gauss_view(S, L, p, true);
   float* dpose = reinterpret_cast<float*>(p + L.dpose);
