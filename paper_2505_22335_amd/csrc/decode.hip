@@ -378,7 +378,7 @@ WorkSizes work_sizes(const DecodeConst& dc) {
   int64_t rows = 0;
   for (int h = 0; h < kHeads; ++h) rows += (int64_t)dc.k * dc.head_m[h];
   z.RP = (rows + 3) / 4 * 4;
-  z.nblk_w = (dc.A + kWChunk - 1) / kWChunk;
+  z.nblk_w = wgrad_blocks(dc.A);
   z.nblk_m = (dc.A + kBwdTileAnchors - 1) / kBwdTileAnchors;
   size_t o = 0;
   z.X = o; o = a256(o + (size_t)dc.A * 36 * 4);
@@ -448,8 +448,7 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
   w.nblk_m = (int32_t)z.nblk_m;
   for (int view = 0; view < dc.n_views; ++view) {
     launch_dec_bwd_tile(dc, ht, dv, xyz, feat, params, dg, view, w, d_xyz, d_feat, s);
-    if (d_params)
-      hipLaunchKernelGGL(k_dec_bwd_wgrad, dim3((unsigned)z.nblk_w), dim3(kWThreads), 0, s, dc, ht, view, w);
+    if (d_params) launch_dec_wgrad_mfma(dc, ht, view, w, s);
   }
   if (d_xyz)
     hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,

@@ -59,7 +59,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_dec_bwd_tile(DecodeConst dc, He
   __shared__ float sG[kWaves][16][4];     // view-direction gradients
   __shared__ float red[kWaves][3];
   const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
+  const int lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index, uniform across the wave
   const int fl = lane & 15, fg = lane >> 4;
   const int A = (int)dc.A;
   const int k = dc.k;

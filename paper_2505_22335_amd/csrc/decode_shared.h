@@ -83,6 +83,9 @@ struct DecWork {
 // contiguous, so the reduction of one run reads one contiguous region.
 ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
 
+constexpr int kWgradMaxWG = 256;     // persistent workgroups of the weight-gradient kernel
+int64_t wgrad_blocks(int64_t n_anchors);
+void launch_dec_wgrad_mfma(const DecodeConst& dc, const HeadTable& ht, int view, const DecWork& w, hipStream_t s);
 constexpr int kBwdTileAnchors = 64;  // anchors per workgroup of the MFMA decoder backward (4 waves x 16)
 
 void launch_dec_bwd_tile(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
