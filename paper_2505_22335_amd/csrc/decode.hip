@@ -12,10 +12,10 @@
 // weight row in registers, broadcasting anchor inputs from LDS; the second
 // layer runs with one output row per thread over the hidden activations held
 // in LDS; many small workgroups keep the SIMDs busy. The BF16 path runs on the
-// matrix cores (decode_mfma.hip). The backward (FP32) recomputes the forward,
-// then forms dL/dH from the second-layer weights, dL/dZ through the
-// activations, dL/dX from the first layer, and the weight gradients as
-// per-workgroup outer-product sums reduced in a fixed order (deterministic,
+// matrix cores (decode_mfma.hip). The backward (FP32) recomputes the forward
+// on the matrix cores, then forms dL/dH from the second-layer weights, dL/dZ
+// through the activations, dL/dX from the first layer, and the weight
+// gradients as per-workgroup sums reduced in a fixed order (deterministic,
 // no atomics).
 #include <math.h>
 
@@ -125,22 +125,11 @@ __global__ void __launch_bounds__(kDecThreads) k_decode_fwd(DecodeConst dc, Head
 }
 
 // ---------------------------------------------------------------------------
-// Backward, per view, in two stages over a workspace holding, per anchor,
-// X (36 floats: input + pad), H (160 hidden activations), dY (second-layer
-// output gradients, row stride RP) and dZ (160 first-layer pre-activation
-// gradients):
-//   tile : on the matrix cores (decode_bwd_mfma.hip): recompute X, H, Y;
-//          dY = dL/d(decoded) * act'(Y), dH = W2^T dY, dZ = dH * act'(Z),
-//          dX = W1^T dZ -> anchor feature and direction gradients,
-//          camera-centre partial sums
-//   wgrad: per chunk of anchors, dW2 = dY^T H, dW1 = dZ^T X and the bias sums,
-//          one partial per workgroup (summed over views), then a fixed-order
-//          reduction over workgroups.
+// Backward, per view: one kernel on the matrix cores (decode_bwd_fused.hip)
+// recomputes the forward per 16-anchor tile and forms the anchor gradients,
+// the camera-centre partial sums and per-workgroup partials of every MLP
+// parameter gradient; the partials are then reduced in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kWChunk = 64;     // anchors per weight-gradient workgroup
-constexpr int kWThreads = 1024;
-constexpr int kWSub = 16;       // anchors staged in LDS at a time
-
 // Mean gradients summed over views: d_off = l_o dmu, d_xyz += sum_i dmu.
 __global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, float* d_off) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -164,132 +153,6 @@ __global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, 
 // Weight gradients of one view, accumulated into per-workgroup partials.
 // Tasks: dW2 rows x 16-column halves, dW1 units x 12-column thirds of the
 // 36-wide (padded) input, and the bias sums.
-__global__ void __launch_bounds__(kWThreads) k_dec_bwd_wgrad(DecodeConst dc, HeadTable ht, int view, DecWork w) {
-  __shared__ float sY[kWSub][kMaxRows + 4];
-  __shared__ float sH[kWSub][160];
-  __shared__ float sZ[kWSub][160];
-  __shared__ float sX[kWSub][36];
-  constexpr int TPT = 2;   // tile tasks per thread (max): 2 * 432 + 3 * 160 <= 2 * 1024
-  const int t = threadIdx.x;
-  const int64_t A = dc.A;
-  const int nrows = ht.nrows, nunits = ht.nunits;
-  const int t2 = nrows * 2;         // dW2 tasks
-  const int t1 = nunits * 3;        // dW1 tasks
-  const int tt = t2 + t1;
-  const int nb = nrows + nunits;    // bias tasks
-  float acc[TPT][16];
-#pragma unroll
-  for (int q = 0; q < TPT; ++q)
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc[q][c] = 0.f;
-  float bacc[1] = {0.f};  // bias tasks: nrows + nunits <= 432 + 160 <= 1024
-  const int64_t c0 = (int64_t)blockIdx.x * kWChunk;
-  for (int64_t s0 = c0; s0 < c0 + kWChunk && s0 < A; s0 += kWSub) {
-    __syncthreads();
-    for (int e = t; e < kWSub * nrows; e += kWThreads) {
-      const int a = e / nrows, o = e - a * nrows;
-      sY[a][o] = (s0 + a < A) ? w.dY[(s0 + a) * w.RP + o] : 0.f;
-    }
-    for (int e = t; e < kWSub * 160; e += kWThreads) {
-      const int a = e / 160, j = e - a * 160;
-      const bool ok = s0 + a < A;
-      sH[a][j] = ok ? w.H[(s0 + a) * 160 + j] : 0.f;
-      sZ[a][j] = ok ? w.dZ[(s0 + a) * 160 + j] : 0.f;
-    }
-    for (int e = t; e < kWSub * 36; e += kWThreads) {
-      const int a = e / 36, c = e - a * 36;
-      sX[a][c] = (s0 + a < A) ? w.X[(s0 + a) * 36 + c] : 0.f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-      const int task = t + q * kWThreads;
-      if (task < t2) {
-        const int o = task >> 1, half = task & 1;
-        const int hseg = row_head(ht, o) * kHid + half * 16;
-        for (int a = 0; a < kWSub; ++a) {
-          const float g = sY[a][o];
-          const float4* hp = reinterpret_cast<const float4*>(&sH[a][hseg]);
-#pragma unroll
-          for (int c4 = 0; c4 < 4; ++c4) {
-            const float4 hv = hp[c4];
-            acc[q][4 * c4 + 0] = fmaf(g, hv.x, acc[q][4 * c4 + 0]);
-            acc[q][4 * c4 + 1] = fmaf(g, hv.y, acc[q][4 * c4 + 1]);
-            acc[q][4 * c4 + 2] = fmaf(g, hv.z, acc[q][4 * c4 + 2]);
-            acc[q][4 * c4 + 3] = fmaf(g, hv.w, acc[q][4 * c4 + 3]);
-          }
-        }
-      } else if (task < tt) {
-        const int u = (task - t2) / 3, third = (task - t2) % 3;
-        for (int a = 0; a < kWSub; ++a) {
-          const float g = sZ[a][u];
-          const float4* xp = reinterpret_cast<const float4*>(&sX[a][third * 12]);
-#pragma unroll
-          for (int c4 = 0; c4 < 3; ++c4) {
-            const float4 xv = xp[c4];
-            acc[q][4 * c4 + 0] = fmaf(g, xv.x, acc[q][4 * c4 + 0]);
-            acc[q][4 * c4 + 1] = fmaf(g, xv.y, acc[q][4 * c4 + 1]);
-            acc[q][4 * c4 + 2] = fmaf(g, xv.z, acc[q][4 * c4 + 2]);
-            acc[q][4 * c4 + 3] = fmaf(g, xv.w, acc[q][4 * c4 + 3]);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 1; ++q) {
-      const int b = t + q * kWThreads;
-      if (b < nrows) {
-        for (int a = 0; a < kWSub; ++a) bacc[q] += sY[a][b];
-      } else if (b < nb) {
-        for (int a = 0; a < kWSub; ++a) bacc[q] += sZ[a][b - nrows];
-      }
-    }
-  }
-  // write (view 0) or accumulate (later views) this workgroup's partial
-  float* P = w.part;
-  const int64_t bk = blockIdx.x, nbk = w.nblk_w;
-  const bool add = view > 0;
-  const int k = dc.k;
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int task = t + q * kWThreads;
-    if (task < t2) {
-      const int o = task >> 1, half = task & 1;
-      const int h = row_head(ht, o);
-      const int oh = o - ht.row0[h];
-      const int64_t pi = ht.off[h] + kHid * kIn + kHid + oh * kHid + half * 16;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        float* dst = P + part_index(pi + c, bk, nbk);
-        *dst = (add ? *dst : 0.f) + acc[q][c];
-      }
-    } else if (task < tt) {
-      const int u = (task - t2) / 3, third = (task - t2) % 3;
-      const int h = u / kHid, jj = u % kHid;
-      const int64_t pi = ht.off[h] + jj * kIn + third * 12;
-#pragma unroll
-      for (int c = 0; c < 12; ++c)
-        if (third * 12 + c < kIn) {
-          float* dst = P + part_index(pi + c, bk, nbk);
-          *dst = (add ? *dst : 0.f) + acc[q][c];
-        }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 1; ++q) {
-    const int b = t + q * kWThreads;
-    float* dst = nullptr;
-    if (b < nrows) {
-      const int h = row_head(ht, b);
-      const int oh = b - ht.row0[h];
-      dst = P + part_index(ht.off[h] + kHid * kIn + kHid + k * ht.m[h] * kHid + oh, bk, nbk);
-    } else if (b < nb) {
-      const int u = b - nrows;
-      dst = P + part_index(ht.off[u / kHid] + kHid * kIn + (u % kHid), bk, nbk);
-    }
-    if (dst) *dst = (add ? *dst : 0.f) + bacc[q];
-  }
-}
 
 // Fixed-order reduction of the workgroup partials: 64 parameters per
 // workgroup, four threads per parameter (each a strided quarter of the
@@ -367,24 +230,17 @@ DecodeViews decode_views(const ViewDev* hv, int n_views) {
 }
 
 struct WorkSizes {
-  int64_t RP, nblk_w, nblk_m;
-  size_t X, H, dY, dZ, part, dcpart, total;
+  int64_t nblk_w, nblk_m;
+  size_t part, dcpart, total;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 WorkSizes work_sizes(const DecodeConst& dc) {
   WorkSizes z;
-  int64_t rows = 0;
-  for (int h = 0; h < kHeads; ++h) rows += (int64_t)dc.k * dc.head_m[h];
-  z.RP = (rows + 3) / 4 * 4;
-  z.nblk_w = wgrad_blocks(dc.A);
-  z.nblk_m = (dc.A + kBwdTileAnchors - 1) / kBwdTileAnchors;
+  z.nblk_w = dec_bwd_fused_blocks(dc.A);
+  z.nblk_m = z.nblk_w;
   size_t o = 0;
-  z.X = o; o = a256(o + (size_t)dc.A * 36 * 4);
-  z.H = o; o = a256(o + (size_t)dc.A * 160 * 4);
-  z.dY = o; o = a256(o + (size_t)dc.A * z.RP * 4);
-  z.dZ = o; o = a256(o + (size_t)dc.A * 160 * 4);
   z.part = o; o = a256(o + (size_t)z.nblk_w * ((dc.n_params + 63) / 64 * 64) * 4);
   z.dcpart = o; o = a256(o + (size_t)z.nblk_m * dc.n_views * 3 * 4);
   z.total = o;
@@ -437,19 +293,12 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
   const WorkSizes z = work_sizes(dc);
   char* wb = reinterpret_cast<char*>(work);
   DecWork w;
-  w.X = reinterpret_cast<float*>(wb + z.X);
-  w.H = reinterpret_cast<float*>(wb + z.H);
-  w.dY = reinterpret_cast<float*>(wb + z.dY);
-  w.dZ = reinterpret_cast<float*>(wb + z.dZ);
   w.part = reinterpret_cast<float*>(wb + z.part);
   w.dcpart = reinterpret_cast<float*>(wb + z.dcpart);
-  w.RP = (int32_t)z.RP;
   w.nblk_w = (int32_t)z.nblk_w;
   w.nblk_m = (int32_t)z.nblk_m;
-  for (int view = 0; view < dc.n_views; ++view) {
-    launch_dec_bwd_tile(dc, ht, dv, xyz, feat, params, dg, view, w, d_xyz, d_feat, s);
-    if (d_params) launch_dec_wgrad_mfma(dc, ht, view, w, s);
-  }
+  for (int view = 0; view < dc.n_views; ++view)
+    launch_dec_bwd_fused(dc, ht, dv, xyz, feat, params, dg, view, w, d_xyz, d_feat, d_params != nullptr, s);
   if (d_xyz)
     hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,
                        d_off);

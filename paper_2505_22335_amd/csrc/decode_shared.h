@@ -67,13 +67,8 @@ ASGS_DEV float act_grad(int h, float y, float l_s) {
 }
 
 struct DecWork {
-  float* X;
-  float* H;
-  float* dY;
-  float* dZ;
   float* part;    // per-workgroup parameter-gradient partials (chunk-major, see part_index)
   float* dcpart;  // [nblk_m][n_views][3], one row per backward workgroup
-  int32_t RP;     // row stride of dY
   int32_t nblk_w, nblk_m;
 };
 
@@ -83,14 +78,12 @@ struct DecWork {
 // contiguous, so the reduction of one run reads one contiguous region.
 ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
 
-constexpr int kWgradMaxWG = 256;     // persistent workgroups of the weight-gradient kernel
-int64_t wgrad_blocks(int64_t n_anchors);
-void launch_dec_wgrad_mfma(const DecodeConst& dc, const HeadTable& ht, int view, const DecWork& w, hipStream_t s);
-constexpr int kBwdTileAnchors = 64;  // anchors per workgroup of the MFMA decoder backward (4 waves x 16)
+int64_t dec_bwd_fused_blocks(int64_t n_anchors);
+void launch_dec_bwd_fused(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
+                          const float* feat, const float* params, const asgs_gaussians& dg, int view,
+                          const DecWork& w, float* d_xyz, float* d_feat, bool want_params, hipStream_t s);
 
-void launch_dec_bwd_tile(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
-                         const float* feat, const float* params, const asgs_gaussians& dg, int view,
-                         const DecWork& w, float* d_xyz, float* d_feat, hipStream_t s);
+
 void launch_decode_mfma(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                         const float* feat, const float* off, const float* params, const asgs_gaussians& out,
                         hipStream_t s);
