@@ -249,7 +249,9 @@ int asgs_decode_backward(const asgs_decoder* d, const float* anchor_xyz, const f
  * width x height; a group whose target is NULL contributes nothing and its
  * gradient plane (if not NULL) is zeroed; NULL gradient planes are not
  * written. loss (NULL or device [n_views]) needs work of
- * asgs_l1_loss_work_size bytes; without loss, work may be NULL.
+ * asgs_l1_loss_work_size bytes; without loss, work may be NULL. Every map,
+ * target, gradient and weight pointer must be 16-byte aligned (ASGS_E_INVALID
+ * otherwise). The loss is a fixed-order sum (deterministic run to run).
  * ------------------------------------------------------------------------- */
 typedef struct asgs_l1_targets {
   const float* rgb;     /* [n_views][3][H][W] or NULL */

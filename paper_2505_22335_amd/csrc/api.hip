@@ -579,6 +579,8 @@ int asgs_l1_loss(int32_t n_views, int32_t width, int32_t height, int32_t n_feat,
       if (ptr && !aligned16(ptr)) return fail(ASGS_E_INVALID, "l1_loss: pointer not 16-byte aligned");
     if (!isfinite(targets->scale[q])) return fail(ASGS_E_INVALID, "l1_loss: scale not finite");
   }
+  if (targets->weight && !aligned16(targets->weight))
+    return fail(ASGS_E_INVALID, "l1_loss: weight pointer not 16-byte aligned");
   if (loss && (!work || work_bytes < (size_t)n_views * kL1Blocks * sizeof(float)))
     return fail(ASGS_E_WORKSPACE, "l1_loss: loss needs %zu bytes of work", (size_t)n_views * kL1Blocks * sizeof(float));
   const int64_t HW = (int64_t)width * height;

@@ -25,6 +25,47 @@ ASGS_DEV int find_view(const ViewDev* views, int n_views, int tile) {
   return v;
 }
 
+// Pixel of thread t: wave w covers the 8x8 quarter (w & 1, w >> 1) of the
+// tile, lane l the pixel (l & 7, l >> 3) inside it. Square quarters keep the
+// per-wave culling below tight.
+ASGS_DEV int tile_lx(int t) { return ((t >> 6) & 1) * 8 + (t & 7); }
+ASGS_DEV int tile_ly(int t) { return ((t >> 7) & 1) * 8 + ((t >> 3) & 7); }
+
+// Which of the tile's four 8x8 quarters (bit w) hold a pixel centre that can
+// pass the alpha test power >= ln(alpha_min / o) of an entry: a conservative
+// test against the bounding box of the ellipse d^T Q d <= 2 L, Q = [[A, B],
+// [B, C]], L = -ln(alpha_min / o), whose half extents are sqrt(2 L C / det Q)
+// and sqrt(2 L A / det Q). The box is computed in FP64 from the stored FP32
+// conic and widened by a relative 1e-3 + 2e-6 cond(Q) (covering the FP32
+// rounding of the per-pixel power, whose error grows with the condition
+// number) plus 0.01 px; entries too ill-conditioned for that bound are kept
+// everywhere. Entries whose threshold no pixel can reach (o < alpha_min, or
+// a NaN threshold) are dropped everywhere.
+ASGS_DEV uint32_t quarter_mask(const float4& g0, const float4& g1, int x0, int y0) {
+  const float lnthr = g1.z;
+  if (!(lnthr <= 0.f)) return 0u;
+  const double a = g0.z, b = g0.w, c = g1.x;
+  const double det = a * c - b * b;
+  if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0)) return 0xFu;
+  const double half_tr = 0.5 * (a + c);
+  const double disc = sqrt(0.25 * (a - c) * (a - c) + b * b);
+  const double lmax = half_tr + disc;
+  const double cond = lmax * lmax / det;  // lmax / lmin
+  const double rel = 1e-3 + 2e-6 * cond;
+  if (!(rel < 0.25)) return 0xFu;
+  const double L2 = -2.0 * (double)lnthr;
+  const double hx = sqrt(L2 * c / det) * (1.0 + rel) + 0.01;
+  const double hy = sqrt(L2 * a / det) * (1.0 + rel) + 0.01;
+  const double u = g0.x, v = g0.y;
+  uint32_t m = 0u;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const double sx = x0 + 8 * (w & 1), sy = y0 + 8 * (w >> 1);
+    if (u + hx >= sx && u - hx <= sx + 7.0 && v + hy >= sy && v - hy <= sy + 7.0) m |= 1u << w;
+  }
+  return m;
+}
+
 template <int NF>
 __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const ViewDev* __restrict__ views,
                                                         char* ctx, CtxLayout L, asgs_images out) {
@@ -36,8 +77,11 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   const int lt = tile - V.tile_base;
   const int ty = lt / V.TX, tx = lt - ty * V.TX;
   const int t = threadIdx.x;
-  const int px = tx * kTile + (t & (kTile - 1));
-  const int py = ty * kTile + (t / kTile);
+  const int lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int x0 = tx * kTile, y0 = ty * kTile;
+  const int px = x0 + tile_lx(t);
+  const int py = y0 + tile_ly(t);
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
@@ -47,6 +91,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
 
   __shared__ float4 sg[kTilePix * 2];
   __shared__ float4 sc[kTilePix * CS4];
+  __shared__ uint8_t smask[kTilePix];
 
   float T = 1.f;
   float acc[CS];
@@ -60,25 +105,28 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
     const uint32_t p = base + t;
     if (p < rg.y) {
       const uint32_t gid = pairgid[p];
-      sg[2 * t] = geom[2 * (size_t)gid];
-      sg[2 * t + 1] = geom[2 * (size_t)gid + 1];
+      const float4 g0 = geom[2 * (size_t)gid];
+      const float4 g1 = geom[2 * (size_t)gid + 1];
+      sg[2 * t] = g0;
+      sg[2 * t + 1] = g1;
 #pragma unroll
       for (int c = 0; c < CS4; ++c) sc[t * CS4 + c] = chan4[(size_t)gid * CS4 + c];
+      smask[t] = (uint8_t)quarter_mask(g0, g1, x0, y0);
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
-    // Every lane walks the whole batch with predicated updates; the channel
-    // accumulation is skipped only when no lane of the wave takes the entry
-    // (a wave-uniform branch), and the wave leaves once all its pixels stop.
-    if (__ballot(!done)) {
-      float4 n0 = sg[0], n1 = sg[1];
-      for (int j = 0; j < cnt; ++j) {
-        // geometry of the next entry is read before this one is evaluated
-        const float4 g0 = n0;
-        const float4 g1 = n1;
-        const int jn = j + 1 < cnt ? j + 1 : j;
-        n0 = sg[2 * jn];
-        n1 = sg[2 * jn + 1];
+    // Each wave visits only the entries that can reach one of its pixels, in
+    // list order; within those, every lane runs predicated and the channel
+    // accumulation is skipped when no lane takes the entry.
+    bool wave_done = __ballot(!done) == 0;
+    for (int c64 = 0; c64 < cnt && !wave_done; c64 += 64) {
+      const bool mine = c64 + lane < cnt && ((smask[c64 + lane] >> wv) & 1u);
+      uint64_t bits = __ballot(mine);
+      while (bits) {
+        const int j = c64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        const float4 g0 = sg[2 * j];
+        const float4 g1 = sg[2 * j + 1];
         float dx, dy;
         const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
         // alpha >= alpha_min  <=>  power >= ln(alpha_min / o) (record slot 6)
@@ -88,7 +136,6 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
         const float Tn = T * (1.f - alpha);
         const bool stop = take && Tn < tmin;
         const bool use = take && !stop;
-        done = done || stop;
         if (__ballot(use)) {
           const float w = use ? alpha * T : 0.f;
 #pragma unroll
@@ -102,7 +149,13 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
           T = use ? Tn : T;
           last = use ? base - rg.x + (uint32_t)j + 1u : last;
         }
-        if (__ballot(stop) && __ballot(!done) == 0) break;
+        if (__ballot(stop)) {
+          done = done || stop;
+          if (__ballot(!done) == 0) {
+            wave_done = true;
+            break;
+          }
+        }
       }
     }
   }
@@ -160,8 +213,8 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int x0 = tx * kTile, y0 = ty * kTile;
-  const int px = x0 + (t & (kTile - 1));
-  const int py = y0 + (t / kTile);
+  const int px = x0 + tile_lx(t);
+  const int py = y0 + tile_ly(t);
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
@@ -207,8 +260,8 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   float bG0[16], bG1[16], bM[16];
 #pragma unroll
   for (int s4 = 0; s4 < 16; ++s4) {
-    const int q = 64 * wv + 4 * s4 + (lane >> 4);  // tile-local pixel
-    const int lx = q & 15, ly = q >> 4;
+    const int q = 64 * wv + 4 * s4 + (lane >> 4);  // pixel of thread q
+    const int lx = tile_lx(q), ly = tile_ly(q);
     const int gx = x0 + lx, gy = y0 + ly;
     const bool in = gx < V.W && gy < V.H;
     const size_t pix = (size_t)gy * V.W + gx;

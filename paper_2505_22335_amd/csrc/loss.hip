@@ -15,34 +15,96 @@ constexpr int kLossThreads = 256;
 
 ASGS_DEV float sgn(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
 
+template <int VW> struct Vec;
+template <> struct Vec<1> { using T = float; };
+template <> struct Vec<4> { using T = float4; };
+
+ASGS_DEV float lane(float v, int) { return v; }
+ASGS_DEV float lane(float4 v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+ASGS_DEV void set_lane(float& v, int, float f) { v = f; }
+ASGS_DEV void set_lane(float4& v, int i, float f) {
+  if (i == 0) v.x = f; else if (i == 1) v.y = f; else if (i == 2) v.z = f; else v.w = f;
+}
+
+// One channel group of VW consecutive pixels starting at p: every load of the
+// group is issued before any store, so the loads are in flight together.
+template <int C, int VW>
+ASGS_DEV float group_l1(const float* __restrict__ x, const float* __restrict__ t, float* __restrict__ g,
+                        int64_t HW, int64_t p, const typename Vec<VW>::T& w, float s) {
+  using V = typename Vec<VW>::T;
+  V xv[C], tv[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    xv[c] = *reinterpret_cast<const V*>(x + c * HW + p);
+    tv[c] = *reinterpret_cast<const V*>(t + c * HW + p);
+  }
+  float l[VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) l[i] = 0.f;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    V gv;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) {
+      const float d = lane(xv[c], i) - lane(tv[c], i);
+      l[i] += fabsf(d);
+      set_lane(gv, i, lane(w, i) * sgn(d) * s);
+    }
+    if (g) *reinterpret_cast<V*>(g + c * HW + p) = gv;
+  }
+  float acc = 0.f;
+#pragma unroll
+  for (int i = 0; i < VW; ++i) acc += lane(w, i) * l[i] * s;
+  return acc;
+}
+
+// Zero gradient for a group without targets.
+template <int C, int VW>
+ASGS_DEV void group_zero(float* __restrict__ g, int64_t HW, int64_t p) {
+  using V = typename Vec<VW>::T;
+  V z;
+#pragma unroll
+  for (int i = 0; i < VW; ++i) set_lane(z, i, 0.f);
+#pragma unroll
+  for (int c = 0; c < C; ++c) *reinterpret_cast<V*>(g + c * HW + p) = z;
+}
+
+template <int C, int VW>
+ASGS_DEV float group(const L1Args& a, const L1Views& tv, int q, int v, int64_t p, const typename Vec<VW>::T& w) {
+  if (!a.x[q]) return 0.f;
+  const int64_t off = (int64_t)v * C * a.HW;
+  float* g = a.g[q] ? a.g[q] + off : nullptr;
+  const float* t = tv.t[q][v];
+  if (!t) {
+    if (g) group_zero<C, VW>(g, a.HW, p);
+    return 0.f;
+  }
+  return group_l1<C, VW>(a.x[q] + off, t, g, a.HW, p, w, a.s[q]);
+}
+
+// Each thread takes VW consecutive pixels per step (VW = 4 when the plane
+// size is a multiple of 4, so every plane start is 16-byte aligned).
+template <int VW>
 __global__ void __launch_bounds__(kLossThreads) k_l1_loss(L1Args a, L1Views tv) {
+  using V = typename Vec<VW>::T;
   __shared__ float red[kLossThreads / 64];
   const int v = blockIdx.y;
   const int64_t HW = a.HW;
   const float* w = tv.w[v];
-  const int nc[4] = {3, 1, a.nf, 1};
   float acc = 0.f;
-  for (int64_t p = (int64_t)blockIdx.x * kLossThreads + threadIdx.x; p < HW; p += (int64_t)gridDim.x * kLossThreads) {
-    const float wp = w ? w[p] : 1.f;
+  for (int64_t p = ((int64_t)blockIdx.x * kLossThreads + threadIdx.x) * VW; p < HW;
+       p += (int64_t)gridDim.x * kLossThreads * VW) {
+    V wv;
+    if (w) {
+      wv = *reinterpret_cast<const V*>(w + p);
+    } else {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int C = nc[g];
-      if (C == 0 || !a.x[g]) continue;
-      const float* x = a.x[g] + (int64_t)v * C * HW;
-      const float* t = tv.t[g][v];
-      float* gr = a.g[g] ? a.g[g] + (int64_t)v * C * HW : nullptr;
-      float l = 0.f;
-      for (int c = 0; c < C; ++c) {
-        float gv = 0.f;
-        if (t) {
-          const float d = x[c * HW + p] - t[c * HW + p];
-          gv = wp * sgn(d) * a.s[g];
-          l += fabsf(d);
-        }
-        if (gr) gr[c * HW + p] = gv;
-      }
-      acc += wp * l * a.s[g];
+      for (int i = 0; i < VW; ++i) set_lane(wv, i, 1.f);
     }
+    acc += group<3, VW>(a, tv, 0, v, p, wv);
+    acc += group<1, VW>(a, tv, 1, v, p, wv);
+    if (a.nf == 16) acc += group<16, VW>(a, tv, 2, v, p, wv);
+    acc += group<1, VW>(a, tv, 3, v, p, wv);
   }
   if (!a.partial) return;
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -66,7 +128,10 @@ __global__ void k_l1_loss_sum(const float* partial, float* loss, int n_views) {
 }  // namespace
 
 void launch_l1_loss(const L1Args& a, const L1Views& tv, hipStream_t s) {
-  hipLaunchKernelGGL(k_l1_loss, dim3(kL1Blocks, a.n_views), dim3(kLossThreads), 0, s, a, tv);
+  if (a.HW % 4 == 0)
+    hipLaunchKernelGGL(k_l1_loss<4>, dim3(kL1Blocks, a.n_views), dim3(kLossThreads), 0, s, a, tv);
+  else
+    hipLaunchKernelGGL(k_l1_loss<1>, dim3(kL1Blocks, a.n_views), dim3(kLossThreads), 0, s, a, tv);
   if (a.partial && a.loss)
     hipLaunchKernelGGL(k_l1_loss_sum, dim3(1), dim3(64), 0, s, a.partial, a.loss, a.n_views);
 }
