@@ -193,12 +193,15 @@ ASGS_DEV f4v mfma4(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_1
 // per-pixel coefficients (w, dpow) with fixed per-pixel features: the
 // channel gradients G_p and the moments (1, lx, ly, lx^2, lx ly, ly^2) of the
 // tile-local pixel coordinates, from which the conic and position gradients
-// follow in closed form. Each wave writes its 64 pixels' coefficients for 16
-// entries to LDS and contracts them on the matrix cores (16x16x4 FP32 MFMA,
-// K = pixels); the four waves' 16x26 partials are summed in LDS and written
-// once to each entry's gradient slot.
+// follow in closed form. The list is staged in rounds of 32 entries from the
+// back. Each wave takes only the round's entries that one of its pixels uses
+// (the quarter test of the forward, then a ballot), writes its pixels'
+// coefficients for batches of up to 16 such entries to LDS and contracts them
+// on the matrix cores (16x16x4 FP32 MFMA, K = pixels) into per-wave partial
+// rows; the four waves' rows are summed in a fixed order and written once to
+// each entry's gradient slot.
 template <int NF>
-__global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const ViewDev* __restrict__ views,
+__global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3))) k_blend_bwd(RenderConst rc, const ViewDev* __restrict__ views,
                                                         char* ctx, CtxLayout L, asgs_images dout) {
   constexpr int CS = 4 + NF;
   constexpr int CS4 = CS / 4;
@@ -211,7 +214,8 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   const int lt = tile - V.tile_base;
   const int ty = lt / V.TX, tx = lt - ty * V.TX;
   const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
+  const int lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int x0 = tx * kTile, y0 = ty * kTile;
   const int px = x0 + tile_lx(t);
   const int py = y0 + tile_ly(t);
@@ -226,13 +230,14 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
   float* gslot = ctx_ptr<float>(ctx, L.gslot);
 
   constexpr int kRecF4 = 2 + CS4;  // float4 per list entry: geometry (2) + channels
-  constexpr int kRound = 32;       // list entries staged per round (two MFMA batches)
+  constexpr int kRound = 32;       // list entries staged per round (one per lane of half a wave)
   constexpr int kPer = (kRound * kRecF4 + kTilePix - 1) / kTilePix;
   constexpr int PS = GS;           // row of a partial-sum entry
   __shared__ float4 srec[kRound * kRecF4];
   __shared__ float cw[NW][64 * CP];     // w of (pixel, entry), per wave
   __shared__ float cp[NW][64 * CP];     // dL/dpower of (pixel, entry), per wave
-  __shared__ float part[2][NW][kBwdBatch][PS];
+  __shared__ float part[NW][kRound][PS];  // per-wave partial rows of the round's entries
+  __shared__ int sent[NW][kBwdBatch];     // round entry of each batch position
   __shared__ uint32_t smax;
 
   const size_t HW = (size_t)V.W * V.H;
@@ -313,10 +318,43 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
       }
     }
   };
+  // Contract the wave's nb batched entries over its 64 pixels on the matrix
+  // cores and store the rows of the partial sums under their round entries.
+  auto flush = [&](int nb) {
+    // the coefficients are read back by other lanes of this wave only
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    f4v c1 = {0.f, 0.f, 0.f, 0.f}, c2 = c1, c3 = c1;
+    const float* acw = &cw[wv][0];
+    const float* acp = &cp[wv][0];
+#pragma unroll
+    for (int s4 = 0; s4 < 16; ++s4) {
+      const int q = 4 * s4 + (lane >> 4);
+      const float aw = acw[q * CP + fcol];
+      const float ap = acp[q * CP + fcol];
+      c1 = mfma4(aw, bG0[s4], c1);
+      if (CS > 16) c2 = mfma4(aw, bG1[s4], c2);
+      c3 = mfma4(ap, bM[s4], c3);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = 4 * (lane >> 4) + r;
+      if (pos < nb) {
+        float* row = part[wv][sent[wv][pos]];
+        if (fcol < CS) row[6 + fcol] = c1[r];
+        if (CS > 16 && fcol < CS - 16) row[6 + 16 + fcol] = c2[r];
+        if (fcol < 6) row[fcol] = c3[r];
+      }
+    }
+    // the next batch overwrites the coefficients and the entry table
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
   int rhi = (int)nproc;
   int rlo = rhi - kRound > 0 ? rhi - kRound : 0;
   if (rhi > 0) fetch(rlo, rhi - rlo);
-  int pbuf = 0;
   while (rhi > 0) {
     __syncthreads();  // every reader of the previous round is done
 #pragma unroll
@@ -324,101 +362,83 @@ __global__ void __launch_bounds__(kTilePix) k_blend_bwd(RenderConst rc, const Vi
       const int e = t + k * kTilePix;
       if (e / kRecF4 < rhi - rlo) srec[e] = stage[k];
     }
+    for (int q = lane; q < kRound * PS; q += 64) (&part[wv][0][0])[q] = 0.f;
     __syncthreads();
+    const int cnt = rhi - rlo;
     const int nrhi = rlo, nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
     if (nrhi > 0) fetch(nrlo, nrhi - nrlo);
-    for (int hi = rhi; hi > rlo; hi -= kBwdBatch) {
-      const int lo = hi - kBwdBatch > rlo ? hi - kBwdBatch : rlo;
-      const int cnt = hi - lo;
-      const float4* rec = &srec[(lo - rlo) * kRecF4];
-      for (int jj = kBwdBatch - 1; jj >= 0; --jj) {
-        // predicated like the forward: entries past cnt compute garbage that
-        // the selects discard
-        const float4 g0 = rec[jj * kRecF4];
-        const float4 g1 = rec[jj * kRecF4 + 1];
-        float wgt = 0.f, dpow = 0.f;
-        // same alpha threshold as the forward
-        float dx, dy;
-        const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
-        const bool use = jj < cnt && (uint32_t)(lo + jj) < last && power <= 0.f && power >= g1.z;
-        if (__ballot(use)) {
-          const float raw = g1.y * __expf(power);
-          const float alpha = fminf(amax, raw);
-          const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
-          const float Tk = T * ioma;
-          float dotg = 0.f;
+    // entries of the round that can reach a pixel of this wave's quarter
+    uint32_t mine = 0u;
+    if (lane < cnt) mine = (quarter_mask(srec[lane * kRecF4], srec[lane * kRecF4 + 1], x0, y0) >> wv) & 1u;
+    uint64_t bits = __ballot(mine);
+    int nb = 0;
+    // back to front over this wave's entries; entries no pixel of the wave
+    // uses are left out of the batches (their partial rows stay zero)
+    while (bits) {
+      const int j = 63 - __builtin_clzll(bits);
+      bits &= ~(1ull << j);
+      const float4 g0 = srec[j * kRecF4];
+      const float4 g1 = srec[j * kRecF4 + 1];
+      float dx, dy;
+      const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
+      // same alpha threshold as the forward
+      const bool use = (uint32_t)(rlo + j) < last && power <= 0.f && power >= g1.z;
+      if (!__ballot(use)) continue;
+      float wgt = 0.f, dpow = 0.f;
+      const float raw = g1.y * __expf(power);
+      const float alpha = fminf(amax, raw);
+      const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
+      const float Tk = T * ioma;
+      float dotg = 0.f;
 #pragma unroll
-          for (int c4 = 0; c4 < CS4; ++c4) {
-            const float4 v = rec[jj * kRecF4 + 2 + c4];
-            dotg = fmaf(G[4 * c4 + 0], v.x, dotg);
-            dotg = fmaf(G[4 * c4 + 1], v.y, dotg);
-            dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
-            dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
-          }
-          const float w_ = alpha * Tk;
-          const float dalpha = Tk * dotg - (sacc + GT * Tf) * ioma;
-          if (use) {
-            T = Tk;
-            wgt = w_;
-            sacc = fmaf(w_, dotg, sacc);
-            dpow = raw < amax ? dalpha * alpha : 0.f;
-          }
-        }
-        mycw[jj] = wgt;
-        mycp[jj] = dpow;
+      for (int c4 = 0; c4 < CS4; ++c4) {
+        const float4 v = srec[j * kRecF4 + 2 + c4];
+        dotg = fmaf(G[4 * c4 + 0], v.x, dotg);
+        dotg = fmaf(G[4 * c4 + 1], v.y, dotg);
+        dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
+        dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
       }
-      // the coefficients are read back by other lanes of this wave only
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // contract this wave's 64 pixels: C[entry][feature]
-      f4v c1 = {0.f, 0.f, 0.f, 0.f}, c2 = c1, c3 = c1;
-      const float* acw = &cw[wv][0];
-      const float* acp = &cp[wv][0];
+      const float w_ = alpha * Tk;
+      const float dalpha = Tk * dotg - (sacc + GT * Tf) * ioma;
+      if (use) {
+        T = Tk;
+        wgt = w_;
+        sacc = fmaf(w_, dotg, sacc);
+        dpow = raw < amax ? dalpha * alpha : 0.f;
+      }
+      mycw[nb] = wgt;
+      mycp[nb] = dpow;
+      if (lane == 0) sent[wv][nb] = j;
+      if (++nb == kBwdBatch) {
+        flush(nb);
+        nb = 0;
+      }
+    }
+    if (nb > 0) flush(nb);
+    __syncthreads();
+    // partial sums of the four waves -> one gradient slot per entry
+    for (int q = t; q < cnt * GS; q += kTilePix) {
+      const int e = q / GS, c = q - e * GS;
+      float val;
+      if (c >= 6) {
+        val = (part[0][e][c] + part[1][e][c]) + (part[2][e][c] + part[3][e][c]);
+      } else {
+        float M[6];
 #pragma unroll
-      for (int s4 = 0; s4 < 16; ++s4) {
-        const int q = 4 * s4 + (lane >> 4);
-        const float aw = acw[q * CP + fcol];
-        const float ap = acp[q * CP + fcol];
-        c1 = mfma4(aw, bG0[s4], c1);
-        if (CS > 16) c2 = mfma4(aw, bG1[s4], c2);
-        c3 = mfma4(ap, bM[s4], c3);
+        for (int m = 0; m < 6; ++m) M[m] = (part[0][e][m] + part[1][e][m]) + (part[2][e][m] + part[3][e][m]);
+        const float4 g0 = srec[e * kRecF4];
+        const float4 g1 = srec[e * kRecF4 + 1];
+        const float uu = g0.x - (float)x0, vv = g0.y - (float)y0;  // tile-local centre
+        const float Sdx = uu * M[0] - M[1];
+        const float Sdy = vv * M[0] - M[2];
+        if (c == 0) val = -(g0.z * Sdx + g0.w * Sdy);
+        else if (c == 1) val = -(g0.w * Sdx + g1.x * Sdy);
+        else if (c == 2) val = -0.5f * (uu * uu * M[0] - 2.f * uu * M[1] + M[3]);
+        else if (c == 3) val = -(uu * vv * M[0] - uu * M[2] - vv * M[1] + M[4]);
+        else if (c == 4) val = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
+        else val = M[0] / g1.y;
       }
-      float (*pt)[kBwdBatch][PS] = part[pbuf];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = 4 * (lane >> 4) + r;
-        if (fcol < CS) pt[wv][e][6 + fcol] = c1[r];
-        if (CS > 16 && fcol < CS - 16) pt[wv][e][6 + 16 + fcol] = c2[r];
-        if (fcol < 6) pt[wv][e][fcol] = c3[r];
-      }
-      __syncthreads();
-      // partial sums of the four waves -> one gradient slot per entry; the
-      // other buffer is written by the next batch meanwhile
-      for (int q = t; q < cnt * GS; q += kTilePix) {
-        const int e = q / GS, c = q - e * GS;
-        float val;
-        if (c >= 6) {
-          val = (pt[0][e][c] + pt[1][e][c]) + (pt[2][e][c] + pt[3][e][c]);
-        } else {
-          float M[6];
-#pragma unroll
-          for (int m = 0; m < 6; ++m) M[m] = (pt[0][e][m] + pt[1][e][m]) + (pt[2][e][m] + pt[3][e][m]);
-          const float4 g0 = rec[e * kRecF4];
-          const float4 g1 = rec[e * kRecF4 + 1];
-          const float uu = g0.x - (float)x0, vv = g0.y - (float)y0;  // tile-local centre
-          const float Sdx = uu * M[0] - M[1];
-          const float Sdy = vv * M[0] - M[2];
-          if (c == 0) val = -(g0.z * Sdx + g0.w * Sdy);
-          else if (c == 1) val = -(g0.w * Sdx + g1.x * Sdy);
-          else if (c == 2) val = -0.5f * (uu * uu * M[0] - 2.f * uu * M[1] + M[3]);
-          else if (c == 3) val = -(uu * vv * M[0] - uu * M[2] - vv * M[1] + M[4]);
-          else if (c == 4) val = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
-          else val = M[0] / g1.y;
-        }
-        gslot[(size_t)pslot[rg.x + lo + e] * GS + c] = val;
-      }
-      pbuf ^= 1;
+      gslot[(size_t)pslot[rg.x + rlo + e] * GS + c] = val;
     }
     rhi = nrhi;
     rlo = nrlo;
