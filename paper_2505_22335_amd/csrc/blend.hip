@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
                                                         char* ctx, CtxLayout L, asgs_images out) {
   constexpr int CS = 4 + NF;
   constexpr int CS4 = CS / 4;
-  const int tile = blockIdx.x;
+  const int tile = (int)ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];  // longest lists first
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
   const int lt = tile - V.tile_base;
@@ -88,10 +88,12 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
+  uint8_t* pmask = ctx_ptr<uint8_t>(ctx, L.pmask);
 
   __shared__ float4 sg[kTilePix * 2];
   __shared__ float4 sc[kTilePix * CS4];
   __shared__ uint8_t smask[kTilePix];
+  __shared__ uint16_t swl[kTilePix / 64][kTilePix];
 
   float T = 1.f;
   float acc[CS];
@@ -111,52 +113,70 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
       sg[2 * t + 1] = g1;
 #pragma unroll
       for (int c = 0; c < CS4; ++c) sc[t * CS4 + c] = chan4[(size_t)gid * CS4 + c];
-      smask[t] = (uint8_t)quarter_mask(g0, g1, x0, y0);
+      const uint8_t m = (uint8_t)quarter_mask(g0, g1, x0, y0);
+      smask[t] = m;
+      pmask[p] = m;  // reused by the backward
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
-    // Each wave visits only the entries that can reach one of its pixels, in
-    // list order; within those, every lane runs predicated and the channel
-    // accumulation is skipped when no lane takes the entry.
-    bool wave_done = __ballot(!done) == 0;
-    for (int c64 = 0; c64 < cnt && !wave_done; c64 += 64) {
+    if (__ballot(!done) == 0) continue;
+    // This wave's entries of the round (those that can reach one of its
+    // pixels), in list order, compacted into swl.
+    int n = 0;
+    for (int c64 = 0; c64 < cnt; c64 += 64) {
       const bool mine = c64 + lane < cnt && ((smask[c64 + lane] >> wv) & 1u);
-      uint64_t bits = __ballot(mine);
-      while (bits) {
-        const int j = c64 + __builtin_ctzll(bits);
-        bits &= bits - 1;
-        const float4 g0 = sg[2 * j];
-        const float4 g1 = sg[2 * j + 1];
-        float dx, dy;
-        const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
-        // alpha >= alpha_min  <=>  power >= ln(alpha_min / o) (record slot 6)
-        const bool take = !done && power <= 0.f && power >= g1.z;
-        if (!__ballot(take)) continue;
+      const uint64_t bits = __ballot(mine);
+      if (mine) swl[wv][n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u))] = (uint16_t)(c64 + lane);
+      n += __builtin_popcountll(bits);
+    }
+    if (n == 0) continue;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Software pipeline over the list: the next entry's geometry is read at
+    // the start of an entry and its channels after the current ones have
+    // been accumulated, so both land while other work runs. Every lane runs
+    // predicated; the accumulation is skipped when no lane takes the entry.
+    int j = __builtin_amdgcn_readfirstlane(swl[wv][0]);
+    int jn = __builtin_amdgcn_readfirstlane(swl[wv][n > 1 ? 1 : 0]);
+    float4 g0 = sg[2 * j], g1 = sg[2 * j + 1];
+    float4 ch[CS4];
+#pragma unroll
+    for (int c4 = 0; c4 < CS4; ++c4) ch[c4] = sc[j * CS4 + c4];
+    for (int i = 0; i < n; ++i) {
+      const int jv = swl[wv][i + 2 < n ? i + 2 : n - 1];
+      const float4 n0 = sg[2 * jn], n1 = sg[2 * jn + 1];
+      float dx, dy;
+      const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
+      // alpha >= alpha_min  <=>  power >= ln(alpha_min / o) (record slot 6)
+      const bool take = !done && power <= 0.f && power >= g1.z;
+      if (__ballot(take)) {
         const float alpha = fminf(amax, g1.y * __expf(power));
         const float Tn = T * (1.f - alpha);
         const bool stop = take && Tn < tmin;
-        const bool use = take && !stop;
-        if (__ballot(use)) {
-          const float w = use ? alpha * T : 0.f;
+        if (take && !stop) {
+          const float w = alpha * T;
 #pragma unroll
           for (int c4 = 0; c4 < CS4; ++c4) {
-            const float4 v = sc[j * CS4 + c4];
-            acc[4 * c4 + 0] = fmaf(w, v.x, acc[4 * c4 + 0]);
-            acc[4 * c4 + 1] = fmaf(w, v.y, acc[4 * c4 + 1]);
-            acc[4 * c4 + 2] = fmaf(w, v.z, acc[4 * c4 + 2]);
-            acc[4 * c4 + 3] = fmaf(w, v.w, acc[4 * c4 + 3]);
+            acc[4 * c4 + 0] = fmaf(w, ch[c4].x, acc[4 * c4 + 0]);
+            acc[4 * c4 + 1] = fmaf(w, ch[c4].y, acc[4 * c4 + 1]);
+            acc[4 * c4 + 2] = fmaf(w, ch[c4].z, acc[4 * c4 + 2]);
+            acc[4 * c4 + 3] = fmaf(w, ch[c4].w, acc[4 * c4 + 3]);
           }
-          T = use ? Tn : T;
-          last = use ? base - rg.x + (uint32_t)j + 1u : last;
+          T = Tn;
+          last = base - rg.x + (uint32_t)j + 1u;
         }
         if (__ballot(stop)) {
           done = done || stop;
-          if (__ballot(!done) == 0) {
-            wave_done = true;
-            break;
-          }
+          if (__ballot(!done) == 0) break;
         }
       }
+#pragma unroll
+      for (int c4 = 0; c4 < CS4; ++c4) ch[c4] = sc[jn * CS4 + c4];
+      j = jn;
+      g0 = n0;
+      g1 = n1;
+      jn = __builtin_amdgcn_readfirstlane(jv);
     }
   }
   if (!inside) return;
@@ -208,7 +228,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
   constexpr int CP = 17;          // padded row of 16 coefficients
-  const int tile = blockIdx.x;
+  const int tile = (int)ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];  // longest lists first
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
   const int lt = tile - V.tile_base;
@@ -227,6 +247,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pval_fin);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
+  const uint8_t* pmask = ctx_ptr<const uint8_t>(ctx, L.pmask);
   float* gslot = ctx_ptr<float>(ctx, L.gslot);
 
   constexpr int kRecF4 = 2 + CS4;  // float4 per list entry: geometry (2) + channels
@@ -238,6 +259,8 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   __shared__ float cp[NW][64 * CP];     // dL/dpower of (pixel, entry), per wave
   __shared__ float part[NW][kRound][PS];  // per-wave partial rows of the round's entries
   __shared__ int sent[NW][kBwdBatch];     // round entry of each batch position
+  __shared__ uint32_t sslot[kRound];      // gradient slot of each round entry
+  __shared__ uint8_t smk[kRound];         // quarter mask of each round entry (from the forward)
   __shared__ uint32_t smax;
 
   const size_t HW = (size_t)V.W * V.H;
@@ -307,6 +330,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   // back; the global loads of the next round are issued before the current
   // round is processed and land in LDS at the start of the next round.
   float4 stage[kPer];
+  uint32_t stage_slot = 0u, stage_mask = 0u;
   auto fetch = [&](int lo_r, int cnt_r) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -316,6 +340,10 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
         const uint32_t gid = pairgid[rg.x + lo_r + ent];
         stage[k] = f < 2 ? geom[2 * (size_t)gid + f] : chan4[(size_t)gid * CS4 + (f - 2)];
       }
+    }
+    if (t < cnt_r) {
+      stage_slot = pslot[rg.x + lo_r + t];
+      stage_mask = pmask[rg.x + lo_r + t];
     }
   };
   // Contract the wave's nb batched entries over its 64 pixels on the matrix
@@ -362,14 +390,17 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
       const int e = t + k * kTilePix;
       if (e / kRecF4 < rhi - rlo) srec[e] = stage[k];
     }
+    if (t < rhi - rlo) {
+      sslot[t] = stage_slot;
+      smk[t] = (uint8_t)stage_mask;
+    }
     for (int q = lane; q < kRound * PS; q += 64) (&part[wv][0][0])[q] = 0.f;
     __syncthreads();
     const int cnt = rhi - rlo;
     const int nrhi = rlo, nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
     if (nrhi > 0) fetch(nrlo, nrhi - nrlo);
     // entries of the round that can reach a pixel of this wave's quarter
-    uint32_t mine = 0u;
-    if (lane < cnt) mine = (quarter_mask(srec[lane * kRecF4], srec[lane * kRecF4 + 1], x0, y0) >> wv) & 1u;
+    const bool mine = lane < cnt && ((smk[lane] >> wv) & 1u);
     uint64_t bits = __ballot(mine);
     int nb = 0;
     // back to front over this wave's entries; entries no pixel of the wave
@@ -438,7 +469,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
         else if (c == 4) val = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
         else val = M[0] / g1.y;
       }
-      gslot[(size_t)pslot[rg.x + rlo + e] * GS + c] = val;
+      gslot[(size_t)sslot[e] * GS + c] = val;
     }
     rhi = nrhi;
     rlo = nrlo;

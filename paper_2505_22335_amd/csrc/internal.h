@@ -67,7 +67,7 @@ enum Counter { kCntDepth0 = 0, kCntScan = 4, kCntTile0 = 5, kCntPose = 9 };
 // Byte layout of a render context; every array 256-byte aligned.
 struct CtxLayout {
   size_t hdr, views, geom, chan, rect, ntiles, rank, dkey0, dkeyA, dvalA, dkeyB, dvalB,
-      toff, bsum, pkeyA, pvalA, pkeyB, pvalB, dupgid, pairgid, ranges, hist, tfinal, ncontrib,
+      toff, bsum, pkeyA, pvalA, pkeyB, pvalB, dupgid, pairgid, pmask, ranges, torder, hist, tfinal, ncontrib,
       gslot, posepart, pkey_fin, pval_fin;
   size_t total;
   int64_t nv, cap;

@@ -310,6 +310,50 @@ __global__ void __launch_bounds__(256) k_ranges(RenderConst rc, char* ctx, CtxLa
   ctx_ptr<uint32_t>(ctx, L.pairgid)[i] = ctx_ptr<const uint32_t>(ctx, L.dupgid)[val[i]];
 }
 
+// Blend order of the tiles: longest list first, so that the longest-running
+// workgroups start first and short tiles fill in behind them. A counting sort
+// on the list length (lengths of 1023 and more share one bucket); the order
+// within a bucket is arbitrary, which changes no result.
+constexpr int kOrderBins = 1024;
+__global__ void __launch_bounds__(kOrderBins) k_tile_order(RenderConst rc, char* ctx, CtxLayout L) {
+  __shared__ uint32_t bins[kOrderBins];
+  __shared__ uint32_t wsum[kOrderBins / 64];
+  const int t = threadIdx.x;
+  const uint2* ranges = ctx_ptr<const uint2>(ctx, L.ranges);
+  uint32_t* order = ctx_ptr<uint32_t>(ctx, L.torder);
+  const int T = rc.total_tiles;
+  bins[t] = 0u;
+  __syncthreads();
+  for (int i = t; i < T; i += kOrderBins) {
+    const uint2 r = ranges[i];
+    const uint32_t c = r.y - r.x;
+    atomicAdd(&bins[kOrderBins - 1 - (c < kOrderBins - 1 ? c : kOrderBins - 1)], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the bins: within each wave, then over the wave sums
+  const uint32_t v = bins[t];
+  uint32_t incl = v;
+  const int lane = t & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(incl, o);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wsum[t >> 6] = incl;
+  __syncthreads();
+  uint32_t before = 0u;
+  for (int w = 0; w < (t >> 6); ++w) before += wsum[w];
+  __syncthreads();
+  bins[t] = before + incl - v;
+  __syncthreads();
+  for (int i = t; i < T; i += kOrderBins) {
+    const uint2 r = ranges[i];
+    const uint32_t c = r.y - r.x;
+    const uint32_t pos = atomicAdd(&bins[kOrderBins - 1 - (c < kOrderBins - 1 ? c : kOrderBins - 1)], 1u);
+    order[pos] = (uint32_t)i;
+  }
+}
+
 }  // namespace
 
 void launch_depth_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s) {
@@ -365,6 +409,7 @@ void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipS
   const unsigned nblk = (unsigned)((rc.cap + 255) / 256);
   hipLaunchKernelGGL(k_ranges, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, s, rc, ctx, L, L.pkey_fin,
                      L.pval_fin);
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderBins), 0, s, rc, ctx, L);
 }
 
 }  // namespace asgs
