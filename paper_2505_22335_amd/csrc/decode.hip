@@ -125,11 +125,73 @@ __global__ void __launch_bounds__(kDecThreads) k_decode_fwd(DecodeConst dc, Head
 }
 
 // ---------------------------------------------------------------------------
-// Backward, per view: one kernel on the matrix cores (decode_bwd_fused.hip)
-// recomputes the forward per 16-anchor tile and forms the anchor gradients,
-// the camera-centre partial sums and per-workgroup partials of every MLP
-// parameter gradient; the partials are then reduced in a fixed order.
+// Backward, per view: one kernel on the matrix cores (decode_bwd_heads.hip)
+// recomputes the forward per 16-anchor tile and forms dL/dX of each head
+// group and per-workgroup partials of every MLP parameter gradient; the
+// anchor gradients follow from dL/dX, then the partials are reduced in a
+// fixed order.
 // ---------------------------------------------------------------------------
+// Anchor gradients of one view from the two head groups' dL/dX: the feature
+// part goes to d_feat, the view-direction part through
+// delta = (x - c) / |x - c| to d_xyz and (negated) to the camera centre,
+// whose per-block sums feed the pose gradient.
+constexpr int kAnchorThreads = 256;
+__global__ void __launch_bounds__(kAnchorThreads) k_dec_bwd_anchor(DecodeConst dc, DecodeViews dv,
+                                                                  const float* __restrict__ xyz, DecWork w,
+                                                                  int view, int has_feat, float* d_xyz,
+                                                                  float* d_feat) {
+  __shared__ float red[3][kAnchorThreads / 64];
+  const int t = threadIdx.x;
+  const int64_t A = dc.A;
+  const int64_t a0 = (int64_t)blockIdx.x * kAnchorThreads;
+  const float* dx0 = w.dxpart;
+  const float* dx1 = w.dxpart + A * 36;
+  if (d_feat) {
+    for (int i = 0; i < 32; ++i) {
+      const int e = i * kAnchorThreads + t;
+      const int64_t a = a0 + e / 32;
+      const int c = e % 32;
+      if (a < A) {
+        const float v = dx0[a * 36 + c] + (has_feat ? dx1[a * 36 + c] : 0.f);
+        float* p = &d_feat[a * 32 + c];
+        *p = (view == 0 ? 0.f : *p) + v;
+      }
+    }
+  }
+  float dcl[3] = {0.f, 0.f, 0.f};
+  const int64_t a = a0 + t;
+  if (a < A) {
+    float gd[3], D[3];
+    for (int c = 0; c < 3; ++c) {
+      gd[c] = dx0[a * 36 + 32 + c] + (has_feat ? dx1[a * 36 + 32 + c] : 0.f);
+      D[c] = xyz[c * A + a] - dv.c[view][c];
+    }
+    const float dist = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    float del[3];
+    for (int c = 0; c < 3; ++c) del[c] = D[c] / dist;
+    const float pr = del[0] * gd[0] + del[1] * gd[1] + del[2] * gd[2];
+    for (int c = 0; c < 3; ++c) {
+      const float dD = (gd[c] - del[c] * pr) / dist;
+      if (d_xyz) {
+        float* p = &d_xyz[c * A + a];
+        *p = (view == 0 ? 0.f : *p) + dD;
+      }
+      dcl[c] = -dD;
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    float x = dcl[c];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if ((t & 63) == 0) red[c][t >> 6] = x;
+  }
+  __syncthreads();
+  if (t < 3) {
+    float sum = 0.f;
+    for (int q = 0; q < kAnchorThreads / 64; ++q) sum += red[t][q];
+    w.dcpart[((int64_t)blockIdx.x * dc.n_views + view) * 3 + t] = sum;
+  }
+}
+
 // Mean gradients summed over views: d_off = l_o dmu, d_xyz += sum_i dmu.
 __global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, float* d_off) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -149,10 +211,6 @@ __global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, 
   }
   d_xyz[c * A + a] += sx;
 }
-
-// Weight gradients of one view, accumulated into per-workgroup partials.
-// Tasks: dW2 rows x 16-column halves, dW1 units x 12-column thirds of the
-// 36-wide (padded) input, and the bias sums.
 
 // Fixed-order reduction of the workgroup partials: 64 parameters per
 // workgroup, four threads per parameter (each a strided quarter of the
@@ -231,18 +289,19 @@ DecodeViews decode_views(const ViewDev* hv, int n_views) {
 
 struct WorkSizes {
   int64_t nblk_w, nblk_m;
-  size_t part, dcpart, total;
+  size_t part, dcpart, dxpart, total;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 WorkSizes work_sizes(const DecodeConst& dc) {
   WorkSizes z;
-  z.nblk_w = dec_bwd_fused_blocks(dc.A);
-  z.nblk_m = z.nblk_w;
+  z.nblk_w = dec_bwd_heads_blocks(dc.A);
+  z.nblk_m = (dc.A + kAnchorThreads - 1) / kAnchorThreads;
   size_t o = 0;
   z.part = o; o = a256(o + (size_t)z.nblk_w * ((dc.n_params + 63) / 64 * 64) * 4);
   z.dcpart = o; o = a256(o + (size_t)z.nblk_m * dc.n_views * 3 * 4);
+  z.dxpart = o; o = a256(o + dec_bwd_dx_floats(dc.A) * 4);
   z.total = o;
   return z;
 }
@@ -295,10 +354,14 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
   DecWork w;
   w.part = reinterpret_cast<float*>(wb + z.part);
   w.dcpart = reinterpret_cast<float*>(wb + z.dcpart);
+  w.dxpart = reinterpret_cast<float*>(wb + z.dxpart);
   w.nblk_w = (int32_t)z.nblk_w;
   w.nblk_m = (int32_t)z.nblk_m;
-  for (int view = 0; view < dc.n_views; ++view)
-    launch_dec_bwd_fused(dc, ht, dv, xyz, feat, params, dg, view, w, d_xyz, d_feat, d_params != nullptr, s);
+  for (int view = 0; view < dc.n_views; ++view) {
+    launch_dec_bwd_heads(dc, ht, dv, xyz, feat, params, dg, view, w, d_params != nullptr, s);
+    hipLaunchKernelGGL(k_dec_bwd_anchor, dim3((unsigned)z.nblk_m), dim3(kAnchorThreads), 0, s, dc, dv, xyz, w, view,
+                       ht.m[4] > 0 ? 1 : 0, d_xyz, d_feat);
+  }
   if (d_xyz)
     hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,
                        d_off);

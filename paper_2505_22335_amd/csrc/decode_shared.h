@@ -68,7 +68,8 @@ ASGS_DEV float act_grad(int h, float y, float l_s) {
 
 struct DecWork {
   float* part;    // per-workgroup parameter-gradient partials (chunk-major, see part_index)
-  float* dcpart;  // [nblk_m][n_views][3], one row per backward workgroup
+  float* dcpart;  // [nblk_m][n_views][3], one row per anchor-gradient block
+  float* dxpart;  // [2][A][36]: dL/dX of each head group for the current view
   int32_t nblk_w, nblk_m;
 };
 
@@ -78,10 +79,11 @@ struct DecWork {
 // contiguous, so the reduction of one run reads one contiguous region.
 ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
 
-int64_t dec_bwd_fused_blocks(int64_t n_anchors);
-void launch_dec_bwd_fused(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
+int64_t dec_bwd_heads_blocks(int64_t n_anchors);
+size_t dec_bwd_dx_floats(int64_t n_anchors);
+void launch_dec_bwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                           const float* feat, const float* params, const asgs_gaussians& dg, int view,
-                          const DecWork& w, float* d_xyz, float* d_feat, bool want_params, hipStream_t s);
+                          const DecWork& w, bool want_params, hipStream_t s);
 
 
 void launch_decode_mfma(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,

@@ -97,4 +97,6 @@ def test_decoder_parameter_count():
     assert L.decode_param_count(d0) == sum(per_head(m) for m in (1, 3, 3, 4))
     with pytest.raises(L.AsgsError):
         L.decode_param_count(L.make_decoder(1000, 17, 16))
-    assert L.decode_workspace_size(d, 2) > L.decode_workspace_size(d, 1)
+    # per-view camera-centre partials: one row of 3 floats per 256 anchors and view
+    big = L.make_decoder(100_000, 10, 16)
+    assert L.decode_workspace_size(big, 2) > L.decode_workspace_size(big, 1) >= L.decode_workspace_size(d, 1)
