@@ -7,16 +7,14 @@
 // (ReLU for the first four, SoftPlus for the feature head), then the output
 // activations: sigmoid (opacity, rgb), l_s * sigmoid (scale), raw (rot, feat).
 //
-// FP32 path: a workgroup decodes 32 anchors of one view. The first layer of
-// all heads (160 hidden units) runs with one hidden unit per thread and its
-// weight row in registers, broadcasting anchor inputs from LDS; the second
-// layer runs with one output row per thread over the hidden activations held
-// in LDS; many small workgroups keep the SIMDs busy. The BF16 path runs on the
-// matrix cores (decode_mfma.hip). The backward (FP32) recomputes the forward
-// on the matrix cores, then forms dL/dH from the second-layer weights, dL/dZ
-// through the activations, dL/dX from the first layer, and the weight
-// gradients as per-workgroup sums reduced in a fixed order (deterministic,
-// no atomics).
+// FP32 path: forward and backward run on the matrix cores with FP32
+// 16x16x4 MFMAs (decode_heads.hip), one 16-anchor tile at a time, the heads
+// split over two kinds of workgroup. The BF16 path runs the forward on the
+// matrix cores in BF16 (decode_mfma.hip). The backward recomputes the forward,
+// then forms dL/dH from the second-layer weights, dL/dZ through the
+// activations, dL/dX from the first layer, and the weight gradients as
+// per-workgroup sums reduced in a fixed order (deterministic, no atomics).
+// This file holds the per-anchor and reduction steps around them.
 #include <math.h>
 
 #include "decode_shared.h"
@@ -25,107 +23,8 @@ namespace asgs {
 
 namespace {
 
-constexpr int kDecThreads = 320;
-constexpr int kFwdAnchors = 32;     // anchors per FP32 forward workgroup
-
-
-// Load the 32 features and the view direction of anchors a0.. into X.
-template <int kDecAnchors>
-ASGS_DEV void load_inputs(const float* xyz, const float* feat, int64_t A, int64_t a0, const float cc[3],
-                          float (*X)[kIn + 1], float* dist) {
-  const int t = threadIdx.x;
-  for (int e = t; e < kDecAnchors * 32; e += blockDim.x) {
-    const int a = e / 32, c = e % 32;
-    X[a][c] = (a0 + a < A) ? feat[(a0 + a) * 32 + c] : 0.f;
-  }
-  if (t < kDecAnchors) {
-    const int64_t a = a0 + t;
-    float D[3] = {0.f, 0.f, 1.f};
-    if (a < A)
-      for (int c = 0; c < 3; ++c) D[c] = xyz[c * A + a] - cc[c];
-    const float d = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-    for (int c = 0; c < 3; ++c) X[t][32 + c] = D[c] / d;
-    X[t][35] = 0.f;
-    dist[t] = d;
-  }
-}
-
-// First layer: Z[a][j] = b1 + W1[j] . X[a] for hidden unit j of this thread,
-// anchors of half `half`. Stores act(Z) into H (and Z itself if Zs given).
-template <int kDecAnchors>
-ASGS_DEV void layer1(const float* params, const HeadTable& ht, float (*X)[kIn + 1],
-                     float (*H)[kHid + 1], float (*Zs)[kHid + 1]) {
-  const int t = threadIdx.x;
-  const int j = t % 160, half = t / 160;
-  if (j >= ht.nunits || half > 1) return;
-  const int h = j / kHid, jj = j % kHid;
-  const float* W1 = params + ht.off[h] + jj * kIn;
-  float w[kIn];
-#pragma unroll
-  for (int c = 0; c < kIn; ++c) w[c] = W1[c];
-  const float b = params[ht.off[h] + kHid * kIn + jj];
-  for (int a = half * (kDecAnchors / 2); a < (half + 1) * (kDecAnchors / 2); ++a) {
-    float z = b;
-#pragma unroll
-    for (int c = 0; c < kIn; ++c) z = fmaf(w[c], X[a][c], z);
-    H[a * kHeads + h][jj] = (h == 4) ? softplus(z) : fmaxf(z, 0.f);
-    if (Zs) Zs[a * kHeads + h][jj] = z;
-  }
-}
-
-__global__ void __launch_bounds__(kDecThreads) k_decode_fwd(DecodeConst dc, HeadTable ht, DecodeViews dv,
-                                                            const float* __restrict__ xyz,
-                                                            const float* __restrict__ feat,
-                                                            const float* __restrict__ off,
-                                                            const float* __restrict__ params,
-                                                            asgs_gaussians out) {
-  constexpr int kDecAnchors = kFwdAnchors;
-  __shared__ float X[kDecAnchors][kIn + 1];
-  __shared__ float H[kDecAnchors * kHeads][kHid + 1];
-  __shared__ float dist[kDecAnchors];
-  const int view = blockIdx.y;
-  const int64_t a0 = (int64_t)blockIdx.x * kDecAnchors;
-  const int64_t A = dc.A;
-  const int k = dc.k;
-  const int64_t n = A * k;
-  load_inputs<kDecAnchors>(xyz, feat, A, a0, dv.c[view], X, dist);
-  __syncthreads();
-  layer1<kDecAnchors>(params, ht, X, H, nullptr);
-  __syncthreads();
-  const int t = threadIdx.x;
-  for (int o = t; o < ht.nrows; o += kDecThreads) {
-    const int h = row_head(ht, o);
-    const int oh = o - ht.row0[h];
-    const int m = ht.m[h];
-    const int i = oh / m, comp = oh - i * m;
-    const float* W2 = params + ht.off[h] + kHid * kIn + kHid + oh * kHid;
-    const float b2 = params[ht.off[h] + kHid * kIn + kHid + k * m * kHid + oh];
-    float w[kHid];
-#pragma unroll
-    for (int c = 0; c < kHid; ++c) w[c] = W2[c];
-    float* plane = out_plane(out, view, h, comp, n);
-    for (int a = 0; a < kDecAnchors; ++a) {
-      if (a0 + a >= A) break;
-      float y = b2;
-#pragma unroll
-      for (int c = 0; c < kHid; ++c) y = fmaf(w[c], H[a * kHeads + h][c], y);
-      plane[(a0 + a) * k + i] = out_act(h, y, dc.l_s);
-    }
-  }
-  if (view == 0) {
-    for (int e = t; e < kDecAnchors * k * 3; e += kDecThreads) {
-      const int c = e / (kDecAnchors * k);
-      const int r = e - c * kDecAnchors * k;
-      const int64_t gn = a0 * k + r;
-      if (gn >= n) continue;
-      const int64_t a = gn / k;
-      out.mean[c * n + gn] = xyz[c * A + a] + dc.l_o * off[c * n + gn];
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Backward, per view: one kernel on the matrix cores (decode_bwd_heads.hip)
+// Backward, per view: one kernel on the matrix cores (decode_heads.hip)
 // recomputes the forward per 16-anchor tile and forms dL/dX of each head
 // group and per-workgroup partials of every MLP parameter gradient; the
 // anchor gradients follow from dL/dX, then the partials are reduced in a
@@ -338,8 +237,7 @@ void launch_decode(const DecodeConst& dc, const float* xyz, const float* feat, c
     launch_decode_mfma(dc, ht, dv, xyz, feat, off, params, out, s);
     return;
   }
-  dim3 grid((unsigned)((dc.A + kFwdAnchors - 1) / kFwdAnchors), (unsigned)dc.n_views);
-  hipLaunchKernelGGL(k_decode_fwd, grid, dim3(kDecThreads), 0, s, dc, ht, dv, xyz, feat, off, params, out);
+  launch_dec_fwd_heads(dc, ht, dv, xyz, feat, off, params, out, s);
 }
 
 void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float* feat, const float* off,

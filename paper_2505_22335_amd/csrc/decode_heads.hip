@@ -51,6 +51,28 @@ ASGS_DEV void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Activations with the hardware exp2 / log2 / reciprocal (relative error of a
+// few ulp, far inside the FP32 decoder's 1e-5 budget).
+ASGS_DEV float fexp(float x) { return __expf(x); }
+ASGS_DEV float fsigm(float y) { return __builtin_amdgcn_rcpf(1.f + fexp(-y)); }
+ASGS_DEV float fsoftplus(float z) { return fmaxf(z, 0.f) + __logf(1.f + fexp(-fabsf(z))); }
+ASGS_DEV float fout_act(int h, float y, float l_s) {
+  switch (h) {
+    case 0:
+    case 1: return fsigm(y);
+    case 2: return l_s * fsigm(y);
+    default: return y;
+  }
+}
+ASGS_DEV float fact_grad(int h, float y, float l_s) {
+  switch (h) {
+    case 0:
+    case 1: { const float s = fsigm(y); return s * (1.f - s); }
+    case 2: { const float s = fsigm(y); return l_s * s * (1.f - s); }
+    default: return 1.f;
+  }
+}
+
 // Float offsets of the LDS arrays of one group (dynamic shared memory).
 struct GroupLds {
   int W1s, b1s, W2s, b2s, X, G, H, T, total;
@@ -66,8 +88,18 @@ struct GroupDesc {
   GroupLds L;
 };
 
+struct GroupPair {
+  GroupDesc g[2];
+};
+
 struct HeadCtx {
   int h, m, rows, lrow0, lunit0, gbase;
+};
+
+// Output row of lane column fl in row tile t0 + i, as (Gaussian of the
+// anchor, component), fixed for all tiles.
+struct RowMap {
+  int gi[4], gc[4];
 };
 
 struct Views {
@@ -80,6 +112,19 @@ struct Views {
   float (*H)[16][kHS];
   float (*T)[16][kTS];
 };
+
+ASGS_DEV Views carve(float* smem, const GroupLds& L) {
+  Views S;
+  S.W1s = smem + L.W1s;
+  S.b1s = smem + L.b1s;
+  S.W2s = smem + L.W2s;
+  S.b2s = smem + L.b2s;
+  S.X = reinterpret_cast<float (*)[kXS]>(smem + L.X);
+  S.G = smem + L.G;
+  S.H = reinterpret_cast<float (*)[16][kHS]>(smem + L.H);
+  S.T = reinterpret_cast<float (*)[16][kTS]>(smem + L.T);
+  return S;
+}
 
 // First layer of head c for the tile: H (rows = anchors) into the wave's rows.
 ASGS_DEV void head_forward(const Views& S, float (*Hw)[kHS], const HeadCtx& c, int fl, int fg) {
@@ -99,16 +144,16 @@ ASGS_DEV void head_forward(const Views& S, float (*Hw)[kHS], const HeadCtx& c, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float zz = z[r] + b;
-      Hw[4 * fg + r][u] = c.h == 4 ? softplus(zz) : fmaxf(zz, 0.f);
+      Hw[4 * fg + r][u] = c.h == 4 ? fsoftplus(zz) : fmaxf(zz, 0.f);
     }
   }
 }
 
 // Output row tiles [t0, t0 + nt) of head c (nt <= kAcc): dY, dW2, db2 and the
 // partial dH over these rows.
-ASGS_DEV void head_rows(const Views& S, float (*Hw)[kHS], float (*Tw)[kTS], const HeadCtx& c, int t0, int nt,
-                        int k, float l_s, f4v (&dw2)[kAcc][2], float (&db2)[kAcc], f4v& dh0, f4v& dh1, int fl,
-                        int fg) {
+ASGS_DEV void head_rows(const Views& S, float (*Hw)[kHS], float (*Tw)[kTS], const HeadCtx& c, const RowMap& rm,
+                        int t0, int nt, int k, float l_s, f4v (&dw2)[kAcc][2], float (&db2)[kAcc], f4v& dh0,
+                        f4v& dh1, int fl, int fg) {
 #pragma unroll
   for (int i = 0; i < kAcc; ++i) {
     if (i >= nt) break;
@@ -123,13 +168,13 @@ ASGS_DEV void head_rows(const Views& S, float (*Hw)[kHS], float (*Tw)[kTS], cons
       y = mfma(Hw[fl][kk], S.W2s[wrow * kW2S + kk], y);
     }
     const float bias = S.b2s[wrow];
-    const int gi = orow / c.m, gc = orow - gi * c.m;
+    const int gi = rm.gi[i], gc = rm.gc[i];
     f4v dy;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int a = 4 * fg + r;
       const float g = S.G[c.gbase + gc * 16 * k + a * k + gi];
-      dy[r] = rok ? g * act_grad(c.h, y[r] + bias, l_s) : 0.f;
+      dy[r] = rok ? g * fact_grad(c.h, y[r] + bias, l_s) : 0.f;
       Tw[a][fl] = dy[r];
     }
     db2[i] += (dy[0] + dy[1]) + (dy[2] + dy[3]);
@@ -168,7 +213,7 @@ ASGS_DEV void head_dz(float (*Hw)[kHS], float (*Tw)[kTS], const HeadCtx& c, f4v 
     for (int r = 0; r < 4; ++r) {
       const int a = 4 * fg + r;
       const float hv = Hw[a][u];
-      dz[half][r] = c.h == 4 ? dh[r] * (1.f - expf(-hv)) : (hv > 0.f ? dh[r] : 0.f);
+      dz[half][r] = c.h == 4 ? dh[r] * (1.f - fexp(-hv)) : (hv > 0.f ? dh[r] : 0.f);
       Tw[a][u] = dz[half][r];
     }
   }
@@ -207,24 +252,97 @@ ASGS_DEV void head_dx(const Views& S, float (*Tw)[kTS], const HeadCtx& c, int ct
   }
 }
 
+// The head and second-layer row tiles [t0, t0 + nt) of wave wv: group 0 one
+// head per wave; group 1 the feature head's row tiles over the four waves,
+// the first ones taking one more.
+ASGS_DEV void assign_rows(const GroupDesc& gd, const HeadTable& ht, int grp, int wv, int k, int fl, HeadCtx& hc,
+                          RowMap& rm, int& t0, int& nt) {
+  hc.h = grp == 0 ? wv : 4;
+  hc.m = ht.m[hc.h];
+  hc.rows = k * hc.m;
+  hc.lrow0 = gd.lrow0[hc.h];
+  hc.lunit0 = 32 * (hc.h - gd.hbase);
+  hc.gbase = gd.gbase[hc.h];
+  const int T = (hc.rows + 15) / 16;
+  if (grp == 0) {
+    t0 = 0;
+    nt = T;
+  } else {
+    const int base = T / kWaves, extra = T - base * kWaves;
+    nt = base + (wv < extra ? 1 : 0);
+    t0 = wv * base + (wv < extra ? wv : extra);
+  }
+#pragma unroll
+  for (int i = 0; i < kAcc; ++i) {
+    const int orow = 16 * (t0 + i) + fl;
+    rm.gi[i] = orow / hc.m;
+    rm.gc[i] = orow - rm.gi[i] * hc.m;
+  }
+}
+
+// The group's weights into LDS: first-layer rows padded to kW1S, second-layer
+// rows to kW2S. Every load of the staging is issued before the first store.
+ASGS_DEV void stage_weights(const Views& S, const GroupDesc& gd, const HeadTable& ht, const float* params, int k,
+                            int t) {
+  constexpr int kQ1 = (4 * 32 * kW1S + kNT - 1) / kNT;          // first-layer elements per thread
+  constexpr int kQ2 = 16 * ASGS_MAX_K * kHid / kNT;             // second-layer elements per thread
+  // the group's heads (at most four) as uniform values: packed offsets and
+  // first local second-layer rows
+  int off[4], lr0[5];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int h = gd.hbase + (j < gd.nheads ? j : 0);
+    off[j] = ht.off[h];
+    lr0[j] = j < gd.nheads ? gd.lrow0[h] : gd.nrows;
+  }
+  lr0[4] = gd.nrows;
+  auto pick = [&](int j, const int (&v)[4]) { return j == 0 ? v[0] : j == 1 ? v[1] : j == 2 ? v[2] : v[3]; };
+  auto head_of_row = [&](int lr) { return (lr >= lr0[1]) + (lr >= lr0[2]) + (lr >= lr0[3]); };
+  const int n1 = gd.nunits * kW1S, n2 = gd.nrows * kHid;
+  float v1[kQ1], v2[kQ2], vb1 = 0.f, vb2 = 0.f;
+#pragma unroll
+  for (int q = 0; q < kQ1; ++q) {
+    const int e = t + q * kNT;
+    const int u = e / kW1S, c = e - u * kW1S;
+    v1[q] = (e < n1 && c < kIn) ? params[pick(u >> 5, off) + (u & 31) * kIn + c] : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < kQ2; ++q) {
+    const int e = t + q * kNT;
+    const int lr = e >> 5, c = e & 31;
+    const int j = head_of_row(lr);
+    const int jr = lr - (j == 0 ? lr0[0] : j == 1 ? lr0[1] : j == 2 ? lr0[2] : lr0[3]);
+    v2[q] = e < n2 ? params[pick(j, off) + kHid * kIn + kHid + jr * kHid + c] : 0.f;
+  }
+  if (t < gd.nunits) vb1 = params[pick(t >> 5, off) + kHid * kIn + (t & 31)];
+  if (t < gd.nrows) {
+    const int j = head_of_row(t);
+    const int r0 = j == 0 ? lr0[0] : j == 1 ? lr0[1] : j == 2 ? lr0[2] : lr0[3];
+    const int rows = (j == 0 ? lr0[1] : j == 1 ? lr0[2] : j == 2 ? lr0[3] : lr0[4]) - r0;
+    vb2 = params[pick(j, off) + kHid * kIn + kHid + rows * kHid + (t - r0)];
+  }
+#pragma unroll
+  for (int q = 0; q < kQ1; ++q)
+    if (t + q * kNT < n1) S.W1s[t + q * kNT] = v1[q];
+#pragma unroll
+  for (int q = 0; q < kQ2; ++q) {
+    const int e = t + q * kNT;
+    if (e < n2) S.W2s[(e >> 5) * kW2S + (e & 31)] = v2[q];
+  }
+  if (t < gd.nunits) S.b1s[t] = vb1;
+  if (t < gd.nrows) S.b2s[t] = vb2;
+  (void)k;
+}
+
 __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTable ht, DecodeViews dv,
                                                           const float* __restrict__ xyz,
                                                           const float* __restrict__ feat,
                                                           const float* __restrict__ params, asgs_gaussians dg,
-                                                          int view, DecWork w, GroupDesc gd0, GroupDesc gd1,
-                                                          int want_params) {
+                                                          int view, DecWork w, GroupPair gp, int want_params) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   const int grp = blockIdx.y;
-  const GroupDesc& gd = grp == 0 ? gd0 : gd1;
-  Views S;
-  S.W1s = smem + gd.L.W1s;
-  S.b1s = smem + gd.L.b1s;
-  S.W2s = smem + gd.L.W2s;
-  S.b2s = smem + gd.L.b2s;
-  S.X = reinterpret_cast<float (*)[kXS]>(smem + gd.L.X);
-  S.G = smem + gd.L.G;
-  S.H = reinterpret_cast<float (*)[16][kHS]>(smem + gd.L.H);
-  S.T = reinterpret_cast<float (*)[16][kTS]>(smem + gd.L.T);
+  const GroupDesc& gd = gp.g[grp];
+  const Views S = carve(smem, gd.L);
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -232,65 +350,12 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
   const int A = (int)dc.A;
   const int k = dc.k;
   const int n = A * k;
-  // ---- stage the group's weights ----
-  for (int e0 = t; e0 < gd.nunits * kW1S; e0 += 8 * kNT) {
-    float v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = e0 + q * kNT;
-      const int u = e / kW1S, c = e - u * kW1S;
-      const int h = gd.hbase + (u >> 5);
-      v[q] = (e < gd.nunits * kW1S && c < kIn) ? params[ht.off[h] + (u & 31) * kIn + c] : 0.f;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (e0 + q * kNT < gd.nunits * kW1S) S.W1s[e0 + q * kNT] = v[q];
-  }
-  for (int u = t; u < gd.nunits; u += kNT)
-    S.b1s[u] = params[ht.off[gd.hbase + (u >> 5)] + kHid * kIn + (u & 31)];
-  for (int hh = 0; hh < gd.nheads; ++hh) {
-    const int h = gd.hbase + hh;
-    const int rows = k * ht.m[h];
-    const float* W2 = params + ht.off[h] + kHid * kIn + kHid;
-    for (int e0 = t; e0 < rows * kHid; e0 += 8 * kNT) {
-      float v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = e0 + q * kNT;
-        v[q] = e < rows * kHid ? W2[e] : 0.f;
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int e = e0 + q * kNT;
-        if (e < rows * kHid) S.W2s[(gd.lrow0[h] + (e >> 5)) * kW2S + (e & 31)] = v[q];
-      }
-    }
-    for (int r = t; r < rows; r += kNT) S.b2s[gd.lrow0[h] + r] = W2[rows * kHid + r];
-  }
+  stage_weights(S, gd, ht, params, k, t);
   // ---- this wave's head and rows ----
   HeadCtx hc;
-  int t0 = 0, nt = 0;
-  if (grp == 0) {
-    hc.h = wv;  // one head per wave
-  } else {
-    hc.h = 4;
-  }
-  hc.m = ht.m[hc.h];
-  hc.rows = k * hc.m;
-  hc.lrow0 = gd.lrow0[hc.h];
-  hc.lunit0 = 32 * (hc.h - gd.hbase);
-  hc.gbase = gd.gbase[hc.h];
-  {
-    const int T = (hc.rows + 15) / 16;
-    if (grp == 0) {
-      nt = T;
-    } else {
-      // the feature head's row tiles over the four waves, the first ones one more
-      const int base = T / kWaves, extra = T - base * kWaves;
-      nt = base + (wv < extra ? 1 : 0);
-      t0 = wv * base + (wv < extra ? wv : extra);
-    }
-  }
+  RowMap rm;
+  int t0, nt;
+  assign_rows(gd, ht, grp, wv, k, fl, hc, rm, t0, nt);
   f4v dw2[kAcc][2];
   float db2[kAcc];
 #pragma unroll
@@ -312,7 +377,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
   constexpr int kMaxPlanes = 16;
   const int run = 16 * k;
   const int nplanes = gd.gtot / run;
-  float xpre[2];
+  float xpre[2], ppre[3];
   float gpre[kMaxPlanes];
   auto fetch = [&](int tile) {
     const int a0 = tile * 16;
@@ -322,6 +387,8 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
       const int a = e >> 5, c = e & 31;
       xpre[q] = a0 + a < A ? feat[(size_t)(a0 + a) * 32 + c] : 0.f;
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ppre[c] = (t < 16 && a0 + t < A) ? xyz[(size_t)c * A + a0 + t] : 0.f;
     const size_t gidx = (size_t)a0 * k + t;
 #pragma unroll
     for (int pl = 0; pl < kMaxPlanes; ++pl) {
@@ -352,7 +419,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
     if (t < 16) {
       float D[3] = {0.f, 0.f, 0.f}, dist = 1.f;
       if (a0 + t < A) {
-        for (int c = 0; c < 3; ++c) D[c] = xyz[(size_t)c * A + a0 + t] - dv.c[view][c];
+        for (int c = 0; c < 3; ++c) D[c] = ppre[c] - dv.c[view][c];
         dist = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
         for (int c = 0; c < 3; ++c) D[c] /= dist;
       }
@@ -369,7 +436,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
     f4v dz[2];
     head_forward(S, Hw, hc, fl, fg);
     wave_sync();
-    head_rows(S, Hw, Tw, hc, t0, nt, k, dc.l_s, dw2, db2, dh0, dh1, fl, fg);
+    head_rows(S, Hw, Tw, hc, rm, t0, nt, k, dc.l_s, dw2, db2, dh0, dh1, fl, fg);
     if (grp == 0) {
       head_dz(Hw, Tw, hc, dh0, dh1, dz, fl, fg);
       head_w1(S, dz, 0, dw1[0], db1[0], fg, fl);
@@ -480,6 +547,119 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
   }
 }
 
+// Forward on the matrix cores, per (view, head group): the first layer and
+// output rows as in the backward's recomputation, then the output
+// activations; outputs are staged per (head, component) plane in LDS and
+// written as the tile's contiguous runs of 16 k values. Group 0 of view 0
+// also writes the Gaussian means x_v + l_o O_i (shared by the views).
+__global__ void __launch_bounds__(kNT, 2) k_dec_fwd_heads(DecodeConst dc, HeadTable ht, DecodeViews dv,
+                                                          const float* __restrict__ xyz,
+                                                          const float* __restrict__ feat,
+                                                          const float* __restrict__ off,
+                                                          const float* __restrict__ params, asgs_gaussians out,
+                                                          GroupPair gp, int ngroups) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  const int grp = blockIdx.y % ngroups;
+  const int view = blockIdx.y / ngroups;
+  const GroupDesc& gd = gp.g[grp];
+  const Views S = carve(smem, gd.L);
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int fl = lane & 15, fg = lane >> 4;
+  const int A = (int)dc.A;
+  const int k = dc.k;
+  const int n = A * k;
+  stage_weights(S, gd, ht, params, k, t);
+  HeadCtx hc;
+  RowMap rm;
+  int t0, nt;
+  assign_rows(gd, ht, grp, wv, k, fl, hc, rm, t0, nt);
+  float (*Hw)[kHS] = S.H[wv];
+  const int run = 16 * k;
+  const int nplanes = gd.gtot / run;
+  const int ngrid = (A + 15) / 16;
+  const int tk = t / k;  // anchor within the tile of the thread's output element
+  float xpre[2], ppre[3];
+  auto fetch = [&](int tile) {
+    const int a0 = tile * 16;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + q * kNT;
+      const int a = e >> 5, c = e & 31;
+      xpre[q] = a0 + a < A ? feat[(size_t)(a0 + a) * 32 + c] : 0.f;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ppre[c] = (t < 16 && a0 + t < A) ? xyz[(size_t)c * A + a0 + t] : 0.f;
+  };
+  if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
+    const int a0 = tile * 16;
+    __syncthreads();  // weights staged / the previous tile's outputs are written
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + q * kNT;
+      S.X[e >> 5][e & 31] = xpre[q];
+    }
+    if (t < 16) {
+      float D[3] = {0.f, 0.f, 0.f}, dist = 1.f;
+      if (a0 + t < A) {
+        for (int c = 0; c < 3; ++c) D[c] = ppre[c] - dv.c[view][c];
+        dist = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+        for (int c = 0; c < 3; ++c) D[c] /= dist;
+      }
+      for (int c = 0; c < 3; ++c) S.X[t][32 + c] = D[c];
+      S.X[t][35] = 0.f;
+      S.X[t][36] = 0.f;
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < ngrid) fetch(tile + gridDim.x);
+    head_forward(S, Hw, hc, fl, fg);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < kAcc; ++i) {
+      if (i >= nt) break;
+      const int r0 = 16 * (t0 + i);
+      const int orow = r0 + fl;
+      const bool rok = orow < hc.rows;
+      const int wrow = hc.lrow0 + (rok ? orow : 0);
+      f4v y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const int kk = 4 * ks + fg;
+        y = mfma(Hw[fl][kk], S.W2s[wrow * kW2S + kk], y);
+      }
+      const float bias = S.b2s[wrow];
+      const int gi = rm.gi[i], gc = rm.gc[i];
+      if (rok) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 4 * fg + r;
+          S.G[hc.gbase + gc * run + a * k + gi] = fout_act(hc.h, y[r] + bias, dc.l_s);
+        }
+      }
+    }
+    __syncthreads();
+    const size_t gidx = (size_t)a0 * k + t;
+    if (t < run && gidx < (size_t)n) {
+      for (int pl = 0; pl < nplanes; ++pl) {
+        int h = 4, comp = pl;
+        if (grp == 0) {
+          h = pl < 1 ? 0 : pl < 4 ? 1 : pl < 7 ? 2 : 3;
+          comp = pl - (h == 0 ? 0 : h == 1 ? 1 : h == 2 ? 4 : 7);
+        }
+        out_plane(out, view, h, comp, n)[gidx] = S.G[pl * run + t];
+      }
+      if (grp == 0 && view == 0) {
+        const int64_t a = a0 + tk;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          out.mean[(size_t)c * n + gidx] = xyz[(size_t)c * A + a] + dc.l_o * off[(size_t)c * n + gidx];
+      }
+    }
+  }
+}
+
 GroupDesc group_desc(const HeadTable& ht, int k, int hbase, int nheads) {
   GroupDesc g{};
   g.hbase = hbase;
@@ -521,6 +701,24 @@ int64_t dec_bwd_heads_blocks(int64_t n_anchors) {
 
 size_t dec_bwd_dx_floats(int64_t n_anchors) { return 2 * (size_t)n_anchors * kDX; }
 
+void launch_dec_fwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
+                          const float* feat, const float* off, const float* params, const asgs_gaussians& out,
+                          hipStream_t s) {
+  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4);
+  const bool has_feat = ht.m[4] > 0;
+  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1) : g0;
+  const int ng = has_feat ? 2 : 1;
+  const int lds = (g0.L.total > g1.L.total ? g0.L.total : g1.L.total) * (int)sizeof(float);
+  static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (at most ~77 KiB for k = 16)
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_dec_fwd_heads),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_dec_fwd_heads, dim3((unsigned)dec_bwd_heads_blocks(dc.A), (unsigned)(ng * dc.n_views)),
+                     dim3(kNT), lds, s, dc, ht, dv, xyz, feat, off, params, out, GroupPair{{g0, g1}}, ng);
+}
+
 void launch_dec_bwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                           const float* feat, const float* params, const asgs_gaussians& dg, int view,
                           const DecWork& w, bool want_params, hipStream_t s) {
@@ -535,7 +733,7 @@ void launch_dec_bwd_heads(const DecodeConst& dc, const HeadTable& ht, const Deco
     attr_set = true;
   }
   hipLaunchKernelGGL(k_dec_bwd_heads, dim3((unsigned)w.nblk_w, has_feat ? 2u : 1u), dim3(kNT), lds, s, dc, ht, dv,
-                     xyz, feat, params, dg, view, w, g0, g1, want_params ? 1 : 0);
+                     xyz, feat, params, dg, view, w, GroupPair{{g0, g1}}, want_params ? 1 : 0);
 }
 
 }  // namespace asgs

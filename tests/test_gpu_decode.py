@@ -51,7 +51,7 @@ def _cams_tiny(nv):
             for v in range(nv)]
 
 
-@pytest.mark.parametrize("k,nf,nv", [(10, 16, 1), (3, 16, 2), (7, 0, 3)])
+@pytest.mark.parametrize("k,nf,nv", [(10, 16, 1), (3, 16, 2), (7, 0, 3), (16, 16, 2), (1, 16, 1)])
 def test_decode_forward_backward(k, nf, nv):
     sc = synth.tiny_anchor_scene(50 + k, 77, k=k, n_feat=nf)
     cams = _cams_tiny(nv)
