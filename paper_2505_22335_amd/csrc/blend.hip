@@ -31,6 +31,15 @@ ASGS_DEV int find_view(const ViewDev* views, int n_views, int tile) {
 ASGS_DEV int tile_lx(int t) { return ((t >> 6) & 1) * 8 + (t & 7); }
 ASGS_DEV int tile_ly(int t) { return ((t >> 7) & 1) * 8 + ((t >> 3) & 7); }
 
+// Issue priority of a tile's waves by list length: the longest lists run on
+// the critical path of the launch, so their waves are preferred over shorter
+// ones sharing a SIMD (the order of the results does not change).
+ASGS_DEV void prioritise(uint32_t len) {
+  if (len > 256u) __builtin_amdgcn_s_setprio(3);
+  else if (len > 192u) __builtin_amdgcn_s_setprio(2);
+  else if (len > 128u) __builtin_amdgcn_s_setprio(1);
+}
+
 // Which of the tile's four 8x8 quarters (bit w) hold a pixel centre that can
 // pass the alpha test power >= ln(alpha_min / o) of an entry: a conservative
 // test against the bounding box of the ellipse d^T Q d <= 2 L, Q = [[A, B],
@@ -85,6 +94,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
+  prioritise(rg.y - rg.x);
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
@@ -102,11 +112,13 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   uint32_t last = 0;
   bool done = !inside;
   const float amax = rc.alpha_max, tmin = rc.T_min;
+  // the Gaussian ids of the next round are read while this round is staged
+  uint32_t gid_next = rg.x + t < rg.y ? pairgid[rg.x + t] : 0u;
   for (uint32_t base = rg.x; base < rg.y; base += kTilePix) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t p = base + t;
     if (p < rg.y) {
-      const uint32_t gid = pairgid[p];
+      const uint32_t gid = gid_next;
       const float4 g0 = geom[2 * (size_t)gid];
       const float4 g1 = geom[2 * (size_t)gid + 1];
       sg[2 * t] = g0;
@@ -116,6 +128,7 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
       const uint8_t m = (uint8_t)quarter_mask(g0, g1, x0, y0);
       smask[t] = m;
       pmask[p] = m;  // reused by the backward
+      if (p + kTilePix < rg.y) gid_next = pairgid[p + kTilePix];
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
@@ -242,6 +255,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
+  prioritise(rg.y - rg.x);
   const uint32_t len = rg.y - rg.x;
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pval_fin);
@@ -329,15 +343,25 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   // Records are staged in rounds of kRound entries, walking the list from the
   // back; the global loads of the next round are issued before the current
   // round is processed and land in LDS at the start of the next round.
+  // The Gaussian ids of a round are read one round earlier still, so that
+  // no load of the staging waits on another.
   float4 stage[kPer];
   uint32_t stage_slot = 0u, stage_mask = 0u;
+  uint32_t gid_next[kPer];
+  auto fetch_gid = [&](int lo_r, int cnt_r) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int ent = (t + k * kTilePix) / kRecF4;
+      gid_next[k] = ent < cnt_r ? pairgid[rg.x + lo_r + ent] : 0u;
+    }
+  };
   auto fetch = [&](int lo_r, int cnt_r) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int e = t + k * kTilePix;
       const int ent = e / kRecF4, f = e - ent * kRecF4;
       if (ent < cnt_r) {
-        const uint32_t gid = pairgid[rg.x + lo_r + ent];
+        const uint32_t gid = gid_next[k];
         stage[k] = f < 2 ? geom[2 * (size_t)gid + f] : chan4[(size_t)gid * CS4 + (f - 2)];
       }
     }
@@ -382,7 +406,12 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   };
   int rhi = (int)nproc;
   int rlo = rhi - kRound > 0 ? rhi - kRound : 0;
-  if (rhi > 0) fetch(rlo, rhi - rlo);
+  if (rhi > 0) {
+    fetch_gid(rlo, rhi - rlo);
+    fetch(rlo, rhi - rlo);
+    const int nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
+    if (rlo > 0) fetch_gid(nrlo, rlo - nrlo);
+  }
   while (rhi > 0) {
     __syncthreads();  // every reader of the previous round is done
 #pragma unroll
@@ -398,7 +427,11 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     __syncthreads();
     const int cnt = rhi - rlo;
     const int nrhi = rlo, nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
-    if (nrhi > 0) fetch(nrlo, nrhi - nrlo);
+    if (nrhi > 0) {
+      fetch(nrlo, nrhi - nrlo);
+      const int n2lo = nrlo - kRound > 0 ? nrlo - kRound : 0;
+      if (nrlo > 0) fetch_gid(n2lo, nrlo - n2lo);
+    }
     // entries of the round that can reach a pixel of this wave's quarter
     const bool mine = lane < cnt && ((smk[lane] >> wv) & 1u);
     uint64_t bits = __ballot(mine);
@@ -420,15 +453,16 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
       const float alpha = fminf(amax, raw);
       const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
       const float Tk = T * ioma;
-      float dotg = 0.f;
+      float dot0 = 0.f, dot1 = 0.f;  // two independent chains
 #pragma unroll
       for (int c4 = 0; c4 < CS4; ++c4) {
         const float4 v = srec[j * kRecF4 + 2 + c4];
-        dotg = fmaf(G[4 * c4 + 0], v.x, dotg);
-        dotg = fmaf(G[4 * c4 + 1], v.y, dotg);
-        dotg = fmaf(G[4 * c4 + 2], v.z, dotg);
-        dotg = fmaf(G[4 * c4 + 3], v.w, dotg);
+        dot0 = fmaf(G[4 * c4 + 0], v.x, dot0);
+        dot1 = fmaf(G[4 * c4 + 1], v.y, dot1);
+        dot0 = fmaf(G[4 * c4 + 2], v.z, dot0);
+        dot1 = fmaf(G[4 * c4 + 3], v.w, dot1);
       }
+      const float dotg = dot0 + dot1;
       const float w_ = alpha * Tk;
       const float dalpha = Tk * dotg - (sacc + GT * Tf) * ioma;
       if (use) {

@@ -42,23 +42,20 @@ __global__ void __launch_bounds__(kAnchorThreads) k_dec_bwd_anchor(DecodeConst d
   __shared__ float red[3][kAnchorThreads / 64];
   const int t = threadIdx.x;
   const int64_t A = dc.A;
-  const int64_t a0 = (int64_t)blockIdx.x * kAnchorThreads;
+  const int64_t i = (int64_t)blockIdx.x * kAnchorThreads + t;
   const float* dx0 = w.dxpart;
   const float* dx1 = w.dxpart + A * 36;
-  if (d_feat) {
-    for (int i = 0; i < 32; ++i) {
-      const int e = i * kAnchorThreads + t;
-      const int64_t a = a0 + e / 32;
-      const int c = e % 32;
-      if (a < A) {
-        const float v = dx0[a * 36 + c] + (has_feat ? dx1[a * 36 + c] : 0.f);
-        float* p = &d_feat[a * 32 + c];
-        *p = (view == 0 ? 0.f : *p) + v;
-      }
-    }
+  // one feature element per thread
+  if (d_feat && i < A * 32) {
+    const int64_t a = i >> 5;
+    const int c = (int)(i & 31);
+    const float v = dx0[a * 36 + c] + (has_feat ? dx1[a * 36 + c] : 0.f);
+    d_feat[i] = (view == 0 ? 0.f : d_feat[i]) + v;
   }
+  // the first blocks also take one anchor's view direction per thread
+  if ((int64_t)blockIdx.x * kAnchorThreads >= A) return;
   float dcl[3] = {0.f, 0.f, 0.f};
-  const int64_t a = a0 + t;
+  const int64_t a = i;
   if (a < A) {
     float gd[3], D[3];
     for (int c = 0; c < 3; ++c) {
@@ -257,8 +254,9 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
   w.nblk_m = (int32_t)z.nblk_m;
   for (int view = 0; view < dc.n_views; ++view) {
     launch_dec_bwd_heads(dc, ht, dv, xyz, feat, params, dg, view, w, d_params != nullptr, s);
-    hipLaunchKernelGGL(k_dec_bwd_anchor, dim3((unsigned)z.nblk_m), dim3(kAnchorThreads), 0, s, dc, dv, xyz, w, view,
-                       ht.m[4] > 0 ? 1 : 0, d_xyz, d_feat);
+    const int64_t nthreads = d_feat ? dc.A * 32 : dc.A;
+    hipLaunchKernelGGL(k_dec_bwd_anchor, dim3((unsigned)((nthreads + kAnchorThreads - 1) / kAnchorThreads)),
+                       dim3(kAnchorThreads), 0, s, dc, dv, xyz, w, view, ht.m[4] > 0 ? 1 : 0, d_xyz, d_feat);
   }
   if (d_xyz)
     hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,
