@@ -189,15 +189,17 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
   // blend kernels test alpha >= alpha_min without an exponential
   geom[2 * gid + 1] = make_float4(C, o, logf(rc.alpha_min / o), 0.f);
   const float* rgb = g.rgb + view * g.view_stride[4];
-  float* ch = chan + gid * CS;
-  ch[0] = rgb[i];
-  ch[1] = rgb[rc.n + i];
-  ch[2] = rgb[2 * rc.n + i];
-  ch[3] = P.t[2];
+  // the channel record (80 or 16 bytes, 16-byte aligned) as float4 stores
+  float4* ch = reinterpret_cast<float4*>(chan + gid * CS);
+  ch[0] = make_float4(rgb[i], rgb[rc.n + i], rgb[2 * rc.n + i], P.t[2]);
   if (NF > 0) {
     const float* fp = g.feat + view * g.view_stride[5];
+    float f[NF > 0 ? NF : 1];
 #pragma unroll
-    for (int c = 0; c < NF; ++c) ch[4 + c] = fp[(int64_t)c * rc.n + i];
+    for (int c = 0; c < NF; ++c) f[c] = fp[(int64_t)c * rc.n + i];
+#pragma unroll
+    for (int c4 = 0; c4 < NF / 4; ++c4)
+      ch[1 + c4] = make_float4(f[4 * c4], f[4 * c4 + 1], f[4 * c4 + 2], f[4 * c4 + 3]);
   }
   rect[gid] = make_short4((short)tx0, (short)tx1, (short)ty0, (short)ty1);
   ntiles[gid] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));

@@ -11,11 +11,12 @@
 // list.
 //
 // Each pass is three kernels: an upsweep (per-block 256-bin digit histogram,
-// stored block-major), a one-workgroup scan that turns the histograms into
-// every block's digit offsets in place (digit totals over all blocks plus the
-// counts of the blocks before it), and a stable scatter. Within a block, wave
-// ballots find lanes with equal digits; ranks follow item order within a
-// wave, across the block's waves and across its rounds.
+// stored digit-major), a scan with one wave per digit that turns a digit's
+// counts over the blocks into each block's offset within the digit and the
+// digit's total, and a stable scatter that adds the digit starts (a scan of
+// the 256 totals, repeated by every block). Within a block, wave ballots find
+// lanes with equal digits; ranks follow item order within a wave, across the
+// block's waves and across its rounds.
 #include "internal.h"
 
 namespace asgs {
@@ -32,7 +33,7 @@ struct RadixArgs {
   uint64_t count_cap;
   int32_t shift;
   int32_t filter;                          // drop keys equal to kInvalidKey
-  uint32_t* hist;                          // [nb][256] block-major histograms, then offsets
+  uint32_t* hist;                          // [256][nb] digit-major histograms, then offsets; [256] totals after
   unsigned int* counter;                   // last-block counter (0 between uses)
   unsigned long long* total_out;           // nullptr or: number of kept items
 };
@@ -65,58 +66,47 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(RadixArgs a) {
     }
   }
   __syncthreads();
-  a.hist[b * kRadixBins + threadIdx.x] = lh[threadIdx.x];
+  a.hist[(uint64_t)threadIdx.x * nb + b] = lh[threadIdx.x];
 }
 
-constexpr int kScanGroups = 4;  // block ranges per digit in the offset scan
+constexpr int kScanPer = 8;  // block counts per lane in one step of the digit scan
 
-// Histograms -> per-block digit offsets, in place. Thread (g, d) owns digit d
-// over the g-th quarter of the blocks; every histogram entry is read and then
-// overwritten by its owner only.
-__global__ void __launch_bounds__(kRadixBins * kScanGroups) k_radix_scan(RadixArgs a) {
-  __shared__ uint32_t part[kScanGroups][kRadixBins];
-  __shared__ uint32_t dbase[kRadixBins];
-  __shared__ uint32_t wsum[kRadixBins / 64];
+// One wave per digit: exclusive prefix of the digit's counts over the
+// blocks, in place, and the digit total after the histograms. Each lane takes
+// kScanPer consecutive blocks; every load of a step is issued before the sums.
+__global__ void __launch_bounds__(256) k_radix_scan(RadixArgs a) {
   const uint64_t n = item_count(a);
   const int nb = (int)((n + kSortItems - 1) / kSortItems);
-  const int d = threadIdx.x & (kRadixBins - 1), g = threadIdx.x / kRadixBins;
-  const int per = (nb + kScanGroups - 1) / kScanGroups;
-  const int b0 = g * per, b1 = min(nb, b0 + per);
-  uint32_t* h = a.hist;
-  uint32_t s = 0u;
-#pragma unroll 8
-  for (int b = b0; b < b1; ++b) s += h[b * kRadixBins + d];
-  part[g][d] = s;
-  __syncthreads();
-  // exclusive scan of the digit totals over the 256 digits (group 0: four waves)
-  uint32_t tot = 0u, incl = 0u;
-  if (g == 0) {
+  const int lane = threadIdx.x & 63;
+  const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+  uint32_t* h = a.hist + (uint64_t)d * nb;
+  uint32_t carry = 0u;
+  for (int b0 = 0; b0 < nb; b0 += 64 * kScanPer) {
+    uint32_t v[kScanPer];
+    uint32_t sum = 0u;
 #pragma unroll
-    for (int q = 0; q < kScanGroups; ++q) tot += part[q][d];
-    incl = tot;
-    const int lane = d & 63;
+    for (int q = 0; q < kScanPer; ++q) {
+      const int b = b0 + lane * kScanPer + q;
+      v[q] = b < nb ? h[b] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) sum += v[q];
+    uint32_t incl = sum;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t v = __shfl_up(incl, o);
-      if (lane >= o) incl += v;
+      const uint32_t u = __shfl_up(incl, o);
+      if (lane >= o) incl += u;
     }
-    if (lane == 63) wsum[d >> 6] = incl;
+    uint32_t run = carry + incl - sum;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+      const int b = b0 + lane * kScanPer + q;
+      if (b < nb) h[b] = run;
+      run += v[q];
+    }
+    carry += __shfl(incl, 63);
   }
-  __syncthreads();
-  if (g == 0) {
-    for (int w = 0; w < (d >> 6); ++w) incl += wsum[w];
-    dbase[d] = incl - tot;
-    if (d == kRadixBins - 1 && a.total_out) *a.total_out = incl;
-  }
-  __syncthreads();
-  uint32_t run = dbase[d];
-  for (int q = 0; q < g; ++q) run += part[q][d];
-#pragma unroll 8
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t c = h[b * kRadixBins + d];
-    h[b * kRadixBins + d] = run;
-    run += c;
-  }
+  if (lane == 0) a.hist[(uint64_t)kRadixBins * nb + d] = carry;
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(RadixArgs a) {
@@ -129,8 +119,23 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(RadixArgs a) {
   if (b >= nb) return;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
-  base[t] = a.hist[b * kRadixBins + t];  // this block's digit offsets (k_radix_scan)
-  (void)lane;
+  // digit starts: exclusive scan of the digit totals (every block repeats it)
+  {
+    const uint32_t tot = a.hist[(uint64_t)kRadixBins * nb + t];
+    uint32_t incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t u = __shfl_up(incl, o);
+      if (lane >= o) incl += u;
+    }
+    if (lane == 63) run[wv] = incl;  // wave totals (run is reset below)
+    __syncthreads();
+    uint32_t before = 0u;
+    for (int w = 0; w < wv; ++w) before += run[w];
+    base[t] = before + incl - tot + a.hist[(uint64_t)t * nb + b];  // + this block's offset in the digit
+    if (b == 0 && t == kRadixBins - 1 && a.total_out) *a.total_out = before + incl;
+    __syncthreads();
+  }
   run[t] = 0u;
   for (int r = 0; r < kSortIPT; ++r) {
     const uint64_t idx = b * kSortItems + (uint64_t)r * kSortThreads + t;
@@ -173,7 +178,7 @@ void radix_pass(const RadixArgs& a, uint64_t max_items, hipStream_t s) {
   const unsigned nblk = (unsigned)((max_items + kSortItems - 1) / kSortItems);
   const unsigned g = nblk > 0 ? nblk : 1;
   hipLaunchKernelGGL(k_radix_upsweep, dim3(g), dim3(kSortThreads), 0, s, a);
-  hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kRadixBins * kScanGroups), 0, s, a);
+  hipLaunchKernelGGL(k_radix_scan, dim3(kRadixBins / 4), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_radix_scatter, dim3(g), dim3(kSortThreads), 0, s, a);
 }
 

@@ -121,6 +121,41 @@ def test_tiny_scene_features_ragged(seed):
     assert rel_err(res["dpose"][0], gr["pose"]) <= GRAD_TOL
 
 
+def test_needle_gaussians_and_faint_opacities():
+    """Per-wave culling stress: anisotropic footprints (log-scale spread 1.0
+    per axis, axis ratios up to ~200, random rotations) and opacities just
+    above alpha_min, whose small ellipses sit near quarter and tile
+    boundaries. (With ratios near 1e3 the FP32 rotation gradient through the
+    projection loses the 1e-3 budget to conditioning, independent of the
+    blend.)"""
+    nf = 16
+    sc = synth.tiny_scene(321, 400, n_feat=nf, logs_mu=-3.0, logs_sd=1.0)
+    rng = np.random.default_rng(5)
+    faint = rng.random(sc.opacity.shape) < 0.5
+    sc.opacity[faint] = (1.0 / 255.0) * (1.0 + rng.uniform(0.01, 0.3, faint.sum())).astype(np.float32)
+    cam = synth.Camera(96, 80, 70.0, 70.0, 47.5, 39.5, np.eye(3, 4, dtype=np.float32))
+    log("case needles")
+    ref = oracle.render_scene(sc, cam, oracle_opts(nf), with_margins=True, keep_lists=True)
+    keep = guard_mask(ref["margins"])
+    log("guard-band pixels excluded:", int((~keep).sum()), "of", keep.size)
+    G = upstream(31, cam.height, cam.width, nf)
+    for k in G:
+        G[k] = G[k] * keep
+    res = _gpu_render(sc, [cam], nf, G=G)
+    out = res["out"]
+    for k in ("rgb", "depth", "alpha", "feat"):
+        e = rel_err(out[k][0], ref[k], keep)
+        log("needles", k, "%.2e" % e)
+        assert e <= IMG_TOL, k
+    mism, ni = _check_lists(res["rc"], ref)
+    assert ni == len(ref["gids"]) and mism == 0
+    _, gr = oracle.render_scene(sc, cam, oracle_opts(nf), grad_out=G, pose_grad=True)
+    for k in ("mean", "scale", "rot", "opacity", "rgb", "feat"):
+        e = rel_err(res["dg"][k][0], gr["gauss"][k])
+        log("needles grad", k, "%.2e" % e)
+        assert e <= GRAD_TOL, k
+
+
 def test_multiview_batch_equals_single():
     """Three views in one call give the same images and gradients as one call
     per view (results are per view; the batch shares one sort)."""
