@@ -1,11 +1,13 @@
 // Front-to-back alpha compositing of colour, depth and the low-dimensional
 // feature (UP-SLAM Sec. 3.1 Eq. 3, Sec. 3.3 Eq. 10) and its backward.
 //
-// One 256-thread workgroup per 16x16 screen tile, one pixel per thread. The
-// tile's depth-ordered list is staged through LDS in batches of records; each
-// pixel walks the batch, skips alpha < alpha_min, stops before the
-// transmittance would fall below T_min, and accumulates w = alpha * T times
-// (rgb, z, feature). The workgroup leaves as soon as every pixel has stopped.
+// One workgroup per 16x16 screen tile; each wave covers an 8x8 quarter of it
+// (the forward has two waves per quarter, see k_blend_fwd). The tile's
+// depth-ordered list is staged through LDS in rounds of records; a wave visits
+// only the entries whose alpha >= alpha_min ellipse can reach its quarter;
+// each pixel skips alpha < alpha_min, stops before the transmittance would
+// fall below T_min, and accumulates w = alpha * T times (rgb, z, feature).
+// The workgroup leaves as soon as every pixel has stopped.
 //
 // The backward replays each pixel's list back to front from its last
 // composited Gaussian, recovering T_k = T_{k+1} / (1 - alpha_k), and sums each
@@ -75,9 +77,23 @@ ASGS_DEV uint32_t quarter_mask(const float4& g0, const float4& g1, int x0, int y
   return m;
 }
 
+constexpr int kFwdThreads = 2 * kTilePix;  // two waves per 8x8 quarter: front and back half of its list
+constexpr int kSplitMin = 16;             // a round's quarter list shorter than this stays on the front wave
+
+// Forward compositing, one 512-thread workgroup per tile. Each 8x8 quarter
+// of the tile has two waves. Per round of staged list entries, the quarter's
+// entries that can reach one of its pixels are split in list order: the
+// front wave composites the first half onto the running state (T, channels,
+// last contributor), the back wave the second half from T = 1 at the same
+// time; then the front wave appends the back half's result,
+//   C <- C + T C_back,  T <- T T_back,
+// which equals compositing the two halves in order as long as the
+// transmittance cannot have crossed T_min inside the back half
+// (T T_back >= T_min, T being monotone). Pixels where it could re-run the
+// back half on the front wave with the sequential rule.
 template <int NF>
-__global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const ViewDev* __restrict__ views,
-                                                        char* ctx, CtxLayout L, asgs_images out) {
+__global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const ViewDev* __restrict__ views,
+                                                           char* ctx, CtxLayout L, asgs_images out) {
   constexpr int CS = 4 + NF;
   constexpr int CS4 = CS / 4;
   const int tile = (int)ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];  // longest lists first
@@ -88,9 +104,12 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int qd = wv & 3;         // quarter
+  const bool back = wv >= 4;     // back half of the quarter's list
+  const int tq = (qd << 6) | lane;
   const int x0 = tx * kTile, y0 = ty * kTile;
-  const int px = x0 + tile_lx(t);
-  const int py = y0 + tile_ly(t);
+  const int px = x0 + tile_lx(tq);
+  const int py = y0 + tile_ly(tq);
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
@@ -103,21 +122,57 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
   __shared__ float4 sg[kTilePix * 2];
   __shared__ float4 sc[kTilePix * CS4];
   __shared__ uint8_t smask[kTilePix];
-  __shared__ uint16_t swl[kTilePix / 64][kTilePix];
+  __shared__ uint16_t swl[kFwdThreads / 64][kTilePix];
+  __shared__ float xch[4][CS + 2][64];  // back-half state per quarter pixel: T, channels, last
+  __shared__ uint64_t qdone[4];         // front lanes already stopped, per quarter
 
   float T = 1.f;
   float acc[CS];
 #pragma unroll
   for (int c = 0; c < CS; ++c) acc[c] = 0.f;
   uint32_t last = 0;
-  bool done = !inside;
+  bool done = back || !inside;  // back lanes keep no running state
   const float amax = rc.alpha_max, tmin = rc.T_min;
+  // Composite list positions [i0, i1) of this wave's round list. real: the
+  // running state with the T_min stop; otherwise a local back-half state.
+  auto run = [&](int i0, int i1, uint32_t base, bool act, bool real) {
+    for (int i = i0; i < i1; ++i) {
+      const int j = __builtin_amdgcn_readfirstlane(swl[wv][i]);
+      const float4 g0 = sg[2 * j], g1 = sg[2 * j + 1];
+      float dx, dy;
+      const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
+      // alpha >= alpha_min  <=>  power >= ln(alpha_min / o) (record slot 6)
+      const bool take = act && power <= 0.f && power >= g1.z;
+      if (!__ballot(take)) continue;
+      const float alpha = fminf(amax, g1.y * __expf(power));
+      const float Tn = T * (1.f - alpha);
+      const bool stop = real && take && Tn < tmin;
+      if (take && !stop) {
+        const float w = alpha * T;
+#pragma unroll
+        for (int c4 = 0; c4 < CS4; ++c4) {
+          const float4 v = sc[j * CS4 + c4];
+          acc[4 * c4 + 0] = fmaf(w, v.x, acc[4 * c4 + 0]);
+          acc[4 * c4 + 1] = fmaf(w, v.y, acc[4 * c4 + 1]);
+          acc[4 * c4 + 2] = fmaf(w, v.z, acc[4 * c4 + 2]);
+          acc[4 * c4 + 3] = fmaf(w, v.w, acc[4 * c4 + 3]);
+        }
+        T = Tn;
+        last = base - rg.x + (uint32_t)j + 1u;
+      }
+      if (real && __ballot(stop)) {
+        done = done || stop;
+        act = act && !stop;
+        if (__ballot(act) == 0) break;
+      }
+    }
+  };
   // the Gaussian ids of the next round are read while this round is staged
-  uint32_t gid_next = rg.x + t < rg.y ? pairgid[rg.x + t] : 0u;
+  uint32_t gid_next = t < kTilePix && rg.x + t < rg.y ? pairgid[rg.x + t] : 0u;
   for (uint32_t base = rg.x; base < rg.y; base += kTilePix) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t p = base + t;
-    if (p < rg.y) {
+    if (t < kTilePix && p < rg.y) {
       const uint32_t gid = gid_next;
       const float4 g0 = geom[2 * (size_t)gid];
       const float4 g1 = geom[2 * (size_t)gid + 1];
@@ -130,69 +185,54 @@ __global__ void __launch_bounds__(kTilePix) k_blend_fwd(RenderConst rc, const Vi
       pmask[p] = m;  // reused by the backward
       if (p + kTilePix < rg.y) gid_next = pairgid[p + kTilePix];
     }
+    {
+      const uint64_t dm = __ballot(done);
+      if (!back && lane == 0) qdone[qd] = dm;
+    }
     __syncthreads();
     const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
-    if (__ballot(!done) == 0) continue;
-    // This wave's entries of the round (those that can reach one of its
-    // pixels), in list order, compacted into swl.
+    // the quarter's entries of the round (those that can reach one of its
+    // pixels), in list order, compacted into swl (the same list on both waves)
     int n = 0;
     for (int c64 = 0; c64 < cnt; c64 += 64) {
-      const bool mine = c64 + lane < cnt && ((smask[c64 + lane] >> wv) & 1u);
+      const bool mine = c64 + lane < cnt && ((smask[c64 + lane] >> qd) & 1u);
       const uint64_t bits = __ballot(mine);
       if (mine) swl[wv][n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u))] = (uint16_t)(c64 + lane);
       n += __builtin_popcountll(bits);
     }
-    if (n == 0) continue;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // Software pipeline over the list: the next entry's geometry is read at
-    // the start of an entry and its channels after the current ones have
-    // been accumulated, so both land while other work runs. Every lane runs
-    // predicated; the accumulation is skipped when no lane takes the entry.
-    int j = __builtin_amdgcn_readfirstlane(swl[wv][0]);
-    int jn = __builtin_amdgcn_readfirstlane(swl[wv][n > 1 ? 1 : 0]);
-    float4 g0 = sg[2 * j], g1 = sg[2 * j + 1];
-    float4 ch[CS4];
+    const int nf = n < kSplitMin ? n : (n + 1) / 2;
+    if (back) {
+      T = 1.f;
 #pragma unroll
-    for (int c4 = 0; c4 < CS4; ++c4) ch[c4] = sc[j * CS4 + c4];
-    for (int i = 0; i < n; ++i) {
-      const int jv = swl[wv][i + 2 < n ? i + 2 : n - 1];
-      const float4 n0 = sg[2 * jn], n1 = sg[2 * jn + 1];
-      float dx, dy;
-      const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
-      // alpha >= alpha_min  <=>  power >= ln(alpha_min / o) (record slot 6)
-      const bool take = !done && power <= 0.f && power >= g1.z;
-      if (__ballot(take)) {
-        const float alpha = fminf(amax, g1.y * __expf(power));
-        const float Tn = T * (1.f - alpha);
-        const bool stop = take && Tn < tmin;
-        if (take && !stop) {
-          const float w = alpha * T;
+      for (int c = 0; c < CS; ++c) acc[c] = 0.f;
+      last = 0u;
+      const bool skip = !inside || ((qdone[qd] >> lane) & 1u);
+      run(nf, n, base, !skip, false);
+      xch[qd][0][lane] = T;
 #pragma unroll
-          for (int c4 = 0; c4 < CS4; ++c4) {
-            acc[4 * c4 + 0] = fmaf(w, ch[c4].x, acc[4 * c4 + 0]);
-            acc[4 * c4 + 1] = fmaf(w, ch[c4].y, acc[4 * c4 + 1]);
-            acc[4 * c4 + 2] = fmaf(w, ch[c4].z, acc[4 * c4 + 2]);
-            acc[4 * c4 + 3] = fmaf(w, ch[c4].w, acc[4 * c4 + 3]);
-          }
-          T = Tn;
-          last = base - rg.x + (uint32_t)j + 1u;
-        }
-        if (__ballot(stop)) {
-          done = done || stop;
-          if (__ballot(!done) == 0) break;
-        }
-      }
-#pragma unroll
-      for (int c4 = 0; c4 < CS4; ++c4) ch[c4] = sc[jn * CS4 + c4];
-      j = jn;
-      g0 = n0;
-      g1 = n1;
-      jn = __builtin_amdgcn_readfirstlane(jv);
+      for (int c = 0; c < CS; ++c) xch[qd][1 + c][lane] = acc[c];
+      xch[qd][CS + 1][lane] = __uint_as_float(last);
+    } else if (__ballot(!done)) {
+      run(0, nf, base, !done, true);
     }
+    __syncthreads();
+    if (back || nf == n) continue;
+    // append the back half
+    const float Tb = xch[qd][0][lane];
+    const uint32_t lastb = __float_as_uint(xch[qd][CS + 1][lane]);
+    const bool fix = !done && T * Tb < tmin;
+    if (!done && !fix) {
+#pragma unroll
+      for (int c = 0; c < CS; ++c) acc[c] = fmaf(T, xch[qd][1 + c][lane], acc[c]);
+      T *= Tb;
+      if (lastb) last = lastb;
+    }
+    if (__ballot(fix)) run(nf, n, base, fix, true);
   }
-  if (!inside) return;
+  if (back || !inside) return;
   const size_t HW = (size_t)V.W * V.H;
   const size_t pix = (size_t)py * V.W + px;
   const size_t pb = (size_t)V.pix_base;
@@ -516,9 +556,9 @@ void launch_blend_forward(const RenderConst& rc, const CtxLayout& L, char* ctx, 
                           hipStream_t s) {
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
   if (rc.nf == 16)
-    hipLaunchKernelGGL(k_blend_fwd<16>, dim3(rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, out);
+    hipLaunchKernelGGL(k_blend_fwd<16>, dim3(rc.total_tiles), dim3(kFwdThreads), 0, s, rc, views, ctx, L, out);
   else
-    hipLaunchKernelGGL(k_blend_fwd<0>, dim3(rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, out);
+    hipLaunchKernelGGL(k_blend_fwd<0>, dim3(rc.total_tiles), dim3(kFwdThreads), 0, s, rc, views, ctx, L, out);
 }
 
 void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx, const asgs_images& dout,
