@@ -281,7 +281,24 @@ constexpr int kBwdBatch = 16;  // list entries per MFMA tile (M = 16)
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-ASGS_DEV f4v mfma4(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+ASGS_DEV f4v mfma_bf(const bf8v& a, const bf8v& b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// v = hi + lo with hi = bf16(v) and lo = bf16(v - hi), both rounded to nearest
+// even: |v - hi - lo| <= 2^-17 |v| for finite v. With exact bf16 products and
+// FP32 accumulation, a b ~ ah bh + ah bl + al bh to ~2^-15 relative.
+ASGS_DEV uint16_t bf_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+ASGS_DEV void bf_split(float v, uint16_t& hi, uint16_t& lo) {
+  hi = bf_rne(v);
+  lo = bf_rne(v - __uint_as_float((uint32_t)hi << 16));
+}
 
 // Backward compositing, one workgroup per tile, one pixel per thread.
 //
@@ -308,7 +325,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int CS4 = CS / 4;
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
-  constexpr int CP = 17;          // padded row of 16 coefficients
+  constexpr int CP = 64;          // row of 64 pixel coefficients (bf16), 8-pixel groups XOR-swizzled by row
   // two workgroups per tile: segment 1 takes the list from the forward's
   // split position of the first round to the end, segment 0 the part before
   // it (from the state the forward recorded there); unsplit tiles run whole
@@ -344,8 +361,11 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int kPer = (kRound * kRecF4 + kTilePix - 1) / kTilePix;
   constexpr int PS = GS;           // row of a partial-sum entry
   __shared__ float4 srec[kRound * kRecF4];
-  __shared__ float cw[NW][64 * CP];     // w of (pixel, entry), per wave
-  __shared__ float cp[NW][64 * CP];     // dL/dpower of (pixel, entry), per wave
+  // per wave, per batch position and pixel: w and dL/dpower as bf16 hi + lo
+  __shared__ __attribute__((aligned(16))) uint16_t awh[NW][kBwdBatch][CP];
+  __shared__ __attribute__((aligned(16))) uint16_t awl[NW][kBwdBatch][CP];
+  __shared__ __attribute__((aligned(16))) uint16_t aph[NW][kBwdBatch][CP];
+  __shared__ __attribute__((aligned(16))) uint16_t apl[NW][kBwdBatch][CP];
   __shared__ float part[NW][kRound][PS];  // per-wave partial rows of the round's entries
   __shared__ int sent[NW][kBwdBatch];     // round entry of each batch position
   __shared__ uint32_t sslot[kRound];      // gradient slot of each round entry
@@ -371,32 +391,46 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     const float ga = dout.alpha ? dout.alpha[pb + pix] : 0.f;
     GT = rc.bg[0] * G[0] + rc.bg[1] * G[1] + rc.bg[2] * G[2] - ga;
   }
-  // B operands of the MFMAs: K-step s covers pixels 4s..4s+3 of this wave;
-  // lane l supplies feature (l % 16) of pixel 4s + l / 16.
+  // B operands of the MFMAs (v_mfma_f32_16x16x32_bf16): K block kb covers
+  // pixels 32 kb .. 32 kb + 31 of this wave; lane l supplies feature l % 16 of
+  // pixels 32 kb + 8 (l / 16) + i, i = 0..7: the channel gradients split into
+  // bf16 hi + lo, the pixel-coordinate moments (small integers, exact).
   const int fcol = lane & 15;
-  float bG0[16], bG1[16], bM[16];
+  bf8v bG0h[2], bG0l[2], bG1h[2], bG1l[2], bM[2];
 #pragma unroll
-  for (int s4 = 0; s4 < 16; ++s4) {
-    const int q = 64 * wv + 4 * s4 + (lane >> 4);  // pixel of thread q
-    const int lx = tile_lx(q), ly = tile_ly(q);
-    const int gx = x0 + lx, gy = y0 + ly;
-    const bool in = gx < V.W && gy < V.H;
-    const size_t pix = (size_t)gy * V.W + gx;
-    float g0 = 0.f, g1 = 0.f;
-    if (in) {
-      const int c0 = fcol;
-      if (c0 < CS) {
-        g0 = c0 < 3 ? dout.rgb[3 * pb + c0 * HW + pix]
-                    : (c0 == 3 ? dout.depth[pb + pix] : dout.feat[NF * pb + (c0 - 4) * HW + pix]);
+  for (int kb = 0; kb < 2; ++kb) {
+    uint16_t h0[8], l0[8], h1[8], l1[8], m[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = 64 * wv + 32 * kb + 8 * (lane >> 4) + i;  // pixel of thread q
+      const int lx = tile_lx(q), ly = tile_ly(q);
+      const int gx = x0 + lx, gy = y0 + ly;
+      const bool in = gx < V.W && gy < V.H;
+      const size_t pix = (size_t)gy * V.W + gx;
+      float g0 = 0.f, g1 = 0.f;
+      if (in) {
+        const int c0 = fcol;
+        if (c0 < CS) {
+          g0 = c0 < 3 ? dout.rgb[3 * pb + c0 * HW + pix]
+                      : (c0 == 3 ? dout.depth[pb + pix] : dout.feat[NF * pb + (c0 - 4) * HW + pix]);
+        }
+        const int c1 = 16 + fcol;
+        if (c1 < CS) g1 = dout.feat[NF * pb + (c1 - 4) * HW + pix];
       }
-      const int c1 = 16 + fcol;
-      if (c1 < CS) g1 = dout.feat[NF * pb + (c1 - 4) * HW + pix];
+      bf_split(g0, h0[i], l0[i]);
+      bf_split(g1, h1[i], l1[i]);
+      const float fx = (float)lx, fy = (float)ly;
+      m[i] = bf_rne(fcol == 0 ? 1.f : fcol == 1 ? fx : fcol == 2 ? fy : fcol == 3 ? fx * fx
+                    : fcol == 4 ? fx * fy : fcol == 5 ? fy * fy : 0.f);
     }
-    bG0[s4] = g0;
-    bG1[s4] = g1;
-    const float fx = (float)lx, fy = (float)ly;
-    bM[s4] = fcol == 0 ? 1.f : fcol == 1 ? fx : fcol == 2 ? fy : fcol == 3 ? fx * fx
-             : fcol == 4 ? fx * fy : fcol == 5 ? fy * fy : 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      bG0h[kb][i] = __builtin_bit_cast(__bf16, h0[i]);
+      bG0l[kb][i] = __builtin_bit_cast(__bf16, l0[i]);
+      bG1h[kb][i] = __builtin_bit_cast(__bf16, h1[i]);
+      bG1l[kb][i] = __builtin_bit_cast(__bf16, l1[i]);
+      bM[kb][i] = __builtin_bit_cast(__bf16, m[i]);
+    }
   }
 
   if (t == 0) smax = 0u;
@@ -427,8 +461,6 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     for (int c = 0; c < CS; ++c) sacc = fmaf(G[c], ck[(size_t)(1 + c) * P + pb + pix], sacc);
   }
   const float amax = rc.alpha_max;
-  float* mycw = &cw[wv][lane * CP];
-  float* mycp = &cp[wv][lane * CP];
   // Records are staged in rounds of kRound entries, walking the list from the
   // back; the global loads of the next round are issued before the current
   // round is processed and land in LDS at the start of the next round.
@@ -467,16 +499,24 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     f4v c1 = {0.f, 0.f, 0.f, 0.f}, c2 = c1, c3 = c1;
-    const float* acw = &cw[wv][0];
-    const float* acp = &cp[wv][0];
+    // A operands: batch position l % 16, pixels 32 kb + 8 (l / 16) .. + 7
 #pragma unroll
-    for (int s4 = 0; s4 < 16; ++s4) {
-      const int q = 4 * s4 + (lane >> 4);
-      const float aw = acw[q * CP + fcol];
-      const float ap = acp[q * CP + fcol];
-      c1 = mfma4(aw, bG0[s4], c1);
-      if (CS > 16) c2 = mfma4(aw, bG1[s4], c2);
-      c3 = mfma4(ap, bM[s4], c3);
+    for (int kb = 0; kb < 2; ++kb) {
+      const int p0 = (32 * kb + 8 * (lane >> 4)) ^ ((fcol & 7) << 3);
+      const bf8v wh = *reinterpret_cast<const bf8v*>(&awh[wv][fcol][p0]);
+      const bf8v wl = *reinterpret_cast<const bf8v*>(&awl[wv][fcol][p0]);
+      const bf8v ph = *reinterpret_cast<const bf8v*>(&aph[wv][fcol][p0]);
+      const bf8v pl = *reinterpret_cast<const bf8v*>(&apl[wv][fcol][p0]);
+      c1 = mfma_bf(wh, bG0h[kb], c1);
+      c1 = mfma_bf(wh, bG0l[kb], c1);
+      c1 = mfma_bf(wl, bG0h[kb], c1);
+      if (CS > 16) {
+        c2 = mfma_bf(wh, bG1h[kb], c2);
+        c2 = mfma_bf(wh, bG1l[kb], c2);
+        c2 = mfma_bf(wl, bG1h[kb], c2);
+      }
+      c3 = mfma_bf(ph, bM[kb], c3);
+      c3 = mfma_bf(pl, bM[kb], c3);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -560,8 +600,14 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
         sacc = fmaf(w_, dotg, sacc);
         dpow = raw < amax ? dalpha * alpha : 0.f;
       }
-      mycw[nb] = wgt;
-      mycp[nb] = dpow;
+      uint16_t hi, lo;
+      const int sp = lane ^ ((nb & 7) << 3);  // swizzled position of this pixel in row nb
+      bf_split(wgt, hi, lo);
+      awh[wv][nb][sp] = hi;
+      awl[wv][nb][sp] = lo;
+      bf_split(dpow, hi, lo);
+      aph[wv][nb][sp] = hi;
+      apl[wv][nb][sp] = lo;
       if (lane == 0) sent[wv][nb] = j;
       if (++nb == kBwdBatch) {
         flush(nb);
