@@ -262,11 +262,9 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.pmask = take((size_t)capc);
   L.ranges = take((size_t)total_tiles * 8);
   L.torder = take((size_t)total_tiles * 4);
-  L.cksplit = take((size_t)total_tiles * 4);
   L.hist = take((size_t)kRadixBins * (L.nblk_hist + 1) * 4);  // histograms + digit totals
   L.tfinal = take((size_t)total_pix * 4);
   L.ncontrib = take((size_t)total_pix * 4);
-  L.ckstate = take((size_t)(L.cs + 1) * total_pix * 4);
   L.gslot = take((size_t)capc * L.gs * sizeof(float));
   L.posepart = take((size_t)n_views * L.pose_blocks * 6 * sizeof(float));
   L.total = o;

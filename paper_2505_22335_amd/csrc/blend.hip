@@ -132,10 +132,6 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   for (int c = 0; c < CS; ++c) acc[c] = 0.f;
   uint32_t last = 0;
   bool done = back || !inside;  // back lanes keep no running state
-  bool split0 = false;          // the first round was split (state at its split below)
-  float Tm = 1.f, accm[CS];
-#pragma unroll
-  for (int c = 0; c < CS; ++c) accm[c] = 0.f;
   const float amax = rc.alpha_max, tmin = rc.T_min;
   // Composite list positions [i0, i1) of this wave's round list. real: the
   // running state with the T_min stop; otherwise a local back-half state.
@@ -196,23 +192,18 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
     __syncthreads();
     const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
     // the quarter's entries of the round (those that can reach one of its
-    // pixels), in list order, compacted into swl (the same list on both
-    // waves); the front wave takes those in the first half of the round's
-    // positions, the back wave the rest
-    const int msplit = cnt >= 2 * kSplitMin ? cnt / 2 : cnt;
-    int n = 0, nf = 0;
+    // pixels), in list order, compacted into swl (the same list on both waves)
+    int n = 0;
     for (int c64 = 0; c64 < cnt; c64 += 64) {
       const bool mine = c64 + lane < cnt && ((smask[c64 + lane] >> qd) & 1u);
       const uint64_t bits = __ballot(mine);
       if (mine) swl[wv][n + __builtin_amdgcn_mbcnt_hi((uint32_t)(bits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bits, 0u))] = (uint16_t)(c64 + lane);
-      const int below = msplit - c64;
-      const uint64_t fm = below >= 64 ? ~0ull : (below <= 0 ? 0ull : ((1ull << below) - 1ull));
       n += __builtin_popcountll(bits);
-      nf += __builtin_popcountll(bits & fm);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nf = n < kSplitMin ? n : (n + 1) / 2;
     if (back) {
       T = 1.f;
 #pragma unroll
@@ -227,15 +218,8 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
     } else if (__ballot(!done)) {
       run(0, nf, base, !done, true);
     }
-    if (base == rg.x && msplit < cnt) {
-      // the state at the first round's split position, for the backward
-      split0 = true;
-      Tm = T;
-#pragma unroll
-      for (int c = 0; c < CS; ++c) accm[c] = acc[c];
-    }
     __syncthreads();
-    if (back || msplit == cnt) continue;
+    if (back || nf == n) continue;
     // append the back half
     const float Tb = xch[qd][0][lane];
     const uint32_t lastb = __float_as_uint(xch[qd][CS + 1][lane]);
@@ -248,22 +232,10 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
     }
     if (__ballot(fix)) run(nf, n, base, fix, true);
   }
-  if (t == 0) {
-    const uint32_t cnt0 = min((uint32_t)kTilePix, rg.y - rg.x);
-    ctx_ptr<uint32_t>(ctx, L.cksplit)[tile] = cnt0 >= 2 * kSplitMin ? cnt0 / 2 : 0u;
-  }
   if (back || !inside) return;
   const size_t HW = (size_t)V.W * V.H;
   const size_t pix = (size_t)py * V.W + px;
   const size_t pb = (size_t)V.pix_base;
-  if (split0) {
-    // T before the split position and the channels composited after it
-    float* ck = ctx_ptr<float>(ctx, L.ckstate);
-    const size_t P = (size_t)rc.total_pix;
-    ck[pb + pix] = Tm;
-#pragma unroll
-    for (int c = 0; c < CS; ++c) ck[(size_t)(1 + c) * P + pb + pix] = acc[c] - accm[c];
-  }
   out.rgb[3 * pb + 0 * HW + pix] = acc[0] + T * rc.bg[0];
   out.rgb[3 * pb + 1 * HW + pix] = acc[1] + T * rc.bg[1];
   out.rgb[3 * pb + 2 * HW + pix] = acc[2] + T * rc.bg[2];
@@ -315,9 +287,9 @@ ASGS_DEV void bf_split(float v, uint16_t& hi, uint16_t& lo) {
 // back. Each wave takes only the round's entries that one of its pixels uses
 // (the quarter test of the forward, then a ballot), writes its pixels'
 // coefficients for batches of up to 16 such entries to LDS and contracts them
-// on the matrix cores (16x16x4 FP32 MFMA, K = pixels) into per-wave partial
-// rows; the four waves' rows are summed in a fixed order and written once to
-// each entry's gradient slot.
+// on the matrix cores (bf16 16x16x32 MFMAs with both operands split into
+// hi + lo parts, K = pixels) into per-wave partial rows; the four waves' rows
+// are summed in a fixed order and written once to each entry's gradient slot.
 template <int NF>
 __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3))) k_blend_bwd(RenderConst rc, const ViewDev* __restrict__ views,
                                                         char* ctx, CtxLayout L, asgs_images dout) {
@@ -326,14 +298,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
   constexpr int CP = 64;          // row of 64 pixel coefficients (bf16), 8-pixel groups XOR-swizzled by row
-  // two workgroups per tile: segment 1 takes the list from the forward's
-  // split position of the first round to the end, segment 0 the part before
-  // it (from the state the forward recorded there); unsplit tiles run whole
-  // on segment 1
-  const int tile = (int)ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x >> 1];  // longest lists first
-  const bool seg_back = (blockIdx.x & 1) != 0;
-  const uint32_t msplit = ctx_ptr<const uint32_t>(ctx, L.cksplit)[tile];
-  if (!seg_back && msplit == 0u) return;
+  const int tile = (int)ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];  // longest lists first
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
   const int lt = tile - V.tile_base;
@@ -439,27 +404,13 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   __syncthreads();
   const uint32_t nproc = smax;
   // entries behind every pixel's last Gaussian get zero gradient
-  if (seg_back) {
-    for (uint32_t q = nproc + t; q < len; q += kTilePix) {
-      float* dst = gslot + (size_t)pslot[rg.x + q] * GS;
+  for (uint32_t q = nproc + t; q < len; q += kTilePix) {
+    float* dst = gslot + (size_t)pslot[rg.x + q] * GS;
 #pragma unroll
-      for (int c = 0; c < GS; ++c) dst[c] = 0.f;
-    }
+    for (int c = 0; c < GS; ++c) dst[c] = 0.f;
   }
-  // this segment's list positions [seg_lo, seg_hi)
-  const int seg_lo = seg_back ? (int)msplit : 0;
-  const int seg_hi = seg_back ? (int)nproc : (int)min(msplit, nproc);
   float T = Tf;
   float sacc = 0.f;  // sum over later Gaussians of w_l (G . c_l)
-  if (!seg_back && inside) {
-    // the forward's state at the split: T there and the channels composited after it
-    const float* ck = ctx_ptr<const float>(ctx, L.ckstate);
-    const size_t P = (size_t)rc.total_pix;
-    const size_t pix = (size_t)py * V.W + px;
-    T = ck[pb + pix];
-#pragma unroll
-    for (int c = 0; c < CS; ++c) sacc = fmaf(G[c], ck[(size_t)(1 + c) * P + pb + pix], sacc);
-  }
   const float amax = rc.alpha_max;
   // Records are staged in rounds of kRound entries, walking the list from the
   // back; the global loads of the next round are issued before the current
@@ -533,15 +484,15 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  int rhi = seg_hi;
-  int rlo = rhi - kRound > seg_lo ? rhi - kRound : seg_lo;
-  if (rhi > seg_lo) {
+  int rhi = (int)nproc;
+  int rlo = rhi - kRound > 0 ? rhi - kRound : 0;
+  if (rhi > 0) {
     fetch_gid(rlo, rhi - rlo);
     fetch(rlo, rhi - rlo);
-    const int nrlo = rlo - kRound > seg_lo ? rlo - kRound : seg_lo;
-    if (rlo > seg_lo) fetch_gid(nrlo, rlo - nrlo);
+    const int nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
+    if (rlo > 0) fetch_gid(nrlo, rlo - nrlo);
   }
-  while (rhi > seg_lo) {
+  while (rhi > 0) {
     __syncthreads();  // every reader of the previous round is done
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -555,11 +506,11 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     for (int q = lane; q < kRound * PS; q += 64) (&part[wv][0][0])[q] = 0.f;
     __syncthreads();
     const int cnt = rhi - rlo;
-    const int nrhi = rlo, nrlo = rlo - kRound > seg_lo ? rlo - kRound : seg_lo;
-    if (nrhi > seg_lo) {
+    const int nrhi = rlo, nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
+    if (nrhi > 0) {
       fetch(nrlo, nrhi - nrlo);
-      const int n2lo = nrlo - kRound > seg_lo ? nrlo - kRound : seg_lo;
-      if (nrlo > seg_lo) fetch_gid(n2lo, nrlo - n2lo);
+      const int n2lo = nrlo - kRound > 0 ? nrlo - kRound : 0;
+      if (nrlo > 0) fetch_gid(n2lo, nrlo - n2lo);
     }
     // entries of the round that can reach a pixel of this wave's quarter
     const bool mine = lane < cnt && ((smk[lane] >> wv) & 1u);
@@ -660,9 +611,9 @@ void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx,
                            hipStream_t s) {
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
   if (rc.nf == 16)
-    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(2 * rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, dout);
+    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, dout);
   else
-    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(2 * rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, dout);
+    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, dout);
 }
 
 }  // namespace asgs

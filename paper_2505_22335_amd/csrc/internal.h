@@ -67,8 +67,8 @@ enum Counter { kCntDepth0 = 0, kCntScan = 4, kCntTile0 = 5, kCntPose = 9 };
 // Byte layout of a render context; every array 256-byte aligned.
 struct CtxLayout {
   size_t hdr, views, geom, chan, rect, ntiles, rank, dkey0, dkeyA, dvalA, dkeyB, dvalB,
-      toff, bsum, pkeyA, pvalA, pkeyB, pvalB, dupgid, pairgid, pmask, ranges, torder, cksplit, hist, tfinal,
-      ncontrib, ckstate, gslot, posepart, pkey_fin, pval_fin;
+      toff, bsum, pkeyA, pvalA, pkeyB, pvalB, dupgid, pairgid, pmask, ranges, torder, hist, tfinal, ncontrib,
+      gslot, posepart, pkey_fin, pval_fin;
   size_t total;
   int64_t nv, cap;
   int32_t total_tiles, total_pix, cs, gs, nblk_hist, tile_passes, pose_blocks;
