@@ -214,7 +214,7 @@ int run_front(const Prep& P, const asgs_gaussians* g, char* ctx, hipStream_t s) 
 }  // namespace
 
 int chan_stride(int nf) { return 4 + nf; }
-int gslot_stride(int nf) { return 6 + 4 + nf; }
+int gslot_stride(int nf) { return (6 + 4 + nf + 3) & ~3; }  // padded to whole float4
 
 CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int nf, int64_t cap) {
   CtxLayout L;

@@ -324,14 +324,14 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int kRecF4 = 2 + CS4;  // float4 per list entry: geometry (2) + channels
   constexpr int kRound = 32;       // list entries staged per round (one per lane of half a wave)
   constexpr int kPer = (kRound * kRecF4 + kTilePix - 1) / kTilePix;
-  constexpr int PS = GS;           // row of a partial-sum entry
+  constexpr int PS = (GS + 3) & ~3;  // row of a partial-sum entry and of a gradient slot (whole float4)
   __shared__ float4 srec[kRound * kRecF4];
   // per wave, per batch position and pixel: w and dL/dpower as bf16 hi + lo
   __shared__ __attribute__((aligned(16))) uint16_t awh[NW][kBwdBatch][CP];
   __shared__ __attribute__((aligned(16))) uint16_t awl[NW][kBwdBatch][CP];
   __shared__ __attribute__((aligned(16))) uint16_t aph[NW][kBwdBatch][CP];
   __shared__ __attribute__((aligned(16))) uint16_t apl[NW][kBwdBatch][CP];
-  __shared__ float part[NW][kRound][PS];  // per-wave partial rows of the round's entries
+  __shared__ __attribute__((aligned(16))) float part[NW][kRound][PS];  // per-wave partial rows of the round's entries
   __shared__ int sent[NW][kBwdBatch];     // round entry of each batch position
   __shared__ uint32_t sslot[kRound];      // gradient slot of each round entry
   __shared__ uint8_t smk[kRound];         // quarter mask of each round entry (from the forward)
@@ -405,9 +405,9 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   const uint32_t nproc = smax;
   // entries behind every pixel's last Gaussian get zero gradient
   for (uint32_t q = nproc + t; q < len; q += kTilePix) {
-    float* dst = gslot + (size_t)pslot[rg.x + q] * GS;
+    float4* dst = reinterpret_cast<float4*>(gslot + (size_t)pslot[rg.x + q] * PS);
 #pragma unroll
-    for (int c = 0; c < GS; ++c) dst[c] = 0.f;
+    for (int c = 0; c < PS / 4; ++c) dst[c] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   float T = Tf;
   float sacc = 0.f;  // sum over later Gaussians of w_l (G . c_l)
@@ -442,6 +442,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
       stage_mask = pmask[rg.x + lo_r + t];
     }
   };
+  auto rec_of = [&](int e) { return &srec[e * kRecF4]; };
   // Contract the wave's nb batched entries over its 64 pixels on the matrix
   // cores and store the rows of the partial sums under their round entries.
   auto flush = [&](int nb) {
@@ -477,6 +478,45 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
         if (fcol < CS) row[6 + fcol] = c1[r];
         if (CS > 16 && fcol < CS - 16) row[6 + 16 + fcol] = c2[r];
         if (fcol < 6) row[fcol] = c3[r];
+      }
+    }
+    // the conic, position and opacity parts of the wave's rows in closed form
+    // from its moment sums (linear in them, so the four waves' rows still add
+    // up): all moments are read before any is overwritten
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float cf[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = lane + 64 * k;
+      cf[k] = 0.f;
+      if (it < nb * 6) {
+        const int pos = it / 6, c = it - pos * 6;
+        const int e = sent[wv][pos];
+        const float* M = part[wv][e];
+        const float4 g0 = rec_of(e)[0];
+        const float4 g1 = rec_of(e)[1];
+        const float uu = g0.x - (float)x0, vv = g0.y - (float)y0;  // tile-local centre
+        const float Sdx = uu * M[0] - M[1];
+        const float Sdy = vv * M[0] - M[2];
+        if (c == 0) cf[k] = -(g0.z * Sdx + g0.w * Sdy);
+        else if (c == 1) cf[k] = -(g0.w * Sdx + g1.x * Sdy);
+        else if (c == 2) cf[k] = -0.5f * (uu * uu * M[0] - 2.f * uu * M[1] + M[3]);
+        else if (c == 3) cf[k] = -(uu * vv * M[0] - uu * M[2] - vv * M[1] + M[4]);
+        else if (c == 4) cf[k] = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
+        else cf[k] = M[0] / g1.y;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int it = lane + 64 * k;
+      if (it < nb * 6) {
+        const int pos = it / 6, c = it - pos * 6;
+        part[wv][sent[wv][pos]][c] = cf[k];
       }
     }
     // the next batch overwrites the coefficients and the entry table
@@ -567,29 +607,17 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     }
     if (nb > 0) flush(nb);
     __syncthreads();
-    // partial sums of the four waves -> one gradient slot per entry
-    for (int q = t; q < cnt * GS; q += kTilePix) {
-      const int e = q / GS, c = q - e * GS;
-      float val;
-      if (c >= 6) {
-        val = (part[0][e][c] + part[1][e][c]) + (part[2][e][c] + part[3][e][c]);
-      } else {
-        float M[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) M[m] = (part[0][e][m] + part[1][e][m]) + (part[2][e][m] + part[3][e][m]);
-        const float4 g0 = srec[e * kRecF4];
-        const float4 g1 = srec[e * kRecF4 + 1];
-        const float uu = g0.x - (float)x0, vv = g0.y - (float)y0;  // tile-local centre
-        const float Sdx = uu * M[0] - M[1];
-        const float Sdy = vv * M[0] - M[2];
-        if (c == 0) val = -(g0.z * Sdx + g0.w * Sdy);
-        else if (c == 1) val = -(g0.w * Sdx + g1.x * Sdy);
-        else if (c == 2) val = -0.5f * (uu * uu * M[0] - 2.f * uu * M[1] + M[3]);
-        else if (c == 3) val = -(uu * vv * M[0] - uu * M[2] - vv * M[1] + M[4]);
-        else if (c == 4) val = -0.5f * (vv * vv * M[0] - 2.f * vv * M[2] + M[5]);
-        else val = M[0] / g1.y;
-      }
-      gslot[(size_t)sslot[e] * GS + c] = val;
+    // the four waves' rows -> one gradient slot per entry, a float4 per thread
+    constexpr int F4 = PS / 4;
+    for (int q = t; q < cnt * F4; q += kTilePix) {
+      const int e = q / F4, f = q - e * F4;
+      const float4 a = reinterpret_cast<const float4*>(part[0][e])[f];
+      const float4 b = reinterpret_cast<const float4*>(part[1][e])[f];
+      const float4 c = reinterpret_cast<const float4*>(part[2][e])[f];
+      const float4 d = reinterpret_cast<const float4*>(part[3][e])[f];
+      reinterpret_cast<float4*>(gslot + (size_t)sslot[e] * PS)[f] =
+          make_float4((a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y), (a.z + b.z) + (c.z + d.z),
+                      (a.w + b.w) + (c.w + d.w));
     }
     rhi = nrhi;
     rlo = nrlo;

@@ -75,7 +75,7 @@ struct CtxLayout {
 };
 
 int chan_stride(int nf);   // floats per channel record: rgb, depth, feat
-int gslot_stride(int nf);  // floats per per-pair gradient slot
+int gslot_stride(int nf);  // floats per per-pair gradient slot (6 + 4 + nf, padded to whole float4)
 CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int nf, int64_t cap);
 
 // ---------------------------------------------------------------------------

@@ -246,11 +246,18 @@ __global__ void __launch_bounds__(256) k_project_backward(RenderConst rc, asgs_g
       float G[GS];
 #pragma unroll
       for (int k = 0; k < GS; ++k) G[k] = 0.f;
+      constexpr int GSP = (GS + 3) & ~3;  // slot stride (whole float4)
       const uint64_t end = min((uint64_t)start + cnt, (uint64_t)rc.cap);
       for (uint64_t p = start; p < end; ++p) {
-        const float* sp = slot + p * GS;
+        const float4* sp = reinterpret_cast<const float4*>(slot + p * GSP);
 #pragma unroll
-        for (int k = 0; k < GS; ++k) G[k] += sp[k];
+        for (int k4 = 0; k4 < GSP / 4; ++k4) {
+          const float4 v = sp[k4];
+          if (4 * k4 + 0 < GS) G[4 * k4 + 0] += v.x;
+          if (4 * k4 + 1 < GS) G[4 * k4 + 1] += v.y;
+          if (4 * k4 + 2 < GS) G[4 * k4 + 2] += v.z;
+          if (4 * k4 + 3 < GS) G[4 * k4 + 3] += v.w;
+        }
       }
       const float du = G[0], dv = G[1], dA = G[2], dB = G[3], dC = G[4];
       dop[i] = G[5];
