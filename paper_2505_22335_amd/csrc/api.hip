@@ -198,17 +198,17 @@ int check_ctx(const Prep& P, const void* ctx, size_t ctx_bytes) {
 // Projection, depth sort and intersection count (shared by count and forward).
 int run_front(const Prep& P, const asgs_gaussians* g, char* ctx, hipStream_t s) {
   launch_set_views(P.views, P.rc.n_views, reinterpret_cast<ViewDev*>(ctx + P.L.views),
-                   reinterpret_cast<CtxHeader*>(ctx + P.L.hdr), s);
+                   reinterpret_cast<CtxHeader*>(ctx + P.L.hdr), reinterpret_cast<uint32_t*>(ctx + P.L.tcur),
+                   P.rc.total_tiles, s);
   {
     ProfScope ps(ASGS_K_PROJECT, s);
     launch_project(P.rc, *g, P.L, ctx, s);
   }
   {
     ProfScope ps(ASGS_K_SORT, s);
-    launch_depth_sort(P.rc, P.L, ctx, s);
-    launch_duplicate(P.rc, P.L, ctx, s);
+    launch_bin(P.rc, P.L, ctx, s);
   }
-  return check_launch("projection/sort launch");
+  return check_launch("projection/binning launch");
 }
 
 }  // namespace
@@ -227,11 +227,6 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.total_pix = total_pix;
   L.cs = chan_stride(nf);
   L.gs = gslot_stride(nf);
-  const int64_t maxitems = nv > capc ? nv : capc;
-  L.nblk_hist = (int32_t)((maxitems + kSortItems - 1) / kSortItems);
-  int passes = 1;
-  while (passes < 4 && ((int64_t)1 << (8 * passes)) < total_tiles) ++passes;
-  L.tile_passes = passes;
   L.pose_blocks = (int32_t)((n + 255) / 256);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -245,32 +240,24 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.chan = take((size_t)nv * L.cs * sizeof(float));
   L.rect = take((size_t)nv * 8);
   L.ntiles = take((size_t)nv * 4);
-  L.rank = take((size_t)nv * 4);
-  L.dkey0 = take((size_t)nv * 4);
-  L.dkeyA = take((size_t)nv * 4);
-  L.dvalA = take((size_t)nv * 4);
-  L.dkeyB = take((size_t)nv * 4);
-  L.dvalB = take((size_t)nv * 4);
-  L.toff = take((size_t)(nv + 1) * 4);
-  L.bsum = take((size_t)((nv + kScanItems - 1) / kScanItems + 1) * 4);
-  L.pkeyA = take((size_t)capc * 4);
-  L.pvalA = take((size_t)capc * 4);
-  L.pkeyB = take((size_t)capc * 4);
-  L.pvalB = take((size_t)capc * 4);
-  L.dupgid = take((size_t)capc * 4);
+  L.dkey = take((size_t)nv * 4);
+  L.toff = take((size_t)nv * 4);
+  L.bsum = take((size_t)scan_blocks(n, n_views) * 4);
+  L.vsum = take((size_t)scan_blocks(n, n_views) * 4);
+  L.tcur = take((size_t)total_tiles * 4);
+  L.ukey = take((size_t)capc * 8);
+  L.tkey = take((size_t)capc * 8);
   L.pairgid = take((size_t)capc * 4);
+  L.pslot = take((size_t)capc * 4);
+  L.ptile = take((size_t)capc * 4);
   L.pmask = take((size_t)capc);
   L.ranges = take((size_t)total_tiles * 8);
   L.torder = take((size_t)total_tiles * 4);
-  L.hist = take((size_t)kRadixBins * (L.nblk_hist + 1) * 4);  // histograms + digit totals
   L.tfinal = take((size_t)total_pix * 4);
   L.ncontrib = take((size_t)total_pix * 4);
   L.gslot = take((size_t)capc * L.gs * sizeof(float));
   L.posepart = take((size_t)n_views * L.pose_blocks * 6 * sizeof(float));
   L.total = o;
-  const bool odd = (L.tile_passes % 2) == 1;
-  L.pkey_fin = odd ? L.pkeyB : L.pkeyA;
-  L.pval_fin = odd ? L.pvalB : L.pvalA;
   return L;
 }
 
@@ -453,7 +440,7 @@ int asgs_ctx_array(const asgs_camera* cams, int32_t n_views, int64_t n_gauss, co
   if (L.total > ctx_bytes) return fail(ASGS_E_WORKSPACE, "ctx too small");
   char* c = static_cast<char*>(ctx);
   switch (which) {
-    case ASGS_CTX_PAIR_TILE: *ptr = c + L.pkey_fin; *count = lo; break;
+    case ASGS_CTX_PAIR_TILE: *ptr = c + L.ptile; *count = lo; break;
     case ASGS_CTX_PAIR_GAUSS: *ptr = c + L.pairgid; *count = lo; break;
     case ASGS_CTX_TILE_RANGE: *ptr = c + L.ranges; *count = L.total_tiles; break;
     case ASGS_CTX_RECT: *ptr = c + L.rect; *count = L.nv; break;

@@ -20,13 +20,6 @@ namespace asgs {
 
 namespace {
 
-ASGS_DEV int find_view(const ViewDev* views, int n_views, int tile) {
-  int v = 0;
-  for (int k = 1; k < n_views; ++k)
-    if (tile >= views[k].tile_base) v = k;
-  return v;
-}
-
 // Pixel of thread t: wave w covers the 8x8 quarter (w & 1, w >> 1) of the
 // tile, lane l the pixel (l & 7, l >> 3) inside it. Square quarters keep the
 // per-wave culling below tight.
@@ -315,7 +308,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   prioritise(rg.y - rg.x);
   const uint32_t len = rg.y - rg.x;
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
-  const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pval_fin);
+  const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pslot);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
   const uint8_t* pmask = ctx_ptr<const uint8_t>(ctx, L.pmask);

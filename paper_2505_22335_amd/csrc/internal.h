@@ -12,15 +12,10 @@ namespace asgs {
 constexpr int kTile = 16;            // screen tile side (pixels)
 constexpr int kTilePix = kTile * kTile;
 constexpr int kGeomStride = 8;       // floats per 2D geometry record: u v A B | C o - -
-constexpr int kRadixBits = 8;
-constexpr int kRadixBins = 1 << kRadixBits;
-constexpr int kSortThreads = 256;
-constexpr int kSortIPT = 4;          // items per thread per radix block
-constexpr int kSortItems = kSortThreads * kSortIPT;
-constexpr int kScanThreads = 256;
-constexpr int kScanIPT = 1;   // one visible Gaussian per thread: enough blocks to fill the GPU
-constexpr int kScanItems = kScanThreads * kScanIPT;
-constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;
+constexpr int kScanThreads = 256;    // (view, Gaussian) pairs per binning block, all of one view
+
+// Binning blocks: ceil(n / kScanThreads) per view, in (view, Gaussian) order.
+__host__ __device__ inline int64_t scan_blocks(int64_t n, int n_views) { return (n + kScanThreads - 1) / kScanThreads * n_views; }
 
 // Device view table entry (128 bytes).
 struct ViewDev {
@@ -62,16 +57,18 @@ struct CtxHeader {
   uint32_t pad[31];
 };
 
-enum Counter { kCntDepth0 = 0, kCntScan = 4, kCntTile0 = 5, kCntPose = 9 };
-
 // Byte layout of a render context; every array 256-byte aligned.
+//  ntiles, dkey, toff  per (view, Gaussian): tile count, depth bits, first gradient slot
+//  bsum, vsum          per scan block: tile-count sum, visible count
+//  tcur                per tile: intersection count, then the emission cursor
+//  ukey, tkey          per intersection: (depth << 32 | gid) in emission order; merge scratch
+//  pairgid, pslot, ptile  per sorted intersection: Gaussian, gradient slot, tile key
 struct CtxLayout {
-  size_t hdr, views, geom, chan, rect, ntiles, rank, dkey0, dkeyA, dvalA, dkeyB, dvalB,
-      toff, bsum, pkeyA, pvalA, pkeyB, pvalB, dupgid, pairgid, pmask, ranges, torder, hist, tfinal, ncontrib,
-      gslot, posepart, pkey_fin, pval_fin;
+  size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, tcur, ukey, tkey, pairgid, pslot,
+      ptile, pmask, ranges, torder, tfinal, ncontrib, gslot, posepart;
   size_t total;
   int64_t nv, cap;
-  int32_t total_tiles, total_pix, cs, gs, nblk_hist, tile_passes, pose_blocks;
+  int32_t total_tiles, total_pix, cs, gs, pose_blocks;
 };
 
 int chan_stride(int nf);   // floats per channel record: rgb, depth, feat
@@ -82,11 +79,10 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
 // Kernel launchers (each defined next to its kernels). All asynchronous.
 // ---------------------------------------------------------------------------
 void launch_set_views(const ViewDev* host_views, int n_views, ViewDev* dev_views,
-                      CtxHeader* hdr, hipStream_t s);
+                      CtxHeader* hdr, uint32_t* tcount, int total_tiles, hipStream_t s);
 void launch_project(const RenderConst& rc, const asgs_gaussians& g, const CtxLayout& L,
                     char* ctx, hipStream_t s);
-void launch_depth_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
-void launch_duplicate(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
+void launch_bin(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
 void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
 void launch_blend_forward(const RenderConst& rc, const CtxLayout& L, char* ctx,
                           const asgs_images& out, hipStream_t s);
@@ -143,6 +139,14 @@ namespace asgs {
 
 template <typename T>
 ASGS_DEV T* ctx_ptr(char* ctx, size_t off) { return reinterpret_cast<T*>(ctx + off); }
+
+// View of a global tile key (views are stored in tile_base order).
+ASGS_DEV int find_view(const ViewDev* views, int n_views, int tile) {
+  int v = 0;
+  for (int k = 1; k < n_views; ++k)
+    if (tile >= views[k].tile_base) v = k;
+  return v;
+}
 
 // Alpha of a Gaussian at a pixel. The same instruction sequence is used by
 // the forward and the backward so both take identical skip/stop decisions.

@@ -18,8 +18,14 @@ struct ViewChunk {
   int32_t first, count;
 };
 
-__global__ void k_set_views(ViewChunk chunk, ViewDev* views, CtxHeader* hdr) {
+// Writes one chunk of the view table; the first chunk also resets the header
+// and the per-tile intersection counters.
+__global__ void k_set_views(ViewChunk chunk, ViewDev* views, CtxHeader* hdr, uint32_t* tcount,
+                            int total_tiles) {
   const int i = threadIdx.x;
+  if (chunk.first == 0)
+    for (int t = blockIdx.x * blockDim.x + i; t < total_tiles; t += gridDim.x * blockDim.x) tcount[t] = 0u;
+  if (blockIdx.x != 0) return;
   if (i < chunk.count) views[chunk.first + i] = chunk.v[i];
   if (chunk.first == 0 && i == 0) {
     hdr->n_isect = 0;
@@ -132,13 +138,6 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
   constexpr int CS = 4 + NF;
   const int view = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // clear the tile ranges of this forward (read by the blend kernels)
-  {
-    const int64_t lin = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * gridDim.y * blockDim.x;
-    uint2* ranges = ctx_ptr<uint2>(ctx, L.ranges);
-    for (int64_t r = lin; r < rc.total_tiles; r += stride) ranges[r] = make_uint2(0u, 0u);
-  }
   if (i >= rc.n) return;
   const ViewDev& V = views[view];
   const int64_t gid = (int64_t)view * rc.n + i;
@@ -175,13 +174,11 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
   float* chan = ctx_ptr<float>(ctx, L.chan);
   short4* rect = ctx_ptr<short4>(ctx, L.rect);
   uint32_t* ntiles = ctx_ptr<uint32_t>(ctx, L.ntiles);
-  uint32_t* dkey = ctx_ptr<uint32_t>(ctx, L.dkey0);
-  int32_t* rank = ctx_ptr<int32_t>(ctx, L.rank);
-  rank[gid] = -1;
+  uint32_t* dkey = ctx_ptr<uint32_t>(ctx, L.dkey);
   if (!vis) {
     rect[gid] = make_short4(1, 0, 1, 0);
     ntiles[gid] = 0u;
-    dkey[gid] = kInvalidKey;
+    dkey[gid] = 0xFFFFFFFFu;
     return;
   }
   geom[2 * gid] = make_float4(u, v, A, B);
@@ -226,7 +223,10 @@ __global__ void __launch_bounds__(256) k_project_backward(RenderConst rc, asgs_g
   if (i < rc.n) {
     const ViewDev& V = views[view];
     const int64_t gid = (int64_t)view * rc.n + i;
-    const int32_t j = ctx_ptr<const int32_t>(ctx, L.rank)[gid];
+    // visible pairs own ntiles consecutive gradient slots from toff; after an
+    // overflowed forward no list was blended and every gradient is zero
+    const uint32_t cnt = ctx_ptr<const uint32_t>(ctx, L.ntiles)[gid];
+    const bool used = cnt > 0u && ctx_ptr<const CtxHeader>(ctx, L.hdr)->overflow == 0u;
     float* dm = dg.mean + view * dg.view_stride[0];
     float* ds = dg.scale + view * dg.view_stride[1];
     float* dq = dg.rot + view * dg.view_stride[2];
@@ -234,14 +234,13 @@ __global__ void __launch_bounds__(256) k_project_backward(RenderConst rc, asgs_g
     float* drgb = dg.rgb + view * dg.view_stride[4];
     float* dft = NF > 0 ? dg.feat + view * dg.view_stride[5] : nullptr;
     const int64_t n = rc.n;
-    if (j < 0) {
+    if (!used) {
       for (int k = 0; k < 3; ++k) { dm[k * n + i] = 0.f; ds[k * n + i] = 0.f; drgb[k * n + i] = 0.f; }
       for (int k = 0; k < 4; ++k) dq[k * n + i] = 0.f;
       dop[i] = 0.f;
       for (int k = 0; k < NF; ++k) dft[k * n + i] = 0.f;
     } else {
-      const uint32_t start = ctx_ptr<const uint32_t>(ctx, L.toff)[j];
-      const uint32_t cnt = ctx_ptr<const uint32_t>(ctx, L.ntiles)[gid];
+      const uint32_t start = ctx_ptr<const uint32_t>(ctx, L.toff)[gid];
       const float* slot = ctx_ptr<const float>(ctx, L.gslot);
       float G[GS];
 #pragma unroll
@@ -406,13 +405,15 @@ __global__ void __launch_bounds__(256) k_pose_reduce(int n_views, int nbx, const
 }  // namespace
 
 void launch_set_views(const ViewDev* host_views, int n_views, ViewDev* dev_views, CtxHeader* hdr,
-                      hipStream_t s) {
+                      uint32_t* tcount, int total_tiles, hipStream_t s) {
   for (int first = 0; first < n_views; first += 16) {
     ViewChunk ch;
     ch.first = first;
     ch.count = n_views - first < 16 ? n_views - first : 16;
     for (int k = 0; k < ch.count; ++k) ch.v[k] = host_views[first + k];
-    hipLaunchKernelGGL(k_set_views, dim3(1), dim3(64), 0, s, ch, dev_views, hdr);
+    const int blocks = first == 0 ? (total_tiles + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_set_views, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, ch, dev_views, hdr,
+                       tcount, total_tiles);
   }
 }
 

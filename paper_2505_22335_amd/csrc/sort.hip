@@ -1,420 +1,445 @@
-// Tile binning and the device radix sort on (tile, depth) keys.
+// Tile binning: the per-tile lists of (tile, Gaussian) intersections, each
+// ordered front to back by (float32 camera depth, index).
 //
-// The per-tile lists must be ordered by (tile, float32 depth, index). This is
-// an LSD radix sort of the 64-bit key (tile << 32 | depth bits) over the
-// Gaussian-major list of intersections, done in an order that touches fewer
-// items: every intersection of one Gaussian shares its depth bits, so the
-// four depth digits are sorted on the (compacted) visible Gaussians before
-// duplication, the list is then emitted Gaussian by Gaussian in depth order,
-// and the remaining tile digits are sorted stably on the intersections. The
-// result equals a stable LSD sort of the full keys of the Gaussian-major
-// list.
-//
-// Each pass is three kernels: an upsweep (per-block 256-bin digit histogram,
-// stored digit-major), a scan with one wave per digit that turns a digit's
-// counts over the blocks into each block's offset within the digit and the
-// digit's total, and a stable scatter that adds the digit starts (a scan of
-// the 256 totals, repeated by every block). Within a block, wave ballots find
-// lanes with equal digits; ranks follow item order within a wave, across the
-// block's waves and across its rounds.
+// The lists are built as a counting sort on the tile followed by a sort of
+// every list on its own:
+//  - each visible Gaussian is counted into the counter of every tile its
+//    rectangle covers, so the list lengths are known;
+//  - one workgroup scans the lengths into the tile ranges (and orders the
+//    tiles longest list first, the order the blend kernels start them in);
+//  - every visible Gaussian takes its places in its tiles' ranges through the
+//    tiles' cursors, writing the 64-bit key (depth bits << 32 | index). The
+//    order inside a range is arbitrary at this point;
+//  - one workgroup per tile sorts its range on the key. The keys are unique,
+//    so the final lists do not depend on the emission order.
+// Every intersection also owns a gradient slot: the Gaussian-major position
+// toff[Gaussian] + (its tile's position in the Gaussian's rectangle), from an
+// exclusive scan of the tile counts in (view, Gaussian) order. The blend
+// backward writes a list entry's gradient into its slot, and the projection
+// backward sums a Gaussian's slots, which are contiguous.
 #include "internal.h"
 
 namespace asgs {
 
 namespace {
 
-struct RadixArgs {
-  const uint32_t* keys_in;
-  const uint32_t* vals_in;                 // nullptr: the value is the item index
-  uint32_t* keys_out;
-  uint32_t* vals_out;
-  const unsigned long long* count_dev;     // nullptr: use count_host
-  uint64_t count_host;
-  uint64_t count_cap;
-  int32_t shift;
-  int32_t filter;                          // drop keys equal to kInvalidKey
-  uint32_t* hist;                          // [256][nb] digit-major histograms, then offsets; [256] totals after
-  unsigned int* counter;                   // last-block counter (0 between uses)
-  unsigned long long* total_out;           // nullptr or: number of kept items
+template <typename T>
+ASGS_DEV T wave_incl_scan(T v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T u = __shfl_up(v, o);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Binning blocks: kScanThreads consecutive (view, Gaussian) pairs of one view,
+// one per thread. A block's intersections reach the per-tile counters through
+// an LDS grid over the bounding box of its Gaussians' rectangles (Gaussians of
+// one block are mostly neighbours in space), so a hot tile takes one global
+// atomic per block instead of one per Gaussian. Gaussians with a rectangle
+// of more than kBoxRect tiles, and every Gaussian of a block whose box has
+// more than kBoxCells tiles, use the global counters directly.
+// ---------------------------------------------------------------------------
+constexpr int kBoxCells = 4096;
+constexpr int kBoxRect = 64;
+
+struct ScanBlock {
+  int view;
+  int64_t j;     // this thread's pair
+  bool valid;    // j is a pair of the block
 };
 
-ASGS_DEV uint64_t item_count(const RadixArgs& a) {
-  uint64_t n = a.count_dev ? (uint64_t)__hip_atomic_load(a.count_dev, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT)
-                           : a.count_host;
-  return n < a.count_cap ? n : a.count_cap;
+ASGS_DEV ScanBlock scan_block(const RenderConst& rc) {
+  const int64_t nbx = (rc.n + kScanThreads - 1) / kScanThreads;
+  ScanBlock sb;
+  sb.view = (int)(blockIdx.x / nbx);
+  const int64_t i = (int64_t)(blockIdx.x - sb.view * nbx) * kScanThreads + threadIdx.x;
+  sb.valid = i < rc.n;
+  sb.j = (int64_t)sb.view * rc.n + i;
+  return sb;
 }
 
-ASGS_DEV uint32_t lanes_below(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+struct TileBox {
+  int x0, y0, w, area;  // LDS cell of tile (tx, ty): (ty - y0) * w + tx - x0
+  bool lds;             // block-uniform: the box fits kBoxCells
+};
+
+template <typename T>
+ASGS_DEV T wave_min(T v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_radix_upsweep(RadixArgs a) {
-  __shared__ uint32_t lh[kRadixBins];
-  const uint64_t n = item_count(a);
-  const uint64_t nb = (n + kSortItems - 1) / kSortItems;
-  const uint64_t b = blockIdx.x;
-  if (b >= nb) return;
-  lh[threadIdx.x] = 0u;
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kSortIPT; ++r) {
-    const uint64_t idx = b * kSortItems + (uint64_t)r * kSortThreads + threadIdx.x;
-    if (idx < n) {
-      const uint32_t k = a.keys_in[idx];
-      if (!a.filter || k != kInvalidKey) atomicAdd(&lh[(k >> a.shift) & (kRadixBins - 1)], 1u);
-    }
-  }
-  __syncthreads();
-  a.hist[(uint64_t)threadIdx.x * nb + b] = lh[threadIdx.x];
-}
-
-constexpr int kScanPer = 8;  // block counts per lane in one step of the digit scan
-
-// One wave per digit: exclusive prefix of the digit's counts over the
-// blocks, in place, and the digit total after the histograms. Each lane takes
-// kScanPer consecutive blocks; every load of a step is issued before the sums.
-__global__ void __launch_bounds__(256) k_radix_scan(RadixArgs a) {
-  const uint64_t n = item_count(a);
-  const int nb = (int)((n + kSortItems - 1) / kSortItems);
-  const int lane = threadIdx.x & 63;
-  const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
-  uint32_t* h = a.hist + (uint64_t)d * nb;
-  uint32_t carry = 0u;
-  for (int b0 = 0; b0 < nb; b0 += 64 * kScanPer) {
-    uint32_t v[kScanPer];
-    uint32_t sum = 0u;
-#pragma unroll
-    for (int q = 0; q < kScanPer; ++q) {
-      const int b = b0 + lane * kScanPer + q;
-      v[q] = b < nb ? h[b] : 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < kScanPer; ++q) sum += v[q];
-    uint32_t incl = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t u = __shfl_up(incl, o);
-      if (lane >= o) incl += u;
-    }
-    uint32_t run = carry + incl - sum;
-#pragma unroll
-    for (int q = 0; q < kScanPer; ++q) {
-      const int b = b0 + lane * kScanPer + q;
-      if (b < nb) h[b] = run;
-      run += v[q];
-    }
-    carry += __shfl(incl, 63);
-  }
-  if (lane == 0) a.hist[(uint64_t)kRadixBins * nb + d] = carry;
-}
-
-__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(RadixArgs a) {
-  __shared__ uint32_t base[kRadixBins];
-  __shared__ uint32_t run[kRadixBins];
-  __shared__ uint32_t wcnt[kSortThreads / 64][kRadixBins];
-  const uint64_t n = item_count(a);
-  const uint64_t nb = (n + kSortItems - 1) / kSortItems;
-  const uint64_t b = blockIdx.x;
-  if (b >= nb) return;
+// Bounding box of the rects of the lanes with small set; clears its cells.
+ASGS_DEV TileBox tile_box(short4 r, bool small, int* red, uint32_t* cell) {
   const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
-  // digit starts: exclusive scan of the digit totals (every block repeats it)
-  {
-    const uint32_t tot = a.hist[(uint64_t)kRadixBins * nb + t];
-    uint32_t incl = tot;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t u = __shfl_up(incl, o);
-      if (lane >= o) incl += u;
-    }
-    if (lane == 63) run[wv] = incl;  // wave totals (run is reset below)
-    __syncthreads();
-    uint32_t before = 0u;
-    for (int w = 0; w < wv; ++w) before += run[w];
-    base[t] = before + incl - tot + a.hist[(uint64_t)t * nb + b];  // + this block's offset in the digit
-    if (b == 0 && t == kRadixBins - 1 && a.total_out) *a.total_out = before + incl;
-    __syncthreads();
-  }
-  run[t] = 0u;
-  for (int r = 0; r < kSortIPT; ++r) {
-    const uint64_t idx = b * kSortItems + (uint64_t)r * kSortThreads + t;
-    uint32_t key = 0u, val = 0u;
-    bool valid = idx < n;
-    if (valid) {
-      key = a.keys_in[idx];
-      val = a.vals_in ? a.vals_in[idx] : (uint32_t)idx;
-      if (a.filter && key == kInvalidKey) valid = false;
-    }
-    const uint32_t d = (key >> a.shift) & (kRadixBins - 1);
-#pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][t] = 0u;
-    __syncthreads();
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < kRadixBits; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const uint64_t bb = __ballot(on);
-      m &= on ? bb : ~bb;
-    }
-    const uint32_t below = lanes_below(m);
-    if (valid && below == 0) wcnt[wv][d] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = base[d] + run[d] + below;
-      for (int w = 0; w < wv; ++w) pos += wcnt[w][d];
-      a.keys_out[pos] = key;
-      a.vals_out[pos] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0u;
-#pragma unroll
-    for (int w = 0; w < kSortThreads / 64; ++w) add += wcnt[w][t];
-    run[t] += add;
-  }
-}
-
-void radix_pass(const RadixArgs& a, uint64_t max_items, hipStream_t s) {
-  const unsigned nblk = (unsigned)((max_items + kSortItems - 1) / kSortItems);
-  const unsigned g = nblk > 0 ? nblk : 1;
-  hipLaunchKernelGGL(k_radix_upsweep, dim3(g), dim3(kSortThreads), 0, s, a);
-  hipLaunchKernelGGL(k_radix_scan, dim3(kRadixBins / 4), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_radix_scatter, dim3(g), dim3(kSortThreads), 0, s, a);
-}
-
-// ---------------------------------------------------------------------------
-// Duplication: exclusive scan of the tile counts in depth order, then each
-// visible Gaussian emits one (tile key, index) pair per tile of its rect.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kScanThreads) k_dup_upsweep(RenderConst rc, char* ctx, CtxLayout L) {
-  __shared__ unsigned long long red[kScanThreads / 64];
-  (void)rc;
-  CtxHeader* hdr = ctx_ptr<CtxHeader>(ctx, L.hdr);
-  const uint64_t m = __hip_atomic_load(&hdr->n_visible, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t nb = (m + kScanItems - 1) / kScanItems;
-  const uint64_t b = blockIdx.x;
-  const uint32_t* ids = ctx_ptr<const uint32_t>(ctx, L.dvalB);
-  const uint32_t* ntiles = ctx_ptr<const uint32_t>(ctx, L.ntiles);
-  uint32_t* bsum = ctx_ptr<uint32_t>(ctx, L.bsum);
-  unsigned long long s = 0;
-  if (b < nb) {
-    for (int r = 0; r < kScanIPT; ++r) {
-      const uint64_t j = b * kScanItems + (uint64_t)r * kScanThreads + threadIdx.x;
-      if (j < m) s += ntiles[ids[j]];
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  if (t < 4) red[t] = 0x7FFFFFFF;
   __syncthreads();
-  if (b < nb && threadIdx.x == 0) {
-    unsigned long long tot = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) tot += red[w];
-    bsum[b] = (uint32_t)tot;
+  const int big = 0x7FFFFFFF;
+  const int x0 = wave_min(small ? (int)r.x : big), nx1 = wave_min(small ? -(int)r.y : big);
+  const int y0 = wave_min(small ? (int)r.z : big), ny1 = wave_min(small ? -(int)r.w : big);
+  if ((t & 63) == 0) {
+    atomicMin(&red[0], x0);
+    atomicMin(&red[1], nx1);
+    atomicMin(&red[2], y0);
+    atomicMin(&red[3], ny1);
   }
+  __syncthreads();
+  TileBox b;
+  b.x0 = red[0];
+  b.y0 = red[2];
+  b.lds = b.x0 != big;
+  b.w = b.lds ? -red[1] - b.x0 + 1 : 0;
+  const int h = b.lds ? -red[3] - b.y0 + 1 : 0;
+  b.area = b.w * h;
+  b.lds = b.lds && b.area <= kBoxCells;
+  if (b.lds)
+    for (int c = t; c < b.area; c += kScanThreads) cell[c] = 0u;
+  __syncthreads();
+  return b;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_dup_emit(RenderConst rc, const ViewDev* __restrict__ views,
-                                                           char* ctx, CtxLayout L) {
-  __shared__ uint32_t tsum[kScanThreads];
-  CtxHeader* hdr = ctx_ptr<CtxHeader>(ctx, L.hdr);
-  const uint64_t m = __hip_atomic_load(&hdr->n_visible, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t nb = (m + kScanItems - 1) / kScanItems;
-  const uint64_t b = blockIdx.x;
-  if (b >= nb) return;
-  const uint32_t* ids = ctx_ptr<const uint32_t>(ctx, L.dvalB);
-  const uint32_t* ntiles = ctx_ptr<const uint32_t>(ctx, L.ntiles);
-  const short4* rect = ctx_ptr<const short4>(ctx, L.rect);
-  const uint32_t* bsum = ctx_ptr<const uint32_t>(ctx, L.bsum);
-  uint32_t* toff = ctx_ptr<uint32_t>(ctx, L.toff);
-  int32_t* rank = ctx_ptr<int32_t>(ctx, L.rank);
-  uint32_t* pkey = ctx_ptr<uint32_t>(ctx, L.pkeyA);
-  uint32_t* dupgid = ctx_ptr<uint32_t>(ctx, L.dupgid);
-  // blocked arrangement: thread t owns items t*IPT .. t*IPT+IPT-1 of the block
-  const uint64_t j0 = b * kScanItems + (uint64_t)threadIdx.x * kScanIPT;
-  uint32_t cnt[kScanIPT];
-  uint32_t mine = 0;
-#pragma unroll
-  for (int r = 0; r < kScanIPT; ++r) {
-    const uint64_t j = j0 + r;
-    cnt[r] = j < m ? ntiles[ids[j]] : 0u;
-    mine += cnt[r];
-  }
-  // sums of the blocks before this one (and, in block 0, of all blocks)
-  __shared__ unsigned long long bred[kScanThreads / 64];
-  __shared__ unsigned long long bbase, btotal;
-  {
-    unsigned long long pre = 0, tot = 0;
-    for (uint64_t bb = threadIdx.x; bb < nb; bb += kScanThreads) {
-      const uint32_t v = bsum[bb];
-      tot += v;
-      pre += bb < b ? v : 0u;
+// Per binning block: the tile-count sum and the number of visible pairs, and
+// the intersections added to the per-tile counters.
+__global__ void __launch_bounds__(kScanThreads) k_dup_upsweep(RenderConst rc, const ViewDev* __restrict__ views,
+                                                              char* ctx, CtxLayout L) {
+  __shared__ unsigned long long red[kScanThreads / 64];
+  __shared__ uint32_t vred[kScanThreads / 64];
+  __shared__ int bred[4];
+  __shared__ uint32_t cell[kBoxCells];
+  const ScanBlock sb = scan_block(rc);
+  const ViewDev& V = views[sb.view];
+  const uint32_t cnt = sb.valid ? ctx_ptr<const uint32_t>(ctx, L.ntiles)[sb.j] : 0u;
+  const short4 r = cnt > 0u ? ctx_ptr<const short4>(ctx, L.rect)[sb.j] : make_short4(1, 0, 1, 0);
+  uint32_t* tcount = ctx_ptr<uint32_t>(ctx, L.tcur);
+  const bool small = cnt > 0u && cnt <= (uint32_t)kBoxRect;
+  const TileBox bx = tile_box(r, small, bred, cell);
+  const bool via_lds = bx.lds && small;
+  for (int ty = r.z; ty <= r.w; ++ty)
+    for (int tx = r.x; tx <= r.y; ++tx) {
+      if (via_lds) atomicAdd(&cell[(ty - bx.y0) * bx.w + tx - bx.x0], 1u);
+      else __hip_atomic_fetch_add(&tcount[V.tile_base + ty * V.TX + tx], 1u, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
     }
-    for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
-    if ((threadIdx.x & 63) == 0) bred[threadIdx.x >> 6] = pre;
-    __syncthreads();
-    if (threadIdx.x == 0) bbase = bred[0] + bred[1] + bred[2] + bred[3];
-    __syncthreads();
-    if (b == 0) {
-      for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-      if ((threadIdx.x & 63) == 0) bred[threadIdx.x >> 6] = tot;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        btotal = bred[0] + bred[1] + bred[2] + bred[3];
-        hdr->n_isect = btotal;
-        hdr->overflow = btotal > (uint64_t)rc.cap ? 1u : 0u;
+  __syncthreads();
+  if (bx.lds)
+    for (int c = threadIdx.x; c < bx.area; c += kScanThreads) {
+      const uint32_t k = cell[c];
+      if (k) {
+        const int cy = c / bx.w;
+        __hip_atomic_fetch_add(&tcount[V.tile_base + (bx.y0 + cy) * V.TX + bx.x0 + c - cy * bx.w], k,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
+  unsigned long long s = cnt;
+  uint32_t vis = cnt > 0u ? 1u : 0u;
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off);
+    vis += __shfl_xor(vis, off);
   }
-  tsum[threadIdx.x] = mine;
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = s;
+    vred[threadIdx.x >> 6] = vis;
+  }
   __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t v = threadIdx.x >= (unsigned)off ? tsum[threadIdx.x - off] : 0u;
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+    uint32_t vt = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+      tot += red[w];
+      vt += vred[w];
+    }
+    ctx_ptr<uint32_t>(ctx, L.bsum)[blockIdx.x] = (uint32_t)tot;
+    ctx_ptr<uint32_t>(ctx, L.vsum)[blockIdx.x] = vt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup: the tile ranges [start, end) from the list lengths, the
+// emission cursors (= starts), the totals and the blend order of the tiles,
+// longest list first (a counting sort on the length; lengths of 1023 and more
+// share one bucket, and the order within a bucket is arbitrary, which changes
+// no result). When the intersections exceed the capacity every range is left
+// empty: nothing is blended and the overflow is recorded.
+// ---------------------------------------------------------------------------
+constexpr int kOrderBins = 1024;
+constexpr int kTileScanThreads = 1024;
+
+ASGS_DEV int order_bin(uint32_t c) { return kOrderBins - 1 - (int)(c < kOrderBins - 1 ? c : kOrderBins - 1); }
+
+__global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, char* ctx, CtxLayout L) {
+  __shared__ uint32_t bins[kOrderBins];
+  __shared__ unsigned long long wtot[kTileScanThreads / 64];
+  __shared__ uint32_t wbin[kTileScanThreads / 64];
+  __shared__ unsigned long long wvis[kTileScanThreads / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int NW = kTileScanThreads / 64;
+  const int T = rc.total_tiles;
+  uint32_t* tcur = ctx_ptr<uint32_t>(ctx, L.tcur);
+  uint2* ranges = ctx_ptr<uint2>(ctx, L.ranges);
+  uint32_t* order = ctx_ptr<uint32_t>(ctx, L.torder);
+  CtxHeader* hdr = ctx_ptr<CtxHeader>(ctx, L.hdr);
+  // thread t owns the consecutive tiles [a0, a1)
+  const int per = (T + kTileScanThreads - 1) / kTileScanThreads;
+  const int a0 = min(T, t * per), a1 = min(T, a0 + per);
+  bins[t] = 0u;
+  __syncthreads();
+  unsigned long long mine = 0;
+  for (int i = a0; i < a1; ++i) {
+    const uint32_t c = tcur[i];
+    mine += c;
+    atomicAdd(&bins[order_bin(c)], 1u);
+  }
+  // visible pairs: sum of the per-block counts
+  unsigned long long vis = 0;
+  {
+    const uint64_t nb = (uint64_t)scan_blocks(rc.n, rc.n_views);
+    const uint32_t* vsum = ctx_ptr<const uint32_t>(ctx, L.vsum);
+    for (uint64_t bb = t; bb < nb; bb += kTileScanThreads) vis += vsum[bb];
+    for (int o = 32; o > 0; o >>= 1) vis += __shfl_xor(vis, o);
+  }
+  const unsigned long long incl = wave_incl_scan(mine, lane);
+  if (lane == 63) wtot[wv] = incl;
+  if (lane == 0) wvis[wv] = vis;
+  __syncthreads();
+  const uint32_t bv = bins[t];
+  const uint32_t bincl = wave_incl_scan(bv, lane);
+  if (lane == 63) wbin[wv] = bincl;
+  unsigned long long before = 0, total = 0, vtot = 0;
+  for (int w = 0; w < NW; ++w) {
+    before += w < wv ? wtot[w] : 0ull;
+    total += wtot[w];
+    vtot += wvis[w];
+  }
+  __syncthreads();
+  uint32_t bbefore = 0;
+  for (int w = 0; w < wv; ++w) bbefore += wbin[w];
+  bins[t] = bbefore + bincl - bv;
+  const bool ovf = total > (unsigned long long)rc.cap;
+  if (t == 0) {
+    hdr->n_isect = total;
+    hdr->n_visible = vtot;
+    hdr->overflow = ovf ? 1u : 0u;
+  }
+  __syncthreads();
+  unsigned long long run = before + incl - mine;
+  for (int i = a0; i < a1; ++i) {
+    const uint32_t c = tcur[i];
+    ranges[i] = ovf ? make_uint2(0u, 0u) : make_uint2((uint32_t)run, (uint32_t)(run + c));
+    tcur[i] = (uint32_t)run;
+    order[atomicAdd(&bins[order_bin(c)], 1u)] = (uint32_t)i;
+    run += c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Emission: the exclusive scan of the tile counts in (view, Gaussian) order
+// gives every visible Gaussian its first gradient slot; the Gaussian then
+// takes one place in the range of every tile of its rectangle. Places are
+// reserved per block and tile through the same LDS box as the counting.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kScanThreads) k_dup_emit(RenderConst rc, const ViewDev* __restrict__ views,
+                                                           char* ctx, CtxLayout L) {
+  __shared__ unsigned long long wred[kScanThreads / 64];
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  __shared__ int bred[4];
+  __shared__ uint32_t cell[kBoxCells];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const ScanBlock sb = scan_block(rc);
+  const ViewDev& V = views[sb.view];
+  const uint32_t cnt = sb.valid ? ctx_ptr<const uint32_t>(ctx, L.ntiles)[sb.j] : 0u;
+  const short4 r = cnt > 0u ? ctx_ptr<const short4>(ctx, L.rect)[sb.j] : make_short4(1, 0, 1, 0);
+  const uint32_t* bsum = ctx_ptr<const uint32_t>(ctx, L.bsum);
+  uint32_t* tcur = ctx_ptr<uint32_t>(ctx, L.tcur);
+  unsigned long long* ukey = ctx_ptr<unsigned long long>(ctx, L.ukey);
+  // first gradient slot: sum of the blocks before this one + the prefix in it
+  unsigned long long pre = 0;
+  for (uint32_t bb = t; bb < blockIdx.x; bb += kScanThreads) pre += bsum[bb];
+  for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
+  const uint32_t incl = wave_incl_scan(cnt, lane);
+  if (lane == 0) wred[wv] = pre;
+  if (lane == 63) wsum[wv] = incl;
+  const bool small = cnt > 0u && cnt <= (uint32_t)kBoxRect;
+  const TileBox bx = tile_box(r, small, bred, cell);  // synchronises: wred, wsum are complete
+  unsigned long long off = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) off += wred[w] + (w < wv ? wsum[w] : 0u);
+  off += incl - cnt;
+  if (sb.valid) ctx_ptr<uint32_t>(ctx, L.toff)[sb.j] = (uint32_t)off;
+  const bool via_lds = bx.lds && small;
+  // count the block's places per tile, reserve them, then hand them out
+  if (via_lds)
+    for (int ty = r.z; ty <= r.w; ++ty)
+      for (int tx = r.x; tx <= r.y; ++tx) atomicAdd(&cell[(ty - bx.y0) * bx.w + tx - bx.x0], 1u);
+  __syncthreads();
+  if (bx.lds)
+    for (int c = t; c < bx.area; c += kScanThreads) {
+      const uint32_t k = cell[c];
+      if (k) {
+        const int cy = c / bx.w;
+        cell[c] = atomicAdd(&tcur[V.tile_base + (bx.y0 + cy) * V.TX + bx.x0 + c - cy * bx.w], k);
+      }
+    }
+  __syncthreads();
+  if (cnt == 0u) return;
+  const unsigned long long key = ((unsigned long long)ctx_ptr<const uint32_t>(ctx, L.dkey)[sb.j] << 32) |
+                                 (uint32_t)sb.j;
+  const uint64_t cap = (uint64_t)rc.cap;
+  for (int ty = r.z; ty <= r.w; ++ty)
+    for (int tx = r.x; tx <= r.y; ++tx) {
+      const uint32_t pos = via_lds ? atomicAdd(&cell[(ty - bx.y0) * bx.w + tx - bx.x0], 1u)
+                                   : atomicAdd(&tcur[V.tile_base + ty * V.TX + tx], 1u);
+      if (pos < cap) ukey[pos] = key;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per tile: sort the range on the key and write the sorted Gaussian, gradient
+// slot and tile key of every list entry. Ranges up to kListSort entries are
+// sorted in LDS by one bitonic network; longer ranges are cut into runs of
+// kListSort entries that are sorted the same way, which the workgroup then
+// merges pairwise (merge-path split of the output among the threads)
+// through a scratch array until one run is left.
+// ---------------------------------------------------------------------------
+constexpr int kListThreads = 256;
+constexpr int kListSort = 2048;
+constexpr unsigned long long kKeyMax = ~0ull;  // above every real key (depth bits < 0x7F800000)
+
+// Ascending bitonic sort of sk[0, P), P a power of two; the caller has
+// synchronised the workgroup after filling sk.
+ASGS_DEV void bitonic_lds(unsigned long long* sk, int P, int t) {
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = t; q < (P >> 1); q += kListThreads) {
+        const int lo = 2 * q - (q & (j - 1));  // q with a zero bit inserted at j
+        const int hi = lo + j;
+        const unsigned long long a = sk[lo], b = sk[hi];
+        const bool up = (lo & k) == 0;
+        if ((a > b) == up) {
+          sk[lo] = b;
+          sk[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+}
+
+struct ListOut {
+  const short4* rect;
+  const uint32_t* toff;
+  uint32_t* pairgid;
+  uint32_t* pslot;
+  uint32_t* ptile;
+  uint32_t tile;
+  int tx, ty;
+
+  // Gaussian, gradient slot and tile of list position pos.
+  ASGS_DEV void put(uint64_t pos, unsigned long long key) const {
+    const uint32_t gid = (uint32_t)key;
+    const short4 r = rect[gid];
+    pairgid[pos] = gid;
+    pslot[pos] = toff[gid] + (uint32_t)((ty - r.z) * (r.y - r.x + 1) + (tx - r.x));
+    ptile[pos] = tile;
+  }
+};
+
+__global__ void __launch_bounds__(kListThreads) k_list_sort(RenderConst rc, const ViewDev* __restrict__ views,
+                                                           char* ctx, CtxLayout L) {
+  __shared__ unsigned long long sk[kListSort];
+  const uint32_t tile = ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];
+  const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
+  const uint32_t n = rg.y - rg.x;
+  if (n == 0u) return;
+  const int t = threadIdx.x;
+  ListOut out;
+  {
+    const ViewDev& V = views[find_view(views, rc.n_views, (int)tile)];
+    const int lt = (int)tile - V.tile_base;
+    out.ty = lt / V.TX;
+    out.tx = lt - out.ty * V.TX;
+  }
+  out.rect = ctx_ptr<const short4>(ctx, L.rect);
+  out.toff = ctx_ptr<const uint32_t>(ctx, L.toff);
+  out.pairgid = ctx_ptr<uint32_t>(ctx, L.pairgid);
+  out.pslot = ctx_ptr<uint32_t>(ctx, L.pslot);
+  out.ptile = ctx_ptr<uint32_t>(ctx, L.ptile);
+  out.tile = tile;
+  unsigned long long* a = ctx_ptr<unsigned long long>(ctx, L.ukey) + rg.x;
+  if (n <= (uint32_t)kListSort) {
+    int P = 1;
+    while ((uint32_t)P < n) P <<= 1;
+    for (int i = t; i < P; i += kListThreads) sk[i] = (uint32_t)i < n ? a[i] : kKeyMax;
     __syncthreads();
-    tsum[threadIdx.x] += v;
+    bitonic_lds(sk, P, t);
+    for (uint32_t i = t; i < n; i += kListThreads) out.put(rg.x + i, sk[i]);
+    return;
+  }
+  // sorted runs of kListSort entries, in place
+  for (uint32_t c0 = 0; c0 < n; c0 += kListSort) {
+    const uint32_t m = min((uint32_t)kListSort, n - c0);
+    for (int i = t; i < kListSort; i += kListThreads) sk[i] = (uint32_t)i < m ? a[c0 + i] : kKeyMax;
+    __syncthreads();
+    bitonic_lds(sk, kListSort, t);
+    for (uint32_t i = t; i < m; i += kListThreads) a[c0 + i] = sk[i];
     __syncthreads();
   }
-  uint64_t off = bbase + (threadIdx.x > 0 ? tsum[threadIdx.x - 1] : 0u);
-  const uint64_t cap = (uint64_t)rc.cap;
-  for (int r = 0; r < kScanIPT; ++r) {
-    const uint64_t j = j0 + r;
-    if (j >= m) break;
-    const uint32_t gid = ids[j];
-    toff[j] = (uint32_t)off;
-    rank[gid] = (int32_t)j;
-    const int view = (int)(gid / (uint64_t)rc.n);
-    const ViewDev& V = views[view];
-    const short4 rc4 = rect[gid];
-    uint64_t p = off;
-    for (int ty = rc4.z; ty <= rc4.w; ++ty) {
-      for (int tx = rc4.x; tx <= rc4.y; ++tx, ++p) {
-        if (p < cap) {
-          pkey[p] = (uint32_t)(V.tile_base + ty * V.TX + tx);
-          dupgid[p] = gid;
+  // pairwise merges of runs of width w, a -> b, until one run is left
+  unsigned long long* b = ctx_ptr<unsigned long long>(ctx, L.tkey) + rg.x;
+  const uint64_t per = ((uint64_t)n + kListThreads - 1) / kListThreads;
+  for (uint64_t w = kListSort; w < n; w <<= 1) {
+    uint64_t o = min((uint64_t)n, (uint64_t)t * per);
+    const uint64_t oend = min((uint64_t)n, o + per);
+    while (o < oend) {
+      const uint64_t lo = o - o % (2 * w);
+      const uint64_t wa = min(w, (uint64_t)n - lo);
+      const uint64_t wb = min(w, (uint64_t)n - lo - wa);
+      const unsigned long long* A = a + lo;
+      const unsigned long long* B = A + wa;
+      const uint64_t diag = o - lo;
+      // entries of A among the first diag outputs of this merge
+      uint64_t i0 = diag > wb ? diag - wb : 0, i1 = min(diag, wa);
+      while (i0 < i1) {
+        const uint64_t mid = (i0 + i1) >> 1;
+        if (A[mid] < B[diag - 1 - mid]) i0 = mid + 1;
+        else i1 = mid;
+      }
+      uint64_t i = i0, j = diag - i0;
+      const uint64_t stop = min(oend, lo + wa + wb);
+      unsigned long long ka = i < wa ? A[i] : kKeyMax, kb = j < wb ? B[j] : kKeyMax;
+      for (; o < stop; ++o) {
+        if (ka < kb) {
+          b[o] = ka;
+          ++i;
+          ka = i < wa ? A[i] : kKeyMax;
+        } else {
+          b[o] = kb;
+          ++j;
+          kb = j < wb ? B[j] : kKeyMax;
         }
       }
     }
-    off += cnt[r];
+    __syncthreads();
+    unsigned long long* tmp = a;
+    a = b;
+    b = tmp;
   }
-}
-
-// Tile ranges [start, end) from the sorted keys, and the Gaussian of every
-// sorted intersection.
-__global__ void __launch_bounds__(256) k_ranges(RenderConst rc, char* ctx, CtxLayout L, size_t key_off,
-                                                size_t val_off) {
-  CtxHeader* hdr = ctx_ptr<CtxHeader>(ctx, L.hdr);
-  uint64_t I = __hip_atomic_load(&hdr->n_isect, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (I > (uint64_t)rc.cap) I = rc.cap;
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= I) return;
-  const uint32_t* key = ctx_ptr<const uint32_t>(ctx, key_off);
-  const uint32_t* val = ctx_ptr<const uint32_t>(ctx, val_off);
-  uint2* ranges = ctx_ptr<uint2>(ctx, L.ranges);
-  const uint32_t k = key[i];
-  if (i == 0 || key[i - 1] != k) ranges[k].x = (uint32_t)i;
-  if (i + 1 == I || key[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
-  ctx_ptr<uint32_t>(ctx, L.pairgid)[i] = ctx_ptr<const uint32_t>(ctx, L.dupgid)[val[i]];
-}
-
-// Blend order of the tiles: longest list first, so that the longest-running
-// workgroups start first and short tiles fill in behind them. A counting sort
-// on the list length (lengths of 1023 and more share one bucket); the order
-// within a bucket is arbitrary, which changes no result.
-constexpr int kOrderBins = 1024;
-__global__ void __launch_bounds__(kOrderBins) k_tile_order(RenderConst rc, char* ctx, CtxLayout L) {
-  __shared__ uint32_t bins[kOrderBins];
-  __shared__ uint32_t wsum[kOrderBins / 64];
-  const int t = threadIdx.x;
-  const uint2* ranges = ctx_ptr<const uint2>(ctx, L.ranges);
-  uint32_t* order = ctx_ptr<uint32_t>(ctx, L.torder);
-  const int T = rc.total_tiles;
-  bins[t] = 0u;
-  __syncthreads();
-  for (int i = t; i < T; i += kOrderBins) {
-    const uint2 r = ranges[i];
-    const uint32_t c = r.y - r.x;
-    atomicAdd(&bins[kOrderBins - 1 - (c < kOrderBins - 1 ? c : kOrderBins - 1)], 1u);
-  }
-  __syncthreads();
-  // exclusive scan of the bins: within each wave, then over the wave sums
-  const uint32_t v = bins[t];
-  uint32_t incl = v;
-  const int lane = t & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t u = __shfl_up(incl, o);
-    if (lane >= o) incl += u;
-  }
-  if (lane == 63) wsum[t >> 6] = incl;
-  __syncthreads();
-  uint32_t before = 0u;
-  for (int w = 0; w < (t >> 6); ++w) before += wsum[w];
-  __syncthreads();
-  bins[t] = before + incl - v;
-  __syncthreads();
-  for (int i = t; i < T; i += kOrderBins) {
-    const uint2 r = ranges[i];
-    const uint32_t c = r.y - r.x;
-    const uint32_t pos = atomicAdd(&bins[kOrderBins - 1 - (c < kOrderBins - 1 ? c : kOrderBins - 1)], 1u);
-    order[pos] = (uint32_t)i;
-  }
+  for (uint32_t i = t; i < n; i += kListThreads) out.put(rg.x + i, a[i]);
 }
 
 }  // namespace
 
-void launch_depth_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s) {
-  CtxHeader* hdr = reinterpret_cast<CtxHeader*>(ctx + L.hdr);
-  const size_t kin[4] = {L.dkey0, L.dkeyA, L.dkeyB, L.dkeyA};
-  const size_t vin[4] = {0, L.dvalA, L.dvalB, L.dvalA};
-  const size_t kout[4] = {L.dkeyA, L.dkeyB, L.dkeyA, L.dkeyB};
-  const size_t vout[4] = {L.dvalA, L.dvalB, L.dvalA, L.dvalB};
-  for (int p = 0; p < 4; ++p) {
-    RadixArgs a;
-    a.keys_in = reinterpret_cast<const uint32_t*>(ctx + kin[p]);
-    a.vals_in = p == 0 ? nullptr : reinterpret_cast<const uint32_t*>(ctx + vin[p]);
-    a.keys_out = reinterpret_cast<uint32_t*>(ctx + kout[p]);
-    a.vals_out = reinterpret_cast<uint32_t*>(ctx + vout[p]);
-    a.count_dev = p == 0 ? nullptr : &hdr->n_visible;
-    a.count_host = (uint64_t)rc.nv;
-    a.count_cap = (uint64_t)rc.nv;
-    a.shift = 8 * p;
-    a.filter = p == 0;
-    a.hist = reinterpret_cast<uint32_t*>(ctx + L.hist);
-      a.counter = nullptr;
-    a.total_out = p == 0 ? &hdr->n_visible : nullptr;
-    radix_pass(a, (uint64_t)rc.nv, s);
-  }
-}
-
-void launch_duplicate(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s) {
-  const unsigned nblk = (unsigned)((rc.nv + kScanItems - 1) / kScanItems);
+void launch_bin(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s) {
+  const unsigned nblk = (unsigned)scan_blocks(rc.n, rc.n_views);
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
-  hipLaunchKernelGGL(k_dup_upsweep, dim3(nblk), dim3(kScanThreads), 0, s, rc, ctx, L);
-  hipLaunchKernelGGL(k_dup_emit, dim3(nblk), dim3(kScanThreads), 0, s, rc, views, ctx, L);
+  if (nblk > 0) hipLaunchKernelGGL(k_dup_upsweep, dim3(nblk), dim3(kScanThreads), 0, s, rc, views, ctx, L);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTileScanThreads), 0, s, rc, ctx, L);
+  if (nblk > 0) hipLaunchKernelGGL(k_dup_emit, dim3(nblk), dim3(kScanThreads), 0, s, rc, views, ctx, L);
 }
 
 void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s) {
-  CtxHeader* hdr = reinterpret_cast<CtxHeader*>(ctx + L.hdr);
-  for (int p = 0; p < L.tile_passes; ++p) {
-    const bool even = (p % 2) == 0;
-    RadixArgs a;
-    a.keys_in = reinterpret_cast<const uint32_t*>(ctx + (even ? L.pkeyA : L.pkeyB));
-    a.vals_in = p == 0 ? nullptr : reinterpret_cast<const uint32_t*>(ctx + (even ? L.pvalA : L.pvalB));
-    a.keys_out = reinterpret_cast<uint32_t*>(ctx + (even ? L.pkeyB : L.pkeyA));
-    a.vals_out = reinterpret_cast<uint32_t*>(ctx + (even ? L.pvalB : L.pvalA));
-    a.count_dev = &hdr->n_isect;
-    a.count_host = 0;
-    a.count_cap = (uint64_t)rc.cap;
-    a.shift = 8 * p;
-    a.filter = 0;
-    a.hist = reinterpret_cast<uint32_t*>(ctx + L.hist);
-    a.counter = nullptr;
-    a.total_out = nullptr;
-    radix_pass(a, (uint64_t)rc.cap, s);
-  }
-  const unsigned nblk = (unsigned)((rc.cap + 255) / 256);
-  hipLaunchKernelGGL(k_ranges, dim3(nblk > 0 ? nblk : 1), dim3(256), 0, s, rc, ctx, L, L.pkey_fin,
-                     L.pval_fin);
-  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderBins), 0, s, rc, ctx, L);
+  const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
+  hipLaunchKernelGGL(k_list_sort, dim3(rc.total_tiles), dim3(kListThreads), 0, s, rc, views, ctx, L);
 }
 
 }  // namespace asgs
