@@ -153,6 +153,19 @@ int check_gauss(const asgs_gaussians* g, int nf, int n_views, bool allow_shared,
   return ASGS_OK;
 }
 
+// Compute units of the current device (cached per device; 0 if unknown).
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n = 0;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 struct Prep {
   ViewDev views[ASGS_MAX_VIEWS];
   int total_tiles = 0, total_pix = 0;
@@ -183,6 +196,7 @@ int prepare(const asgs_camera* cams, int32_t n_views, int64_t n, const asgs_rend
   rc.total_tiles = P.total_tiles;
   rc.total_pix = P.total_pix;
   rc.cap = capacity;
+  rc.n_cu = device_cu_count();
   P.L = ctx_layout(n, n_views, P.total_tiles, P.total_pix, opts->n_feat, capacity);
   return ASGS_OK;
 }

@@ -26,13 +26,17 @@ namespace {
 ASGS_DEV int tile_lx(int t) { return ((t >> 6) & 1) * 8 + (t & 7); }
 ASGS_DEV int tile_ly(int t) { return ((t >> 7) & 1) * 8 + ((t >> 3) & 7); }
 
-// Issue priority of a tile's waves by list length: the longest lists run on
-// the critical path of the launch, so their waves are preferred over shorter
-// ones sharing a SIMD (the order of the results does not change).
-ASGS_DEV void prioritise(uint32_t len) {
-  if (len > 256u) __builtin_amdgcn_s_setprio(3);
-  else if (len > 192u) __builtin_amdgcn_s_setprio(2);
-  else if (len > 128u) __builtin_amdgcn_s_setprio(1);
+// Issue priority of a tile's waves by its rank in the blend order (longest
+// list first). The first workgroups of a launch spread over the compute units,
+// so the longest list on each unit gets the highest priority, the next one the
+// next level: the tiles on the critical path of the launch are preferred over
+// the shorter ones sharing their SIMDs (the order of the results does not
+// change).
+ASGS_DEV void prioritise(uint32_t rank, int n_cu) {
+  const uint32_t band = rank / (uint32_t)(n_cu > 0 ? n_cu : 1);
+  if (band == 0u) __builtin_amdgcn_s_setprio(3);
+  else if (band == 1u) __builtin_amdgcn_s_setprio(2);
+  else if (band == 2u) __builtin_amdgcn_s_setprio(1);
 }
 
 // Which of the tile's four 8x8 quarters (bit w) hold a pixel centre that can
@@ -106,7 +110,7 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
-  prioritise(rg.y - rg.x);
+  prioritise(blockIdx.x, rc.n_cu);
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
@@ -255,11 +259,9 @@ ASGS_DEV f4v mfma_bf(const bf8v& a, const bf8v& b, f4v c) {
 // v = hi + lo with hi = bf16(v) and lo = bf16(v - hi), both rounded to nearest
 // even: |v - hi - lo| <= 2^-17 |v| for finite v. With exact bf16 products and
 // FP32 accumulation, a b ~ ah bh + ah bl + al bh to ~2^-15 relative.
-ASGS_DEV uint16_t bf_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// Round to nearest even bfloat16 (the hardware conversion of gfx950).
+ASGS_DEV uint16_t bf_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+// v = hi + lo + O(2^-16 |v|), both bfloat16.
 ASGS_DEV void bf_split(float v, uint16_t& hi, uint16_t& lo) {
   hi = bf_rne(v);
   lo = bf_rne(v - __uint_as_float((uint32_t)hi << 16));
@@ -305,7 +307,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
   const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
-  prioritise(rg.y - rg.x);
+  prioritise(blockIdx.x, rc.n_cu);
   const uint32_t len = rg.y - rg.x;
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pslot);
@@ -320,10 +322,13 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int PS = (GS + 3) & ~3;  // row of a partial-sum entry and of a gradient slot (whole float4)
   __shared__ float4 srec[kRound * kRecF4];
   // per wave, per batch position and pixel: w and dL/dpower as bf16 hi + lo
-  __shared__ __attribute__((aligned(16))) uint16_t awh[NW][kBwdBatch][CP];
-  __shared__ __attribute__((aligned(16))) uint16_t awl[NW][kBwdBatch][CP];
-  __shared__ __attribute__((aligned(16))) uint16_t aph[NW][kBwdBatch][CP];
-  __shared__ __attribute__((aligned(16))) uint16_t apl[NW][kBwdBatch][CP];
+  // (one array: before the first batch it holds each wave's channel gradients
+  // for the exchange into the MFMA operand layout)
+  __shared__ __attribute__((aligned(16))) uint16_t acf[4][NW][kBwdBatch][CP];
+  uint16_t (&awh)[NW][kBwdBatch][CP] = acf[0];
+  uint16_t (&awl)[NW][kBwdBatch][CP] = acf[1];
+  uint16_t (&aph)[NW][kBwdBatch][CP] = acf[2];
+  uint16_t (&apl)[NW][kBwdBatch][CP] = acf[3];
   __shared__ __attribute__((aligned(16))) float part[NW][kRound][PS];  // per-wave partial rows of the round's entries
   __shared__ int sent[NW][kBwdBatch];     // round entry of each batch position
   __shared__ uint32_t sslot[kRound];      // gradient slot of each round entry
@@ -352,32 +357,48 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   // B operands of the MFMAs (v_mfma_f32_16x16x32_bf16): K block kb covers
   // pixels 32 kb .. 32 kb + 31 of this wave; lane l supplies feature l % 16 of
   // pixels 32 kb + 8 (l / 16) + i, i = 0..7: the channel gradients split into
-  // bf16 hi + lo, the pixel-coordinate moments (small integers, exact).
+  // bf16 hi + lo, the pixel-coordinate moments (small integers, exact). The
+  // gradients reach that layout through the wave's rows of LDS (stride GXS,
+  // so that the 16 channel rows of one read fall in different banks).
+  constexpr int GXS = 68;
+  static_assert(NW * CS * GXS * 4 <= (int)sizeof(acf), "exchange rows fit the coefficient array");
+  float* gx = reinterpret_cast<float*>(&acf[0][0][0][0]) + wv * CS * GXS;
+#pragma unroll
+  for (int c = 0; c < CS; ++c) gx[c * GXS + lane] = G[c];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int fcol = lane & 15;
   bf8v bG0h[2], bG0l[2], bG1h[2], bG1l[2], bM[2];
 #pragma unroll
   for (int kb = 0; kb < 2; ++kb) {
+    const int q0 = 32 * kb + 8 * (lane >> 4);  // first of the lane's 8 pixels in the wave
+    float g0[8], g1[8];
+    if (fcol < CS) {
+      const float4 a = *reinterpret_cast<const float4*>(&gx[fcol * GXS + q0]);
+      const float4 b = *reinterpret_cast<const float4*>(&gx[fcol * GXS + q0 + 4]);
+      g0[0] = a.x; g0[1] = a.y; g0[2] = a.z; g0[3] = a.w;
+      g0[4] = b.x; g0[5] = b.y; g0[6] = b.z; g0[7] = b.w;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) g0[i] = 0.f;
+    }
+    if (16 + fcol < CS) {
+      const float4 a = *reinterpret_cast<const float4*>(&gx[(16 + fcol) * GXS + q0]);
+      const float4 b = *reinterpret_cast<const float4*>(&gx[(16 + fcol) * GXS + q0 + 4]);
+      g1[0] = a.x; g1[1] = a.y; g1[2] = a.z; g1[3] = a.w;
+      g1[4] = b.x; g1[5] = b.y; g1[6] = b.z; g1[7] = b.w;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) g1[i] = 0.f;
+    }
     uint16_t h0[8], l0[8], h1[8], l1[8], m[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int q = 64 * wv + 32 * kb + 8 * (lane >> 4) + i;  // pixel of thread q
-      const int lx = tile_lx(q), ly = tile_ly(q);
-      const int gx = x0 + lx, gy = y0 + ly;
-      const bool in = gx < V.W && gy < V.H;
-      const size_t pix = (size_t)gy * V.W + gx;
-      float g0 = 0.f, g1 = 0.f;
-      if (in) {
-        const int c0 = fcol;
-        if (c0 < CS) {
-          g0 = c0 < 3 ? dout.rgb[3 * pb + c0 * HW + pix]
-                      : (c0 == 3 ? dout.depth[pb + pix] : dout.feat[NF * pb + (c0 - 4) * HW + pix]);
-        }
-        const int c1 = 16 + fcol;
-        if (c1 < CS) g1 = dout.feat[NF * pb + (c1 - 4) * HW + pix];
-      }
-      bf_split(g0, h0[i], l0[i]);
-      bf_split(g1, h1[i], l1[i]);
-      const float fx = (float)lx, fy = (float)ly;
+      const int q = 64 * wv + q0 + i;  // pixel of thread q
+      bf_split(g0[i], h0[i], l0[i]);
+      bf_split(g1[i], h1[i], l1[i]);
+      const float fx = (float)tile_lx(q), fy = (float)tile_ly(q);
       m[i] = bf_rne(fcol == 0 ? 1.f : fcol == 1 ? fx : fcol == 2 ? fy : fcol == 3 ? fx * fx
                     : fcol == 4 ? fx * fy : fcol == 5 ? fy * fy : 0.f);
     }
@@ -550,22 +571,27 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     uint64_t bits = __ballot(mine);
     int nb = 0;
     // back to front over this wave's entries; entries no pixel of the wave
-    // uses are left out of the batches (their partial rows stay zero)
-    while (bits) {
-      const int j = 63 - __builtin_clzll(bits);
-      bits &= ~(1ull << j);
+    // uses are left out of the batches (their partial rows stay zero). Two
+    // entries are taken at a time: everything that does not depend on T
+    // (footprint, alpha, the channel dot product) is formed for both before
+    // the T recursion consumes them in order, so the two chains overlap.
+    struct Cand {
+      int j;
+      bool use;
+      float raw, alpha, ioma, dotg;
+    };
+    auto prepare = [&](int j) {
+      Cand c;
+      c.j = j;
       const float4 g0 = srec[j * kRecF4];
       const float4 g1 = srec[j * kRecF4 + 1];
       float dx, dy;
       const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
       // same alpha threshold as the forward
-      const bool use = (uint32_t)(rlo + j) < last && power <= 0.f && power >= g1.z;
-      if (!__ballot(use)) continue;
-      float wgt = 0.f, dpow = 0.f;
-      const float raw = g1.y * __expf(power);
-      const float alpha = fminf(amax, raw);
-      const float ioma = __builtin_amdgcn_rcpf(1.f - alpha);
-      const float Tk = T * ioma;
+      c.use = (uint32_t)(rlo + j) < last && power <= 0.f && power >= g1.z;
+      c.raw = g1.y * __expf(power);
+      c.alpha = fminf(amax, c.raw);
+      c.ioma = __builtin_amdgcn_rcpf(1.f - c.alpha);
       float dot0 = 0.f, dot1 = 0.f;  // two independent chains
 #pragma unroll
       for (int c4 = 0; c4 < CS4; ++c4) {
@@ -575,14 +601,20 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
         dot0 = fmaf(G[4 * c4 + 2], v.z, dot0);
         dot1 = fmaf(G[4 * c4 + 3], v.w, dot1);
       }
-      const float dotg = dot0 + dot1;
-      const float w_ = alpha * Tk;
-      const float dalpha = Tk * dotg - (sacc + GT * Tf) * ioma;
-      if (use) {
+      c.dotg = dot0 + dot1;
+      return c;
+    };
+    auto consume = [&](const Cand& c) {
+      if (!__ballot(c.use)) return;
+      float wgt = 0.f, dpow = 0.f;
+      const float Tk = T * c.ioma;
+      const float w_ = c.alpha * Tk;
+      const float dalpha = Tk * c.dotg - (sacc + GT * Tf) * c.ioma;
+      if (c.use) {
         T = Tk;
         wgt = w_;
-        sacc = fmaf(w_, dotg, sacc);
-        dpow = raw < amax ? dalpha * alpha : 0.f;
+        sacc = fmaf(w_, c.dotg, sacc);
+        dpow = c.raw < amax ? dalpha * c.alpha : 0.f;
       }
       uint16_t hi, lo;
       const int sp = lane ^ ((nb & 7) << 3);  // swizzled position of this pixel in row nb
@@ -592,10 +624,25 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
       bf_split(dpow, hi, lo);
       aph[wv][nb][sp] = hi;
       apl[wv][nb][sp] = lo;
-      if (lane == 0) sent[wv][nb] = j;
-      if (++nb == kBwdBatch) {
+      if (lane == 0) sent[wv][nb] = c.j;
+      ++nb;
+    };
+    while (bits) {
+      const int j1 = 63 - __builtin_clzll(bits);
+      bits &= ~(1ull << j1);
+      if (nb > kBwdBatch - 2) {  // room for two more rows
         flush(nb);
         nb = 0;
+      }
+      const Cand c1 = prepare(j1);
+      if (bits) {
+        const int j2 = 63 - __builtin_clzll(bits);
+        bits &= ~(1ull << j2);
+        const Cand c2 = prepare(j2);
+        consume(c1);
+        consume(c2);
+      } else {
+        consume(c1);
       }
     }
     if (nb > 0) flush(nb);

@@ -42,6 +42,7 @@ struct RenderConst {
   int32_t total_tiles;
   int32_t total_pix;
   int64_t cap;         // intersection capacity
+  int32_t n_cu;        // compute units of the device (issue-priority bands of the blend kernels)
 };
 
 // Header at the start of every render context (device memory).
