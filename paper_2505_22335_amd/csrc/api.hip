@@ -266,7 +266,7 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.ptile = take((size_t)capc * 4);
   L.pmask = take((size_t)capc);
   L.ranges = take((size_t)total_tiles * 8);
-  L.torder = take((size_t)total_tiles * 4);
+  L.binfo = take((size_t)total_tiles * 16);
   L.tfinal = take((size_t)total_pix * 4);
   L.ncontrib = take((size_t)total_pix * 4);
   L.gslot = take((size_t)capc * L.gs * sizeof(float));

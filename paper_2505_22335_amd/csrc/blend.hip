@@ -93,7 +93,9 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
                                                            char* ctx, CtxLayout L, asgs_images out) {
   constexpr int CS = 4 + NF;
   constexpr int CS4 = CS / 4;
-  const int tile = (int)ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];  // longest lists first
+  uint4* binfo = ctx_ptr<uint4>(ctx, L.binfo);
+  const uint4 bi = binfo[blockIdx.x];  // longest lists first
+  const int tile = (int)bi.x;
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
   const int lt = tile - V.tile_base;
@@ -109,7 +111,7 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   const int py = y0 + tile_ly(tq);
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
-  const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
+  const uint2 rg = make_uint2(bi.y, bi.z);
   prioritise(blockIdx.x, rc.n_cu);
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
@@ -229,6 +231,12 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
     }
     if (__ballot(fix)) run(nf, n, base, fix, true);
   }
+  // the list length the backward walks: the tile's largest last contributor
+  if (!back) {
+    uint32_t lm = inside ? last : 0u;
+    for (int o = 32; o > 0; o >>= 1) lm = max(lm, (uint32_t)__shfl_xor((int)lm, o));
+    if (lane == 0 && lm > 0u) atomicMax(&binfo[blockIdx.x].w, lm);
+  }
   if (back || !inside) return;
   const size_t HW = (size_t)V.W * V.H;
   const size_t pix = (size_t)py * V.W + px;
@@ -293,7 +301,8 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
   constexpr int CP = 64;          // row of 64 pixel coefficients (bf16), 8-pixel groups XOR-swizzled by row
-  const int tile = (int)ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];  // longest lists first
+  const uint4 bi = ctx_ptr<const uint4>(ctx, L.binfo)[blockIdx.x];  // longest lists first
+  const int tile = (int)bi.x;
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
   const int lt = tile - V.tile_base;
@@ -306,9 +315,10 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   const int py = y0 + tile_ly(t);
   const bool inside = px < V.W && py < V.H;
   const float pxf = (float)px, pyf = (float)py;
-  const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
+  const uint2 rg = make_uint2(bi.y, bi.z);
   prioritise(blockIdx.x, rc.n_cu);
   const uint32_t len = rg.y - rg.x;
+  const uint32_t nproc = bi.w;  // entries behind every pixel's last Gaussian are not walked
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pslot);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
@@ -333,8 +343,20 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   __shared__ int sent[NW][kBwdBatch];     // round entry of each batch position
   __shared__ uint32_t sslot[kRound];      // gradient slot of each round entry
   __shared__ uint8_t smk[kRound];         // quarter mask of each round entry (from the forward)
-  __shared__ uint32_t smax;
 
+  // The Gaussian ids of the first round (the back kRound entries of the
+  // walked list) are requested before anything else.
+  uint32_t gid_next[kPer];
+  auto fetch_gid = [&](int lo_r, int cnt_r) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int ent = (t + k * kTilePix) / kRecF4;
+      gid_next[k] = ent < cnt_r ? pairgid[rg.x + lo_r + ent] : 0u;
+    }
+  };
+  int rhi = (int)nproc;
+  int rlo = rhi - kRound > 0 ? rhi - kRound : 0;
+  if (rhi > 0) fetch_gid(rlo, rhi - rlo);
   const size_t HW = (size_t)V.W * V.H;
   const size_t pb = (size_t)V.pix_base;
   float Tf = 1.f;
@@ -412,11 +434,6 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     }
   }
 
-  if (t == 0) smax = 0u;
-  __syncthreads();
-  atomicMax(&smax, last);
-  __syncthreads();
-  const uint32_t nproc = smax;
   // entries behind every pixel's last Gaussian get zero gradient
   for (uint32_t q = nproc + t; q < len; q += kTilePix) {
     float4* dst = reinterpret_cast<float4*>(gslot + (size_t)pslot[rg.x + q] * PS);
@@ -433,14 +450,6 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   // no load of the staging waits on another.
   float4 stage[kPer];
   uint32_t stage_slot = 0u, stage_mask = 0u;
-  uint32_t gid_next[kPer];
-  auto fetch_gid = [&](int lo_r, int cnt_r) {
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int ent = (t + k * kTilePix) / kRecF4;
-      gid_next[k] = ent < cnt_r ? pairgid[rg.x + lo_r + ent] : 0u;
-    }
-  };
   auto fetch = [&](int lo_r, int cnt_r) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -538,10 +547,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  int rhi = (int)nproc;
-  int rlo = rhi - kRound > 0 ? rhi - kRound : 0;
   if (rhi > 0) {
-    fetch_gid(rlo, rhi - rlo);
     fetch(rlo, rhi - rlo);
     const int nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
     if (rlo > 0) fetch_gid(nrlo, rlo - nrlo);

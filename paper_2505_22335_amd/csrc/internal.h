@@ -64,9 +64,11 @@ struct CtxHeader {
 //  tcur                per tile: intersection count, then the emission cursor
 //  ukey, tkey          per intersection: (depth << 32 | gid) in emission order; merge scratch
 //  pairgid, pslot, ptile  per sorted intersection: Gaussian, gradient slot, tile key
+//  binfo               per blend position (longest list first): tile, start, end, and the
+//                      list length the backward walks (largest last contributor + 1)
 struct CtxLayout {
   size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, tcur, ukey, tkey, pairgid, pslot,
-      ptile, pmask, ranges, torder, tfinal, ncontrib, gslot, posepart;
+      ptile, pmask, ranges, binfo, tfinal, ncontrib, gslot, posepart;
   size_t total;
   int64_t nv, cap;
   int32_t total_tiles, total_pix, cs, gs, pose_blocks;

@@ -158,7 +158,8 @@ __global__ void __launch_bounds__(kScanThreads) k_dup_upsweep(RenderConst rc, co
 
 // ---------------------------------------------------------------------------
 // One workgroup: the tile ranges [start, end) from the list lengths, the
-// emission cursors (= starts), the totals and the blend order of the tiles,
+// emission cursors (= starts), the totals and the blend order of the tiles
+// (per position: tile, start, end; the forward adds the walked length),
 // longest list first (a counting sort on the length; lengths of 1023 and more
 // share one bucket, and the order within a bucket is arbitrary, which changes
 // no result). When the intersections exceed the capacity every range is left
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   const int T = rc.total_tiles;
   uint32_t* tcur = ctx_ptr<uint32_t>(ctx, L.tcur);
   uint2* ranges = ctx_ptr<uint2>(ctx, L.ranges);
-  uint32_t* order = ctx_ptr<uint32_t>(ctx, L.torder);
+  uint4* binfo = ctx_ptr<uint4>(ctx, L.binfo);
   CtxHeader* hdr = ctx_ptr<CtxHeader>(ctx, L.hdr);
   // thread t owns the consecutive tiles [a0, a1)
   const int per = (T + kTileScanThreads - 1) / kTileScanThreads;
@@ -227,9 +228,10 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   unsigned long long run = before + incl - mine;
   for (int i = a0; i < a1; ++i) {
     const uint32_t c = tcur[i];
-    ranges[i] = ovf ? make_uint2(0u, 0u) : make_uint2((uint32_t)run, (uint32_t)(run + c));
+    const uint2 r = ovf ? make_uint2(0u, 0u) : make_uint2((uint32_t)run, (uint32_t)(run + c));
+    ranges[i] = r;
     tcur[i] = (uint32_t)run;
-    order[atomicAdd(&bins[order_bin(c)], 1u)] = (uint32_t)i;
+    binfo[atomicAdd(&bins[order_bin(c)], 1u)] = make_uint4((uint32_t)i, r.x, r.y, 0u);
     run += c;
   }
 }
@@ -347,8 +349,9 @@ struct ListOut {
 __global__ void __launch_bounds__(kListThreads) k_list_sort(RenderConst rc, const ViewDev* __restrict__ views,
                                                            char* ctx, CtxLayout L) {
   __shared__ unsigned long long sk[kListSort];
-  const uint32_t tile = ctx_ptr<const uint32_t>(ctx, L.torder)[blockIdx.x];
-  const uint2 rg = ctx_ptr<const uint2>(ctx, L.ranges)[tile];
+  const uint4 bi = ctx_ptr<const uint4>(ctx, L.binfo)[blockIdx.x];
+  const uint32_t tile = bi.x;
+  const uint2 rg = make_uint2(bi.y, bi.z);
   const uint32_t n = rg.y - rg.x;
   if (n == 0u) return;
   const int t = threadIdx.x;
