@@ -41,6 +41,7 @@ constexpr int kHS = 37;    // per-wave H rows (32 units), reused for the dX part
 constexpr int kTS = 33;    // per-wave transpose rows
 constexpr int kAcc = 4;    // second-layer row tiles accumulated per wave
 constexpr int kMaxWG = 256;
+constexpr int kMaxFwdWG = 384;
 constexpr int kDX = 36;    // floats per anchor of a dX partial in the workspace
 
 ASGS_DEV f4v mfma(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
@@ -350,7 +351,6 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
   const int A = (int)dc.A;
   const int k = dc.k;
   const int n = A * k;
-  stage_weights(S, gd, ht, params, k, t);
   // ---- this wave's head and rows ----
   HeadCtx hc;
   RowMap rm;
@@ -404,7 +404,10 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
       }
     }
   };
+  // the first tile's inputs are requested before the weights, so that the
+  // two latencies overlap
   if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
+  stage_weights(S, gd, ht, params, k, t);
   for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
     const int a0 = tile * 16;
     __syncthreads();  // weights staged / the previous tile's readers are done
@@ -552,7 +555,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
 // activations; outputs are staged per (head, component) plane in LDS and
 // written as the tile's contiguous runs of 16 k values. Group 0 of view 0
 // also writes the Gaussian means x_v + l_o O_i (shared by the views).
-__global__ void __launch_bounds__(kNT, 2) k_dec_fwd_heads(DecodeConst dc, HeadTable ht, DecodeViews dv,
+__global__ void __launch_bounds__(kNT, 3) k_dec_fwd_heads(DecodeConst dc, HeadTable ht, DecodeViews dv,
                                                           const float* __restrict__ xyz,
                                                           const float* __restrict__ feat,
                                                           const float* __restrict__ off,
@@ -570,7 +573,6 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_fwd_heads(DecodeConst dc, HeadTa
   const int A = (int)dc.A;
   const int k = dc.k;
   const int n = A * k;
-  stage_weights(S, gd, ht, params, k, t);
   HeadCtx hc;
   RowMap rm;
   int t0, nt;
@@ -580,7 +582,8 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_fwd_heads(DecodeConst dc, HeadTa
   const int nplanes = gd.gtot / run;
   const int ngrid = (A + 15) / 16;
   const int tk = t / k;  // anchor within the tile of the thread's output element
-  float xpre[2], ppre[3];
+  const bool means = grp == 0 && view == 0;  // this group also writes the Gaussian means
+  float xpre[2], ppre[3], mxp[3] = {0.f, 0.f, 0.f}, mop[3] = {0.f, 0.f, 0.f};
   auto fetch = [&](int tile) {
     const int a0 = tile * 16;
 #pragma unroll
@@ -591,8 +594,19 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_fwd_heads(DecodeConst dc, HeadTa
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) ppre[c] = (t < 16 && a0 + t < A) ? xyz[(size_t)c * A + a0 + t] : 0.f;
+    const size_t gidx = (size_t)a0 * k + t;
+    if (means && t < run && gidx < (size_t)n) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        mxp[c] = xyz[(size_t)c * A + a0 + tk];
+        mop[c] = off[(size_t)c * n + gidx];
+      }
+    }
   };
+  // the first tile's inputs are requested before the weights, so that the
+  // two latencies overlap
   if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
+  stage_weights(S, gd, ht, params, k, t);
   for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
     const int a0 = tile * 16;
     __syncthreads();  // weights staged / the previous tile's outputs are written
@@ -612,6 +626,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_fwd_heads(DecodeConst dc, HeadTa
       S.X[t][35] = 0.f;
       S.X[t][36] = 0.f;
     }
+    const float mx[3] = {mxp[0], mxp[1], mxp[2]}, mo[3] = {mop[0], mop[1], mop[2]};
     __syncthreads();
     if (tile + (int)gridDim.x < ngrid) fetch(tile + gridDim.x);
     head_forward(S, Hw, hc, fl, fg);
@@ -650,17 +665,16 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_fwd_heads(DecodeConst dc, HeadTa
         }
         out_plane(out, view, h, comp, n)[gidx] = S.G[pl * run + t];
       }
-      if (grp == 0 && view == 0) {
-        const int64_t a = a0 + tk;
+      if (means) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          out.mean[(size_t)c * n + gidx] = xyz[(size_t)c * A + a] + dc.l_o * off[(size_t)c * n + gidx];
+        for (int c = 0; c < 3; ++c) out.mean[(size_t)c * n + gidx] = mx[c] + dc.l_o * mo[c];
       }
     }
   }
 }
 
-GroupDesc group_desc(const HeadTable& ht, int k, int hbase, int nheads) {
+// LDS of one group; the forward needs no transpose rows (with_t false).
+GroupDesc group_desc(const HeadTable& ht, int k, int hbase, int nheads, bool with_t) {
   GroupDesc g{};
   g.hbase = hbase;
   g.nheads = nheads;
@@ -687,7 +701,7 @@ GroupDesc group_desc(const HeadTable& ht, int k, int hbase, int nheads) {
   g.L.X = take(16 * kXS);
   g.L.G = take(gb);
   g.L.H = take(kWaves * 16 * kHS);
-  g.L.T = take(kWaves * 16 * kTS);
+  g.L.T = with_t ? take(kWaves * 16 * kTS) : 0;
   g.L.total = o;
   return g;
 }
@@ -704,9 +718,9 @@ size_t dec_bwd_dx_floats(int64_t n_anchors) { return 2 * (size_t)n_anchors * kDX
 void launch_dec_fwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                           const float* feat, const float* off, const float* params, const asgs_gaussians& out,
                           hipStream_t s) {
-  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4);
+  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4, false);
   const bool has_feat = ht.m[4] > 0;
-  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1) : g0;
+  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1, false) : g0;
   const int ng = has_feat ? 2 : 1;
   const int lds = (g0.L.total > g1.L.total ? g0.L.total : g1.L.total) * (int)sizeof(float);
   static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (at most ~77 KiB for k = 16)
@@ -715,16 +729,19 @@ void launch_dec_fwd_heads(const DecodeConst& dc, const HeadTable& ht, const Deco
                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_dec_fwd_heads, dim3((unsigned)dec_bwd_heads_blocks(dc.A), (unsigned)(ng * dc.n_views)),
+  // up to three workgroups per compute unit (the forward's LDS allows it)
+  const int64_t tiles = (dc.A + 15) / 16;
+  const unsigned nblk = (unsigned)(tiles < kMaxFwdWG ? tiles : kMaxFwdWG);
+  hipLaunchKernelGGL(k_dec_fwd_heads, dim3(nblk, (unsigned)(ng * dc.n_views)),
                      dim3(kNT), lds, s, dc, ht, dv, xyz, feat, off, params, out, GroupPair{{g0, g1}}, ng);
 }
 
 void launch_dec_bwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                           const float* feat, const float* params, const asgs_gaussians& dg, int view,
                           const DecWork& w, bool want_params, hipStream_t s) {
-  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4);
+  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4, true);
   const bool has_feat = ht.m[4] > 0;
-  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1) : g0;
+  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1, true) : g0;
   const int lds = (g0.L.total > g1.L.total ? g0.L.total : g1.L.total) * (int)sizeof(float);
   static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (at most ~77 KiB for k = 16)
   if (!attr_set) {
