@@ -384,21 +384,30 @@ __global__ void __launch_bounds__(256) k_project_backward(RenderConst rc, asgs_g
   }
 }
 
-// Fixed-order sum of the per-block pose partials of each view.
+// Fixed-order sum of the per-block pose partials of each view: every thread
+// adds the six partials of its blocks, then six wave and workgroup sums.
 __global__ void __launch_bounds__(256) k_pose_reduce(int n_views, int nbx, const float* __restrict__ part,
                                                      float* d_pose) {
-  __shared__ float fin[256 / 64];
+  __shared__ float fin[6][256 / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int vv = 0; vv < n_views; ++vv) {
-    for (int k = 0; k < 6; ++k) {
-      float acc = 0.f;
-      for (int bx = threadIdx.x; bx < nbx; bx += blockDim.x) acc += part[((int64_t)vv * nbx + bx) * 6 + k];
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-      __syncthreads();
-      if (lane == 0) fin[wv] = acc;
-      __syncthreads();
-      if (threadIdx.x == 0) d_pose[vv * 6 + k] = (fin[0] + fin[1]) + (fin[2] + fin[3]);
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int bx = threadIdx.x; bx < nbx; bx += blockDim.x) {
+      const float* p = part + ((int64_t)vv * nbx + bx) * 6;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[k] += p[k];
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+      if (lane == 0) fin[k][wv] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const int k = threadIdx.x;
+      d_pose[vv * 6 + k] = (fin[k][0] + fin[k][1]) + (fin[k][2] + fin[k][3]);
+    }
+    __syncthreads();
   }
 }
 
