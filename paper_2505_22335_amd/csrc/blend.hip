@@ -134,10 +134,20 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   const float amax = rc.alpha_max, tmin = rc.T_min;
   // Composite list positions [i0, i1) of this wave's round list. real: the
   // running state with the T_min stop; otherwise a local back-half state.
+  // The next entry's index and geometry are read from LDS while the current
+  // one is composited.
   auto run = [&](int i0, int i1, uint32_t base, bool act, bool real) {
+    if (i0 >= i1) return;
+    int jn = __builtin_amdgcn_readfirstlane(swl[wv][i0]);
+    float4 g0n = sg[2 * jn], g1n = sg[2 * jn + 1];
     for (int i = i0; i < i1; ++i) {
-      const int j = __builtin_amdgcn_readfirstlane(swl[wv][i]);
-      const float4 g0 = sg[2 * j], g1 = sg[2 * j + 1];
+      const int j = jn;
+      const float4 g0 = g0n, g1 = g1n;
+      if (i + 1 < i1) {
+        jn = __builtin_amdgcn_readfirstlane(swl[wv][i + 1]);
+        g0n = sg[2 * jn];
+        g1n = sg[2 * jn + 1];
+      }
       float dx, dy;
       const float power = eval_power(g0.x, g0.y, g0.z, g0.w, g1.x, pxf, pyf, dx, dy);
       // alpha >= alpha_min  <=>  power >= ln(alpha_min / o) (record slot 6)
