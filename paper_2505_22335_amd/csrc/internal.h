@@ -143,6 +143,58 @@ namespace asgs {
 template <typename T>
 ASGS_DEV T* ctx_ptr(char* ctx, size_t off) { return reinterpret_cast<T*>(ctx + off); }
 
+// ---------------------------------------------------------------------------
+// Binning blocks: kScanThreads consecutive (view, Gaussian) pairs of one view,
+// one per thread. A block's intersections reach the per-tile counters through
+// an LDS grid over the bounding box of its Gaussians' rectangles (Gaussians of
+// one block are mostly neighbours in space), so a hot tile takes one global
+// atomic per block instead of one per Gaussian. Gaussians with a rectangle
+// of more than kBoxRect tiles, and every Gaussian of a block whose box has
+// more than kBoxCells tiles, use the global counters directly.
+// ---------------------------------------------------------------------------
+constexpr int kBoxCells = 4096;
+constexpr int kBoxRect = 64;
+
+struct TileBox {
+  int x0, y0, w, area;  // LDS cell of tile (tx, ty): (ty - y0) * w + tx - x0
+  bool lds;             // block-uniform: the box fits kBoxCells
+};
+
+template <typename T>
+ASGS_DEV T wave_min(T v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Bounding box of the rects of the lanes with small set; clears its cells.
+ASGS_DEV TileBox tile_box(short4 r, bool small, int* red, uint32_t* cell) {
+  const int t = threadIdx.x;
+  if (t < 4) red[t] = 0x7FFFFFFF;
+  __syncthreads();
+  const int big = 0x7FFFFFFF;
+  const int x0 = wave_min(small ? (int)r.x : big), nx1 = wave_min(small ? -(int)r.y : big);
+  const int y0 = wave_min(small ? (int)r.z : big), ny1 = wave_min(small ? -(int)r.w : big);
+  if ((t & 63) == 0) {
+    atomicMin(&red[0], x0);
+    atomicMin(&red[1], nx1);
+    atomicMin(&red[2], y0);
+    atomicMin(&red[3], ny1);
+  }
+  __syncthreads();
+  TileBox b;
+  b.x0 = red[0];
+  b.y0 = red[2];
+  b.lds = b.x0 != big;
+  b.w = b.lds ? -red[1] - b.x0 + 1 : 0;
+  const int h = b.lds ? -red[3] - b.y0 + 1 : 0;
+  b.area = b.w * h;
+  b.lds = b.lds && b.area <= kBoxCells;
+  if (b.lds)
+    for (int c = t; c < b.area; c += kScanThreads) cell[c] = 0u;
+  __syncthreads();
+  return b;
+}
+
 // View of a global tile key (views are stored in tile_base order).
 ASGS_DEV int find_view(const ViewDev* views, int n_views, int tile) {
   int v = 0;

@@ -6,7 +6,9 @@
 // (rgb, camera depth, feature) in array-of-structures form so the blend
 // kernels fetch one contiguous record per list entry; plus the tile rectangle,
 // the tile count and the 32-bit depth key (float bits of camera depth, which
-// order like the floats since depth > znear > 0).
+// order like the floats since depth > znear > 0). Each workgroup is also a
+// binning block: it adds its Gaussians to the per-tile intersection counters
+// and writes its tile-count sum and visible count.
 #include "internal.h"
 
 namespace asgs {
@@ -137,15 +139,16 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
                                                  CtxLayout L) {
   constexpr int CS = 4 + NF;
   const int view = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rc.n) return;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i0 < rc.n;  // every thread reaches the block's tile counting below
+  const int64_t i = valid ? i0 : 0;
   const ViewDev& V = views[view];
   const int64_t gid = (int64_t)view * rc.n + i;
   float m[3], s[3], q[4], o;
   load_gauss(g, view, i, rc.n, m, s, q, o);
   Proj P;
   bool vis = proj_core(V, m, s, q, rc.dilation, rc.znear, P);
-  vis = vis && (P.det > 0.f) && (o > rc.alpha_min);
+  vis = valid && vis && (P.det > 0.f) && (o > rc.alpha_min);
   float u = 0.f, v = 0.f, A = 0.f, B = 0.f, C = 0.f;
   int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
   if (vis) {
@@ -176,11 +179,12 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
   uint32_t* ntiles = ctx_ptr<uint32_t>(ctx, L.ntiles);
   uint32_t* dkey = ctx_ptr<uint32_t>(ctx, L.dkey);
   if (!vis) {
-    rect[gid] = make_short4(1, 0, 1, 0);
-    ntiles[gid] = 0u;
-    dkey[gid] = 0xFFFFFFFFu;
-    return;
-  }
+    if (valid) {
+      rect[gid] = make_short4(1, 0, 1, 0);
+      ntiles[gid] = 0u;
+      dkey[gid] = 0xFFFFFFFFu;
+    }
+  } else {
   geom[2 * gid] = make_float4(u, v, A, B);
   // slot 6: the power at which o exp(power) reaches alpha_min, so that the
   // blend kernels test alpha >= alpha_min without an exponential
@@ -201,6 +205,51 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
   rect[gid] = make_short4((short)tx0, (short)tx1, (short)ty0, (short)ty1);
   ntiles[gid] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
   dkey[gid] = __float_as_uint(P.t[2]);
+  }
+  // Binning block (the workgroup's pairs): its intersections into the per-tile
+  // counters, its tile-count sum and number of visible pairs.
+  __shared__ unsigned long long red[256 / 64];
+  __shared__ uint32_t vred[256 / 64];
+  __shared__ int bred[4];
+  __shared__ uint32_t cell[kBoxCells];
+  const uint32_t cnt = vis ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u;
+  const short4 r = vis ? make_short4((short)tx0, (short)tx1, (short)ty0, (short)ty1) : make_short4(1, 0, 1, 0);
+  uint32_t* tcount = ctx_ptr<uint32_t>(ctx, L.tcur);
+  const bool small = cnt > 0u && cnt <= (uint32_t)kBoxRect;
+  const TileBox bx = tile_box(r, small, bred, cell);
+  const bool via_lds = bx.lds && small;
+  for (int ty = r.z; ty <= r.w; ++ty)
+    for (int tx = r.x; tx <= r.y; ++tx) {
+      if (via_lds) atomicAdd(&cell[(ty - bx.y0) * bx.w + tx - bx.x0], 1u);
+      else __hip_atomic_fetch_add(&tcount[V.tile_base + ty * V.TX + tx], 1u, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+    }
+  __syncthreads();
+  if (bx.lds)
+    for (int c = threadIdx.x; c < bx.area; c += blockDim.x) {
+      const uint32_t k = cell[c];
+      if (k) {
+        const int cy = c / bx.w;
+        __hip_atomic_fetch_add(&tcount[V.tile_base + (bx.y0 + cy) * V.TX + bx.x0 + c - cy * bx.w], k,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  unsigned long long sum = cnt;
+  uint32_t nvis = cnt > 0u ? 1u : 0u;
+  for (int off = 32; off > 0; off >>= 1) {
+    sum += __shfl_xor(sum, off);
+    nvis += __shfl_xor(nvis, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = sum;
+    vred[threadIdx.x >> 6] = nvis;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;  // binning block
+    ctx_ptr<uint32_t>(ctx, L.bsum)[b] = (uint32_t)((red[0] + red[1]) + (red[2] + red[3]));
+    ctx_ptr<uint32_t>(ctx, L.vsum)[b] = (vred[0] + vred[1]) + (vred[2] + vred[3]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -428,6 +477,7 @@ void launch_set_views(const ViewDev* host_views, int n_views, ViewDev* dev_views
 
 void launch_project(const RenderConst& rc, const asgs_gaussians& g, const CtxLayout& L, char* ctx,
                     hipStream_t s) {
+  static_assert(kScanThreads == 256, "a projection workgroup is one binning block");
   dim3 grid((unsigned)((rc.n + 255) / 256), (unsigned)rc.n_views);
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
   if (rc.nf == 16)

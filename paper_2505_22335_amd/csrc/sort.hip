@@ -33,18 +33,7 @@ ASGS_DEV T wave_incl_scan(T v, int lane) {
   return v;
 }
 
-// ---------------------------------------------------------------------------
-// Binning blocks: kScanThreads consecutive (view, Gaussian) pairs of one view,
-// one per thread. A block's intersections reach the per-tile counters through
-// an LDS grid over the bounding box of its Gaussians' rectangles (Gaussians of
-// one block are mostly neighbours in space), so a hot tile takes one global
-// atomic per block instead of one per Gaussian. Gaussians with a rectangle
-// of more than kBoxRect tiles, and every Gaussian of a block whose box has
-// more than kBoxCells tiles, use the global counters directly.
-// ---------------------------------------------------------------------------
-constexpr int kBoxCells = 4096;
-constexpr int kBoxRect = 64;
-
+// The block's (view, Gaussian) pair of this thread.
 struct ScanBlock {
   int view;
   int64_t j;     // this thread's pair
@@ -59,101 +48,6 @@ ASGS_DEV ScanBlock scan_block(const RenderConst& rc) {
   sb.valid = i < rc.n;
   sb.j = (int64_t)sb.view * rc.n + i;
   return sb;
-}
-
-struct TileBox {
-  int x0, y0, w, area;  // LDS cell of tile (tx, ty): (ty - y0) * w + tx - x0
-  bool lds;             // block-uniform: the box fits kBoxCells
-};
-
-template <typename T>
-ASGS_DEV T wave_min(T v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
-}
-
-// Bounding box of the rects of the lanes with small set; clears its cells.
-ASGS_DEV TileBox tile_box(short4 r, bool small, int* red, uint32_t* cell) {
-  const int t = threadIdx.x;
-  if (t < 4) red[t] = 0x7FFFFFFF;
-  __syncthreads();
-  const int big = 0x7FFFFFFF;
-  const int x0 = wave_min(small ? (int)r.x : big), nx1 = wave_min(small ? -(int)r.y : big);
-  const int y0 = wave_min(small ? (int)r.z : big), ny1 = wave_min(small ? -(int)r.w : big);
-  if ((t & 63) == 0) {
-    atomicMin(&red[0], x0);
-    atomicMin(&red[1], nx1);
-    atomicMin(&red[2], y0);
-    atomicMin(&red[3], ny1);
-  }
-  __syncthreads();
-  TileBox b;
-  b.x0 = red[0];
-  b.y0 = red[2];
-  b.lds = b.x0 != big;
-  b.w = b.lds ? -red[1] - b.x0 + 1 : 0;
-  const int h = b.lds ? -red[3] - b.y0 + 1 : 0;
-  b.area = b.w * h;
-  b.lds = b.lds && b.area <= kBoxCells;
-  if (b.lds)
-    for (int c = t; c < b.area; c += kScanThreads) cell[c] = 0u;
-  __syncthreads();
-  return b;
-}
-
-// Per binning block: the tile-count sum and the number of visible pairs, and
-// the intersections added to the per-tile counters.
-__global__ void __launch_bounds__(kScanThreads) k_dup_upsweep(RenderConst rc, const ViewDev* __restrict__ views,
-                                                              char* ctx, CtxLayout L) {
-  __shared__ unsigned long long red[kScanThreads / 64];
-  __shared__ uint32_t vred[kScanThreads / 64];
-  __shared__ int bred[4];
-  __shared__ uint32_t cell[kBoxCells];
-  const ScanBlock sb = scan_block(rc);
-  const ViewDev& V = views[sb.view];
-  const uint32_t cnt = sb.valid ? ctx_ptr<const uint32_t>(ctx, L.ntiles)[sb.j] : 0u;
-  const short4 r = cnt > 0u ? ctx_ptr<const short4>(ctx, L.rect)[sb.j] : make_short4(1, 0, 1, 0);
-  uint32_t* tcount = ctx_ptr<uint32_t>(ctx, L.tcur);
-  const bool small = cnt > 0u && cnt <= (uint32_t)kBoxRect;
-  const TileBox bx = tile_box(r, small, bred, cell);
-  const bool via_lds = bx.lds && small;
-  for (int ty = r.z; ty <= r.w; ++ty)
-    for (int tx = r.x; tx <= r.y; ++tx) {
-      if (via_lds) atomicAdd(&cell[(ty - bx.y0) * bx.w + tx - bx.x0], 1u);
-      else __hip_atomic_fetch_add(&tcount[V.tile_base + ty * V.TX + tx], 1u, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-    }
-  __syncthreads();
-  if (bx.lds)
-    for (int c = threadIdx.x; c < bx.area; c += kScanThreads) {
-      const uint32_t k = cell[c];
-      if (k) {
-        const int cy = c / bx.w;
-        __hip_atomic_fetch_add(&tcount[V.tile_base + (bx.y0 + cy) * V.TX + bx.x0 + c - cy * bx.w], k,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-  unsigned long long s = cnt;
-  uint32_t vis = cnt > 0u ? 1u : 0u;
-  for (int off = 32; off > 0; off >>= 1) {
-    s += __shfl_xor(s, off);
-    vis += __shfl_xor(vis, off);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = s;
-    vred[threadIdx.x >> 6] = vis;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long tot = 0;
-    uint32_t vt = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) {
-      tot += red[w];
-      vt += vred[w];
-    }
-    ctx_ptr<uint32_t>(ctx, L.bsum)[blockIdx.x] = (uint32_t)tot;
-    ctx_ptr<uint32_t>(ctx, L.vsum)[blockIdx.x] = vt;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -435,7 +329,6 @@ __global__ void __launch_bounds__(kListThreads) k_list_sort(RenderConst rc, cons
 void launch_bin(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s) {
   const unsigned nblk = (unsigned)scan_blocks(rc.n, rc.n_views);
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
-  if (nblk > 0) hipLaunchKernelGGL(k_dup_upsweep, dim3(nblk), dim3(kScanThreads), 0, s, rc, views, ctx, L);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTileScanThreads), 0, s, rc, ctx, L);
   if (nblk > 0) hipLaunchKernelGGL(k_dup_emit, dim3(nblk), dim3(kScanThreads), 0, s, rc, views, ctx, L);
 }
