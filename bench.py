@@ -228,7 +228,6 @@ def main():
 
     import synth
     from paper_2505_22335_amd import _lib as L
-    from paper_2505_22335_amd.core import l1_loss_grad
     from paper_2505_22335_amd.pipeline import AnchorRenderer, anchors_to_device
 
     if args.serve_only:
@@ -253,9 +252,9 @@ def main():
     scale = {k: 1.0 / v.numel() for k, v in tgt.items()}
 
     def step():
-        img = r.forward()
-        # L1 loss gradient, mean over each output (one fused library kernel)
-        l1_loss_grad(img, tgt, dimg, scale)
+        # render with the L1 residual gradient (mean over each output) formed
+        # in the forward's output stage, then the backward
+        r.forward_l1(tgt, dimg, scale)
         r.backward(dimg)
 
     if args.copy_probe_mb:

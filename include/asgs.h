@@ -267,6 +267,23 @@ int asgs_l1_loss(int32_t n_views, int32_t width, int32_t height, int32_t n_feat,
                  const asgs_l1_targets* targets, const asgs_images* grad, float* loss, void* work,
                  size_t work_bytes, void* stream);
 
+/* Forward render fused with the weighted L1 residual: the same images as
+ * asgs_render_forward, plus, in the forward's output stage, exactly the
+ * gradient planes asgs_l1_loss(out, targets, grad) would write (same
+ * arithmetic, bitwise equal) and, if loss is not NULL (device [n_views]),
+ * the per-view loss as a fixed-order sum over tiles (equal to asgs_l1_loss's
+ * value up to the order of the FP32 sum). Saves the separate pass over the
+ * maps (the tracking loss of Sec. 3.4 in one kernel). targets and grad are
+ * packed like the images (weight [H][W] shared by the views); a group
+ * without target gets a zeroed gradient plane, NULL gradient planes are not
+ * written; with n_feat = 0 the feature group is ignored. ctx and the
+ * capacity rules are those of asgs_render_forward; after an overflow the
+ * residual is that of the incomplete images. */
+int asgs_render_forward_l1(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                           const asgs_render_opts* opts, const asgs_images* out,
+                           const asgs_l1_targets* targets, const asgs_images* grad, float* loss,
+                           void* ctx, size_t ctx_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Timing hook (for measurement tools; off by default)
  *

@@ -84,6 +84,9 @@ _sigs = {
                                     P, C.c_size_t, C.POINTER(C.c_int64), P]),
     "asgs_render_forward": (C.c_int, [C.POINTER(Camera), C.c_int32, C.POINTER(Gaussians),
                                       C.POINTER(RenderOpts), C.POINTER(Images), P, C.c_size_t, P]),
+    "asgs_render_forward_l1": (C.c_int, [C.POINTER(Camera), C.c_int32, C.POINTER(Gaussians),
+                                         C.POINTER(RenderOpts), C.POINTER(Images), C.POINTER(L1Targets),
+                                         C.POINTER(Images), P, P, C.c_size_t, P]),
     "asgs_render_backward": (C.c_int, [C.POINTER(Camera), C.c_int32, C.POINTER(Gaussians),
                                        C.POINTER(RenderOpts), C.POINTER(Images), C.POINTER(Gaussians), P, P,
                                        C.c_size_t, P]),
@@ -213,6 +216,14 @@ def render_forward(cams, g: Gaussians, opts: RenderOpts, out: Images, ctx, strea
     ca = make_cameras(cams)
     check(lib.asgs_render_forward(ca, len(cams), C.byref(g), C.byref(opts), C.byref(out), ctx.data_ptr(),
                                   ctx.numel(), _stream(stream)), "asgs_render_forward")
+
+
+def render_forward_l1(cams, g: Gaussians, opts: RenderOpts, out: Images, targets: "L1Targets", grad: Images,
+                      loss, ctx, stream=None):
+    ca = make_cameras(cams)
+    check(lib.asgs_render_forward_l1(ca, len(cams), C.byref(g), C.byref(opts), C.byref(out), C.byref(targets),
+                                     C.byref(grad), _ptr(loss), ctx.data_ptr(), ctx.numel(), _stream(stream)),
+          "asgs_render_forward_l1")
 
 
 def render_backward(cams, g: Gaussians, opts: RenderOpts, dout: Images, dg: Gaussians, d_pose, ctx,

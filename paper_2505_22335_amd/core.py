@@ -115,6 +115,17 @@ class RenderContext:
         L.render_forward(self.cams, L.make_gaussians(g, self.n), self.opts, L.make_images(out), self.ctx)
         return out
 
+    def forward_l1(self, g: Dict[str, torch.Tensor], targets: Dict[str, torch.Tensor],
+                   grad: Dict[str, torch.Tensor], scale: Dict[str, float], weight: Optional[torch.Tensor] = None,
+                   loss: Optional[torch.Tensor] = None, out: Optional[Dict[str, torch.Tensor]] = None):
+        """Forward render and the weighted L1 residual gradient (and, with
+        loss, the per-view loss) in one pass (asgs_render_forward_l1): the
+        images and grad as render_forward followed by l1_loss_grad."""
+        out = out if out is not None else self.new_images()
+        L.render_forward_l1(self.cams, L.make_gaussians(g, self.n), self.opts, L.make_images(out),
+                            l1_targets(targets, scale, weight), L.make_images(grad), loss, self.ctx)
+        return out
+
     def new_grads(self) -> Dict[str, torch.Tensor]:
         V, n = self.V, self.n
         kw = dict(dtype=torch.float32, device=self.device)
@@ -191,6 +202,17 @@ class Decoder:
         return d_xyz, d_feat, d_off, d_params
 
 
+def l1_targets(targets: Dict[str, torch.Tensor], scale: Dict[str, float],
+               weight: Optional[torch.Tensor] = None) -> "L.L1Targets":
+    t = L.L1Targets()
+    for k in ("rgb", "depth", "feat", "alpha"):
+        setattr(t, k, L._ptr(targets.get(k)))
+    t.weight = L._ptr(weight)
+    for i, k in enumerate(("rgb", "depth", "feat", "alpha")):
+        t.scale[i] = float(scale.get(k, 0.0))
+    return t
+
+
 def l1_loss_grad(maps: Dict[str, torch.Tensor], targets: Dict[str, torch.Tensor], grad: Dict[str, torch.Tensor],
                  scale: Dict[str, float], weight: Optional[torch.Tensor] = None,
                  loss: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
@@ -200,12 +222,7 @@ def l1_loss_grad(maps: Dict[str, torch.Tensor], targets: Dict[str, torch.Tensor]
     rgb = maps["rgb"]
     V, H, W = rgb.shape[0], rgb.shape[-2], rgb.shape[-1]
     nf = maps["feat"].shape[1] if "feat" in maps else 0
-    t = L.L1Targets()
-    for k in ("rgb", "depth", "feat", "alpha"):
-        setattr(t, k, L._ptr(targets.get(k)))
-    t.weight = L._ptr(weight)
-    for i, k in enumerate(("rgb", "depth", "feat", "alpha")):
-        t.scale[i] = float(scale.get(k, 0.0))
+    t = l1_targets(targets, scale, weight)
     work = None
     if loss is not None:
         work = torch.empty(L.l1_loss_work_size(V), dtype=torch.uint8, device=rgb.device)

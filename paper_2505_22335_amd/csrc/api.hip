@@ -267,6 +267,7 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.pmask = take((size_t)capc);
   L.ranges = take((size_t)total_tiles * 8);
   L.binfo = take((size_t)total_tiles * 16);
+  L.lpart = take((size_t)total_tiles * 4 * sizeof(float));
   L.tfinal = take((size_t)total_pix * 4);
   L.ncontrib = take((size_t)total_pix * 4);
   L.gslot = take((size_t)capc * L.gs * sizeof(float));
@@ -341,9 +342,9 @@ int asgs_render_count(const asgs_camera* cams, int32_t n_views, const asgs_gauss
   return ASGS_OK;
 }
 
-int asgs_render_forward(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
-                        const asgs_render_opts* opts, const asgs_images* out, void* ctx, size_t ctx_bytes,
-                        void* stream) {
+static int render_forward_impl(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                        const asgs_render_opts* opts, const asgs_images* out, const asgs_l1_targets* targets,
+                        const asgs_images* grad, float* loss, void* ctx, size_t ctx_bytes, void* stream) {
   if (!g) return fail(ASGS_E_INVALID, "g is NULL");
   if (!out || !out->rgb || !out->depth || !out->alpha || (opts && opts->n_feat > 0 && !out->feat))
     return fail(ASGS_E_INVALID, "output images missing");
@@ -369,6 +370,20 @@ int asgs_render_forward(const asgs_camera* cams, int32_t n_views, const asgs_gau
     P.L = ctx_layout(g->n, n_views, P.total_tiles, P.total_pix, opts->n_feat, lo);
   }
   if ((st = check_ctx(P, ctx, ctx_bytes))) return st;
+  BlendL1 l1{};
+  if (targets) {
+    if (!grad) return fail(ASGS_E_INVALID, "render_forward_l1: grad is NULL");
+    const float* tg[4] = {targets->rgb, targets->depth, targets->feat, targets->alpha};
+    float* gr[4] = {grad->rgb, grad->depth, grad->feat, grad->alpha};
+    for (int q = 0; q < 4; ++q) {
+      const bool used = !(q == 2 && opts->n_feat == 0);
+      l1.t[q] = used ? tg[q] : nullptr;
+      l1.g[q] = used ? gr[q] : nullptr;
+      l1.s[q] = targets->scale[q];
+      if (!isfinite(targets->scale[q])) return fail(ASGS_E_INVALID, "render_forward_l1: scale not finite");
+    }
+    l1.w = targets->weight;
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* c = static_cast<char*>(ctx);
   if ((st = run_front(P, g, c, s))) return st;
@@ -378,9 +393,23 @@ int asgs_render_forward(const asgs_camera* cams, int32_t n_views, const asgs_gau
   }
   {
     ProfScope ps(ASGS_K_BLEND_FWD, s);
-    launch_blend_forward(P.rc, P.L, c, *out, s);
+    launch_blend_forward(P.rc, P.L, c, *out, targets ? &l1 : nullptr, s);
   }
+  if (targets && loss) launch_l1_tile_loss(P.rc, P.L, c, loss, s);
   return check_launch("render_forward launch");
+}
+
+int asgs_render_forward(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                        const asgs_render_opts* opts, const asgs_images* out, void* ctx, size_t ctx_bytes,
+                        void* stream) {
+  return render_forward_impl(cams, n_views, g, opts, out, nullptr, nullptr, nullptr, ctx, ctx_bytes, stream);
+}
+
+int asgs_render_forward_l1(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,
+                           const asgs_render_opts* opts, const asgs_images* out, const asgs_l1_targets* targets,
+                           const asgs_images* grad, float* loss, void* ctx, size_t ctx_bytes, void* stream) {
+  if (!targets || !grad) return fail(ASGS_E_INVALID, "render_forward_l1: targets or grad is NULL");
+  return render_forward_impl(cams, n_views, g, opts, out, targets, grad, loss, ctx, ctx_bytes, stream);
 }
 
 int asgs_render_backward(const asgs_camera* cams, int32_t n_views, const asgs_gaussians* g,

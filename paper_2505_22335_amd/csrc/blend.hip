@@ -88,9 +88,15 @@ constexpr int kSplitMin = 16;             // a round's quarter list shorter than
 // transmittance cannot have crossed T_min inside the back half
 // (T T_back >= T_min, T being monotone). Pixels where it could re-run the
 // back half on the front wave with the sequential rule.
-template <int NF>
+//
+// With L1, the output stage also forms the weighted L1 residual of the maps
+// against the targets and its gradient (the terms of the L1 loss kernel, in
+// the same arithmetic), and each quarter's loss partial.
+ASGS_DEV float l1_sgn(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
+
+template <int NF, bool L1>
 __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const ViewDev* __restrict__ views,
-                                                           char* ctx, CtxLayout L, asgs_images out) {
+                                                           char* ctx, CtxLayout L, asgs_images out, BlendL1 l1) {
   constexpr int CS = 4 + NF;
   constexpr int CS4 = CS / 4;
   uint4* binfo = ctx_ptr<uint4>(ctx, L.binfo);
@@ -124,6 +130,27 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   __shared__ uint16_t swl[kFwdThreads / 64][kTilePix];
   __shared__ float xch[4][CS + 2][64];  // back-half state per quarter pixel: T, channels, last
   __shared__ uint64_t qdone[4];         // front lanes already stopped, per quarter
+
+  // L1 targets and weight of the pixel, requested now and used in the output stage
+  float tv[CS + 1], tw = 1.f;
+  if (L1) {
+#pragma unroll
+    for (int c = 0; c <= CS; ++c) tv[c] = 0.f;
+    if (!back && inside) {
+      const size_t HW = (size_t)V.W * V.H;
+      const size_t pix = (size_t)py * V.W + px;
+      const size_t pb = (size_t)V.pix_base;
+      if (l1.w) tw = l1.w[pix];
+      if (l1.t[0])
+        for (int c = 0; c < 3; ++c) tv[c] = l1.t[0][3 * pb + c * HW + pix];
+      if (l1.t[1]) tv[3] = l1.t[1][pb + pix];
+      if (NF > 0 && l1.t[2]) {
+#pragma unroll
+        for (int c = 0; c < NF; ++c) tv[4 + c] = l1.t[2][NF * pb + c * HW + pix];
+      }
+      if (l1.t[3]) tv[CS] = l1.t[3][pb + pix];
+    }
+  }
 
   float T = 1.f;
   float acc[CS];
@@ -247,21 +274,75 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
     for (int o = 32; o > 0; o >>= 1) lm = max(lm, (uint32_t)__shfl_xor((int)lm, o));
     if (lane == 0 && lm > 0u) atomicMax(&binfo[blockIdx.x].w, lm);
   }
-  if (back || !inside) return;
-  const size_t HW = (size_t)V.W * V.H;
-  const size_t pix = (size_t)py * V.W + px;
-  const size_t pb = (size_t)V.pix_base;
-  out.rgb[3 * pb + 0 * HW + pix] = acc[0] + T * rc.bg[0];
-  out.rgb[3 * pb + 1 * HW + pix] = acc[1] + T * rc.bg[1];
-  out.rgb[3 * pb + 2 * HW + pix] = acc[2] + T * rc.bg[2];
-  out.depth[pb + pix] = acc[3];
-  if (NF > 0) {
+  if (back) return;
+  float lsum = 0.f;  // this pixel's L1 loss terms
+  if (inside) {
+    const size_t HW = (size_t)V.W * V.H;
+    const size_t pix = (size_t)py * V.W + px;
+    const size_t pb = (size_t)V.pix_base;
+    float map[CS + 1];  // rgb, depth, feature, opacity sum
+    map[0] = acc[0] + T * rc.bg[0];
+    map[1] = acc[1] + T * rc.bg[1];
+    map[2] = acc[2] + T * rc.bg[2];
 #pragma unroll
-    for (int c = 0; c < NF; ++c) out.feat[NF * pb + c * HW + pix] = acc[4 + c];
+    for (int c = 3; c < CS; ++c) map[c] = acc[c];
+    map[CS] = 1.f - T;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.rgb[3 * pb + c * HW + pix] = map[c];
+    out.depth[pb + pix] = map[3];
+    if (NF > 0) {
+#pragma unroll
+      for (int c = 0; c < NF; ++c) out.feat[NF * pb + c * HW + pix] = map[4 + c];
+    }
+    out.alpha[pb + pix] = map[CS];
+    ctx_ptr<float>(ctx, L.tfinal)[pb + pix] = T;
+    ctx_ptr<uint32_t>(ctx, L.ncontrib)[pb + pix] = last;
+    if (L1) {
+      const float w = tw;
+      // group q: channels [c0, c0 + nc) of the maps, plane base of view v
+      auto group = [&](int q, int c0, int nc, size_t vbase) {
+        float* g = l1.g[q];
+        if (!l1.t[q]) {
+          if (g)
+            for (int c = 0; c < nc; ++c) g[vbase + c * HW + pix] = 0.f;
+          return;
+        }
+        float l = 0.f;
+        for (int c = 0; c < nc; ++c) {
+          const float d = map[c0 + c] - tv[c0 + c];
+          l += fabsf(d);
+          if (g) g[vbase + c * HW + pix] = w * l1_sgn(d) * l1.s[q];
+        }
+        lsum += w * l * l1.s[q];
+      };
+      group(0, 0, 3, 3 * pb);
+      group(1, 3, 1, pb);
+      if (NF > 0) group(2, 4, NF, NF * pb);
+      group(3, CS, 1, pb);
+    }
   }
-  out.alpha[pb + pix] = 1.f - T;
-  ctx_ptr<float>(ctx, L.tfinal)[pb + pix] = T;
-  ctx_ptr<uint32_t>(ctx, L.ncontrib)[pb + pix] = last;
+  if (L1) {
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+    if (lane == 0) ctx_ptr<float>(ctx, L.lpart)[4 * tile + qd] = lsum;
+  }
+}
+
+// Per view: the fused forward's loss, a fixed-order sum of its tiles' quarter
+// partials.
+__global__ void __launch_bounds__(256) k_l1_tile_loss(const ViewDev* __restrict__ views, const float* lpart,
+                                                      float* loss) {
+  __shared__ float red[256 / 64];
+  const ViewDev& V = views[blockIdx.x];
+  const int nt = V.TX * V.TY;
+  float s = 0.f;
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) {
+    const float* p = lpart + 4 * (size_t)(V.tile_base + t);
+    s += (p[0] + p[1]) + (p[2] + p[3]);
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) loss[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 constexpr int kBwdBatch = 16;  // list entries per MFMA tile (M = 16)
@@ -683,12 +764,23 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
 }  // namespace
 
 void launch_blend_forward(const RenderConst& rc, const CtxLayout& L, char* ctx, const asgs_images& out,
-                          hipStream_t s) {
+                          const BlendL1* l1, hipStream_t s) {
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
-  if (rc.nf == 16)
-    hipLaunchKernelGGL(k_blend_fwd<16>, dim3(rc.total_tiles), dim3(kFwdThreads), 0, s, rc, views, ctx, L, out);
-  else
-    hipLaunchKernelGGL(k_blend_fwd<0>, dim3(rc.total_tiles), dim3(kFwdThreads), 0, s, rc, views, ctx, L, out);
+  const BlendL1 a = l1 ? *l1 : BlendL1{};
+  const dim3 grid(rc.total_tiles), block(kFwdThreads);
+  if (rc.nf == 16) {
+    if (l1) hipLaunchKernelGGL((k_blend_fwd<16, true>), grid, block, 0, s, rc, views, ctx, L, out, a);
+    else hipLaunchKernelGGL((k_blend_fwd<16, false>), grid, block, 0, s, rc, views, ctx, L, out, a);
+  } else {
+    if (l1) hipLaunchKernelGGL((k_blend_fwd<0, true>), grid, block, 0, s, rc, views, ctx, L, out, a);
+    else hipLaunchKernelGGL((k_blend_fwd<0, false>), grid, block, 0, s, rc, views, ctx, L, out, a);
+  }
+}
+
+void launch_l1_tile_loss(const RenderConst& rc, const CtxLayout& L, char* ctx, float* loss, hipStream_t s) {
+  const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
+  hipLaunchKernelGGL(k_l1_tile_loss, dim3(rc.n_views), dim3(256), 0, s, views,
+                     reinterpret_cast<const float*>(ctx + L.lpart), loss);
 }
 
 void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx, const asgs_images& dout,

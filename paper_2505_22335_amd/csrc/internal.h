@@ -66,9 +66,10 @@ struct CtxHeader {
 //  pairgid, pslot, ptile  per sorted intersection: Gaussian, gradient slot, tile key
 //  binfo               per blend position (longest list first): tile, start, end, and the
 //                      list length the backward walks (largest last contributor + 1)
+//  lpart               per tile and 8x8 quarter: L1 loss partial of the fused forward
 struct CtxLayout {
   size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, tcur, ukey, tkey, pairgid, pslot,
-      ptile, pmask, ranges, binfo, tfinal, ncontrib, gslot, posepart;
+      ptile, pmask, ranges, binfo, lpart, tfinal, ncontrib, gslot, posepart;
   size_t total;
   int64_t nv, cap;
   int32_t total_tiles, total_pix, cs, gs, pose_blocks;
@@ -87,8 +88,17 @@ void launch_project(const RenderConst& rc, const asgs_gaussians& g, const CtxLay
                     char* ctx, hipStream_t s);
 void launch_bin(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
 void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
+// Weighted L1 residual fused into the forward's output stage (same terms as
+// launch_l1_loss, targets and gradients packed like the images).
+struct BlendL1 {
+  const float* t[4];  // targets per group (rgb, depth, feat, opacity sum), NULL = no term
+  const float* w;     // per-pixel weight [H][W] shared by the views, NULL = 1
+  float* g[4];        // gradient planes per group, NULL = not written
+  float s[4];         // scale of each group's term
+};
 void launch_blend_forward(const RenderConst& rc, const CtxLayout& L, char* ctx,
-                          const asgs_images& out, hipStream_t s);
+                          const asgs_images& out, const BlendL1* l1, hipStream_t s);
+void launch_l1_tile_loss(const RenderConst& rc, const CtxLayout& L, char* ctx, float* loss, hipStream_t s);
 void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx,
                            const asgs_images& dout, hipStream_t s);
 void launch_project_backward(const RenderConst& rc, const asgs_gaussians& g,

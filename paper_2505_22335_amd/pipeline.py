@@ -70,6 +70,14 @@ class AnchorRenderer:
         self.images = self.rc.forward(self.g, out=self.images)
         return self.images
 
+    def forward_l1(self, targets: Dict[str, torch.Tensor], grad: Dict[str, torch.Tensor], scale: Dict[str, float],
+                   weight: Optional[torch.Tensor] = None, loss: Optional[torch.Tensor] = None):
+        """Decode, render and the weighted L1 residual gradient in the
+        forward's output stage (RenderContext.forward_l1)."""
+        self.decode()
+        self.images = self.rc.forward_l1(self.g, targets, grad, scale, weight, loss, out=self.images)
+        return self.images
+
     def backward(self, dimg: Dict[str, torch.Tensor], pose: bool = True, render_only: bool = False):
         """dimg: upstream gradients shaped like the images. Returns dict with
         d_gauss (per view) and, unless render_only, d_xyz, d_feat, d_off,
