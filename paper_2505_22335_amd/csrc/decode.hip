@@ -88,9 +88,10 @@ __global__ void __launch_bounds__(kAnchorThreads) k_dec_bwd_anchor(DecodeConst d
   }
 }
 
-// Mean gradients summed over views: d_off = l_o dmu, d_xyz += sum_i dmu.
-__global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, float* d_off) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Mean gradients summed over views: d_off = l_o dmu, d_xyz += sum_i dmu
+// (element e of the 3 A anchor coordinates).
+ASGS_DEV void dec_bwd_mean(const DecodeConst& dc, const asgs_gaussians& dg, float* d_xyz, float* d_off,
+                           int64_t e) {
   const int64_t A = dc.A;
   const int k = dc.k;
   const int64_t n = A * k;
@@ -111,9 +112,15 @@ __global__ void k_dec_bwd_mean(DecodeConst dc, asgs_gaussians dg, float* d_xyz, 
 // Fixed-order reduction of the workgroup partials: 64 parameters per
 // workgroup, four threads per parameter (each a strided quarter of the
 // partials, four independent sums), combined in LDS. The extra workgroup
-// adds -R_cw dL/dc to the translation part of the pose gradient.
+// adds -R_cw dL/dc to the translation part of the pose gradient. Workgroups
+// from mean_first on take the mean gradients instead (one launch for both).
 __global__ void __launch_bounds__(256) k_decode_reduce(DecodeConst dc, DecodeViews dv, DecWork w, float* d_params,
-                                                       float* d_pose) {
+                                                       float* d_pose, int mean_first, asgs_gaussians dg,
+                                                       float* d_xyz, float* d_off) {
+  if ((int)blockIdx.x >= mean_first) {
+    dec_bwd_mean(dc, dg, d_xyz, d_off, (int64_t)(blockIdx.x - mean_first) * blockDim.x + threadIdx.x);
+    return;
+  }
   // without d_params only the camera-centre term is reduced (one block)
   __shared__ float red[4][64];
   const int t = threadIdx.x;
@@ -258,11 +265,10 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
     hipLaunchKernelGGL(k_dec_bwd_anchor, dim3((unsigned)((nthreads + kAnchorThreads - 1) / kAnchorThreads)),
                        dim3(kAnchorThreads), 0, s, dc, dv, xyz, w, view, ht.m[4] > 0 ? 1 : 0, d_xyz, d_feat);
   }
-  if (d_xyz)
-    hipLaunchKernelGGL(k_dec_bwd_mean, dim3((unsigned)((dc.A * 3 + 255) / 256)), dim3(256), 0, s, dc, dg, d_xyz,
-                       d_off);
   const unsigned nrb = d_params ? (unsigned)((dc.n_params + 63) / 64) + 1 : 1u;
-  hipLaunchKernelGGL(k_decode_reduce, dim3(nrb), dim3(256), 0, s, dc, dv, w, d_params, d_pose);
+  const unsigned nmean = d_xyz ? (unsigned)((dc.A * 3 + 255) / 256) : 0u;
+  hipLaunchKernelGGL(k_decode_reduce, dim3(nrb + nmean), dim3(256), 0, s, dc, dv, w, d_params, d_pose, (int)nrb, dg,
+                     d_xyz, d_off);
 }
 
 }  // namespace asgs
