@@ -123,6 +123,11 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
   uint8_t* pmask = ctx_ptr<uint8_t>(ctx, L.pmask);
+  // lists walked by two backward workgroups: per pixel state at kSplitAt
+  static_assert(kSplitAt == kTilePix, "the split follows the first staging round");
+  const bool split = list_split(blockIdx.x, rg.y - rg.x);
+  constexpr int SA = split_first(CS), SR = split_rec(CS);
+  float* sp = ctx_ptr<float>(ctx, L.split) + ((size_t)(split ? blockIdx.x : 0) * kTilePix + tq) * SR;
 
   __shared__ float4 sg[kTilePix * 2];
   __shared__ float4 sc[kTilePix * CS4];
@@ -255,18 +260,40 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
       run(0, nf, base, !done, true);
     }
     __syncthreads();
-    if (back || nf == n) continue;
-    // append the back half
-    const float Tb = xch[qd][0][lane];
-    const uint32_t lastb = __float_as_uint(xch[qd][CS + 1][lane]);
-    const bool fix = !done && T * Tb < tmin;
-    if (!done && !fix) {
+    if (!back && nf != n) {
+      // append the back half
+      const float Tb = xch[qd][0][lane];
+      const uint32_t lastb = __float_as_uint(xch[qd][CS + 1][lane]);
+      const bool fix = !done && T * Tb < tmin;
+      if (!done && !fix) {
 #pragma unroll
-      for (int c = 0; c < CS; ++c) acc[c] = fmaf(T, xch[qd][1 + c][lane], acc[c]);
-      T *= Tb;
-      if (lastb) last = lastb;
+        for (int c = 0; c < CS; ++c) acc[c] = fmaf(T, xch[qd][1 + c][lane], acc[c]);
+        T *= Tb;
+        if (lastb) last = lastb;
+      }
+      if (__ballot(fix)) run(nf, n, base, fix, true);
     }
-    if (__ballot(fix)) run(nf, n, base, fix, true);
+    if (split && !back && base == rg.x) {
+      // state after the first kSplitAt entries (the first round)
+      float r[SA];
+      r[0] = T;
+#pragma unroll
+      for (int c = 0; c < CS; ++c) r[1 + c] = acc[c];
+#pragma unroll
+      for (int c = 1 + CS; c < SA; ++c) r[c] = 0.f;
+#pragma unroll
+      for (int c4 = 0; c4 < SA / 4; ++c4)
+        reinterpret_cast<float4*>(sp)[c4] = make_float4(r[4 * c4], r[4 * c4 + 1], r[4 * c4 + 2], r[4 * c4 + 3]);
+    }
+  }
+  if (split && !back) {
+    // the final channels (the later entries add C_final - C_first)
+    float r[SR - SA];
+#pragma unroll
+    for (int c = 0; c < SR - SA; ++c) r[c] = c < CS ? acc[c < CS ? c : 0] : 0.f;
+#pragma unroll
+    for (int c4 = 0; c4 < (SR - SA) / 4; ++c4)
+      reinterpret_cast<float4*>(sp + SA)[c4] = make_float4(r[4 * c4], r[4 * c4 + 1], r[4 * c4 + 2], r[4 * c4 + 3]);
   }
   // the list length the backward walks: the tile's largest last contributor
   if (!back) {
@@ -392,7 +419,15 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
   constexpr int CP = 64;          // row of 64 pixel coefficients (bf16), 8-pixel groups XOR-swizzled by row
-  const uint4 bi = ctx_ptr<const uint4>(ctx, L.binfo)[blockIdx.x];  // longest lists first
+  // The first kSplitMax workgroups take the first kSplitAt entries of the
+  // split lists (and exit at once for the others), the rest one blend
+  // position each: the whole walked list, or its entries from kSplitAt on.
+  const bool front = blockIdx.x < (unsigned)kSplitMax;
+  const uint32_t pos = front ? blockIdx.x : blockIdx.x - kSplitMax;
+  if (pos >= (uint32_t)rc.total_tiles) return;
+  const uint4 bi = ctx_ptr<const uint4>(ctx, L.binfo)[pos];  // longest lists first
+  const bool split = list_split(pos, bi.z - bi.y);
+  if (front && !split) return;
   const int tile = (int)bi.x;
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
@@ -410,6 +445,9 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   prioritise(blockIdx.x, rc.n_cu);
   const uint32_t len = rg.y - rg.x;
   const uint32_t nproc = bi.w;  // entries behind every pixel's last Gaussian are not walked
+  // this workgroup's entries [elo, ehi) of the walked list
+  const int elo = split && !front ? kSplitAt : 0;
+  const int ehi = front ? min((int)nproc, kSplitAt) : (int)nproc;
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pslot);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
@@ -445,9 +483,9 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
       gid_next[k] = ent < cnt_r ? pairgid[rg.x + lo_r + ent] : 0u;
     }
   };
-  int rhi = (int)nproc;
-  int rlo = rhi - kRound > 0 ? rhi - kRound : 0;
-  if (rhi > 0) fetch_gid(rlo, rhi - rlo);
+  int rhi = ehi;
+  int rlo = rhi - kRound > elo ? rhi - kRound : elo;
+  if (rhi > elo) fetch_gid(rlo, rhi - rlo);
   const size_t HW = (size_t)V.W * V.H;
   const size_t pb = (size_t)V.pix_base;
   float Tf = 1.f;
@@ -526,13 +564,32 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   }
 
   // entries behind every pixel's last Gaussian get zero gradient
-  for (uint32_t q = nproc + t; q < len; q += kTilePix) {
+  for (uint32_t q = nproc + t; !front && q < len; q += kTilePix) {
     float4* dst = reinterpret_cast<float4*>(gslot + (size_t)pslot[rg.x + q] * PS);
 #pragma unroll
     for (int c = 0; c < PS / 4; ++c) dst[c] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   float T = Tf;
   float sacc = 0.f;  // sum over later Gaussians of w_l (G . c_l)
+  if (front && inside) {
+    // the state after the first kSplitAt entries: T there, and the later
+    // entries' sum, G . (C_final - C_first)
+    constexpr int SA = split_first(CS), SR = split_rec(CS);
+    const float4* sp = reinterpret_cast<const float4*>(ctx_ptr<const float>(ctx, L.split) +
+                                                       ((size_t)pos * kTilePix + t) * SR);
+    float r[SR];
+#pragma unroll
+    for (int c4 = 0; c4 < SR / 4; ++c4) {
+      const float4 v = sp[c4];
+      r[4 * c4] = v.x;
+      r[4 * c4 + 1] = v.y;
+      r[4 * c4 + 2] = v.z;
+      r[4 * c4 + 3] = v.w;
+    }
+    T = r[0];
+#pragma unroll
+    for (int c = 0; c < CS; ++c) sacc = fmaf(G[c], r[SA + c] - r[1 + c], sacc);
+  }
   const float amax = rc.alpha_max;
   // Records are staged in rounds of kRound entries, walking the list from the
   // back; the global loads of the next round are issued before the current
@@ -638,12 +695,12 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
-  if (rhi > 0) {
+  if (rhi > elo) {
     fetch(rlo, rhi - rlo);
-    const int nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
-    if (rlo > 0) fetch_gid(nrlo, rlo - nrlo);
+    const int nrlo = rlo - kRound > elo ? rlo - kRound : elo;
+    if (rlo > elo) fetch_gid(nrlo, rlo - nrlo);
   }
-  while (rhi > 0) {
+  while (rhi > elo) {
     __syncthreads();  // every reader of the previous round is done
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -657,11 +714,11 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     for (int q = lane; q < kRound * PS; q += 64) (&part[wv][0][0])[q] = 0.f;
     __syncthreads();
     const int cnt = rhi - rlo;
-    const int nrhi = rlo, nrlo = rlo - kRound > 0 ? rlo - kRound : 0;
-    if (nrhi > 0) {
+    const int nrhi = rlo, nrlo = rlo - kRound > elo ? rlo - kRound : elo;
+    if (nrhi > elo) {
       fetch(nrlo, nrhi - nrlo);
-      const int n2lo = nrlo - kRound > 0 ? nrlo - kRound : 0;
-      if (nrlo > 0) fetch_gid(n2lo, nrlo - n2lo);
+      const int n2lo = nrlo - kRound > elo ? nrlo - kRound : elo;
+      if (nrlo > elo) fetch_gid(n2lo, nrlo - n2lo);
     }
     // entries of the round that can reach a pixel of this wave's quarter
     const bool mine = lane < cnt && ((smk[lane] >> wv) & 1u);
@@ -787,9 +844,11 @@ void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx,
                            hipStream_t s) {
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
   if (rc.nf == 16)
-    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, dout);
+    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(rc.total_tiles + kSplitMax), dim3(kTilePix), 0, s, rc, views, ctx, L,
+                       dout);
   else
-    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(rc.total_tiles), dim3(kTilePix), 0, s, rc, views, ctx, L, dout);
+    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(rc.total_tiles + kSplitMax), dim3(kTilePix), 0, s, rc, views, ctx, L,
+                       dout);
 }
 
 }  // namespace asgs
