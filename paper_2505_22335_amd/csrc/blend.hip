@@ -123,11 +123,14 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
   const float4* chan4 = ctx_ptr<const float4>(ctx, L.chan);
   uint8_t* pmask = ctx_ptr<uint8_t>(ctx, L.pmask);
-  // lists walked by two backward workgroups: per pixel state at kSplitAt
-  static_assert(kSplitAt == kTilePix, "the split follows the first staging round");
-  const bool split = list_split(blockIdx.x, rg.y - rg.x);
-  constexpr int SA = split_first(CS), SR = split_rec(CS);
-  float* sp = ctx_ptr<float>(ctx, L.split) + ((size_t)(split ? blockIdx.x : 0) * kTilePix + tq) * SR;
+  // lists walked by several backward workgroups: staged kSeg entries at a
+  // time, with the pixel's state recorded at every segment boundary
+  static_assert(kSeg * 2 == kTilePix && split_floats(CS) == ((kSegMax - 1) * split_first(CS) + split_final(CS)) * kTilePix,
+                "segment layout");
+  const int nseg = list_segments(blockIdx.x, rg.y - rg.x);
+  const uint32_t rstep = nseg > 1 ? (uint32_t)kSeg : (uint32_t)kTilePix;  // entries staged per round
+  constexpr int SA = split_first(CS), SF = split_final(CS);
+  float* sp = ctx_ptr<float>(ctx, L.split) + (size_t)(nseg > 1 ? blockIdx.x : 0) * split_floats(CS);
 
   __shared__ float4 sg[kTilePix * 2];
   __shared__ float4 sc[kTilePix * CS4];
@@ -209,11 +212,11 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
     }
   };
   // the Gaussian ids of the next round are read while this round is staged
-  uint32_t gid_next = t < kTilePix && rg.x + t < rg.y ? pairgid[rg.x + t] : 0u;
-  for (uint32_t base = rg.x; base < rg.y; base += kTilePix) {
+  uint32_t gid_next = t < rstep && rg.x + t < rg.y ? pairgid[rg.x + t] : 0u;
+  for (uint32_t base = rg.x; base < rg.y; base += rstep) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t p = base + t;
-    if (t < kTilePix && p < rg.y) {
+    if (t < rstep && p < rg.y) {
       const uint32_t gid = gid_next;
       const float4 g0 = geom[2 * (size_t)gid];
       const float4 g1 = geom[2 * (size_t)gid + 1];
@@ -224,14 +227,14 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
       const uint8_t m = (uint8_t)quarter_mask(g0, g1, x0, y0);
       smask[t] = m;
       pmask[p] = m;  // reused by the backward
-      if (p + kTilePix < rg.y) gid_next = pairgid[p + kTilePix];
+      if (p + rstep < rg.y) gid_next = pairgid[p + rstep];
     }
     {
       const uint64_t dm = __ballot(done);
       if (!back && lane == 0) qdone[qd] = dm;
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kTilePix, rg.y - base);
+    const int cnt = (int)min(rstep, rg.y - base);
     // the quarter's entries of the round (those that can reach one of its
     // pixels), in list order, compacted into swl (the same list on both waves)
     int n = 0;
@@ -273,8 +276,10 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
       }
       if (__ballot(fix)) run(nf, n, base, fix, true);
     }
-    if (split && !back && base == rg.x) {
-      // state after the first kSplitAt entries (the first round)
+    const int bnd = (int)((base - rg.x) / kSeg) + 1;  // segment boundary after this round
+    if (nseg > 1 && !back && bnd < nseg) {
+      // state after the first bnd * kSeg entries
+      float* rp = sp + ((size_t)(bnd - 1) * kTilePix + tq) * SA;
       float r[SA];
       r[0] = T;
 #pragma unroll
@@ -283,17 +288,18 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
       for (int c = 1 + CS; c < SA; ++c) r[c] = 0.f;
 #pragma unroll
       for (int c4 = 0; c4 < SA / 4; ++c4)
-        reinterpret_cast<float4*>(sp)[c4] = make_float4(r[4 * c4], r[4 * c4 + 1], r[4 * c4 + 2], r[4 * c4 + 3]);
+        reinterpret_cast<float4*>(rp)[c4] = make_float4(r[4 * c4], r[4 * c4 + 1], r[4 * c4 + 2], r[4 * c4 + 3]);
     }
   }
-  if (split && !back) {
-    // the final channels (the later entries add C_final - C_first)
-    float r[SR - SA];
+  if (nseg > 1 && !back) {
+    // the final channels (the entries after a boundary add C_final - C_boundary)
+    float* rp = sp + (size_t)(kSegMax - 1) * kTilePix * SA + (size_t)tq * SF;
+    float r[SF];
 #pragma unroll
-    for (int c = 0; c < SR - SA; ++c) r[c] = c < CS ? acc[c < CS ? c : 0] : 0.f;
+    for (int c = 0; c < SF; ++c) r[c] = c < CS ? acc[c < CS ? c : 0] : 0.f;
 #pragma unroll
-    for (int c4 = 0; c4 < (SR - SA) / 4; ++c4)
-      reinterpret_cast<float4*>(sp + SA)[c4] = make_float4(r[4 * c4], r[4 * c4 + 1], r[4 * c4 + 2], r[4 * c4 + 3]);
+    for (int c4 = 0; c4 < SF / 4; ++c4)
+      reinterpret_cast<float4*>(rp)[c4] = make_float4(r[4 * c4], r[4 * c4 + 1], r[4 * c4 + 2], r[4 * c4 + 3]);
   }
   // the list length the backward walks: the tile's largest last contributor
   if (!back) {
@@ -419,15 +425,17 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
   constexpr int CP = 64;          // row of 64 pixel coefficients (bf16), 8-pixel groups XOR-swizzled by row
-  // The first kSplitMax workgroups take the first kSplitAt entries of the
-  // split lists (and exit at once for the others), the rest one blend
-  // position each: the whole walked list, or its entries from kSplitAt on.
-  const bool front = blockIdx.x < (unsigned)kSplitMax;
-  const uint32_t pos = front ? blockIdx.x : blockIdx.x - kSplitMax;
+  // The first kSplitMax (kSegMax - 1) workgroups take the segments but the
+  // last of the split lists (and exit at once where there is none), the rest
+  // one blend position each: the whole walked list, or its last segment.
+  constexpr int kExtra = kSplitMax * (kSegMax - 1);
+  const bool front = blockIdx.x < (unsigned)kExtra;
+  const uint32_t pos = front ? blockIdx.x / (kSegMax - 1) : blockIdx.x - kExtra;
   if (pos >= (uint32_t)rc.total_tiles) return;
   const uint4 bi = ctx_ptr<const uint4>(ctx, L.binfo)[pos];  // longest lists first
-  const bool split = list_split(pos, bi.z - bi.y);
-  if (front && !split) return;
+  const int nseg = list_segments(pos, bi.z - bi.y);
+  const int seg = front ? (int)(blockIdx.x % (kSegMax - 1)) : nseg - 1;
+  if (front && seg >= nseg - 1) return;
   const int tile = (int)bi.x;
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
@@ -446,8 +454,9 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   const uint32_t len = rg.y - rg.x;
   const uint32_t nproc = bi.w;  // entries behind every pixel's last Gaussian are not walked
   // this workgroup's entries [elo, ehi) of the walked list
-  const int elo = split && !front ? kSplitAt : 0;
-  const int ehi = front ? min((int)nproc, kSplitAt) : (int)nproc;
+  const bool lastseg = seg == nseg - 1;
+  const int elo = seg * kSeg;
+  const int ehi = lastseg ? (int)nproc : min((int)nproc, (seg + 1) * kSeg);
   const uint32_t* pairgid = ctx_ptr<const uint32_t>(ctx, L.pairgid);
   const uint32_t* pslot = ctx_ptr<const uint32_t>(ctx, L.pslot);
   const float4* geom = ctx_ptr<const float4>(ctx, L.geom);
@@ -564,31 +573,40 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   }
 
   // entries behind every pixel's last Gaussian get zero gradient
-  for (uint32_t q = nproc + t; !front && q < len; q += kTilePix) {
+  for (uint32_t q = nproc + t; lastseg && q < len; q += kTilePix) {
     float4* dst = reinterpret_cast<float4*>(gslot + (size_t)pslot[rg.x + q] * PS);
 #pragma unroll
     for (int c = 0; c < PS / 4; ++c) dst[c] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   float T = Tf;
   float sacc = 0.f;  // sum over later Gaussians of w_l (G . c_l)
-  if (front && inside) {
-    // the state after the first kSplitAt entries: T there, and the later
-    // entries' sum, G . (C_final - C_first)
-    constexpr int SA = split_first(CS), SR = split_rec(CS);
-    const float4* sp = reinterpret_cast<const float4*>(ctx_ptr<const float>(ctx, L.split) +
-                                                       ((size_t)pos * kTilePix + t) * SR);
-    float r[SR];
+  if (!lastseg && ehi == (seg + 1) * kSeg && inside) {
+    // the state at the segment's end (a boundary the forward passed): T
+    // there, and the later entries' sum, G . (C_final - C_boundary)
+    constexpr int SA = split_first(CS), SF = split_final(CS);
+    const float* sp = ctx_ptr<const float>(ctx, L.split) + (size_t)pos * split_floats(CS);
+    const float4* rb = reinterpret_cast<const float4*>(sp + ((size_t)seg * kTilePix + t) * SA);
+    const float4* rf = reinterpret_cast<const float4*>(sp + (size_t)(kSegMax - 1) * kTilePix * SA + (size_t)t * SF);
+    float r[SA], f[SF];
 #pragma unroll
-    for (int c4 = 0; c4 < SR / 4; ++c4) {
-      const float4 v = sp[c4];
+    for (int c4 = 0; c4 < SA / 4; ++c4) {
+      const float4 v = rb[c4];
       r[4 * c4] = v.x;
       r[4 * c4 + 1] = v.y;
       r[4 * c4 + 2] = v.z;
       r[4 * c4 + 3] = v.w;
     }
+#pragma unroll
+    for (int c4 = 0; c4 < SF / 4; ++c4) {
+      const float4 v = rf[c4];
+      f[4 * c4] = v.x;
+      f[4 * c4 + 1] = v.y;
+      f[4 * c4 + 2] = v.z;
+      f[4 * c4 + 3] = v.w;
+    }
     T = r[0];
 #pragma unroll
-    for (int c = 0; c < CS; ++c) sacc = fmaf(G[c], r[SA + c] - r[1 + c], sacc);
+    for (int c = 0; c < CS; ++c) sacc = fmaf(G[c], f[c] - r[1 + c], sacc);
   }
   const float amax = rc.alpha_max;
   // Records are staged in rounds of kRound entries, walking the list from the
@@ -844,10 +862,12 @@ void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx,
                            hipStream_t s) {
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
   if (rc.nf == 16)
-    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(rc.total_tiles + kSplitMax), dim3(kTilePix), 0, s, rc, views, ctx, L,
+    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(rc.total_tiles + kSplitMax * (kSegMax - 1)), dim3(kTilePix), 0, s, rc,
+                       views, ctx, L,
                        dout);
   else
-    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(rc.total_tiles + kSplitMax), dim3(kTilePix), 0, s, rc, views, ctx, L,
+    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(rc.total_tiles + kSplitMax * (kSegMax - 1)), dim3(kTilePix), 0, s, rc,
+                       views, ctx, L,
                        dout);
 }
 

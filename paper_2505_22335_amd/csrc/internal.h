@@ -69,7 +69,7 @@ struct CtxHeader {
 //  lpart               per tile and 8x8 quarter: L1 loss partial of the fused forward
 //  split               per split list (the first kSplitMax blend positions whose list is
 //                      longer than kSplitLen): per pixel the transmittance and channels
-//                      after the first kSplitAt entries, and the final channels
+//                      at each segment boundary, and the final channels
 struct CtxLayout {
   size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, tcur, ukey, tkey, pairgid, pslot,
       ptile, pmask, ranges, binfo, lpart, split, tfinal, ncontrib, gslot, posepart;
@@ -91,18 +91,29 @@ void launch_project(const RenderConst& rc, const asgs_gaussians& g, const CtxLay
                     char* ctx, hipStream_t s);
 void launch_bin(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
 void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
-// The longest lists are walked by two backward workgroups: entries
-// [0, kSplitAt) and [kSplitAt, end). A list at blend position k is split when
-// k < kSplitMax and it has more than kSplitLen entries (the forward records
-// the state at kSplitAt for these lists).
-constexpr int kSplitAt = 256;
-constexpr int kSplitLen = 288;
+// The longest lists are walked by several backward workgroups, one per
+// segment of kSeg entries (the last segment takes the rest). A list at blend
+// position k is split when k < kSplitMax and it has more than kSplitLen
+// entries, into min(kSegMax, ceil(len / kSeg)) segments; the forward stages
+// such lists kSeg entries at a time and records the state at every segment
+// boundary.
+constexpr int kSeg = 128;
+constexpr int kSegMax = 4;
+constexpr int kSplitLen = 160;
 constexpr int kSplitMax = 64;
-__host__ __device__ inline bool list_split(uint32_t pos, uint32_t len) { return pos < (uint32_t)kSplitMax && len > (uint32_t)kSplitLen; }
-// Floats per pixel of a split record: T and the channels after kSplitAt entries
-// (padded to whole float4), then the final channels (padded).
+__host__ __device__ inline int list_segments(uint32_t pos, uint32_t len) {
+  if (pos >= (uint32_t)kSplitMax || len <= (uint32_t)kSplitLen) return 1;
+  const uint32_t n = (len + kSeg - 1) / kSeg;
+  return n < (uint32_t)kSegMax ? (int)n : kSegMax;
+}
+// Floats per pixel of a boundary record (T and the channels, padded to whole
+// float4) and of the final channels (padded).
 __host__ __device__ constexpr int split_first(int cs) { return (1 + cs + 3) & ~3; }
-__host__ __device__ constexpr int split_rec(int cs) { return split_first(cs) + ((cs + 3) & ~3); }
+__host__ __device__ constexpr int split_final(int cs) { return (cs + 3) & ~3; }
+// Floats of the split records of one list.
+__host__ __device__ constexpr int split_floats(int cs) {
+  return ((kSegMax - 1) * split_first(cs) + split_final(cs)) * 256;
+}
 
 // Weighted L1 residual fused into the forward's output stage (same terms as
 // launch_l1_loss, targets and gradients packed like the images).
