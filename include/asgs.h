@@ -6,7 +6,8 @@
  *                   head MLPs (UP-SLAM Sec. 3.3, Eq. 8 and Eq. 9; MLP details
  *                   in the appendix);
  *   render_forward  EWA projection of the Gaussians (Sec. 3.1, Eq. 2), tile
- *                   binning with a device radix sort on (tile, depth) keys, and
+ *                   binning (a counting sort on the tile, then every tile list
+ *                   sorted on (depth, index) on its own), and
  *                   front-to-back alpha compositing of colour, depth, the opacity
  *                   sum (Eq. 3) and the low-dimensional feature (Eq. 10);
  *   render_backward the vector-Jacobian product of render_forward w.r.t. the
@@ -294,7 +295,7 @@ int asgs_render_forward_l1(const asgs_camera* cams, int32_t n_views, const asgs_
  * ------------------------------------------------------------------------- */
 enum {
   ASGS_K_PROJECT = 0,      /* projection (one kernel) */
-  ASGS_K_SORT = 1,         /* depth sort, duplication, tile sort, ranges (several kernels) */
+  ASGS_K_SORT = 1,         /* binning: tile scan, duplication, per-tile list sort (several kernels) */
   ASGS_K_BLEND_FWD = 2,    /* forward compositing (one kernel) */
   ASGS_K_BLEND_BWD = 3,    /* backward compositing (one kernel) */
   ASGS_K_PROJECT_BWD = 4,  /* projection backward + pose reduction (one kernel) */

@@ -209,7 +209,7 @@ int check_ctx(const Prep& P, const void* ctx, size_t ctx_bytes) {
   return ASGS_OK;
 }
 
-// Projection, depth sort and intersection count (shared by count and forward).
+// Projection, tile counting, ranges and duplication (shared by count and forward).
 int run_front(const Prep& P, const asgs_gaussians* g, char* ctx, hipStream_t s) {
   launch_set_views(P.views, P.rc.n_views, reinterpret_cast<ViewDev*>(ctx + P.L.views),
                    reinterpret_cast<CtxHeader*>(ctx + P.L.hdr), reinterpret_cast<uint32_t*>(ctx + P.L.tcur),
