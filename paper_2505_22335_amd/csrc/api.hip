@@ -268,7 +268,9 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.ranges = take((size_t)total_tiles * 8);
   L.binfo = take((size_t)total_tiles * 16);
   L.lpart = take((size_t)total_tiles * 4 * sizeof(float));
-  L.split = take((size_t)kSplitMax * split_floats(L.cs) * sizeof(float));
+  L.bslot = take((size_t)total_tiles * 4);
+  L.sinfo = take((size_t)n_views * kSplitPerView * 16);
+  L.split = take((size_t)n_views * kSplitPerView * split_floats(L.cs) * sizeof(float));
   L.tfinal = take((size_t)total_pix * 4);
   L.ncontrib = take((size_t)total_pix * 4);
   L.gslot = take((size_t)capc * L.gs * sizeof(float));

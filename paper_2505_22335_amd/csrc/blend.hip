@@ -127,10 +127,11 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   // time, with the pixel's state recorded at every segment boundary
   static_assert(kSeg * 2 == kTilePix && split_floats(CS) == ((kSegMax - 1) * split_first(CS) + split_final(CS)) * kTilePix,
                 "segment layout");
-  const int nseg = list_segments(blockIdx.x, rg.y - rg.x);
+  const uint32_t sl = ctx_ptr<const uint32_t>(ctx, L.bslot)[tile];  // 1 + split-record slot, or 0
+  const int nseg = sl ? split_segments(rg.y - rg.x) : 1;
   const uint32_t rstep = nseg > 1 ? (uint32_t)kSeg : (uint32_t)kTilePix;  // entries staged per round
   constexpr int SA = split_first(CS), SF = split_final(CS);
-  float* sp = ctx_ptr<float>(ctx, L.split) + (size_t)(nseg > 1 ? blockIdx.x : 0) * split_floats(CS);
+  float* sp = ctx_ptr<float>(ctx, L.split) + (size_t)(sl ? sl - 1u : 0u) * split_floats(CS);
 
   __shared__ float4 sg[kTilePix * 2];
   __shared__ float4 sc[kTilePix * CS4];
@@ -305,7 +306,10 @@ __global__ void __launch_bounds__(kFwdThreads) k_blend_fwd(RenderConst rc, const
   if (!back) {
     uint32_t lm = inside ? last : 0u;
     for (int o = 32; o > 0; o >>= 1) lm = max(lm, (uint32_t)__shfl_xor((int)lm, o));
-    if (lane == 0 && lm > 0u) atomicMax(&binfo[blockIdx.x].w, lm);
+    if (lane == 0 && lm > 0u) {
+      atomicMax(&binfo[blockIdx.x].w, lm);
+      if (sl) atomicMax(&ctx_ptr<uint4>(ctx, L.sinfo)[sl - 1u].w, lm);
+    }
   }
   if (back) return;
   float lsum = 0.f;  // this pixel's L1 loss terms
@@ -425,17 +429,29 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   constexpr int GS = 6 + CS;
   constexpr int NW = kTilePix / 64;
   constexpr int CP = 64;          // row of 64 pixel coefficients (bf16), 8-pixel groups XOR-swizzled by row
-  // The first kSplitMax (kSegMax - 1) workgroups take the segments but the
-  // last of the split lists (and exit at once where there is none), the rest
-  // one blend position each: the whole walked list, or its last segment.
-  constexpr int kExtra = kSplitMax * (kSegMax - 1);
-  const bool front = blockIdx.x < (unsigned)kExtra;
-  const uint32_t pos = front ? blockIdx.x / (kSegMax - 1) : blockIdx.x - kExtra;
-  if (pos >= (uint32_t)rc.total_tiles) return;
-  const uint4 bi = ctx_ptr<const uint4>(ctx, L.binfo)[pos];  // longest lists first
-  const int nseg = list_segments(pos, bi.z - bi.y);
-  const int seg = front ? (int)(blockIdx.x % (kSegMax - 1)) : nseg - 1;
-  if (front && seg >= nseg - 1) return;
+  // The first n_views kSplitPerView (kSegMax - 1) workgroups take the
+  // segments but the last of the split lists, one split-record slot each
+  // (and exit at once where there is none), the rest one blend position each
+  // (longest lists first): the whole walked list, or its last segment.
+  const uint32_t extra = (uint32_t)rc.n_views * kSplitPerView * (kSegMax - 1);
+  const bool front = blockIdx.x < extra;
+  uint4 bi;
+  uint32_t slot;
+  int nseg, seg;
+  if (front) {
+    slot = blockIdx.x / (kSegMax - 1);
+    bi = ctx_ptr<const uint4>(ctx, L.sinfo)[slot];
+    if (bi.x == ~0u) return;
+    nseg = split_segments(bi.z - bi.y);
+    seg = (int)(blockIdx.x % (kSegMax - 1));
+    if (seg >= nseg - 1) return;
+  } else {
+    bi = ctx_ptr<const uint4>(ctx, L.binfo)[blockIdx.x - extra];
+    const uint32_t sl = ctx_ptr<const uint32_t>(ctx, L.bslot)[bi.x];
+    slot = sl ? sl - 1u : 0u;
+    nseg = sl ? split_segments(bi.z - bi.y) : 1;
+    seg = nseg - 1;
+  }
   const int tile = (int)bi.x;
   const int view = find_view(views, rc.n_views, tile);
   const ViewDev& V = views[view];
@@ -584,7 +600,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     // the state at the segment's end (a boundary the forward passed): T
     // there, and the later entries' sum, G . (C_final - C_boundary)
     constexpr int SA = split_first(CS), SF = split_final(CS);
-    const float* sp = ctx_ptr<const float>(ctx, L.split) + (size_t)pos * split_floats(CS);
+    const float* sp = ctx_ptr<const float>(ctx, L.split) + (size_t)slot * split_floats(CS);
     const float4* rb = reinterpret_cast<const float4*>(sp + ((size_t)seg * kTilePix + t) * SA);
     const float4* rf = reinterpret_cast<const float4*>(sp + (size_t)(kSegMax - 1) * kTilePix * SA + (size_t)t * SF);
     float r[SA], f[SF];
@@ -862,11 +878,13 @@ void launch_blend_backward(const RenderConst& rc, const CtxLayout& L, char* ctx,
                            hipStream_t s) {
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
   if (rc.nf == 16)
-    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(rc.total_tiles + kSplitMax * (kSegMax - 1)), dim3(kTilePix), 0, s, rc,
+    hipLaunchKernelGGL(k_blend_bwd<16>, dim3(rc.total_tiles + rc.n_views * kSplitPerView * (kSegMax - 1)),
+                       dim3(kTilePix), 0, s, rc,
                        views, ctx, L,
                        dout);
   else
-    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(rc.total_tiles + kSplitMax * (kSegMax - 1)), dim3(kTilePix), 0, s, rc,
+    hipLaunchKernelGGL(k_blend_bwd<0>, dim3(rc.total_tiles + rc.n_views * kSplitPerView * (kSegMax - 1)),
+                       dim3(kTilePix), 0, s, rc,
                        views, ctx, L,
                        dout);
 }

@@ -67,12 +67,14 @@ struct CtxHeader {
 //  binfo               per blend position (longest list first): tile, start, end, and the
 //                      list length the backward walks (largest last contributor + 1)
 //  lpart               per tile and 8x8 quarter: L1 loss partial of the fused forward
-//  split               per split list (the first kSplitMax blend positions whose list is
-//                      longer than kSplitLen): per pixel the transmittance and channels
-//                      at each segment boundary, and the final channels
+//  bslot               per tile: 1 + its split-record slot, 0 when the list is not split
+//  sinfo               per split-record slot: tile, start, end, walked length (tile ~0u: unused)
+//  split               per split-record slot (kSplitPerView per view): per pixel the
+//                      transmittance and channels at each segment boundary, and the
+//                      final channels
 struct CtxLayout {
   size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, tcur, ukey, tkey, pairgid, pslot,
-      ptile, pmask, ranges, binfo, lpart, split, tfinal, ncontrib, gslot, posepart;
+      ptile, pmask, ranges, binfo, lpart, bslot, sinfo, split, tfinal, ncontrib, gslot, posepart;
   size_t total;
   int64_t nv, cap;
   int32_t total_tiles, total_pix, cs, gs, pose_blocks;
@@ -92,17 +94,20 @@ void launch_project(const RenderConst& rc, const asgs_gaussians& g, const CtxLay
 void launch_bin(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
 void launch_tile_sort(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s);
 // The longest lists are walked by several backward workgroups, one per
-// segment of kSeg entries (the last segment takes the rest). A list at blend
-// position k is split when k < kSplitMax and it has more than kSplitLen
-// entries, into min(kSegMax, ceil(len / kSeg)) segments; the forward stages
-// such lists kSeg entries at a time and records the state at every segment
-// boundary.
+// segment of kSeg entries (the last segment takes the rest):
+// min(kSegMax, ceil(len / kSeg)) segments. The forward stages such lists kSeg
+// entries at a time and records the state at every segment boundary. Which
+// lists are split depends only on the lengths of the lists of their own
+// view (so that results do not depend on the batch or on the order of equal
+// lengths): those longer than the smallest threshold kSplitLen + j kSplitStep
+// that at most kSplitPerView lists of the view exceed.
 constexpr int kSeg = 128;
 constexpr int kSegMax = 4;
 constexpr int kSplitLen = 160;
-constexpr int kSplitMax = 64;
-__host__ __device__ inline int list_segments(uint32_t pos, uint32_t len) {
-  if (pos >= (uint32_t)kSplitMax || len <= (uint32_t)kSplitLen) return 1;
+constexpr int kSplitStep = 32;
+constexpr int kSplitThresholds = 28;  // kSplitLen + j kSplitStep, j < 28 (up to 1024)
+constexpr int kSplitPerView = 64;
+__host__ __device__ inline int split_segments(uint32_t len) {
   const uint32_t n = (len + kSeg - 1) / kSeg;
   return n < (uint32_t)kSegMax ? (int)n : kSegMax;
 }

@@ -64,8 +64,11 @@ constexpr int kTileScanThreads = 1024;
 
 ASGS_DEV int order_bin(uint32_t c) { return kOrderBins - 1 - (int)(c < kOrderBins - 1 ? c : kOrderBins - 1); }
 
-__global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, char* ctx, CtxLayout L) {
+__global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, const ViewDev* __restrict__ views,
+                                                               char* ctx, CtxLayout L) {
   __shared__ uint32_t bins[kOrderBins];
+  __shared__ uint32_t scount[ASGS_MAX_VIEWS][kSplitThresholds];  // lists above each threshold, per view
+  __shared__ uint32_t sused[ASGS_MAX_VIEWS];
   __shared__ unsigned long long wtot[kTileScanThreads / 64];
   __shared__ uint32_t wbin[kTileScanThreads / 64];
   __shared__ unsigned long long wvis[kTileScanThreads / 64];
@@ -80,12 +83,19 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   const int per = (T + kTileScanThreads - 1) / kTileScanThreads;
   const int a0 = min(T, t * per), a1 = min(T, a0 + per);
   bins[t] = 0u;
+  for (int q = t; q < ASGS_MAX_VIEWS * kSplitThresholds; q += kTileScanThreads) (&scount[0][0])[q] = 0u;
+  if (t < ASGS_MAX_VIEWS) sused[t] = 0u;
   __syncthreads();
   unsigned long long mine = 0;
   for (int i = a0; i < a1; ++i) {
     const uint32_t c = tcur[i];
     mine += c;
     atomicAdd(&bins[order_bin(c)], 1u);
+    if (c > (uint32_t)kSplitLen) {
+      const int v = find_view(views, rc.n_views, i);
+      for (int j = 0; j < kSplitThresholds; ++j)
+        if (c > (uint32_t)(kSplitLen + j * kSplitStep)) atomicAdd(&scount[v][j], 1u);
+    }
   }
   // visible pairs: sum of the per-block counts
   unsigned long long vis = 0;
@@ -119,6 +129,10 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
     hdr->overflow = ovf ? 1u : 0u;
   }
   __syncthreads();
+  uint4* sinfo = ctx_ptr<uint4>(ctx, L.sinfo);
+  for (int q = t; q < rc.n_views * kSplitPerView; q += kTileScanThreads) sinfo[q] = make_uint4(~0u, 0u, 0u, 0u);
+  __syncthreads();  // the slot table is cleared before any slot is taken
+  uint32_t* bslot = ctx_ptr<uint32_t>(ctx, L.bslot);
   unsigned long long run = before + incl - mine;
   for (int i = a0; i < a1; ++i) {
     const uint32_t c = tcur[i];
@@ -126,6 +140,19 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
     ranges[i] = r;
     tcur[i] = (uint32_t)run;
     binfo[atomicAdd(&bins[order_bin(c)], 1u)] = make_uint4((uint32_t)i, r.x, r.y, 0u);
+    // split when longer than the view's threshold (the slot order is arbitrary)
+    uint32_t sl = 0u;
+    if (!ovf && c > (uint32_t)kSplitLen) {
+      const int v = find_view(views, rc.n_views, i);
+      int j = 0;
+      while (j < kSplitThresholds && scount[v][j] > (uint32_t)kSplitPerView) ++j;
+      if (j < kSplitThresholds && c > (uint32_t)(kSplitLen + j * kSplitStep)) {
+        const uint32_t slot = (uint32_t)v * kSplitPerView + atomicAdd(&sused[v], 1u);
+        sinfo[slot] = make_uint4((uint32_t)i, r.x, r.y, 0u);
+        sl = slot + 1u;
+      }
+    }
+    bslot[i] = sl;
     run += c;
   }
 }
@@ -329,7 +356,7 @@ __global__ void __launch_bounds__(kListThreads) k_list_sort(RenderConst rc, cons
 void launch_bin(const RenderConst& rc, const CtxLayout& L, char* ctx, hipStream_t s) {
   const unsigned nblk = (unsigned)scan_blocks(rc.n, rc.n_views);
   const ViewDev* views = reinterpret_cast<const ViewDev*>(ctx + L.views);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTileScanThreads), 0, s, rc, ctx, L);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kTileScanThreads), 0, s, rc, views, ctx, L);
   if (nblk > 0) hipLaunchKernelGGL(k_dup_emit, dim3(nblk), dim3(kScanThreads), 0, s, rc, views, ctx, L);
 }
 
