@@ -61,6 +61,7 @@ struct CtxHeader {
 // Byte layout of a render context; every array 256-byte aligned.
 //  ntiles, dkey, toff  per (view, Gaussian): tile count, depth bits, first gradient slot
 //  bsum, vsum          per scan block: tile-count sum, visible count
+//  vlist, vcount       per view: its visible Gaussians in index order (region of n), their number
 //  tcur                per tile: intersection count, then the emission cursor
 //  ukey, tkey          per intersection: (depth << 32 | gid) in emission order; merge scratch
 //  pairgid, pslot, ptile  per sorted intersection: Gaussian, gradient slot, tile key
@@ -73,7 +74,7 @@ struct CtxHeader {
 //                      transmittance and channels at each segment boundary, and the
 //                      final channels
 struct CtxLayout {
-  size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, tcur, ukey, tkey, pairgid, pslot,
+  size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, vlist, vcount, tcur, ukey, tkey, pairgid, pslot,
       ptile, pmask, ranges, binfo, lpart, bslot, sinfo, split, tfinal, ncontrib, gslot, posepart;
   size_t total;
   int64_t nv, cap;

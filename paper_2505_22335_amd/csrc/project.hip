@@ -267,28 +267,34 @@ __global__ void __launch_bounds__(256) k_project_backward(RenderConst rc, asgs_g
   constexpr int CS = 4 + NF;
   constexpr int GS = 6 + CS;
   const int view = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = rc.n;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (i < rc.n) {
+  float* dm = dg.mean + view * dg.view_stride[0];
+  float* ds = dg.scale + view * dg.view_stride[1];
+  float* dq = dg.rot + view * dg.view_stride[2];
+  float* dop = dg.opacity + view * dg.view_stride[3];
+  float* drgb = dg.rgb + view * dg.view_stride[4];
+  float* dft = NF > 0 ? dg.feat + view * dg.view_stride[5] : nullptr;
+  // after an overflowed forward no list was blended and every gradient is zero
+  const bool ovf = ctx_ptr<const CtxHeader>(ctx, L.hdr)->overflow != 0u;
+  // Gaussian e of the view gets zero gradients when it was not visible
+  if (e < n && (ovf || ctx_ptr<const uint32_t>(ctx, L.ntiles)[(int64_t)view * n + e] == 0u)) {
+    for (int k = 0; k < 3; ++k) { dm[k * n + e] = 0.f; ds[k * n + e] = 0.f; drgb[k * n + e] = 0.f; }
+    for (int k = 0; k < 4; ++k) dq[k * n + e] = 0.f;
+    dop[e] = 0.f;
+    for (int k = 0; k < NF; ++k) dft[k * n + e] = 0.f;
+  }
+  // and the e-th visible Gaussian of the view (index order) the full chain,
+  // so that the waves on this path carry no invisible lanes
+  const int64_t nvis = ovf ? 0 : (int64_t)ctx_ptr<const uint32_t>(ctx, L.vcount)[view];
+  if (e < nvis) {
     const ViewDev& V = views[view];
-    const int64_t gid = (int64_t)view * rc.n + i;
-    // visible pairs own ntiles consecutive gradient slots from toff; after an
-    // overflowed forward no list was blended and every gradient is zero
+    const int64_t gid = (int64_t)ctx_ptr<const uint32_t>(ctx, L.vlist)[(int64_t)view * n + e];
+    const int64_t i = gid - (int64_t)view * n;
+    // visible pairs own ntiles consecutive gradient slots from toff
     const uint32_t cnt = ctx_ptr<const uint32_t>(ctx, L.ntiles)[gid];
-    const bool used = cnt > 0u && ctx_ptr<const CtxHeader>(ctx, L.hdr)->overflow == 0u;
-    float* dm = dg.mean + view * dg.view_stride[0];
-    float* ds = dg.scale + view * dg.view_stride[1];
-    float* dq = dg.rot + view * dg.view_stride[2];
-    float* dop = dg.opacity + view * dg.view_stride[3];
-    float* drgb = dg.rgb + view * dg.view_stride[4];
-    float* dft = NF > 0 ? dg.feat + view * dg.view_stride[5] : nullptr;
-    const int64_t n = rc.n;
-    if (!used) {
-      for (int k = 0; k < 3; ++k) { dm[k * n + i] = 0.f; ds[k * n + i] = 0.f; drgb[k * n + i] = 0.f; }
-      for (int k = 0; k < 4; ++k) dq[k * n + i] = 0.f;
-      dop[i] = 0.f;
-      for (int k = 0; k < NF; ++k) dft[k * n + i] = 0.f;
-    } else {
+    {
       const uint32_t start = ctx_ptr<const uint32_t>(ctx, L.toff)[gid];
       const float* slot = ctx_ptr<const float>(ctx, L.gslot);
       float G[GS];

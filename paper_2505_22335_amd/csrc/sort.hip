@@ -69,6 +69,7 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   __shared__ uint32_t bins[kOrderBins];
   __shared__ uint32_t scount[ASGS_MAX_VIEWS][kSplitThresholds];  // lists above each threshold, per view
   __shared__ uint32_t sused[ASGS_MAX_VIEWS];
+  __shared__ uint32_t vcnt[ASGS_MAX_VIEWS];
   __shared__ unsigned long long wtot[kTileScanThreads / 64];
   __shared__ uint32_t wbin[kTileScanThreads / 64];
   __shared__ unsigned long long wvis[kTileScanThreads / 64];
@@ -84,7 +85,10 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   const int a0 = min(T, t * per), a1 = min(T, a0 + per);
   bins[t] = 0u;
   for (int q = t; q < ASGS_MAX_VIEWS * kSplitThresholds; q += kTileScanThreads) (&scount[0][0])[q] = 0u;
-  if (t < ASGS_MAX_VIEWS) sused[t] = 0u;
+  if (t < ASGS_MAX_VIEWS) {
+    sused[t] = 0u;
+    vcnt[t] = 0u;
+  }
   __syncthreads();
   unsigned long long mine = 0;
   for (int i = a0; i < a1; ++i) {
@@ -102,7 +106,11 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   {
     const uint64_t nb = (uint64_t)scan_blocks(rc.n, rc.n_views);
     const uint32_t* vsum = ctx_ptr<const uint32_t>(ctx, L.vsum);
-    for (uint64_t bb = t; bb < nb; bb += kTileScanThreads) vis += vsum[bb];
+    const uint64_t nbx = (uint64_t)((rc.n + kScanThreads - 1) / kScanThreads);
+    for (uint64_t bb = t; bb < nb; bb += kTileScanThreads) {
+      vis += vsum[bb];
+      atomicAdd(&vcnt[bb / nbx], vsum[bb]);  // visible Gaussians per view
+    }
     for (int o = 32; o > 0; o >>= 1) vis += __shfl_xor(vis, o);
   }
   const unsigned long long incl = wave_incl_scan(mine, lane);
@@ -129,6 +137,7 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
     hdr->overflow = ovf ? 1u : 0u;
   }
   __syncthreads();
+  if (t < rc.n_views) ctx_ptr<uint32_t>(ctx, L.vcount)[t] = vcnt[t];
   uint4* sinfo = ctx_ptr<uint4>(ctx, L.sinfo);
   for (int q = t; q < rc.n_views * kSplitPerView; q += kTileScanThreads) sinfo[q] = make_uint4(~0u, 0u, 0u, 0u);
   __syncthreads();  // the slot table is cleared before any slot is taken
@@ -167,6 +176,7 @@ __global__ void __launch_bounds__(kScanThreads) k_dup_emit(RenderConst rc, const
                                                            char* ctx, CtxLayout L) {
   __shared__ unsigned long long wred[kScanThreads / 64];
   __shared__ uint32_t wsum[kScanThreads / 64];
+  __shared__ uint32_t wvp[kScanThreads / 64], wvc[kScanThreads / 64];
   __shared__ int bred[4];
   __shared__ uint32_t cell[kBoxCells];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -184,12 +194,29 @@ __global__ void __launch_bounds__(kScanThreads) k_dup_emit(RenderConst rc, const
   const uint32_t incl = wave_incl_scan(cnt, lane);
   if (lane == 0) wred[wv] = pre;
   if (lane == 63) wsum[wv] = incl;
+  // place in the view's visible list: visible Gaussians of the view's earlier
+  // blocks, of the earlier waves, of the earlier lanes
+  const int64_t nbx = (rc.n + kScanThreads - 1) / kScanThreads;
+  uint32_t vpre = 0;
+  for (int64_t bb = (int64_t)sb.view * nbx + t; bb < (int64_t)blockIdx.x; bb += kScanThreads)
+    vpre += ctx_ptr<const uint32_t>(ctx, L.vsum)[bb];
+  for (int o = 32; o > 0; o >>= 1) vpre += __shfl_xor(vpre, o);
+  const uint64_t vbits = __ballot(cnt > 0u);
+  if (lane == 0) {
+    wvp[wv] = vpre;
+    wvc[wv] = (uint32_t)__popcll(vbits);
+  }
   const bool small = cnt > 0u && cnt <= (uint32_t)kBoxRect;
   const TileBox bx = tile_box(r, small, bred, cell);  // synchronises: wred, wsum are complete
   unsigned long long off = 0;
   for (int w = 0; w < kScanThreads / 64; ++w) off += wred[w] + (w < wv ? wsum[w] : 0u);
   off += incl - cnt;
   if (sb.valid) ctx_ptr<uint32_t>(ctx, L.toff)[sb.j] = (uint32_t)off;
+  if (cnt > 0u) {
+    uint32_t vp = __builtin_amdgcn_mbcnt_hi((uint32_t)(vbits >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)vbits, 0u));
+    for (int w = 0; w < kScanThreads / 64; ++w) vp += wvp[w] + (w < wv ? wvc[w] : 0u);
+    ctx_ptr<uint32_t>(ctx, L.vlist)[(int64_t)sb.view * rc.n + vp] = (uint32_t)sb.j;
+  }
   const bool via_lds = bx.lds && small;
   // count the block's places per tile, reserve them, then hand them out
   if (via_lds)
