@@ -67,7 +67,7 @@ ASGS_DEV int order_bin(uint32_t c) { return kOrderBins - 1 - (int)(c < kOrderBin
 __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, const ViewDev* __restrict__ views,
                                                                char* ctx, CtxLayout L) {
   __shared__ uint32_t bins[kOrderBins];
-  __shared__ uint32_t scount[ASGS_MAX_VIEWS][kSplitThresholds];  // lists above each threshold, per view
+  __shared__ uint32_t scount[ASGS_MAX_VIEWS][kSplitThresholds];  // per view: lists per length band, then above each threshold
   __shared__ uint32_t sused[ASGS_MAX_VIEWS];
   __shared__ uint32_t vcnt[ASGS_MAX_VIEWS];
   __shared__ unsigned long long wtot[kTileScanThreads / 64];
@@ -96,9 +96,9 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
     mine += c;
     atomicAdd(&bins[order_bin(c)], 1u);
     if (c > (uint32_t)kSplitLen) {
-      const int v = find_view(views, rc.n_views, i);
-      for (int j = 0; j < kSplitThresholds; ++j)
-        if (c > (uint32_t)(kSplitLen + j * kSplitStep)) atomicAdd(&scount[v][j], 1u);
+      // band j: kSplitLen + j kSplitStep < c <= kSplitLen + (j + 1) kSplitStep (the last open)
+      const uint32_t j = (c - kSplitLen - 1) / kSplitStep;
+      atomicAdd(&scount[find_view(views, rc.n_views, i)][j < kSplitThresholds ? j : kSplitThresholds - 1], 1u);
     }
   }
   // visible pairs: sum of the per-block counts
@@ -117,6 +117,14 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   if (lane == 63) wtot[wv] = incl;
   if (lane == 0) wvis[wv] = vis;
   __syncthreads();
+  // lists above each threshold: suffix sums of the bands, one view per thread
+  if (t < rc.n_views) {
+    uint32_t above = 0u;
+    for (int j = kSplitThresholds - 1; j >= 0; --j) {
+      above += scount[t][j];
+      scount[t][j] = above;
+    }
+  }
   const uint32_t bv = bins[t];
   const uint32_t bincl = wave_incl_scan(bv, lane);
   if (lane == 63) wbin[wv] = bincl;
