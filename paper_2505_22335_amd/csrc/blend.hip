@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
   uint16_t (&apl)[NW][kBwdBatch][CP] = acf[3];
   __shared__ __attribute__((aligned(16))) float part[NW][kRound][PS];  // per-wave partial rows of the round's entries
   __shared__ int sent[NW][kBwdBatch];     // round entry of each batch position
-  __shared__ uint32_t sslot[kRound];      // gradient slot of each round entry
+  __shared__ uint32_t sslot[2][kRound];   // gradient slot of each round entry (two rounds in flight)
   __shared__ uint8_t smk[kRound];         // quarter mask of each round entry (from the forward)
 
   // The Gaussian ids of the first round (the back kRound entries of the
@@ -734,19 +734,24 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     const int nrlo = rlo - kRound > elo ? rlo - kRound : elo;
     if (rlo > elo) fetch_gid(nrlo, rlo - nrlo);
   }
+  // partial rows start at zero; the reduction of each round zeroes the rows
+  // it has read
+  for (int q = lane; q < kRound * PS; q += 64) (&part[wv][0][0])[q] = 0.f;
+  int par = 0;  // sslot buffer of this round
   while (rhi > elo) {
-    __syncthreads();  // every reader of the previous round is done
+    // Every wave has passed the previous round's candidate loop (the barrier
+    // before its reduction), so the records and masks can be overwritten;
+    // the slots the reduction still reads are in the other buffer.
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int e = t + k * kTilePix;
       if (e / kRecF4 < rhi - rlo) srec[e] = stage[k];
     }
     if (t < rhi - rlo) {
-      sslot[t] = stage_slot;
+      sslot[par][t] = stage_slot;
       smk[t] = (uint8_t)stage_mask;
     }
-    for (int q = lane; q < kRound * PS; q += 64) (&part[wv][0][0])[q] = 0.f;
-    __syncthreads();
+    __syncthreads();  // staging visible; the previous reduction has zeroed its rows
     const int cnt = rhi - rlo;
     const int nrhi = rlo, nrlo = rlo - kRound > elo ? rlo - kRound : elo;
     if (nrhi > elo) {
@@ -835,18 +840,25 @@ __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3
     }
     if (nb > 0) flush(nb);
     __syncthreads();
-    // the four waves' rows -> one gradient slot per entry, a float4 per thread
+    // the four waves' rows -> one gradient slot per entry, a float4 per
+    // thread; the rows read are zeroed for the next round
     constexpr int F4 = PS / 4;
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int q = t; q < cnt * F4; q += kTilePix) {
       const int e = q / F4, f = q - e * F4;
       const float4 a = reinterpret_cast<const float4*>(part[0][e])[f];
       const float4 b = reinterpret_cast<const float4*>(part[1][e])[f];
       const float4 c = reinterpret_cast<const float4*>(part[2][e])[f];
       const float4 d = reinterpret_cast<const float4*>(part[3][e])[f];
-      reinterpret_cast<float4*>(gslot + (size_t)sslot[e] * PS)[f] =
+      reinterpret_cast<float4*>(gslot + (size_t)sslot[par][e] * PS)[f] =
           make_float4((a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y), (a.z + b.z) + (c.z + d.z),
                       (a.w + b.w) + (c.w + d.w));
+      reinterpret_cast<float4*>(part[0][e])[f] = z4;
+      reinterpret_cast<float4*>(part[1][e])[f] = z4;
+      reinterpret_cast<float4*>(part[2][e])[f] = z4;
+      reinterpret_cast<float4*>(part[3][e])[f] = z4;
     }
+    par ^= 1;
     rhi = nrhi;
     rlo = nrlo;
   }
