@@ -403,7 +403,8 @@ ASGS_DEV void bf_split(float v, uint16_t& hi, uint16_t& lo) {
   lo = bf_rne(v - __uint_as_float((uint32_t)hi << 16));
 }
 
-// Backward compositing, one workgroup per tile, one pixel per thread.
+// Backward compositing, one workgroup per tile (or per 128-entry segment of
+// a split list), one pixel per thread.
 //
 // Per list entry k and pixel p the gradient contributions are
 //   dL/dc_k      += w_kp G_p                 (w = alpha T, G = upstream channel gradients)
@@ -421,6 +422,9 @@ ASGS_DEV void bf_split(float v, uint16_t& hi, uint16_t& lo) {
 // on the matrix cores (bf16 16x16x32 MFMAs with both operands split into
 // hi + lo parts, K = pixels) into per-wave partial rows; the four waves' rows
 // are summed in a fixed order and written once to each entry's gradient slot.
+// A segment of a split list starts from the state the forward recorded at the
+// segment's end: T there and the sum the later entries contribute,
+// G . (C_final - C_boundary), instead of T_final and zero.
 template <int NF>
 __global__ void __launch_bounds__(kTilePix) __attribute__((amdgpu_waves_per_eu(3))) k_blend_bwd(RenderConst rc, const ViewDev* __restrict__ views,
                                                         char* ctx, CtxLayout L, asgs_images dout) {
