@@ -281,58 +281,84 @@ ASGS_DEV void assign_rows(const GroupDesc& gd, const HeadTable& ht, int grp, int
   }
 }
 
-// The group's weights into LDS: first-layer rows padded to kW1S, second-layer
-// rows to kW2S. Every load of the staging is issued before the first store.
-ASGS_DEV void stage_weights(const Views& S, const GroupDesc& gd, const HeadTable& ht, const float* params, int k,
-                            int t) {
-  constexpr int kQ1 = (4 * 32 * kW1S + kNT - 1) / kNT;          // first-layer elements per thread
-  constexpr int kQ2 = 16 * ASGS_MAX_K * kHid / kNT;             // second-layer elements per thread
-  // the group's heads (at most four) as uniform values: packed offsets and
-  // first local second-layer rows
-  int off[4], lr0[5];
+// The group's weights into LDS: first-layer rows padded to kW1S (pad columns
+// zero), second-layer rows to kW2S. Head h's packed parameters start at
+// ht.off[h]: W1 [32][35], b1 [32], W2 [rows][32], b2 [rows]. Every load is
+// issued before the first store. The index arithmetic is branch-free: the
+// head of an element is chosen by comparisons with the group's (uniform) head
+// boundaries, a lane past the end loads the last element and stores it into
+// the never-read pad column of the first second-layer row.
+ASGS_DEV void stage_weights(const Views& S, const GroupDesc& gd, const HeadTable& ht, const float* params, int t) {
+  constexpr int kW1 = kHid * kIn;                          // first-layer weights per head
+  constexpr int kQ1 = (4 * kW1 + kNT - 1) / kNT;           // first-layer elements per thread
+  constexpr int kQ2 = 16 * ASGS_MAX_K * kHid / kNT;        // second-layer elements per thread
+  static_assert(4 * kW1 <= 4480, "the unit index below divides by 35 with a multiply and shift");
+  // per head j of the group: source base of its first-layer elements (indexed
+  // by the group's element e = j * kW1 + u * kIn + c), of its second-layer
+  // elements (e = 32 * local row + c), of b1 (by unit) and b2 (by local row);
+  // absent heads repeat the last one and start past the end
+  int o1[4], o2[4], ob1[4], ob2[4], r0[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int h = gd.hbase + (j < gd.nheads ? j : 0);
-    off[j] = ht.off[h];
-    lr0[j] = j < gd.nheads ? gd.lrow0[h] : gd.nrows;
+    const int jj = j < gd.nheads ? j : gd.nheads - 1;
+    const int h = gd.hbase + jj;
+    const int rows = (jj + 1 < gd.nheads ? gd.lrow0[h + 1] : gd.nrows) - gd.lrow0[h];
+    r0[j] = j < gd.nheads ? gd.lrow0[h] : gd.nrows;
+    o1[j] = ht.off[h] - jj * kW1;
+    o2[j] = ht.off[h] + kW1 + kHid - kHid * gd.lrow0[h];
+    ob1[j] = ht.off[h] + kW1 - kHid * jj;
+    ob2[j] = ht.off[h] + kW1 + kHid + kHid * rows - gd.lrow0[h];
   }
-  lr0[4] = gd.nrows;
-  auto pick = [&](int j, const int (&v)[4]) { return j == 0 ? v[0] : j == 1 ? v[1] : j == 2 ? v[2] : v[3]; };
-  auto head_of_row = [&](int lr) { return (lr >= lr0[1]) + (lr >= lr0[2]) + (lr >= lr0[3]); };
-  const int n1 = gd.nunits * kW1S, n2 = gd.nrows * kHid;
-  float v1[kQ1], v2[kQ2], vb1 = 0.f, vb2 = 0.f;
+  const int n1 = gd.nunits * kIn, n2 = gd.nrows * kHid;
+  float* const trash = S.W2s + kHid;  // column 32 of second-layer row 0: never read
+  float v1[kQ1], v2[kQ2];
+  int d1[kQ1], d2[kQ2];
 #pragma unroll
   for (int q = 0; q < kQ1; ++q) {
     const int e = t + q * kNT;
-    const int u = e / kW1S, c = e - u * kW1S;
-    v1[q] = (e < n1 && c < kIn) ? params[pick(u >> 5, off) + (u & 31) * kIn + c] : 0.f;
+    const int ec = e < n1 ? e : n1 - 1;
+    int base = o1[0];
+    base = ec >= kW1 ? o1[1] : base;
+    base = ec >= 2 * kW1 ? o1[2] : base;
+    base = ec >= 3 * kW1 ? o1[3] : base;
+    v1[q] = params[(unsigned)(base + ec)];
+    const int u = (ec * 3745) >> 17;  // ec / 35, exact for ec < 4480
+    d1[q] = e < n1 ? ec + (kW1S - kIn) * u : -1;  // row u * kW1S, column ec - kIn * u
   }
 #pragma unroll
   for (int q = 0; q < kQ2; ++q) {
     const int e = t + q * kNT;
-    const int lr = e >> 5, c = e & 31;
-    const int j = head_of_row(lr);
-    const int jr = lr - (j == 0 ? lr0[0] : j == 1 ? lr0[1] : j == 2 ? lr0[2] : lr0[3]);
-    v2[q] = e < n2 ? params[pick(j, off) + kHid * kIn + kHid + jr * kHid + c] : 0.f;
+    const int ec = e < n2 ? e : n2 - 1;
+    const int lr = ec >> 5;
+    int base = o2[0];
+    base = lr >= r0[1] ? o2[1] : base;
+    base = lr >= r0[2] ? o2[2] : base;
+    base = lr >= r0[3] ? o2[3] : base;
+    v2[q] = params[(unsigned)(base + ec)];
+    d2[q] = e < n2 ? ec + (kW2S - kHid) * lr : -1;  // row lr * kW2S, column ec & 31
   }
-  if (t < gd.nunits) vb1 = params[pick(t >> 5, off) + kHid * kIn + (t & 31)];
-  if (t < gd.nrows) {
-    const int j = head_of_row(t);
-    const int r0 = j == 0 ? lr0[0] : j == 1 ? lr0[1] : j == 2 ? lr0[2] : lr0[3];
-    const int rows = (j == 0 ? lr0[1] : j == 1 ? lr0[2] : j == 2 ? lr0[3] : lr0[4]) - r0;
-    vb2 = params[pick(j, off) + kHid * kIn + kHid + rows * kHid + (t - r0)];
-  }
+  const int tb1 = t < gd.nunits ? t : gd.nunits - 1;
+  int bb1 = ob1[0];
+  bb1 = tb1 >= 32 ? ob1[1] : bb1;
+  bb1 = tb1 >= 64 ? ob1[2] : bb1;
+  bb1 = tb1 >= 96 ? ob1[3] : bb1;
+  const float vb1 = params[(unsigned)(bb1 + tb1)];
+  const int tb2 = t < gd.nrows ? t : gd.nrows - 1;
+  int bb2 = ob2[0];
+  bb2 = tb2 >= r0[1] ? ob2[1] : bb2;
+  bb2 = tb2 >= r0[2] ? ob2[2] : bb2;
+  bb2 = tb2 >= r0[3] ? ob2[3] : bb2;
+  const float vb2 = params[(unsigned)(bb2 + tb2)];
 #pragma unroll
-  for (int q = 0; q < kQ1; ++q)
-    if (t + q * kNT < n1) S.W1s[t + q * kNT] = v1[q];
+  for (int q = 0; q < kQ1; ++q) *(d1[q] >= 0 ? S.W1s + d1[q] : trash) = v1[q];
 #pragma unroll
-  for (int q = 0; q < kQ2; ++q) {
-    const int e = t + q * kNT;
-    if (e < n2) S.W2s[(e >> 5) * kW2S + (e & 31)] = v2[q];
+  for (int q = 0; q < kQ2; ++q) *(d2[q] >= 0 ? S.W2s + d2[q] : trash) = v2[q];
+  if (t < gd.nunits) {
+    S.W1s[t * kW1S + kIn] = 0.f;
+    S.W1s[t * kW1S + kIn + 1] = 0.f;
+    S.b1s[t] = vb1;
   }
-  if (t < gd.nunits) S.b1s[t] = vb1;
   if (t < gd.nrows) S.b2s[t] = vb2;
-  (void)k;
 }
 
 __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTable ht, DecodeViews dv,
@@ -407,7 +433,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
   // the first tile's inputs are requested before the weights, so that the
   // two latencies overlap
   if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
-  stage_weights(S, gd, ht, params, k, t);
+  stage_weights(S, gd, ht, params, t);
   for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
     const int a0 = tile * 16;
     __syncthreads();  // weights staged / the previous tile's readers are done
@@ -606,7 +632,7 @@ __global__ void __launch_bounds__(kNT, 3) k_dec_fwd_heads(DecodeConst dc, HeadTa
   // the first tile's inputs are requested before the weights, so that the
   // two latencies overlap
   if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
-  stage_weights(S, gd, ht, params, k, t);
+  stage_weights(S, gd, ht, params, t);
   for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
     const int a0 = tile * 16;
     __syncthreads();  // weights staged / the previous tile's outputs are written
