@@ -13,8 +13,10 @@
 // Persistent grid, one workgroup per CU: the workgroup stages both layers'
 // weights once in LDS (padded rows against bank conflicts) together with a
 // per-row output table, then its 12 waves loop over 16-anchor tiles of the
-// grid-strided sequence. Everything a wave keeps per tile is bfloat16 in LDS
-// so that 12 waves fit beside the weights. The backward always runs in FP32
+// grid-strided sequence (dealt out workgroup-first, so that every compute
+// unit gets tiles also when there are fewer than 12 per unit). Everything a
+// wave keeps per tile is bfloat16 in LDS so that 12 waves fit beside the
+// weights. The backward always runs in FP32
 // (decode.hip).
 #include <math.h>
 
@@ -40,6 +42,16 @@ ASGS_DEV uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
   return (uint16_t)(u >> 16);
+}
+
+// v0 .. v4 selected by four ordered conditions (the last true one wins).
+ASGS_DEV int sel5(bool c1, bool c2, bool c3, bool c4, int v0, int v1, int v2, int v3, int v4) {
+  int x = v0;
+  x = c1 ? v1 : x;
+  x = c2 ? v2 : x;
+  x = c3 ? v3 : x;
+  x = c4 ? v4 : x;
+  return x;
 }
 
 ASGS_DEV float fast_sigm(float y) { return __builtin_amdgcn_rcpf(1.f + __expf(-y)); }
@@ -81,31 +93,94 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
     prow0[kHeads] = r;
   }
   // ---- stage the weights and the output table ----
+  // Every load is issued before the first store (one round trip to memory):
+  // thread t takes the elements t + q * kThreads of the first layer's
+  // 160 x 32 feature weights and of the padded second-layer rows. The source
+  // of an element is selected from the heads' (uniform) offsets by
+  // comparisons, without branches; elements of absent heads or of padding
+  // rows load a valid address and are stored as zero or into rows that are
+  // never read.
+  constexpr int kQ1 = (kHeads * kHid * 32 + kThreads - 1) / kThreads;
+  constexpr int kQ2 = kMaxPRows * 32 / kThreads;
+  static_assert(kQ2 * kThreads == kMaxPRows * 32, "second-layer rounds cover the padded rows exactly");
+  static_assert(kMaxPRows <= kThreads && kHeads * kHid <= kThreads, "one bias row per thread");
+  const int nprows = prow0[kHeads];
+  // per head (uniform): packed offset, source base of its padded-row
+  // elements, end of its real rows, output components and source of b2
+  int o1[kHeads], ob[kHeads], rend[kHeads], mm[kHeads], obb[kHeads];
   for (int h = 0; h < kHeads; ++h) {
-    const int m = ht.m[h];
-    if (m == 0) continue;
-    const float* W1 = params + ht.off[h];
-    for (int e = t; e < kHid * 32; e += kThreads) {
-      const int jj = e >> 5, c = e & 31;
-      w1[(h * kHid + jj) * kRow + c] = f2bf(W1[jj * kIn + c]);
-    }
-    for (int jj = t; jj < kHid; jj += kThreads) {
-      w1d[h * kHid + jj][0] = W1[jj * kIn + 32];
-      w1d[h * kHid + jj][1] = W1[jj * kIn + 33];
-      w1d[h * kHid + jj][2] = W1[jj * kIn + 34];
-      w1d[h * kHid + jj][3] = W1[kHid * kIn + jj];
-    }
-    const int rows = k * m;
-    const int prows = prow0[h + 1] - prow0[h];
-    const float* W2 = W1 + kHid * kIn + kHid;
-    for (int e = t; e < prows * 32; e += kThreads) {
-      const int r = e >> 5, c = e & 31;
-      w2[(prow0[h] + r) * kRow + c] = f2bf(r < rows ? W2[r * kHid + c] : 0.f);
-    }
-    for (int r = t; r < prows; r += kThreads) {
-      b2s[prow0[h] + r] = r < rows ? W2[rows * kHid + r] : 0.f;
-      epi[prow0[h] + r] = r < rows ? (r % m) * n + r / m : -1;
-    }
+    o1[h] = ht.off[h];
+    ob[h] = ht.off[h] + kHid * kIn + kHid - kHid * prow0[h];
+    rend[h] = prow0[h] + k * ht.m[h];
+    mm[h] = ht.m[h];
+    obb[h] = ht.off[h] + kHid * kIn + kHid + kHid * k * ht.m[h] - prow0[h];
+  }
+  // value of the head that hidden unit u (by unit) or padded row pr (by row)
+  // belongs to; the arrays are read at constant indices only
+#define ASGS_BY_UNIT(u, v) sel5((u) >= 32, (u) >= 64, (u) >= 96, (u) >= 128, v[0], v[1], v[2], v[3], v[4])
+#define ASGS_BY_ROW(pr, v) \
+  sel5((pr) >= prow0[1], (pr) >= prow0[2], (pr) >= prow0[3], (pr) >= prow0[4], v[0], v[1], v[2], v[3], v[4])
+  float v1[kQ1], v2[kQ2];
+#pragma unroll
+  for (int q = 0; q < kQ1; ++q) {
+    const int e = t + q * kThreads;
+    int u = e >> 5;
+    u = u < nunits ? u : nunits - 1;
+    v1[q] = params[(unsigned)(ASGS_BY_UNIT(u, o1) + (u & 31) * kIn + (e & 31))];
+  }
+#pragma unroll
+  for (int q = 0; q < kQ2; ++q) {
+    const int e = t + q * kThreads;
+    int pr = e >> 5;
+    pr = pr < nprows ? pr : nprows - 1;
+    const int re = ASGS_BY_ROW(pr, rend);
+    const int prc = pr < re ? pr : re - 1;  // padding rows read the head's last row
+    const float w = params[(unsigned)(ASGS_BY_ROW(pr, ob) + prc * kHid + (e & 31))];
+    v2[q] = pr < re ? w : 0.f;
+  }
+  float wd[4];
+  {
+    const int u = t < nunits ? t : nunits - 1;
+    const int src = ASGS_BY_UNIT(u, o1) + (u & 31) * kIn;
+    wd[0] = params[(unsigned)(src + 32)];
+    wd[1] = params[(unsigned)(src + 33)];
+    wd[2] = params[(unsigned)(src + 34)];
+    wd[3] = params[(unsigned)(ASGS_BY_UNIT(u, o1) + kHid * kIn + (u & 31))];
+  }
+  // per padded row t: second-layer bias and output code (r % m) * n + r / m
+  float bias2;
+  int code;
+  {
+    const int pr = t < nprows ? t : nprows - 1;
+    const int m = ASGS_BY_ROW(pr, mm);
+    const int re = ASGS_BY_ROW(pr, rend);
+    const int r = pr - (re - k * m);
+    const bool real = pr < re;
+    const float bv = params[(unsigned)(ASGS_BY_ROW(pr, obb) + (real ? pr : re - 1))];
+    bias2 = real ? bv : 0.f;
+    code = real ? (r % m) * n + r / m : -1;
+  }
+#undef ASGS_BY_UNIT
+#undef ASGS_BY_ROW
+#pragma unroll
+  for (int q = 0; q < kQ1; ++q) {
+    const int e = t + q * kThreads;
+    if (e < kHeads * kHid * 32) w1[(e >> 5) * kRow + (e & 31)] = f2bf(v1[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < kQ2; ++q) {
+    const int e = t + q * kThreads;
+    w2[(e >> 5) * kRow + (e & 31)] = f2bf(v2[q]);
+  }
+  if (t < kHeads * kHid) {
+    w1d[t][0] = wd[0];
+    w1d[t][1] = wd[1];
+    w1d[t][2] = wd[2];
+    w1d[t][3] = wd[3];
+  }
+  if (t < kMaxPRows) {
+    b2s[t] = t < nprows ? bias2 : 0.f;
+    epi[t] = t < nprows ? code : -1;
   }
   __syncthreads();
   float* hbase[kHeads];
@@ -131,7 +206,9 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
 #pragma unroll
     for (int c = 0; c < 3; ++c) xd[c] = xyz[c * A + a];
   };
-  int tile = (int)blockIdx.x * kWaves + wv;
+  // tiles are dealt out workgroup-first (tile b + gridDim.x * (wv + kWaves * i)),
+  // so that a short sequence still reaches every compute unit
+  int tile = (int)blockIdx.x + (int)gridDim.x * wv;
   if (tile < ntiles) load_tile(tile);
   for (; tile < ntiles; tile += tstride) {
     const int a0 = tile * kMT;
@@ -222,8 +299,7 @@ void launch_decode_mfma(const DecodeConst& dc, const HeadTable& ht, const Decode
                         const float* feat, const float* off, const float* params, const asgs_gaussians& out,
                         hipStream_t s) {
   const int64_t tiles = (dc.A + kMT - 1) / kMT;
-  const int64_t wgs = (tiles + kWaves - 1) / kWaves;
-  dim3 grid((unsigned)(wgs < kMaxWG ? wgs : kMaxWG), (unsigned)dc.n_views);
+  dim3 grid((unsigned)(tiles < kMaxWG ? tiles : kMaxWG), (unsigned)dc.n_views);
   hipLaunchKernelGGL(k_decode_bf16, grid, dim3(kThreads), 0, s, dc, ht, dv, xyz, feat, off, params, out);
 }
 

@@ -163,15 +163,18 @@ def test_end_to_end_config2_full():
     assert e <= GRAD_TOL
 
 
-def test_decode_bf16_matches_bf16_emulation():
+@pytest.mark.parametrize("k,nf,nv", [(10, 16, 2), (3, 16, 1), (7, 0, 2), (16, 16, 1), (1, 16, 1)])
+def test_decode_bf16_matches_bf16_emulation(k, nf, nv):
     """BF16 matrix-core decode equals the oracle's bfloat16 emulation (same
     operand rounding, exact products, float64 sums) up to FP32 accumulation
     and rare operand-rounding flips; its error against the FP64 decode is
-    logged."""
-    sc = synth.tiny_anchor_scene(91, 300, k=10, n_feat=16)
-    cams = _cams_tiny(2)
+    logged. Gaussians per anchor from 1 to 16 (second-layer rows padded to
+    tiles of 16 per head) and a decoder without the feature head."""
+    sc = synth.tiny_anchor_scene(91 + k, 300, k=k, n_feat=nf)
+    cams = _cams_tiny(nv)
+    log("case bf16 decode", k, nf, nv)
     a = anchors_to_device(sc)
-    dec = P.Decoder(a.A, 10, 16, 1, a.l_o, a.l_s)
+    dec = P.Decoder(a.A, k, nf, 1, a.l_o, a.l_s)
     out = dec.decode(a.xyz, a.feat, a.off, a.params, cams)
     torch.cuda.synchronize()
     t = lambda x: torch.as_tensor(np.asarray(x, np.float64))
@@ -181,8 +184,10 @@ def test_decode_bf16_matches_bf16_emulation():
         c = camera_center(R, tc)
         g16 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s, precision="bf16")
         g64 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s)
-        for f in ("opacity", "rgb", "scale", "rot", "feat"):
-            x = to_np(out[f][v])
+        for f in ("opacity", "rgb", "scale", "rot", "feat", "mean"):
+            if f == "feat" and nf == 0:
+                continue
+            x = to_np(out[f][v]) if f != "mean" else to_np(out[f])
             e16 = rel_err(x, g16[f].numpy().T)
             e64 = rel_err(x, g64[f].numpy().T)
             log("bf16 decode", v, f, "vs bf16 emulation %.2e" % e16, "vs fp64 %.2e" % e64)
