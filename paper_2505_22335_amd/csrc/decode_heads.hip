@@ -150,6 +150,24 @@ ASGS_DEV void head_forward(const Views& S, float (*Hw)[kHS], const HeadCtx& c, i
   }
 }
 
+// One 16-unit half of the first layer of head c (the feature head's units
+// are split over two waves that write one shared H).
+ASGS_DEV void head_forward_half(const Views& S, float (*Hw)[kHS], const HeadCtx& c, int half, int fl, int fg) {
+  f4v z = {0.f, 0.f, 0.f, 0.f};
+  const int u = 16 * half + fl;
+#pragma unroll
+  for (int ks = 0; ks < 9; ++ks) {
+    const int kk = 4 * ks + fg;
+    z = mfma(S.X[fl][kk], S.W1s[(c.lunit0 + u) * kW1S + kk], z);
+  }
+  const float b = S.b1s[c.lunit0 + u];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float zz = z[r] + b;
+    Hw[4 * fg + r][u] = c.h == 4 ? fsoftplus(zz) : fmaxf(zz, 0.f);
+  }
+}
+
 // Output row tiles [t0, t0 + nt) of head c (nt <= kAcc): dY, dW2, db2 and the
 // partial dH over these rows.
 ASGS_DEV void head_rows(const Views& S, float (*Hw)[kHS], float (*Tw)[kTS], const HeadCtx& c, const RowMap& rm,
@@ -393,7 +411,9 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
   float db1[2] = {0.f, 0.f};
 #pragma unroll
   for (int q = 0; q < 2; ++q) dw1[q][0] = dw1[q][1] = dw1[q][2] = f4v{0.f, 0.f, 0.f, 0.f};
-  float (*Hw)[kHS] = S.H[wv];
+  // group 1 (one head over four waves): one H for the workgroup, its two
+  // unit halves formed by waves 0 and 1 (read-only until the next tile)
+  float (*Hw)[kHS] = grp == 1 ? S.H[0] : S.H[wv];
   float (*Tw)[kTS] = S.T[wv];
   float* dxout = w.dxpart + (size_t)grp * A * kDX;
   const int ngrid = (A + 15) / 16;
@@ -463,8 +483,13 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
     for (int ct = 0; ct < 3; ++ct) dx[ct] = f4v{0.f, 0.f, 0.f, 0.f};
     f4v dh0 = {0.f, 0.f, 0.f, 0.f}, dh1 = dh0;
     f4v dz[2];
-    head_forward(S, Hw, hc, fl, fg);
-    wave_sync();
+    if (grp == 1) {
+      if (wv < 2) head_forward_half(S, Hw, hc, wv, fl, fg);
+      __syncthreads();  // the shared H is complete
+    } else {
+      head_forward(S, Hw, hc, fl, fg);
+      wave_sync();
+    }
     head_rows(S, Hw, Tw, hc, rm, t0, nt, k, dc.l_s, dw2, db2, dh0, dh1, fl, fg);
     if (grp == 0) {
       head_dz(Hw, Tw, hc, dh0, dh1, dz, fl, fg);
@@ -603,7 +628,9 @@ __global__ void __launch_bounds__(kNT, 3) k_dec_fwd_heads(DecodeConst dc, HeadTa
   RowMap rm;
   int t0, nt;
   assign_rows(gd, ht, grp, wv, k, fl, hc, rm, t0, nt);
-  float (*Hw)[kHS] = S.H[wv];
+  // group 1 (one head over four waves): one H for the workgroup, its two
+  // unit halves formed by waves 0 and 1
+  float (*Hw)[kHS] = grp == 1 ? S.H[0] : S.H[wv];
   const int run = 16 * k;
   const int nplanes = gd.gtot / run;
   const int ngrid = (A + 15) / 16;
@@ -655,8 +682,13 @@ __global__ void __launch_bounds__(kNT, 3) k_dec_fwd_heads(DecodeConst dc, HeadTa
     const float mx[3] = {mxp[0], mxp[1], mxp[2]}, mo[3] = {mop[0], mop[1], mop[2]};
     __syncthreads();
     if (tile + (int)gridDim.x < ngrid) fetch(tile + gridDim.x);
-    head_forward(S, Hw, hc, fl, fg);
-    wave_sync();
+    if (grp == 1) {
+      if (wv < 2) head_forward_half(S, Hw, hc, wv, fl, fg);
+      __syncthreads();  // the shared H is complete
+    } else {
+      head_forward(S, Hw, hc, fl, fg);
+      wave_sync();
+    }
 #pragma unroll
     for (int i = 0; i < kAcc; ++i) {
       if (i >= nt) break;
