@@ -11,8 +11,9 @@
 // The heads are split over two kinds of workgroup that run side by side
 // (blockIdx.y): group 0 takes opacity, colour, scale and rotation, one head
 // per wave, and sums the four dX_h through LDS; group 1 takes the feature
-// head, its output rows split over the four waves, whose dH partials are
-// summed through LDS before dZ. Each group writes its dX partial per anchor
+// head: its hidden layer is formed once (one 16-unit half on each of waves 0
+// and 1), its output rows are split over the four waves, whose dH partials
+// are summed through LDS before dZ. Each group writes its dX partial per anchor
 // and one partial of each of its parameters per workgroup; the anchor
 // gradients and the parameter sums follow in fixed order (deterministic).
 //
