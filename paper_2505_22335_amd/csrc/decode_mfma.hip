@@ -266,26 +266,26 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
       }
     }
     wave_sync();
-    // ---- layer 2, head by head: 16 anchors x (k * m) rows ----
+    // ---- layer 2, head by head: (k * m) rows x 16 anchors ----
+    // The weight rows are the A operand and the anchors the B operand, so
+    // that lane (fl, fg) holds rows 4 fg + r of anchor fl: a store
+    // instruction writes four rows of 16 consecutive anchors (stride k).
+    const int a = a0 + fl;
     for (int h = 0; h < kHeads; ++h) {
       if (ht.m[h] == 0) continue;
       const bf8v ha = *reinterpret_cast<const bf8v*>(&Hs[wv][fl][32 * h + 8 * fg]);
       float* base = hbase[h];
       for (int pr0 = prow0[h]; pr0 < prow0[h + 1]; pr0 += 16) {
-        const int pr = pr0 + fl;
-        const bf8v b = *reinterpret_cast<const bf8v*>(&w2[pr * kRow + 8 * fg]);
+        const bf8v b = *reinterpret_cast<const bf8v*>(&w2[(pr0 + fl) * kRow + 8 * fg]);
         f4v c4 = {0.f, 0.f, 0.f, 0.f};
-        c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ha, b, c4, 0, 0, 0);
-        const int code = epi[pr];
-        const float bias = b2s[pr];
-        if (code >= 0) {
+        c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, ha, c4, 0, 0, 0);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int a = a0 + 4 * fg + r;
-            const float y = c4[r] + bias;
-            const float v = h <= 1 ? fast_sigm(y) : (h == 2 ? dc.l_s * fast_sigm(y) : y);
-            if (a < A) base[code + a * k] = v;
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int pr = pr0 + 4 * fg + r;
+          const int code = epi[pr];
+          const float y = c4[r] + b2s[pr];
+          const float v = h <= 1 ? fast_sigm(y) : (h == 2 ? dc.l_s * fast_sigm(y) : y);
+          if (code >= 0 && a < A) base[code + a * k] = v;
         }
       }
     }
