@@ -219,8 +219,8 @@ def main():
                     help="capture one step into a HIP graph and time its replays (checked bitwise against the eager step)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the hot path is not sharded across GPUs in this build "
-              "(see DESIGN.md, 'More than one GPU'). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the hot path is not sharded across GPUs. "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
