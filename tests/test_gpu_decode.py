@@ -163,16 +163,18 @@ def test_end_to_end_config2_full():
     assert e <= GRAD_TOL
 
 
-@pytest.mark.parametrize("k,nf,nv", [(10, 16, 2), (3, 16, 1), (7, 0, 2), (16, 16, 1), (1, 16, 1)])
-def test_decode_bf16_matches_bf16_emulation(k, nf, nv):
+@pytest.mark.parametrize("k,nf,nv,A", [(10, 16, 2, 300), (3, 16, 1, 300), (7, 0, 2, 300), (16, 16, 1, 300),
+                                        (1, 16, 1, 300), (10, 16, 1, 5)])
+def test_decode_bf16_matches_bf16_emulation(k, nf, nv, A):
     """BF16 matrix-core decode equals the oracle's bfloat16 emulation (same
     operand rounding, exact products, float64 sums) up to FP32 accumulation
     and rare operand-rounding flips; its error against the FP64 decode is
     logged. Gaussians per anchor from 1 to 16 (second-layer rows padded to
-    tiles of 16 per head) and a decoder without the feature head."""
-    sc = synth.tiny_anchor_scene(91 + k, 300, k=k, n_feat=nf)
+    tiles of 16 per head), a decoder without the feature head, and a single
+    partial tile of 5 anchors."""
+    sc = synth.tiny_anchor_scene(91 + k, A, k=k, n_feat=nf)
     cams = _cams_tiny(nv)
-    log("case bf16 decode", k, nf, nv)
+    log("case bf16 decode", k, nf, nv, A)
     a = anchors_to_device(sc)
     dec = P.Decoder(a.A, k, nf, 1, a.l_o, a.l_s)
     out = dec.decode(a.xyz, a.feat, a.off, a.params, cams)
