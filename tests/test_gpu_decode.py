@@ -51,11 +51,12 @@ def _cams_tiny(nv):
             for v in range(nv)]
 
 
-@pytest.mark.parametrize("k,nf,nv", [(10, 16, 1), (3, 16, 2), (7, 0, 3), (16, 16, 2), (1, 16, 1)])
-def test_decode_forward_backward(k, nf, nv):
-    sc = synth.tiny_anchor_scene(50 + k, 77, k=k, n_feat=nf)
+@pytest.mark.parametrize("k,nf,nv,A", [(10, 16, 1, 77), (3, 16, 2, 77), (7, 0, 3, 77), (16, 16, 2, 77), (1, 16, 1, 77),
+                                        (10, 16, 2, 5)])
+def test_decode_forward_backward(k, nf, nv, A):
+    sc = synth.tiny_anchor_scene(50 + k, A, k=k, n_feat=nf)
     cams = _cams_tiny(nv)
-    log("case decode", k, nf, nv)
+    log("case decode", k, nf, nv, A)
     a = anchors_to_device(sc)
     dec = P.Decoder(a.A, k, nf, 0, a.l_o, a.l_s)
     out = dec.decode(a.xyz, a.feat, a.off, a.params, cams)
