@@ -168,6 +168,18 @@ int asgs_ctx_status(const void* ctx, void* stream, int64_t* n_isect, int64_t* n_
  *  ASGS_CTX_NCONTRIB    uint32[P]   per pixel: list position + 1 of the last
  *                                   composited Gaussian of its tile
  *  ASGS_CTX_TFINAL      float[P]    per pixel final transmittance
+ *  ASGS_CTX_GEOM        float[V*n][8] u, v, conic A, B, C, opacity, ln(alpha_min / o), 0;
+ *                                   written for the (view, Gaussian) pairs whose radius
+ *                                   entry is >= 0, undefined for the others
+ *  ASGS_CTX_RADIUS      float[V*n][2] footprint half-widths r_x, r_y in whole pixels
+ *                                   (ceil of sqrt(2 ln(o / alpha_min) Sigma'), Eq. 2),
+ *                                   -1 for pairs culled before the footprint
+ *  ASGS_CTX_DEPTH_KEY   uint32[V*n] float32 bits of the camera depth that orders the
+ *                                   tile lists; 0xFFFFFFFF for pairs that touch no tile
+ *  ASGS_CTX_NTILES      uint32[V*n] tiles of the pair's rectangle, 0 when not listed
+ * Tile rectangle of a listed pair from its geometry and radii (integer
+ * arithmetic, T = tile side): tx0 = max(0, floor((floor(u) - r_x) / T)),
+ * tx1 = min(tiles_x - 1, floor((floor(u) + r_x) / T)), ty likewise with v, r_y.
  * cams/n_views/n_gauss/opts/ctx_bytes must be those of the forward call.
  * `*ptr` is a device pointer inside ctx and `*count` its element count
  * (for the pair arrays: the capacity; read I from asgs_ctx_status). */
@@ -177,7 +189,11 @@ enum {
   ASGS_CTX_TILE_RANGE = 3,
   ASGS_CTX_RECT = 4,
   ASGS_CTX_NCONTRIB = 5,
-  ASGS_CTX_TFINAL = 6
+  ASGS_CTX_TFINAL = 6,
+  ASGS_CTX_GEOM = 7,
+  ASGS_CTX_RADIUS = 8,
+  ASGS_CTX_DEPTH_KEY = 9,
+  ASGS_CTX_NTILES = 10
 };
 int asgs_ctx_array(const asgs_camera* cams, int32_t n_views, int64_t n_gauss,
                    const asgs_render_opts* opts, void* ctx, size_t ctx_bytes, int32_t which,

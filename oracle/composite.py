@@ -74,17 +74,19 @@ def composite_tile(u, v, A, B, C, o, chans, px, py, opts: RenderOpts, with_margi
         return acc, alpha_sum, T_final, n_contrib
     # Guard-band margins: relative distance of each decision to its threshold,
     # over the Gaussians a pixel actually reaches (up to and including the one
-    # that stops it). A decision taken where the transmittance is below
-    # impact_T cannot move the outputs by more than ~2 alpha_min impact_T
-    # times a channel value and is ignored.
+    # that stops it). An alpha_min (or alpha_max) decision taken where the
+    # transmittance is below impact_T cannot move the outputs by more than
+    # ~2 alpha_min impact_T times a channel value and is ignored. A
+    # termination decision is never ignored: the Gaussian it admits or stops
+    # may have any alpha, so its effect is up to T times a channel value.
     with torch.no_grad():
         first_stop = term & (torch.cumsum(term.to(torch.int64), 0) == 1)
-        reached = ((~stopped) | first_stop).numpy() & (power.numpy() <= 0)
-        reached &= T_before.numpy() >= impact_T
+        reached_all = ((~stopped) | first_stop).numpy() & (power.numpy() <= 0)
+        reached = reached_all & (T_before.numpy() >= impact_T)
         vn = valid.numpy()
         m_alpha = np.where(reached, np.abs(alpha.numpy() - opts.alpha_min) / opts.alpha_min, np.inf)
         m_clamp = np.where(reached & vn, np.abs(raw.numpy() - opts.alpha_max) / opts.alpha_max, np.inf)
-        m_term = np.where(reached & vn, np.abs(T_after.numpy() - opts.T_min) / opts.T_min, np.inf)
+        m_term = np.where(reached_all & vn, np.abs(T_after.numpy() - opts.T_min) / opts.T_min, np.inf)
         margins = dict(alpha=m_alpha.min(0), clamp=m_clamp.min(0), term=m_term.min(0),
                        tie=np.full(P, np.inf))
         if z32 is not None and K > 1:

@@ -32,7 +32,8 @@ def project(mean, scale, rot, opacity, R_cw, t_cw, width, height, fx, fy, cx, cy
     non-differentiable numpy arrays: visible (bool), rect (N,4) int64
     [tx0, tx1, ty0, ty1] inclusive, ntiles, z32 (float32 depth key), and the
     guard-band margin of the footprint radius (distance of its real value
-    to the nearest integer).
+    to the nearest integer), the whole-pixel radii and their unrounded
+    values (extent).
     """
     N = mean.shape[0]
     t = mean @ R_cw.T + t_cw[None, :]
@@ -104,4 +105,4 @@ def project(mean, scale, rot, opacity, R_cw, t_cw, width, height, fx, fy, cx, cy
     z32 = tz_raw.detach().numpy().astype(np.float32)
     return dict(u=u, v=v, A=A, B=B, C=C, z=tz_raw, visible=vis, rect=rect,
                 ntiles=ntiles.astype(np.int64), z32=z32, margin_r=margin_r,
-                radius=np.stack([rx, ry], 1), tiles_xy=(TX, TY))
+                radius=np.stack([rx, ry], 1), extent=np.stack([sx, sy], 1), tiles_xy=(TX, TY))

@@ -29,7 +29,8 @@ lib = C.CDLL(LIB_PATH)
 OK, E_INVALID, E_WORKSPACE, E_CAPACITY, E_DEVICE, E_UNSUPPORTED = range(6)
 MAX_VIEWS = 64
 K_PROJECT, K_SORT, K_BLEND_FWD, K_BLEND_BWD, K_PROJECT_BWD, K_DECODE, K_DECODE_BWD = range(7)
-CTX_PAIR_TILE, CTX_PAIR_GAUSS, CTX_TILE_RANGE, CTX_RECT, CTX_NCONTRIB, CTX_TFINAL = range(1, 7)
+(CTX_PAIR_TILE, CTX_PAIR_GAUSS, CTX_TILE_RANGE, CTX_RECT, CTX_NCONTRIB, CTX_TFINAL, CTX_GEOM, CTX_RADIUS,
+ CTX_DEPTH_KEY, CTX_NTILES) = range(1, 11)
 
 
 class AsgsError(RuntimeError):

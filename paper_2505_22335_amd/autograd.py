@@ -27,6 +27,7 @@ import numpy as np
 import scipy.linalg
 import torch
 
+from .core import RenderContext
 from .pipeline import AnchorRenderer, DeviceAnchors
 
 
@@ -147,6 +148,7 @@ class _DecodeRender(torch.autograd.Function):
         tr = ctx.tr
         if tr.generation != ctx.gen:
             raise RuntimeError("TrackedRenderer: backward after a newer forward on the same renderer")
+        _raise_on_overflow(tr.r.rc)
 
         def g(x, key):
             return x.contiguous() if x is not None else torch.zeros(ctx.shapes[key], device=tr.r.a.xyz.device)
@@ -171,5 +173,101 @@ def decode_render(xi: torch.Tensor, xyz: torch.Tensor, feat: torch.Tensor, off: 
     rgb, depth, alpha, fimg = _DecodeRender.apply(xi, xyz, feat, off, params, tr, check)
     out = {"rgb": rgb, "depth": depth, "alpha": alpha}
     if tr.r.a.n_feat:
+        out["feat"] = fimg
+    return out
+
+
+def _raise_on_overflow(rc: RenderContext):
+    """An overflowed forward renders incomplete images and its backward gives
+    zero gradients: refuse to return them (one synchronising header read)."""
+    ni, _, ov = rc.status()
+    if ov:
+        raise RuntimeError(f"render context overflow: {ni} intersections exceed the capacity {rc.capacity}; "
+                           "render with check=True or enlarge the context")
+
+
+class GaussianRenderer:
+    """Render context for plain (explicit) Gaussians seen by a fixed set of
+    cameras of one resolution, whose poses are base poses times a twist as in
+    TrackedRenderer."""
+
+    def __init__(self, cams: Sequence, n_gauss: int, n_feat: int = 0, **opt_kw):
+        self.base = [T_cw_of(c) for c in cams]
+        self.intr = list(cams)
+        self.rc = RenderContext(self.intr, n_gauss, n_feat=n_feat, **opt_kw)
+        self.n, self.nf = int(n_gauss), int(n_feat)
+        self.generation = 0
+
+    @property
+    def V(self) -> int:
+        return len(self.base)
+
+    def place(self, xi: Optional[np.ndarray]):
+        if xi is None:
+            cams = self.intr
+        else:
+            cams = [camera_at(c, se3_exp(xi[v]) @ self.base[v]) for v, c in enumerate(self.intr)]
+        self.rc.set_cameras(cams)
+
+
+class _RenderGaussians(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xi, mean, scale, rot, opacity, rgb, feat, gr: GaussianRenderer, check: bool):
+        V = gr.V
+        xi_h = None if xi is None else xi.detach().to("cpu", torch.float64).numpy().reshape(V, 6)
+        gr.place(xi_h)
+        g = {"mean": mean.detach().contiguous(), "scale": scale.detach().contiguous(),
+             "rot": rot.detach().contiguous(), "opacity": opacity.detach().contiguous(),
+             "rgb": rgb.detach().contiguous()}
+        if gr.nf:
+            g["feat"] = feat.detach().contiguous()
+        if check:
+            gr.rc.fit(g)
+        img = gr.rc.forward(g)
+        gr.generation += 1
+        ctx.gr, ctx.gen, ctx.g = gr, gr.generation, g
+        ctx.pose = xi is not None
+        if ctx.pose:
+            ctx.J = torch.as_tensor(np.stack([se3_left_jacobian(x) for x in xi_h]), dtype=torch.float32,
+                                    device=mean.device)
+        ctx.shapes = {k: v.shape for k, v in img.items()}
+        return img["rgb"], img["depth"], img["alpha"], img["feat"] if gr.nf else img["depth"].new_zeros(0)
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_depth, d_alpha, d_feat):
+        gr = ctx.gr
+        if gr.generation != ctx.gen:
+            raise RuntimeError("GaussianRenderer: backward after a newer forward on the same renderer")
+        _raise_on_overflow(gr.rc)
+
+        def g(x, key):
+            return x.contiguous() if x is not None else torch.zeros(ctx.shapes[key], device=ctx.g["mean"].device)
+        dimg = {"rgb": g(d_rgb, "rgb"), "depth": g(d_depth, "depth"), "alpha": g(d_alpha, "alpha")}
+        if gr.nf:
+            dimg["feat"] = g(d_feat, "feat")
+        dg, d_pose = gr.rc.backward(ctx.g, dimg, pose=ctx.pose)
+        d_xi = None
+        if ctx.pose:
+            d_xi = torch.bmm(ctx.J.transpose(1, 2).contiguous(), d_pose[:, :, None])[:, :, 0]
+        # the views share one set of Gaussians: their gradients add up
+        red = {k: v.sum(0) for k, v in dg.items()}
+        return (d_xi, red["mean"], red["scale"], red["rot"], red["opacity"], red["rgb"],
+                red.get("feat"), None, None)
+
+
+def render_gaussians(mean: torch.Tensor, log_scale: torch.Tensor, rot: torch.Tensor, logit_opacity: torch.Tensor,
+                     rgb: torch.Tensor, gr: GaussianRenderer, feat: Optional[torch.Tensor] = None,
+                     xi: Optional[torch.Tensor] = None, check: bool = True) -> Dict[str, torch.Tensor]:
+    """Differentiable render of plain Gaussians (Sec. 3.1, Eq. 2, Eq. 3) with
+    the usual 3DGS parametrisation: scale = exp(log_scale), opacity =
+    sigmoid(logit_opacity), quaternion rot (any norm). Planes [c][n] float32
+    on the device. With xi ((V, 6) twists), the views are rendered at
+    Exp(xi_v) T_cw,v and xi receives its gradient. Returns rgb (V,3,H,W),
+    depth, alpha (V,H,W) and, with features, feat (V,16,H,W)."""
+    scale = torch.exp(log_scale)
+    opacity = torch.sigmoid(logit_opacity)
+    rgb_, depth, alpha, fimg = _RenderGaussians.apply(xi, mean, scale, rot, opacity, rgb, feat, gr, check)
+    out = {"rgb": rgb_, "depth": depth, "alpha": alpha}
+    if gr.nf:
         out["feat"] = fimg
     return out

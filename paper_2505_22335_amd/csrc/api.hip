@@ -252,6 +252,7 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.views = take(sizeof(ViewDev) * ASGS_MAX_VIEWS);
   L.geom = take((size_t)nv * kGeomStride * sizeof(float));
   L.chan = take((size_t)nv * L.cs * sizeof(float));
+  L.rad = take((size_t)nv * 8);
   L.rect = take((size_t)nv * 8);
   L.ntiles = take((size_t)nv * 4);
   L.dkey = take((size_t)nv * 4);
@@ -494,6 +495,10 @@ int asgs_ctx_array(const asgs_camera* cams, int32_t n_views, int64_t n_gauss, co
     case ASGS_CTX_RECT: *ptr = c + L.rect; *count = L.nv; break;
     case ASGS_CTX_NCONTRIB: *ptr = c + L.ncontrib; *count = L.total_pix; break;
     case ASGS_CTX_TFINAL: *ptr = c + L.tfinal; *count = L.total_pix; break;
+    case ASGS_CTX_GEOM: *ptr = c + L.geom; *count = L.nv; break;
+    case ASGS_CTX_RADIUS: *ptr = c + L.rad; *count = L.nv; break;
+    case ASGS_CTX_DEPTH_KEY: *ptr = c + L.dkey; *count = L.nv; break;
+    case ASGS_CTX_NTILES: *ptr = c + L.ntiles; *count = L.nv; break;
     default: return fail(ASGS_E_INVALID, "unknown context array %d", which);
   }
   return ASGS_OK;

@@ -59,6 +59,8 @@ struct CtxHeader {
 };
 
 // Byte layout of a render context; every array 256-byte aligned.
+//  rad                 per (view, Gaussian): footprint radii (r_x, r_y), -1 when culled before
+//                      the footprint
 //  ntiles, dkey, toff  per (view, Gaussian): tile count, depth bits, first gradient slot
 //  bsum, vsum          per scan block: tile-count sum, visible count
 //  vlist, vcount       per view: its visible Gaussians in index order (region of n), their number
@@ -74,7 +76,7 @@ struct CtxHeader {
 //                      transmittance and channels at each segment boundary, and the
 //                      final channels
 struct CtxLayout {
-  size_t hdr, views, geom, chan, rect, ntiles, dkey, toff, bsum, vsum, vlist, vcount, tcur, ukey, tkey, pairgid, pslot,
+  size_t hdr, views, geom, chan, rad, rect, ntiles, dkey, toff, bsum, vsum, vlist, vcount, tcur, ukey, tkey, pairgid, pslot,
       ptile, pmask, ranges, binfo, lpart, bslot, sinfo, split, tfinal, ncontrib, gslot, posepart;
   size_t total;
   int64_t nv, cap;

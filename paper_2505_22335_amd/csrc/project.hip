@@ -89,9 +89,18 @@ ASGS_DEV float dot3(const float a[3], const float b[3]) { return a[0] * b[0] + a
 ASGS_DEV bool proj_core(const ViewDev& V, const float m[3], const float s[3], const float q[4],
                         float dilation, float znear, Proj& P) {
   const float* W = V.R;
-  P.t[0] = W[0] * m[0] + W[1] * m[1] + W[2] * m[2] + V.t[0];
-  P.t[1] = W[3] * m[0] + W[4] * m[1] + W[5] * m[2] + V.t[1];
-  P.t[2] = W[6] * m[0] + W[7] * m[1] + W[8] * m[2] + V.t[2];
+  // t = R_cw mu + t_cw = R_cw (mu - c), evaluated in FP64 from the float32
+  // rotation and camera centre (exact copies of the pose) and rounded once:
+  // the camera-space mean, and with it the depth key that orders the tile
+  // lists, is the correctly rounded float32 of its exact value
+  {
+    const double d0 = (double)m[0] - (double)V.cc[0];
+    const double d1 = (double)m[1] - (double)V.cc[1];
+    const double d2 = (double)m[2] - (double)V.cc[2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      P.t[r] = (float)fma((double)W[r * 3 + 0], d0, fma((double)W[r * 3 + 1], d1, (double)W[r * 3 + 2] * d2));
+  }
   if (!(P.t[2] > znear)) return false;
   const float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
   P.qinv = 1.0f / sqrtf(qq);
@@ -150,6 +159,8 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
   bool vis = proj_core(V, m, s, q, rc.dilation, rc.znear, P);
   vis = valid && vis && (P.det > 0.f) && (o > rc.alpha_min);
   float u = 0.f, v = 0.f, A = 0.f, B = 0.f, C = 0.f;
+  float rx = -1.f, ry = -1.f;
+  bool staged = false;  // the footprint was computed (u, v, radii finite and in range)
   int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
   if (vis) {
     const float tz = P.t[2];
@@ -160,10 +171,11 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
     C = P.a / P.det;
     // tight box of the ellipse alpha = alpha_min: half-widths sqrt(kappa^2 Sigma'_xx), ...
     const float kap2 = 2.f * logf(o / rc.alpha_min);
-    const float rx = ceilf(sqrtf(kap2 * P.a));
-    const float ry = ceilf(sqrtf(kap2 * P.c));
+    rx = ceilf(sqrtf(kap2 * P.a));
+    ry = ceilf(sqrtf(kap2 * P.c));
     const float lim = 8388608.f;  // 2^23: beyond this the box arithmetic is not exact
-    vis = isfinite(u) && isfinite(v) && fabsf(u) < lim && fabsf(v) < lim && rx < lim && ry < lim;
+    staged = isfinite(u) && isfinite(v) && fabsf(u) < lim && fabsf(v) < lim && rx < lim && ry < lim;
+    vis = staged;
     if (vis) {
       const float iu = floorf(u), iv = floorf(v);
       tx0 = (int)fmaxf(0.f, floorf((iu - rx) * (1.f / kTile)));
@@ -178,6 +190,15 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
   short4* rect = ctx_ptr<short4>(ctx, L.rect);
   uint32_t* ntiles = ctx_ptr<uint32_t>(ctx, L.ntiles);
   uint32_t* dkey = ctx_ptr<uint32_t>(ctx, L.dkey);
+  // footprint radii of every Gaussian that reached the tile rectangle (-1
+  // otherwise), with its geometry record: what the tile lists follow from
+  if (valid) ctx_ptr<float2>(ctx, L.rad)[gid] = staged ? make_float2(rx, ry) : make_float2(-1.f, -1.f);
+  if (staged) {
+    geom[2 * gid] = make_float4(u, v, A, B);
+    // slot 6: the power at which o exp(power) reaches alpha_min, so that the
+    // blend kernels test alpha >= alpha_min without an exponential
+    geom[2 * gid + 1] = make_float4(C, o, logf(rc.alpha_min / o), 0.f);
+  }
   if (!vis) {
     if (valid) {
       rect[gid] = make_short4(1, 0, 1, 0);
@@ -185,10 +206,6 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
       dkey[gid] = 0xFFFFFFFFu;
     }
   } else {
-  geom[2 * gid] = make_float4(u, v, A, B);
-  // slot 6: the power at which o exp(power) reaches alpha_min, so that the
-  // blend kernels test alpha >= alpha_min without an exponential
-  geom[2 * gid + 1] = make_float4(C, o, logf(rc.alpha_min / o), 0.f);
   const float* rgb = g.rgb + view * g.view_stride[4];
   // the channel record (80 or 16 bytes, 16-byte aligned) as float4 stores
   float4* ch = reinterpret_cast<float4*>(chan + gid * CS);

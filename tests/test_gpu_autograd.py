@@ -9,13 +9,14 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import GRAD_TOL, guard_mask, log, oracle_opts, rel_err, to_np, upstream
+from tests.gpu_util import GRAD_TOL, IMG_TOL, guard_mask, guard_report, log, oracle_opts, rel_err, to_np, upstream
 
 pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     import paper_2505_22335_amd as P
-    from paper_2505_22335_amd.autograd import TrackedRenderer, decode_render, se3_exp
+    from paper_2505_22335_amd.autograd import (GaussianRenderer, TrackedRenderer, decode_render, render_gaussians,
+                                               se3_exp)
     from paper_2505_22335_amd.pipeline import anchors_to_device
 
 
@@ -165,3 +166,65 @@ def test_tracking_loop_config4():
     # a quarter and rotation within a tenth of the initial error
     assert hist[-1][1] < hist[0][1] / 20
     assert t_err < 0.25 * err0[0] and r_err < 0.1 * err0[1], (t_err, r_err, err0)
+
+
+def test_c1_l1_loss_through_autograd():
+    """Config 1 as stated: 10k plain Gaussians at 160x120, identity pose,
+    L = mean |C - C*| + mean |D - D*| against the seeded U[0,1] targets, with
+    gradients to the mean, log-scale, quaternion, logit-opacity, colour and
+    the pose twist through render_gaussians, against the oracle's derivative
+    of the same loss at the same leaves (scale = exp(log s), opacity =
+    sigmoid(logit o) in float64). Pixels in the guard band, and channels
+    whose rendered value is within 1e-5 of the target (where the sign of the
+    residual is not decided), carry weight 0 on both sides."""
+    sc, cam, tgt = synth.c1()
+    log("case c1 autograd l1")
+    f64 = np.float64
+    logs = np.log(sc.scale.astype(f64)).astype(np.float32)
+    o32 = sc.opacity.astype(f64)
+    logit = np.log(o32 / (1.0 - o32)).astype(np.float32)
+    scale64 = np.exp(logs.astype(f64))
+    op64 = 1.0 / (1.0 + np.exp(-logit.astype(f64)))
+    sc64 = synth.PlainScene(mean=sc.mean, scale=scale64, rot=sc.rot, opacity=op64, rgb=sc.rgb)
+    opts = oracle_opts(0)
+    ref = oracle.render_scene(sc64, cam, opts, with_margins=True)
+    keep, grep = guard_report(ref["margins"], tie_ulps=0)
+    log("guard band c1 autograd", grep)
+    assert grep["frac"] <= 0.01
+    H, W = cam.height, cam.width
+    t_rgb, t_d = tgt[:3].astype(f64), tgt[3].astype(f64)
+    w_rgb = (keep[None] & (np.abs(ref["rgb"] - t_rgb) > 1e-5)).astype(f64)
+    w_d = (keep & (np.abs(ref["depth"] - t_d) > 1e-5)).astype(f64)
+    loss_ref = (w_rgb * np.abs(ref["rgb"] - t_rgb)).sum() / (3 * H * W) + (w_d * np.abs(ref["depth"] - t_d)).sum() / (H * W)
+    G = dict(rgb=w_rgb * np.sign(ref["rgb"] - t_rgb) / (3 * H * W), depth=w_d * np.sign(ref["depth"] - t_d) / (H * W),
+             alpha=np.zeros((H, W)))
+    _, gr = oracle.render_scene(sc64, cam, opts, grad_out=G, pose_grad=True)
+    expect = dict(mean=gr["gauss"]["mean"], log_scale=gr["gauss"]["scale"] * scale64,
+                  rot=gr["gauss"]["rot"], logit_opacity=gr["gauss"]["opacity"] * op64 * (1.0 - op64),
+                  rgb=gr["gauss"]["rgb"])
+
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    leaves = dict(mean=dev(sc.mean), log_scale=dev(logs), rot=dev(sc.rot), logit_opacity=dev(logit), rgb=dev(sc.rgb))
+    for t in leaves.values():
+        t.requires_grad_(True)
+    xi = torch.zeros((1, 6), dtype=torch.float32, device="cuda", requires_grad=True)
+    gren = GaussianRenderer([cam], sc.n, n_feat=0)
+    img = render_gaussians(leaves["mean"], leaves["log_scale"], leaves["rot"], leaves["logit_opacity"],
+                           leaves["rgb"], gren, xi=xi)
+    for k in ("rgb", "depth", "alpha"):
+        e = rel_err(to_np(img[k][0]), ref[k], keep)
+        log("c1 autograd image", k, "%.2e" % e)
+        assert e <= IMG_TOL, k
+    loss = (dev(w_rgb) * (img["rgb"][0] - dev(t_rgb)).abs()).sum() / (3 * H * W) + \
+        (dev(w_d) * (img["depth"][0] - dev(t_d)).abs()).sum() / (H * W)
+    loss.backward()
+    torch.cuda.synchronize()
+    log("c1 autograd loss gpu %.8f oracle %.8f" % (float(loss.detach()), loss_ref))
+    assert abs(float(loss.detach()) - loss_ref) <= 1e-5 * loss_ref
+    for k, t in leaves.items():
+        e = rel_err(to_np(t.grad), expect[k])
+        log("c1 autograd grad", k, "%.2e" % e)
+        assert e <= GRAD_TOL, k
+    e = rel_err(to_np(xi.grad[0]), gr["pose"])
+    log("c1 autograd pose grad %.2e" % e, to_np(xi.grad[0]), gr["pose"])
+    assert e <= GRAD_TOL

@@ -7,7 +7,8 @@ import torch
 import oracle
 import synth
 from oracle.geometry import camera_center, pose_cw
-from tests.gpu_util import GRAD_TOL, IMG_TOL, guard_mask, log, oracle_opts, rel_err, to_np, upstream
+from tests.gpu_util import (GRAD_TOL, IMG_TOL, check_binning_self_consistent, check_lists_vs_oracle, guard_report,
+                            log, oracle_opts, rel_err, to_np, upstream)
 
 pytestmark = pytest.mark.gpu
 
@@ -91,10 +92,11 @@ def test_decode_forward_backward(k, nf, nv, A):
     assert e <= DEC_TOL
 
 
-def _e2e(sc, cam, nf, G_seed=7):
-    ref = oracle.render_scene(sc, cam, oracle_opts(nf), with_margins=True)
-    keep = guard_mask(ref["margins"])
-    log("guard-band pixels excluded:", int((~keep).sum()), "of", keep.size)
+def _e2e(sc, cam, nf, G_seed=7, label="", max_guard=0.01):
+    ref = oracle.render_scene(sc, cam, oracle_opts(nf), with_margins=True, keep_lists=True)
+    keep, grep = guard_report(ref["margins"])
+    log("guard band", label, grep)
+    assert grep["frac"] <= max_guard, grep
     G = upstream(G_seed, cam.height, cam.width, nf)
     for key in G:
         G[key] = G[key] * keep
@@ -105,6 +107,8 @@ def _e2e(sc, cam, nf, G_seed=7):
     dimg = {key: torch.as_tensor(G[key][None]).cuda() for key in G}
     grads = r.backward(dimg)
     torch.cuda.synchronize()
+    st, _ = check_binning_self_consistent(r.rc, label)
+    check_lists_vs_oracle(r.rc, ref, st, label=label)
     return ref, keep, G, img, grads, r
 
 
@@ -112,7 +116,7 @@ def test_end_to_end_room_small():
     """Config-2 room and camera, 2000 anchors (k=10), 640x480, 16-d features."""
     sc, cam, _ = synth.c2("shell", 2000, seed=12)
     log("case e2e small")
-    ref, keep, G, img, grads, r = _e2e(sc, cam, 16)
+    ref, keep, G, img, grads, r = _e2e(sc, cam, 16, label="e2e small")
     for key in ("rgb", "depth", "alpha", "feat"):
         e = rel_err(to_np(img[key][0]), ref[key], keep)
         log("e2e", key, "%.2e" % e)
@@ -137,11 +141,16 @@ def test_end_to_end_room_small():
 
 
 @pytest.mark.slow
-def test_end_to_end_config2_full():
-    """Config 2 at full size: 20k anchors x 10 = 200k Gaussians, 640x480."""
-    sc, cam, _ = synth.c2()
-    log("case e2e c2 full")
-    ref, keep, G, img, grads, r = _e2e(sc, cam, 16)
+@pytest.mark.parametrize("mode", ["shell", "volume"])
+def test_end_to_end_config2_full(mode):
+    """Config 2 at full size: 20k anchors x 10 = 200k Gaussians, 640x480, on
+    the surface-shell room (the headline workload) and on the volume room
+    (anchors anywhere in the room: about 2.6x the intersections and longer
+    lists)."""
+    sc, cam, _ = synth.c2(mode)
+    log("case e2e c2 full", mode)
+    ref, keep, G, img, grads, r = _e2e(sc, cam, 16, label="c2 " + mode,
+                                       max_guard=0.01 if mode == "shell" else 0.02)
     ni, nvis, ov = r.rc.status()
     log("c2 intersections", ni, "visible", nvis)
     for key in ("rgb", "depth", "alpha", "feat"):
@@ -162,6 +171,13 @@ def test_end_to_end_config2_full():
     e = rel_err(to_np(grads["d_pose"][0]), gr["pose"])
     log("c2 pose %.2e" % e)
     assert e <= GRAD_TOL
+
+
+# BF16 decoder bounds, about 2.5x the largest measured values: against the
+# bfloat16 emulation (FP32 accumulation order; an operand that lands on a
+# bfloat16 rounding tie can round the other way) and against FP64 per field
+BF16_VS_EMULATION = 1e-4
+BF16_VS_FP64 = dict(opacity=2e-3, rgb=1.5e-3, scale=2e-3, rot=8e-3, feat=1e-2, mean=1e-6)
 
 
 @pytest.mark.parametrize("k,nf,nv,A", [(10, 16, 2, 300), (3, 16, 1, 300), (7, 0, 2, 300), (16, 16, 1, 300),
@@ -194,8 +210,14 @@ def test_decode_bf16_matches_bf16_emulation(k, nf, nv, A):
             e16 = rel_err(x, g16[f].numpy().T)
             e64 = rel_err(x, g64[f].numpy().T)
             log("bf16 decode", v, f, "vs bf16 emulation %.2e" % e16, "vs fp64 %.2e" % e64)
-            assert e16 <= 2e-3, (f, e16)
-            assert e64 <= 3e-2, (f, e64)
+            assert e16 <= BF16_VS_EMULATION, (f, e16)
+            assert e64 <= BF16_VS_FP64[f], (f, e64)
+
+
+# BF16 decoder's stated C3 error bound per map, max |x - ref| / max |ref| over
+# the guard-kept pixels (about 3x the measured value) and over all pixels
+C3_BF16_MASKED = dict(rgb=2.5e-3, depth=7e-4, feat=1.5e-2, alpha=1.5e-3)
+C3_BF16_ALL = dict(rgb=2.5e-3, depth=7e-4, feat=1.8e-2, alpha=1.5e-3)
 
 
 @pytest.mark.slow
@@ -203,25 +225,37 @@ def test_decode_bf16_matches_bf16_emulation(k, nf, nv, A):
 def test_config3_error_report(precision):
     """Config 3: 100k anchors x 10 = 1M Gaussians at 640x480. Rendered maps
     with the BF16 (1) or FP32 (0) decoder against the FP64 oracle; max and mean
-    errors are logged (the BF16 path's stated error), FP32 must meet 1e-4."""
+    errors over the guard-kept pixels and over all pixels are logged (the BF16
+    path's stated error) and bounded; FP32 must meet 1e-4 on the kept pixels.
+    The binning is checked against its integer re-derivation for both
+    decoders and, with the FP32 decoder, against the oracle's lists."""
     sc, cam, _ = synth.c3()
     log("case config3 precision", precision)
-    ref = oracle.render_scene(sc, cam, oracle_opts(16), with_margins=True)
-    keep = guard_mask(ref["margins"])
+    ref = oracle.render_scene(sc, cam, oracle_opts(16), with_margins=True, keep_lists=precision == 0)
+    keep, grep = guard_report(ref["margins"])
+    log("guard band config3", grep)
+    # the depth-tie band drives it: 1M Gaussians on the same walls put many
+    # list neighbours within 4 float32 ulps of each other
+    assert grep["frac"] <= 0.04, grep
     r = AnchorRenderer(anchors_to_device(sc), [cam], precision=precision)
     r.fit()
     img = r.forward()
     torch.cuda.synchronize()
     ni, nvis, ov = r.rc.status()
-    log("config3 intersections", ni, "visible", nvis, "guard-excluded", int((~keep).sum()))
+    log("config3 intersections", ni, "visible", nvis)
+    st, _ = check_binning_self_consistent(r.rc, "config3 p%d" % precision)
+    if precision == 0:
+        check_lists_vs_oracle(r.rc, ref, st, max_tie_frac=6e-3, label="config3")
     for key in ("rgb", "depth", "feat", "alpha"):
         x = to_np(img[key][0]).astype(np.float64)
         refk = ref[key]
-        d = np.abs(x - refk)[..., keep]
         scale = np.abs(refk).max()
-        log("config3 %s precision=%d max_abs %.3e mean_abs %.3e max_rel %.3e mean_rel %.3e" %
-            (key, precision, d.max(), d.mean(), d.max() / scale, d.mean() / scale))
+        dk = np.abs(x - refk)[..., keep]
+        da = np.abs(x - refk)
+        log("config3 %s precision=%d kept: max_rel %.3e mean_rel %.3e | all: max_rel %.3e mean_rel %.3e" %
+            (key, precision, dk.max() / scale, dk.mean() / scale, da.max() / scale, da.mean() / scale))
         if precision == 0:
-            assert d.max() / scale <= IMG_TOL, key
+            assert dk.max() / scale <= IMG_TOL, key
         else:
-            assert d.max() / scale <= 5e-2, key
+            assert dk.max() / scale <= C3_BF16_MASKED[key], key
+            assert da.max() / scale <= C3_BF16_ALL[key], key

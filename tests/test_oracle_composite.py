@@ -158,3 +158,72 @@ def test_golden_two_gaussians():
     np.testing.assert_allclose(acc[0, :3].numpy(), gd["expected"]["rgb"], rtol=1e-9)
     np.testing.assert_allclose(acc[0, 3].item(), gd["expected"]["depth"], rtol=1e-9)
     np.testing.assert_allclose(asum[0].item(), gd["expected"]["alpha"], rtol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Guard-band margins of composite_tile: hand cases where every decision sits
+# at a known relative distance from its threshold. Gaussians are centred on
+# the pixel (power = 0), so alpha = min(alpha_max, o) exactly.
+# ---------------------------------------------------------------------------
+def _centred(ops, zs=None, impact_T=1e-3):
+    K = len(ops)
+    one = torch.ones(K, dtype=torch.float64)
+    u = torch.full((K,), 3.0, dtype=torch.float64)
+    v = torch.full((K,), 5.0, dtype=torch.float64)
+    o = torch.as_tensor(np.asarray(ops, np.float64))
+    z = np.asarray(zs if zs is not None else np.arange(1, K + 1), np.float32)
+    chans = torch.stack([one, torch.as_tensor(z.astype(np.float64))], 1)
+    px = torch.tensor([3.0], dtype=torch.float64)
+    py = torch.tensor([5.0], dtype=torch.float64)
+    res = composite_tile(u, v, 0.5 * one, 0.0 * one, 0.5 * one, o, chans, px, py, RenderOpts(n_feat=0),
+                         with_margins=True, impact_T=impact_T, z32=z)
+    return res[3][0], {k: float(m[0]) for k, m in res[4].items()}
+
+
+def test_margin_alpha_min():
+    am = 1.0 / 255.0
+    n, m = _centred([am * 1.01])
+    assert n == 1
+    assert abs(m["alpha"] - 0.01) < 1e-12
+    assert abs(m["clamp"] - abs(am * 1.01 - 0.99) / 0.99) < 1e-12
+    # skipped just below the threshold, at the same distance
+    n, m = _centred([am * 0.99])
+    assert n == 0
+    assert abs(m["alpha"] - 0.01) < 1e-12
+    assert m["term"] == np.inf  # a skipped Gaussian takes no termination decision
+
+
+def test_margin_alpha_max():
+    n, m = _centred([0.9999])
+    assert n == 1
+    assert abs(m["clamp"] - 0.0099 / 0.99) < 1e-12
+
+
+def test_margin_termination_counted_below_impact_T():
+    """T after the fourth Gaussian is 1.03e-4 (kept, 3 % above T_min); with
+    impact_T = 0.5 only the first Gaussian's alpha decision counts, but the
+    termination decisions of all of them do."""
+    n, m = _centred([0.9, 0.9, 0.9, 0.897], impact_T=0.5)
+    assert n == 4
+    T4 = (1 - 0.9) ** 3 * (1 - 0.897)
+    assert abs(m["term"] - abs(T4 - 1e-4) / 1e-4) < 1e-9
+    assert abs(m["term"] - 0.03) < 1e-9
+    assert abs(m["alpha"] - abs(0.9 - 1 / 255) * 255) < 1e-9
+
+
+def test_margin_of_the_stopping_gaussian():
+    """The fourth Gaussian would take T to 5e-5 < T_min: compositing stops
+    before it (three contributors) and its decision sits at 0.5."""
+    n, m = _centred([0.9, 0.9, 0.9, 0.95])
+    assert n == 3
+    assert abs(m["term"] - 0.5) < 1e-9
+
+
+def test_margin_depth_tie_in_ulps():
+    z1 = np.float32(1.0)
+    z2 = np.float32(z1 + 3 * np.spacing(z1))
+    n, m = _centred([0.5, 0.5], zs=[z1, z2])
+    assert n == 2 and m["tie"] == 3.0
+    # a neighbour that is skipped at the pixel takes no order decision
+    n, m = _centred([0.5, 0.001], zs=[z1, z2])
+    assert n == 1 and m["tie"] == np.inf

@@ -106,3 +106,41 @@ def test_bf16_mode_within_operand_rounding():
         d = (g16[key] - g64[key]).abs().max().item()
         assert 0 < d < 2e-2, (key, d)
     assert torch.equal(g16["mean"], g64["mean"])
+
+
+def test_bf16_mode_rounds_exactly_the_matrix_operands():
+    """Hand-built rotation head (raw output, k = 1) where rounding each operand
+    to bfloat16 moves the result by a distinct, known amount (u = 2^-7, the
+    bfloat16 spacing in [1, 2)):
+      hidden 0: anchor feature 1 + 0.75u (rounds to 1 + u), bias -0.375u
+      hidden 1: first-layer weight 1 + 0.75u (rounds to 1 + u), bias -0.375u
+      hidden 2: view-direction weight 1 + 0.375u (must stay exact), bias 0.25u
+      hidden 3: pre-activation 1 + 0.25u (the hidden value rounds to 1)
+      output 3: second-layer weight 1 + 0.75u (rounds to 1 + u)
+      output 0: second-layer bias 1 + 2^-10 (must stay exact).
+    Rounding a wrong operand, or missing one, changes at least one output."""
+    u = 2.0 ** -7
+    A, k = 1, 1
+    xyz = torch.tensor([[2.0, 0.0, 0.0]], dtype=F64)   # unit view direction (1, 0, 0)
+    c = torch.zeros(3, dtype=F64)
+    feat = torch.zeros((1, 32), dtype=F64)
+    feat[0, 0], feat[0, 1], feat[0, 3] = 1 + 0.75 * u, 1.0, 1.0
+    off = torch.zeros((1, 3), dtype=F64)
+    W = {}
+    for name, m in (("opacity", 1), ("rgb", 3), ("scale", 3), ("rot", 4)):
+        W[name] = dict(W1=torch.zeros((32, 35), dtype=F64), b1=torch.zeros(32, dtype=F64),
+                       W2=torch.zeros((k * m, 32), dtype=F64), b2=torch.zeros(k * m, dtype=F64))
+    w = W["rot"]
+    w["W1"][0, 0], w["b1"][0] = 1.0, -0.375 * u
+    w["W1"][1, 1], w["b1"][1] = 1 + 0.75 * u, -0.375 * u
+    w["W1"][2, 32], w["b1"][2] = 1 + 0.375 * u, 0.25 * u
+    w["W1"][3, 3], w["b1"][3] = 1.0, 0.25 * u
+    w["W2"][0, 0], w["W2"][1, 1], w["W2"][2, 2], w["W2"][3, 3] = 1.0, 1.0, 1.0, 1 + 0.75 * u
+    w["b2"][0] = 1 + 2.0 ** -10
+    g16 = decode(xyz, feat, off, W, c, k, 1.0, 0.02, precision="bf16")
+    g64 = decode(xyz, feat, off, W, c, k, 1.0, 0.02)
+    expect16 = [2 + u + 2.0 ** -10, 1 + u, 1 + u, 1 + u]
+    expect64 = [2 + 0.375 * u + 2.0 ** -10, 1 + 0.375 * u, 1 + 0.625 * u,
+                (1 + 0.25 * u) * (1 + 0.75 * u)]
+    assert g16["rot"][0].tolist() == expect16
+    assert torch.allclose(g64["rot"][0], torch.tensor(expect64, dtype=F64), rtol=0, atol=1e-15)
