@@ -284,6 +284,22 @@ int asgs_l1_loss(int32_t n_views, int32_t width, int32_t height, int32_t n_feat,
                  const asgs_l1_targets* targets, const asgs_images* grad, float* loss, void* work,
                  size_t work_bytes, void* stream);
 
+/* Allocation-free asgs_l1_loss, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same arguments, results and status codes without
+ * work/work_bytes. The loss partials live in a library-owned device array of
+ * ASGS_L1_NOALLOC_MAX_VIEWS * 512 floats (128 KiB) that each GPU the library
+ * runs on holds until the process ends; its address is looked up on the
+ * first call on a device (the device current at the call must be the
+ * stream's). Nothing in it needs clearing: every call writes all the
+ * partials it reads. Calls that overlap on one GPU share the array and race:
+ * serialise them (one stream, or events). n_views above
+ * ASGS_L1_NOALLOC_MAX_VIEWS is ASGS_E_UNSUPPORTED. Allocates nothing. */
+#define ASGS_L1_NOALLOC_MAX_VIEWS 64
+int asgs_l1_loss_noalloc(int32_t n_views, int32_t width, int32_t height, int32_t n_feat,
+                         const asgs_images* maps, const asgs_l1_targets* targets, const asgs_images* grad,
+                         float* loss, void* stream);
+
 /* Forward render fused with the weighted L1 residual: the same images as
  * asgs_render_forward, plus, in the forward's output stage, exactly the
  * gradient planes asgs_l1_loss(out, targets, grad) would write (same

@@ -103,6 +103,8 @@ _sigs = {
     "asgs_l1_loss_work_size": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
     "asgs_l1_loss": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Images), C.POINTER(L1Targets),
                                C.POINTER(Images), P, P, C.c_size_t, P]),
+    "asgs_l1_loss_noalloc": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Images),
+                                       C.POINTER(L1Targets), C.POINTER(Images), P, P]),
     "asgs_profile_enable": (C.c_int, [C.c_uint32]),
     "asgs_profile_read": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
@@ -295,6 +297,12 @@ def l1_loss(n_views: int, width: int, height: int, n_feat: int, maps: Images, ta
     check(lib.asgs_l1_loss(n_views, width, height, n_feat, C.byref(maps), C.byref(targets), C.byref(grad),
                            _ptr(loss), _ptr(work), 0 if work is None else work.numel(), _stream(stream)),
           "asgs_l1_loss")
+
+
+def l1_loss_noalloc(n_views: int, width: int, height: int, n_feat: int, maps: Images, targets: L1Targets,
+                    grad: Images, loss=None, stream=None):
+    check(lib.asgs_l1_loss_noalloc(n_views, width, height, n_feat, C.byref(maps), C.byref(targets), C.byref(grad),
+                                   _ptr(loss), _stream(stream)), "asgs_l1_loss_noalloc")
 
 
 def profile_enable(mask: int):

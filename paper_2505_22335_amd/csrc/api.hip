@@ -282,6 +282,41 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   return L;
 }
 
+int l1_setup(int32_t n_views, int32_t width, int32_t height, int32_t n_feat, const asgs_images* maps,
+             const asgs_l1_targets* targets, const asgs_images* grad, L1Args& a, L1Views& tv) {
+  if (n_views < 1 || n_views > ASGS_MAX_VIEWS) return fail(ASGS_E_INVALID, "n_views out of range");
+  if (width < 1 || height < 1 || width > 8192 || height > 8192) return fail(ASGS_E_INVALID, "bad resolution");
+  if (n_feat != 0 && n_feat != 16) return fail(ASGS_E_UNSUPPORTED, "n_feat must be 0 or 16");
+  if (!maps || !targets || !grad) return fail(ASGS_E_INVALID, "l1_loss: NULL argument");
+  const float* x[4] = {maps->rgb, maps->depth, maps->feat, maps->alpha};
+  const float* tg[4] = {targets->rgb, targets->depth, targets->feat, targets->alpha};
+  float* g[4] = {grad->rgb, grad->depth, grad->feat, grad->alpha};
+  for (int q = 0; q < 4; ++q) {
+    if (q == 2 && n_feat == 0) continue;
+    if ((tg[q] || g[q]) && !x[q]) return fail(ASGS_E_INVALID, "l1_loss: map %d missing", q);
+    for (const void* ptr : {(const void*)x[q], (const void*)tg[q], (const void*)g[q]})
+      if (ptr && !aligned16(ptr)) return fail(ASGS_E_INVALID, "l1_loss: pointer not 16-byte aligned");
+    if (!isfinite(targets->scale[q])) return fail(ASGS_E_INVALID, "l1_loss: scale not finite");
+  }
+  if (targets->weight && !aligned16(targets->weight))
+    return fail(ASGS_E_INVALID, "l1_loss: weight pointer not 16-byte aligned");
+  const int64_t HW = (int64_t)width * height;
+  a = L1Args{};
+  tv = L1Views{};
+  const int nc[4] = {3, 1, n_feat, 1};
+  for (int q = 0; q < 4; ++q) {
+    a.x[q] = (q == 2 && n_feat == 0) ? nullptr : x[q];
+    a.g[q] = (q == 2 && n_feat == 0) ? nullptr : g[q];
+    a.s[q] = targets->scale[q];
+    for (int v = 0; v < n_views; ++v) tv.t[q][v] = tg[q] ? tg[q] + (int64_t)v * nc[q] * HW : nullptr;
+  }
+  for (int v = 0; v < n_views; ++v) tv.w[v] = targets->weight;
+  a.HW = HW;
+  a.nf = n_feat;
+  a.n_views = n_views;
+  return ASGS_OK;
+}
+
 }  // namespace asgs
 
 using namespace asgs;
@@ -607,40 +642,14 @@ int asgs_l1_loss_work_size(int32_t n_views, size_t* bytes) {
 int asgs_l1_loss(int32_t n_views, int32_t width, int32_t height, int32_t n_feat, const asgs_images* maps,
                  const asgs_l1_targets* targets, const asgs_images* grad, float* loss, void* work,
                  size_t work_bytes, void* stream) {
-  if (n_views < 1 || n_views > ASGS_MAX_VIEWS) return fail(ASGS_E_INVALID, "n_views out of range");
-  if (width < 1 || height < 1 || width > 8192 || height > 8192) return fail(ASGS_E_INVALID, "bad resolution");
-  if (n_feat != 0 && n_feat != 16) return fail(ASGS_E_UNSUPPORTED, "n_feat must be 0 or 16");
-  if (!maps || !targets || !grad) return fail(ASGS_E_INVALID, "l1_loss: NULL argument");
-  const float* x[4] = {maps->rgb, maps->depth, maps->feat, maps->alpha};
-  const float* tg[4] = {targets->rgb, targets->depth, targets->feat, targets->alpha};
-  float* g[4] = {grad->rgb, grad->depth, grad->feat, grad->alpha};
-  for (int q = 0; q < 4; ++q) {
-    if (q == 2 && n_feat == 0) continue;
-    if ((tg[q] || g[q]) && !x[q]) return fail(ASGS_E_INVALID, "l1_loss: map %d missing", q);
-    for (const void* ptr : {(const void*)x[q], (const void*)tg[q], (const void*)g[q]})
-      if (ptr && !aligned16(ptr)) return fail(ASGS_E_INVALID, "l1_loss: pointer not 16-byte aligned");
-    if (!isfinite(targets->scale[q])) return fail(ASGS_E_INVALID, "l1_loss: scale not finite");
-  }
-  if (targets->weight && !aligned16(targets->weight))
-    return fail(ASGS_E_INVALID, "l1_loss: weight pointer not 16-byte aligned");
-  if (loss && (!work || work_bytes < (size_t)n_views * kL1Blocks * sizeof(float)))
-    return fail(ASGS_E_WORKSPACE, "l1_loss: loss needs %zu bytes of work", (size_t)n_views * kL1Blocks * sizeof(float));
-  const int64_t HW = (int64_t)width * height;
   L1Args a{};
   L1Views tv{};
-  const int nc[4] = {3, 1, n_feat, 1};
-  for (int q = 0; q < 4; ++q) {
-    a.x[q] = (q == 2 && n_feat == 0) ? nullptr : x[q];
-    a.g[q] = (q == 2 && n_feat == 0) ? nullptr : g[q];
-    a.s[q] = targets->scale[q];
-    for (int v = 0; v < n_views; ++v) tv.t[q][v] = tg[q] ? tg[q] + (int64_t)v * nc[q] * HW : nullptr;
-  }
-  for (int v = 0; v < n_views; ++v) tv.w[v] = targets->weight;
+  int st = l1_setup(n_views, width, height, n_feat, maps, targets, grad, a, tv);
+  if (st) return st;
+  if (loss && (!work || work_bytes < (size_t)n_views * kL1Blocks * sizeof(float)))
+    return fail(ASGS_E_WORKSPACE, "l1_loss: loss needs %zu bytes of work", (size_t)n_views * kL1Blocks * sizeof(float));
   a.partial = loss ? static_cast<float*>(work) : nullptr;
   a.loss = loss;
-  a.HW = HW;
-  a.nf = n_feat;
-  a.n_views = n_views;
   launch_l1_loss(a, tv, reinterpret_cast<hipStream_t>(stream));
   return check_launch("l1_loss launch");
 }

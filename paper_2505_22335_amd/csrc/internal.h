@@ -157,6 +157,10 @@ struct L1Args {
   float s[4];         // scale of each group's term
 };
 void launch_l1_loss(const L1Args& a, const L1Views& tv, hipStream_t s);
+// Validates the arguments of the L1 residual calls and fills a and tv (the
+// loss outputs, a.partial and a.loss, are left NULL). Launches nothing.
+int l1_setup(int32_t n_views, int32_t width, int32_t height, int32_t n_feat, const asgs_images* maps,
+             const asgs_l1_targets* targets, const asgs_images* grad, L1Args& a, L1Views& tv);
 
 struct DecodeConst {
   int64_t A;

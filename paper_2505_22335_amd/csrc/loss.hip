@@ -5,6 +5,8 @@
 //   L_v += s_g w_p |x - x*|,   dL/dx = s_g w_p sign(x - x*)   (sign(0) = 0).
 // A group without targets contributes nothing and gets zero gradient. The
 // per-view loss is a fixed-order sum of per-block partial sums.
+#include <mutex>
+
 #include "internal.h"
 
 namespace asgs {
@@ -137,3 +139,61 @@ void launch_l1_loss(const L1Args& a, const L1Views& tv, hipStream_t s) {
 }
 
 }  // namespace asgs
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of asgs_l1_loss. Its per-(view, block) loss partials
+// live in a file-scope device array instead of a caller workspace. Every block
+// of k_l1_loss writes its own partial on every call, so nothing has to be
+// cleared between calls; calls that overlap on one GPU share the array and
+// race.
+// ---------------------------------------------------------------------------
+static_assert(ASGS_L1_NOALLOC_MAX_VIEWS <= ASGS_MAX_VIEWS, "scratch sized per view");
+static __device__ __align__(256) float scratch[(size_t)ASGS_L1_NOALLOC_MAX_VIEWS * asgs::kL1Blocks];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};  // device address of scratch per device (host-side name is not one)
+
+// Device address of scratch on the current device, looked up once per device.
+int scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return asgs::fail(ASGS_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return asgs::fail(ASGS_E_UNSUPPORTED, "device ordinal %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return asgs::fail(ASGS_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return ASGS_OK;
+}
+
+}  // namespace
+
+extern "C" int asgs_l1_loss_noalloc(int32_t n_views, int32_t width, int32_t height, int32_t n_feat,
+                                    const asgs_images* maps, const asgs_l1_targets* targets,
+                                    const asgs_images* grad, float* loss, void* stream) {
+  if (n_views > ASGS_L1_NOALLOC_MAX_VIEWS)
+    return asgs::fail(ASGS_E_UNSUPPORTED, "l1_loss_noalloc: at most %d views (its scratch holds %d loss partials)",
+                      ASGS_L1_NOALLOC_MAX_VIEWS, ASGS_L1_NOALLOC_MAX_VIEWS * asgs::kL1Blocks);
+  asgs::L1Args a{};
+  asgs::L1Views tv{};
+  int st = asgs::l1_setup(n_views, width, height, n_feat, maps, targets, grad, a, tv);
+  if (st) return st;
+  if (loss) {
+    float* part = nullptr;
+    if ((st = scratch_address(&part))) return st;
+    a.partial = part;
+    a.loss = loss;
+  }
+  asgs::launch_l1_loss(a, tv, reinterpret_cast<hipStream_t>(stream));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return asgs::fail(ASGS_E_DEVICE, "l1_loss_noalloc launch: %s", hipGetErrorString(e));
+  return ASGS_OK;
+}
