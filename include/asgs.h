@@ -318,6 +318,49 @@ int asgs_render_forward_l1(const asgs_camera* cams, int32_t n_views, const asgs_
                            void* ctx, size_t ctx_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Multi-modal tracking residual and per-pixel uncertainty (UP-SLAM Sec. 3.2,
+ * Eq. 6; Sec. 3.4, Eq. 15)
+ *
+ * Per pixel of view v, from the rendered colour C~, depth D~ and opacity sum
+ * alpha (Eq. 3), the cosine of the DINO feature F and the rendered
+ * high-dimensional feature F^ (Eq. 11), and the observed colour C and depth D:
+ *   R     = vis (w_rgb sum_c |C~_c - C_c| + w_depth |D~ - box3(D)| + w_feat min(1, 1 - cos)),
+ *           vis = (1 - alpha < vis_T), box3 = mean of D over the pixel's in-image 3x3 neighbourhood;
+ *   sigma = max(sigma_min, sqrt(2 R)), the minimiser over sigma >= sigma_min of the
+ *           pixel's term 1/2 (R / sigma^2 + log sigma) of Eq. 15;
+ *   dynamic = 2 sigma^2 > dyn_thresh (evaluated as 2 max(sigma_min^2, 2R) > dyn_thresh):
+ *           the motion mask (1 = dynamic);
+ *   xi[v] = the mean over the view's pixels of that term at sigma (Eq. 15's value).
+ * ------------------------------------------------------------------------- */
+typedef struct asgs_residual_opts {
+  float w_rgb, w_depth, w_feat;  /* residual weights lambda_1^t..3^t: 0.25, 0.7, 0.1 (appendix) */
+  float vis_T;                   /* 0.1: pixels with remaining transmittance below this contribute */
+  float sigma_min;               /* 1e-3: lower bound of sigma (> 0) */
+  float dyn_thresh;              /* 1: motion mask threshold on 2 sigma^2 (Eq. 14's criterion) */
+  int32_t reserved;              /* must be 0 */
+} asgs_residual_opts;
+
+typedef struct asgs_residual_maps {
+  const float* rgb;        /* [V][3][H][W] rendered colour */
+  const float* depth;      /* [V][H][W] rendered depth */
+  const float* alpha;      /* [V][H][W] rendered opacity sum */
+  const float* cosine;     /* [V][H][W] cos(F, F^) (asgs_feature_lift) */
+  const float* obs_rgb;    /* [V][3][H][W] observed colour */
+  const float* obs_depth;  /* [V][H][W] observed depth */
+} asgs_residual_maps;
+
+void asgs_residual_opts_default(asgs_residual_opts* opts);
+/* Bytes of work asgs_tracking_residual needs to produce xi. */
+int asgs_residual_work_size(int32_t n_views, int32_t width, int32_t height, size_t* bytes);
+/* Writes the outputs that are not NULL: R, sigma ([V][H][W] float), dynamic
+ * ([V][H][W] uint8), xi ([V] float, needs work). Device pointers, no
+ * alignment requirement. At least one output must be given. Asynchronous
+ * on stream; xi is a fixed-order sum (deterministic). */
+int asgs_tracking_residual(int32_t n_views, int32_t width, int32_t height, const asgs_residual_opts* opts,
+                           const asgs_residual_maps* in, float* R, float* sigma, uint8_t* dynamic, float* xi,
+                           void* work, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Timing hook (for measurement tools; off by default)
  *
  * While a kernel class is enabled, each launch of it made by this library is
@@ -333,7 +376,8 @@ enum {
   ASGS_K_PROJECT_BWD = 4,  /* projection backward + pose reduction (one kernel) */
   ASGS_K_DECODE = 5,       /* decoder forward (one kernel) */
   ASGS_K_DECODE_BWD = 6,   /* decoder backward + parameter reduction (several kernels) */
-  ASGS_K_NUM = 7
+  ASGS_K_RESIDUAL = 7,     /* tracking residual and uncertainty (one kernel + the per-view mean) */
+  ASGS_K_NUM = 8
 };
 /* Enable the classes whose bit (1 << class) is set in mask; 0 disables all.
  * Clears earlier measurements. */

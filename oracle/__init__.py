@@ -16,6 +16,8 @@ in float64 with PyTorch CPU ops:
                   follows, Sec. 2 and Sec. 3.1);
 * ``composite``   front-to-back alpha compositing of colour, depth, the opacity
                   sum (Eq. 3) and the low-dimensional feature (Eq. 10);
+* ``uncertainty`` the multi-modal tracking residual (Sec. 3.2, Eq. 6) and
+                  the per-pixel uncertainty and motion mask (Sec. 3.4, Eq. 15);
 * ``render``      the whole path, with the backward pass as the vector-Jacobian
                   product of the forward definition (torch autograd in float64)
                   and the SE(3) pose gradient.
@@ -24,10 +26,11 @@ Readings of the paper where it is silent are listed in ``oracle.readings``.
 Parity pins (closed forms, invariants, brute force, finite differences) live
 in ``tests/test_oracle_*.py``.
 """
-from .readings import RenderOpts, READINGS  # noqa: F401
+from .readings import RenderOpts, READINGS, RESIDUAL_READINGS  # noqa: F401
 from .geometry import quat_to_rotmat, se3_exp, pose_cw, camera_center  # noqa: F401
 from .decode import decode, HEAD_ORDER  # noqa: F401
 from .project import project  # noqa: F401
 from .binning import bin_and_sort  # noqa: F401
 from .composite import composite_tile, composite_bruteforce  # noqa: F401
 from .render import render, render_scene, gaussians_from_plain, Leaves  # noqa: F401
+from .uncertainty import box3, cosine, residual, uncertainty, RESIDUAL_WEIGHTS  # noqa: F401

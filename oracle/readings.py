@@ -46,3 +46,21 @@ READINGS = (
     "A Gaussian is culled when o <= alpha_min (no pixel can reach alpha_min), when t_z <= znear, "
     "when det(Sigma') <= 0, or when its tile rectangle is empty.",
 )
+
+
+# Readings for the tracking residual and uncertainty (Sec. 3.2 Eq. 6, Sec. 3.4 Eq. 15).
+RESIDUAL_READINGS = (
+    "Eq.6 names its mask (T~ < 0.1) after the 'accumulated transmittance' but says it keeps low-opacity "
+    "regions out: a pixel contributes when its remaining transmittance 1 - alpha (alpha = the opacity "
+    "sum of Eq.3) is below 0.1.",
+    "|C~ - C| is the L1 norm over the three colour channels (their sum of absolute differences).",
+    "The 3x3 box filter of the observed depth averages the pixel and its neighbours inside the image "
+    "(no padding values); no pixel is treated as missing depth.",
+    "cos(F, F^) divides by the product of the two norms bounded below by 1e-12; the feature term is "
+    "min(1, 1 - cos).",
+    "Eq.15 is minimised pixel by pixel: sigma = max(sigma_min, sqrt(2R)), the exact minimiser of "
+    "1/2 (R/sigma^2 + log sigma) over sigma >= sigma_min (sigma_min = 1e-3 keeps R = 0 finite).",
+    "The tracking motion mask threshold is unstated: the mapping mask's criterion 2 sigma^2 > 1 (Eq.14) "
+    "is used, i.e. dynamic where 4R > 1 above the floor.",
+    "Residual weights (lambda_1^t, lambda_2^t, lambda_3^t) = (0.25, 0.7, 0.1) from the appendix.",
+)

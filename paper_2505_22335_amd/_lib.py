@@ -28,7 +28,8 @@ lib = C.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_WORKSPACE, E_CAPACITY, E_DEVICE, E_UNSUPPORTED = range(6)
 MAX_VIEWS = 64
-K_PROJECT, K_SORT, K_BLEND_FWD, K_BLEND_BWD, K_PROJECT_BWD, K_DECODE, K_DECODE_BWD = range(7)
+K_PROJECT, K_SORT, K_BLEND_FWD, K_BLEND_BWD, K_PROJECT_BWD, K_DECODE, K_DECODE_BWD, K_RESIDUAL = range(8)
+K_NUM = 8
 (CTX_PAIR_TILE, CTX_PAIR_GAUSS, CTX_TILE_RANGE, CTX_RECT, CTX_NCONTRIB, CTX_TFINAL, CTX_GEOM, CTX_RADIUS,
  CTX_DEPTH_KEY, CTX_NTILES) = range(1, 11)
 
@@ -73,6 +74,16 @@ class L1Targets(C.Structure):
                 ("weight", C.c_void_p), ("scale", C.c_float * 4)]
 
 
+class ResidualOpts(C.Structure):
+    _fields_ = [("w_rgb", C.c_float), ("w_depth", C.c_float), ("w_feat", C.c_float), ("vis_T", C.c_float),
+                ("sigma_min", C.c_float), ("dyn_thresh", C.c_float), ("reserved", C.c_int32)]
+
+
+class ResidualMaps(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p), ("cosine", C.c_void_p),
+                ("obs_rgb", C.c_void_p), ("obs_depth", C.c_void_p)]
+
+
 P = C.c_void_p
 _sigs = {
     "asgs_abi_version": (C.c_int, []),
@@ -105,6 +116,10 @@ _sigs = {
                                C.POINTER(Images), P, P, C.c_size_t, P]),
     "asgs_l1_loss_noalloc": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Images),
                                        C.POINTER(L1Targets), C.POINTER(Images), P, P]),
+    "asgs_residual_opts_default": (None, [C.POINTER(ResidualOpts)]),
+    "asgs_residual_work_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "asgs_tracking_residual": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(ResidualOpts),
+                                         C.POINTER(ResidualMaps), P, P, P, P, P, C.c_size_t, P]),
     "asgs_profile_enable": (C.c_int, [C.c_uint32]),
     "asgs_profile_read": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
@@ -303,6 +318,27 @@ def l1_loss_noalloc(n_views: int, width: int, height: int, n_feat: int, maps: Im
                     grad: Images, loss=None, stream=None):
     check(lib.asgs_l1_loss_noalloc(n_views, width, height, n_feat, C.byref(maps), C.byref(targets), C.byref(grad),
                                    _ptr(loss), _stream(stream)), "asgs_l1_loss_noalloc")
+
+
+def residual_opts(**kw) -> ResidualOpts:
+    o = ResidualOpts()
+    lib.asgs_residual_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def residual_work_size(n_views: int, width: int, height: int) -> int:
+    b = C.c_size_t()
+    check(lib.asgs_residual_work_size(n_views, width, height, C.byref(b)), "asgs_residual_work_size")
+    return b.value
+
+
+def tracking_residual(n_views: int, width: int, height: int, opts: ResidualOpts, maps: ResidualMaps, R=None,
+                      sigma=None, dynamic=None, xi=None, work=None, stream=None):
+    check(lib.asgs_tracking_residual(n_views, width, height, C.byref(opts), C.byref(maps), _ptr(R), _ptr(sigma),
+                                     _ptr(dynamic), _ptr(xi), _ptr(work), 0 if work is None else work.numel(),
+                                     _stream(stream)), "asgs_tracking_residual")
 
 
 def profile_enable(mask: int):

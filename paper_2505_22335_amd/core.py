@@ -228,3 +228,28 @@ def l1_loss_grad(maps: Dict[str, torch.Tensor], targets: Dict[str, torch.Tensor]
         work = torch.empty(L.l1_loss_work_size(V), dtype=torch.uint8, device=rgb.device)
     L.l1_loss(V, W, H, nf, L.make_images(maps), t, L.make_images(grad), loss, work)
     return loss
+
+
+def tracking_residual(rendered: Dict[str, torch.Tensor], cosine: torch.Tensor, obs_rgb: torch.Tensor,
+                      obs_depth: torch.Tensor, want_xi: bool = True, **opt_kw) -> Dict[str, torch.Tensor]:
+    """Multi-modal residual R (Eq. 6), per-pixel uncertainty sigma and motion
+    mask (Eq. 15) and the per-view objective xi, in one library kernel
+    (asgs_tracking_residual). rendered: rgb (V,3,H,W), depth, alpha (V,H,W);
+    cosine (V,H,W); observations obs_rgb (V,3,H,W), obs_depth (V,H,W)."""
+    rgb = rendered["rgb"]
+    V, H, W = rgb.shape[0], rgb.shape[-2], rgb.shape[-1]
+    dev = rgb.device
+    m = L.ResidualMaps()
+    c = lambda t: t.contiguous()
+    keep = [c(rgb), c(rendered["depth"]), c(rendered["alpha"]), c(cosine), c(obs_rgb), c(obs_depth)]
+    m.rgb, m.depth, m.alpha, m.cosine, m.obs_rgb, m.obs_depth = (t.data_ptr() for t in keep)
+    out = dict(R=torch.empty((V, H, W), dtype=torch.float32, device=dev),
+               sigma=torch.empty((V, H, W), dtype=torch.float32, device=dev),
+               dynamic=torch.empty((V, H, W), dtype=torch.uint8, device=dev))
+    work = None
+    if want_xi:
+        out["xi"] = torch.empty(V, dtype=torch.float32, device=dev)
+        work = torch.empty(L.residual_work_size(V, W, H), dtype=torch.uint8, device=dev)
+    L.tracking_residual(V, W, H, L.residual_opts(**opt_kw), m, out["R"], out["sigma"], out["dynamic"],
+                        out.get("xi"), work)
+    return out

@@ -654,6 +654,69 @@ int asgs_l1_loss(int32_t n_views, int32_t width, int32_t height, int32_t n_feat,
   return check_launch("l1_loss launch");
 }
 
+void asgs_residual_opts_default(asgs_residual_opts* o) {
+  if (!o) return;
+  o->w_rgb = 0.25f;
+  o->w_depth = 0.7f;
+  o->w_feat = 0.1f;
+  o->vis_T = 0.1f;
+  o->sigma_min = 1e-3f;
+  o->dyn_thresh = 1.f;
+  o->reserved = 0;
+}
+
+int asgs_residual_work_size(int32_t n_views, int32_t width, int32_t height, size_t* bytes) {
+  if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
+  if (n_views < 1 || n_views > ASGS_MAX_VIEWS) return fail(ASGS_E_INVALID, "n_views out of range");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(ASGS_E_INVALID, "bad resolution");
+  *bytes = (size_t)n_views * (size_t)residual_partials(width, height) * sizeof(float);
+  return ASGS_OK;
+}
+
+int asgs_tracking_residual(int32_t n_views, int32_t width, int32_t height, const asgs_residual_opts* opts,
+                           const asgs_residual_maps* in, float* R, float* sigma, uint8_t* dynamic, float* xi,
+                           void* work, size_t work_bytes, void* stream) {
+  if (n_views < 1 || n_views > ASGS_MAX_VIEWS) return fail(ASGS_E_INVALID, "n_views out of range");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(ASGS_E_INVALID, "bad resolution");
+  if ((int64_t)width * height * n_views > ((int64_t)1 << 31)) return fail(ASGS_E_INVALID, "too many pixels");
+  if (!opts || !in) return fail(ASGS_E_INVALID, "tracking_residual: NULL argument");
+  const float wts[6] = {opts->w_rgb, opts->w_depth, opts->w_feat, opts->vis_T, opts->sigma_min, opts->dyn_thresh};
+  for (float f : wts)
+    if (!isfinite(f)) return fail(ASGS_E_INVALID, "tracking_residual: non-finite option");
+  if (!(opts->sigma_min > 0.f)) return fail(ASGS_E_INVALID, "tracking_residual: sigma_min must be > 0");
+  if (opts->reserved != 0) return fail(ASGS_E_INVALID, "tracking_residual: reserved must be 0");
+  for (const float* ptr : {in->rgb, in->depth, in->alpha, in->cosine, in->obs_rgb, in->obs_depth})
+    if (!ptr) return fail(ASGS_E_INVALID, "tracking_residual: input map missing");
+  if (!R && !sigma && !dynamic && !xi) return fail(ASGS_E_INVALID, "tracking_residual: no output requested");
+  const size_t need = (size_t)n_views * (size_t)residual_partials(width, height) * sizeof(float);
+  if (xi && (!work || work_bytes < need))
+    return fail(ASGS_E_WORKSPACE, "tracking_residual: xi needs %zu bytes of work", need);
+  ResidualArgs a{};
+  a.rgb = in->rgb;
+  a.depth = in->depth;
+  a.alpha = in->alpha;
+  a.cosine = in->cosine;
+  a.obs_rgb = in->obs_rgb;
+  a.obs_depth = in->obs_depth;
+  a.R = R;
+  a.sigma = sigma;
+  a.dynamic = dynamic;
+  a.partial = xi ? static_cast<float*>(work) : nullptr;
+  a.W = width;
+  a.H = height;
+  a.w[0] = opts->w_rgb;
+  a.w[1] = opts->w_depth;
+  a.w[2] = opts->w_feat;
+  a.vis_T = opts->vis_T;
+  a.sigma_min = opts->sigma_min;
+  a.dyn_thresh = opts->dyn_thresh;
+  {
+    ProfScope ps(ASGS_K_RESIDUAL, reinterpret_cast<hipStream_t>(stream));
+    launch_residual(a, n_views, xi, reinterpret_cast<hipStream_t>(stream));
+  }
+  return check_launch("tracking_residual launch");
+}
+
 int asgs_profile_enable(uint32_t mask) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto& e : g_prof) {

@@ -162,6 +162,20 @@ void launch_l1_loss(const L1Args& a, const L1Views& tv, hipStream_t s);
 int l1_setup(int32_t n_views, int32_t width, int32_t height, int32_t n_feat, const asgs_images* maps,
              const asgs_l1_targets* targets, const asgs_images* grad, L1Args& a, L1Views& tv);
 
+// Tracking residual and uncertainty (residual.hip). Maps packed [V][C][H][W].
+struct ResidualArgs {
+  const float *rgb, *depth, *alpha, *cosine, *obs_rgb, *obs_depth;
+  float* R;            // [V][H][W] or NULL
+  float* sigma;        // [V][H][W] or NULL
+  uint8_t* dynamic;    // [V][H][W] or NULL
+  float* partial;      // [V][residual_partials] objective partials, or NULL (no xi)
+  int32_t W, H;
+  float w[3];          // residual weights: colour, depth, feature
+  float vis_T, sigma_min, dyn_thresh;
+};
+int64_t residual_partials(int width, int height);  // per view
+void launch_residual(const ResidualArgs& a, int n_views, float* xi, hipStream_t s);
+
 struct DecodeConst {
   int64_t A;
   int32_t k, nf, n_views, precision;

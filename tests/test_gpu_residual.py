@@ -1,0 +1,117 @@
+"""GPU: the multi-modal tracking residual, per-pixel uncertainty and motion
+mask (asgs_tracking_residual; Sec. 3.2 Eq. 6, Sec. 3.4 Eq. 15) against the
+FP64 oracle, through the C ABI.
+
+R and sigma: max |x - ref| / max |ref| <= 1e-5 per view (FP32 arithmetic of a
+handful of terms); xi within 1e-5 relative; the motion mask bit for bit except
+pixels whose mask decision sits within 1e-5 of its threshold in the oracle
+(counted, bounded), and the visibility decision likewise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import IMG_TOL, guard_report, log, oracle_opts, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2505_22335_amd.core import tracking_residual
+    from paper_2505_22335_amd.pipeline import AnchorRenderer, anchors_to_device
+
+RES_TOL = 1e-5
+
+
+def _oracle_views(m, smin=1e-3, thr=1.0, weights=oracle.RESIDUAL_WEIGHTS):
+    out = []
+    for v in range(m["rgb"].shape[0]):
+        R = oracle.residual(m["rgb"][v], m["depth"][v], m["alpha"][v], m["cosine"][v], m["obs_rgb"][v],
+                            m["obs_depth"][v], weights=weights)
+        sig, xi, dyn = oracle.uncertainty(R, sigma_min=smin, dyn_thresh=thr)
+        out.append(dict(R=R, sigma=sig, xi=xi, dynamic=dyn,
+                        band=np.abs(2 * np.maximum(smin * smin, 2 * R) - thr) <= 1e-5 * thr))
+    return out
+
+
+def _gpu(m, **kw):
+    d = {k: torch.as_tensor(v).cuda() for k, v in m.items()}
+    res = tracking_residual({"rgb": d["rgb"], "depth": d["depth"], "alpha": d["alpha"]}, d["cosine"],
+                            d["obs_rgb"], d["obs_depth"], **kw)
+    torch.cuda.synchronize()
+    return {k: to_np(v) if v.dtype != torch.uint8 else v.cpu().numpy() for k, v in res.items()}
+
+
+def _compare(g, ref, label):
+    for v, r in enumerate(ref):
+        eR = rel_err(g["R"][v], r["R"])
+        eS = rel_err(g["sigma"][v], r["sigma"])
+        exi = abs(g["xi"][v] - r["xi"]) / max(abs(r["xi"]), 1e-12)
+        keep = ~r["band"]
+        mism = int(((g["dynamic"][v] != 0) != r["dynamic"])[keep].sum())
+        log(label, "view", v, "R %.2e sigma %.2e xi %.2e (gpu %.7f ref %.7f)" % (eR, eS, exi, g["xi"][v], r["xi"]),
+            "mask band", int(r["band"].sum()), "mask mismatches", mism, "dynamic", int(r["dynamic"].sum()))
+        assert eR <= RES_TOL and eS <= RES_TOL and exi <= RES_TOL
+        assert mism == 0
+        assert r["band"].sum() <= 1e-4 * r["band"].size + 2
+
+
+@pytest.mark.parametrize("V,H,W", [(1, 53, 75), (3, 48, 64), (1, 480, 640), (2, 1, 1), (1, 2, 3), (1, 5, 130)])
+def test_residual_matches_oracle(V, H, W):
+    """Ragged tiles (75 x 53 against 64 x 4 tiles), several views, the full
+    640x480 frame, and degenerate images where the 3x3 box has 1 to 6
+    in-image pixels."""
+    log("case residual", V, H, W)
+    m = synth.residual_maps(100 + V * H + W, V, H, W)
+    _compare(_gpu(m), _oracle_views(m), "residual %dx%dx%d" % (V, H, W))
+
+
+@pytest.mark.parametrize("opts", [dict(sigma_min=0.05, dyn_thresh=0.5), dict(w_rgb=1.0, w_depth=0.0, w_feat=2.0),
+                                  dict(vis_T=0.2)])
+def test_residual_options(opts):
+    log("case residual options", opts)
+    m = synth.residual_maps(7, 2, 37, 70)
+    w = (opts.get("w_rgb", 0.25), opts.get("w_depth", 0.7), opts.get("w_feat", 0.1))
+    smin, thr, visT = opts.get("sigma_min", 1e-3), opts.get("dyn_thresh", 1.0), opts.get("vis_T", 0.1)
+    ref = []
+    for v in range(2):
+        R = oracle.residual(m["rgb"][v], m["depth"][v], m["alpha"][v], m["cosine"][v], m["obs_rgb"][v],
+                            m["obs_depth"][v], weights=w, vis_T=visT)
+        sig, xi, dyn = oracle.uncertainty(R, sigma_min=smin, dyn_thresh=thr)
+        ref.append(dict(R=R, sigma=sig, xi=xi, dynamic=dyn,
+                        band=np.abs(2 * np.maximum(smin * smin, 2 * R) - thr) <= 1e-5 * thr))
+    _compare(_gpu(m, **opts), ref, "residual options")
+
+
+def test_residual_of_rendered_room():
+    """End to end on the 640x480 room of 200k decoded Gaussians: the library
+    renders the maps and computes the residual against seeded observations,
+    the oracle does the same from its own FP64 render. Pixels in the
+    rendering guard band or whose visibility decision sits within 1e-5 of
+    its level are excluded."""
+    sc, cam, _ = synth.c2()
+    log("case residual rendered room")
+    ref = oracle.render_scene(sc, cam, oracle_opts(16), with_margins=True)
+    keep, grep = guard_report(ref["margins"])
+    m = synth.residual_maps(11, 1, cam.height, cam.width)
+    obs = dict(obs_rgb=m["obs_rgb"][0], obs_depth=m["obs_depth"][0])
+    cos = m["cosine"][0]
+    R = oracle.residual(ref["rgb"], ref["depth"], ref["alpha"], cos, obs["obs_rgb"], obs["obs_depth"])
+    sig, xi, dyn = oracle.uncertainty(R)
+    r = AnchorRenderer(anchors_to_device(sc), [cam])
+    r.fit()
+    img = r.forward()
+    dev = lambda a: torch.as_tensor(a).cuda()
+    res = tracking_residual(img, dev(cos[None]), dev(obs["obs_rgb"][None]), dev(obs["obs_depth"][None]))
+    torch.cuda.synchronize()
+    # (the box filter reads only the observed depth, which both sides share)
+    k3 = keep & (np.abs((1 - ref["alpha"]) - 0.1) > 1e-5)
+    e = rel_err(to_np(res["R"][0]), R, k3)
+    es = rel_err(to_np(res["sigma"][0]), sig, k3)
+    band = np.abs(2 * np.maximum(1e-6, 2 * R) - 1.0) <= 1e-4
+    mism = int(((res["dynamic"][0].cpu().numpy() != 0) != dyn)[k3 & ~band].sum())
+    log("rendered room residual R %.2e sigma %.2e" % (e, es), "kept", int(k3.sum()), "dynamic", int(dyn.sum()),
+        "mask mismatches", mism, "xi gpu %.6f ref %.6f" % (float(res["xi"][0]), xi))
+    assert e <= IMG_TOL and es <= IMG_TOL and mism == 0
+    assert 1000 < dyn.sum() < dyn.size - 1000
