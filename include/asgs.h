@@ -361,6 +361,67 @@ int asgs_tracking_residual(int32_t n_views, int32_t width, int32_t height, const
                            void* work, size_t work_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Feature lift F_m and cosine distillation (UP-SLAM Sec. 3.3, Eq. 11, Eq. 12)
+ *
+ * Per pixel p of view v, the rendered low-dimensional feature x = F~_p (16
+ * channels, Eq. 10) is lifted by the per-pixel MLP F_m (1x1 convolutions):
+ *   h = relu(W1 x + b1) (128),  F^_p = W2 h + b2 (N_h),
+ * and compared with the DINO feature F_p, the patch grid dino upsampled
+ * bilinearly to the image (sample centres at half-integers, clamped):
+ *   cos_p = F_p . F^_p / max(|F_p| |F^_p|, 1e-12),   loss[v] = mean_p (1 - cos_p).
+ * The per-pixel cosine is also the feature term of the tracking residual.
+ * Parameters, packed float: W1 [128][16], b1 [128], W2 [N_h][128], b2 [N_h].
+ * F^ is never formed: F . F^ and |F^|^2 are evaluated through W2^T F (per
+ * patch) and the Gram matrix W2^T W2 (FP32 sums of products taken on the
+ * matrix cores with high and low bfloat16 parts, three products per pair).
+ * ------------------------------------------------------------------------- */
+typedef struct asgs_feature_lift {
+  int32_t n_high;          /* N_h, channels of the DINO features: 1..1024 */
+  int32_t grid_h, grid_w;  /* patch grid of the DINO features; at most 3 patches per 16 pixels */
+  int32_t reserved;        /* must be 0 */
+} asgs_feature_lift;
+
+int asgs_feature_param_count(const asgs_feature_lift* f, int64_t* count);
+/* Bytes of work both calls need for n_views views of width x height. */
+int asgs_feature_workspace_size(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height,
+                                size_t* bytes);
+/* feat [V][16][H][W] rendered features, params (packed), dino [V][N_h][grid_h][grid_w];
+ * writes cosine [V][H][W] and, if not NULL, loss [V] (fixed-order sums). */
+int asgs_feature_forward(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height,
+                         const float* feat, const float* params, const float* dino, float* cosine, float* loss,
+                         void* work, size_t work_bytes, void* stream);
+/* Backward of the cosine map: d_cos [V][H][W] = dL/dcos. Writes (overwrites)
+ * d_feat [V][16][H][W] = dL/dF~ and d_params (packed like params, summed over
+ * views). Recomputes the forward; deterministic. The DINO features get no
+ * gradient. */
+int asgs_feature_backward(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height,
+                          const float* feat, const float* params, const float* dino, const float* d_cos,
+                          float* d_feat, float* d_params, void* work, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Probabilistic anchor update (UP-SLAM Sec. 3.3, Eq. 7)
+ *
+ * Per anchor, the occupancy probability p is updated with the observation
+ * probability p_obs = P(n | z_t) by Bayes' rule in odds form with the prior
+ * P(n) (Eq. 7's P(n)/P(n) factor read as the prior odds P(n)/(1 - P(n))):
+ *   p <- 1 / (1 + (1 - p_obs)/p_obs * (1 - p)/p * prior/(1 - prior)),
+ * then clamped to [p_min, p_max]. keep[i] = (p >= prune_below) marks the
+ * anchors that stay; *n_keep (device int64, may be NULL) receives their
+ * number. p is updated in place ([n] float, device); p_obs [n] float
+ * (device); keep [n] uint8 (device) or NULL. Probabilities outside (0, 1)
+ * give the IEEE result of the formula. Asynchronous; the count is exact.
+ * ------------------------------------------------------------------------- */
+typedef struct asgs_anchor_update_opts {
+  float prior;        /* P(n), in (0, 1) */
+  float p_min, p_max; /* clamp of the result, 0 <= p_min <= p_max <= 1 (0, 1: none) */
+  float prune_below;  /* keep anchors with p >= this (0: keep all) */
+  int32_t reserved;   /* must be 0 */
+} asgs_anchor_update_opts;
+
+int asgs_anchor_update(int64_t n_anchors, const asgs_anchor_update_opts* opts, const float* p_obs, float* p,
+                       uint8_t* keep, int64_t* n_keep, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Timing hook (for measurement tools; off by default)
  *
  * While a kernel class is enabled, each launch of it made by this library is
@@ -377,7 +438,9 @@ enum {
   ASGS_K_DECODE = 5,       /* decoder forward (one kernel) */
   ASGS_K_DECODE_BWD = 6,   /* decoder backward + parameter reduction (several kernels) */
   ASGS_K_RESIDUAL = 7,     /* tracking residual and uncertainty (one kernel + the per-view mean) */
-  ASGS_K_NUM = 8
+  ASGS_K_FEATURE = 8,      /* feature lift forward (weight and patch preparation + per-pixel kernel) */
+  ASGS_K_FEATURE_BWD = 9,  /* feature lift backward (preparation, per-pixel kernel, reductions) */
+  ASGS_K_NUM = 10
 };
 /* Enable the classes whose bit (1 << class) is set in mask; 0 disables all.
  * Clears earlier measurements. */

@@ -18,6 +18,9 @@ in float64 with PyTorch CPU ops:
                   sum (Eq. 3) and the low-dimensional feature (Eq. 10);
 * ``uncertainty`` the multi-modal tracking residual (Sec. 3.2, Eq. 6) and
                   the per-pixel uncertainty and motion mask (Sec. 3.4, Eq. 15);
+* ``feature``     the feature lift F_m and the cosine distillation loss
+                  (Sec. 3.3, Eq. 11 and Eq. 12);
+* ``anchors``     the probabilistic anchor update (Sec. 3.3, Eq. 7);
 * ``render``      the whole path, with the backward pass as the vector-Jacobian
                   product of the forward definition (torch autograd in float64)
                   and the SE(3) pose gradient.
@@ -26,7 +29,7 @@ Readings of the paper where it is silent are listed in ``oracle.readings``.
 Parity pins (closed forms, invariants, brute force, finite differences) live
 in ``tests/test_oracle_*.py``.
 """
-from .readings import RenderOpts, READINGS, RESIDUAL_READINGS  # noqa: F401
+from .readings import RenderOpts, READINGS, RESIDUAL_READINGS, FEATURE_READINGS, ANCHOR_READINGS  # noqa: F401
 from .geometry import quat_to_rotmat, se3_exp, pose_cw, camera_center  # noqa: F401
 from .decode import decode, HEAD_ORDER  # noqa: F401
 from .project import project  # noqa: F401
@@ -34,3 +37,5 @@ from .binning import bin_and_sort  # noqa: F401
 from .composite import composite_tile, composite_bruteforce  # noqa: F401
 from .render import render, render_scene, gaussians_from_plain, Leaves  # noqa: F401
 from .uncertainty import box3, cosine, residual, uncertainty, RESIDUAL_WEIGHTS  # noqa: F401
+from .feature import upsample, lift, cosine_map, distill, relu_margin  # noqa: F401
+from .anchors import anchor_update  # noqa: F401

@@ -64,3 +64,28 @@ RESIDUAL_READINGS = (
     "is used, i.e. dynamic where 4R > 1 above the floor.",
     "Residual weights (lambda_1^t, lambda_2^t, lambda_3^t) = (0.25, 0.7, 0.1) from the appendix.",
 )
+
+
+# Readings for the feature lift and the distillation loss (Sec. 3.3, Eq. 11, Eq. 12).
+FEATURE_READINGS = (
+    "F_m is a per-pixel MLP: the appendix's 'Convolution -> ReLU -> Convolution' with a 128-wide hidden "
+    "layer is read as 1x1 convolutions 16 -> 128 -> N_h (a 'shallow MLP' lifting each pixel's feature).",
+    "N_h is unstated: 384, the width of DINOv2 ViT-S/14 features, as a parameter.",
+    "DINO features live on the patch grid (34 x 46 patches of 14 px for a 476 x 644 crop of a 640 x 480 "
+    "frame) and are upsampled bilinearly to the image with half-pixel sample centres, clamped at the "
+    "borders (the usual align-corners-off convention).",
+    "Eq.12's sum over i = 0..N_d divided by N_d is the mean over the image's pixels (feature vectors) of "
+    "1 - cos(F, F^).",
+    "cos divides by the product of the norms bounded below by 1e-12, as in the tracking residual.",
+)
+
+
+# Readings for the probabilistic anchor update (Sec. 3.3, Eq. 7).
+ANCHOR_READINGS = (
+    "Eq.7's factor P(n)/P(n) is read as the prior odds P(n)/(1 - P(n)), the occupancy-mapping form the "
+    "paper cites: the log-odds of the posterior are those of the observation plus those of the previous "
+    "estimate minus those of the prior.",
+    "The observation model P(n | z_t) is not stated: it is an input per anchor.",
+    "Clamping bounds and the pruning level are not stated: options, by default no clamping [0, 1] and no "
+    "pruning.",
+)

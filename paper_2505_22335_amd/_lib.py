@@ -28,8 +28,9 @@ lib = C.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_WORKSPACE, E_CAPACITY, E_DEVICE, E_UNSUPPORTED = range(6)
 MAX_VIEWS = 64
-K_PROJECT, K_SORT, K_BLEND_FWD, K_BLEND_BWD, K_PROJECT_BWD, K_DECODE, K_DECODE_BWD, K_RESIDUAL = range(8)
-K_NUM = 8
+(K_PROJECT, K_SORT, K_BLEND_FWD, K_BLEND_BWD, K_PROJECT_BWD, K_DECODE, K_DECODE_BWD, K_RESIDUAL, K_FEATURE,
+ K_FEATURE_BWD) = range(10)
+K_NUM = 10
 (CTX_PAIR_TILE, CTX_PAIR_GAUSS, CTX_TILE_RANGE, CTX_RECT, CTX_NCONTRIB, CTX_TFINAL, CTX_GEOM, CTX_RADIUS,
  CTX_DEPTH_KEY, CTX_NTILES) = range(1, 11)
 
@@ -84,6 +85,15 @@ class ResidualMaps(C.Structure):
                 ("obs_rgb", C.c_void_p), ("obs_depth", C.c_void_p)]
 
 
+class FeatureLift(C.Structure):
+    _fields_ = [("n_high", C.c_int32), ("grid_h", C.c_int32), ("grid_w", C.c_int32), ("reserved", C.c_int32)]
+
+
+class AnchorUpdateOpts(C.Structure):
+    _fields_ = [("prior", C.c_float), ("p_min", C.c_float), ("p_max", C.c_float), ("prune_below", C.c_float),
+                ("reserved", C.c_int32)]
+
+
 P = C.c_void_p
 _sigs = {
     "asgs_abi_version": (C.c_int, []),
@@ -120,6 +130,14 @@ _sigs = {
     "asgs_residual_work_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "asgs_tracking_residual": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(ResidualOpts),
                                          C.POINTER(ResidualMaps), P, P, P, P, P, C.c_size_t, P]),
+    "asgs_feature_param_count": (C.c_int, [C.POINTER(FeatureLift), C.POINTER(C.c_int64)]),
+    "asgs_feature_workspace_size": (C.c_int, [C.POINTER(FeatureLift), C.c_int32, C.c_int32, C.c_int32,
+                                              C.POINTER(C.c_size_t)]),
+    "asgs_feature_forward": (C.c_int, [C.POINTER(FeatureLift), C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P,
+                                       C.c_size_t, P]),
+    "asgs_feature_backward": (C.c_int, [C.POINTER(FeatureLift), C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P,
+                                        P, C.c_size_t, P]),
+    "asgs_anchor_update": (C.c_int, [C.c_int64, C.POINTER(AnchorUpdateOpts), P, P, P, P, P]),
     "asgs_profile_enable": (C.c_int, [C.c_uint32]),
     "asgs_profile_read": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
@@ -339,6 +357,47 @@ def tracking_residual(n_views: int, width: int, height: int, opts: ResidualOpts,
     check(lib.asgs_tracking_residual(n_views, width, height, C.byref(opts), C.byref(maps), _ptr(R), _ptr(sigma),
                                      _ptr(dynamic), _ptr(xi), _ptr(work), 0 if work is None else work.numel(),
                                      _stream(stream)), "asgs_tracking_residual")
+
+
+def feature_lift(n_high: int, grid_h: int, grid_w: int) -> FeatureLift:
+    f = FeatureLift()
+    f.n_high, f.grid_h, f.grid_w, f.reserved = n_high, grid_h, grid_w, 0
+    return f
+
+
+def feature_param_count(f: FeatureLift) -> int:
+    n = C.c_int64()
+    check(lib.asgs_feature_param_count(C.byref(f), C.byref(n)), "asgs_feature_param_count")
+    return n.value
+
+
+def feature_workspace_size(f: FeatureLift, n_views: int, width: int, height: int) -> int:
+    b = C.c_size_t()
+    check(lib.asgs_feature_workspace_size(C.byref(f), n_views, width, height, C.byref(b)),
+          "asgs_feature_workspace_size")
+    return b.value
+
+
+def feature_forward(f: FeatureLift, n_views: int, width: int, height: int, feat, params, dino, cosine, loss, work,
+                    stream=None):
+    check(lib.asgs_feature_forward(C.byref(f), n_views, width, height, feat.data_ptr(), params.data_ptr(),
+                                   dino.data_ptr(), cosine.data_ptr(), _ptr(loss), work.data_ptr(), work.numel(),
+                                   _stream(stream)), "asgs_feature_forward")
+
+
+def feature_backward(f: FeatureLift, n_views: int, width: int, height: int, feat, params, dino, d_cos, d_feat,
+                     d_params, work, stream=None):
+    check(lib.asgs_feature_backward(C.byref(f), n_views, width, height, feat.data_ptr(), params.data_ptr(),
+                                    dino.data_ptr(), d_cos.data_ptr(), d_feat.data_ptr(), d_params.data_ptr(),
+                                    work.data_ptr(), work.numel(), _stream(stream)), "asgs_feature_backward")
+
+
+def anchor_update(p_obs, p, keep=None, n_keep=None, prior=0.5, p_min=0.0, p_max=1.0, prune_below=0.0,
+                  stream=None):
+    o = AnchorUpdateOpts()
+    o.prior, o.p_min, o.p_max, o.prune_below, o.reserved = prior, p_min, p_max, prune_below, 0
+    check(lib.asgs_anchor_update(p.numel(), C.byref(o), p_obs.data_ptr(), p.data_ptr(), _ptr(keep), _ptr(n_keep),
+                                 _stream(stream)), "asgs_anchor_update")
 
 
 def profile_enable(mask: int):

@@ -253,3 +253,34 @@ def tracking_residual(rendered: Dict[str, torch.Tensor], cosine: torch.Tensor, o
     L.tracking_residual(V, W, H, L.residual_opts(**opt_kw), m, out["R"], out["sigma"], out["dynamic"],
                         out.get("xi"), work)
     return out
+
+
+class FeatureLift:
+    """The feature lift F_m and the cosine distillation (asgs_feature_forward
+    / asgs_feature_backward) for views of one resolution, with its device
+    workspace. params: packed W1 [128][16], b1, W2 [n_high][128], b2."""
+
+    def __init__(self, n_views: int, width: int, height: int, n_high: int, grid_h: int, grid_w: int,
+                 device="cuda"):
+        self.desc = L.feature_lift(n_high, grid_h, grid_w)
+        self.V, self.W, self.H = n_views, width, height
+        self.n_params = L.feature_param_count(self.desc)
+        self.work = torch.empty(L.feature_workspace_size(self.desc, n_views, width, height), dtype=torch.uint8,
+                                device=device)
+        self.device = device
+
+    def forward(self, feat: torch.Tensor, params: torch.Tensor, dino: torch.Tensor, want_loss: bool = True):
+        """feat (V,16,H,W), dino (V,n_high,grid_h,grid_w) -> cosine (V,H,W), loss (V,) mean 1 - cos."""
+        cos = torch.empty((self.V, self.H, self.W), dtype=torch.float32, device=self.device)
+        loss = torch.empty(self.V, dtype=torch.float32, device=self.device) if want_loss else None
+        L.feature_forward(self.desc, self.V, self.W, self.H, feat.contiguous(), params.contiguous(),
+                          dino.contiguous(), cos, loss, self.work)
+        return cos, loss
+
+    def backward(self, feat: torch.Tensor, params: torch.Tensor, dino: torch.Tensor, d_cos: torch.Tensor):
+        """dL/dcos (V,H,W) -> dL/dfeat (V,16,H,W), dL/dparams (packed)."""
+        d_feat = torch.empty((self.V, 16, self.H, self.W), dtype=torch.float32, device=self.device)
+        d_params = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        L.feature_backward(self.desc, self.V, self.W, self.H, feat.contiguous(), params.contiguous(),
+                           dino.contiguous(), d_cos.contiguous(), d_feat, d_params, self.work)
+        return d_feat, d_params

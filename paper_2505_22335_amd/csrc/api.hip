@@ -717,6 +717,108 @@ int asgs_tracking_residual(int32_t n_views, int32_t width, int32_t height, const
   return check_launch("tracking_residual launch");
 }
 
+static int feature_check(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height) {
+  if (!f) return fail(ASGS_E_INVALID, "feature lift descriptor is NULL");
+  if (f->reserved != 0) return fail(ASGS_E_INVALID, "feature lift: reserved must be 0");
+  if (f->n_high < 1 || f->n_high > 1024) return fail(ASGS_E_UNSUPPORTED, "feature lift: n_high must be in 1..1024");
+  if (n_views < 1 || n_views > ASGS_MAX_VIEWS) return fail(ASGS_E_INVALID, "n_views out of range");
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(ASGS_E_INVALID, "bad resolution");
+  if (f->grid_h < 1 || f->grid_w < 1 || f->grid_h > height || f->grid_w > width)
+    return fail(ASGS_E_INVALID, "feature lift: patch grid must be 1..height x 1..width");
+  if (feature_max_patch_span(width, height, f->grid_h, f->grid_w) > 4)
+    return fail(ASGS_E_UNSUPPORTED, "feature lift: a 16x16 pixel tile reaches more than 4x4 patches (grid too fine)");
+  return ASGS_OK;
+}
+
+int asgs_feature_param_count(const asgs_feature_lift* f, int64_t* count) {
+  if (!f || !count) return fail(ASGS_E_INVALID, "NULL argument");
+  if (f->n_high < 1 || f->n_high > 1024) return fail(ASGS_E_UNSUPPORTED, "feature lift: n_high must be in 1..1024");
+  *count = 128 * 16 + 128 + (int64_t)f->n_high * 128 + f->n_high;
+  return ASGS_OK;
+}
+
+int asgs_feature_workspace_size(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height,
+                                size_t* bytes) {
+  if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
+  int st = feature_check(f, n_views, width, height);
+  if (st) return st;
+  *bytes = feature_layout(f->n_high, n_views, width, height, f->grid_h, f->grid_w).total;
+  return ASGS_OK;
+}
+
+static int feature_call(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height, const float* feat,
+                        const float* params, const float* dino, void* work, size_t work_bytes, FeatCall& c,
+                        FeatLayout& L) {
+  int st = feature_check(f, n_views, width, height);
+  if (st) return st;
+  if (!feat || !params || !dino || !work) return fail(ASGS_E_INVALID, "feature lift: NULL input or work");
+  if (!aligned16(feat) || !aligned16(params) || !aligned16(dino) || (reinterpret_cast<uintptr_t>(work) & 255u))
+    return fail(ASGS_E_INVALID, "feature lift: inputs must be 16-byte and work 256-byte aligned");
+  L = feature_layout(f->n_high, n_views, width, height, f->grid_h, f->grid_w);
+  if (work_bytes < L.total) return fail(ASGS_E_WORKSPACE, "feature lift needs %zu bytes of work", L.total);
+  c = FeatCall{};
+  c.n_views = n_views;
+  c.width = width;
+  c.height = height;
+  c.nh = f->n_high;
+  c.Hp = f->grid_h;
+  c.Wp = f->grid_w;
+  c.feat = feat;
+  c.params = params;
+  c.dino = dino;
+  return ASGS_OK;
+}
+
+int asgs_feature_forward(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height,
+                         const float* feat, const float* params, const float* dino, float* cosine, float* loss,
+                         void* work, size_t work_bytes, void* stream) {
+  FeatCall c;
+  FeatLayout L;
+  int st = feature_call(f, n_views, width, height, feat, params, dino, work, work_bytes, c, L);
+  if (st) return st;
+  if (!cosine) return fail(ASGS_E_INVALID, "feature_forward: cosine is NULL");
+  c.cosine = cosine;
+  c.loss = loss;
+  {
+    ProfScope ps(ASGS_K_FEATURE, reinterpret_cast<hipStream_t>(stream));
+    launch_feature_forward(c, L, static_cast<char*>(work), reinterpret_cast<hipStream_t>(stream));
+  }
+  return check_launch("feature_forward launch");
+}
+
+int asgs_feature_backward(const asgs_feature_lift* f, int32_t n_views, int32_t width, int32_t height,
+                          const float* feat, const float* params, const float* dino, const float* d_cos,
+                          float* d_feat, float* d_params, void* work, size_t work_bytes, void* stream) {
+  FeatCall c;
+  FeatLayout L;
+  int st = feature_call(f, n_views, width, height, feat, params, dino, work, work_bytes, c, L);
+  if (st) return st;
+  if (!d_cos || !d_feat || !d_params) return fail(ASGS_E_INVALID, "feature_backward: NULL gradient argument");
+  c.dcos = d_cos;
+  c.dfeat = d_feat;
+  c.dparams = d_params;
+  {
+    ProfScope ps(ASGS_K_FEATURE_BWD, reinterpret_cast<hipStream_t>(stream));
+    launch_feature_backward(c, L, static_cast<char*>(work), reinterpret_cast<hipStream_t>(stream));
+  }
+  return check_launch("feature_backward launch");
+}
+
+int asgs_anchor_update(int64_t n_anchors, const asgs_anchor_update_opts* opts, const float* p_obs, float* p,
+                       uint8_t* keep, int64_t* n_keep, void* stream) {
+  if (!opts) return fail(ASGS_E_INVALID, "anchor_update: opts is NULL");
+  if (n_anchors < 1 || n_anchors > ((int64_t)1 << 31)) return fail(ASGS_E_INVALID, "anchor_update: n_anchors out of range");
+  if (!p_obs || !p) return fail(ASGS_E_INVALID, "anchor_update: NULL probabilities");
+  if (!(opts->prior > 0.f && opts->prior < 1.f)) return fail(ASGS_E_INVALID, "anchor_update: prior must be in (0, 1)");
+  if (!(opts->p_min >= 0.f && opts->p_max <= 1.f && opts->p_min <= opts->p_max) || !isfinite(opts->prune_below))
+    return fail(ASGS_E_INVALID, "anchor_update: need 0 <= p_min <= p_max <= 1 and a finite prune level");
+  if (opts->reserved != 0) return fail(ASGS_E_INVALID, "anchor_update: reserved must be 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  launch_anchor_update(n_anchors, p_obs, p, keep, reinterpret_cast<unsigned long long*>(n_keep), opts->prior,
+                       opts->p_min, opts->p_max, opts->prune_below, s);
+  return check_launch("anchor_update launch");
+}
+
 int asgs_profile_enable(uint32_t mask) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto& e : g_prof) {

@@ -1,0 +1,811 @@
+// Feature lift F_m and cosine distillation (UP-SLAM Sec. 3.3, Eq. 11, Eq. 12).
+//
+// Per pixel p: x = F~_p (16), h = relu(W1 x + b1) (128), F^_p = W2 h + b2 (N_h),
+// F_p = bilinear upsampling of the DINO patch grid, cos_p = F.F^ / |F||F^|.
+// F^ (N_h wide per pixel) is never formed. With the patch vectors G_c:
+//   F.F^   = sum_c w_c (Q_c . h + beta_c),   Q_c = W2^T G_c,  beta_c = b2 . G_c
+//   |F^|^2 = h^T M h + 2 m . h + mu,         M = W2^T W2,     m = W2^T b2, mu = b2 . b2
+//   |F|^2  = sum_{c,c'} w_c w_c' G_c . G_c'
+// over the four bilinear corners c of the pixel. Q_c, beta_c and the dot
+// products of neighbouring patches are prepared once per patch, M once per
+// call; per pixel the work is the 16 -> 128 first layer (vector ALUs, FP32)
+// and the 128 x 128 product M h on the matrix cores (v_mfma_f32_16x16x32_bf16,
+// both operands split into high and low bfloat16 parts, three products per
+// pair: FP32 sums of products good to ~2^-16 relative).
+//
+// The backward is the same identities differentiated: with g = dL/dcos,
+//   s1 = 1 / (|F||F^|),  dq = -g cos / (2 |F^|^2),
+//   dL/dh = g s1 sum_c w_c Q_c + 2 dq (M h + m),  dL/dz = dL/dh [h > 0],
+//   dL/dx = W1^T dL/dz,  dW1 = sum_p dL/dz x^T,  db1 = sum_p dL/dz,
+//   dL/dM = S = sum_p dq h h^T,  dL/dm = sum_p 2 dq h,  dL/dmu = sum_p dq,
+//   dL/dQ_c = sum_p g s1 w_c h,  dL/dbeta_c = sum_p g s1 w_c,
+//   dW2 = sum_c G_c dQ_c^T + W2 (S + S^T) + b2 dm^T,
+//   db2 = sum_c dbeta_c G_c + W2 dm + 2 dmu b2.
+// The pixel sums S, dQ and dW1 are matrix products with K = pixels, taken on
+// the matrix cores from per-round LDS tiles of h, dq h, the corner weights,
+// x and dL/dz. Every sum has a fixed order (deterministic).
+#include "internal.h"
+
+namespace asgs {
+
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+constexpr int kFIn = 16;       // rendered feature channels
+constexpr int kFHid = 128;     // hidden width of F_m
+constexpr int kFT = 16;        // pixel tile side
+constexpr int kSlots = 16;     // patches one tile reaches (at most 4 x 4)
+constexpr int kCell = 136;     // floats per patch record: Q[128], beta, s, r, d, rd, x, pad
+constexpr int kFrag = 8 * 4 * 2 * 64 * 8;  // bf16 of M as A fragments: 8 mb x 4 kb x (hi, lo) x 64 lanes x 8
+constexpr int kBwdWG = 256;    // persistent workgroups of the backward (fixed: the sum order)
+constexpr int kPart = 16384 + 2048 + 128 + 128 + 1;  // per workgroup: S, dW1^T, db1, dm, dmu
+constexpr int kPartStride = 18944;                   // padded to a multiple of 256 floats
+constexpr int kDQ = kFHid + 1;                       // per (tile, slot): dQ[128], dbeta
+
+ASGS_DEV f4v mfma_bf(const bf8v& a, const bf8v& b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+ASGS_DEV uint16_t bf_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+ASGS_DEV float bf_val(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
+// v = hi + lo + O(2^-17 |v|)
+ASGS_DEV void bf_split(float v, uint16_t& hi, uint16_t& lo) {
+  hi = bf_rne(v);
+  lo = bf_rne(v - bf_val(hi));
+}
+ASGS_DEV bf8v as_bf8(const uint16_t* u) {
+  bf8v r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = __builtin_bit_cast(__bf16, u[i]);
+  return r;
+}
+// sum over the four lanes of one pixel column (lanes l, l^16, l^32, l^48);
+// every lane of the column gets the same bits
+ASGS_DEV float col_sum(float v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+// LDS position of hidden unit k in tables read one unit per lane group at a
+// time (units 32 apart land in neighbouring rows)
+ASGS_DEV int hpos(int k) { return (k & 31) * 4 + (k >> 5); }
+
+// Bilinear source of output index p along one axis (sample centres at
+// half-integers, clamped): value = (1 - w1) v[i0] + w1 v[i1].
+ASGS_DEV void bilin(int p, int n_in, float scale, int& i0, int& i1, float& w1) {
+  const float s = fmaxf(((float)p + 0.5f) * scale - 0.5f, 0.f);
+  i0 = min((int)s, n_in - 1);
+  i1 = min(i0 + 1, n_in - 1);
+  w1 = s - (float)i0;
+}
+
+struct FeatArgs {
+  int32_t V, W, H, nh, Hp, Wp;
+  int32_t tiles_x, tiles_y, tiles;  // tiles per view; tiles * V in all
+  float sx, sy;                     // Wp / W, Hp / H
+  const float* feat;                // [V][16][H][W]
+  const float* params;              // W1 [128][16], b1 [128], W2 [nh][128], b2 [nh]
+  const float* dino;                // [V][nh][Hp][Wp]
+  const uint16_t* mfrag;            // M as A fragments (hi, lo)
+  const float* mvec;                // m [128], mu at [128]
+  const float* cells;               // [V][Hp * Wp][kCell]
+  float* cosine;                    // [V][H][W]
+  float* tile_loss;                 // [V * tiles]: sum of 1 - cos over the tile
+  const float* dcos;                // backward: [V][H][W]
+  float* dfeat;                     // backward: [V][16][H][W]
+  float* part;                      // backward: [kBwdWG][kPartStride]
+  float* dqt;                       // backward: [V * tiles][kSlots][kDQ]
+};
+
+// Patch rectangle a tile reaches: rows cy0 .. cy0 + ncy - 1, cols cx0 ..
+struct TileCells {
+  int cy0, ncy, cx0, ncx;
+};
+ASGS_DEV TileCells tile_cells(const FeatArgs& a, int tx, int ty) {
+  TileCells t;
+  int i0, i1;
+  float w;
+  const int xa = tx * kFT, xe = min(xa + kFT - 1, a.W - 1);
+  const int ya = ty * kFT, ye = min(ya + kFT - 1, a.H - 1);
+  bilin(xa, a.Wp, a.sx, i0, i1, w);
+  t.cx0 = i0;
+  bilin(xe, a.Wp, a.sx, i0, i1, w);
+  t.ncx = i1 - t.cx0 + 1;
+  bilin(ya, a.Hp, a.sy, i0, i1, w);
+  t.cy0 = i0;
+  bilin(ye, a.Hp, a.sy, i0, i1, w);
+  t.ncy = i1 - t.cy0 + 1;
+  return t;
+}
+
+// Everything one lane knows about its pixel after the forward.
+struct LanePix {
+  bool valid;
+  int64_t p;           // pixel index in the view
+  float x[kFIn];
+  float h[32];         // hidden units 32 g + u of the lane's group g
+  float mh[32];        // (M h) at the same units
+  float cw[4];         // corner weights
+  int cs[4];           // corner slots in the tile's patch table
+  float q, a, nF, den, cos;
+  bool floored;
+};
+
+// Staged per workgroup: M fragments, first-layer weights, m, the tile's patches.
+struct FeatShared {
+  uint16_t frag[kFrag];
+  float w1[kFHid * kFIn];  // row k at hpos(k)
+  float b1[kFHid];         // at hpos(k)
+  float m[kFHid];          // at hpos(k)
+  float cell[kSlots][kCell];
+};
+
+ASGS_DEV void stage_weights(const FeatArgs& a, FeatShared& S) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const uint4* src = reinterpret_cast<const uint4*>(a.mfrag);
+  uint4* dst = reinterpret_cast<uint4*>(S.frag);
+  for (int q = t; q < kFrag / 8; q += nt) dst[q] = src[q];
+  for (int q = t; q < kFHid * kFIn; q += nt) {
+    const int k = q / kFIn, c = q - k * kFIn;
+    S.w1[hpos(k) * kFIn + c] = a.params[q];
+  }
+  for (int k = t; k < kFHid; k += nt) {
+    S.b1[hpos(k)] = a.params[kFHid * kFIn + k];
+    S.m[hpos(k)] = a.mvec[k];
+  }
+}
+
+ASGS_DEV void stage_cells(const FeatArgs& a, FeatShared& S, int view, const TileCells& tc) {
+  const int n = tc.ncy * tc.ncx;
+  const float* base = a.cells + (int64_t)view * a.Hp * a.Wp * kCell;
+  for (int q = threadIdx.x; q < n * kCell; q += blockDim.x) {
+    const int sl = q / kCell, e = q - sl * kCell;
+    const int cy = tc.cy0 + sl / tc.ncx, cx = tc.cx0 + sl % tc.ncx;
+    S.cell[sl][e] = base[((int64_t)cy * a.Wp + cx) * kCell + e];
+  }
+}
+
+ASGS_DEV float corner_sum(const FeatShared& S, const LanePix& L, int k) {
+  float r = 0.f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) r = fmaf(L.cw[c], S.cell[L.cs[c]][k], r);
+  return r;
+}
+
+// G_c . G_c' of two patches of the tile (at most one row and one column
+// apart): the record of the upper-left patch of the pair holds it (self,
+// right, lower, lower-right, or right-with-lower for the anti-diagonal).
+ASGS_DEV float patch_dot(const FeatShared& S, const TileCells& tc, int ya, int xa, int yb, int xb) {
+  const int dy = yb - ya, dx = xb - xa;
+  const int e = dy == 0 ? (dx == 0 ? 129 : 130) : (dx == 0 ? 131 : (dx == dy ? 132 : 133));
+  const int y = min(ya, yb), x = min(xa, xb);
+  return S.cell[(y - tc.cy0) * tc.ncx + (x - tc.cx0)][e];
+}
+
+// Forward of one pixel per lane (column n = lane & 15, group g = lane >> 4):
+// first layer on the vector ALUs, M h on the matrix cores, the scalars of the
+// cosine summed over the four lanes of the pixel.
+ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCells& tc, int view, int px, int py,
+                           LanePix& L) {
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  L.valid = px < a.W && py < a.H;
+  const int cpx = min(px, a.W - 1), cpy = min(py, a.H - 1);
+  const int64_t HW = (int64_t)a.W * a.H;
+  L.p = (int64_t)cpy * a.W + cpx;
+  const float* fx = a.feat + (int64_t)view * kFIn * HW + L.p;
+#pragma unroll
+  for (int c = 0; c < kFIn; ++c) L.x[c] = L.valid ? fx[c * HW] : 0.f;
+  // hidden units 32 g + u, u = 8 kb + i: B operands of M h (K = hidden)
+  bf8v bh[4], bl[4];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    uint16_t hi[8], lo[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int u = 8 * kb + i, k = 32 * g + u;
+      const float* w = &S.w1[hpos(k) * kFIn];
+      float z = S.b1[hpos(k)];
+#pragma unroll
+      for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], L.x[c], z);
+      L.h[u] = fmaxf(z, 0.f);
+      bf_split(L.h[u], hi[i], lo[i]);
+      if (i & 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    bh[kb] = as_bf8(hi);
+    bl[kb] = as_bf8(lo);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // M h: row block mb holds units 32 g' + 4 mb + j for lane group g'
+  const uint16_t* fr = S.frag + lane * 8;
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+    f4v d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const bf8v ah = *reinterpret_cast<const bf8v*>(fr + ((mb * 4 + kb) * 2 + 0) * 512);
+      const bf8v al = *reinterpret_cast<const bf8v*>(fr + ((mb * 4 + kb) * 2 + 1) * 512);
+      d = mfma_bf(ah, bh[kb], d);
+      d = mfma_bf(ah, bl[kb], d);
+      d = mfma_bf(al, bh[kb], d);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) L.mh[4 * mb + j] = d[j];
+    // keep the fragment loads of one row block together (hoisting all 64 of
+    // them would take every register)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // bilinear corners of the pixel in the tile's patch table
+  int y0, y1, x0, x1;
+  float wy, wx;
+  bilin(cpy, a.Hp, a.sy, y0, y1, wy);
+  bilin(cpx, a.Wp, a.sx, x0, x1, wx);
+  const int ys[4] = {y0, y0, y1, y1}, xs[4] = {x0, x1, x0, x1};
+  L.cw[0] = (1.f - wy) * (1.f - wx);
+  L.cw[1] = (1.f - wy) * wx;
+  L.cw[2] = wy * (1.f - wx);
+  L.cw[3] = wy * wx;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) L.cs[c] = (ys[c] - tc.cy0) * tc.ncx + (xs[c] - tc.cx0);
+  float qp = 0.f, ap = 0.f;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const int k = 32 * g + u;
+    qp = fmaf(L.h[u], L.mh[u] + 2.f * S.m[hpos(k)], qp);
+    ap = fmaf(corner_sum(S, L, k), L.h[u], ap);
+  }
+  L.q = fmaxf(col_sum(qp) + a.mvec[kFHid], 0.f);
+  float beta = 0.f, nF = 0.f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    beta = fmaf(L.cw[c], S.cell[L.cs[c]][128], beta);
+    nF = fmaf(L.cw[c] * L.cw[c], patch_dot(S, tc, ys[c], xs[c], ys[c], xs[c]), nF);
+#pragma unroll
+    for (int e = c + 1; e < 4; ++e)
+      nF = fmaf(2.f * L.cw[c] * L.cw[e], patch_dot(S, tc, ys[c], xs[c], ys[e], xs[e]), nF);
+  }
+  L.a = col_sum(ap) + beta;
+  L.nF = fmaxf(nF, 0.f);
+  const float den = sqrtf(L.nF) * sqrtf(L.q);
+  L.floored = !(den >= 1e-12f);
+  L.den = L.floored ? 1e-12f : den;
+  L.cos = L.a / L.den;
+}
+
+// ---------------------------------------------------------------------------
+// Preparation: M as bfloat16 hi/lo A fragments, m and mu; per patch Q, beta
+// and the dot products with its right, lower and lower-right neighbours and
+// of its right and lower neighbours.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_feat_gram(FeatArgs a, uint16_t* mfrag, float* mvec) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const float* W2 = a.params + kFHid * kFIn + kFHid;
+  const float* b2 = W2 + (int64_t)a.nh * kFHid;
+  if (e < kFrag / 2) {
+    // fragment (mb, kb), lane, element i: row unit 32 (rr/4) + 4 mb + rr%4 (rr = lane & 15),
+    // column unit 32 (lane/16) + 8 kb + i
+    const int i = e & 7, lane = (e >> 3) & 63, kb = (e >> 9) & 3, mb = e >> 11;
+    const int rr = lane & 15;
+    const int ru = 32 * (rr >> 2) + 4 * mb + (rr & 3);
+    const int cu = 32 * (lane >> 4) + 8 * kb + i;
+    float acc = 0.f;
+    for (int c = 0; c < a.nh; ++c) acc = fmaf(W2[(int64_t)c * kFHid + ru], W2[(int64_t)c * kFHid + cu], acc);
+    uint16_t hi, lo;
+    bf_split(acc, hi, lo);
+    mfrag[((mb * 4 + kb) * 2 + 0) * 512 + lane * 8 + i] = hi;
+    mfrag[((mb * 4 + kb) * 2 + 1) * 512 + lane * 8 + i] = lo;
+  }
+  if (e < kFHid) {
+    float acc = 0.f;
+    for (int c = 0; c < a.nh; ++c) acc = fmaf(W2[(int64_t)c * kFHid + e], b2[c], acc);
+    mvec[e] = acc;
+  } else if (e == kFHid) {
+    float acc = 0.f;
+    for (int c = 0; c < a.nh; ++c) acc = fmaf(b2[c], b2[c], acc);
+    mvec[kFHid] = acc;
+  }
+}
+
+constexpr int kMaxHigh = 1024;
+
+__global__ void __launch_bounds__(128) k_feat_cells(FeatArgs a, float* cells) {
+  __shared__ float sg[4][kMaxHigh];
+  __shared__ float red[6][2];
+  const int cell = blockIdx.x, view = blockIdx.y;
+  const int gy = cell / a.Wp, gx = cell - gy * a.Wp;
+  const int64_t plane = (int64_t)a.Hp * a.Wp;
+  const float* G = a.dino + (int64_t)view * a.nh * plane;
+  const float* W2 = a.params + kFHid * kFIn + kFHid;
+  const float* b2 = W2 + (int64_t)a.nh * kFHid;
+  const bool rx = gx + 1 < a.Wp, dy = gy + 1 < a.Hp;
+  const int nb[4] = {cell, rx ? cell + 1 : -1, dy ? cell + a.Wp : -1, (rx && dy) ? cell + a.Wp + 1 : -1};
+  for (int q = threadIdx.x; q < 4 * a.nh; q += 128) {
+    const int k = q / a.nh, c = q - k * a.nh;
+    sg[k][c] = nb[k] >= 0 ? G[c * plane + nb[k]] : 0.f;
+  }
+  __syncthreads();
+  const int j = threadIdx.x;
+  float qj = 0.f;
+  for (int c = 0; c < a.nh; ++c) qj = fmaf(W2[(int64_t)c * kFHid + j], sg[0][c], qj);
+  float p[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int c = j; c < a.nh; c += 128) {
+    const float g0 = sg[0][c], g1 = sg[1][c], g2 = sg[2][c], g3 = sg[3][c];
+    p[0] = fmaf(b2[c], g0, p[0]);
+    p[1] = fmaf(g0, g0, p[1]);
+    p[2] = fmaf(g0, g1, p[2]);
+    p[3] = fmaf(g0, g2, p[3]);
+    p[4] = fmaf(g0, g3, p[4]);
+    p[5] = fmaf(g1, g2, p[5]);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    for (int o = 32; o > 0; o >>= 1) p[k] += __shfl_xor(p[k], o);
+    if ((j & 63) == 0) red[k][j >> 6] = p[k];
+  }
+  __syncthreads();
+  float* out = cells + ((int64_t)view * plane + cell) * kCell;
+  out[j] = qj;
+  if (j < 6) out[kFHid + j] = red[j][0] + red[j][1];
+}
+
+// ---------------------------------------------------------------------------
+// Forward: persistent workgroups of kFwdWaves waves over 16x16 pixel tiles;
+// each wave takes one row of 16 pixels per round.
+// ---------------------------------------------------------------------------
+constexpr int kFwdWaves = 8;
+
+__global__ void __launch_bounds__(64 * kFwdWaves) k_feat_fwd(FeatArgs a) {
+  __shared__ __attribute__((aligned(16))) FeatShared S;
+  __shared__ float tl[kFwdWaves];
+  stage_weights(a, S);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+  const int total = a.tiles * a.V;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int view = t / a.tiles, lt = t - view * a.tiles;
+    const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
+    const TileCells tc = tile_cells(a, tx, ty);
+    __syncthreads();  // the previous tile's patches are no longer read
+    stage_cells(a, S, view, tc);
+    __syncthreads();
+    float acc = 0.f;
+    for (int row = wv; row < kFT; row += kFwdWaves) {
+      LanePix L;
+      lane_forward(a, S, tc, view, tx * kFT + n, ty * kFT + row, L);
+      if (L.valid && g == 0) {
+        a.cosine[(int64_t)view * a.W * a.H + L.p] = L.cos;
+        acc += 1.f - L.cos;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) tl[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float s = 0.f;
+      for (int w = 0; w < kFwdWaves; ++w) s += tl[w];
+      a.tile_loss[t] = s;
+    }
+  }
+}
+
+// mean of 1 - cos per view: fixed-order sum of the view's tile sums
+__global__ void __launch_bounds__(256) k_feat_loss(FeatArgs a, float* loss) {
+  __shared__ float red[4];
+  const int view = blockIdx.x;
+  float s = 0.f;
+  for (int t = threadIdx.x; t < a.tiles; t += 256) s += a.tile_loss[(int64_t)view * a.tiles + t];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) loss[view] = ((red[0] + red[1]) + (red[2] + red[3])) / ((float)a.W * (float)a.H);
+}
+
+// ---------------------------------------------------------------------------
+// Backward: persistent workgroups (kBwdWG, a fixed number so that every sum
+// keeps its order on any device) of 4 waves over the tiles; a round is 4
+// rows of 16 pixels (64 pixels, one row per wave).
+// ---------------------------------------------------------------------------
+constexpr int kBwdWaves = 4;
+constexpr int kRP = 64;  // pixels per round
+
+// [128 units][64 pixels] bfloat16 with the 8-pixel chunks of row k at chunk ^ (k & 7)
+ASGS_DEV int rp_index(int k, int pxl) { return k * kRP + ((((pxl >> 3) ^ (k & 7)) << 3) | (pxl & 7)); }
+
+struct BwdShared {
+  FeatShared F;
+  uint16_t Hhi[kFHid * kRP], Hlo[kFHid * kRP];    // h
+  uint16_t Ghi[kFHid * kRP], Glo[kFHid * kRP];    // dq h, then dL/dz
+  float X[kFIn][kRP];                             // x
+  float Wc[kSlots][kRP];                          // g s1 w_c at each pixel's corner slots
+};
+
+// A or B fragment of a [128][64] bf16 table: row k, pixels 32 kb + 8 (lane / 16) .. + 7
+ASGS_DEV bf8v tab_frag(const uint16_t* T, int k, int kb, int lane) {
+  const int p0 = 32 * kb + 8 * (lane >> 4);
+  return *reinterpret_cast<const bf8v*>(T + rp_index(k, p0));
+}
+// A fragment of a [rows][64] fp32 table (row r, the same pixels), split on the fly
+ASGS_DEV void f32_frag(const float (*T)[kRP], int r, int kb, int lane, bf8v& hi, bf8v& lo) {
+  const int p0 = 32 * kb + 8 * (lane >> 4);
+  uint16_t h[8], l[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) bf_split(T[r][p0 + i], h[i], l[i]);
+  hi = as_bf8(h);
+  lo = as_bf8(l);
+}
+
+__global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
+  __shared__ __attribute__((aligned(16))) BwdShared S;
+  stage_weights(a, S.F);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+  // per-lane accumulators: db1 and dm at units 32 g + u (u < 32), dmu (group 0)
+  float adb1[32], adm[32], admu = 0.f;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) adb1[u] = adm[u] = 0.f;
+  // matrix accumulators: S rows 32 wv .. 32 wv + 31 (two 16-row blocks) x 128 columns;
+  // dW1^T column blocks 2 wv, 2 wv + 1; dQ column blocks wv, wv + 4 (and 8 = dbeta on wave 0)
+  f4v accS[2][8], accW[2], accQ[3];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) accS[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    accW[i] = f4v{0.f, 0.f, 0.f, 0.f};
+  }
+  const int total = a.tiles * a.V;
+  const int64_t HW = (int64_t)a.W * a.H;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int view = t / a.tiles, lt = t - view * a.tiles;
+    const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
+    const TileCells tc = tile_cells(a, tx, ty);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) accQ[i] = f4v{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    stage_cells(a, S.F, view, tc);
+    for (int round = 0; round < kFT / kBwdWaves; ++round) {
+      __syncthreads();  // patches staged; the previous round's tables are no longer read
+      const int row = round * kBwdWaves + wv;
+      LanePix L;
+      lane_forward(a, S.F, tc, view, tx * kFT + n, ty * kFT + row, L);
+      const float gp = L.valid ? a.dcos[(int64_t)view * HW + L.p] : 0.f;
+      const float s1 = 1.f / L.den;
+      const float al = gp * s1;
+      const float dq = L.floored ? 0.f : -0.5f * gp * L.cos / L.q;
+      const int pr = wv * 16 + n;  // pixel of the round
+      __builtin_amdgcn_sched_barrier(0);
+      // dL/dz at the lane's units; dL/dx summed over the pixel's four lanes
+      float dz[32];
+      float dxp[kFIn];
+#pragma unroll
+      for (int c = 0; c < kFIn; ++c) dxp[c] = 0.f;
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const int k = 32 * g + u;
+        const float dh = fmaf(al, corner_sum(S.F, L, k), 2.f * dq * (L.mh[u] + S.F.m[hpos(k)]));
+        dz[u] = L.h[u] > 0.f ? dh : 0.f;
+        const float* w = &S.F.w1[hpos(k) * kFIn];
+#pragma unroll
+        for (int c = 0; c < kFIn; ++c) dxp[c] = fmaf(w[c], dz[u], dxp[c]);
+        adb1[u] += dz[u];
+        adm[u] = fmaf(2.f * dq, L.h[u], adm[u]);
+        if ((u & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+      if (g == 0) admu += dq;
+#pragma unroll
+      for (int c = 0; c < kFIn; ++c) dxp[c] = col_sum(dxp[c]);
+      if (g == 0 && L.valid) {
+        float* dfx = a.dfeat + (int64_t)view * kFIn * HW + L.p;
+#pragma unroll
+        for (int c = 0; c < kFIn; ++c) dfx[c * HW] = dxp[c];
+      }
+      // round tables: h, dq h (units of the lane's group), x, corner weights
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const int k = 32 * g + u;
+        uint16_t hi, lo;
+        bf_split(L.h[u], hi, lo);
+        S.Hhi[rp_index(k, pr)] = hi;
+        S.Hlo[rp_index(k, pr)] = lo;
+        bf_split(dq * L.h[u], hi, lo);
+        S.Ghi[rp_index(k, pr)] = hi;
+        S.Glo[rp_index(k, pr)] = lo;
+      }
+      if (g == 0) {
+#pragma unroll
+        for (int c = 0; c < kFIn; ++c) S.X[c][pr] = L.x[c];
+      }
+      if (g == 1) {
+        float wc[kSlots];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) wc[s] = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int s = 0; s < kSlots; ++s) wc[s] += (L.cs[c] == s) ? al * L.cw[c] : 0.f;
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) S.Wc[s][pr] = wc[s];
+      }
+      __syncthreads();
+      // S += (dq h)^T h over the round's pixels: rows 32 wv .. 32 wv + 31
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int rk = 32 * wv + 16 * i + n;
+          const bf8v gh = tab_frag(S.Ghi, rk, kb, lane), gl = tab_frag(S.Glo, rk, kb, lane);
+#pragma unroll
+          for (int nb = 0; nb < 8; ++nb) {
+            const int ck = 16 * nb + n;
+            const bf8v hh = tab_frag(S.Hhi, ck, kb, lane), hl = tab_frag(S.Hlo, ck, kb, lane);
+            accS[i][nb] = mfma_bf(gh, hh, accS[i][nb]);
+            accS[i][nb] = mfma_bf(gh, hl, accS[i][nb]);
+            accS[i][nb] = mfma_bf(gl, hh, accS[i][nb]);
+            if (nb & 1) __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+        // dQ += Wc^T h (rows = slots), and the constant-one column for dbeta
+        bf8v wh, wl;
+        f32_frag(S.Wc, n, kb, lane, wh, wl);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int nb = i == 0 ? wv : (i == 1 ? wv + 4 : 8);
+          if (nb == 8 && wv != 0) continue;
+          bf8v bh, bl;
+          if (nb < 8) {
+            bh = tab_frag(S.Hhi, 16 * nb + n, kb, lane);
+            bl = tab_frag(S.Hlo, 16 * nb + n, kb, lane);
+          } else {
+            uint16_t one[8], zero[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              one[e] = n == 0 ? bf_rne(1.f) : (uint16_t)0;
+              zero[e] = 0;
+            }
+            bh = as_bf8(one);
+            bl = as_bf8(zero);
+          }
+          accQ[i] = mfma_bf(wh, bh, accQ[i]);
+          accQ[i] = mfma_bf(wh, bl, accQ[i]);
+          accQ[i] = mfma_bf(wl, bh, accQ[i]);
+        }
+      }
+      __syncthreads();  // S and dQ products done: the dq h table takes dL/dz
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        uint16_t hi, lo;
+        bf_split(dz[u], hi, lo);
+        S.Ghi[rp_index(32 * g + u, pr)] = hi;
+        S.Glo[rp_index(32 * g + u, pr)] = lo;
+      }
+      __syncthreads();
+      // dW1^T += x^T dL/dz: rows = input channels, columns 16 nb + n
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        bf8v xh, xl;
+        f32_frag(S.X, n, kb, lane, xh, xl);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int ck = 16 * (2 * wv + i) + n;
+          const bf8v zh = tab_frag(S.Ghi, ck, kb, lane), zl = tab_frag(S.Glo, ck, kb, lane);
+          accW[i] = mfma_bf(xh, zh, accW[i]);
+          accW[i] = mfma_bf(xh, zl, accW[i]);
+          accW[i] = mfma_bf(xl, zh, accW[i]);
+        }
+      }
+    }
+    // the tile's patch gradients: rows = slots 4 (lane / 16) + j, column 16 nb + n
+    float* dq = a.dqt + (int64_t)t * kSlots * kDQ;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int nb = i == 0 ? wv : (i == 1 ? wv + 4 : 8);
+      if (nb == 8 && (wv != 0 || n != 0)) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dq[(4 * g + j) * kDQ + 16 * nb + n] = accQ[i][j];
+    }
+  }
+  // workgroup partials
+  float* part = a.part + (int64_t)blockIdx.x * kPartStride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[(32 * wv + 16 * i + 4 * g + j) * kFHid + 16 * nb + n] = accS[i][nb][j];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[16384 + (4 * g + j) * kFHid + 16 * (2 * wv + i) + n] = accW[i][j];
+  // db1, dm, dmu: over the 16 lanes of each group, then over the waves (fixed order)
+  __syncthreads();
+  float* red = &S.X[0][0];  // per wave 128 sums of db1 (in X) and of dm (in Wc)
+  float* red2 = &S.Wc[0][0];
+  static_assert(sizeof(S.X) >= kBwdWaves * kFHid * sizeof(float) && sizeof(S.Wc) >= kBwdWaves * kFHid * sizeof(float),
+                "reduction space");
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    float b = adb1[u], m = adm[u];
+    for (int o = 1; o < 16; o <<= 1) {
+      b += __shfl_xor(b, o);
+      m += __shfl_xor(m, o);
+    }
+    if (n == 0) {
+      red[wv * 128 + 32 * g + u] = b;
+      red2[wv * 128 + 32 * g + u] = m;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) admu += __shfl_xor(admu, o);
+  __syncthreads();
+  if (threadIdx.x < kFHid) {
+    const int k = threadIdx.x;
+    part[16384 + 2048 + k] = (red[k] + red[128 + k]) + (red[256 + k] + red[384 + k]);
+    part[16384 + 2048 + 128 + k] = (red2[k] + red2[128 + k]) + (red2[256 + k] + red2[384 + k]);
+  }
+  __syncthreads();
+  if (lane == 0) red[wv] = admu;
+  __syncthreads();
+  if (threadIdx.x == 0) part[16384 + 2048 + 256] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Sums of the workgroup partials: S + S^T, dW1^T, db1, dm, dmu (fixed order).
+__global__ void __launch_bounds__(256) k_feat_reduce(const float* __restrict__ part, int nwg, float* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kPart) return;
+  float s = 0.f;
+  for (int b = 0; b < nwg; ++b) s += part[(int64_t)b * kPartStride + e];
+  if (e < 16384) {
+    const int r = e >> 7, c = e & 127;
+    float s2 = 0.f;
+    for (int b = 0; b < nwg; ++b) s2 += part[(int64_t)b * kPartStride + c * 128 + r];
+    s = s + s2;  // symmetric: the (c, r) entry adds the same two sums
+  }
+  out[e] = s;
+}
+
+// Per patch: dQ and dbeta summed over the tiles that reach it (fixed order).
+__global__ void __launch_bounds__(kDQ) k_feat_cell_reduce(FeatArgs a, float* dqc) {
+  const int cell = blockIdx.x, view = blockIdx.y, k = threadIdx.x;
+  const int cy = cell / a.Wp, cx = cell - cy * a.Wp;
+  float s = 0.f;
+  for (int ty = 0; ty < a.tiles_y; ++ty) {
+    const TileCells ry = tile_cells(a, 0, ty);
+    if (cy < ry.cy0 || cy >= ry.cy0 + ry.ncy) continue;
+    for (int tx = 0; tx < a.tiles_x; ++tx) {
+      const TileCells tc = tile_cells(a, tx, ty);
+      if (cx < tc.cx0 || cx >= tc.cx0 + tc.ncx) continue;
+      const int64_t t = (int64_t)view * a.tiles + ty * a.tiles_x + tx;
+      s += a.dqt[(t * kSlots + (cy - tc.cy0) * tc.ncx + (cx - tc.cx0)) * kDQ + k];
+    }
+  }
+  dqc[((int64_t)view * a.Hp * a.Wp + cell) * kDQ + k] = s;
+}
+
+// Parameter gradients: one workgroup per output channel of W2 (row ch of dW2
+// and db2[ch]); the last workgroup writes dW1 and db1.
+__global__ void __launch_bounds__(kFHid) k_feat_params(FeatArgs a, const float* __restrict__ red,
+                                                      const float* __restrict__ dqc, float* d_params) {
+  __shared__ float sred[2];
+  const int ch = blockIdx.x, j = threadIdx.x;
+  const float* W2 = a.params + kFHid * kFIn + kFHid;
+  const float* b2 = W2 + (int64_t)a.nh * kFHid;
+  const float* Ssym = red;
+  const float* dW1t = red + 16384;
+  const float* db1 = red + 16384 + 2048;
+  const float* dm = db1 + 128;
+  const float dmu = dm[128];
+  if (ch == a.nh) {
+    for (int c = 0; c < kFIn; ++c) d_params[j * kFIn + c] = dW1t[c * kFHid + j];
+    d_params[kFHid * kFIn + j] = db1[j];
+    return;
+  }
+  const int64_t plane = (int64_t)a.Hp * a.Wp;
+  float acc = 0.f, accb = 0.f;
+  for (int v = 0; v < a.V; ++v) {
+    const float* G = a.dino + ((int64_t)v * a.nh + ch) * plane;
+    const float* D = dqc + (int64_t)v * plane * kDQ;
+    for (int64_t c = 0; c < plane; ++c) acc = fmaf(G[c], D[c * kDQ + j], acc);
+    for (int64_t c = j; c < plane; c += kFHid) accb = fmaf(G[c], D[c * kDQ + kFHid], accb);
+  }
+  const float* w2 = W2 + (int64_t)ch * kFHid;
+  float acc2 = 0.f;
+  for (int u = 0; u < kFHid; ++u) acc2 = fmaf(w2[u], Ssym[u * kFHid + j], acc2);
+  float* dW2 = d_params + kFHid * kFIn + kFHid;
+  dW2[(int64_t)ch * kFHid + j] = fmaf(b2[ch], dm[j], acc + acc2);
+  // db2[ch] = sum_c dbeta_c G_c[ch] + W2[ch] . dm + 2 dmu b2[ch]
+  accb = fmaf(w2[j], dm[j], accb);
+  for (int o = 32; o > 0; o >>= 1) accb += __shfl_xor(accb, o);
+  if ((j & 63) == 0) sred[j >> 6] = accb;
+  __syncthreads();
+  if (j == 0) dW2[(int64_t)a.nh * kFHid + ch] = (sred[0] + sred[1]) + 2.f * dmu * b2[ch];
+}
+
+}  // namespace
+
+FeatLayout feature_layout(int nh, int n_views, int width, int height, int Hp, int Wp) {
+  FeatLayout L{};
+  const int64_t tiles = (int64_t)((width + kFT - 1) / kFT) * ((height + kFT - 1) / kFT) * n_views;
+  const int64_t cells = (int64_t)Hp * Wp * n_views;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o = (o + b + 255) & ~(size_t)255;
+    return at;
+  };
+  L.mfrag = take((size_t)kFrag * 2);
+  L.mvec = take((kFHid + 1) * 4);
+  L.cells = take((size_t)cells * kCell * 4);
+  L.tile_loss = take((size_t)tiles * 4);
+  L.part = take((size_t)kBwdWG * kPartStride * 4);
+  L.dqt = take((size_t)tiles * kSlots * kDQ * 4);
+  L.red = take((size_t)kPart * 4);
+  L.dqc = take((size_t)cells * kDQ * 4);
+  L.total = o;
+  (void)nh;
+  return L;
+}
+
+int feature_max_patch_span(int width, int height, int Hp, int Wp) {
+  // a tile's 16 pixels span 15 steps of the source coordinate: at most
+  // floor(15 scale) + 1 first corners, plus the last pixel's second corner,
+  // plus one for rounding of the single-precision source coordinate
+  const double sx = 15.0 * Wp / width, sy = 15.0 * Hp / height;
+  const double s = sx > sy ? sx : sy;
+  return (int)(s + 1e-3) + 3;  // the margin covers the rounding of the device's float coordinates
+}
+
+namespace {
+FeatArgs feat_args(const FeatCall& c, const FeatLayout& L, char* work) {
+  FeatArgs a{};
+  a.V = c.n_views;
+  a.W = c.width;
+  a.H = c.height;
+  a.nh = c.nh;
+  a.Hp = c.Hp;
+  a.Wp = c.Wp;
+  a.tiles_x = (c.width + kFT - 1) / kFT;
+  a.tiles_y = (c.height + kFT - 1) / kFT;
+  a.tiles = a.tiles_x * a.tiles_y;
+  a.sx = (float)c.Wp / (float)c.width;
+  a.sy = (float)c.Hp / (float)c.height;
+  a.feat = c.feat;
+  a.params = c.params;
+  a.dino = c.dino;
+  a.mfrag = reinterpret_cast<const uint16_t*>(work + L.mfrag);
+  a.mvec = reinterpret_cast<const float*>(work + L.mvec);
+  a.cells = reinterpret_cast<const float*>(work + L.cells);
+  a.cosine = c.cosine;
+  a.tile_loss = reinterpret_cast<float*>(work + L.tile_loss);
+  a.dcos = c.dcos;
+  a.dfeat = c.dfeat;
+  a.part = reinterpret_cast<float*>(work + L.part);
+  a.dqt = reinterpret_cast<float*>(work + L.dqt);
+  return a;
+}
+
+void launch_prep(const FeatArgs& a, const FeatLayout& L, char* work, hipStream_t s) {
+  hipLaunchKernelGGL(k_feat_gram, dim3((kFrag / 2 + 255) / 256), dim3(256), 0, s, a,
+                     reinterpret_cast<uint16_t*>(work + L.mfrag), reinterpret_cast<float*>(work + L.mvec));
+  hipLaunchKernelGGL(k_feat_cells, dim3((unsigned)(a.Hp * a.Wp), (unsigned)a.V), dim3(128), 0, s, a,
+                     reinterpret_cast<float*>(work + L.cells));
+}
+}  // namespace
+
+void launch_feature_forward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s) {
+  const FeatArgs a = feat_args(c, L, work);
+  launch_prep(a, L, work, s);
+  const int total = a.tiles * a.V;
+  hipLaunchKernelGGL(k_feat_fwd, dim3((unsigned)(total < 512 ? total : 512)), dim3(64 * kFwdWaves), 0, s, a);
+  if (c.loss) hipLaunchKernelGGL(k_feat_loss, dim3((unsigned)a.V), dim3(256), 0, s, a, c.loss);
+}
+
+void launch_feature_backward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s) {
+  const FeatArgs a = feat_args(c, L, work);
+  launch_prep(a, L, work, s);
+  const int total = a.tiles * a.V;
+  const int nwg = total < kBwdWG ? total : kBwdWG;
+  hipLaunchKernelGGL(k_feat_bwd, dim3((unsigned)nwg), dim3(64 * kBwdWaves), 0, s, a);
+  float* red = reinterpret_cast<float*>(work + L.red);
+  hipLaunchKernelGGL(k_feat_reduce, dim3((kPart + 255) / 256), dim3(256), 0, s, a.part, nwg, red);
+  float* dqc = reinterpret_cast<float*>(work + L.dqc);
+  hipLaunchKernelGGL(k_feat_cell_reduce, dim3((unsigned)(a.Hp * a.Wp), (unsigned)a.V), dim3(kDQ), 0, s, a, dqc);
+  hipLaunchKernelGGL(k_feat_params, dim3((unsigned)(a.nh + 1)), dim3(kFHid), 0, s, a, red, dqc, c.dparams);
+}
+
+}  // namespace asgs

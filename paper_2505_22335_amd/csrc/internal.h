@@ -176,6 +176,25 @@ struct ResidualArgs {
 int64_t residual_partials(int width, int height);  // per view
 void launch_residual(const ResidualArgs& a, int n_views, float* xi, hipStream_t s);
 
+// Feature lift and cosine distillation (feature.hip).
+struct FeatLayout {
+  size_t mfrag, mvec, cells, tile_loss, part, dqt, red, dqc, total;
+};
+struct FeatCall {
+  int32_t n_views, width, height, nh, Hp, Wp;
+  const float *feat, *params, *dino, *dcos;
+  float *cosine, *loss, *dfeat, *dparams;
+};
+FeatLayout feature_layout(int nh, int n_views, int width, int height, int Hp, int Wp);
+// patch rows or columns one 16x16 pixel tile can reach (bound)
+int feature_max_patch_span(int width, int height, int Hp, int Wp);
+void launch_feature_forward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s);
+void launch_feature_backward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s);
+
+// Probabilistic anchor update (anchor.hip); n_keep (device, may be NULL) is zeroed first.
+void launch_anchor_update(int64_t n, const float* p_obs, float* p, uint8_t* keep, unsigned long long* n_keep,
+                          float prior, float p_min, float p_max, float prune_below, hipStream_t s);
+
 struct DecodeConst {
   int64_t A;
   int32_t k, nf, n_views, precision;

@@ -1,0 +1,111 @@
+"""GPU: the feature lift F_m and cosine distillation (asgs_feature_forward /
+asgs_feature_backward; Sec. 3.3 Eq. 11, Eq. 12) against the FP64 oracle,
+through the C ABI.
+
+Cosine maps: max |x - ref| / max |ref| <= 1e-4 (the FP32 tolerance of the
+maps; the matrix-core sums are split into high and low bfloat16 parts);
+loss within 1e-5 relative; gradients (features, each parameter tensor)
+<= 1e-3. No pixel decision is taken, so nothing is excluded.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import GRAD_TOL, IMG_TOL, log, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2505_22335_amd.core import FeatureLift
+
+
+def _pack(m):
+    return np.concatenate([m["W1"].ravel(), m["b1"], m["W2"].ravel(), m["b2"]]).astype(np.float32)
+
+
+def _unpack(flat, nh):
+    o = 0
+    out = {}
+    for k, shape in (("W1", (128, 16)), ("b1", (128,)), ("W2", (nh, 128)), ("b2", (nh,))):
+        n = int(np.prod(shape))
+        out[k] = flat[o:o + n].reshape(shape)
+        o += n
+    return out
+
+
+# relative distance of a hidden pre-activation to 0 (oracle.relu_margin) below
+# which FP32 (16 products and a bias, error ~1e-6 of the terms) and FP64 may
+# take the ReLU decision differently
+RELU_BAND = 2e-6
+
+
+def _run(V, H, W, Hp, Wp, nh, seed, backward=True):
+    log("case feature lift", V, H, W, Hp, Wp, nh)
+    m = synth.feature_inputs(seed, V, H, W, Hp, Wp, nh)
+    # guard band of the ReLU decisions: those pixels get zero upstream
+    # gradient on both sides (the forward is continuous and compared everywhere)
+    band = np.stack([oracle.relu_margin(m["feat"][v], m["W1"], m["b1"]) <= RELU_BAND for v in range(V)])
+    log("relu guard band pixels", int(band.sum()), "of", band.size)
+    assert band.sum() <= 1e-3 * band.size + 2
+    m["d_cos"] = np.where(band, 0.0, m["d_cos"]).astype(np.float32)
+    dev = lambda a: torch.as_tensor(a).cuda()
+    fl = FeatureLift(V, W, H, nh, Hp, Wp)
+    params = dev(_pack(m))
+    cos, loss = fl.forward(dev(m["feat"]), params, dev(m["dino"]))
+    torch.cuda.synchronize()
+    for v in range(V):
+        ref = oracle.distill(m["feat"][v], m["W1"], m["b1"], m["W2"], m["b2"], m["dino"][v],
+                             d_cos=m["d_cos"][v] if backward else None)
+        e = rel_err(to_np(cos[v]), ref["cos"])
+        el = abs(float(loss[v]) - ref["loss"]) / max(abs(ref["loss"]), 1e-12)
+        log("feature view %d cos %.2e loss %.2e (gpu %.7f ref %.7f)" % (v, e, el, float(loss[v]), ref["loss"]))
+        assert e <= IMG_TOL and el <= 1e-5
+        if backward:
+            if v == 0:
+                gsum = {k: np.zeros_like(x, dtype=np.float64) for k, x in ref["grads"].items() if k != "feat"}
+            for k in gsum:
+                gsum[k] += ref["grads"][k]
+            if v == 0:
+                refs_feat = []
+            refs_feat.append(ref["grads"]["feat"])
+    if not backward:
+        return
+    d_feat, d_params = fl.backward(dev(m["feat"]), params, dev(m["dino"]), dev(m["d_cos"]))
+    torch.cuda.synchronize()
+    for v in range(V):
+        e = rel_err(to_np(d_feat[v]), refs_feat[v])
+        log("feature view %d d_feat %.2e" % (v, e))
+        assert e <= GRAD_TOL
+    got = _unpack(to_np(d_params), nh)
+    for k in ("W1", "b1", "W2", "b2"):
+        e = rel_err(got[k], gsum[k])
+        log("feature d_%s %.2e" % (k, e))
+        assert e <= GRAD_TOL, k
+    # a second call with the same inputs reproduces the first bit for bit
+    d_feat2, d_params2 = fl.backward(dev(m["feat"]), params, dev(m["dino"]), dev(m["d_cos"]))
+    torch.cuda.synchronize()
+    assert torch.equal(d_feat, d_feat2) and torch.equal(d_params, d_params2)
+
+
+@pytest.mark.parametrize("V,H,W,Hp,Wp,nh", [(1, 37, 53, 3, 4, 48), (2, 64, 80, 5, 6, 384), (1, 16, 16, 1, 1, 40),
+                                             (1, 40, 130, 3, 9, 17), (2, 256, 320, 17, 23, 64)])
+def test_feature_lift_matches_oracle(V, H, W, Hp, Wp, nh):
+    """Ragged tiles, two views, a single patch, a wide strip with an odd
+    channel count, and more tiles than the backward's workgroups (each
+    walks several)."""
+    _run(V, H, W, Hp, Wp, nh, seed=10 + H + W)
+
+
+@pytest.mark.slow
+def test_feature_lift_full_frame():
+    """The 640x480 frame with the 34x46 DINO patch grid and 384 channels."""
+    _run(1, 480, 640, 34, 46, 384, seed=5)
+
+
+def test_feature_lift_rejects_fine_grids():
+    from paper_2505_22335_amd import _lib as L
+    with pytest.raises(L.AsgsError) as ei:
+        FeatureLift(1, 64, 64, 32, 32, 32)
+    assert ei.value.status == L.E_UNSUPPORTED
