@@ -31,21 +31,67 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(I, nvis, N, A, P, nf=16):
+VALU_PEAK_OPS = 39.3e12     # FP32 lane-ops/s without packed math (78.6 TFLOP/s counting an FMA as 2)
+MFMA_PEAK = {"f32": 157.3e12, "bf16": 2.5e15}  # dense FLOP/s
+
+
+def algorithmic_bytes(I, nvis, N, A, P, nf=16, l1=True):
     """Minimum bytes each kernel class must move (per launch), from the
     method's data: per intersection a 2D record (u,v,conic,opacity = 6
     floats) plus channels (rgb, depth, feature), per pixel the outputs or the
-    upstream gradients, per Gaussian its parameters."""
+    upstream gradients, per Gaussian its parameters. With l1, the forward
+    also reads the targets of its ch + 1 outputs and writes their L1
+    gradients (the fused residual of the benchmark step)."""
     ch = 4 + nf
     rec = 4 * (6 + ch)
     return {
-        "blend_fwd": I * rec + I * 4 + P * 4 * (ch + 1 + 2),
+        "blend_fwd": I * rec + I * 4 + P * 4 * (ch + 1 + 2) + (P * 4 * 2 * (ch + 1) if l1 else 0),
         "blend_bwd": I * rec + P * 4 * (ch + 1 + 2) + nvis * rec,
         "project": N * 4 * (3 + 3 + 4 + 1 + 3 + nf) + nvis * rec,
+        "sort": N * 8 + I * 12,
         "project_bwd": nvis * rec + N * 4 * (3 + 3 + 4 + 1) + N * 4 * (3 + 3 + 4 + 1 + 3 + nf),
         "decode": A * 4 * (3 + 32 + 30) + N * 4 * (3 + 3 + 4 + 1 + 3 + nf),
         "decode_bwd": N * 4 * (3 + 3 + 4 + 1 + 3 + nf) + A * 4 * 2 * (3 + 32 + 30),
+        # rendered rgb, depth, opacity sum, cosine, observed rgb and depth in; R, sigma, mask out
+        "residual": P * (4 * (3 + 1 + 1 + 1 + 3 + 1) + 4 + 4 + 1),
     }
+
+
+def algorithmic_ops(A, k, V, N, evals, nf=16, precision=0):
+    """Lower bounds on the arithmetic of each kernel class (per launch):
+    vector lane-op slots (an FMA is one slot, an exponential four) and
+    matrix FLOPs with their type. evals = pixel-Gaussian evaluations the
+    forward performs at least (sum over pixels of the list position of the
+    last composited Gaussian); each needs the offset (2), the conic power
+    (5), the alpha_min test (1) and one exponential (4 slots). The decoder's
+    two layers per head are dense contractions: 2 (32 * 35 + k m 32) FLOPs
+    per anchor and head; its backward is twice that (input and weight
+    gradients). Projection: ~200 lane-ops per (view, Gaussian)."""
+    ms = (1, 3, 3, 4, nf) if nf else (1, 3, 3, 4)
+    dec = A * V * sum(2 * (32 * 35 + k * m * 32) for m in ms)
+    dt = "f32" if precision == 0 else "bf16"
+    return {
+        "blend_fwd": {"valu": 12 * evals},
+        "blend_bwd": {"valu": 12 * evals},
+        "project": {"valu": 200 * N},
+        "project_bwd": {"valu": 400 * N},
+        "decode": {"mfma": dec, "mfma_type": dt},
+        "decode_bwd": {"mfma": 2 * dec, "mfma_type": "f32"},
+    }
+
+
+def roofline_entry(avg_ms, nbytes, ops):
+    """Per-kernel fractions: of HBM (algorithmic bytes / time / 8 TB/s) and of
+    the binding roofline (the largest of the HBM, vector-ALU and matrix-core
+    lower-bound times, over the measured time)."""
+    t = avg_ms * 1e-3
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_valu = ops.get("valu", 0) / VALU_PEAK_OPS
+    t_mfma = ops.get("mfma", 0) / MFMA_PEAK[ops.get("mfma_type", "f32")]
+    bound = max((t_hbm, "hbm"), (t_valu, "valu"), (t_mfma, "mfma"))
+    return {"avg_us": round(avg_ms * 1e3, 2), "alg_bytes": int(nbytes), "valu_ops": int(ops.get("valu", 0)),
+            "mfma_flops": int(ops.get("mfma", 0)), "pct_hbm": round(100 * t_hbm / t, 1) if t > 0 else None,
+            "bound": bound[1], "pct_bound": round(100 * bound[0] / t, 1) if t > 0 else None}
 
 
 def measured_traffic(path=os.path.join(ROOT, "profiles", "blend_bwd_c2s_traffic.md")):
@@ -65,20 +111,51 @@ def measured_traffic(path=os.path.join(ROOT, "profiles", "blend_bwd_c2s_traffic.
     return val if cur == sha else None
 
 
-def cpu_baseline(sc, cam, G, budget_s=30.0):
-    """The FP64 oracle's forward + backward of the same frame on the host."""
+def cpu_baseline(sc, cam, G):
+    """The FP64 oracle's forward + backward of the workload's frame on the
+    host: median of 3 full frames on all the threads torch uses, and median
+    of 3 runs of the frame's central 320x240 quarter (the same rays, a camera
+    with the principal point shifted) on one thread."""
+    import statistics
+
     import torch
 
     import oracle
+    import synth
     from oracle import RenderOpts
     threads = torch.get_num_threads()
-    t0 = time.perf_counter()
-    oracle.render_scene(sc, cam, RenderOpts(n_feat=16), grad_out=G, pose_grad=True)
-    dt = time.perf_counter() - t0
-    mpix = cam.width * cam.height / 1e6
-    return {"value": mpix / dt, "unit": "Mpix/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full {cam.width}x{cam.height} frame, forward+backward incl. decoder and pose "
-                      f"({dt:.1f} s, torch CPU threads={threads})"}
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+
+    def timed(c, g):
+        t0 = time.perf_counter()
+        oracle.render_scene(sc, c, RenderOpts(n_feat=16), grad_out=g, pose_grad=True)
+        return time.perf_counter() - t0
+    full = [timed(cam, G) for _ in range(3)]
+    x0, y0, w, h = cam.width // 4, cam.height // 4, cam.width // 2, cam.height // 2
+    quarter = synth.Camera(w, h, cam.fx, cam.fy, cam.cx - x0, cam.cy - y0, cam.T_wc)
+    Gq = {k: v[..., y0:y0 + h, x0:x0 + w] for k, v in G.items()}
+    torch.set_num_threads(1)
+    try:
+        one = [timed(quarter, Gq) for _ in range(3)]
+    finally:
+        torch.set_num_threads(threads)
+    mpix, mq = cam.width * cam.height / 1e6, w * h / 1e6
+    tf, tq = statistics.median(full), statistics.median(one)
+    return {"value": mpix / tf, "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+            "sample": f"full {cam.width}x{cam.height} frame, forward+backward incl. decoder and pose gradient, "
+                      f"median of 3 on {threads} torch threads",
+            "cpu_model": model, "runs_s": [round(x, 2) for x in full],
+            "one_core": {"value": mq / tq, "unit": "Mpix/s", "cores": 1,
+                         "sample": f"central {w}x{h} quarter of the frame, median of 3 on one thread",
+                         "runs_s": [round(x, 2) for x in one]}}
 
 
 def serving_c5(warmup_s=2.0, measure_s=20.0, burst_s=1.0, seed=5, log=None):
@@ -209,11 +286,10 @@ def main():
     ap.add_argument("--views", type=int, default=1)
     ap.add_argument("--precision", type=int, default=0, help="decoder precision: 0 FP32, 1 BF16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--breakdown", action="store_true", help="also time every kernel class (untimed pass)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
-    ap.add_argument("--serve-seconds", type=float, default=4.0,
-                    help="measured seconds of the serving mix (after 1 s warm-up; 0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="measured seconds of the serving mix (after 2 s warm-up; 0 = skip)")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving mix (2 s warm-up)")
     ap.add_argument("--graph", action="store_true",
                     help="capture one step into a HIP graph and time its replays (checked bitwise against the eager step)")
@@ -321,6 +397,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.precision == 0 else "bf16-decode/f32",
+        "precision": ("FP32 arithmetic throughout, except the blend backward's per-entry sums over pixels: "
+                      "bf16 matrix cores with both operands split into high and low bfloat16 parts "
+                      "(three products, relative error per product below 2^-15)"
+                      + ("" if args.precision == 0 else "; decoder forward on bf16 matrix cores")),
         "data": "synthetic",
         "config": {"workload": wl["desc"] + f", {V} view(s), decoder {'FP32' if args.precision == 0 else 'BF16'}",
                    "anchors": A, "gaussians": N, "views": V, "width": W, "height": H, "n_feat": 16,
@@ -334,24 +414,45 @@ def main():
         "wall_s": round(wall, 3),
         "launch": "hip-graph" if args.graph else "host",
     }
-    if args.breakdown:
-        L.profile_enable((1 << L.K_NUM) - 1 if hasattr(L, "K_NUM") else 0x7F)
-        for _ in range(5):
-            step()
-        torch.cuda.synchronize()
-        names = ["project", "sort", "blend_fwd", "blend_bwd", "project_bwd", "decode", "decode_bwd"]
-        br = {}
-        for c, nm in enumerate(names):
-            t, n = L.profile_read(c)
-            avg = t / max(n, 1)
-            entry = {"avg_ms": round(avg, 5)}
-            if nm in ab:
-                entry["alg_GBs"] = round(ab[nm] / (avg * 1e-3) / 1e9, 1) if avg > 0 else None
-            br[nm] = entry
-        L.profile_enable(0)
-        res["kernels"] = br
+    # every kernel class: mean launch time over extra steps with the
+    # library's per-launch events, algorithmic bytes and operation lower
+    # bounds, fraction of HBM and of the binding roofline
+    evals = int(r.rc.array(L.CTX_NCONTRIB, torch.int32).sum().item())
+    ops = algorithmic_ops(A, r.a.k, V, N * V, evals, precision=args.precision)
+    rm = synth.residual_maps(wl["seed"] + 200, V, H, W)
+    obs = {k: torch.as_tensor(rm[k]).cuda() for k in ("cosine", "obs_rgb", "obs_depth")}
+    res_out = dict(R=torch.empty((V, H, W), device="cuda"), sigma=torch.empty((V, H, W), device="cuda"),
+                   dynamic=torch.empty((V, H, W), dtype=torch.uint8, device="cuda"),
+                   xi=torch.empty(V, device="cuda"),
+                   work=torch.empty(L.residual_work_size(V, W, H), dtype=torch.uint8, device="cuda"))
+    res_maps = L.ResidualMaps()
+    res_maps.rgb, res_maps.depth, res_maps.alpha = (r.images[k].data_ptr() for k in ("rgb", "depth", "alpha"))
+    res_maps.cosine, res_maps.obs_rgb, res_maps.obs_depth = (obs[k].data_ptr() for k in ("cosine", "obs_rgb",
+                                                                                          "obs_depth"))
+    res_opts = L.residual_opts()
+    L.profile_enable((1 << L.K_NUM) - 1)
+    for _ in range(10):
+        step()
+    # the residual kernels are short: a queued delay keeps the device busy
+    # while the host enqueues them, so their events time the kernels alone
+    torch.cuda._sleep(20_000_000)
+    for _ in range(10):
+        L.tracking_residual(V, W, H, res_opts, res_maps, res_out["R"], res_out["sigma"], res_out["dynamic"],
+                            res_out["xi"], res_out["work"])
+    torch.cuda.synchronize()
+    names = ["project", "sort", "blend_fwd", "blend_bwd", "project_bwd", "decode", "decode_bwd", "residual"]
+    br = {}
+    for c, nm in enumerate(names):
+        t, n = L.profile_read(c)
+        if n:
+            br[nm] = roofline_entry(t / n, ab[nm], ops.get(nm, {}))
+    L.profile_enable(0)
+    br["blend_fwd"]["note"] = "includes the fused L1 residual gradient of the step"
+    br["residual"]["note"] = "tracking residual + uncertainty on the step's maps (not part of the timed step)"
+    res["kernels"] = br
+    res["config"]["pixel_evaluations"] = evals
     if args.serve_seconds > 0:
-        res["serving"] = serving_c5(warmup_s=1.0, measure_s=args.serve_seconds)
+        res["serving"] = serving_c5(warmup_s=2.0, measure_s=args.serve_seconds)
     if not args.no_cpu_baseline:
         g_rng = np.random.default_rng(7)  # seeded upstream gradient of the frame's shape
         G = {"rgb": g_rng.normal(size=(3, H, W)), "depth": g_rng.normal(size=(H, W)),
