@@ -5,12 +5,16 @@ Test infrastructure (see the package docstring).
 Each anchor v carries a position x_v, a 32-d feature f_v and k offsets O_vi.
 Its k Gaussians are decoded by five separate two-layer MLPs (opacity, colour,
 scale, rotation, low-dimensional feature), each fed with the anchor feature
-and the unit direction from the camera centre to the anchor (Eq. 8). The
+and the unit direction from the camera centre to the anchor (Eq. 8); the
+scene-variant decoders also take the anchor's distance to the camera centre
+and the temporal embedding l_t = (sin pi t, cos pi t) of the frame time t
+(Sec. 3.3, Temporal Encoding; inputs of Eq. 8 and Eq. 9). The
 feature decoder F_d is Linear -> SoftPlus -> Linear with a 32-wide hidden
 layer (appendix, MLP details); the other four use ReLU as in Scaffold-GS.
 """
 from __future__ import annotations
 
+import math
 from typing import Dict
 
 import torch
@@ -35,14 +39,17 @@ def _bf16(x: torch.Tensor) -> torch.Tensor:
 
 def decode(xyz: torch.Tensor, feat: torch.Tensor, off: torch.Tensor,
            weights: Dict[str, Dict[str, torch.Tensor]], cam_center: torch.Tensor,
-           k: int, l_o: float = 1.0, l_s: float = 0.02, precision: str = "fp64"):
+           k: int, l_o: float = 1.0, l_s: float = 0.02, precision: str = "fp64", t: float = 0.0):
     """Decode anchors into Gaussians.
 
     xyz (A,3), feat (A,32), off (A*k,3) row n = v*k+i; weights[head] =
-    {W1 (32,35), b1 (32), W2 (k*m,32), b2 (k*m)}; cam_center (3,).
+    {W1 (32,in_dim), b1 (32), W2 (k*m,32), b2 (k*m)}; cam_center (3,).
+    The input of every head is X = [f_v (32), delta (3)] for in_dim 35,
+    followed by the distance |x_v - c| for in_dim 36, and by sin(pi t),
+    cos(pi t) as well for in_dim 38 (t the frame time of the view).
     precision 'bf16' rounds the feature-part operands of layer 1 and both
     operands of layer 2 to bfloat16 (what the matrix-core variant feeds its
-    MFMAs); sums, biases, the view-direction part and activations stay exact.
+    MFMAs); sums, biases, the other input columns and activations stay exact.
 
     Returns dict of (N, c) float64 tensors: mean, scale, rot, opacity (N,),
     rgb, [feat].
@@ -51,6 +58,9 @@ def decode(xyz: torch.Tensor, feat: torch.Tensor, off: torch.Tensor,
     D = xyz - cam_center[None, :]
     dist = torch.linalg.norm(D, dim=1, keepdim=True)
     delta = D / dist
+    # the input columns after the anchor feature, by their number
+    lt = torch.tensor([[math.sin(math.pi * t), math.cos(math.pi * t)]], dtype=F64).expand(A, 2)
+    extra = {3: [delta], 4: [delta, dist], 6: [delta, dist, lt]}
     out = {}
     for name, m, act in HEAD_ORDER:
         if name not in weights:
@@ -58,10 +68,13 @@ def decode(xyz: torch.Tensor, feat: torch.Tensor, off: torch.Tensor,
         w = weights[name]
         W1, b1, W2, b2 = w["W1"], w["b1"], w["W2"], w["b2"]
         nf = feat.shape[1]
+        if W1.shape[1] - nf not in extra:
+            raise ValueError("decoder input width must be 35, 36 or 38 (got %d)" % W1.shape[1])
+        rest = torch.cat(extra[W1.shape[1] - nf], 1)
         if precision == "bf16":
-            Z = _bf16(feat) @ _bf16(W1[:, :nf]).T + delta @ W1[:, nf:].T + b1
+            Z = _bf16(feat) @ _bf16(W1[:, :nf]).T + rest @ W1[:, nf:].T + b1
         else:
-            Z = torch.cat([feat, delta], 1) @ W1.T + b1
+            Z = torch.cat([feat, rest], 1) @ W1.T + b1
         H = torch.relu(Z) if act == "relu" else F.softplus(Z, beta=1.0, threshold=1e9)
         if precision == "bf16":
             Y = _bf16(H) @ _bf16(W2).T + b2

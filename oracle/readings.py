@@ -41,6 +41,9 @@ READINGS = (
     "Five separate head MLPs in->32->k*m (opacity, colour, scale, rotation with ReLU; feature with "
     "SoftPlus); outputs: opacity=sigmoid, colour=sigmoid, scale=l_s*sigmoid, rotation raw, feature raw.",
     "Decoder input is [anchor feature (32), unit view direction (3)] (35 wide); mean = x_v + l_o*O_vi.",
+    "Scene-variant decoders append the anchor-camera distance |x_v - c| (unnormalised, metres; 36 wide) "
+    "and then the temporal embedding (sin pi t, cos pi t) (38 wide) to every head's input; t is the "
+    "frame time of the view, given by the caller.",
     "Pose gradient is w.r.t. xi=(rho,phi) under T_cw <- Exp(xi) T_cw and includes the camera-centre "
     "path through the decoder's view direction.",
     "A Gaussian is culled when o <= alpha_min (no pixel can reach alpha_min), when t_z <= znear, "

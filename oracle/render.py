@@ -190,7 +190,7 @@ def render_scene(scene, cam, opts: RenderOpts, grad_out=None, pose_grad=False,
         lv.weights = {h: {k: _t(v, need) for k, v in w.items()} for h, w in scene.weights.items()}
         c = camera_center(R_cw, t_cw)
         g = decode(lv.anchor["xyz"], lv.anchor["feat"], lv.anchor["off"], lv.weights, c,
-                   scene.k, scene.l_o, scene.l_s, precision=precision)
+                   scene.k, scene.l_o, scene.l_s, precision=precision, t=getattr(cam, "t", 0.0))
         if need:
             for v in g.values():
                 v.retain_grad()

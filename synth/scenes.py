@@ -40,10 +40,11 @@ class Camera:
     cx: float
     cy: float
     T_wc: np.ndarray  # (3, 4) float32, camera-to-world, row-major
+    t: float = 0.0    # frame time (the temporal embedding of the scene-variant decoder)
 
     def copy_with(self, T_wc: np.ndarray) -> "Camera":
         return Camera(self.width, self.height, self.fx, self.fy, self.cx, self.cy,
-                      np.ascontiguousarray(T_wc, dtype=np.float32))
+                      np.ascontiguousarray(T_wc, dtype=np.float32), self.t)
 
 
 @dataclass

@@ -144,3 +144,74 @@ def test_bf16_mode_rounds_exactly_the_matrix_operands():
                 (1 + 0.25 * u) * (1 + 0.75 * u)]
     assert g16["rot"][0].tolist() == expect16
     assert torch.allclose(g64["rot"][0], torch.tensor(expect64, dtype=F64), rtol=0, atol=1e-15)
+
+
+def _widen(w, n_extra, rng=None):
+    """Head weights with n_extra more first-layer columns (zero, or random)."""
+    out = {}
+    for h, d in w.items():
+        e = torch.zeros((d["W1"].shape[0], n_extra), dtype=F64) if rng is None else \
+            torch.as_tensor(rng.uniform(-0.3, 0.3, (d["W1"].shape[0], n_extra)))
+        out[h] = dict(d, W1=torch.cat([d["W1"], e], 1))
+    return out
+
+
+def test_extra_inputs_with_zero_weights_reduce_to_base_decoder():
+    """Distance and temporal columns with zero weights leave every output of
+    the 35-input decoder unchanged (both precisions, any frame time)."""
+    sc = synth.tiny_anchor_scene(3, 9, k=2, n_feat=16)
+    xyz, feat, off, w = _tens(sc)
+    c = torch.tensor([0.3, -0.1, -0.4], dtype=F64)
+    for prec in ("fp64", "bf16"):
+        base = decode(xyz, feat, off, w, c, sc.k, sc.l_o, sc.l_s, precision=prec)
+        for n_extra in (1, 3):
+            g = decode(xyz, feat, off, _widen(w, n_extra), c, sc.k, sc.l_o, sc.l_s, precision=prec, t=0.37)
+            for key in base:
+                assert torch.equal(g[key], base[key]), (prec, n_extra, key)
+
+
+def test_distance_and_time_hand_case():
+    """One anchor at (3, 4, 0) from a camera at the origin (distance 5), one
+    opacity hidden unit fed by the distance (weight 1), sin(pi t) (weight 2)
+    and cos(pi t) (weight 4) at t = 1/3: z = 5 + sqrt(3) + 2, and the second
+    layer passes the unit through, so opacity = sigmoid(7 + sqrt(3))."""
+    xyz = torch.tensor([[3.0, 4.0, 0.0]], dtype=F64)
+    feat = torch.zeros((1, 32), dtype=F64)
+    off = torch.zeros((1, 3), dtype=F64)
+    w = {}
+    for name, m, _ in HEAD_ORDER[:4]:
+        W1 = torch.zeros((32, 38), dtype=F64)
+        W2 = torch.zeros((m, 32), dtype=F64)
+        if name == "opacity":
+            W1[0, 35], W1[0, 36], W1[0, 37] = 1.0, 2.0, 4.0
+            W2[0, 0] = 1.0
+        w[name] = dict(W1=W1, b1=torch.zeros(32, dtype=F64), W2=W2, b2=torch.zeros(m, dtype=F64))
+    g = decode(xyz, feat, off, w, torch.zeros(3, dtype=F64), 1, t=1.0 / 3.0)
+    assert abs(float(g["opacity"][0]) - _sig(7.0 + math.sqrt(3.0))) < 1e-15
+    # only the distance column: the unit reads 5 for any t
+    w["opacity"]["W1"][0, 36:] = 0.0
+    g = decode(xyz, feat, off, w, torch.zeros(3, dtype=F64), 1, t=0.8)
+    assert abs(float(g["opacity"][0]) - _sig(5.0)) < 1e-15
+
+
+def test_time_embedding_folds_into_bias_and_is_periodic():
+    """At t = 1/2 the embedding is (1, 0): the 38-input decoder equals the
+    36-input one with b1 + W1[:, 36]; at t = 1 it is (0, -1). Frames two
+    time units apart share their embedding."""
+    sc = synth.tiny_anchor_scene(4, 11, k=3, n_feat=16)
+    xyz, feat, off, w = _tens(sc)
+    rng = np.random.default_rng(5)
+    w38 = _widen(w, 3, rng)
+    c = torch.tensor([-0.2, 0.5, 0.1], dtype=F64)
+    for t, col, sgn in ((0.5, 36, 1.0), (1.0, 37, -1.0)):
+        w36 = {h: dict(d, W1=d["W1"][:, :36], b1=d["b1"] + sgn * d["W1"][:, col]) for h, d in w38.items()}
+        g38 = decode(xyz, feat, off, w38, c, sc.k, sc.l_o, sc.l_s, t=t)
+        g36 = decode(xyz, feat, off, w36, c, sc.k, sc.l_o, sc.l_s)
+        for key in g36:
+            assert (g38[key] - g36[key]).abs().max() < 1e-14, (t, key)
+    g0 = decode(xyz, feat, off, w38, c, sc.k, sc.l_o, sc.l_s, t=0.3)
+    g2 = decode(xyz, feat, off, w38, c, sc.k, sc.l_o, sc.l_s, t=2.3)
+    for key in g0:
+        assert (g0[key] - g2[key]).abs().max() < 1e-13
+    with np.testing.assert_raises(ValueError):
+        decode(xyz, feat, off, _widen(w, 2), c, sc.k)
