@@ -21,6 +21,10 @@ in float64 with PyTorch CPU ops:
 * ``feature``     the feature lift F_m and the cosine distillation loss
                   (Sec. 3.3, Eq. 11 and Eq. 12);
 * ``anchors``     the probabilistic anchor update (Sec. 3.3, Eq. 7);
+* ``mapping``     the mapping losses: SSIM geometric loss (Sec. 3.1, Eq. 4),
+                  the uncertainty MLP F_u and its loss (Sec. 3.2 Eq. 5,
+                  Sec. 3.3 Eq. 13), the motion mask and the total loss with
+                  the mean-scale term (Sec. 3.3, Eq. 14);
 * ``render``      the whole path, with the backward pass as the vector-Jacobian
                   product of the forward definition (torch autograd in float64)
                   and the SE(3) pose gradient.
@@ -29,7 +33,8 @@ Readings of the paper where it is silent are listed in ``oracle.readings``.
 Parity pins (closed forms, invariants, brute force, finite differences) live
 in ``tests/test_oracle_*.py``.
 """
-from .readings import RenderOpts, READINGS, RESIDUAL_READINGS, FEATURE_READINGS, ANCHOR_READINGS  # noqa: F401
+from .readings import (RenderOpts, READINGS, RESIDUAL_READINGS, FEATURE_READINGS, ANCHOR_READINGS,  # noqa: F401
+                       MAPPING_READINGS)
 from .geometry import quat_to_rotmat, se3_exp, pose_cw, camera_center  # noqa: F401
 from .decode import decode, HEAD_ORDER  # noqa: F401
 from .project import project  # noqa: F401
@@ -39,3 +44,5 @@ from .render import render, render_scene, gaussians_from_plain, Leaves  # noqa: 
 from .uncertainty import box3, cosine, residual, uncertainty, RESIDUAL_WEIGHTS  # noqa: F401
 from .feature import upsample, lift, cosine_map, distill, relu_margin  # noqa: F401
 from .anchors import anchor_update  # noqa: F401
+from .mapping import (gaussian_filter, ssim_map, pixel_loss, mapping_loss, mean_scale,  # noqa: F401
+                      uncertainty_mlp, uncertainty_loss, MAPPING_WEIGHTS)

@@ -92,3 +92,25 @@ ANCHOR_READINGS = (
     "Clamping bounds and the pruning level are not stated: options, by default no clamping [0, 1] and no "
     "pruning.",
 )
+
+
+# Readings for the mapping losses (Sec. 3.1 Eq. 4, Sec. 3.2 Eq. 5, Sec. 3.3 Eq. 13 and Eq. 14).
+MAPPING_READINGS = (
+    "The appendix lists five values {0.8, 0.6, 1.0, 0.4, 0.01} for six names {lambda, lambda_1 .. lambda_5}: "
+    "they are read in order (lambda 0.8, lambda_1 0.6, lambda_2 1.0, lambda_3 0.4, lambda_4 0.01) and "
+    "lambda_5, left without a value, is an option with default 0.01.",
+    "The squared norms of Eq.4 are per pixel (the colour one summed over the three channels) and the loss "
+    "is their mean over the pixels; SSIM(C~, C) is the mean over channels and pixels of the structural-"
+    "similarity map with the vanilla 3DGS window: 11 x 11 Gaussian, sigma 1.5, zero padding, "
+    "C1 = 0.01^2, C2 = 0.03^2.",
+    "Eq.14 writes M(L_g + lambda_4 L_d) with M = [2 sigma^2 > 1] true on dynamic pixels; the loss is read as "
+    "gating out the dynamic pixels, i.e. weighting each pixel's terms by 1 - M, then averaging over all "
+    "pixels.",
+    "s_bar is the mean over Gaussians and axes of the linear (post-activation) scale.",
+    "F_u (Conv -> ReLU -> Conv -> SoftPlus, hidden 128) is a per-pixel MLP N_h -> 128 -> 1 on the DINO "
+    "feature bilinearly upsampled to the pixel (the F of Eq.12); sigma = sigma_min + its output with "
+    "sigma_min = 1e-3, which keeps L_u bounded below where R = 0.",
+    "R in Eq.5 is the residual of Eq.6 (the same weights as tracking), taken as a constant: L_u's "
+    "gradient reaches only F_u's parameters, L's only the Gaussians (and F_m), which is how the two "
+    "gradient flows are kept separate; M is formed from F_u's sigma before F_u's update.",
+)
