@@ -73,6 +73,8 @@ typedef struct asgs_camera {
   int32_t width, height;   /* pixels, 1..16384 each */
   float fx, fy, cx, cy;    /* focal lengths and principal point, pixels */
   float T_wc[12];          /* row-major 3x4 camera-to-world pose (Sec. 3.1) */
+  float t;                 /* frame time of the view (finite); read only by decoders with the
+                              temporal input (in_dim 38, Sec. 3.3 Temporal Encoding) */
 } asgs_camera;
 
 /* Rasteriser constants. asgs_render_opts_default fills the values the paper's
@@ -204,15 +206,21 @@ int asgs_ctx_array(const asgs_camera* cams, int32_t n_views, int64_t n_gauss,
  *
  * Each anchor v has a position x_v, a 32-d feature f_v and k offsets O_vi.
  * Input X_v = [f_v (32), delta_v (3)], delta_v = (x_v - c)/|x_v - c|, c the
- * camera centre of the view. Five heads h in the order opacity(m=1),
- * rgb(3), scale(3), rot(4), feat(n_feat): Y_h = W2_h act_h(W1_h X + b1_h) + b2_h,
- * act = ReLU for the first four, SoftPlus for feat; W1_h is [32][35], W2_h is
- * [k*m_h][32]. Gaussian n = v*k + i gets opacity sigmoid(Y[i]), rgb
+ * camera centre of the view (in_dim 35); the scene-variant decoders append
+ * the distance |x_v - c| (in_dim 36) and then the temporal embedding
+ * (sin pi t, cos pi t) of the camera's frame time t (in_dim 38; Sec. 3.3,
+ * Temporal Encoding). Five heads h in the order opacity(m=1), rgb(3),
+ * scale(3), rot(4), feat(n_feat): Y_h = W2_h act_h(W1_h X + b1_h) + b2_h,
+ * act = ReLU for the first four, SoftPlus for feat; W1_h is [32][in_dim],
+ * W2_h is [k*m_h][32]. Gaussian n = v*k + i gets opacity sigmoid(Y[i]), rgb
  * sigmoid(Y[3i..]), scale l_s * sigmoid(Y[3i..]), rot Y[4i..], feat
  * Y[16i..], mean x_v + l_o * O_vi.
  *
  * Parameters of all heads live in one float array, per head in the order
- * above: W1 (32*35, row-major), b1 (32), W2 (k*m*32, row-major), b2 (k*m).
+ * above: W1's first 35 columns (32*35, row-major), b1 (32), W2 (k*m*32,
+ * row-major), b2 (k*m), then W1's remaining in_dim - 35 columns (32 rows of
+ * in_dim - 35, row-major; nothing for in_dim 35). The 35-input parameters
+ * are thus a prefix of each head's block.
  * ------------------------------------------------------------------------- */
 
 typedef struct asgs_decoder {
@@ -224,7 +232,8 @@ typedef struct asgs_decoder {
                               backward always recomputes and differentiates in FP32. */
   float l_o;               /* offset scale (metres) */
   float l_s;               /* scale bound (metres) */
-  int32_t reserved;        /* must be 0 */
+  int32_t in_dim;          /* head input width: 35 (or 0, the same), 36 (+ distance) or 38 (+ distance
+                              and temporal embedding); others ASGS_E_UNSUPPORTED */
 } asgs_decoder;
 
 /* Number of floats of the packed head parameters. */
@@ -422,6 +431,91 @@ int asgs_anchor_update(int64_t n_anchors, const asgs_anchor_update_opts* opts, c
                        uint8_t* keep, int64_t* n_keep, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Mapping loss (UP-SLAM Sec. 3.1 Eq. 4, Sec. 3.3 Eq. 14) and its gradient
+ * w.r.t. the rendered maps, in one call. Per view of width x height pixels:
+ *   l_p = (1 - M_p) [ lam1 (lam |C~_p - C_p|^2 + (1 - lam)(1 - SSIM_p))
+ *                     + lam2 (D~_p - D_p)^2 + lam4 (1 - cos_p) ]
+ *   loss[v] = sum_p l_p / (width * height)
+ * |.|^2 sums the three colour channels; SSIM_p is the mean over the channels
+ * of the structural-similarity map (11 x 11 Gaussian window, sigma 1.5, zero
+ * padding, C1 = 0.01^2, C2 = 0.03^2); cos_p is the distillation cosine of
+ * Eq. 12 (asgs_feature_forward); M_p = dynamic[p] != 0 (the motion mask,
+ * e.g. from asgs_uncertainty). The mean-scale term of Eq. 14 is
+ * asgs_mean_scale. Maps are packed per view like asgs_images: rgb and
+ * obs_rgb [V][3][H][W], the others [V][H][W] (device). Outputs (device,
+ * overwritten, each may be NULL): loss [V], d_rgb [V][3][H][W], d_depth and
+ * d_cos [V][H][W]; a NULL cosine drops the lam4 term (d_cos must then be
+ * NULL). work holds asgs_mapping_work_size bytes (the SSIM backward maps and
+ * the loss partials). Deterministic: fixed-order sums.
+ * ------------------------------------------------------------------------- */
+typedef struct asgs_mapping_opts {
+  float lam;          /* 0.8: share of the squared colour error against 1 - SSIM */
+  float lam1;         /* 0.6: colour weight */
+  float lam2;         /* 1.0: depth weight */
+  float lam4;         /* 0.01: distillation weight */
+  int32_t reserved;   /* must be 0 */
+} asgs_mapping_opts;
+
+typedef struct asgs_mapping_maps {
+  const float* rgb;        /* rendered colour */
+  const float* depth;      /* rendered depth */
+  const float* obs_rgb;    /* observed colour */
+  const float* obs_depth;  /* observed depth */
+  const float* cosine;     /* cos(F, F^) per pixel, or NULL */
+  const uint8_t* dynamic;  /* motion mask (nonzero: dynamic, excluded), or NULL (all static) */
+} asgs_mapping_maps;
+
+void asgs_mapping_opts_default(asgs_mapping_opts* opts);
+int asgs_mapping_work_size(int32_t n_views, int32_t width, int32_t height, size_t* bytes);
+int asgs_mapping_loss(int32_t n_views, int32_t width, int32_t height, const asgs_mapping_opts* opts,
+                      const asgs_mapping_maps* maps, float* loss, float* d_rgb, float* d_depth, float* d_cos,
+                      void* work, size_t work_bytes, void* stream);
+
+/* Mean-scale term s_bar of Eq. 14: *value = mean of scale[0 .. count) (device
+ * float, may be NULL) and, if d_scale is not NULL, d_scale[i] += lam5 / count
+ * (the gradient of lam5 s_bar; call after the render backward that writes
+ * d_scale). scale is the flat [3][n] (or all views') linear scale array.
+ * work holds asgs_mean_scale_work_size bytes. */
+int asgs_mean_scale_work_size(size_t* bytes);
+int asgs_mean_scale(int64_t count, const float* scale, float lam5, float* value, float* d_scale, void* work,
+                    size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Uncertainty MLP F_u, its loss L_u and the motion mask (UP-SLAM Sec. 3.2
+ * Eq. 5, Sec. 3.3 Eq. 13). Per pixel p of a view, with F_p the DINO feature
+ * upsampled bilinearly from the patch grid as for the feature lift:
+ *   sigma_p = sigma_min + softplus(w2 . relu(W1 F_p + b1) + b2)
+ *   dynamic_p = (2 sigma_p^2 > 1)                       (the motion mask M)
+ *   loss[v] = mean_p R_p / (2 sigma_p^2) + lam3 log sigma_p   (L_u)
+ * R is the residual of Eq. 6 (asgs_tracking_residual) and is held constant:
+ * d_params receives dL_u/d(F_u parameters) summed over the views, and no
+ * gradient flows to the rendered maps (the mapping loss trains the Gaussians
+ * with the mask as a constant; the two gradient flows stay separate).
+ *
+ * params (device, packed): W1 [128][n_high] row-major, b1 [128], w2 [128],
+ * b2 [1] (asgs_uncertainty_param_count floats). dino [V][n_high][grid_h]
+ * [grid_w]; R, sigma [V][H][W] float; dynamic [V][H][W] uint8; loss [V];
+ * every output may be NULL; R is required for loss and d_params. Grids as
+ * for the feature lift (a 16 x 16 pixel tile reaches at most 4 x 4 patches,
+ * else ASGS_E_UNSUPPORTED); n_high a multiple of 16 in 16..2048.
+ * ------------------------------------------------------------------------- */
+typedef struct asgs_uncertainty_mlp {
+  int32_t n_high;      /* N_h, DINO feature channels */
+  int32_t grid_h;      /* patch rows */
+  int32_t grid_w;      /* patch columns */
+  float sigma_min;     /* floor added to the SoftPlus output: 1e-3 */
+  float lam3;          /* weight of log sigma in L_u: 0.4 */
+  int32_t reserved;    /* must be 0 */
+} asgs_uncertainty_mlp;
+
+int asgs_uncertainty_param_count(const asgs_uncertainty_mlp* u, int64_t* count);
+int asgs_uncertainty_workspace_size(const asgs_uncertainty_mlp* u, int32_t n_views, int32_t width, int32_t height,
+                                    size_t* bytes);
+int asgs_uncertainty(const asgs_uncertainty_mlp* u, int32_t n_views, int32_t width, int32_t height,
+                     const float* params, const float* dino, const float* R, float* sigma, uint8_t* dynamic,
+                     float* loss, float* d_params, void* work, size_t work_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Timing hook (for measurement tools; off by default)
  *
  * While a kernel class is enabled, each launch of it made by this library is
@@ -440,7 +534,9 @@ enum {
   ASGS_K_RESIDUAL = 7,     /* tracking residual and uncertainty (one kernel + the per-view mean) */
   ASGS_K_FEATURE = 8,      /* feature lift forward (weight and patch preparation + per-pixel kernel) */
   ASGS_K_FEATURE_BWD = 9,  /* feature lift backward (preparation, per-pixel kernel, reductions) */
-  ASGS_K_NUM = 10
+  ASGS_K_MAPPING = 10,     /* mapping loss with SSIM and its gradient (two stencil kernels + the mean) */
+  ASGS_K_UNCERTAINTY = 11, /* uncertainty MLP, its loss and parameter gradient */
+  ASGS_K_NUM = 12
 };
 /* Enable the classes whose bit (1 << class) is set in mask; 0 disables all.
  * Clears earlier measurements. */

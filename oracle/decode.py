@@ -17,6 +17,7 @@ from __future__ import annotations
 import math
 from typing import Dict
 
+import numpy as np
 import torch
 import torch.nn.functional as F
 
@@ -91,3 +92,40 @@ def decode(xyz: torch.Tensor, feat: torch.Tensor, off: torch.Tensor,
     if "feat" in out:
         g["feat"] = out["feat"]
     return g
+
+
+def bf16_hidden_margin(xyz: torch.Tensor, feat: torch.Tensor, weights: Dict[str, Dict[str, torch.Tensor]],
+                       cam_center: torch.Tensor, t: float = 0.0):
+    """Guard band of the bfloat16 variant's one computed operand: the hidden
+    activations H are rounded to bfloat16 after a single-precision first
+    layer, so an H within that layer's rounding of a bfloat16 rounding
+    midpoint may round either way. Per head, per anchor: the minimum over
+    the 32 hidden units of |H - nearest midpoint| / (sum of |terms| of Z),
+    with H and Z as in the bf16 mode above (inf where H = 0). Returns
+    {head: (A,) float64 numpy array}."""
+    A = xyz.shape[0]
+    D = xyz - cam_center[None, :]
+    dist = torch.linalg.norm(D, dim=1, keepdim=True)
+    delta = D / dist
+    lt = torch.tensor([[math.sin(math.pi * t), math.cos(math.pi * t)]], dtype=F64).expand(A, 2)
+    extra = {3: [delta], 4: [delta, dist], 6: [delta, dist, lt]}
+    out = {}
+    for name, m, act in HEAD_ORDER:
+        if name not in weights:
+            continue
+        W1, b1 = weights[name]["W1"].detach(), weights[name]["b1"].detach()
+        nf = feat.shape[1]
+        rest = torch.cat(extra[W1.shape[1] - nf], 1).detach()
+        f16, w16 = _bf16(feat.detach()), _bf16(W1[:, :nf])
+        Z = f16 @ w16.T + rest @ W1[:, nf:].T + b1
+        scale = f16.abs() @ w16.abs().T + rest.abs() @ W1[:, nf:].abs().T + b1.abs()
+        H = torch.relu(Z) if act == "relu" else F.softplus(Z, beta=1.0, threshold=1e9)
+        Hn = H.numpy()
+        with np.errstate(divide="ignore"):
+            e = np.floor(np.log2(np.abs(Hn)))
+        ulp = np.exp2(e - 7)  # spacing of bfloat16 values around H (8 significant bits)
+        q = np.abs(Hn) / np.where(Hn != 0, ulp, 1.0)
+        d = np.abs((q - np.floor(q)) - 0.5) * ulp
+        marg = np.where(Hn != 0, d / np.maximum(scale.numpy(), 1e-300), np.inf)
+        out[name] = marg.min(axis=1)
+    return out

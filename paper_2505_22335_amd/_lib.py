@@ -29,8 +29,8 @@ lib = C.CDLL(LIB_PATH)
 OK, E_INVALID, E_WORKSPACE, E_CAPACITY, E_DEVICE, E_UNSUPPORTED = range(6)
 MAX_VIEWS = 64
 (K_PROJECT, K_SORT, K_BLEND_FWD, K_BLEND_BWD, K_PROJECT_BWD, K_DECODE, K_DECODE_BWD, K_RESIDUAL, K_FEATURE,
- K_FEATURE_BWD) = range(10)
-K_NUM = 10
+ K_FEATURE_BWD, K_MAPPING, K_UNCERTAINTY) = range(12)
+K_NUM = 12
 (CTX_PAIR_TILE, CTX_PAIR_GAUSS, CTX_TILE_RANGE, CTX_RECT, CTX_NCONTRIB, CTX_TFINAL, CTX_GEOM, CTX_RADIUS,
  CTX_DEPTH_KEY, CTX_NTILES) = range(1, 11)
 
@@ -44,7 +44,7 @@ class AsgsError(RuntimeError):
 
 class Camera(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
-                ("cx", C.c_float), ("cy", C.c_float), ("T_wc", C.c_float * 12)]
+                ("cx", C.c_float), ("cy", C.c_float), ("T_wc", C.c_float * 12), ("t", C.c_float)]
 
 
 class RenderOpts(C.Structure):
@@ -67,7 +67,7 @@ class Images(C.Structure):
 class Decoder(C.Structure):
     _fields_ = [("n_anchors", C.c_int64), ("k", C.c_int32), ("n_feat", C.c_int32),
                 ("precision", C.c_int32), ("l_o", C.c_float), ("l_s", C.c_float),
-                ("reserved", C.c_int32)]
+                ("in_dim", C.c_int32)]
 
 
 class L1Targets(C.Structure):
@@ -92,6 +92,21 @@ class FeatureLift(C.Structure):
 class AnchorUpdateOpts(C.Structure):
     _fields_ = [("prior", C.c_float), ("p_min", C.c_float), ("p_max", C.c_float), ("prune_below", C.c_float),
                 ("reserved", C.c_int32)]
+
+
+class MappingOpts(C.Structure):
+    _fields_ = [("lam", C.c_float), ("lam1", C.c_float), ("lam2", C.c_float), ("lam4", C.c_float),
+                ("reserved", C.c_int32)]
+
+
+class MappingMaps(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("obs_rgb", C.c_void_p), ("obs_depth", C.c_void_p),
+                ("cosine", C.c_void_p), ("dynamic", C.c_void_p)]
+
+
+class UncertaintyMlp(C.Structure):
+    _fields_ = [("n_high", C.c_int32), ("grid_h", C.c_int32), ("grid_w", C.c_int32), ("sigma_min", C.c_float),
+                ("lam3", C.c_float), ("reserved", C.c_int32)]
 
 
 P = C.c_void_p
@@ -138,6 +153,17 @@ _sigs = {
     "asgs_feature_backward": (C.c_int, [C.POINTER(FeatureLift), C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P,
                                         P, C.c_size_t, P]),
     "asgs_anchor_update": (C.c_int, [C.c_int64, C.POINTER(AnchorUpdateOpts), P, P, P, P, P]),
+    "asgs_mapping_opts_default": (None, [C.POINTER(MappingOpts)]),
+    "asgs_mapping_work_size": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "asgs_mapping_loss": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(MappingOpts), C.POINTER(MappingMaps),
+                                    P, P, P, P, P, C.c_size_t, P]),
+    "asgs_mean_scale_work_size": (C.c_int, [C.POINTER(C.c_size_t)]),
+    "asgs_uncertainty_param_count": (C.c_int, [C.POINTER(UncertaintyMlp), C.POINTER(C.c_int64)]),
+    "asgs_uncertainty_workspace_size": (C.c_int, [C.POINTER(UncertaintyMlp), C.c_int32, C.c_int32, C.c_int32,
+                                                  C.POINTER(C.c_size_t)]),
+    "asgs_uncertainty": (C.c_int, [C.POINTER(UncertaintyMlp), C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P,
+                                   P, C.c_size_t, P]),
+    "asgs_mean_scale": (C.c_int, [C.c_int64, P, C.c_float, P, P, P, C.c_size_t, P]),
     "asgs_profile_enable": (C.c_int, [C.c_uint32]),
     "asgs_profile_read": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
@@ -178,7 +204,8 @@ def _ptr(t) -> Optional[int]:
 # ---------------------------------------------------------------------------
 
 def make_cameras(cams: Sequence) -> "C.Array":
-    """Objects with width, height, fx, fy, cx, cy, T_wc (3x4) -> Camera[]."""
+    """Objects with width, height, fx, fy, cx, cy, T_wc (3x4) and optionally
+    t (frame time, default 0) -> Camera[]."""
     arr = (Camera * len(cams))()
     for i, c in enumerate(cams):
         arr[i].width, arr[i].height = int(c.width), int(c.height)
@@ -186,6 +213,7 @@ def make_cameras(cams: Sequence) -> "C.Array":
         T = [float(x) for row in c.T_wc for x in row]
         for k in range(12):
             arr[i].T_wc[k] = T[k]
+        arr[i].t = float(getattr(c, "t", 0.0))
     return arr
 
 
@@ -286,9 +314,10 @@ def ctx_array(cams, n_gauss: int, opts: RenderOpts, ctx, which: int):
 
 
 def make_decoder(n_anchors: int, k: int, n_feat: int = 16, precision: int = 0, l_o: float = 1.0,
-                 l_s: float = 0.02) -> Decoder:
+                 l_s: float = 0.02, in_dim: int = 35) -> Decoder:
     d = Decoder()
-    d.n_anchors, d.k, d.n_feat, d.precision, d.l_o, d.l_s, d.reserved = n_anchors, k, n_feat, precision, l_o, l_s, 0
+    d.n_anchors, d.k, d.n_feat, d.precision, d.l_o, d.l_s = n_anchors, k, n_feat, precision, l_o, l_s
+    d.in_dim = in_dim
     return d
 
 
@@ -398,6 +427,65 @@ def anchor_update(p_obs, p, keep=None, n_keep=None, prior=0.5, p_min=0.0, p_max=
     o.prior, o.p_min, o.p_max, o.prune_below, o.reserved = prior, p_min, p_max, prune_below, 0
     check(lib.asgs_anchor_update(p.numel(), C.byref(o), p_obs.data_ptr(), p.data_ptr(), _ptr(keep), _ptr(n_keep),
                                  _stream(stream)), "asgs_anchor_update")
+
+
+def mapping_opts(**kw) -> MappingOpts:
+    o = MappingOpts()
+    lib.asgs_mapping_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mapping_work_size(n_views: int, width: int, height: int) -> int:
+    b = C.c_size_t()
+    check(lib.asgs_mapping_work_size(n_views, width, height, C.byref(b)), "asgs_mapping_work_size")
+    return b.value
+
+
+def mapping_loss(n_views: int, width: int, height: int, opts: MappingOpts, maps: MappingMaps, loss=None, d_rgb=None,
+                 d_depth=None, d_cos=None, work=None, stream=None):
+    check(lib.asgs_mapping_loss(n_views, width, height, C.byref(opts), C.byref(maps), _ptr(loss), _ptr(d_rgb),
+                                _ptr(d_depth), _ptr(d_cos), _ptr(work), 0 if work is None else work.numel(),
+                                _stream(stream)), "asgs_mapping_loss")
+
+
+def mean_scale_work_size() -> int:
+    b = C.c_size_t()
+    check(lib.asgs_mean_scale_work_size(C.byref(b)), "asgs_mean_scale_work_size")
+    return b.value
+
+
+def mean_scale(scale, lam5: float, value=None, d_scale=None, work=None, stream=None):
+    check(lib.asgs_mean_scale(scale.numel(), scale.data_ptr(), lam5, _ptr(value), _ptr(d_scale), _ptr(work),
+                              0 if work is None else work.numel(), _stream(stream)), "asgs_mean_scale")
+
+
+def uncertainty_mlp(n_high: int, grid_h: int, grid_w: int, sigma_min: float = 1e-3,
+                    lam3: float = 0.4) -> UncertaintyMlp:
+    u = UncertaintyMlp()
+    u.n_high, u.grid_h, u.grid_w, u.sigma_min, u.lam3, u.reserved = n_high, grid_h, grid_w, sigma_min, lam3, 0
+    return u
+
+
+def uncertainty_param_count(u: UncertaintyMlp) -> int:
+    n = C.c_int64()
+    check(lib.asgs_uncertainty_param_count(C.byref(u), C.byref(n)), "asgs_uncertainty_param_count")
+    return n.value
+
+
+def uncertainty_workspace_size(u: UncertaintyMlp, n_views: int, width: int, height: int) -> int:
+    b = C.c_size_t()
+    check(lib.asgs_uncertainty_workspace_size(C.byref(u), n_views, width, height, C.byref(b)),
+          "asgs_uncertainty_workspace_size")
+    return b.value
+
+
+def uncertainty(u: UncertaintyMlp, n_views: int, width: int, height: int, params, dino, R=None, sigma=None,
+                dynamic=None, loss=None, d_params=None, work=None, stream=None):
+    check(lib.asgs_uncertainty(C.byref(u), n_views, width, height, params.data_ptr(), dino.data_ptr(), _ptr(R),
+                               _ptr(sigma), _ptr(dynamic), _ptr(loss), _ptr(d_params), _ptr(work),
+                               0 if work is None else work.numel(), _stream(stream)), "asgs_uncertainty")
 
 
 def profile_enable(mask: int):

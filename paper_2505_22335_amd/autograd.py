@@ -40,6 +40,7 @@ class PinholeCamera:
     cx: float
     cy: float
     T_wc: np.ndarray  # (3, 4) camera -> world, row-major
+    t: float = 0.0    # frame time (temporal decoder input)
 
 
 def hat(w) -> np.ndarray:
@@ -86,7 +87,7 @@ def T_cw_of(cam) -> np.ndarray:
 def camera_at(cam, T_cw: np.ndarray) -> PinholeCamera:
     T_wc = np.linalg.inv(T_cw)[:3, :]
     return PinholeCamera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx),
-                         float(cam.cy), np.ascontiguousarray(T_wc, dtype=np.float32))
+                         float(cam.cy), np.ascontiguousarray(T_wc, dtype=np.float32), float(getattr(cam, "t", 0.0)))
 
 
 class TrackedRenderer:

@@ -27,33 +27,43 @@ def gaussians_to_device(planes: Dict[str, object], device="cuda") -> Dict[str, t
 
 def pack_params(weights: Dict[str, Dict[str, object]], k: int, n_feat: int = 16, device="cuda") -> torch.Tensor:
     """Head weights {head: {W1, b1, W2, b2}} -> the packed parameter vector of
-    the decoder ABI (per head in order opacity, rgb, scale, rot, feat: W1
-    row-major, b1, W2 row-major, b2)."""
+    the decoder ABI (per head in order opacity, rgb, scale, rot, feat: the
+    first 35 columns of W1 row-major, b1, W2 row-major, b2, then W1's other
+    in_dim - 35 columns row-major)."""
     parts = []
     for name, m in HEADS:
         if name == "feat" and n_feat == 0:
             continue
         w = weights[name]
-        for key in ("W1", "b1", "W2", "b2"):
+        W1 = _dev(w["W1"], device)
+        parts.append(W1[:, :35].reshape(-1))
+        for key in ("b1", "W2", "b2"):
             parts.append(_dev(w[key], device).reshape(-1))
+        parts.append(W1[:, 35:].reshape(-1))
     return torch.cat(parts)
 
 
-def unpack_params(flat: torch.Tensor, k: int, n_feat: int = 16) -> Dict[str, Dict[str, torch.Tensor]]:
+def unpack_params(flat: torch.Tensor, k: int, n_feat: int = 16, in_dim: int = 35) -> Dict[str, Dict[str, torch.Tensor]]:
+    """Inverse of pack_params: {head: {W1 (32, in_dim), b1, W2, b2}}."""
     out, o = {}, 0
+    nx = in_dim - 35
     for name, m in HEADS:
         if name == "feat":
             if n_feat == 0:
                 continue
             m = n_feat
-        shapes = dict(W1=(32, 35), b1=(32,), W2=(k * m, 32), b2=(k * m,))
-        out[name] = {}
-        for key in ("W1", "b1", "W2", "b2"):
+        shapes = dict(W1=(32, 35), b1=(32,), W2=(k * m, 32), b2=(k * m,), W1x=(32, nx))
+        part = {}
+        for key in ("W1", "b1", "W2", "b2", "W1x"):
             sz = 1
             for d in shapes[key]:
                 sz *= d
-            out[name][key] = flat[o:o + sz].reshape(shapes[key])
+            part[key] = flat[o:o + sz].reshape(shapes[key])
             o += sz
+        W1x = part.pop("W1x")
+        if nx:
+            part["W1"] = torch.cat([part["W1"], W1x], 1)
+        out[name] = part
     return out
 
 
@@ -163,8 +173,9 @@ class Decoder:
     """Device-resident decoder parameters plus its workspace."""
 
     def __init__(self, n_anchors: int, k: int, n_feat: int = 16, precision: int = 0, l_o: float = 1.0,
-                 l_s: float = 0.02, device="cuda"):
-        self.desc = L.make_decoder(n_anchors, k, n_feat, precision, l_o, l_s)
+                 l_s: float = 0.02, device="cuda", in_dim: int = 35):
+        self.desc = L.make_decoder(n_anchors, k, n_feat, precision, l_o, l_s, in_dim)
+        self.in_dim = in_dim
         self.A, self.k, self.nf = n_anchors, k, n_feat
         self.n = n_anchors * k
         self.n_params = L.decode_param_count(self.desc)
@@ -284,3 +295,70 @@ class FeatureLift:
         L.feature_backward(self.desc, self.V, self.W, self.H, feat.contiguous(), params.contiguous(),
                            dino.contiguous(), d_cos.contiguous(), d_feat, d_params, self.work)
         return d_feat, d_params
+
+
+def mapping_loss(rendered: Dict[str, torch.Tensor], obs_rgb: torch.Tensor, obs_depth: torch.Tensor,
+                 cosine: Optional[torch.Tensor] = None, dynamic: Optional[torch.Tensor] = None,
+                 want_grad: bool = True, **opt_kw) -> Dict[str, torch.Tensor]:
+    """Mapping loss of Eq. 4 / Eq. 14 per view with SSIM, and its gradients
+    w.r.t. the rendered colour and depth and the distillation cosine, in the
+    library's stencil kernels (asgs_mapping_loss). rendered: rgb (V,3,H,W),
+    depth (V,H,W); obs_rgb, obs_depth alike; cosine (V,H,W) or None; dynamic
+    (V,H,W) uint8 motion mask or None."""
+    rgb = rendered["rgb"]
+    V, H, W = rgb.shape[0], rgb.shape[-2], rgb.shape[-1]
+    dev = rgb.device
+    c = lambda t: None if t is None else t.contiguous()
+    keep = [c(rgb), c(rendered["depth"]), c(obs_rgb), c(obs_depth), c(cosine), c(dynamic)]
+    m = L.MappingMaps()
+    m.rgb, m.depth, m.obs_rgb, m.obs_depth, m.cosine, m.dynamic = (L._ptr(t) for t in keep)
+    kw = dict(dtype=torch.float32, device=dev)
+    out = dict(loss=torch.empty(V, **kw))
+    if want_grad:
+        out["d_rgb"] = torch.empty((V, 3, H, W), **kw)
+        out["d_depth"] = torch.empty((V, H, W), **kw)
+        if cosine is not None:
+            out["d_cos"] = torch.empty((V, H, W), **kw)
+    work = torch.empty(L.mapping_work_size(V, W, H), dtype=torch.uint8, device=dev)
+    L.mapping_loss(V, W, H, L.mapping_opts(**opt_kw), m, out["loss"], out.get("d_rgb"), out.get("d_depth"),
+                   out.get("d_cos"), work)
+    return out
+
+
+def mean_scale(scale: torch.Tensor, lam5: float = 0.01, d_scale: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """s_bar of Eq. 14 (device scalar); adds lam5 / count to d_scale if given."""
+    value = torch.empty(1, dtype=torch.float32, device=scale.device)
+    work = torch.empty(L.mean_scale_work_size(), dtype=torch.uint8, device=scale.device)
+    L.mean_scale(scale.contiguous(), lam5, value, d_scale, work)
+    return value
+
+
+class UncertaintyMLP:
+    """The uncertainty MLP F_u with its loss L_u and the motion mask
+    (asgs_uncertainty) for views of one resolution, with its device
+    workspace. params: packed W1 [128][n_high], b1, w2 [128], b2."""
+
+    def __init__(self, n_views: int, width: int, height: int, n_high: int, grid_h: int, grid_w: int,
+                 sigma_min: float = 1e-3, lam3: float = 0.4, device="cuda"):
+        self.desc = L.uncertainty_mlp(n_high, grid_h, grid_w, sigma_min, lam3)
+        self.V, self.W, self.H = n_views, width, height
+        self.n_params = L.uncertainty_param_count(self.desc)
+        self.work = torch.empty(L.uncertainty_workspace_size(self.desc, n_views, width, height), dtype=torch.uint8,
+                                device=device)
+        self.device = device
+
+    def __call__(self, params: torch.Tensor, dino: torch.Tensor, R: Optional[torch.Tensor] = None,
+                 want_grad: bool = True) -> Dict[str, torch.Tensor]:
+        """dino (V,n_high,grid_h,grid_w), R (V,H,W) or None -> sigma, dynamic
+        (V,H,W); with R also loss (V,) and, with want_grad, d_params."""
+        kw = dict(dtype=torch.float32, device=self.device)
+        out = dict(sigma=torch.empty((self.V, self.H, self.W), **kw),
+                   dynamic=torch.empty((self.V, self.H, self.W), dtype=torch.uint8, device=self.device))
+        if R is not None:
+            out["loss"] = torch.empty(self.V, **kw)
+            if want_grad:
+                out["d_params"] = torch.empty(self.n_params, **kw)
+        L.uncertainty(self.desc, self.V, self.W, self.H, params.contiguous(), dino.contiguous(),
+                      None if R is None else R.contiguous(), out["sigma"], out["dynamic"], out.get("loss"),
+                      out.get("d_params"), self.work)
+        return out

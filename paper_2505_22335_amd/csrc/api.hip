@@ -100,6 +100,7 @@ int make_views(const asgs_camera* cams, int32_t n_views, float fov_clamp, ViewDe
       return fail(ASGS_E_INVALID, "view %d: bad intrinsics", v);
     for (int k = 0; k < 12; ++k)
       if (!isfinite(c.T_wc[k])) return fail(ASGS_E_INVALID, "view %d: non-finite T_wc", v);
+    if (!isfinite(c.t)) return fail(ASGS_E_INVALID, "view %d: non-finite frame time", v);
     ViewDev& V = out[v];
     memset(&V, 0, sizeof(V));
     double Rwc[9], ctr[3];
@@ -116,6 +117,8 @@ int make_views(const asgs_camera* cams, int32_t n_views, float fov_clamp, ViewDe
       V.t[r] = (float)tr;
       V.cc[r] = (float)ctr[r];
     }
+    V.lt[0] = (float)sin(M_PI * (double)c.t);
+    V.lt[1] = (float)cos(M_PI * (double)c.t);
     V.fx = c.fx;
     V.fy = c.fy;
     V.cx = c.cx;
@@ -541,6 +544,168 @@ int asgs_ctx_array(const asgs_camera* cams, int32_t n_views, int64_t n_gauss, co
 
 /* ------------------------------------------------------------------------- */
 
+static int check_maps_size(int32_t n_views, int32_t width, int32_t height, const char* what) {
+  if (n_views < 1 || n_views > ASGS_MAX_VIEWS) return fail(ASGS_E_INVALID, "%s: n_views out of range", what);
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return fail(ASGS_E_INVALID, "%s: bad resolution", what);
+  if ((int64_t)width * height * n_views > ((int64_t)1 << 31)) return fail(ASGS_E_INVALID, "%s: too many pixels", what);
+  return ASGS_OK;
+}
+
+static size_t mapping_work_bytes(int32_t n_views, int32_t width, int32_t height) {
+  const size_t abc = (size_t)n_views * 9 * (size_t)width * (size_t)height * sizeof(float);
+  const size_t part = (size_t)n_views * (size_t)mapping_tiles(width, height) * sizeof(double);
+  return ((abc + 255) & ~(size_t)255) + part;
+}
+
+void asgs_mapping_opts_default(asgs_mapping_opts* o) {
+  if (!o) return;
+  o->lam = 0.8f;
+  o->lam1 = 0.6f;
+  o->lam2 = 1.0f;
+  o->lam4 = 0.01f;
+  o->reserved = 0;
+}
+
+int asgs_mapping_work_size(int32_t n_views, int32_t width, int32_t height, size_t* bytes) {
+  int st = check_maps_size(n_views, width, height, "mapping_work_size");
+  if (st) return st;
+  if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
+  *bytes = mapping_work_bytes(n_views, width, height);
+  return ASGS_OK;
+}
+
+int asgs_mapping_loss(int32_t n_views, int32_t width, int32_t height, const asgs_mapping_opts* opts,
+                      const asgs_mapping_maps* m, float* loss, float* d_rgb, float* d_depth, float* d_cos, void* work,
+                      size_t work_bytes, void* stream) {
+  int st = check_maps_size(n_views, width, height, "mapping_loss");
+  if (st) return st;
+  if (!opts || !m) return fail(ASGS_E_INVALID, "mapping_loss: NULL argument");
+  for (float f : {opts->lam, opts->lam1, opts->lam2, opts->lam4})
+    if (!isfinite(f)) return fail(ASGS_E_INVALID, "mapping_loss: non-finite weight");
+  if (opts->reserved != 0) return fail(ASGS_E_INVALID, "mapping_loss: reserved must be 0");
+  for (const float* ptr : {m->rgb, m->depth, m->obs_rgb, m->obs_depth})
+    if (!ptr) return fail(ASGS_E_INVALID, "mapping_loss: input map missing");
+  if (d_cos && !m->cosine) return fail(ASGS_E_INVALID, "mapping_loss: d_cos needs the cosine map");
+  if (!loss && !d_rgb && !d_depth && !d_cos) return fail(ASGS_E_INVALID, "mapping_loss: no output requested");
+  const size_t need = mapping_work_bytes(n_views, width, height);
+  if (!work || work_bytes < need) return fail(ASGS_E_WORKSPACE, "mapping_loss needs %zu bytes of work", need);
+  const size_t abc = (size_t)n_views * 9 * (size_t)width * (size_t)height * sizeof(float);
+  MappingArgs a{};
+  a.rgb = m->rgb;
+  a.depth = m->depth;
+  a.obs_rgb = m->obs_rgb;
+  a.obs_depth = m->obs_depth;
+  a.cosine = m->cosine;
+  a.dynamic = m->dynamic;
+  a.d_rgb = d_rgb;
+  a.d_depth = d_depth;
+  a.d_cos = d_cos;
+  a.abc = d_rgb ? static_cast<float*>(work) : nullptr;
+  a.partial = reinterpret_cast<double*>(static_cast<char*>(work) + ((abc + 255) & ~(size_t)255));
+  a.W = width;
+  a.H = height;
+  a.lam = opts->lam;
+  a.lam1 = opts->lam1;
+  a.lam2 = opts->lam2;
+  a.lam4 = opts->lam4;
+  mapping_window(a.taps, a.ftaps);
+  {
+    ProfScope ps(ASGS_K_MAPPING, reinterpret_cast<hipStream_t>(stream));
+    launch_mapping_loss(a, n_views, loss, reinterpret_cast<hipStream_t>(stream));
+  }
+  return check_launch("mapping_loss launch");
+}
+
+int asgs_mean_scale_work_size(size_t* bytes) {
+  if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
+  *bytes = mean_scale_work_bytes();
+  return ASGS_OK;
+}
+
+int asgs_mean_scale(int64_t count, const float* scale, float lam5, float* value, float* d_scale, void* work,
+                    size_t work_bytes, void* stream) {
+  if (count < 1 || count > ((int64_t)1 << 34)) return fail(ASGS_E_INVALID, "mean_scale: count out of range");
+  if (!scale) return fail(ASGS_E_INVALID, "mean_scale: scale is NULL");
+  if (!isfinite(lam5)) return fail(ASGS_E_INVALID, "mean_scale: non-finite lam5");
+  if (!value && !d_scale) return fail(ASGS_E_INVALID, "mean_scale: no output requested");
+  if (!work || work_bytes < mean_scale_work_bytes())
+    return fail(ASGS_E_WORKSPACE, "mean_scale needs %zu bytes of work", mean_scale_work_bytes());
+  {
+    ProfScope ps(ASGS_K_MAPPING, reinterpret_cast<hipStream_t>(stream));
+    launch_mean_scale(count, scale, lam5, value, d_scale, static_cast<double*>(work),
+                      reinterpret_cast<hipStream_t>(stream));
+  }
+  return check_launch("mean_scale launch");
+}
+
+static int check_uncertainty(const asgs_uncertainty_mlp* u) {
+  if (!u) return fail(ASGS_E_INVALID, "uncertainty: descriptor is NULL");
+  if (u->n_high < 16 || u->n_high > 2048 || u->n_high % 16 != 0)
+    return fail(ASGS_E_UNSUPPORTED, "uncertainty: n_high must be a multiple of 16 in 16..2048");
+  if (u->grid_h < 1 || u->grid_w < 1 || u->grid_h > 4096 || u->grid_w > 4096)
+    return fail(ASGS_E_INVALID, "uncertainty: bad patch grid");
+  if (!(u->sigma_min > 0.f) || !isfinite(u->sigma_min) || !isfinite(u->lam3))
+    return fail(ASGS_E_INVALID, "uncertainty: sigma_min must be > 0 and lam3 finite");
+  if (u->reserved != 0) return fail(ASGS_E_INVALID, "uncertainty: reserved must be 0");
+  return ASGS_OK;
+}
+
+int asgs_uncertainty_param_count(const asgs_uncertainty_mlp* u, int64_t* count) {
+  int st = check_uncertainty(u);
+  if (st) return st;
+  if (!count) return fail(ASGS_E_INVALID, "count is NULL");
+  *count = (int64_t)128 * u->n_high + 128 + 128 + 1;
+  return ASGS_OK;
+}
+
+int asgs_uncertainty_workspace_size(const asgs_uncertainty_mlp* u, int32_t n_views, int32_t width, int32_t height,
+                                    size_t* bytes) {
+  int st = check_uncertainty(u);
+  if (st) return st;
+  if ((st = check_maps_size(n_views, width, height, "uncertainty_workspace_size"))) return st;
+  if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
+  *bytes = uncertainty_layout(n_views, width, height, u->grid_h, u->grid_w).total;
+  return ASGS_OK;
+}
+
+int asgs_uncertainty(const asgs_uncertainty_mlp* u, int32_t n_views, int32_t width, int32_t height,
+                     const float* params, const float* dino, const float* R, float* sigma, uint8_t* dynamic,
+                     float* loss, float* d_params, void* work, size_t work_bytes, void* stream) {
+  int st = check_uncertainty(u);
+  if (st) return st;
+  if ((st = check_maps_size(n_views, width, height, "uncertainty"))) return st;
+  if (feature_max_patch_span(width, height, u->grid_h, u->grid_w) > 4)
+    return fail(ASGS_E_UNSUPPORTED, "uncertainty: patch grid %dx%d too fine for %dx%d pixels", u->grid_w, u->grid_h,
+                width, height);
+  if (!params || !dino) return fail(ASGS_E_INVALID, "uncertainty: params and dino are required");
+  if ((loss || d_params) && !R) return fail(ASGS_E_INVALID, "uncertainty: loss and d_params need R");
+  if (!sigma && !dynamic && !loss && !d_params) return fail(ASGS_E_INVALID, "uncertainty: no output requested");
+  const UncLayout L = uncertainty_layout(n_views, width, height, u->grid_h, u->grid_w);
+  if (!work || work_bytes < L.total) return fail(ASGS_E_WORKSPACE, "uncertainty needs %zu bytes of work", L.total);
+  UncArgs a{};
+  a.V = n_views;
+  a.W = width;
+  a.H = height;
+  a.nh = u->n_high;
+  a.Hp = u->grid_h;
+  a.Wp = u->grid_w;
+  a.sx = (float)((double)u->grid_w / width);
+  a.sy = (float)((double)u->grid_h / height);
+  a.sigma_min = u->sigma_min;
+  a.lam3 = u->lam3;
+  a.inv_hw = (float)(1.0 / ((double)width * height));
+  a.params = params;
+  a.dino = dino;
+  a.R = R;
+  a.sigma = sigma;
+  a.dynamic = dynamic;
+  {
+    ProfScope ps(ASGS_K_UNCERTAINTY, reinterpret_cast<hipStream_t>(stream));
+    launch_uncertainty(a, L, static_cast<char*>(work), loss, d_params, reinterpret_cast<hipStream_t>(stream));
+  }
+  return check_launch("uncertainty launch");
+}
+
 static int check_decoder(const asgs_decoder* d) {
   if (!d) return fail(ASGS_E_INVALID, "decoder is NULL");
   if (d->n_anchors < 1 || d->n_anchors > ((int64_t)1 << 24)) return fail(ASGS_E_INVALID, "n_anchors out of range");
@@ -550,7 +715,8 @@ static int check_decoder(const asgs_decoder* d) {
   if (d->precision == 1 && d->n_anchors * d->k > ((int64_t)1 << 27))
     return fail(ASGS_E_UNSUPPORTED, "BF16 decode supports at most 2^27 Gaussians (n_anchors * k)");
   if (!isfinite(d->l_o) || !(d->l_s > 0.f) || !isfinite(d->l_s)) return fail(ASGS_E_INVALID, "bad l_o/l_s");
-  if (d->reserved != 0) return fail(ASGS_E_INVALID, "decoder.reserved must be 0");
+  if (d->in_dim != 0 && d->in_dim != 35 && d->in_dim != 36 && d->in_dim != 38)
+    return fail(ASGS_E_UNSUPPORTED, "decoder.in_dim must be 35, 36 or 38 (got %d)", d->in_dim);
   return ASGS_OK;
 }
 

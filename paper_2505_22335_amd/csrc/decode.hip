@@ -2,8 +2,10 @@
 // Eq. 8 and Eq. 9; head MLP details in the appendix).
 //
 // Per anchor v and view with camera centre c: X = [f_v (32), delta (3)],
-// delta = (x_v - c)/|x_v - c|. Five heads (opacity, rgb, scale, rot, feat),
-// each Y_h = W2_h act_h(W1_h X + b1_h) + b2_h with a 32-wide hidden layer
+// delta = (x_v - c)/|x_v - c|, optionally followed by |x_v - c| and the
+// temporal embedding (sin pi t, cos pi t) of the view. Five heads (opacity,
+// rgb, scale, rot, feat), each Y_h = W2_h act_h(W1_h X + b1_h) + b2_h with a
+// 32-wide hidden layer
 // (ReLU for the first four, SoftPlus for the feature head), then the output
 // activations: sigmoid (opacity, rgb), l_s * sigmoid (scale), raw (rot, feat).
 //
@@ -32,7 +34,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // Anchor gradients of one view from the two head groups' dL/dX: the feature
 // part goes to d_feat, the view-direction part through
-// delta = (x - c) / |x - c| to d_xyz and (negated) to the camera centre,
+// delta = (x - c) / |x - c| (and the distance input |x - c|, when the decoder
+// has one) to d_xyz and (negated) to the camera centre,
 // whose per-block sums feed the pose gradient.
 constexpr int kAnchorThreads = 256;
 __global__ void __launch_bounds__(kAnchorThreads) k_dec_bwd_anchor(DecodeConst dc, DecodeViews dv,
@@ -62,12 +65,15 @@ __global__ void __launch_bounds__(kAnchorThreads) k_dec_bwd_anchor(DecodeConst d
       gd[c] = dx0[a * 36 + 32 + c] + (has_feat ? dx1[a * 36 + 32 + c] : 0.f);
       D[c] = xyz[c * A + a] - dv.c[view][c];
     }
+    // dL/d|x - c| of the distance input (column 35), when present
+    const float gdist = dc.n_x > 0 ? dx0[a * 36 + 35] + (has_feat ? dx1[a * 36 + 35] : 0.f) : 0.f;
     const float dist = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
     float del[3];
     for (int c = 0; c < 3; ++c) del[c] = D[c] / dist;
     const float pr = del[0] * gd[0] + del[1] * gd[1] + del[2] * gd[2];
     for (int c = 0; c < 3; ++c) {
-      const float dD = (gd[c] - del[c] * pr) / dist;
+      // through delta = D / |D| (projected, scaled by 1/|D|) and |D| (along delta)
+      const float dD = (gd[c] - del[c] * pr) / dist + gdist * del[c];
       if (d_xyz) {
         float* p = &d_xyz[c * A + a];
         *p = (view == 0 ? 0.f : *p) + dD;
@@ -168,8 +174,10 @@ __global__ void __launch_bounds__(256) k_decode_reduce(DecodeConst dc, DecodeVie
 HeadTable head_table(const DecodeConst& dc) {
   HeadTable ht;
   int units = 0, rows = 0;
+  ht.nx = dc.n_x;
   for (int h = 0; h < kHeads; ++h) {
     ht.off[h] = (int32_t)dc.head_off[h];
+    ht.xoff[h] = (int32_t)dc.head_xoff[h];
     ht.m[h] = dc.head_m[h];
     ht.row0[h] = rows;
     rows += dc.k * dc.head_m[h];
@@ -186,6 +194,8 @@ DecodeViews decode_views(const ViewDev* hv, int n_views) {
   for (int v = 0; v < n_views; ++v) {
     for (int c = 0; c < 3; ++c) dv.c[v][c] = hv[v].cc[c];
     for (int c = 0; c < 9; ++c) dv.R[v][c] = hv[v].R[c];
+    dv.lt[v][0] = hv[v].lt[0];
+    dv.lt[v][1] = hv[v].lt[1];
   }
   return dv;
 }
@@ -221,11 +231,14 @@ DecodeConst decode_const(const asgs_decoder& d, int n_views) {
   dc.l_o = d.l_o;
   dc.l_s = d.l_s;
   const int ms[kHeads] = {1, 3, 3, 4, d.n_feat};
+  dc.n_x = d.in_dim > kIn ? d.in_dim - kIn : 0;
   int64_t o = 0;
   for (int h = 0; h < kHeads; ++h) {
     dc.head_off[h] = o;
     dc.head_m[h] = ms[h];
     if (ms[h] > 0) o += (int64_t)kHid * kIn + kHid + (int64_t)d.k * ms[h] * kHid + (int64_t)d.k * ms[h];
+    dc.head_xoff[h] = o;
+    if (ms[h] > 0) o += (int64_t)kHid * dc.n_x;
   }
   dc.n_params = o;
   return dc;

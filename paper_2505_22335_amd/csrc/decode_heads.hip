@@ -300,14 +300,19 @@ ASGS_DEV void assign_rows(const GroupDesc& gd, const HeadTable& ht, int grp, int
   }
 }
 
-// The group's weights into LDS: first-layer rows padded to kW1S (pad columns
-// zero), second-layer rows to kW2S. Head h's packed parameters start at
-// ht.off[h]: W1 [32][35], b1 [32], W2 [rows][32], b2 [rows]. Every load is
+// The group's weights into LDS: first-layer rows padded to kW1S, second-layer
+// rows to kW2S. Head h's packed parameters start at ht.off[h]: W1 [32][35],
+// b1 [32], W2 [rows][32], b2 [rows]; its extra input columns [32][nx] sit at
+// ht.xoff[h]. The distance weight (or zero) fills pad column 35, matching the
+// distance in column 35 of the anchor rows; the temporal weights are folded
+// into the bias with the view's embedding lt (the time input is the same for
+// every anchor of a view), the last pad column stays zero. Every load is
 // issued before the first store. The index arithmetic is branch-free: the
 // head of an element is chosen by comparisons with the group's (uniform) head
 // boundaries, a lane past the end loads the last element and stores it into
 // the never-read pad column of the first second-layer row.
-ASGS_DEV void stage_weights(const Views& S, const GroupDesc& gd, const HeadTable& ht, const float* params, int t) {
+ASGS_DEV void stage_weights(const Views& S, const GroupDesc& gd, const HeadTable& ht, const float* params, int t,
+                            float lt0, float lt1) {
   constexpr int kW1 = kHid * kIn;                          // first-layer weights per head
   constexpr int kQ1 = (4 * kW1 + kNT - 1) / kNT;           // first-layer elements per thread
   constexpr int kQ2 = 16 * ASGS_MAX_K * kHid / kNT;        // second-layer elements per thread
@@ -372,10 +377,21 @@ ASGS_DEV void stage_weights(const Views& S, const GroupDesc& gd, const HeadTable
   for (int q = 0; q < kQ1; ++q) *(d1[q] >= 0 ? S.W1s + d1[q] : trash) = v1[q];
 #pragma unroll
   for (int q = 0; q < kQ2; ++q) *(d2[q] >= 0 ? S.W2s + d2[q] : trash) = v2[q];
+  // the extra columns after the stores (one more round trip, only for the
+  // scene-variant inputs; loading them with the rest costs registers)
+  float vxd = 0.f, vxs = 0.f, vxc = 0.f;
+  if (ht.nx > 0) {
+    const int xsrc = ht.xoff[gd.hbase + (tb1 >> 5)] + (tb1 & 31) * ht.nx;
+    vxd = params[(unsigned)xsrc];
+    if (ht.nx == 3) {
+      vxs = params[(unsigned)(xsrc + 1)];
+      vxc = params[(unsigned)(xsrc + 2)];
+    }
+  }
   if (t < gd.nunits) {
-    S.W1s[t * kW1S + kIn] = 0.f;
+    S.W1s[t * kW1S + kIn] = vxd;
     S.W1s[t * kW1S + kIn + 1] = 0.f;
-    S.b1s[t] = vb1;
+    S.b1s[t] = vb1 + (vxs * lt0 + vxc * lt1);
   }
   if (t < gd.nrows) S.b2s[t] = vb2;
 }
@@ -454,7 +470,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
   // the first tile's inputs are requested before the weights, so that the
   // two latencies overlap
   if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
-  stage_weights(S, gd, ht, params, t);
+  stage_weights(S, gd, ht, params, t, dv.lt[view][0], dv.lt[view][1]);
   for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
     const int a0 = tile * 16;
     __syncthreads();  // weights staged / the previous tile's readers are done
@@ -474,7 +490,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
         for (int c = 0; c < 3; ++c) D[c] /= dist;
       }
       for (int c = 0; c < 3; ++c) S.X[t][32 + c] = D[c];
-      S.X[t][35] = 0.f;
+      S.X[t][35] = ht.nx > 0 && a0 + t < A ? dist : 0.f;  // distance input (weight column 35)
       S.X[t][36] = 0.f;
     }
     __syncthreads();
@@ -505,9 +521,9 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
         for (int r = 0; r < 4; ++r)
           if (16 * ct + fl < kXS) Hw[4 * fg + r][16 * ct + fl] = dx[ct][r];
       __syncthreads();
-      // the four heads' dX in a fixed order
-      for (int e = t; e < 16 * kIn; e += kNT) {
-        const int a = e / kIn, c = e - a * kIn;
+      // the four heads' dX in a fixed order (column 35: the distance input)
+      for (int e = t; e < 16 * kDX; e += kNT) {
+        const int a = e / kDX, c = e - a * kDX;
         if (a0 + a < A)
           dxout[(size_t)(a0 + a) * kDX + c] = (S.H[0][a][c] + S.H[1][a][c]) + (S.H[2][a][c] + S.H[3][a][c]);
       }
@@ -532,7 +548,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
       } else if (wv == 1) {
         head_w1(S, dz, 1, dw1[0], db1[0], fg, fl);
       } else {
-        // input columns 0..31 on wave 2, 32..34 on wave 3, straight to the workspace
+        // input columns 0..31 on wave 2, 32..35 on wave 3, straight to the workspace
         const int ct0 = wv == 2 ? 0 : 2, ct1 = wv == 2 ? 2 : 3;
         head_dx(S, Tw, hc, ct0, ct1, dx, fl, fg);
 #pragma unroll
@@ -542,7 +558,7 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int a = 4 * fg + r;
-            if (c < kIn && a0 + a < A) dxout[(size_t)(a0 + a) * kDX + c] = dx[ct][r];
+            if (c < kDX && a0 + a < A) dxout[(size_t)(a0 + a) * kDX + c] = dx[ct][r];
           }
         }
       }
@@ -579,6 +595,12 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
     }
   }
   const int64_t w1b = ht.off[hc.h];
+  const int64_t xb = ht.xoff[hc.h];
+  const int nx = ht.nx;
+  const float lt0 = dv.lt[view][0], lt1 = dv.lt[view][1];
+  // extra input columns: the distance weight's gradient is column 35 of the
+  // products with X; the temporal weights' gradients are the bias gradient
+  // times the view's embedding (accumulated over views by put)
   auto put_half = [&](int half, const f4v (&d)[3], float b) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -586,11 +608,19 @@ __global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTa
       put(w1b + (int64_t)u * kIn + fl, d[0][r]);
       put(w1b + (int64_t)u * kIn + 16 + fl, d[1][r]);
       if (fl < 3) put(w1b + (int64_t)u * kIn + 32 + fl, d[2][r]);
+      if (fl == 3 && nx > 0) put(xb + (int64_t)u * nx, d[2][r]);
     }
     float sb = b;
     sb += __shfl_xor(sb, 16);
     sb += __shfl_xor(sb, 32);
-    if (fg == 0) put(w1b + kHid * kIn + 16 * half + fl, sb);
+    if (fg == 0) {
+      const int u = 16 * half + fl;
+      put(w1b + kHid * kIn + u, sb);
+      if (nx == 3) {
+        put(xb + (int64_t)u * 3 + 1, sb * lt0);
+        put(xb + (int64_t)u * 3 + 2, sb * lt1);
+      }
+    }
   };
   if (grp == 0) {
     put_half(0, dw1[0], db1[0]);
@@ -660,7 +690,7 @@ __global__ void __launch_bounds__(kNT, 3) k_dec_fwd_heads(DecodeConst dc, HeadTa
   // the first tile's inputs are requested before the weights, so that the
   // two latencies overlap
   if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
-  stage_weights(S, gd, ht, params, t);
+  stage_weights(S, gd, ht, params, t, dv.lt[view][0], dv.lt[view][1]);
   for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
     const int a0 = tile * 16;
     __syncthreads();  // weights staged / the previous tile's outputs are written
@@ -677,7 +707,7 @@ __global__ void __launch_bounds__(kNT, 3) k_dec_fwd_heads(DecodeConst dc, HeadTa
         for (int c = 0; c < 3; ++c) D[c] /= dist;
       }
       for (int c = 0; c < 3; ++c) S.X[t][32 + c] = D[c];
-      S.X[t][35] = 0.f;
+      S.X[t][35] = ht.nx > 0 && a0 + t < A ? dist : 0.f;  // distance input (weight column 35)
       S.X[t][36] = 0.f;
     }
     const float mx[3] = {mxp[0], mxp[1], mxp[2]}, mo[3] = {mop[0], mop[1], mop[2]};

@@ -2,13 +2,14 @@
 //
 // The two layers of the five heads are dense contractions over anchors:
 //   layer 1: Z[a][u] = X_f[a] . W1f[u] + delta[a] . W1d[u] + b1[u]   (u < 160 hidden units)
+//            (+ dist[a] W1x[u] + lt . W1t[u] for the distance and temporal inputs)
 //   layer 2: Y[a][r] = H_h[a] . W2[r] + b2[r]                        (rows r of head h)
 // with X_f the 32-d anchor feature and H_h the 32 hidden activations of head
 // h, so K = 32 for both: one v_mfma_f32_16x16x32_bf16 per 16x16 output tile.
 // Operands (anchor features, first- and second-layer weights, hidden
 // activations) are rounded to bfloat16 (nearest even); accumulation, the
-// view-direction term (K = 3, on the vector ALUs), biases and activations are
-// FP32. Means do not pass through the MLP and stay FP32.
+// view-direction and distance terms (on the vector ALUs), biases (with the
+// view's temporal term folded in) and activations are FP32. Means do not pass through the MLP and stay FP32.
 //
 // Persistent grid, one workgroup per CU: the workgroup stages both layers'
 // weights once in LDS (padded rows against bank conflicts) together with a
@@ -69,7 +70,7 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
                                                          const float* __restrict__ params, asgs_gaussians out) {
   __shared__ __attribute__((aligned(16))) uint16_t w1[160 * kRow];
   __shared__ __attribute__((aligned(16))) uint16_t w2[kMaxPRows * kRow];
-  __shared__ float w1d[160][4];        // direction weights (3) and bias of each hidden unit
+  __shared__ float w1d[160][5];        // direction weights (3), bias, distance weight of each hidden unit
   __shared__ float b2s[kMaxPRows];     // second-layer bias per padded row
   __shared__ int32_t epi[kMaxPRows];   // per padded row: comp * n + i (or -1 for padding)
   __shared__ __attribute__((aligned(16))) uint16_t Xs[kWaves][kMT][kRow];
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
     const float w = params[(unsigned)(ASGS_BY_ROW(pr, ob) + prc * kHid + (e & 31))];
     v2[q] = pr < re ? w : 0.f;
   }
-  float wd[4];
+  float wd[5];
   {
     const int u = t < nunits ? t : nunits - 1;
     const int src = ASGS_BY_UNIT(u, o1) + (u & 31) * kIn;
@@ -146,6 +147,15 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
     wd[1] = params[(unsigned)(src + 33)];
     wd[2] = params[(unsigned)(src + 34)];
     wd[3] = params[(unsigned)(ASGS_BY_UNIT(u, o1) + kHid * kIn + (u & 31))];
+    wd[4] = 0.f;
+    if (ht.nx > 0) {  // distance weight; temporal weights folded into the bias
+      int xo[kHeads];
+      for (int h = 0; h < kHeads; ++h) xo[h] = ht.xoff[h];
+      const int xsrc = ASGS_BY_UNIT(u, xo) + (u & 31) * ht.nx;
+      wd[4] = params[(unsigned)xsrc];
+      if (ht.nx == 3)
+        wd[3] += params[(unsigned)(xsrc + 1)] * dv.lt[view][0] + params[(unsigned)(xsrc + 2)] * dv.lt[view][1];
+    }
   }
   // per padded row t: second-layer bias and output code (r % m) * n + r / m
   float bias2;
@@ -173,10 +183,8 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
     w2[(e >> 5) * kRow + (e & 31)] = f2bf(v2[q]);
   }
   if (t < kHeads * kHid) {
-    w1d[t][0] = wd[0];
-    w1d[t][1] = wd[1];
-    w1d[t][2] = wd[2];
-    w1d[t][3] = wd[3];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) w1d[t][c] = wd[c];
   }
   if (t < kMaxPRows) {
     b2s[t] = t < nprows ? bias2 : 0.f;
@@ -235,16 +243,17 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
       for (int c = 0; c < 3; ++c) D[c] = xd[c] - dv.c[view][c];
       const float d = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
       for (int c = 0; c < 3; ++c) dls[wv][lane][c] = D[c] / d;
+      dls[wv][lane][3] = d;
     }
     if (tile + tstride < ntiles) load_tile(tile + tstride);
     wave_sync();
     // ---- layer 1: 16 anchors x 160 hidden units, two column tiles at a time ----
     const bf8v xa = *reinterpret_cast<const bf8v*>(&Xs[wv][fl][8 * fg]);
-    float dl[4][3];
+    float dl[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) dl[r][c] = dls[wv][4 * fg + r][c];
+      for (int c = 0; c < 4; ++c) dl[r][c] = dls[wv][4 * fg + r][c];
     for (int nt = 0; nt < nunits / 16; nt += 2) {
       const int ua = 16 * nt + fl, ub = ua + 16;
       const bf8v ba = *reinterpret_cast<const bf8v*>(&w1[ua * kRow + 8 * fg]);
@@ -257,10 +266,10 @@ __global__ void __launch_bounds__(kThreads) k_decode_bf16(DecodeConst dc, HeadTa
         const int u = half ? ub : ua;
         const f4v c4 = half ? cb : ca;
         const bool sp = (u >> 5) == 4;  // the feature head's hidden layer uses SoftPlus
-        const float wd0 = w1d[u][0], wd1 = w1d[u][1], wd2 = w1d[u][2], b1 = w1d[u][3];
+        const float wd0 = w1d[u][0], wd1 = w1d[u][1], wd2 = w1d[u][2], b1 = w1d[u][3], wx = w1d[u][4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float z = c4[r] + b1 + dl[r][0] * wd0 + dl[r][1] * wd1 + dl[r][2] * wd2;
+          const float z = c4[r] + b1 + dl[r][0] * wd0 + dl[r][1] * wd1 + dl[r][2] * wd2 + dl[r][3] * wx;
           Hs[wv][4 * fg + r][u] = f2bf(sp ? softplus(z) : fmaxf(z, 0.f));
         }
       }

@@ -7,7 +7,8 @@
 
 namespace asgs {
 
-constexpr int kIn = 35;      // decoder input: 32-d anchor feature + 3-d view direction
+constexpr int kIn = 35;      // decoder input: 32-d anchor feature + 3-d view direction (the
+                             // distance and time columns of wider inputs are packed apart)
 constexpr int kHid = 32;     // hidden width of every head
 constexpr int kHeads = 5;    // opacity, rgb, scale, rot, feat
 constexpr int kMaxRows = ASGS_MAX_K * 27;  // second-layer rows (k * (1+3+3+4+16))
@@ -15,10 +16,13 @@ constexpr int kMaxRows = ASGS_MAX_K * 27;  // second-layer rows (k * (1+3+3+4+16
 struct DecodeViews {
   float c[ASGS_MAX_VIEWS][3];
   float R[ASGS_MAX_VIEWS][9];
+  float lt[ASGS_MAX_VIEWS][2];  // temporal embedding (sin pi t, cos pi t) of each view
 };
 
 struct HeadTable {
   int32_t off[kHeads];      // packed offset of W1 of head h
+  int32_t xoff[kHeads];     // packed offset of head h's extra first-layer columns [32][nx]
+  int32_t nx;               // extra input columns: 0, 1 (distance) or 3 (distance, sin, cos)
   int32_t m[kHeads];        // values per Gaussian (0 = absent)
   int32_t row0[kHeads + 1]; // first second-layer row of head h (prefix over k*m)
   int32_t nunits;           // 32 * number of present heads

@@ -71,15 +71,6 @@ ASGS_DEV float col_sum(float v) {
 // time (units 32 apart land in neighbouring rows)
 ASGS_DEV int hpos(int k) { return (k & 31) * 4 + (k >> 5); }
 
-// Bilinear source of output index p along one axis (sample centres at
-// half-integers, clamped): value = (1 - w1) v[i0] + w1 v[i1].
-ASGS_DEV void bilin(int p, int n_in, float scale, int& i0, int& i1, float& w1) {
-  const float s = fmaxf(((float)p + 0.5f) * scale - 0.5f, 0.f);
-  i0 = min((int)s, n_in - 1);
-  i1 = min(i0 + 1, n_in - 1);
-  w1 = s - (float)i0;
-}
-
 struct FeatArgs {
   int32_t V, W, H, nh, Hp, Wp;
   int32_t tiles_x, tiles_y, tiles;  // tiles per view; tiles * V in all

@@ -27,7 +27,8 @@ struct ViewDev {
   int32_t W, H, TX, TY;
   int32_t tile_base; // first global tile key of this view
   int32_t pix_base;  // first pixel of this view in the packed image planes
-  int32_t pad[5];
+  float lt[2];       // temporal embedding (sin pi t, cos pi t) of the frame time
+  int32_t pad[3];
 };
 static_assert(sizeof(ViewDev) == 128, "ViewDev size");
 
@@ -191,6 +192,48 @@ int feature_max_patch_span(int width, int height, int Hp, int Wp);
 void launch_feature_forward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s);
 void launch_feature_backward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s);
 
+// Mapping loss with SSIM and the mean-scale term (mapping.hip).
+struct MappingArgs {
+  const float *rgb, *depth, *obs_rgb, *obs_depth, *cosine;
+  const uint8_t* dynamic;  // motion mask or NULL
+  float *d_rgb, *d_depth, *d_cos;
+  float* abc;              // work: [V][9][H][W] SSIM backward maps (NULL without d_rgb)
+  double* partial;         // work: [V][mapping_tiles] loss partials
+  int32_t W, H;
+  float lam, lam1, lam2, lam4;
+  double taps[11];         // normalised Gaussian window (sigma 1.5)
+  float ftaps[11];
+};
+int64_t mapping_tiles(int width, int height);  // per view
+void mapping_window(double* taps, float* ftaps);
+void launch_mapping_loss(const MappingArgs& a, int n_views, float* loss, hipStream_t s);
+size_t mean_scale_work_bytes();
+void launch_mean_scale(int64_t count, const float* scale, float lam5, float* value, float* d_scale, double* work,
+                       hipStream_t s);
+
+// Uncertainty MLP F_u, its loss and the motion mask (uncertainty.hip).
+struct UncArgs {
+  int32_t V, W, H, nh, Hp, Wp;
+  int32_t tiles_x, tiles_y, tiles;  // 16 x 16 pixel tiles per view
+  float sx, sy;                     // Wp / W, Hp / H
+  float sigma_min, lam3, inv_hw;
+  const float* params;              // W1 [128][nh], b1 [128], w2 [128], b2
+  const float* dino;                // [V][nh][Hp][Wp]
+  const float* R;                   // [V][H][W] or NULL
+  float* sigma;                     // [V][H][W] or NULL
+  uint8_t* dynamic;                 // [V][H][W] or NULL
+  float* zg;                        // work: [V][Hp * Wp][128] first layer per patch
+  double* partial;                  // work: [V * tiles] loss partials, or NULL
+  float* dzt;                       // work: [V * tiles][16][128], or NULL (no gradient)
+  float* w2t;                       // work: [V * tiles][129] dw2 and db2 partials
+  float* dzc;                       // work: [V][Hp * Wp][128] dZ per patch
+};
+struct UncLayout {
+  size_t zg, partial, dzt, w2t, dzc, total;
+};
+UncLayout uncertainty_layout(int n_views, int width, int height, int Hp, int Wp);
+void launch_uncertainty(UncArgs a, const UncLayout& L, char* work, float* loss, float* d_params, hipStream_t s);
+
 // Probabilistic anchor update (anchor.hip); n_keep (device, may be NULL) is zeroed first.
 void launch_anchor_update(int64_t n, const float* p_obs, float* p, uint8_t* keep, unsigned long long* n_keep,
                           float prior, float p_min, float p_max, float prune_below, hipStream_t s);
@@ -200,7 +243,9 @@ struct DecodeConst {
   int32_t k, nf, n_views, precision;
   float l_o, l_s;
   int64_t head_off[5];   // float offset of each head's W1 in the packed params
+  int64_t head_xoff[5];  // float offset of each head's extra first-layer columns [32][n_x]
   int32_t head_m[5];     // values per Gaussian of each head (0 = absent)
+  int32_t n_x;           // input columns past the first 35: 0, 1 (distance) or 3 (+ time)
   int64_t n_params;
 };
 DecodeConst decode_const(const asgs_decoder& d, int n_views);
@@ -224,6 +269,16 @@ namespace asgs {
 
 template <typename T>
 ASGS_DEV T* ctx_ptr(char* ctx, size_t off) { return reinterpret_cast<T*>(ctx + off); }
+
+// Bilinear source of output index p along one axis when n_in samples are
+// upsampled with scale = n_in / n_out (sample centres at half-integers,
+// clamped at both ends): value = (1 - w1) v[i0] + w1 v[i1].
+ASGS_DEV void bilin(int p, int n_in, float scale, int& i0, int& i1, float& w1) {
+  const float s = fmaxf(((float)p + 0.5f) * scale - 0.5f, 0.f);
+  i0 = min((int)s, n_in - 1);
+  i1 = min(i0 + 1, n_in - 1);
+  w1 = s - (float)i0;
+}
 
 // ---------------------------------------------------------------------------
 // Binning blocks: kScanThreads consecutive (view, Gaussian) pairs of one view,

@@ -5,6 +5,7 @@ from __future__ import annotations
 from dataclasses import dataclass
 from typing import Dict, Optional, Sequence
 
+import numpy as np
 import torch
 
 from .core import Decoder, RenderContext, pack_params
@@ -20,6 +21,7 @@ class DeviceAnchors:
     n_feat: int
     l_o: float
     l_s: float
+    in_dim: int = 35
 
     @property
     def A(self) -> int:
@@ -35,7 +37,8 @@ def anchors_to_device(scene, device="cuda") -> DeviceAnchors:
         return torch.as_tensor(x, dtype=torch.float32).to(device).contiguous()
     return DeviceAnchors(xyz=t(scene.xyz), feat=t(scene.feat), off=t(scene.off),
                          params=pack_params(scene.weights, scene.k, nf, device), k=int(scene.k),
-                         n_feat=nf, l_o=float(scene.l_o), l_s=float(scene.l_s))
+                         n_feat=nf, l_o=float(scene.l_o), l_s=float(scene.l_s),
+                         in_dim=int(np.shape(scene.weights["opacity"]["W1"])[1]))
 
 
 class AnchorRenderer:
@@ -45,7 +48,8 @@ class AnchorRenderer:
                  **opt_kw):
         self.a = anchors
         self.cams = list(cams)
-        self.dec = Decoder(anchors.A, anchors.k, anchors.n_feat, precision, anchors.l_o, anchors.l_s)
+        self.dec = Decoder(anchors.A, anchors.k, anchors.n_feat, precision, anchors.l_o, anchors.l_s,
+                           in_dim=anchors.in_dim)
         self.rc = RenderContext(self.cams, anchors.A * anchors.k, anchors.n_feat, capacity, **opt_kw)
         self.g = None
         self.images = None

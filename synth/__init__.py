@@ -28,4 +28,4 @@ from .scenes import (  # noqa: F401
     c4,
     c5,
 )
-from .maps import residual_maps, feature_inputs  # noqa: F401,E402
+from .maps import residual_maps, feature_inputs, mapping_maps, uncertainty_inputs  # noqa: F401,E402

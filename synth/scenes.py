@@ -177,7 +177,7 @@ def tiny_scene(seed: int, n: int, n_feat: int = 0, logs_mu: float = -2.3,
 
 
 def tiny_anchor_scene(seed: int, n_anchors: int = 24, k: int = 4, n_feat: int = 4,
-                      l_s: float = 0.15) -> AnchorScene:
+                      l_s: float = 0.15, in_dim: int = 35) -> AnchorScene:
     """A few anchors in front of an identity camera for brute-force and
     finite-difference checks of the decoder.
 
@@ -191,9 +191,9 @@ def tiny_anchor_scene(seed: int, n_anchors: int = 24, k: int = 4, n_feat: int = 
     xyz = np.stack([xy[:, 0] * z / 2, xy[:, 1] * z / 2, z])
     feat = rng.normal(0.0, 0.3, (n_anchors, 32))
     off = rng.normal(0.0, 0.1, (n_anchors, k, 3))
-    weights = anchor_weights(rng, k, n_feat=n_feat)
+    weights = anchor_weights(rng, k, in_dim=in_dim, n_feat=n_feat)
     return AnchorScene(xyz=_f32(xyz), feat=_f32(feat), off=_f32(off.reshape(n_anchors * k, 3).T),
-                       k=k, weights=weights, l_s=l_s)
+                       k=k, weights=weights, l_s=l_s, in_dim=in_dim)
 
 
 def room_cells(mode: str) -> np.ndarray:

@@ -100,3 +100,69 @@ def test_decoder_parameter_count():
     # per-view camera-centre partials: one row of 3 floats per 256 anchors and view
     big = L.make_decoder(100_000, 10, 16)
     assert L.decode_workspace_size(big, 2) > L.decode_workspace_size(big, 1) >= L.decode_workspace_size(d, 1)
+
+
+def test_decoder_input_widths():
+    """in_dim 35 (or 0), 36 and 38 are accepted; each extra input column adds
+    one first-layer weight per hidden unit of every present head (5 heads
+    with the feature head, 4 without); other widths are not built."""
+    for nf, heads in ((16, 5), (0, 4)):
+        base = L.decode_param_count(L.make_decoder(100, 10, nf, in_dim=35))
+        assert L.decode_param_count(L.make_decoder(100, 10, nf, in_dim=0)) == base
+        assert L.decode_param_count(L.make_decoder(100, 10, nf, in_dim=36)) == base + 32 * heads
+        assert L.decode_param_count(L.make_decoder(100, 10, nf, in_dim=38)) == base + 3 * 32 * heads
+    for bad in (37, 34, 39, 64):
+        with pytest.raises(L.AsgsError) as ei:
+            L.decode_param_count(L.make_decoder(100, 10, 16, in_dim=bad))
+        assert ei.value.status == L.E_UNSUPPORTED
+
+
+def test_pack_params_layout_round_trip():
+    """Per head: W1's first 35 columns, b1, W2, b2, then W1's extra columns;
+    unpack inverts it for every input width."""
+    import torch
+    from paper_2505_22335_amd.core import pack_params, unpack_params
+    for in_dim in (35, 36, 38):
+        w = synth.anchor_weights(np.random.default_rng(in_dim), 3, in_dim=in_dim, n_feat=16)
+        flat = pack_params(w, 3, 16, device="cpu")
+        assert flat.numel() == L.decode_param_count(L.make_decoder(10, 3, 16, in_dim=in_dim))
+        W1 = w["opacity"]["W1"]
+        assert torch.equal(flat[:35], torch.as_tensor(W1[0, :35]))
+        o = 32 * 35 + 32 + 3 * 32 + 3
+        assert torch.equal(flat[o:o + (in_dim - 35)], torch.as_tensor(W1[0, 35:]))
+        back = unpack_params(flat, 3, 16, in_dim)
+        for h in w:
+            for key in w[h]:
+                assert np.array_equal(back[h][key].numpy(), w[h][key]), (in_dim, h, key)
+
+
+def test_bad_frame_time_rejected():
+    cam = synth.camera_c2()
+    bad = synth.Camera(cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy, cam.T_wc, t=float("inf"))
+    with pytest.raises(L.AsgsError) as ei:
+        L.render_ctx_size([bad], 100, L.make_opts(16), 10)
+    assert "frame time" in str(ei.value)
+
+
+def test_mapping_and_uncertainty_host_checks():
+    """Size queries and argument checks of the mapping-loss, mean-scale and
+    uncertainty calls (host side, nothing launched)."""
+    b = L.mapping_work_size(2, 640, 480)
+    assert b >= 2 * 9 * 640 * 480 * 4
+    with pytest.raises(L.AsgsError) as ei:
+        L.mapping_work_size(0, 640, 480)
+    assert ei.value.status == L.E_INVALID
+    o = L.mapping_opts()
+    assert abs(o.lam - 0.8) < 1e-7 and abs(o.lam1 - 0.6) < 1e-7 and o.lam2 == 1.0 and abs(o.lam4 - 0.01) < 1e-9
+    maps = L.MappingMaps()
+    st = L.lib.asgs_mapping_loss(1, 8, 8, C.byref(o), C.byref(maps), None, None, None, None, None, 0, None)
+    assert st == L.E_INVALID and b"missing" in L.lib.asgs_last_error()
+    assert L.mean_scale_work_size() > 0
+    u = L.uncertainty_mlp(384, 34, 46)
+    assert L.uncertainty_param_count(u) == 128 * 384 + 257
+    assert L.uncertainty_workspace_size(u, 1, 640, 480) > 34 * 46 * 128 * 4
+    for bad, status in ((L.uncertainty_mlp(20, 34, 46), L.E_UNSUPPORTED), (L.uncertainty_mlp(384, 0, 46), L.E_INVALID),
+                        (L.uncertainty_mlp(384, 34, 46, sigma_min=0.0), L.E_INVALID)):
+        with pytest.raises(L.AsgsError) as ei:
+            L.uncertainty_param_count(bad)
+        assert ei.value.status == status

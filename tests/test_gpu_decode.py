@@ -29,7 +29,7 @@ def _oracle_decode(sc, cams, grads=None):
     for v, cam in enumerate(cams):
         xi = torch.zeros(6, dtype=torch.float64, requires_grad=grads is not None)
         R, tc = pose_cw(np.asarray(cam.T_wc, np.float64), xi)
-        g = oracle.decode(xyz, feat, off, W, camera_center(R, tc), sc.k, sc.l_o, sc.l_s)
+        g = oracle.decode(xyz, feat, off, W, camera_center(R, tc), sc.k, sc.l_o, sc.l_s, t=getattr(cam, "t", 0.0))
         outs.append(g)
         xis.append(xi)
     if grads is None:
@@ -46,20 +46,28 @@ def _oracle_decode(sc, cams, grads=None):
 
 
 def _cams_tiny(nv):
+    """nv views around the identity pose; frame times 0.13, 0.53, 0.93, ...
+    (read only by decoders with the temporal input)."""
     base = np.eye(3, 4, dtype=np.float32)
     return [synth.Camera(48, 40, 50.0, 50.0, 23.5, 19.5,
-                         synth.perturb_pose(base, [0.1 * v, -0.05, 0.02 * v], [0.01, -0.02 * v, 0.03]))
+                         synth.perturb_pose(base, [0.1 * v, -0.05, 0.02 * v], [0.01, -0.02 * v, 0.03]),
+                         t=0.13 + 0.4 * v)
             for v in range(nv)]
 
 
-@pytest.mark.parametrize("k,nf,nv,A", [(10, 16, 1, 77), (3, 16, 2, 77), (7, 0, 3, 77), (16, 16, 2, 77), (1, 16, 1, 77),
-                                        (10, 16, 2, 5)])
-def test_decode_forward_backward(k, nf, nv, A):
-    sc = synth.tiny_anchor_scene(50 + k, A, k=k, n_feat=nf)
+@pytest.mark.parametrize("k,nf,nv,A,in_dim", [(10, 16, 1, 77, 35), (3, 16, 2, 77, 35), (7, 0, 3, 77, 35),
+                                               (16, 16, 2, 77, 35), (1, 16, 1, 77, 35), (10, 16, 2, 5, 35),
+                                               (10, 16, 2, 77, 36), (10, 16, 3, 77, 38), (4, 0, 2, 40, 38),
+                                               (16, 16, 1, 33, 38)])
+def test_decode_forward_backward(k, nf, nv, A, in_dim):
+    """FP32 decode and its backward, including the scene-variant inputs
+    (distance, and distance plus temporal embedding, at distinct frame times
+    per view: the temporal weights' gradient sums over the views)."""
+    sc = synth.tiny_anchor_scene(50 + k, A, k=k, n_feat=nf, in_dim=in_dim)
     cams = _cams_tiny(nv)
-    log("case decode", k, nf, nv, A)
+    log("case decode", k, nf, nv, A, in_dim)
     a = anchors_to_device(sc)
-    dec = P.Decoder(a.A, k, nf, 0, a.l_o, a.l_s)
+    dec = P.Decoder(a.A, k, nf, 0, a.l_o, a.l_s, in_dim=in_dim)
     out = dec.decode(a.xyz, a.feat, a.off, a.params, cams)
     torch.cuda.synchronize()
     rng = np.random.default_rng(k)
@@ -82,7 +90,7 @@ def test_decode_forward_backward(k, nf, nv, A):
         e = rel_err(to_np(x), r)
         log("decode grad", name, "%.2e" % e)
         assert e <= DEC_TOL, name
-    W = P.unpack_params(d_params, k, nf)
+    W = P.unpack_params(d_params, k, nf, in_dim)
     for h in W:
         for key in W[h]:
             e = rel_err(to_np(W[h][key]), gr["weights"][h][key])
@@ -176,24 +184,34 @@ def test_end_to_end_config2_full(mode):
 # BF16 decoder bounds, about 2.5x the largest measured values: against the
 # bfloat16 emulation (FP32 accumulation order; an operand that lands on a
 # bfloat16 rounding tie can round the other way) and against FP64 per field
-BF16_VS_EMULATION = 1e-4
+# BF16 decode against the bfloat16 emulation: FP32 accumulation (observed
+# ~2e-7) on the anchors whose hidden activations all sit more than 2^-20 of
+# the first layer's term sizes from a bfloat16 rounding midpoint; a hidden
+# unit inside that band may round the other way in the kernel's single-
+# precision first layer (one bfloat16 spacing, ~1e-4 of the output), so the
+# anchors in the band (about 10% per head) are held to that flip scale.
+BF16_VS_EMULATION = 2e-6
+BF16_FLIP_BAND = 2.0 ** -20
+BF16_FLIP_TOL = 5e-4
 BF16_VS_FP64 = dict(opacity=2e-3, rgb=1.5e-3, scale=2e-3, rot=8e-3, feat=1e-2, mean=1e-6)
 
 
-@pytest.mark.parametrize("k,nf,nv,A", [(10, 16, 2, 300), (3, 16, 1, 300), (7, 0, 2, 300), (16, 16, 1, 300),
-                                        (1, 16, 1, 300), (10, 16, 1, 5)])
-def test_decode_bf16_matches_bf16_emulation(k, nf, nv, A):
+@pytest.mark.parametrize("k,nf,nv,A,in_dim", [(10, 16, 2, 300, 35), (3, 16, 1, 300, 35), (7, 0, 2, 300, 35),
+                                               (16, 16, 1, 300, 35), (1, 16, 1, 300, 35), (10, 16, 1, 5, 35),
+                                               (10, 16, 2, 300, 36), (10, 16, 3, 300, 38)])
+def test_decode_bf16_matches_bf16_emulation(k, nf, nv, A, in_dim):
     """BF16 matrix-core decode equals the oracle's bfloat16 emulation (same
     operand rounding, exact products, float64 sums) up to FP32 accumulation
     and rare operand-rounding flips; its error against the FP64 decode is
     logged. Gaussians per anchor from 1 to 16 (second-layer rows padded to
     tiles of 16 per head), a decoder without the feature head, and a single
-    partial tile of 5 anchors."""
-    sc = synth.tiny_anchor_scene(91 + k, A, k=k, n_feat=nf)
+    partial tile of 5 anchors; and the scene-variant inputs (distance,
+    temporal embedding), which stay FP32 like the view direction."""
+    sc = synth.tiny_anchor_scene(91 + k, A, k=k, n_feat=nf, in_dim=in_dim)
     cams = _cams_tiny(nv)
-    log("case bf16 decode", k, nf, nv, A)
+    log("case bf16 decode", k, nf, nv, A, in_dim)
     a = anchors_to_device(sc)
-    dec = P.Decoder(a.A, k, nf, 1, a.l_o, a.l_s)
+    dec = P.Decoder(a.A, k, nf, 1, a.l_o, a.l_s, in_dim=in_dim)
     out = dec.decode(a.xyz, a.feat, a.off, a.params, cams)
     torch.cuda.synchronize()
     t = lambda x: torch.as_tensor(np.asarray(x, np.float64))
@@ -201,16 +219,29 @@ def test_decode_bf16_matches_bf16_emulation(k, nf, nv, A):
     for v, cam in enumerate(cams):
         R, tc = pose_cw(np.asarray(cam.T_wc, np.float64))
         c = camera_center(R, tc)
-        g16 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s, precision="bf16")
-        g64 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s)
+        g16 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s, precision="bf16",
+                            t=cam.t)
+        g64 = oracle.decode(t(sc.xyz.T), t(sc.feat), t(sc.off.T), W, c, sc.k, sc.l_o, sc.l_s, t=cam.t)
+        margin = oracle.bf16_hidden_margin(t(sc.xyz.T), t(sc.feat), W, c, t=cam.t)
         for f in ("opacity", "rgb", "scale", "rot", "feat", "mean"):
             if f == "feat" and nf == 0:
                 continue
             x = to_np(out[f][v]) if f != "mean" else to_np(out[f])
-            e16 = rel_err(x, g16[f].numpy().T)
+            ref16 = g16[f].numpy().T
             e64 = rel_err(x, g64[f].numpy().T)
-            log("bf16 decode", v, f, "vs bf16 emulation %.2e" % e16, "vs fp64 %.2e" % e64)
-            assert e16 <= BF16_VS_EMULATION, (f, e16)
+            if f == "mean":
+                e16 = rel_err(x, ref16)
+                log("bf16 decode", v, f, "vs bf16 emulation %.2e" % e16, "vs fp64 %.2e" % e64)
+                assert e16 <= BF16_VS_EMULATION, (f, e16)
+            else:
+                band = np.repeat(margin[f] < BF16_FLIP_BAND, k)
+                keep = np.broadcast_to(~band, x.shape)
+                e16 = rel_err(x, ref16, keep)
+                eb = rel_err(x, ref16)
+                log("bf16 decode", v, f, "vs bf16 emulation %.2e (band %.1f%%, all %.2e)" % (e16, 100 * band.mean(), eb),
+                    "vs fp64 %.2e" % e64)
+                assert e16 <= BF16_VS_EMULATION, (f, e16)
+                assert eb <= BF16_FLIP_TOL and band.mean() <= 0.25, (f, eb, band.mean())
             assert e64 <= BF16_VS_FP64[f], (f, e64)
 
 

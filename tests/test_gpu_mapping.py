@@ -1,0 +1,79 @@
+"""GPU: the mapping loss with SSIM and its gradients (asgs_mapping_loss;
+Sec. 3.1 Eq. 4, Sec. 3.3 Eq. 14) and the mean-scale term (asgs_mean_scale)
+against the FP64 oracle, through the C ABI.
+
+The window sums run in FP64 on the device and the SSIM backward maps are
+stored and filtered in FP32: loss within 1e-6 relative, gradients within
+MAP_TOL of their largest magnitude (max |x - ref| / max |ref|) per view.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import log, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2505_22335_amd.core import mapping_loss, mean_scale
+
+MAP_TOL = 1e-5
+LOSS_TOL = 1e-6
+
+
+def _run(m, use_cos=True, use_dyn=True, weights=None, **kw):
+    d = {k: torch.as_tensor(v).cuda() for k, v in m.items()}
+    out = mapping_loss({"rgb": d["rgb"], "depth": d["depth"]}, d["obs_rgb"], d["obs_depth"],
+                       cosine=d["cosine"] if use_cos else None, dynamic=d["dynamic"] if use_dyn else None, **kw)
+    torch.cuda.synchronize()
+    V = m["rgb"].shape[0]
+    for v in range(V):
+        ref = oracle.mapping_loss(m["rgb"][v], m["depth"][v], m["obs_rgb"][v], m["obs_depth"][v],
+                                  m["cosine"][v] if use_cos else None, m["dynamic"][v] if use_dyn else None,
+                                  weights=weights)
+        el = abs(float(out["loss"][v]) - ref["loss"]) / max(abs(ref["loss"]), 1e-12)
+        er = rel_err(to_np(out["d_rgb"][v]), ref["d_rgb"])
+        ed = rel_err(to_np(out["d_depth"][v]), ref["d_depth"])
+        msg = "loss %.2e (gpu %.8f ref %.8f) d_rgb %.2e d_depth %.2e" % (el, float(out["loss"][v]), ref["loss"], er, ed)
+        if use_cos:
+            ec = rel_err(to_np(out["d_cos"][v]), ref["d_cos"])
+            msg += " d_cos %.2e" % ec
+            assert ec <= 1e-6
+        log("mapping view", v, msg)
+        assert el <= LOSS_TOL and er <= MAP_TOL and ed <= 1e-6
+
+
+@pytest.mark.parametrize("V,H,W", [(1, 37, 53), (2, 48, 64), (1, 16, 32), (1, 480, 640), (1, 1, 1), (1, 3, 12),
+                                   (1, 40, 7)])
+def test_mapping_loss_matches_oracle(V, H, W):
+    """Ragged tiles (53 x 37 against 32 x 16), several views, the full frame,
+    and images smaller than the 11 x 11 window (zero padding everywhere)."""
+    log("case mapping", V, H, W)
+    _run(synth.mapping_maps(300 + V * H + W, V, H, W))
+
+
+def test_mapping_loss_options():
+    m = synth.mapping_maps(5, 2, 45, 70)
+    log("case mapping without cosine and mask")
+    _run(m, use_cos=False, use_dyn=False)
+    log("case mapping weights")
+    w = dict(lam=0.3, lam1=1.5, lam2=0.2, lam4=0.7)
+    _run(m, weights=w, **w)
+
+
+@pytest.mark.parametrize("count", [1, 1000, 600_000])
+def test_mean_scale(count):
+    rng = np.random.default_rng(count)
+    s = rng.uniform(0.001, 0.05, count).astype(np.float32)
+    g0 = rng.normal(size=count).astype(np.float32)
+    st, gt = torch.as_tensor(s).cuda(), torch.as_tensor(g0).cuda()
+    val = mean_scale(st, 0.01, gt)
+    torch.cuda.synchronize()
+    ref = oracle.mean_scale(s)
+    ev = abs(float(val[0]) - ref) / ref
+    step = np.float32(np.float64(np.float32(0.01)) / count)
+    eg = np.abs(to_np(gt) - (g0 + step)).max()
+    log("mean scale", count, "rel %.2e grad err %.2e" % (ev, eg))
+    assert ev <= 1e-6 and eg == 0.0

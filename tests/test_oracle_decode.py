@@ -215,3 +215,30 @@ def test_time_embedding_folds_into_bias_and_is_periodic():
         assert (g0[key] - g2[key]).abs().max() < 1e-13
     with np.testing.assert_raises(ValueError):
         decode(xyz, feat, off, _widen(w, 2), c, sc.k)
+
+
+def test_bf16_hidden_margin_hand_cases():
+    """One opacity unit fed by one feature column (weight 1, bf16 exact):
+    z = 1 + 2^-8 sits on the midpoint between the bfloat16 values 1 and
+    1 + 2^-7 (margin 0); z = 1 is half a spacing (2^-8) from the midpoints,
+    relative to the term sizes 1; z = 0 (ReLU zero) has no rounding risk."""
+    from oracle import bf16_hidden_margin
+    xyz = torch.tensor([[0.0, 0.0, 2.0], [0.0, 0.0, 3.0], [0.0, 0.0, 4.0]], dtype=F64)
+    feat = torch.zeros((3, 32), dtype=F64)
+    feat[:, 0] = torch.tensor([1.0 + 2.0 ** -8, 1.0, 0.0])
+    w = {}
+    for name, m, _ in HEAD_ORDER[:4]:
+        W1 = torch.zeros((32, 35), dtype=F64)
+        W1[0, 0] = 1.0
+        w[name] = dict(W1=W1, b1=torch.zeros(32, dtype=F64), W2=torch.zeros((m, 32), dtype=F64),
+                       b2=torch.zeros(m, dtype=F64))
+    mg = bf16_hidden_margin(xyz, feat, w, torch.zeros(3, dtype=F64))
+    # feature 1 + 2^-8 is itself rounded to bf16 (ties to even: 1.0) in layer 1, so z = 1
+    assert mg["opacity"][0] == 2.0 ** -8 and mg["opacity"][1] == 2.0 ** -8
+    assert np.isinf(mg["opacity"][2])
+    # a bias moves z onto the midpoint: b1 = 2^-8 with the feature 1 gives
+    # margin 0; alone (feature 0) z = 2^-8 is a bfloat16 value, half its
+    # spacing 2^-15 from the midpoints, relative to |b1| = 2^-8
+    w["opacity"]["b1"][0] = 2.0 ** -8
+    mg = bf16_hidden_margin(xyz, feat, w, torch.zeros(3, dtype=F64))
+    assert mg["opacity"][1] == 0.0 and mg["opacity"][2] == 2.0 ** -8
