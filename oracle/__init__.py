@@ -45,4 +45,4 @@ from .uncertainty import box3, cosine, residual, uncertainty, RESIDUAL_WEIGHTS  
 from .feature import upsample, lift, cosine_map, distill, relu_margin  # noqa: F401
 from .anchors import anchor_update  # noqa: F401
 from .mapping import (gaussian_filter, ssim_map, pixel_loss, mapping_loss, mean_scale,  # noqa: F401
-                      uncertainty_mlp, uncertainty_loss, MAPPING_WEIGHTS)
+                      uncertainty_mlp, uncertainty_loss, uncertainty_flip_bound, MAPPING_WEIGHTS)

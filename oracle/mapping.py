@@ -144,3 +144,28 @@ def uncertainty_loss(grid, W1, b1, w2, b2, R, sigma_min: float = 1e-3, lam3: flo
 def softplus_inverse(s: float) -> float:
     """y with softplus(y) = s (s > 0), for building cases with a chosen sigma."""
     return s + math.log(-math.expm1(-s))
+
+
+def uncertainty_flip_bound(grid, W1, b1, w2, b2, R, sigma_min: float = 1e-3, lam3: float = MAPPING_WEIGHTS["lam3"],
+                           band: float = 2e-5):
+    """Guard band of the ReLU decisions of F_u's hidden layer for one view:
+    a (pixel, unit) pair whose pre-activation z lies within band * (sum of
+    |terms| of z) of zero may take the other decision in single precision.
+    Returns, per parameter of F_u, the sum over such pairs of the magnitude
+    of their contribution to dL_u/dparameter (so that any mix of decisions
+    moves the gradient by at most this), and the number of pairs:
+    dict(W1 (128, N_h), b1 (128), w2 (128), b2 0.0, pairs)."""
+    H, W = np.shape(R)
+    F = upsample(grid, H, W).numpy().reshape(-1, H * W)
+    W1 = np.asarray(W1, np.float64)
+    b1 = np.asarray(b1, np.float64)
+    w2 = np.asarray(w2, np.float64)
+    Z = W1 @ F + b1[:, None]
+    near = np.abs(Z) <= band * (np.abs(W1) @ np.abs(F) + np.abs(b1)[:, None])
+    y = w2 @ np.maximum(Z, 0.0) + float(b2)
+    sig = sigma_min + np.logaddexp(0.0, y)
+    Rf = np.asarray(R, np.float64).reshape(-1)
+    dy = (-Rf / sig ** 3 + lam3 / sig) / (H * W) / (1.0 + np.exp(-y))
+    A = near * np.abs(dy)[None, :] * np.abs(w2)[:, None]
+    return dict(W1=A @ np.abs(F).T, b1=A.sum(1), w2=(near * np.abs(dy)[None, :] * np.abs(Z)).sum(1), b2=0.0,
+                pairs=int(near.sum()))

@@ -189,3 +189,28 @@ def test_uncertainty_loss_gradients_by_finite_differences():
             fd = (f(1e-6) - f(-1e-6)) / 2e-6
             an = np.reshape(r["grads"][name], -1)[idx]
             assert abs(fd - an) <= 1e-8 + 1e-6 * abs(an), (name, idx, fd, an)
+
+
+def test_uncertainty_flip_bound_hand_case():
+    """1 x 1 image, one patch with feature (2, -1): unit 0 has z = 2 - 2 = 0
+    (in the band), unit 1 z = 2 (far), the others z = b1 = 1. The bound of
+    dW1[0] is |dy w2_0| |F| = |dy| 0.5 (2, 1) and of db1[0] |dy| 0.5, with dy
+    from sigma = sigma_min + softplus(w2 . relu(z) + b2); nothing else."""
+    from oracle.mapping import uncertainty_flip_bound
+    grid = np.array([2.0, -1.0]).reshape(2, 1, 1)
+    W1 = np.zeros((128, 2))
+    W1[0] = (1.0, 0.0)
+    W1[1] = (1.0, 1.0)
+    b1 = np.ones(128)
+    b1[0] = -2.0
+    w2 = np.full(128, 0.01)
+    w2[0] = 0.5
+    R = np.array([[0.3]])
+    b = uncertainty_flip_bound(grid, W1, b1, w2, 0.1, R)
+    y = 0.01 * (126 + 2) + 0.1  # unit 0 contributes relu(0) = 0
+    sig = 1e-3 + math.log1p(math.exp(y))
+    dy = (-0.3 / sig ** 3 + MAPPING_WEIGHTS["lam3"] / sig) / (1 + math.exp(-y))
+    assert b["pairs"] == 1
+    assert np.allclose(b["W1"][0], abs(dy) * 0.5 * np.array([2.0, 1.0]), rtol=1e-14, atol=0)
+    assert abs(b["b1"][0] - abs(dy) * 0.5) < 1e-15 and not np.any(b["W1"][1:]) and not np.any(b["b1"][1:])
+    assert not np.any(b["w2"])  # |z| = 0 for the banded pair
