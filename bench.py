@@ -57,6 +57,40 @@ def algorithmic_bytes(I, nvis, N, A, P, nf=16, l1=True):
     }
 
 
+def mapping_bytes(P, cells, nh=384, nl=16):
+    """Minimum bytes of the mapping-iteration kernels (per launch): the
+    feature lift reads the rendered low-dimensional feature and the DINO
+    patch grid and writes the cosine (the backward also reads the upstream
+    cosine gradient and writes the feature gradient); the mapping loss reads
+    rendered and observed colour and depth, the cosine and the mask and
+    writes the colour, depth and cosine gradients; the uncertainty MLP reads
+    the grid and R and writes sigma and the mask."""
+    grid = cells * nh * 4
+    return {
+        "feature": P * 4 * (nl + 1) + grid,
+        "feature_bwd": P * 4 * (nl + 1 + nl) + grid,
+        "mapping": P * (4 * (3 + 3 + 1 + 1 + 1 + 3 + 1 + 1) + 1),
+        "uncertainty": P * (4 + 4 + 1) + grid,
+    }
+
+
+def mapping_ops(P, cells, nh=384, nl=16):
+    """Operation lower bounds of the mapping-iteration kernels: the feature
+    lift's first layer per pixel (nl x 128 FMAs, vector) and its second layer
+    as the Gram form hT M h (128 x 128, matrix cores; bf16 with three split
+    products), the backward twice that; the SSIM window sums (5 maps x 2
+    separable 11-tap passes x 3 channels, FP64 at the FP32 vector rate) and
+    the backward filter (3 maps x 22 taps x 3 channels); the uncertainty MLP's
+    first layer once per patch (nh x 128) and per pixel the interpolation and
+    second layer (128 x 6), twice with the gradient."""
+    return {
+        "feature": {"valu": P * nl * 128, "mfma": P * 2 * 128 * 128 * 3, "mfma_type": "bf16"},
+        "feature_bwd": {"valu": 2 * P * nl * 128, "mfma": 2 * P * 2 * 128 * 128 * 3, "mfma_type": "bf16"},
+        "mapping": {"valu": P * (5 * 22 * 3 + 3 * 22 * 3)},
+        "uncertainty": {"valu": cells * nh * 128 + 2 * P * 128 * 6},
+    }
+
+
 def algorithmic_ops(A, k, V, N, evals, nf=16, precision=0):
     """Lower bounds on the arithmetic of each kernel class (per launch):
     vector lane-op slots (an FMA is one slot, an exponential four) and
@@ -277,6 +311,59 @@ def serving_c5(warmup_s=2.0, measure_s=20.0, burst_s=1.0, seed=5, log=None):
     return out
 
 
+def time_mapping_kernels(r, V, H, W, seed, reps=10):
+    """The mapping iteration's kernels on the step's rendered maps (not part
+    of the timed step): feature lift forward and backward (N_h 384 on the
+    34 x 46 DINO grid of a 476 x 644 crop), the mapping loss with SSIM and
+    its gradients, and the uncertainty MLP with L_u's gradient; per class the
+    mean launch time from the library's per-launch events."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2505_22335_amd import _lib as L
+    from paper_2505_22335_amd.core import FeatureLift, UncertaintyMLP, mapping_loss
+
+    gh, gw, nh = 34, 46, 384
+    dev = lambda a: torch.as_tensor(a).cuda()
+    fi = synth.feature_inputs(seed + 300, V, H, W, gh, gw, nh)
+    fparams = dev(np.concatenate([fi["W1"].ravel(), fi["b1"], fi["W2"].ravel(), fi["b2"]]))
+    fl = FeatureLift(V, W, H, nh, gh, gw)
+    feat = r.images["feat"].contiguous()
+    dino = dev(fi["dino"])
+    mm = synth.mapping_maps(seed + 301, V, H, W)
+    ui = synth.uncertainty_inputs(seed + 302, V, H, W, gh, gw, nh)
+    uparams = dev(np.concatenate([ui["W1"].ravel(), ui["b1"], ui["w2"], ui["b2"]]))
+    um = UncertaintyMLP(V, W, H, nh, gh, gw)
+    R = dev(ui["R"])
+    obs_rgb, obs_depth, dyn = dev(mm["obs_rgb"]), dev(mm["obs_depth"]), dev(mm["dynamic"])
+    out = fl.forward(feat, fparams, dino)
+    cos = out["cosine"] if isinstance(out, dict) else out[0]
+    classes = (L.K_FEATURE, L.K_FEATURE_BWD, L.K_MAPPING, L.K_UNCERTAINTY)
+    mask = 0
+    for c in classes:
+        mask |= 1 << c
+    L.profile_enable(mask)
+    torch.cuda._sleep(20_000_000)
+    for _ in range(reps):
+        fl.forward(feat, fparams, dino)
+        ml = mapping_loss({"rgb": r.images["rgb"], "depth": r.images["depth"]}, obs_rgb, obs_depth, cosine=cos,
+                          dynamic=dyn)
+        fl.backward(feat, fparams, dino, ml["d_cos"])
+        um(uparams, dino, R)
+    torch.cuda.synchronize()
+    P, cells = V * H * W, V * gh * gw
+    ab, ops = mapping_bytes(P, cells, nh), mapping_ops(P, cells, nh)
+    br = {}
+    for c, nm in zip(classes, ("feature", "feature_bwd", "mapping", "uncertainty")):
+        t, n = L.profile_read(c)
+        if n:
+            br[nm] = roofline_entry(t / n, ab[nm], ops[nm])
+            br[nm]["note"] = "mapping iteration on the step's maps (not part of the timed step)"
+    L.profile_enable(0)
+    return br
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,6 +536,7 @@ def main():
     L.profile_enable(0)
     br["blend_fwd"]["note"] = "includes the fused L1 residual gradient of the step"
     br["residual"]["note"] = "tracking residual + uncertainty on the step's maps (not part of the timed step)"
+    br.update(time_mapping_kernels(r, V, H, W, wl["seed"]))
     res["kernels"] = br
     res["config"]["pixel_evaluations"] = evals
     if args.serve_seconds > 0:

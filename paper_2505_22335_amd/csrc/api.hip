@@ -664,7 +664,7 @@ int asgs_uncertainty_workspace_size(const asgs_uncertainty_mlp* u, int32_t n_vie
   if (st) return st;
   if ((st = check_maps_size(n_views, width, height, "uncertainty_workspace_size"))) return st;
   if (!bytes) return fail(ASGS_E_INVALID, "bytes is NULL");
-  *bytes = uncertainty_layout(n_views, width, height, u->grid_h, u->grid_w).total;
+  *bytes = uncertainty_layout(n_views, width, height, u->grid_h, u->grid_w, u->n_high).total;
   return ASGS_OK;
 }
 
@@ -680,7 +680,7 @@ int asgs_uncertainty(const asgs_uncertainty_mlp* u, int32_t n_views, int32_t wid
   if (!params || !dino) return fail(ASGS_E_INVALID, "uncertainty: params and dino are required");
   if ((loss || d_params) && !R) return fail(ASGS_E_INVALID, "uncertainty: loss and d_params need R");
   if (!sigma && !dynamic && !loss && !d_params) return fail(ASGS_E_INVALID, "uncertainty: no output requested");
-  const UncLayout L = uncertainty_layout(n_views, width, height, u->grid_h, u->grid_w);
+  const UncLayout L = uncertainty_layout(n_views, width, height, u->grid_h, u->grid_w, u->n_high);
   if (!work || work_bytes < L.total) return fail(ASGS_E_WORKSPACE, "uncertainty needs %zu bytes of work", L.total);
   UncArgs a{};
   a.V = n_views;

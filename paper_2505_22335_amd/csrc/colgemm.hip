@@ -1,0 +1,99 @@
+// Split-K products over rows, for the parameter gradients and Gram matrices of
+// the per-pixel MLPs (feature lift and uncertainty MLP):
+//   out[col][k] = sum_r D[r][col] F_k(r)
+// where r runs over (view, patch) rows, D is a row-major table (one row per
+// r) and F_k(r) a strided view of the DINO grid or of a weight matrix, with an
+// optional extra row from a vector (tail) and an optional row of ones (so that
+// out[col][.] also holds sum_r D[r][col]). The rows are cut into nsplit
+// contiguous chunks; each workgroup forms a 64-column x 32-row tile of one
+// chunk's partial product from LDS-staged blocks of D and F, and a second
+// kernel adds the chunks' partials in chunk order (deterministic).
+#include "internal.h"
+
+namespace asgs {
+
+namespace {
+
+constexpr int kCT = 64;   // columns per workgroup
+constexpr int kKT = 32;   // k per workgroup
+constexpr int kRB = 32;   // rows per staged block
+
+ASGS_DEV float fval(const ColGemm& g, int k, int64_t r) {
+  const int64_t v = r / g.rows, c = r - v * g.rows;
+  if (k < g.nk) return g.F[v * g.fview + (int64_t)k * g.fk + c * g.fr];
+  if (g.tail && k == g.nk) return g.tail[c];
+  return 1.f;  // the row of ones
+}
+
+__global__ void __launch_bounds__(256) k_colgemm_part(ColGemm g) {
+  __shared__ float ds[kRB][kCT + 1];
+  __shared__ float fs[kKT][kRB + 1];
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.x * kCT, k0 = blockIdx.y * kKT, s = blockIdx.z;
+  const int col = c0 + (t & (kCT - 1)), kq = t >> 6;
+  const int nkt = g.nk + (g.tail ? 1 : 0) + (g.ones ? 1 : 0);
+  const int64_t R = (int64_t)g.V * g.rows;
+  const int64_t r0 = R * s / g.nsplit, r1 = R * (s + 1) / g.nsplit;
+  float acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  for (int64_t rb = r0; rb < r1; rb += kRB) {
+    __syncthreads();
+    for (int q = t; q < kRB * kCT; q += 256) {
+      const int rr = q / kCT, cc = q - rr * kCT;
+      const int64_t r = rb + rr;
+      ds[rr][cc] = r < r1 && c0 + cc < g.ncol ? g.D[r * g.dstride + c0 + cc] : 0.f;
+    }
+    for (int q = t; q < kKT * kRB; q += 256) {
+      const int kk = q / kRB, rr = q - kk * kRB;
+      const int64_t r = rb + rr;
+      fs[kk][rr] = r < r1 && k0 + kk < nkt ? fval(g, k0 + kk, r) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < kRB; ++rr) {
+      const float d = ds[rr][t & (kCT - 1)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[i] = fmaf(d, fs[kq * 8 + i][rr], acc[i]);
+    }
+  }
+  if (col >= g.ncol) return;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = k0 + kq * 8 + i;
+    if (k < nkt) g.part[((int64_t)s * g.ncol + col) * nkt + k] = acc[i];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_colgemm_reduce(ColGemm g, float* out) {
+  const int nkt = g.nk + (g.tail ? 1 : 0) + (g.ones ? 1 : 0);
+  const int64_t n = (int64_t)g.ncol * nkt;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  float s = 0.f;
+  for (int b = 0; b < g.nsplit; ++b) s += g.part[(int64_t)b * n + e];
+  out[e] = s;
+}
+
+}  // namespace
+
+int colgemm_splits(int64_t rows) {
+  const int64_t s = rows / 48;
+  return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
+}
+
+size_t colgemm_part_floats(const ColGemm& g) {
+  const int nkt = g.nk + (g.tail ? 1 : 0) + (g.ones ? 1 : 0);
+  return (size_t)g.nsplit * g.ncol * nkt;
+}
+
+void launch_colgemm(const ColGemm& g, float* out, hipStream_t s) {
+  const int nkt = g.nk + (g.tail ? 1 : 0) + (g.ones ? 1 : 0);
+  hipLaunchKernelGGL(k_colgemm_part, dim3((unsigned)((g.ncol + kCT - 1) / kCT), (unsigned)((nkt + kKT - 1) / kKT),
+                                          (unsigned)g.nsplit),
+                     dim3(256), 0, s, g);
+  const int64_t n = (int64_t)g.ncol * nkt;
+  hipLaunchKernelGGL(k_colgemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, out);
+}
+
+}  // namespace asgs

@@ -264,14 +264,15 @@ ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCel
 }
 
 // ---------------------------------------------------------------------------
-// Preparation: M as bfloat16 hi/lo A fragments, m and mu; per patch Q, beta
-// and the dot products with its right, lower and lower-right neighbours and
-// of its right and lower neighbours.
+// Preparation: M = W2^T W2 and m = W2^T b2 come from the split-K product
+// (colgemm.hip) as gm = [128][129]; here M becomes bfloat16 hi/lo A
+// fragments, and mu = b2 . b2 is summed (one workgroup, fixed order). Per
+// patch (k_feat_cells): Q, beta and the dot products with its right, lower
+// and lower-right neighbours and of its right and lower neighbours.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_feat_gram(FeatArgs a, uint16_t* mfrag, float* mvec) {
+__global__ void __launch_bounds__(256) k_feat_frag(FeatArgs a, const float* __restrict__ gm, uint16_t* mfrag,
+                                                   float* mvec) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const float* W2 = a.params + kFHid * kFIn + kFHid;
-  const float* b2 = W2 + (int64_t)a.nh * kFHid;
   if (e < kFrag / 2) {
     // fragment (mb, kb), lane, element i: row unit 32 (rr/4) + 4 mb + rr%4 (rr = lane & 15),
     // column unit 32 (lane/16) + 8 kb + i
@@ -279,21 +280,21 @@ __global__ void __launch_bounds__(256) k_feat_gram(FeatArgs a, uint16_t* mfrag, 
     const int rr = lane & 15;
     const int ru = 32 * (rr >> 2) + 4 * mb + (rr & 3);
     const int cu = 32 * (lane >> 4) + 8 * kb + i;
-    float acc = 0.f;
-    for (int c = 0; c < a.nh; ++c) acc = fmaf(W2[(int64_t)c * kFHid + ru], W2[(int64_t)c * kFHid + cu], acc);
     uint16_t hi, lo;
-    bf_split(acc, hi, lo);
+    bf_split(gm[ru * (kFHid + 1) + cu], hi, lo);
     mfrag[((mb * 4 + kb) * 2 + 0) * 512 + lane * 8 + i] = hi;
     mfrag[((mb * 4 + kb) * 2 + 1) * 512 + lane * 8 + i] = lo;
   }
-  if (e < kFHid) {
+  if (e < kFHid) mvec[e] = gm[e * (kFHid + 1) + kFHid];
+  if (blockIdx.x == 0) {
+    __shared__ float red[4];
+    const float* b2 = a.params + kFHid * kFIn + kFHid + (int64_t)a.nh * kFHid;
     float acc = 0.f;
-    for (int c = 0; c < a.nh; ++c) acc = fmaf(W2[(int64_t)c * kFHid + e], b2[c], acc);
-    mvec[e] = acc;
-  } else if (e == kFHid) {
-    float acc = 0.f;
-    for (int c = 0; c < a.nh; ++c) acc = fmaf(b2[c], b2[c], acc);
-    mvec[kFHid] = acc;
+    for (int c = threadIdx.x; c < a.nh; c += 256) acc = fmaf(b2[c], b2[c], acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) mvec[kFHid] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
 
@@ -635,18 +636,12 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
   if (threadIdx.x == 0) part[16384 + 2048 + 256] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Sums of the workgroup partials: S + S^T, dW1^T, db1, dm, dmu (fixed order).
+// Sums of the workgroup partials: S, dW1^T, db1, dm, dmu (fixed order).
 __global__ void __launch_bounds__(256) k_feat_reduce(const float* __restrict__ part, int nwg, float* out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kPart) return;
   float s = 0.f;
   for (int b = 0; b < nwg; ++b) s += part[(int64_t)b * kPartStride + e];
-  if (e < 16384) {
-    const int r = e >> 7, c = e & 127;
-    float s2 = 0.f;
-    for (int b = 0; b < nwg; ++b) s2 += part[(int64_t)b * kPartStride + c * 128 + r];
-    s = s + s2;  // symmetric: the (c, r) entry adds the same two sums
-  }
   out[e] = s;
 }
 
@@ -668,15 +663,18 @@ __global__ void __launch_bounds__(kDQ) k_feat_cell_reduce(FeatArgs a, float* dqc
   dqc[((int64_t)view * a.Hp * a.Wp + cell) * kDQ + k] = s;
 }
 
-// Parameter gradients: one workgroup per output channel of W2 (row ch of dW2
-// and db2[ch]); the last workgroup writes dW1 and db1.
+// Parameter gradients: one workgroup per output channel ch of W2, thread j:
+//   dW2[ch][j] = (sum_c G_c[ch] dQ_c[j]) + sum_u W2[ch][u] (S[u][j] + S[j][u]) + b2[ch] dm[j]
+//   db2[ch]    = (sum_c G_c[ch] dbeta_c) + W2[ch] . dm + 2 dmu b2[ch]
+// with the patch sums gq = [129][nh] from the split-K product (colgemm.hip);
+// the last workgroup writes dW1 and db1.
 __global__ void __launch_bounds__(kFHid) k_feat_params(FeatArgs a, const float* __restrict__ red,
-                                                      const float* __restrict__ dqc, float* d_params) {
+                                                      const float* __restrict__ gq, float* d_params) {
   __shared__ float sred[2];
   const int ch = blockIdx.x, j = threadIdx.x;
   const float* W2 = a.params + kFHid * kFIn + kFHid;
   const float* b2 = W2 + (int64_t)a.nh * kFHid;
-  const float* Ssym = red;
+  const float* S = red;
   const float* dW1t = red + 16384;
   const float* db1 = red + 16384 + 2048;
   const float* dm = db1 + 128;
@@ -686,25 +684,51 @@ __global__ void __launch_bounds__(kFHid) k_feat_params(FeatArgs a, const float* 
     d_params[kFHid * kFIn + j] = db1[j];
     return;
   }
-  const int64_t plane = (int64_t)a.Hp * a.Wp;
-  float acc = 0.f, accb = 0.f;
-  for (int v = 0; v < a.V; ++v) {
-    const float* G = a.dino + ((int64_t)v * a.nh + ch) * plane;
-    const float* D = dqc + (int64_t)v * plane * kDQ;
-    for (int64_t c = 0; c < plane; ++c) acc = fmaf(G[c], D[c * kDQ + j], acc);
-    for (int64_t c = j; c < plane; c += kFHid) accb = fmaf(G[c], D[c * kDQ + kFHid], accb);
-  }
   const float* w2 = W2 + (int64_t)ch * kFHid;
   float acc2 = 0.f;
-  for (int u = 0; u < kFHid; ++u) acc2 = fmaf(w2[u], Ssym[u * kFHid + j], acc2);
+  for (int u = 0; u < kFHid; ++u) acc2 = fmaf(w2[u], S[u * kFHid + j] + S[j * kFHid + u], acc2);
   float* dW2 = d_params + kFHid * kFIn + kFHid;
-  dW2[(int64_t)ch * kFHid + j] = fmaf(b2[ch], dm[j], acc + acc2);
-  // db2[ch] = sum_c dbeta_c G_c[ch] + W2[ch] . dm + 2 dmu b2[ch]
-  accb = fmaf(w2[j], dm[j], accb);
+  dW2[(int64_t)ch * kFHid + j] = fmaf(b2[ch], dm[j], gq[(int64_t)j * a.nh + ch] + acc2);
+  float accb = w2[j] * dm[j];
   for (int o = 32; o > 0; o >>= 1) accb += __shfl_xor(accb, o);
   if ((j & 63) == 0) sred[j >> 6] = accb;
   __syncthreads();
-  if (j == 0) dW2[(int64_t)a.nh * kFHid + ch] = (sred[0] + sred[1]) + 2.f * dmu * b2[ch];
+  if (j == 0)
+    dW2[(int64_t)a.nh * kFHid + ch] = gq[(int64_t)kFHid * a.nh + ch] + (sred[0] + sred[1]) + 2.f * dmu * b2[ch];
+}
+
+ColGemm gram_gemm(const FeatArgs& a) {
+  ColGemm g{};
+  const float* W2 = a.params + kFHid * kFIn + kFHid;
+  g.D = W2;
+  g.dstride = kFHid;
+  g.ncol = kFHid;
+  g.F = W2;
+  g.fk = 1;
+  g.fr = kFHid;
+  g.fview = 0;
+  g.nk = kFHid;
+  g.tail = W2 + (int64_t)a.nh * kFHid;  // b2: the column m = W2^T b2
+  g.V = 1;
+  g.rows = a.nh;
+  g.nsplit = colgemm_splits(a.nh);
+  return g;
+}
+
+ColGemm dq_gemm(const FeatArgs& a, const float* dqc) {
+  ColGemm g{};
+  g.D = dqc;
+  g.dstride = kDQ;
+  g.ncol = kDQ;
+  g.F = a.dino;
+  g.fk = (int64_t)a.Hp * a.Wp;
+  g.fr = 1;
+  g.fview = (int64_t)a.nh * a.Hp * a.Wp;
+  g.nk = a.nh;
+  g.V = a.V;
+  g.rows = a.Hp * a.Wp;
+  g.nsplit = colgemm_splits((int64_t)a.V * a.Hp * a.Wp);
+  return g;
 }
 
 }  // namespace
@@ -727,8 +751,16 @@ FeatLayout feature_layout(int nh, int n_views, int width, int height, int Hp, in
   L.dqt = take((size_t)tiles * kSlots * kDQ * 4);
   L.red = take((size_t)kPart * 4);
   L.dqc = take((size_t)cells * kDQ * 4);
+  FeatArgs ga{};
+  ga.V = n_views;
+  ga.Hp = Hp;
+  ga.Wp = Wp;
+  ga.nh = nh;
+  L.gpart = take(colgemm_part_floats(gram_gemm(ga)) * 4);
+  L.gout = take((size_t)kFHid * (kFHid + 1) * 4);
+  L.ppart = take(colgemm_part_floats(dq_gemm(ga, nullptr)) * 4);
+  L.pout = take((size_t)kDQ * nh * 4);
   L.total = o;
-  (void)nh;
   return L;
 }
 
@@ -771,7 +803,11 @@ FeatArgs feat_args(const FeatCall& c, const FeatLayout& L, char* work) {
 }
 
 void launch_prep(const FeatArgs& a, const FeatLayout& L, char* work, hipStream_t s) {
-  hipLaunchKernelGGL(k_feat_gram, dim3((kFrag / 2 + 255) / 256), dim3(256), 0, s, a,
+  ColGemm g = gram_gemm(a);
+  g.part = reinterpret_cast<float*>(work + L.gpart);
+  float* gm = reinterpret_cast<float*>(work + L.gout);
+  launch_colgemm(g, gm, s);
+  hipLaunchKernelGGL(k_feat_frag, dim3((kFrag / 2 + 255) / 256), dim3(256), 0, s, a, (const float*)gm,
                      reinterpret_cast<uint16_t*>(work + L.mfrag), reinterpret_cast<float*>(work + L.mvec));
   hipLaunchKernelGGL(k_feat_cells, dim3((unsigned)(a.Hp * a.Wp), (unsigned)a.V), dim3(128), 0, s, a,
                      reinterpret_cast<float*>(work + L.cells));
@@ -796,7 +832,12 @@ void launch_feature_backward(const FeatCall& c, const FeatLayout& L, char* work,
   hipLaunchKernelGGL(k_feat_reduce, dim3((kPart + 255) / 256), dim3(256), 0, s, a.part, nwg, red);
   float* dqc = reinterpret_cast<float*>(work + L.dqc);
   hipLaunchKernelGGL(k_feat_cell_reduce, dim3((unsigned)(a.Hp * a.Wp), (unsigned)a.V), dim3(kDQ), 0, s, a, dqc);
-  hipLaunchKernelGGL(k_feat_params, dim3((unsigned)(a.nh + 1)), dim3(kFHid), 0, s, a, red, dqc, c.dparams);
+  ColGemm g = dq_gemm(a, dqc);
+  g.part = reinterpret_cast<float*>(work + L.ppart);
+  float* gq = reinterpret_cast<float*>(work + L.pout);
+  launch_colgemm(g, gq, s);
+  hipLaunchKernelGGL(k_feat_params, dim3((unsigned)(a.nh + 1)), dim3(kFHid), 0, s, a, red, (const float*)gq,
+                     c.dparams);
 }
 
 }  // namespace asgs

@@ -179,7 +179,7 @@ void launch_residual(const ResidualArgs& a, int n_views, float* xi, hipStream_t 
 
 // Feature lift and cosine distillation (feature.hip).
 struct FeatLayout {
-  size_t mfrag, mvec, cells, tile_loss, part, dqt, red, dqc, total;
+  size_t mfrag, mvec, cells, tile_loss, part, dqt, red, dqc, gpart, gout, ppart, pout, total;
 };
 struct FeatCall {
   int32_t n_views, width, height, nh, Hp, Wp;
@@ -191,6 +191,27 @@ FeatLayout feature_layout(int nh, int n_views, int width, int height, int Hp, in
 int feature_max_patch_span(int width, int height, int Hp, int Wp);
 void launch_feature_forward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s);
 void launch_feature_backward(const FeatCall& c, const FeatLayout& L, char* work, hipStream_t s);
+
+// Split-K products over (view, patch) rows (colgemm.hip):
+//   out[col][k] = sum_r D[r * dstride + col] F_k(r),  r = v * rows + c,
+//   F_k(r) = F[v * fview + k * fk + c * fr] (k < nk), tail[c] (k = nk, if tail),
+//   1 (the last k, if ones); out is [ncol][nk (+1) (+1)].
+struct ColGemm {
+  const float* D;
+  int64_t dstride;
+  int32_t ncol;
+  const float* F;
+  int64_t fk, fr, fview;
+  int32_t nk;
+  const float* tail;
+  int32_t ones;
+  int32_t V, rows;
+  int32_t nsplit;
+  float* part;  // work: colgemm_part_floats
+};
+int colgemm_splits(int64_t rows);
+size_t colgemm_part_floats(const ColGemm& g);
+void launch_colgemm(const ColGemm& g, float* out, hipStream_t s);
 
 // Mapping loss with SSIM and the mean-scale term (mapping.hip).
 struct MappingArgs {
@@ -229,9 +250,9 @@ struct UncArgs {
   float* dzc;                       // work: [V][Hp * Wp][128] dZ per patch
 };
 struct UncLayout {
-  size_t zg, partial, dzt, w2t, dzc, total;
+  size_t zg, partial, dzt, w2t, dzc, gpart, gout, total;
 };
-UncLayout uncertainty_layout(int n_views, int width, int height, int Hp, int Wp);
+UncLayout uncertainty_layout(int n_views, int width, int height, int Hp, int Wp, int nh);
 void launch_uncertainty(UncArgs a, const UncLayout& L, char* work, float* loss, float* d_params, hipStream_t s);
 
 // Probabilistic anchor update (anchor.hip); n_keep (device, may be NULL) is zeroed first.

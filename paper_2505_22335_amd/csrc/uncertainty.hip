@@ -33,8 +33,8 @@ constexpr int kT = 16;        // pixel tile side
 constexpr int kSlots = 16;    // patches one tile reaches (4 x 4 at most)
 constexpr int kZS = kHid + 1; // LDS row of one patch's 128 values (padded)
 constexpr int kGC = 16;       // patches per workgroup of the grid contraction
-constexpr int kKC = 32;       // input channels per staged chunk
-constexpr int kPG = 16;       // input channels per workgroup of the weight gradient
+constexpr int kGU = 16;       // hidden units per workgroup of the grid contraction
+constexpr int kKC = 64;       // input channels per staged block
 
 struct TileCells {
   int cy0, ncy, cx0, ncx;
@@ -57,44 +57,47 @@ ASGS_DEV TileCells tile_cells(const UncArgs& a, int tx, int ty) {
   return t;
 }
 
-// Z_c = W1 F_c + b1 for kGC patches of one view: thread (u, half) keeps 8
-// patches' sums; weight and feature chunks staged in LDS.
+// Z_c = W1 F_c + b1: one workgroup per 16 patches x 16 hidden units of a
+// view, one (patch, unit) per thread; weight and feature blocks of kKC input
+// channels staged in LDS, the next block's loads issued before the current
+// block is used.
 __global__ void __launch_bounds__(256) k_fu_grid(UncArgs a) {
-  __shared__ float w1s[kHid][kKC + 1];
+  __shared__ float ws[kGU][kKC + 1];
   __shared__ float fs[kKC][kGC];
-  const int v = blockIdx.y;
+  const int v = blockIdx.z;
   const int plane = a.Hp * a.Wp;
-  const int c0 = blockIdx.x * kGC;
+  const int c0 = blockIdx.x * kGC, u0 = blockIdx.y * kGU;
   const int t = threadIdx.x;
-  const int u = t & (kHid - 1), half = t >> 7;
+  const int pc = t & (kGC - 1), uu = t / kGC;
   const float* F = a.dino + (int64_t)v * a.nh * plane;
-  float acc[kGC / 2];
+  constexpr int kPer = kGU * kKC / 256;  // staged values of each block per thread
+  float wn[kPer], fn[kPer];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int j = 0; j < kGC / 2; ++j) acc[j] = 0.f;
+    for (int i = 0; i < kPer; ++i) {
+      const int q = t + 256 * i;
+      const int r = q / kKC, c = q - r * kKC;  // weight block: unit r, channel c
+      wn[i] = k0 + c < a.nh ? a.params[(int64_t)(u0 + r) * a.nh + k0 + c] : 0.f;
+      const int kk = q / kGC, pp = q - kk * kGC;  // feature block: channel kk, patch pp
+      fn[i] = k0 + kk < a.nh && c0 + pp < plane ? F[(int64_t)(k0 + kk) * plane + c0 + pp] : 0.f;
+    }
+  };
+  float acc = 0.f;
+  load(0);
   for (int k0 = 0; k0 < a.nh; k0 += kKC) {
-    __syncthreads();
-    for (int q = t; q < kHid * kKC; q += 256) {
-      const int r = q / kKC, c = q - r * kKC;
-      w1s[r][c] = k0 + c < a.nh ? a.params[(int64_t)r * a.nh + k0 + c] : 0.f;
-    }
-    for (int q = t; q < kKC * kGC; q += 256) {
-      const int k = q / kGC, c = q - k * kGC;
-      fs[k][c] = c0 + c < plane && k0 + k < a.nh ? F[(int64_t)(k0 + k) * plane + c0 + c] : 0.f;
+    __syncthreads();  // the previous block has been read
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int q = t + 256 * i;
+      ws[q / kKC][q % kKC] = wn[i];
+      fs[q / kGC][q % kGC] = fn[i];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < kKC; ++k) {
-      const float w = w1s[u][k];
-#pragma unroll
-      for (int j = 0; j < kGC / 2; ++j) acc[j] = fmaf(w, fs[k][half * (kGC / 2) + j], acc[j]);
-    }
+    if (k0 + kKC < a.nh) load(k0 + kKC);
+#pragma unroll 8
+    for (int k = 0; k < kKC; ++k) acc = fmaf(ws[uu][k], fs[k][pc], acc);
   }
-  const float b1 = a.params[(int64_t)kHid * a.nh + u];
-#pragma unroll
-  for (int j = 0; j < kGC / 2; ++j) {
-    const int c = c0 + half * (kGC / 2) + j;
-    if (c < plane) a.zg[((int64_t)v * plane + c) * kHid + u] = acc[j] + b1;
-  }
+  if (c0 + pc < plane) a.zg[((int64_t)v * plane + c0 + pc) * kHid + u0 + uu] = acc + a.params[(int64_t)kHid * a.nh + u0 + uu];
 }
 
 struct PixShared {
@@ -240,41 +243,33 @@ __global__ void __launch_bounds__(kHid) k_fu_cell_reduce(UncArgs a) {
   a.dzc[((int64_t)v * a.Hp * a.Wp + cell) * kHid + u] = s;
 }
 
-// Parameter gradients: workgroup g < nh / kPG forms dW1[u][16 g .. 16 g + 15]
-// (thread u, sums over views and patches); the last one db1, dw2, db2.
-__global__ void __launch_bounds__(kHid) k_fu_params(UncArgs a, float* d_params) {
-  const int g = blockIdx.x, u = threadIdx.x;
-  const int plane = a.Hp * a.Wp;
-  if (g * kPG < a.nh) {
-    float acc[kPG];
-#pragma unroll
-    for (int j = 0; j < kPG; ++j) acc[j] = 0.f;
-    for (int v = 0; v < a.V; ++v) {
-      const float* F = a.dino + ((int64_t)v * a.nh + g * kPG) * plane;
-      const float* D = a.dzc + (int64_t)v * plane * kHid;
-      for (int c = 0; c < plane; ++c) {
-        const float d = D[(int64_t)c * kHid + u];
-#pragma unroll
-        for (int j = 0; j < kPG; ++j) acc[j] = fmaf(d, F[(int64_t)j * plane + c], acc[j]);
-      }
+// Parameter gradients from the patch sums out = [128][nh + 1] (dW1 | db1,
+// from the split-K product of dZ with the DINO grid and a row of ones) and the
+// tile partials of dw2, db2: thread e < 128 nh copies dW1, the next 128 db1;
+// workgroups past those sum one column of the tile partials (fixed order).
+__global__ void __launch_bounds__(256) k_fu_params(UncArgs a, const float* __restrict__ out, float* d_params) {
+  const int64_t n1 = (int64_t)kHid * a.nh + kHid;
+  const int64_t nb1 = (n1 + 255) / 256;
+  if ((int64_t)blockIdx.x < nb1) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < (int64_t)kHid * a.nh) {
+      const int64_t u = e / a.nh, k = e - u * a.nh;
+      d_params[e] = out[u * (a.nh + 1) + k];
+    } else if (e < n1) {
+      const int64_t u = e - (int64_t)kHid * a.nh;
+      d_params[e] = out[u * (a.nh + 1) + a.nh];
     }
-#pragma unroll
-    for (int j = 0; j < kPG; ++j) d_params[(int64_t)u * a.nh + g * kPG + j] = acc[j];
     return;
   }
-  float sb = 0.f, sw = 0.f;
-  for (int v = 0; v < a.V; ++v)
-    for (int c = 0; c < plane; ++c) sb += a.dzc[((int64_t)v * plane + c) * kHid + u];
+  __shared__ float red[4];
+  const int j = (int)(blockIdx.x - nb1);  // column of w2t: dw2[j] (j < 128) or db2 (j = 128)
   const int64_t ntiles = (int64_t)a.V * a.tiles;
-  for (int64_t tile = 0; tile < ntiles; ++tile) sw += a.w2t[tile * (kHid + 1) + u];
-  float* db1 = d_params + (int64_t)kHid * a.nh;
-  db1[u] = sb;
-  db1[kHid + u] = sw;
-  if (u == 0) {
-    float s2 = 0.f;
-    for (int64_t tile = 0; tile < ntiles; ++tile) s2 += a.w2t[tile * (kHid + 1) + kHid];
-    db1[2 * kHid] = s2;
-  }
+  float s = 0.f;
+  for (int64_t tile = threadIdx.x; tile < ntiles; tile += 256) s += a.w2t[tile * (kHid + 1) + j];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) d_params[n1 + j] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // L_u of each view: fixed-order sum of its tile partials, over its pixels.
@@ -292,9 +287,27 @@ __global__ void __launch_bounds__(256) k_fu_mean(const double* __restrict__ part
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+
+ColGemm dw1_gemm(const UncArgs& a) {
+  ColGemm g{};
+  g.D = a.dzc;
+  g.dstride = kHid;
+  g.ncol = kHid;
+  g.F = a.dino;
+  g.fk = (int64_t)a.Hp * a.Wp;
+  g.fr = 1;
+  g.fview = (int64_t)a.nh * a.Hp * a.Wp;
+  g.nk = a.nh;
+  g.ones = 1;
+  g.V = a.V;
+  g.rows = a.Hp * a.Wp;
+  g.nsplit = colgemm_splits((int64_t)a.V * a.Hp * a.Wp);
+  return g;
+}
+
 }  // namespace
 
-UncLayout uncertainty_layout(int n_views, int width, int height, int Hp, int Wp) {
+UncLayout uncertainty_layout(int n_views, int width, int height, int Hp, int Wp, int nh) {
   UncLayout L{};
   const int64_t tiles = (int64_t)((width + kT - 1) / kT) * ((height + kT - 1) / kT) * n_views;
   const int64_t cells = (int64_t)Hp * Wp * n_views;
@@ -309,6 +322,15 @@ UncLayout uncertainty_layout(int n_views, int width, int height, int Hp, int Wp)
   o = a256(o + (size_t)tiles * (kHid + 1) * 4);
   L.dzc = o;
   o = a256(o + (size_t)cells * kHid * 4);
+  UncArgs ga{};
+  ga.V = n_views;
+  ga.Hp = Hp;
+  ga.Wp = Wp;
+  ga.nh = nh;
+  L.gpart = o;
+  o = a256(o + colgemm_part_floats(dw1_gemm(ga)) * 4);
+  L.gout = o;
+  o = a256(o + (size_t)kHid * (nh + 1) * 4);
   L.total = o;
   return L;
 }
@@ -323,14 +345,20 @@ void launch_uncertainty(UncArgs a, const UncLayout& L, char* work, float* loss, 
   a.tiles_y = (a.H + kT - 1) / kT;
   a.tiles = a.tiles_x * a.tiles_y;
   const int plane = a.Hp * a.Wp;
-  hipLaunchKernelGGL(k_fu_grid, dim3((unsigned)((plane + kGC - 1) / kGC), (unsigned)a.V), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_fu_grid, dim3((unsigned)((plane + kGC - 1) / kGC), kHid / kGU, (unsigned)a.V), dim3(256), 0, s,
+                     a);
   hipLaunchKernelGGL(k_fu_pix, dim3((unsigned)a.tiles_x, (unsigned)a.tiles_y, (unsigned)a.V), dim3(256), 0, s, a);
   if (loss && a.partial)
     hipLaunchKernelGGL(k_fu_mean, dim3((unsigned)a.V), dim3(256), 0, s, (const double*)a.partial, a.tiles,
                        1.0 / ((double)a.W * (double)a.H), loss);
   if (d_params) {
     hipLaunchKernelGGL(k_fu_cell_reduce, dim3((unsigned)plane, (unsigned)a.V), dim3(kHid), 0, s, a);
-    hipLaunchKernelGGL(k_fu_params, dim3((unsigned)(a.nh / kPG + 1)), dim3(kHid), 0, s, a, d_params);
+    ColGemm g = dw1_gemm(a);
+    g.part = reinterpret_cast<float*>(work + L.gpart);
+    float* out = reinterpret_cast<float*>(work + L.gout);
+    launch_colgemm(g, out, s);
+    const int64_t nb1 = ((int64_t)kHid * a.nh + kHid + 255) / 256;
+    hipLaunchKernelGGL(k_fu_params, dim3((unsigned)(nb1 + kHid + 1)), dim3(256), 0, s, a, (const float*)out, d_params);
   }
 }
 
