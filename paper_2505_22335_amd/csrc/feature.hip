@@ -87,6 +87,7 @@ struct FeatArgs {
   float* dfeat;                     // backward: [V][16][H][W]
   float* part;                      // backward: [kBwdWG][kPartStride]
   float* dqt;                       // backward: [V * tiles][kSlots][kDQ]
+  float* dqpix;                     // backward: [V][H][W] dq of each pixel (first pass -> second)
 };
 
 // Patch rectangle a tile reaches: rows cy0 .. cy0 + ncy - 1, cols cx0 ..
@@ -425,25 +426,28 @@ ASGS_DEV void f32_frag(const float (*T)[kRP], int r, int kb, int lane, bf8v& hi,
   lo = as_bf8(l);
 }
 
+// Backward, first pass (per round of 64 pixels): the forward again, dL/dz and
+// dL/dx (written), dq per pixel (for the second pass), and on the matrix
+// cores dQ += (g s1 w_c)^T h per patch slot, dW1^T += x^T dL/dz and
+// db1 += 1^T dL/dz (a row of ones).
 __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
   __shared__ __attribute__((aligned(16))) BwdShared S;
   stage_weights(a, S.F);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
-  // per-lane accumulators: db1 and dm at units 32 g + u (u < 32), dmu (group 0)
-  float adb1[32], adm[32], admu = 0.f;
+  // dW1^T and db1 column blocks 2 wv, 2 wv + 1; dQ column blocks wv, wv + 4 (and 8 = dbeta on wave 0)
+  f4v accW[2], accB[2], accQ[3];
 #pragma unroll
-  for (int u = 0; u < 32; ++u) adb1[u] = adm[u] = 0.f;
-  // matrix accumulators: S rows 32 wv .. 32 wv + 31 (two 16-row blocks) x 128 columns;
-  // dW1^T column blocks 2 wv, 2 wv + 1; dQ column blocks wv, wv + 4 (and 8 = dbeta on wave 0)
-  f4v accS[2][8], accW[2], accQ[3];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) accS[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-    accW[i] = f4v{0.f, 0.f, 0.f, 0.f};
-  }
+  for (int i = 0; i < 2; ++i) accW[i] = accB[i] = f4v{0.f, 0.f, 0.f, 0.f};
   const int total = a.tiles * a.V;
   const int64_t HW = (int64_t)a.W * a.H;
+  // A operand of the row of ones (row 0 of the block, exact in bfloat16)
+  bf8v ones;
+  {
+    uint16_t o[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = n == 0 ? bf_rne(1.f) : (uint16_t)0;
+    ones = as_bf8(o);
+  }
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     const int view = t / a.tiles, lt = t - view * a.tiles;
     const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
@@ -462,9 +466,9 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       const float al = gp * s1;
       const float dq = L.floored ? 0.f : -0.5f * gp * L.cos / L.q;
       const int pr = wv * 16 + n;  // pixel of the round
+      if (g == 0 && L.valid) a.dqpix[(int64_t)view * HW + L.p] = dq;
       __builtin_amdgcn_sched_barrier(0);
-      // dL/dz at the lane's units; dL/dx summed over the pixel's four lanes
-      float dz[32];
+      // dL/dz at the lane's units into the table; dL/dx summed over the pixel's four lanes
       float dxp[kFIn];
 #pragma unroll
       for (int c = 0; c < kFIn; ++c) dxp[c] = 0.f;
@@ -472,33 +476,25 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       for (int u = 0; u < 32; ++u) {
         const int k = 32 * g + u;
         const float dh = fmaf(al, corner_sum(S.F, L, k), 2.f * dq * (L.mh[u] + S.F.m[hpos(k)]));
-        dz[u] = L.h[u] > 0.f ? dh : 0.f;
+        const float dz = L.h[u] > 0.f ? dh : 0.f;
         const float* w = &S.F.w1[hpos(k) * kFIn];
 #pragma unroll
-        for (int c = 0; c < kFIn; ++c) dxp[c] = fmaf(w[c], dz[u], dxp[c]);
-        adb1[u] += dz[u];
-        adm[u] = fmaf(2.f * dq, L.h[u], adm[u]);
+        for (int c = 0; c < kFIn; ++c) dxp[c] = fmaf(w[c], dz, dxp[c]);
+        uint16_t hi, lo;
+        bf_split(dz, hi, lo);
+        S.Ghi[rp_index(k, pr)] = hi;
+        S.Glo[rp_index(k, pr)] = lo;
+        bf_split(L.h[u], hi, lo);
+        S.Hhi[rp_index(k, pr)] = hi;
+        S.Hlo[rp_index(k, pr)] = lo;
         if ((u & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
-      if (g == 0) admu += dq;
 #pragma unroll
       for (int c = 0; c < kFIn; ++c) dxp[c] = col_sum(dxp[c]);
       if (g == 0 && L.valid) {
         float* dfx = a.dfeat + (int64_t)view * kFIn * HW + L.p;
 #pragma unroll
         for (int c = 0; c < kFIn; ++c) dfx[c * HW] = dxp[c];
-      }
-      // round tables: h, dq h (units of the lane's group), x, corner weights
-#pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const int k = 32 * g + u;
-        uint16_t hi, lo;
-        bf_split(L.h[u], hi, lo);
-        S.Hhi[rp_index(k, pr)] = hi;
-        S.Hlo[rp_index(k, pr)] = lo;
-        bf_split(dq * L.h[u], hi, lo);
-        S.Ghi[rp_index(k, pr)] = hi;
-        S.Glo[rp_index(k, pr)] = lo;
       }
       if (g == 0) {
 #pragma unroll
@@ -507,32 +503,17 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       if (g == 1) {
         float wc[kSlots];
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) wc[s] = 0.f;
+        for (int sl = 0; sl < kSlots; ++sl) wc[sl] = 0.f;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-          for (int s = 0; s < kSlots; ++s) wc[s] += (L.cs[c] == s) ? al * L.cw[c] : 0.f;
+          for (int sl = 0; sl < kSlots; ++sl) wc[sl] += (L.cs[c] == sl) ? al * L.cw[c] : 0.f;
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) S.Wc[s][pr] = wc[s];
+        for (int sl = 0; sl < kSlots; ++sl) S.Wc[sl][pr] = wc[sl];
       }
       __syncthreads();
-      // S += (dq h)^T h over the round's pixels: rows 32 wv .. 32 wv + 31
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int rk = 32 * wv + 16 * i + n;
-          const bf8v gh = tab_frag(S.Ghi, rk, kb, lane), gl = tab_frag(S.Glo, rk, kb, lane);
-#pragma unroll
-          for (int nb = 0; nb < 8; ++nb) {
-            const int ck = 16 * nb + n;
-            const bf8v hh = tab_frag(S.Hhi, ck, kb, lane), hl = tab_frag(S.Hlo, ck, kb, lane);
-            accS[i][nb] = mfma_bf(gh, hh, accS[i][nb]);
-            accS[i][nb] = mfma_bf(gh, hl, accS[i][nb]);
-            accS[i][nb] = mfma_bf(gl, hh, accS[i][nb]);
-            if (nb & 1) __builtin_amdgcn_sched_barrier(0);
-          }
-        }
         // dQ += Wc^T h (rows = slots), and the constant-one column for dbeta
         bf8v wh, wl;
         f32_frag(S.Wc, n, kb, lane, wh, wl);
@@ -545,32 +526,15 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
             bh = tab_frag(S.Hhi, 16 * nb + n, kb, lane);
             bl = tab_frag(S.Hlo, 16 * nb + n, kb, lane);
           } else {
-            uint16_t one[8], zero[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              one[e] = n == 0 ? bf_rne(1.f) : (uint16_t)0;
-              zero[e] = 0;
-            }
-            bh = as_bf8(one);
+            bh = ones;
+            uint16_t zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             bl = as_bf8(zero);
           }
           accQ[i] = mfma_bf(wh, bh, accQ[i]);
           accQ[i] = mfma_bf(wh, bl, accQ[i]);
           accQ[i] = mfma_bf(wl, bh, accQ[i]);
         }
-      }
-      __syncthreads();  // S and dQ products done: the dq h table takes dL/dz
-#pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        uint16_t hi, lo;
-        bf_split(dz[u], hi, lo);
-        S.Ghi[rp_index(32 * g + u, pr)] = hi;
-        S.Glo[rp_index(32 * g + u, pr)] = lo;
-      }
-      __syncthreads();
-      // dW1^T += x^T dL/dz: rows = input channels, columns 16 nb + n
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb) {
+        // dW1^T += x^T dL/dz and db1 += 1^T dL/dz: columns 16 nb + n
         bf8v xh, xl;
         f32_frag(S.X, n, kb, lane, xh, xl);
 #pragma unroll
@@ -580,60 +544,158 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
           accW[i] = mfma_bf(xh, zh, accW[i]);
           accW[i] = mfma_bf(xh, zl, accW[i]);
           accW[i] = mfma_bf(xl, zh, accW[i]);
+          accB[i] = mfma_bf(ones, zh, accB[i]);
+          accB[i] = mfma_bf(ones, zl, accB[i]);
         }
       }
     }
     // the tile's patch gradients: rows = slots 4 (lane / 16) + j, column 16 nb + n
-    float* dq = a.dqt + (int64_t)t * kSlots * kDQ;
+    float* dqt = a.dqt + (int64_t)t * kSlots * kDQ;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const int nb = i == 0 ? wv : (i == 1 ? wv + 4 : 8);
       if (nb == 8 && (wv != 0 || n != 0)) continue;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dq[(4 * g + j) * kDQ + 16 * nb + n] = accQ[i][j];
+      for (int j = 0; j < 4; ++j) dqt[(4 * g + j) * kDQ + 16 * nb + n] = accQ[i][j];
     }
   }
-  // workgroup partials
+  // workgroup partials: dW1^T rows 4 g + j, db1 (row 0 of the ones block)
   float* part = a.part + (int64_t)blockIdx.x * kPartStride;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int nb = 0; nb < 8; ++nb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) part[(32 * wv + 16 * i + 4 * g + j) * kFHid + 16 * nb + n] = accS[i][nb][j];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) part[16384 + (4 * g + j) * kFHid + 16 * (2 * wv + i) + n] = accW[i][j];
-  // db1, dm, dmu: over the 16 lanes of each group, then over the waves (fixed order)
-  __syncthreads();
-  float* red = &S.X[0][0];  // per wave 128 sums of db1 (in X) and of dm (in Wc)
-  float* red2 = &S.Wc[0][0];
-  static_assert(sizeof(S.X) >= kBwdWaves * kFHid * sizeof(float) && sizeof(S.Wc) >= kBwdWaves * kFHid * sizeof(float),
-                "reduction space");
+    if (g == 0) part[16384 + 2048 + 16 * (2 * wv + i) + n] = accB[i][0];
+  }
+}
+
+// Backward, second pass: S = sum_p dq h h^T (symmetric: the 36 blocks on and
+// above the diagonal of 16 x 16, nine per wave), dm = 2 sum_p dq h and
+// dmu = sum_p dq, from the first layer recomputed per pixel and dq of the
+// first pass. The partial holds T with T + T^T = S + S^T: off-diagonal
+// blocks doubled, diagonal blocks once, blocks below the diagonal zero.
+ASGS_DEV void sblock(int q, int& bi, int& bj) {
+  // q-th block (bi <= bj) of the upper triangle of an 8 x 8 block grid
+  bi = 0;
+  int left = q;
+  while (left >= 8 - bi) {
+    left -= 8 - bi;
+    ++bi;
+  }
+  bj = bi + left;
+}
+
+struct SShared {
+  float w1[kFHid * kFIn];
+  float b1[kFHid];
+  uint16_t Hhi[kFHid * kRP], Hlo[kFHid * kRP];  // h
+  uint16_t Ghi[kFHid * kRP], Glo[kFHid * kRP];  // dq h
+  float red[kBwdWaves][kFHid];
+};
+
+__global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd_s(FeatArgs a) {
+  __shared__ __attribute__((aligned(16))) SShared S;
+  for (int q = threadIdx.x; q < kFHid * kFIn; q += blockDim.x) {
+    const int k = q / kFIn, c = q - k * kFIn;
+    S.w1[hpos(k) * kFIn + c] = a.params[q];
+  }
+  for (int k = threadIdx.x; k < kFHid; k += blockDim.x) S.b1[hpos(k)] = a.params[kFHid * kFIn + k];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+  f4v accS[9], accM[2];
 #pragma unroll
-  for (int u = 0; u < 32; ++u) {
-    float b = adb1[u], m = adm[u];
-    for (int o = 1; o < 16; o <<= 1) {
-      b += __shfl_xor(b, o);
-      m += __shfl_xor(m, o);
-    }
-    if (n == 0) {
-      red[wv * 128 + 32 * g + u] = b;
-      red2[wv * 128 + 32 * g + u] = m;
+  for (int i = 0; i < 9; ++i) accS[i] = f4v{0.f, 0.f, 0.f, 0.f};
+  accM[0] = accM[1] = f4v{0.f, 0.f, 0.f, 0.f};
+  float admu = 0.f;
+  bf8v ones;
+  {
+    uint16_t o[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = n == 0 ? bf_rne(1.f) : (uint16_t)0;
+    ones = as_bf8(o);
+  }
+  const int total = a.tiles * a.V;
+  const int64_t HW = (int64_t)a.W * a.H;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int view = t / a.tiles, lt = t - view * a.tiles;
+    const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
+    for (int round = 0; round < kFT / kBwdWaves; ++round) {
+      __syncthreads();  // weights staged; the previous round's tables are no longer read
+      const int px = tx * kFT + n, py = ty * kFT + round * kBwdWaves + wv;
+      const bool valid = px < a.W && py < a.H;
+      const int64_t p = (int64_t)min(py, a.H - 1) * a.W + min(px, a.W - 1);
+      const float dq = valid ? a.dqpix[(int64_t)view * HW + p] : 0.f;
+      float x[kFIn];
+      const float* fx = a.feat + (int64_t)view * kFIn * HW + p;
+#pragma unroll
+      for (int c = 0; c < kFIn; ++c) x[c] = valid ? fx[c * HW] : 0.f;
+      if (g == 0) admu += dq;
+      const int pr = wv * 16 + n;
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const int k = 32 * g + u;
+        const float* w = &S.w1[hpos(k) * kFIn];
+        float z = S.b1[hpos(k)];
+#pragma unroll
+        for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], x[c], z);
+        const float h = fmaxf(z, 0.f);
+        uint16_t hi, lo;
+        bf_split(h, hi, lo);
+        S.Hhi[rp_index(k, pr)] = hi;
+        S.Hlo[rp_index(k, pr)] = lo;
+        bf_split(dq * h, hi, lo);
+        S.Ghi[rp_index(k, pr)] = hi;
+        S.Glo[rp_index(k, pr)] = lo;
+        if ((u & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          int bi, bj;
+          sblock(9 * wv + i, bi, bj);
+          const bf8v gh = tab_frag(S.Ghi, 16 * bi + n, kb, lane), gl = tab_frag(S.Glo, 16 * bi + n, kb, lane);
+          const bf8v hh = tab_frag(S.Hhi, 16 * bj + n, kb, lane), hl = tab_frag(S.Hlo, 16 * bj + n, kb, lane);
+          accS[i] = mfma_bf(gh, hh, accS[i]);
+          accS[i] = mfma_bf(gh, hl, accS[i]);
+          accS[i] = mfma_bf(gl, hh, accS[i]);
+          if (i & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        // dm over the row blocks 2 wv, 2 wv + 1: (dq h) times a column of ones
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int rb = 2 * wv + i;
+          const bf8v gh = tab_frag(S.Ghi, 16 * rb + n, kb, lane), gl = tab_frag(S.Glo, 16 * rb + n, kb, lane);
+          accM[i] = mfma_bf(gh, ones, accM[i]);
+          accM[i] = mfma_bf(gl, ones, accM[i]);
+        }
+      }
     }
   }
+  float* part = a.part + (int64_t)blockIdx.x * kPartStride;
+  // S (T form): rows 16 bi + 4 g + j, columns 16 bj + n; zero blocks below the diagonal
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int bi, bj;
+    sblock(9 * wv + i, bi, bj);
+    const float f = bi == bj ? 1.f : 2.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      part[(16 * bi + 4 * g + j) * kFHid + 16 * bj + n] = f * accS[i][j];
+      if (bi != bj) part[(16 * bj + 4 * g + j) * kFHid + 16 * bi + n] = 0.f;
+    }
+  }
+  // dm: column 0 of the product with the ones column (lanes n == 0), doubled
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (n == 0) part[16384 + 2048 + 128 + 16 * (2 * wv + i) + 4 * g + j] = 2.f * accM[i][j];
   for (int o = 32; o > 0; o >>= 1) admu += __shfl_xor(admu, o);
   __syncthreads();
-  if (threadIdx.x < kFHid) {
-    const int k = threadIdx.x;
-    part[16384 + 2048 + k] = (red[k] + red[128 + k]) + (red[256 + k] + red[384 + k]);
-    part[16384 + 2048 + 128 + k] = (red2[k] + red2[128 + k]) + (red2[256 + k] + red2[384 + k]);
-  }
+  if (lane == 0) S.red[0][wv] = admu;
   __syncthreads();
-  if (lane == 0) red[wv] = admu;
-  __syncthreads();
-  if (threadIdx.x == 0) part[16384 + 2048 + 256] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) part[16384 + 2048 + 256] = (S.red[0][0] + S.red[0][1]) + (S.red[0][2] + S.red[0][3]);
 }
 
 // Sums of the workgroup partials: S, dW1^T, db1, dm, dmu (fixed order).
@@ -751,6 +813,7 @@ FeatLayout feature_layout(int nh, int n_views, int width, int height, int Hp, in
   L.dqt = take((size_t)tiles * kSlots * kDQ * 4);
   L.red = take((size_t)kPart * 4);
   L.dqc = take((size_t)cells * kDQ * 4);
+  L.dqpix = take((size_t)n_views * width * height * 4);
   FeatArgs ga{};
   ga.V = n_views;
   ga.Hp = Hp;
@@ -799,6 +862,7 @@ FeatArgs feat_args(const FeatCall& c, const FeatLayout& L, char* work) {
   a.dfeat = c.dfeat;
   a.part = reinterpret_cast<float*>(work + L.part);
   a.dqt = reinterpret_cast<float*>(work + L.dqt);
+  a.dqpix = reinterpret_cast<float*>(work + L.dqpix);
   return a;
 }
 
@@ -828,6 +892,7 @@ void launch_feature_backward(const FeatCall& c, const FeatLayout& L, char* work,
   const int total = a.tiles * a.V;
   const int nwg = total < kBwdWG ? total : kBwdWG;
   hipLaunchKernelGGL(k_feat_bwd, dim3((unsigned)nwg), dim3(64 * kBwdWaves), 0, s, a);
+  hipLaunchKernelGGL(k_feat_bwd_s, dim3((unsigned)nwg), dim3(64 * kBwdWaves), 0, s, a);
   float* red = reinterpret_cast<float*>(work + L.red);
   hipLaunchKernelGGL(k_feat_reduce, dim3((kPart + 255) / 256), dim3(256), 0, s, a.part, nwg, red);
   float* dqc = reinterpret_cast<float*>(work + L.dqc);

@@ -179,7 +179,7 @@ void launch_residual(const ResidualArgs& a, int n_views, float* xi, hipStream_t 
 
 // Feature lift and cosine distillation (feature.hip).
 struct FeatLayout {
-  size_t mfrag, mvec, cells, tile_loss, part, dqt, red, dqc, gpart, gout, ppart, pout, total;
+  size_t mfrag, mvec, cells, tile_loss, part, dqt, red, dqc, dqpix, gpart, gout, ppart, pout, total;
 };
 struct FeatCall {
   int32_t n_views, width, height, nh, Hp, Wp;
