@@ -89,7 +89,9 @@ typedef struct asgs_render_opts {
   float znear;             /* 0.2: cull Gaussians with camera depth <= znear */
   float fov_clamp;         /* 1.3: Jacobian x/z clamp, in units of W/(2 fx); 0 = off */
   float bg[3];             /* background colour (colour channels only) */
-  int32_t reserved;        /* must be 0 */
+  int32_t extent_mode;     /* footprint listed in the tiles: 0 = the tight box of the alpha >= alpha_min
+                              ellipse (default; compositing then equals per-pixel evaluation), 1 = the
+                              square of half side ceil(3 sqrt(lambda_max(Sigma'))) of vanilla 3DGS */
 } asgs_render_opts;
 
 void asgs_render_opts_default(asgs_render_opts* opts);

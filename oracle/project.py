@@ -83,8 +83,16 @@ def project(mean, scale, rot, opacity, R_cw, t_cw, width, height, fx, fy, cx, cy
         kap2 = 2.0 * np.log(o / opts.alpha_min)
         okop = o > opts.alpha_min
         kap2 = np.where(okop, kap2, 0.0)
-        sx = np.sqrt(kap2 * np.maximum(an, 0.0))
-        sy = np.sqrt(kap2 * np.maximum(cn, 0.0))
+        if getattr(opts, "extent_mode", 0) == 0:
+            # tight box of the ellipse where alpha = alpha_min
+            sx = np.sqrt(kap2 * np.maximum(an, 0.0))
+            sy = np.sqrt(kap2 * np.maximum(cn, 0.0))
+        else:
+            # square of three standard deviations along the major axis
+            bn = b.detach().numpy()
+            mid = 0.5 * (an + cn)
+            lmax = mid + np.sqrt(np.maximum(0.1, mid * mid - (an * cn - bn * bn)))
+            sx = sy = 3.0 * np.sqrt(np.maximum(lmax, 0.0))
     rx = np.ceil(sx)
     ry = np.ceil(sy)
     margin_r = np.minimum(np.abs(sx - np.round(sx)), np.abs(sy - np.round(sy)))

@@ -19,6 +19,7 @@ class RenderOpts:
     znear: float = 0.2              # camera-space depth below which a Gaussian is culled
     fov_clamp: float = 1.3          # Jacobian evaluated with x/z clamped to +-fov_clamp*W/(2 fx); 0 = off
     bg: Tuple[float, float, float] = field(default=(0.0, 0.0, 0.0))
+    extent_mode: int = 0            # 0: tight alpha_min box; 1: 3-sigma square (vanilla 3DGS)
 
 
 # Each reading: where the paper is silent, ambiguous or garbled, and what is taken.
@@ -32,7 +33,9 @@ READINGS = (
     "Termination is exclusive: the Gaussian that would take T below T_min is not composited, and the "
     "pixel stops there.",
     "Footprint is the exact axis-aligned box of the ellipse where alpha >= alpha_min, so tiled "
-    "compositing equals per-pixel brute force and does not depend on the tile size.",
+    "compositing equals per-pixel brute force and does not depend on the tile size. The vanilla "
+    "rasteriser's footprint (a square of half side ceil(3 sqrt(lambda_max)), lambda_max = mid + "
+    "sqrt(max(0.1, mid^2 - det)), mid = (a + c)/2 of the dilated 2D covariance) is an option.",
     "Pixel (px, py) is evaluated at the integer point (px, py); cx = (W-1)/2 in the workloads.",
     "z_i is the camera-space depth of the Gaussian centre; rendered depth is not normalised by alpha; "
     "background is zero unless bg is set (colour only).",

@@ -51,7 +51,7 @@ class RenderOpts(C.Structure):
     _fields_ = [("tile", C.c_int32), ("n_feat", C.c_int32), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("dilation", C.c_float),
                 ("znear", C.c_float), ("fov_clamp", C.c_float), ("bg", C.c_float * 3),
-                ("reserved", C.c_int32)]
+                ("extent_mode", C.c_int32)]
 
 
 class Gaussians(C.Structure):

@@ -80,7 +80,7 @@ int check_opts(const asgs_render_opts* o) {
       !(o->T_min > 0.f && o->T_min < 1.f) || !(o->dilation >= 0.f) || !(o->znear > 0.f) ||
       !(o->fov_clamp >= 0.f) || !isfinite(o->bg[0]) || !isfinite(o->bg[1]) || !isfinite(o->bg[2]))
     return fail(ASGS_E_INVALID, "render options out of range");
-  if (o->reserved != 0) return fail(ASGS_E_INVALID, "opts.reserved must be 0");
+  if (o->extent_mode != 0 && o->extent_mode != 1) return fail(ASGS_E_INVALID, "opts.extent_mode must be 0 or 1");
   return ASGS_OK;
 }
 
@@ -190,6 +190,7 @@ int prepare(const asgs_camera* cams, int32_t n_views, int64_t n, const asgs_rend
   rc.alpha_max = opts->alpha_max;
   rc.T_min = opts->T_min;
   rc.dilation = opts->dilation;
+  rc.extent_mode = opts->extent_mode;
   rc.znear = opts->znear;
   for (int c = 0; c < 3; ++c) rc.bg[c] = opts->bg[c];
   rc.n_views = n_views;
@@ -353,7 +354,7 @@ void asgs_render_opts_default(asgs_render_opts* o) {
   o->znear = 0.2f;
   o->fov_clamp = 1.3f;
   o->bg[0] = o->bg[1] = o->bg[2] = 0.f;
-  o->reserved = 0;
+  o->extent_mode = 0;
 }
 
 int asgs_render_ctx_size(const asgs_camera* cams, int32_t n_views, int64_t n_gauss, const asgs_render_opts* opts,

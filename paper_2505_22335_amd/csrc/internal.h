@@ -44,6 +44,7 @@ struct RenderConst {
   int32_t total_pix;
   int64_t cap;         // intersection capacity
   int32_t n_cu;        // compute units of the device (issue-priority bands of the blend kernels)
+  int32_t extent_mode; // 0: tight alpha_min box; 1: 3-sigma square
 };
 
 // Header at the start of every render context (device memory).

@@ -169,10 +169,17 @@ __global__ void __launch_bounds__(256) k_project(RenderConst rc, asgs_gaussians 
     A = P.c / P.det;
     B = -P.b / P.det;
     C = P.a / P.det;
-    // tight box of the ellipse alpha = alpha_min: half-widths sqrt(kappa^2 Sigma'_xx), ...
-    const float kap2 = 2.f * logf(o / rc.alpha_min);
-    rx = ceilf(sqrtf(kap2 * P.a));
-    ry = ceilf(sqrtf(kap2 * P.c));
+    if (rc.extent_mode == 0) {
+      // tight box of the ellipse alpha = alpha_min: half-widths sqrt(kappa^2 Sigma'_xx), ...
+      const float kap2 = 2.f * logf(o / rc.alpha_min);
+      rx = ceilf(sqrtf(kap2 * P.a));
+      ry = ceilf(sqrtf(kap2 * P.c));
+    } else {
+      // square of half side three standard deviations along the major axis
+      const float mid = 0.5f * (P.a + P.c);
+      const float lmax = mid + sqrtf(fmaxf(0.1f, mid * mid - P.det));
+      rx = ry = ceilf(3.f * sqrtf(lmax));
+    }
     const float lim = 8388608.f;  // 2^23: beyond this the box arithmetic is not exact
     staged = isfinite(u) && isfinite(v) && fabsf(u) < lim && fabsf(v) < lim && rx < lim && ry < lim;
     vis = staged;

@@ -35,7 +35,7 @@ def test_ctx_size_grows_with_capacity_and_views():
 
 @pytest.mark.parametrize("field,value,status", [
     ("n_feat", 3, L.E_UNSUPPORTED), ("tile", 8, L.E_UNSUPPORTED), ("alpha_min", 0.0, L.E_INVALID),
-    ("T_min", 2.0, L.E_INVALID), ("znear", -1.0, L.E_INVALID), ("reserved", 1, L.E_INVALID)])
+    ("T_min", 2.0, L.E_INVALID), ("znear", -1.0, L.E_INVALID), ("extent_mode", 2, L.E_INVALID)])
 def test_bad_options_rejected(field, value, status):
     o = L.make_opts(16)
     setattr(o, field, value)

@@ -91,6 +91,39 @@ def test_c1_forward_backward(bg):
     assert e <= GRAD_TOL
 
 
+@pytest.mark.parametrize("case", ["c1", "tiny"])
+def test_three_sigma_footprint(case):
+    """extent_mode 1 (the vanilla 3-sigma square footprint): images,
+    gradients and tile lists against the oracle in the same mode; C1 (10k
+    Gaussians, 640x480) and a ragged 16-d feature scene."""
+    if case == "c1":
+        sc, cam, _ = synth.c1()
+        nf = 0
+    else:
+        nf = 16
+        sc = synth.tiny_scene(210, 300, n_feat=nf, logs_mu=-2.6)
+        cam = synth.Camera(75, 53, 60.0, 60.0, 37.0, 26.0, np.eye(3, 4, dtype=np.float32))
+    log("case three-sigma footprint", case)
+    ref = oracle.render_scene(sc, cam, oracle_opts(nf, extent_mode=1), with_margins=True, keep_lists=True)
+    keep = _guard(ref, "3sigma " + case, 0.02)
+    G = upstream(21, cam.height, cam.width, nf)
+    for k in G:
+        G[k] = G[k] * keep
+    res = _gpu_render(sc, [cam], nf, G=G, extent_mode=1)
+    keys = ("rgb", "depth", "alpha") + (("feat",) if nf else ())
+    for k in keys:
+        e = rel_err(res["out"][k][0], ref[k], keep)
+        log("3sigma", case, k, "%.2e" % e)
+        assert e <= IMG_TOL, k
+    _check_lists(res["rc"], ref, "3sigma " + case)
+    _, gr = oracle.render_scene(sc, cam, oracle_opts(nf, extent_mode=1), grad_out=G, pose_grad=True)
+    for k in ("mean", "scale", "rot", "opacity", "rgb") + (("feat",) if nf else ()):
+        e = rel_err(res["dg"][k][0], gr["gauss"][k])
+        log("3sigma grad", case, k, "%.2e" % e)
+        assert e <= GRAD_TOL, k
+    assert rel_err(res["dpose"][0], gr["pose"]) <= GRAD_TOL
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_tiny_scene_features_ragged(seed):
     """Small image that is not a multiple of the tile size, 16-d features."""

@@ -191,3 +191,50 @@ def test_served_maps_match_oracle(precision, tol):
         e = rel_err(to_np(x), ref[k], keep)
         log("served %s precision=%d rel err %.3e" % (k, precision, e))
         assert e <= tol, k
+
+
+@pytest.mark.slow
+def test_mapping_request_gradients_match_oracle(wl):
+    """One served mapping request (half resolution, the 10k-anchor room):
+    its anchor, decoder-parameter and pose gradients against the FP64
+    oracle's gradients of the same weighted L1 residual. Pixels in the
+    rendering guard band, and pixels where a channel of the oracle's image
+    lies within 1e-4 of its target (where the sign of the residual is not
+    decided by the rendering alone), get weight 0 in the request and in
+    the oracle's upstream gradient."""
+    import paper_2505_22335_amd as P
+    i = 5
+    cam = _jitter(wl.half[i], 300 + i)
+    H, W = cam.height, cam.width
+    tr, td, tf = (to_np(x[i]) for x in wl.th)
+    ref = oracle.render_scene(wl.sc, cam, oracle_opts(16), with_margins=True)
+    keep = guard_mask(ref["margins"])
+    far = (np.abs(ref["rgb"] - tr).min(0) > 1e-4) & (np.abs(ref["depth"] - td) > 1e-4) & \
+        (np.abs(ref["feat"] - tf).min(0) > 1e-4)
+    w = np.random.default_rng(4).uniform(size=(H, W)) * keep * far
+    log("mapping request: weighted pixels", int((w > 0).sum()), "of", H * W)
+    assert (w > 0).mean() > 0.5
+    HW = H * W
+    G = {"rgb": w * np.sign(ref["rgb"] - tr) / (3 * HW), "depth": w * np.sign(ref["depth"] - td) / HW,
+         "feat": w * np.sign(ref["feat"] - tf) / (16 * HW), "alpha": np.zeros((H, W))}
+    A, n, npar = wl.a.A, wl.a.A * wl.a.k, wl.a.params.numel()
+    sp = RequestSpec(MAP, [cam], [wl.th[0][i]], [wl.th[1][i]], target_feat=[wl.th[2][i]],
+                     weight=torch.as_tensor(w, dtype=torch.float32).cuda(), d_pose=torch.empty(1, 6, device="cuda"),
+                     loss=torch.empty(1, device="cuda"), d_xyz=torch.empty(3, A, device="cuda"),
+                     d_feat=torch.empty(A, 32, device="cuda"), d_off=torch.empty(3, n, device="cuda"),
+                     d_params=torch.empty(npar, device="cuda"))
+    with Server(wl.a, n_streams=2, arena_bytes=4 << 30) as s:
+        assert s.wait(s.submit(sp)).status == 0
+    torch.cuda.synchronize()
+    _, gr = oracle.render_scene(wl.sc, cam, oracle_opts(16), grad_out=G, pose_grad=True)
+    for name in ("xyz", "feat", "off"):
+        e = rel_err(to_np(getattr(sp, "d_" + name)), gr["anchor"][name])
+        log("mapping request d_%s %.2e" % (name, e))
+        assert e <= 1e-3, name
+    Wg = P.unpack_params(sp.d_params, wl.sc.k, 16)
+    worst = max(rel_err(to_np(Wg[h][k]), gr["weights"][h][k]) for h in Wg for k in Wg[h])
+    log("mapping request d_params worst tensor %.2e" % worst)
+    assert worst <= 1e-3
+    e = rel_err(to_np(sp.d_pose[0]), gr["pose"])
+    log("mapping request d_pose %.2e" % e)
+    assert e <= 1e-3

@@ -177,3 +177,43 @@ def test_culling_rules():
     p = _proj(mean, s, q, o, cam.T_wc, cam, opts)
     assert p["visible"].tolist() == [False, True, False, False, False]
     assert p["ntiles"][1] >= 1 and p["ntiles"][0] == 0
+
+
+def test_three_sigma_footprint_closed_form():
+    """On-axis isotropic Gaussians (2D covariance s_x^2 + 0.3 and s_y^2 + 0.3,
+    no correlation): the 3-sigma square has half side ceil(3 sqrt(l)) in both
+    axes with l = mid + sqrt(max(0.1, ((s_x^2 - s_y^2)/2)^2)) (the larger
+    eigenvalue, with the vanilla floor of 0.1 on the squared half gap),
+    whatever the opacity; the tight box depends on the opacity instead."""
+    cam = synth.Camera(640, 480, 500.0, 520.0, 319.5, 239.5, np.eye(3, 4, dtype=np.float32))
+    z = np.array([2.0, 3.0, 1.5])
+    s = np.array([0.03, 0.011, 0.05])
+    mean = np.stack([np.zeros(3), np.zeros(3), z], 1)
+    scale = np.stack([s, s, s], 1)
+    q = np.tile([1.0, 0.0, 0.0, 0.0], (3, 1))
+    sxx = (cam.fx * s / z) ** 2 + 0.3
+    syy = (cam.fy * s / z) ** 2 + 0.3
+    for o in (0.2, 0.95):
+        p = _proj(mean, scale, q, np.full(3, o), cam.T_wc, cam, RenderOpts(n_feat=0, extent_mode=1))
+        lmax = 0.5 * (sxx + syy) + np.sqrt(np.maximum(0.1, (0.5 * (sxx - syy)) ** 2))
+        r = np.ceil(3 * np.sqrt(lmax))
+        np.testing.assert_array_equal(p["radius"][:, 0], r)
+        np.testing.assert_array_equal(p["radius"][:, 1], r)
+        pt = _proj(mean, scale, q, np.full(3, o), cam.T_wc, cam, RenderOpts(n_feat=0))
+        k = math.sqrt(2 * math.log(o * 255.0))
+        np.testing.assert_array_equal(pt["radius"][:, 0], np.ceil(k * np.sqrt(sxx)))
+
+
+def test_three_sigma_footprint_renders_alike_for_faint_gaussians():
+    """With every opacity below alpha_min e^4.5 (~0.353) the alpha >= alpha_min
+    ellipse lies inside 3 sigma, so both footprints give the same images
+    (per-pixel alpha tests decide; the lists differ only by entries that
+    contribute nothing)."""
+    from oracle import render_scene
+    sc = synth.tiny_scene(11, 60, n_feat=0)
+    sc.opacity[:] = np.minimum(sc.opacity, 0.34).astype(np.float32)
+    cam = synth.Camera(40, 32, 40.0, 40.0, 19.5, 15.5, np.eye(3, 4, dtype=np.float32))
+    a = render_scene(sc, cam, RenderOpts(n_feat=0))
+    b = render_scene(sc, cam, RenderOpts(n_feat=0, extent_mode=1))
+    for key in ("rgb", "depth", "alpha"):
+        assert np.abs(a[key] - b[key]).max() < 1e-12, key
