@@ -69,6 +69,9 @@ RESIDUAL_READINGS = (
     "The tracking motion mask threshold is unstated: the mapping mask's criterion 2 sigma^2 > 1 (Eq.14) "
     "is used, i.e. dynamic where 4R > 1 above the floor.",
     "Residual weights (lambda_1^t, lambda_2^t, lambda_3^t) = (0.25, 0.7, 0.1) from the appendix.",
+    "The tracking optimiser is unstated: Adam on the pose twist (lr 5e-4), the twist folded into the pose "
+    "after every step; the colour and depth terms of a weighted L1 residual carry lambda_1^t and "
+    "lambda_2^t, with per-pixel weights standing in for the uncertainty mask.",
 )
 
 

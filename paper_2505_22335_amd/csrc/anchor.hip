@@ -38,8 +38,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_anchor_update(int64_t n, const 
   }
 }
 
-// the count starts from zero (a kernel rather than a memset node, which some
-// graph replays on this platform have mishandled)
+// the count starts from zero (a kernel rather than a memset, so that the
+// call can be captured in a graph)
 __global__ void k_zero_count(unsigned long long* n_keep) { *n_keep = 0ull; }
 
 }  // namespace
