@@ -10,13 +10,13 @@
 // activations: sigmoid (opacity, rgb), l_s * sigmoid (scale), raw (rot, feat).
 //
 // FP32 path: forward and backward run on the matrix cores with FP32
-// 16x16x4 MFMAs (decode_heads.hip), one 16-anchor tile at a time, the heads
-// split over two kinds of workgroup. The BF16 path runs the forward on the
-// matrix cores in BF16 (decode_mfma.hip). The backward recomputes the forward,
-// then forms dL/dH from the second-layer weights, dL/dZ through the
-// activations, dL/dX from the first layer, and the weight gradients as
-// per-workgroup sums reduced in a fixed order (deterministic, no atomics).
-// This file holds the per-anchor and reduction steps around them.
+// 16x16x4 MFMAs, one 16-anchor tile at a time (forward: decode_heads.hip,
+// backward: decode_bwd.hip). The BF16 path runs the forward on the matrix
+// cores in BF16 (decode_mfma.hip). The backward recomputes the forward, forms
+// dL/dH from the second-layer weights, dL/dZ through the activations, dL/dX
+// from the first layer and from it the anchor gradients, and the weight
+// gradients as per-workgroup sums reduced here in a fixed order
+// (deterministic, no atomics). This file holds the reductions around them.
 #include <math.h>
 
 #include "decode_shared.h"
@@ -24,75 +24,6 @@
 namespace asgs {
 
 namespace {
-
-// ---------------------------------------------------------------------------
-// Backward, per view: one kernel on the matrix cores (decode_heads.hip)
-// recomputes the forward per 16-anchor tile and forms dL/dX of each head
-// group and per-workgroup partials of every MLP parameter gradient; the
-// anchor gradients follow from dL/dX, then the partials are reduced in a
-// fixed order.
-// ---------------------------------------------------------------------------
-// Anchor gradients of one view from the two head groups' dL/dX: the feature
-// part goes to d_feat, the view-direction part through
-// delta = (x - c) / |x - c| (and the distance input |x - c|, when the decoder
-// has one) to d_xyz and (negated) to the camera centre,
-// whose per-block sums feed the pose gradient.
-constexpr int kAnchorThreads = 256;
-__global__ void __launch_bounds__(kAnchorThreads) k_dec_bwd_anchor(DecodeConst dc, DecodeViews dv,
-                                                                  const float* __restrict__ xyz, DecWork w,
-                                                                  int view, int has_feat, float* d_xyz,
-                                                                  float* d_feat) {
-  __shared__ float red[3][kAnchorThreads / 64];
-  const int t = threadIdx.x;
-  const int64_t A = dc.A;
-  const int64_t i = (int64_t)blockIdx.x * kAnchorThreads + t;
-  const float* dx0 = w.dxpart;
-  const float* dx1 = w.dxpart + A * 36;
-  // one feature element per thread
-  if (d_feat && i < A * 32) {
-    const int64_t a = i >> 5;
-    const int c = (int)(i & 31);
-    const float v = dx0[a * 36 + c] + (has_feat ? dx1[a * 36 + c] : 0.f);
-    d_feat[i] = (view == 0 ? 0.f : d_feat[i]) + v;
-  }
-  // the first blocks also take one anchor's view direction per thread
-  if ((int64_t)blockIdx.x * kAnchorThreads >= A) return;
-  float dcl[3] = {0.f, 0.f, 0.f};
-  const int64_t a = i;
-  if (a < A) {
-    float gd[3], D[3];
-    for (int c = 0; c < 3; ++c) {
-      gd[c] = dx0[a * 36 + 32 + c] + (has_feat ? dx1[a * 36 + 32 + c] : 0.f);
-      D[c] = xyz[c * A + a] - dv.c[view][c];
-    }
-    // dL/d|x - c| of the distance input (column 35), when present
-    const float gdist = dc.n_x > 0 ? dx0[a * 36 + 35] + (has_feat ? dx1[a * 36 + 35] : 0.f) : 0.f;
-    const float dist = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-    float del[3];
-    for (int c = 0; c < 3; ++c) del[c] = D[c] / dist;
-    const float pr = del[0] * gd[0] + del[1] * gd[1] + del[2] * gd[2];
-    for (int c = 0; c < 3; ++c) {
-      // through delta = D / |D| (projected, scaled by 1/|D|) and |D| (along delta)
-      const float dD = (gd[c] - del[c] * pr) / dist + gdist * del[c];
-      if (d_xyz) {
-        float* p = &d_xyz[c * A + a];
-        *p = (view == 0 ? 0.f : *p) + dD;
-      }
-      dcl[c] = -dD;
-    }
-  }
-  for (int c = 0; c < 3; ++c) {
-    float x = dcl[c];
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    if ((t & 63) == 0) red[c][t >> 6] = x;
-  }
-  __syncthreads();
-  if (t < 3) {
-    float sum = 0.f;
-    for (int q = 0; q < kAnchorThreads / 64; ++q) sum += red[t][q];
-    w.dcpart[((int64_t)blockIdx.x * dc.n_views + view) * 3 + t] = sum;
-  }
-}
 
 // Mean gradients summed over views: d_off = l_o dmu, d_xyz += sum_i dmu
 // (element e of the 3 A anchor coordinates).
@@ -157,7 +88,7 @@ __global__ void __launch_bounds__(256) k_decode_reduce(DecodeConst dc, DecodeVie
     float g[3];
     for (int c = 0; c < 3; ++c) {
       float acc = 0.f;
-      for (int b = t; b < w.nblk_m; b += blockDim.x) acc += w.dcpart[((int64_t)b * dc.n_views + view) * 3 + c];
+      for (int b = t; b < w.nblk_w; b += blockDim.x) acc += w.dcpart[((int64_t)b * dc.n_views + view) * 3 + c];
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
       __syncthreads();
       if ((t & 63) == 0) red[t >> 6][0] = acc;
@@ -201,20 +132,18 @@ DecodeViews decode_views(const ViewDev* hv, int n_views) {
 }
 
 struct WorkSizes {
-  int64_t nblk_w, nblk_m;
-  size_t part, dcpart, dxpart, total;
+  int64_t nblk_w;
+  size_t part, dcpart, total;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 WorkSizes work_sizes(const DecodeConst& dc) {
   WorkSizes z;
-  z.nblk_w = dec_bwd_heads_blocks(dc.A);
-  z.nblk_m = (dc.A + kAnchorThreads - 1) / kAnchorThreads;
+  z.nblk_w = dec_bwd_blocks(dc.A);
   size_t o = 0;
   z.part = o; o = a256(o + (size_t)z.nblk_w * ((dc.n_params + 63) / 64 * 64) * 4);
-  z.dcpart = o; o = a256(o + (size_t)z.nblk_m * dc.n_views * 3 * 4);
-  z.dxpart = o; o = a256(o + dec_bwd_dx_floats(dc.A) * 4);
+  z.dcpart = o; o = a256(o + (size_t)z.nblk_w * dc.n_views * 3 * 4);
   z.total = o;
   return z;
 }
@@ -269,15 +198,9 @@ void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float
   DecWork w;
   w.part = reinterpret_cast<float*>(wb + z.part);
   w.dcpart = reinterpret_cast<float*>(wb + z.dcpart);
-  w.dxpart = reinterpret_cast<float*>(wb + z.dxpart);
   w.nblk_w = (int32_t)z.nblk_w;
-  w.nblk_m = (int32_t)z.nblk_m;
-  for (int view = 0; view < dc.n_views; ++view) {
-    launch_dec_bwd_heads(dc, ht, dv, xyz, feat, params, dg, view, w, d_params != nullptr, s);
-    const int64_t nthreads = d_feat ? dc.A * 32 : dc.A;
-    hipLaunchKernelGGL(k_dec_bwd_anchor, dim3((unsigned)((nthreads + kAnchorThreads - 1) / kAnchorThreads)),
-                       dim3(kAnchorThreads), 0, s, dc, dv, xyz, w, view, ht.m[4] > 0 ? 1 : 0, d_xyz, d_feat);
-  }
+  for (int view = 0; view < dc.n_views; ++view)
+    launch_dec_bwd(dc, ht, dv, xyz, feat, params, dg, view, w, d_xyz, d_feat, d_params != nullptr, s);
   const unsigned nrb = d_params ? (unsigned)((dc.n_params + 63) / 64) + 1 : 1u;
   const unsigned nmean = d_xyz ? (unsigned)((dc.A * 3 + 255) / 256) : 0u;
   hipLaunchKernelGGL(k_decode_reduce, dim3(nrb + nmean), dim3(256), 0, s, dc, dv, w, d_params, d_pose, (int)nrb, dg,

@@ -1,28 +1,16 @@
-// Decoder backward on the matrix cores (VJP of UP-SLAM Eq. 8 and Eq. 9),
-// per view. For each 16-anchor tile a workgroup recomputes the first layer
-// and the outputs of its heads, then forms every gradient with FP32 16x16x4
-// MFMAs and keeps the parameter gradients in registers across its tiles:
+// Decoder forward on the matrix cores (UP-SLAM Eq. 8 and Eq. 9), per view and
+// head group. For each 16-anchor tile a workgroup forms the first layer and
+// the second-layer rows of its heads with FP32 16x16x4 MFMAs:
 //   Z_h = X W1_h^T + b1_h, H_h = act(Z_h)       (ReLU; SoftPlus for features)
-//   Y_h = H_h W2_h^T + b2_h, dY = dL/d(decoded) * act'(Y_h)
-//   dW2_h += dY^T H_h, db2_h += sum_a dY        (K = the tile's anchors)
-//   dH_h = dY W2_h, dZ_h = dH_h * act'(Z_h)     (act' from H)
-//   dW1_h += dZ_h^T X, db1_h += sum_a dZ_h
-//   dX_h = dZ_h W1_h
+//   Y_h = H_h W2_h^T + b2_h, decoded = out_act(Y_h)
 // The heads are split over two kinds of workgroup that run side by side
 // (blockIdx.y): group 0 takes opacity, colour, scale and rotation, one head
-// per wave, and sums the four dX_h through LDS; group 1 takes the feature
-// head: its hidden layer is formed once (one 16-unit half on each of waves 0
-// and 1), its output rows are split over the four waves, whose dH partials
-// are summed through LDS before dZ. Each group writes its dX partial per anchor
-// and one partial of each of its parameters per workgroup; the anchor
-// gradients and the parameter sums follow in fixed order (deterministic).
+// per wave; group 1 takes the feature head: its hidden layer is formed once
+// (one 16-unit half on each of waves 0 and 1) and its output rows are split
+// over the four waves.
 //
 // Layouts of v_mfma_f32_16x16x4f32 (wave64): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16] and receives D rows 4 (l / 16) + r, column l % 16.
-// With K-step ks taken as anchors 4 (l / 16) + ks, the D tiles of dY and dZ
-// (rows = anchors) are directly the A operands of the weight-gradient
-// products; products with K over rows or units go through a per-wave LDS
-// transpose.
 #include <math.h>
 
 #include "decode_shared.h"
@@ -37,13 +25,10 @@ constexpr int kWaves = 4;
 constexpr int kNT = 64 * kWaves;
 constexpr int kW1S = 37;   // LDS row of a first-layer weight row (35 inputs + zero pad)
 constexpr int kW2S = 33;   // LDS row of a second-layer weight row (32 hidden units)
-constexpr int kXS = 37;    // LDS row of an anchor input (35 + pad); also the dX rows
-constexpr int kHS = 37;    // per-wave H rows (32 units), reused for the dX partial
-constexpr int kTS = 33;    // per-wave transpose rows
+constexpr int kXS = 37;    // LDS row of an anchor input (35 + distance column + pad)
+constexpr int kHS = 37;    // per-wave H rows (32 units + pad)
 constexpr int kAcc = 4;    // second-layer row tiles accumulated per wave
-constexpr int kMaxWG = 256;
 constexpr int kMaxFwdWG = 384;
-constexpr int kDX = 36;    // floats per anchor of a dX partial in the workspace
 
 ASGS_DEV f4v mfma(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
@@ -53,31 +38,9 @@ ASGS_DEV void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Activations with the hardware exp2 / log2 / reciprocal (relative error of a
-// few ulp, far inside the FP32 decoder's 1e-5 budget).
-ASGS_DEV float fexp(float x) { return __expf(x); }
-ASGS_DEV float fsigm(float y) { return __builtin_amdgcn_rcpf(1.f + fexp(-y)); }
-ASGS_DEV float fsoftplus(float z) { return fmaxf(z, 0.f) + __logf(1.f + fexp(-fabsf(z))); }
-ASGS_DEV float fout_act(int h, float y, float l_s) {
-  switch (h) {
-    case 0:
-    case 1: return fsigm(y);
-    case 2: return l_s * fsigm(y);
-    default: return y;
-  }
-}
-ASGS_DEV float fact_grad(int h, float y, float l_s) {
-  switch (h) {
-    case 0:
-    case 1: { const float s = fsigm(y); return s * (1.f - s); }
-    case 2: { const float s = fsigm(y); return l_s * s * (1.f - s); }
-    default: return 1.f;
-  }
-}
-
 // Float offsets of the LDS arrays of one group (dynamic shared memory).
 struct GroupLds {
-  int W1s, b1s, W2s, b2s, X, G, H, T, total;
+  int W1s, b1s, W2s, b2s, X, G, H, total;
 };
 
 // What one group of heads needs: its heads [hbase, hbase + nheads), their
@@ -112,7 +75,6 @@ struct Views {
   float (*X)[kXS];
   float* G;
   float (*H)[16][kHS];
-  float (*T)[16][kTS];
 };
 
 ASGS_DEV Views carve(float* smem, const GroupLds& L) {
@@ -124,7 +86,6 @@ ASGS_DEV Views carve(float* smem, const GroupLds& L) {
   S.X = reinterpret_cast<float (*)[kXS]>(smem + L.X);
   S.G = smem + L.G;
   S.H = reinterpret_cast<float (*)[16][kHS]>(smem + L.H);
-  S.T = reinterpret_cast<float (*)[16][kTS]>(smem + L.T);
   return S;
 }
 
@@ -166,109 +127,6 @@ ASGS_DEV void head_forward_half(const Views& S, float (*Hw)[kHS], const HeadCtx&
   for (int r = 0; r < 4; ++r) {
     const float zz = z[r] + b;
     Hw[4 * fg + r][u] = c.h == 4 ? fsoftplus(zz) : fmaxf(zz, 0.f);
-  }
-}
-
-// Output row tiles [t0, t0 + nt) of head c (nt <= kAcc): dY, dW2, db2 and the
-// partial dH over these rows.
-ASGS_DEV void head_rows(const Views& S, float (*Hw)[kHS], float (*Tw)[kTS], const HeadCtx& c, const RowMap& rm,
-                        int t0, int nt, int k, float l_s, f4v (&dw2)[kAcc][2], float (&db2)[kAcc], f4v& dh0,
-                        f4v& dh1, int fl, int fg) {
-#pragma unroll
-  for (int i = 0; i < kAcc; ++i) {
-    if (i >= nt) break;
-    const int r0 = 16 * (t0 + i);
-    const int orow = r0 + fl;
-    const bool rok = orow < c.rows;
-    const int wrow = c.lrow0 + (rok ? orow : 0);
-    f4v y = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const int kk = 4 * ks + fg;
-      y = mfma(Hw[fl][kk], S.W2s[wrow * kW2S + kk], y);
-    }
-    const float bias = S.b2s[wrow];
-    const int gi = rm.gi[i], gc = rm.gc[i];
-    f4v dy;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int a = 4 * fg + r;
-      const float g = S.G[c.gbase + gc * 16 * k + a * k + gi];
-      dy[r] = rok ? g * fact_grad(c.h, y[r] + bias, l_s) : 0.f;
-      Tw[a][fl] = dy[r];
-    }
-    db2[i] += (dy[0] + dy[1]) + (dy[2] + dy[3]);
-    // dW2 += dY^T H: A = own dY registers (K = anchors 4 fg + ks), B = H rows
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int a = 4 * fg + ks;
-      dw2[i][0] = mfma(dy[ks], Hw[a][fl], dw2[i][0]);
-      dw2[i][1] = mfma(dy[ks], Hw[a][16 + fl], dw2[i][1]);
-    }
-    wave_sync();
-    // dH += dY W2 (K = the tile's rows, through the transpose)
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int kr = r0 + 4 * ks + fg;
-      const bool kok = kr < c.rows;
-      const int wr = c.lrow0 + (kok ? kr : 0);
-      const float av = Tw[fl][4 * ks + fg];
-      const float b0 = S.W2s[wr * kW2S + fl], b1 = S.W2s[wr * kW2S + 16 + fl];
-      dh0 = mfma(av, kok ? b0 : 0.f, dh0);
-      dh1 = mfma(av, kok ? b1 : 0.f, dh1);
-    }
-    wave_sync();
-  }
-}
-
-// dZ of head c from the complete dH into the wave's transpose rows (and
-// registers, rows = anchors).
-ASGS_DEV void head_dz(float (*Hw)[kHS], float (*Tw)[kTS], const HeadCtx& c, f4v dh0, f4v dh1, f4v (&dz)[2],
-                      int fl, int fg) {
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    const int u = 16 * half + fl;
-    const f4v dh = half ? dh1 : dh0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int a = 4 * fg + r;
-      const float hv = Hw[a][u];
-      dz[half][r] = c.h == 4 ? dh[r] * (1.f - fexp(-hv)) : (hv > 0.f ? dh[r] : 0.f);
-      Tw[a][u] = dz[half][r];
-    }
-  }
-  wave_sync();
-}
-
-// dW1 += dZ^T X for unit half `half`: A = own dZ registers (K = anchors), B = X rows.
-ASGS_DEV void head_w1(const Views& S, const f4v (&dz)[2], int half, f4v (&dw1)[3], float& db1, int fg, int fl) {
-  db1 += (dz[half][0] + dz[half][1]) + (dz[half][2] + dz[half][3]);
-#pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
-    const int a = 4 * fg + ks;
-#pragma unroll
-    for (int ct = 0; ct < 3; ++ct) {
-      const int cc = 16 * ct + fl;
-      dw1[ct] = mfma(dz[half][ks], cc < kXS ? S.X[a][cc] : 0.f, dw1[ct]);
-    }
-  }
-}
-
-// dX += dZ W1_h for input column tiles [ct0, ct1) (K = the head's 32 units,
-// through the transpose).
-ASGS_DEV void head_dx(const Views& S, float (*Tw)[kTS], const HeadCtx& c, int ct0, int ct1, f4v (&dx)[3], int fl,
-                      int fg) {
-#pragma unroll
-  for (int ks = 0; ks < 8; ++ks) {
-    const int u = 4 * ks + fg;
-    const float av = Tw[fl][u];
-    const float* w1 = &S.W1s[(c.lunit0 + u) * kW1S];
-#pragma unroll
-    for (int ct = 0; ct < 3; ++ct) {
-      if (ct < ct0 || ct >= ct1) continue;
-      const int cc = 16 * ct + fl;
-      dx[ct] = mfma(av, cc < kW1S ? w1[cc] : 0.f, dx[ct]);
-    }
   }
 }
 
@@ -394,242 +252,6 @@ ASGS_DEV void stage_weights(const Views& S, const GroupDesc& gd, const HeadTable
     S.b1s[t] = vb1 + (vxs * lt0 + vxc * lt1);
   }
   if (t < gd.nrows) S.b2s[t] = vb2;
-}
-
-__global__ void __launch_bounds__(kNT, 2) k_dec_bwd_heads(DecodeConst dc, HeadTable ht, DecodeViews dv,
-                                                          const float* __restrict__ xyz,
-                                                          const float* __restrict__ feat,
-                                                          const float* __restrict__ params, asgs_gaussians dg,
-                                                          int view, DecWork w, GroupPair gp, int want_params) {
-  extern __shared__ __attribute__((aligned(16))) float smem[];
-  const int grp = blockIdx.y;
-  const GroupDesc& gd = gp.g[grp];
-  const Views S = carve(smem, gd.L);
-  const int t = threadIdx.x;
-  const int lane = t & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int fl = lane & 15, fg = lane >> 4;
-  const int A = (int)dc.A;
-  const int k = dc.k;
-  const int n = A * k;
-  // ---- this wave's head and rows ----
-  HeadCtx hc;
-  RowMap rm;
-  int t0, nt;
-  assign_rows(gd, ht, grp, wv, k, fl, hc, rm, t0, nt);
-  f4v dw2[kAcc][2];
-  float db2[kAcc];
-#pragma unroll
-  for (int i = 0; i < kAcc; ++i) {
-    dw2[i][0] = dw2[i][1] = f4v{0.f, 0.f, 0.f, 0.f};
-    db2[i] = 0.f;
-  }
-  f4v dw1[2][3];
-  float db1[2] = {0.f, 0.f};
-#pragma unroll
-  for (int q = 0; q < 2; ++q) dw1[q][0] = dw1[q][1] = dw1[q][2] = f4v{0.f, 0.f, 0.f, 0.f};
-  // group 1 (one head over four waves): one H for the workgroup, its two
-  // unit halves formed by waves 0 and 1 (read-only until the next tile)
-  float (*Hw)[kHS] = grp == 1 ? S.H[0] : S.H[wv];
-  float (*Tw)[kTS] = S.T[wv];
-  float* dxout = w.dxpart + (size_t)grp * A * kDX;
-  const int ngrid = (A + 15) / 16;
-  // inputs of a tile, fetched one tile ahead: features, then the upstream
-  // gradients, one element of each (head, component) plane per thread (the
-  // tile's run of 16 k <= 256 values of a plane is contiguous)
-  constexpr int kMaxPlanes = 16;
-  const int run = 16 * k;
-  const int nplanes = gd.gtot / run;
-  float xpre[2], ppre[3];
-  float gpre[kMaxPlanes];
-  auto fetch = [&](int tile) {
-    const int a0 = tile * 16;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = t + q * kNT;
-      const int a = e >> 5, c = e & 31;
-      xpre[q] = a0 + a < A ? feat[(size_t)(a0 + a) * 32 + c] : 0.f;
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ppre[c] = (t < 16 && a0 + t < A) ? xyz[(size_t)c * A + a0 + t] : 0.f;
-    const size_t gidx = (size_t)a0 * k + t;
-#pragma unroll
-    for (int pl = 0; pl < kMaxPlanes; ++pl) {
-      gpre[pl] = 0.f;
-      if (pl < nplanes && t < run && gidx < (size_t)n) {
-        // plane pl -> (head, component); heads of group 0: 1, 3, 3, 4 components
-        int h = 4, comp = pl;
-        if (grp == 0) {
-          h = pl < 1 ? 0 : pl < 4 ? 1 : pl < 7 ? 2 : 3;
-          comp = pl - (h == 0 ? 0 : h == 1 ? 1 : h == 2 ? 4 : 7);
-        }
-        gpre[pl] = out_plane(dg, view, h, comp, n)[gidx];
-      }
-    }
-  };
-  // the first tile's inputs are requested before the weights, so that the
-  // two latencies overlap
-  if ((int)blockIdx.x < ngrid) fetch(blockIdx.x);
-  stage_weights(S, gd, ht, params, t, dv.lt[view][0], dv.lt[view][1]);
-  for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x) {
-    const int a0 = tile * 16;
-    __syncthreads();  // weights staged / the previous tile's readers are done
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int e = t + q * kNT;
-      S.X[e >> 5][e & 31] = xpre[q];
-    }
-#pragma unroll
-    for (int pl = 0; pl < kMaxPlanes; ++pl)
-      if (pl < nplanes && t < run) S.G[pl * run + t] = gpre[pl];
-    if (t < 16) {
-      float D[3] = {0.f, 0.f, 0.f}, dist = 1.f;
-      if (a0 + t < A) {
-        for (int c = 0; c < 3; ++c) D[c] = ppre[c] - dv.c[view][c];
-        dist = sqrtf(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
-        for (int c = 0; c < 3; ++c) D[c] /= dist;
-      }
-      for (int c = 0; c < 3; ++c) S.X[t][32 + c] = D[c];
-      S.X[t][35] = ht.nx > 0 && a0 + t < A ? dist : 0.f;  // distance input (weight column 35)
-      S.X[t][36] = 0.f;
-    }
-    __syncthreads();
-    if (tile + (int)gridDim.x < ngrid) fetch(tile + gridDim.x);
-    f4v dx[3];
-#pragma unroll
-    for (int ct = 0; ct < 3; ++ct) dx[ct] = f4v{0.f, 0.f, 0.f, 0.f};
-    f4v dh0 = {0.f, 0.f, 0.f, 0.f}, dh1 = dh0;
-    f4v dz[2];
-    if (grp == 1) {
-      if (wv < 2) head_forward_half(S, Hw, hc, wv, fl, fg);
-      __syncthreads();  // the shared H is complete
-    } else {
-      head_forward(S, Hw, hc, fl, fg);
-      wave_sync();
-    }
-    head_rows(S, Hw, Tw, hc, rm, t0, nt, k, dc.l_s, dw2, db2, dh0, dh1, fl, fg);
-    if (grp == 0) {
-      head_dz(Hw, Tw, hc, dh0, dh1, dz, fl, fg);
-      head_w1(S, dz, 0, dw1[0], db1[0], fg, fl);
-      head_w1(S, dz, 1, dw1[1], db1[1], fg, fl);
-      head_dx(S, Tw, hc, 0, 3, dx, fl, fg);
-      wave_sync();
-      // this head's dX into the wave's H rows (H is no longer read)
-#pragma unroll
-      for (int ct = 0; ct < 3; ++ct)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (16 * ct + fl < kXS) Hw[4 * fg + r][16 * ct + fl] = dx[ct][r];
-      __syncthreads();
-      // the four heads' dX in a fixed order (column 35: the distance input)
-      for (int e = t; e < 16 * kDX; e += kNT) {
-        const int a = e / kDX, c = e - a * kDX;
-        if (a0 + a < A)
-          dxout[(size_t)(a0 + a) * kDX + c] = (S.H[0][a][c] + S.H[1][a][c]) + (S.H[2][a][c] + S.H[3][a][c]);
-      }
-    } else {
-      // the feature head's dH partials of the four waves, summed in a fixed order
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        Tw[4 * fg + r][fl] = dh0[r];
-        Tw[4 * fg + r][16 + fl] = dh1[r];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = 4 * fg + r;
-        dh0[r] = (S.T[0][a][fl] + S.T[1][a][fl]) + (S.T[2][a][fl] + S.T[3][a][fl]);
-        dh1[r] = (S.T[0][a][16 + fl] + S.T[1][a][16 + fl]) + (S.T[2][a][16 + fl] + S.T[3][a][16 + fl]);
-      }
-      __syncthreads();  // every wave has read the partials before dZ overwrites them
-      head_dz(Hw, Tw, hc, dh0, dh1, dz, fl, fg);
-      if (wv == 0) {
-        head_w1(S, dz, 0, dw1[0], db1[0], fg, fl);
-      } else if (wv == 1) {
-        head_w1(S, dz, 1, dw1[0], db1[0], fg, fl);
-      } else {
-        // input columns 0..31 on wave 2, 32..35 on wave 3, straight to the workspace
-        const int ct0 = wv == 2 ? 0 : 2, ct1 = wv == 2 ? 2 : 3;
-        head_dx(S, Tw, hc, ct0, ct1, dx, fl, fg);
-#pragma unroll
-        for (int ct = 0; ct < 3; ++ct) {
-          if (ct < ct0 || ct >= ct1) continue;
-          const int c = 16 * ct + fl;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int a = 4 * fg + r;
-            if (c < kDX && a0 + a < A) dxout[(size_t)(a0 + a) * kDX + c] = dx[ct][r];
-          }
-        }
-      }
-    }
-  }
-  if (!want_params) return;
-  // ---- this workgroup's parameter partials ----
-  float* P = w.part;
-  const int64_t bk = blockIdx.x, nbk = w.nblk_w;
-  const bool add = view > 0;
-  auto put = [&](int64_t pi, float v) {
-    float* dst = P + part_index(pi, bk, nbk);
-    *dst = (add ? *dst : 0.f) + v;
-  };
-  {
-    const int64_t wb = ht.off[hc.h] + kHid * kIn + kHid;
-#pragma unroll
-    for (int i = 0; i < kAcc; ++i) {
-      if (i >= nt) continue;
-      const int r0 = 16 * (t0 + i);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + 4 * fg + r;
-        if (row < hc.rows) {
-          put(wb + (int64_t)row * kHid + fl, dw2[i][0][r]);
-          put(wb + (int64_t)row * kHid + 16 + fl, dw2[i][1][r]);
-        }
-      }
-      // bias: lanes of row fl summed over the four anchor groups
-      float sb = db2[i];
-      sb += __shfl_xor(sb, 16);
-      sb += __shfl_xor(sb, 32);
-      if (fg == 0 && r0 + fl < hc.rows) put(wb + (int64_t)hc.rows * kHid + r0 + fl, sb);
-    }
-  }
-  const int64_t w1b = ht.off[hc.h];
-  const int64_t xb = ht.xoff[hc.h];
-  const int nx = ht.nx;
-  const float lt0 = dv.lt[view][0], lt1 = dv.lt[view][1];
-  // extra input columns: the distance weight's gradient is column 35 of the
-  // products with X; the temporal weights' gradients are the bias gradient
-  // times the view's embedding (accumulated over views by put)
-  auto put_half = [&](int half, const f4v (&d)[3], float b) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int u = 16 * half + 4 * fg + r;
-      put(w1b + (int64_t)u * kIn + fl, d[0][r]);
-      put(w1b + (int64_t)u * kIn + 16 + fl, d[1][r]);
-      if (fl < 3) put(w1b + (int64_t)u * kIn + 32 + fl, d[2][r]);
-      if (fl == 3 && nx > 0) put(xb + (int64_t)u * nx, d[2][r]);
-    }
-    float sb = b;
-    sb += __shfl_xor(sb, 16);
-    sb += __shfl_xor(sb, 32);
-    if (fg == 0) {
-      const int u = 16 * half + fl;
-      put(w1b + kHid * kIn + u, sb);
-      if (nx == 3) {
-        put(xb + (int64_t)u * 3 + 1, sb * lt0);
-        put(xb + (int64_t)u * 3 + 2, sb * lt1);
-      }
-    }
-  };
-  if (grp == 0) {
-    put_half(0, dw1[0], db1[0]);
-    put_half(1, dw1[1], db1[1]);
-  } else if (wv == 0) {
-    put_half(0, dw1[0], db1[0]);
-  } else if (wv == 1) {
-    put_half(1, dw1[0], db1[0]);
-  }
 }
 
 // Forward on the matrix cores, per (view, head group): the first layer and
@@ -762,8 +384,8 @@ __global__ void __launch_bounds__(kNT, 3) k_dec_fwd_heads(DecodeConst dc, HeadTa
   }
 }
 
-// LDS of one group; the forward needs no transpose rows (with_t false).
-GroupDesc group_desc(const HeadTable& ht, int k, int hbase, int nheads, bool with_t) {
+// LDS of one group.
+GroupDesc group_desc(const HeadTable& ht, int k, int hbase, int nheads) {
   GroupDesc g{};
   g.hbase = hbase;
   g.nheads = nheads;
@@ -790,26 +412,18 @@ GroupDesc group_desc(const HeadTable& ht, int k, int hbase, int nheads, bool wit
   g.L.X = take(16 * kXS);
   g.L.G = take(gb);
   g.L.H = take(kWaves * 16 * kHS);
-  g.L.T = with_t ? take(kWaves * 16 * kTS) : 0;
   g.L.total = o;
   return g;
 }
 
 }  // namespace
 
-int64_t dec_bwd_heads_blocks(int64_t n_anchors) {
-  const int64_t tiles = (n_anchors + 15) / 16;
-  return tiles < kMaxWG ? tiles : kMaxWG;
-}
-
-size_t dec_bwd_dx_floats(int64_t n_anchors) { return 2 * (size_t)n_anchors * kDX; }
-
 void launch_dec_fwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                           const float* feat, const float* off, const float* params, const asgs_gaussians& out,
                           hipStream_t s) {
-  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4, false);
+  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4);
   const bool has_feat = ht.m[4] > 0;
-  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1, false) : g0;
+  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1) : g0;
   const int ng = has_feat ? 2 : 1;
   const int lds = (g0.L.total > g1.L.total ? g0.L.total : g1.L.total) * (int)sizeof(float);
   static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (at most ~77 KiB for k = 16)
@@ -823,23 +437,6 @@ void launch_dec_fwd_heads(const DecodeConst& dc, const HeadTable& ht, const Deco
   const unsigned nblk = (unsigned)(tiles < kMaxFwdWG ? tiles : kMaxFwdWG);
   hipLaunchKernelGGL(k_dec_fwd_heads, dim3(nblk, (unsigned)(ng * dc.n_views)),
                      dim3(kNT), lds, s, dc, ht, dv, xyz, feat, off, params, out, GroupPair{{g0, g1}}, ng);
-}
-
-void launch_dec_bwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
-                          const float* feat, const float* params, const asgs_gaussians& dg, int view,
-                          const DecWork& w, bool want_params, hipStream_t s) {
-  const GroupDesc g0 = group_desc(ht, dc.k, 0, 4, true);
-  const bool has_feat = ht.m[4] > 0;
-  const GroupDesc g1 = has_feat ? group_desc(ht, dc.k, 4, 1, true) : g0;
-  const int lds = (g0.L.total > g1.L.total ? g0.L.total : g1.L.total) * (int)sizeof(float);
-  static bool attr_set = false;  // allow more than 64 KiB of dynamic LDS (at most ~77 KiB for k = 16)
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_dec_bwd_heads),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(k_dec_bwd_heads, dim3((unsigned)w.nblk_w, has_feat ? 2u : 1u), dim3(kNT), lds, s, dc, ht, dv,
-                     xyz, feat, params, dg, view, w, GroupPair{{g0, g1}}, want_params ? 1 : 0);
 }
 
 }  // namespace asgs

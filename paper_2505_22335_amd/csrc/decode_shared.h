@@ -70,11 +70,32 @@ ASGS_DEV float act_grad(int h, float y, float l_s) {
   }
 }
 
+// Activations with the hardware exp2 / log2 / reciprocal (relative error of a
+// few ulp, far inside the FP32 decoder's 1e-5 budget).
+ASGS_DEV float fexp(float x) { return __expf(x); }
+ASGS_DEV float fsigm(float y) { return __builtin_amdgcn_rcpf(1.f + fexp(-y)); }
+ASGS_DEV float fsoftplus(float z) { return fmaxf(z, 0.f) + __logf(1.f + fexp(-fabsf(z))); }
+ASGS_DEV float fout_act(int h, float y, float l_s) {
+  switch (h) {
+    case 0:
+    case 1: return fsigm(y);
+    case 2: return l_s * fsigm(y);
+    default: return y;
+  }
+}
+ASGS_DEV float fact_grad(int h, float y, float l_s) {
+  switch (h) {
+    case 0:
+    case 1: { const float s = fsigm(y); return s * (1.f - s); }
+    case 2: { const float s = fsigm(y); return l_s * s * (1.f - s); }
+    default: return 1.f;
+  }
+}
+
 struct DecWork {
   float* part;    // per-workgroup parameter-gradient partials (chunk-major, see part_index)
-  float* dcpart;  // [nblk_m][n_views][3], one row per anchor-gradient block
-  float* dxpart;  // [2][A][36]: dL/dX of each head group for the current view
-  int32_t nblk_w, nblk_m;
+  float* dcpart;  // [nblk_w][n_views][3]: camera-centre gradient partial of each workgroup
+  int32_t nblk_w;
 };
 
 
@@ -83,14 +104,13 @@ struct DecWork {
 // contiguous, so the reduction of one run reads one contiguous region.
 ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
 
-int64_t dec_bwd_heads_blocks(int64_t n_anchors);
-size_t dec_bwd_dx_floats(int64_t n_anchors);
+int64_t dec_bwd_blocks(int64_t n_anchors);
 void launch_dec_fwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                           const float* feat, const float* off, const float* params, const asgs_gaussians& out,
                           hipStream_t s);
-void launch_dec_bwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
-                          const float* feat, const float* params, const asgs_gaussians& dg, int view,
-                          const DecWork& w, bool want_params, hipStream_t s);
+void launch_dec_bwd(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
+                    const float* feat, const float* params, const asgs_gaussians& dg, int view, const DecWork& w,
+                    float* d_xyz, float* d_feat, bool want_params, hipStream_t s);
 
 
 void launch_decode_mfma(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
