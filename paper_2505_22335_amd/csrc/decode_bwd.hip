@@ -52,7 +52,8 @@ constexpr int kOffW1 = 0;
 constexpr int kOffX = kOffW1 + kHeads * kHid * kW1L;
 constexpr int kOffHB = kOffX + 2 * 16 * kXL;
 constexpr int kOffYB = kOffHB + kBW * 16 * kHB;
-constexpr int kOffDH = kOffYB + kBW * 16 * kYB;
+constexpr int kOffHF = kOffYB + kBW * 16 * kYB;  // the feature head's H, shared by its waves
+constexpr int kOffDH = kOffHF + 16 * kHB;
 constexpr int kOffDX = kOffDH + 4 * 64 * 8;
 constexpr int kOffG = kOffDX + 2 * kSlots * 16 * kDXL;
 constexpr int kPlanes = 27;    // (head, component) planes of the upstream gradients: 1 + 3 + 3 + 4 + 16
@@ -96,6 +97,7 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
   float (*const XB)[16][kXL] = reinterpret_cast<float (*)[16][kXL]>(smem + kOffX);
   float (*const HBw)[kHB] = reinterpret_cast<float (*)[kHB]>(smem + kOffHB + wv * 16 * kHB);
   float (*const YBw)[kYB] = reinterpret_cast<float (*)[kYB]>(smem + kOffYB + wv * 16 * kYB);
+  float (*const HF)[kHB] = reinterpret_cast<float (*)[kHB]>(smem + kOffHF);
   float* const DH = smem + kOffDH;
   float (*const DX)[kSlots][16][kDXL] = reinterpret_cast<float (*)[kSlots][16][kDXL]>(smem + kOffDX);
   float* const GB = smem + kOffG;
@@ -118,9 +120,11 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
     nt = base + (q < extra ? 1 : 0);
     t0 = q * base + (q < extra ? q : extra);
   }
-  const bool do_dw1 = wv < 4 || q == 3;  // dW1, db1 of the head (dX: waves 0..3 and feature wave 2)
-  const int off = (int)ht.off[hd], xoff = (int)ht.xoff[hd];  // parameter offsets (also in the LDS copy)
-  const int w2o = off + kHid * kIn + kHid;  // W2 [rows][32], then b2 [rows]
+  // dX: waves 0..3 and feature wave 2. dW1, db1: waves 0..2 of their heads,
+  // feature wave 0 of the rotation head (its wave has the most rows) and
+  // feature wave 3 of the feature head
+  const int hw1 = wv < 3 ? wv : wv == 4 ? 3 : (wv == 7 && has_feat) ? 4 : -1;
+  const int w2o = (int)ht.off[hd] + kHid * kIn + kHid;  // the head's W2 [rows][32], then b2 [rows]
   // the tile's upstream gradients are staged per (head, component) plane as
   // runs of 16 k values (stride run + 1, odd, against bank conflicts)
   const int run = 16 * k, gstride = run + 1;
@@ -154,13 +158,18 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
   // wave w loads planes w, w + 8, w + 16, w + 24 (those present), each as
   // kR coalesced chunks of 64 values (16 k <= 64 kR)
   const int nplanes = has_feat ? kPlanes : 11;
-  const float* pbase[4];  // the plane, or a valid stand-in when absent
+  // the plane, or for an absent plane the first parameter as a stand-in
+  // that is only ever read at index 0
+  const float* pbase[4];
+  int plim[4];  // indices below plim are read from the plane, others at 0
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int p = wv + 8 * i;
     const int ph = p < 1 ? 0 : p < 4 ? 1 : p < 7 ? 2 : p < 11 ? 3 : 4;
     const int pc = p - (ph == 0 ? 0 : ph == 1 ? 1 : ph == 2 ? 4 : ph == 3 ? 7 : 11);
-    pbase[i] = p < nplanes ? out_plane(dg, view, ph, pc, n) : params;
+    const bool present = p < nplanes;
+    pbase[i] = present ? out_plane(dg, view, ph, pc, n) : params;
+    plim[i] = present ? n : 0;
   }
   float gpre[4][kR];
   auto fetch_g = [&](int tile) {
@@ -170,7 +179,7 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
 #pragma unroll
       for (int c = 0; c < kR; ++c) {
         const int gi = g0 + lane + 64 * c;
-        gpre[i][c] = pbase[i][gi < n ? gi : 0];
+        gpre[i][c] = pbase[i][gi < plim[i] ? gi : 0];
       }
   };
   auto put_g = [&](int buf, int tile) {
@@ -319,8 +328,8 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
   const float* w1l = W1L + hd * kHid * kW1L;
 
   // dZ from dH and H (registers, units x anchors), then the head's dX^T into
-  // its slot and dW1 += dZ^T X (dZ transposed through the wave's rows)
-  auto tail = [&](const f4v (&h)[2], const f4v (&dh)[2], int buf, bool dx_now, bool dw1_now) {
+  // its slot; with publish, dZ also into the wave's transpose rows
+  auto tail = [&](const f4v (&h)[2], const f4v (&dh)[2], int buf, bool dx_now, bool publish) {
     f4v dz[2];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -349,31 +358,34 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
       for (int ct = 0; ct < 3; ++ct)
         if (16 * ct + 4 * fg < kDXL) *reinterpret_cast<f4v*>(&DX[buf][wv < 4 ? wv : 4][fl][16 * ct + 4 * fg]) = dx[ct];
     }
-    if (dw1_now) {
+    if (publish) {
 #pragma unroll
       for (int b = 0; b < 2; ++b) *reinterpret_cast<f4v*>(&HBw[fl][16 * b + 4 * fg]) = dz[b];
-      wave_sync();
-      float dzt[2][4];
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dzt[b][r] = HBw[4 * fg + r][16 * b + fl];
-      wave_sync();
-      float xa[3][4];
-#pragma unroll
-      for (int ct = 0; ct < 3; ++ct)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) xa[ct][r] = XB[buf][4 * fg + r][16 * ct + fl];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        db1[b] += (dzt[b][0] + dzt[b][1]) + (dzt[b][2] + dzt[b][3]);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int ct = 0; ct < 3; ++ct) dw1[b][ct] = mfma(dzt[b][r], xa[ct][r], dw1[b][ct]);
-      }
     }
   };
+  // dW1 += dZ^T X, db1 += sum_a dZ, with dZ read by rows of anchors from the
+  // transpose rows src of the wave that formed it
+  auto acc_dw1 = [&](const float (*src)[kHB], int buf) {
+    float dzt[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dzt[b][r] = src[4 * fg + r][16 * b + fl];
+    float xa[3][4];
+#pragma unroll
+    for (int ct = 0; ct < 3; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xa[ct][r] = XB[buf][4 * fg + r][16 * ct + fl];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      db1[b] += (dzt[b][0] + dzt[b][1]) + (dzt[b][2] + dzt[b][3]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int ct = 0; ct < 3; ++ct) dw1[b][ct] = mfma(dzt[b][r], xa[ct][r], dw1[b][ct]);
+    }
+  };
+  float (*const HB3)[kHB] = reinterpret_cast<float (*)[kHB]>(smem + kOffHB + 3 * 16 * kHB);
 
   int j = 0;
   for (int tile = blockIdx.x; tile < ngrid; tile += gridDim.x, ++j) {
@@ -387,7 +399,8 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
     }
     f4v h[2], dh[2];
     dh[0] = dh[1] = f4v{0.f, 0.f, 0.f, 0.f};
-    if (active) {
+    float ht_[2][4];
+    if (wv < 4) {
       // Z^T (units x anchors) = W1 X^T, K = inputs
       f4v z0 = {0.f, 0.f, 0.f, 0.f}, z1 = z0;
 #pragma unroll
@@ -398,20 +411,37 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float za = z0[r] + b1r[0][r], zb = z1[r] + b1r[1][r];
-        h[0][r] = hd == 4 ? fsoftplus(za) : fmaxf(za, 0.f);
-        h[1][r] = hd == 4 ? fsoftplus(zb) : fmaxf(zb, 0.f);
+        h[0][r] = fmaxf(z0[r] + b1r[0][r], 0.f);
+        h[1][r] = fmaxf(z1[r] + b1r[1][r], 0.f);
       }
       // H by rows of anchors (B operand of dW2)
 #pragma unroll
       for (int b = 0; b < 2; ++b) *reinterpret_cast<f4v*>(&HBw[fl][16 * b + 4 * fg]) = h[b];
       wave_sync();
-      float ht_[2][4];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) ht_[b][r] = HBw[4 * fg + r][16 * b + fl];
-      wave_sync();
+    } else if (has_feat && q < 2) {
+      // the feature head's hidden layer once: unit block q on feature wave q
+      f4v z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 9; ++s) z = mfma(w1l[(16 * q + fl) * kW1L + 4 * s + fg], XB[buf][fl][4 * s + fg], z);
+      f4v hq;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hq[r] = fsoftplus(z[r] + (q ? b1r[1][r] : b1r[0][r]));
+      *reinterpret_cast<f4v*>(&HF[fl][16 * q + 4 * fg]) = hq;
+    }
+    __syncthreads();  // the feature head's H is complete
+    if (wv >= 4 && has_feat) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        h[b] = *reinterpret_cast<const f4v*>(&HF[fl][16 * b + 4 * fg]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ht_[b][r] = HF[4 * fg + r][16 * b + fl];
+      }
+    }
+    if (active) {
 #pragma unroll
       for (int i = 0; i < kR; ++i) {
         if (i >= nt) break;
@@ -447,12 +477,17 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
     }
     if (wv < 4) {
       tail(h, dh, buf, true, true);
+      if (hw1 >= 0) {
+        wave_sync();
+        acc_dw1(HBw, buf);
+      }
     } else if (active) {
       // the feature waves' dH partials, summed below in a fixed order
 #pragma unroll
       for (int b = 0; b < 2; ++b) *reinterpret_cast<f4v*>(&DH[(q * 64 + lane) * 8 + 4 * b]) = dh[b];
     }
-    __syncthreads();  // feature dH partials written; every thread is past the last tile's anchor step
+    __syncthreads();  // feature dH partials and the rotation head's dZ written; every thread is past the last tile's anchor step
+    if (wv == 4) acc_dw1(HB3, buf);  // the rotation head's dW1
     if (wv >= 4 && active && (q == 2 || q == 3)) {
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
@@ -463,6 +498,10 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
         dh[b] = (p0 + p1) + (p2 + p3);
       }
       tail(h, dh, buf, q == 2, q == 3);
+      if (q == 3) {
+        wave_sync();
+        acc_dw1(HBw, buf);
+      }
     }
     if (more) {
       put_x(buf ^ 1, tile + gridDim.x);
@@ -516,7 +555,7 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
       if (lane == 0) w.dcpart[((int64_t)blockIdx.x * dc.n_views + view) * 3 + cc] = x;
     }
   }
-  if (!want_params || !active) return;
+  if (!want_params) return;
   // ---- this workgroup's parameter partials ----
   float* P = w.part;
   const int64_t bk = blockIdx.x, nbk = w.nblk_w;
@@ -527,7 +566,7 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
   };
 #pragma unroll
   for (int i = 0; i < kR; ++i) {
-    if (i >= nt) break;
+    if (!active || i >= nt) break;
     const int r0 = 16 * (t0 + i);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -542,7 +581,8 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
     sb += __shfl_xor(sb, 32);
     if (fg == 0 && r0 + fl < rows) put(w2o + (int64_t)rows * kHid + r0 + fl, sb);
   }
-  if (!do_dw1) return;
+  if (hw1 < 0) return;
+  const int o1w = (int)ht.off[hw1], oxw = (int)ht.xoff[hw1];  // the head of this wave's dW1
   // extra input columns: the distance weight's gradient is column 35 of the
   // products with X; the temporal weights' gradients are the bias gradient
   // times the view's embedding (accumulated over views by put)
@@ -551,20 +591,20 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int u = 16 * b + 4 * fg + r;
-      put(off + (int64_t)u * kIn + fl, dw1[b][0][r]);
-      put(off + (int64_t)u * kIn + 16 + fl, dw1[b][1][r]);
-      if (fl < 3) put(off + (int64_t)u * kIn + 32 + fl, dw1[b][2][r]);
-      if (fl == 3 && nx > 0) put(xoff + (int64_t)u * nx, dw1[b][2][r]);
+      put(o1w + u * kIn + fl, dw1[b][0][r]);
+      put(o1w + u * kIn + 16 + fl, dw1[b][1][r]);
+      if (fl < 3) put(o1w + u * kIn + 32 + fl, dw1[b][2][r]);
+      if (fl == 3 && nx > 0) put(oxw + u * nx, dw1[b][2][r]);
     }
     float sb = db1[b];
     sb += __shfl_xor(sb, 16);
     sb += __shfl_xor(sb, 32);
     if (fg == 0) {
       const int u = 16 * b + fl;
-      put(off + kHid * kIn + u, sb);
+      put(o1w + kHid * kIn + u, sb);
       if (nx == 3) {
-        put(xoff + (int64_t)u * 3 + 1, sb * lt0);
-        put(xoff + (int64_t)u * 3 + 2, sb * lt1);
+        put(oxw + u * 3 + 1, sb * lt0);
+        put(oxw + u * 3 + 2, sb * lt1);
       }
     }
   }
