@@ -10,7 +10,7 @@
 // activations: sigmoid (opacity, rgb), l_s * sigmoid (scale), raw (rot, feat).
 //
 // FP32 path: forward and backward run on the matrix cores with FP32
-// 16x16x4 MFMAs, one 16-anchor tile at a time (forward: decode_heads.hip,
+// 16x16x4 MFMAs, one 16-anchor tile at a time (forward: decode_fwd.hip,
 // backward: decode_bwd.hip). The BF16 path runs the forward on the matrix
 // cores in BF16 (decode_mfma.hip). The backward recomputes the forward, forms
 // dL/dH from the second-layer weights, dL/dZ through the activations, dL/dX
@@ -48,7 +48,7 @@ ASGS_DEV void dec_bwd_mean(const DecodeConst& dc, const asgs_gaussians& dg, floa
 
 // Fixed-order reduction of the workgroup partials: 64 parameters per
 // workgroup, four threads per parameter (each a strided quarter of the
-// partials, four independent sums), combined in LDS. The extra workgroup
+// partials), combined in LDS. The extra workgroup
 // adds -R_cw dL/dc to the translation part of the pose gradient. Workgroups
 // from mean_first on take the mean gradients instead (one launch for both).
 __global__ void __launch_bounds__(256) k_decode_reduce(DecodeConst dc, DecodeViews dv, DecWork w, float* d_params,
@@ -65,18 +65,25 @@ __global__ void __launch_bounds__(256) k_decode_reduce(DecodeConst dc, DecodeVie
   const int64_t p = (int64_t)blockIdx.x * 64 + pl;
   const int64_t nparam_blocks = d_params ? (dc.n_params + 63) / 64 : 0;
   if ((int64_t)blockIdx.x < nparam_blocks) {
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    // sixteen loads in flight per thread and round, summed in a fixed tree
+    float acc = 0.f;
     if (p < dc.n_params) {
-      int b = q;
-      for (; b + 12 < w.nblk_w; b += 16) {
-        s0 += w.part[part_index(p, b, w.nblk_w)];
-        s1 += w.part[part_index(p, b + 4, w.nblk_w)];
-        s2 += w.part[part_index(p, b + 8, w.nblk_w)];
-        s3 += w.part[part_index(p, b + 12, w.nblk_w)];
+      const float* src = w.part + part_index(p, 0, w.nblk_w);  // workgroup b at src[64 b]
+      for (int b0 = q; b0 < w.nblk_w; b0 += 64) {
+        float v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int b = b0 + 4 * i;
+          v[i] = b < w.nblk_w ? src[(int64_t)b * 64] : 0.f;
+        }
+#pragma unroll
+        for (int st = 8; st > 0; st >>= 1)
+#pragma unroll
+          for (int i = 0; i < st; ++i) v[i] += v[i + st];
+        acc += v[0];
       }
-      for (; b < w.nblk_w; b += 4) s0 += w.part[part_index(p, b, w.nblk_w)];
     }
-    red[q][pl] = (s0 + s1) + (s2 + s3);
+    red[q][pl] = acc;
     __syncthreads();
     if (q == 0 && p < dc.n_params) d_params[p] = (red[0][pl] + red[1][pl]) + (red[2][pl] + red[3][pl]);
     return;
@@ -183,7 +190,7 @@ void launch_decode(const DecodeConst& dc, const float* xyz, const float* feat, c
     launch_decode_mfma(dc, ht, dv, xyz, feat, off, params, out, s);
     return;
   }
-  launch_dec_fwd_heads(dc, ht, dv, xyz, feat, off, params, out, s);
+  launch_dec_fwd(dc, ht, dv, xyz, feat, off, params, out, s);
 }
 
 void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float* feat, const float* off,

@@ -61,7 +61,7 @@ constexpr int kGB = kPlanes * (16 * ASGS_MAX_K + 1);  // one buffer: each plane'
 constexpr int kLdsFloats = kOffG + 2 * kGB;
 // the second-layer weights (at most 27 k = 432 rows of kW2L), b2 and b1 are
 // copied once into the region from kOffHB on
-static_assert(kLdsFloats - kOffHB >= 27 * ASGS_MAX_K * (kW2L + 1) + kHeads * kHid, "weight copy does not fit");
+static_assert(kLdsFloats - kOffHB >= 27 * ASGS_MAX_K * (kW2L + 1) + 3 + kHeads * kHid, "weight copy does not fit");
 
 ASGS_DEV f4v mfma(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(kBT, 1) k_dec_bwd(DecodeConst dc, HeadTable ht
   float* const W2L = smem + kOffHB;                         // [all rows][kW2L]
   const int nrows = ht.nrows;
   float* const B2L = W2L + nrows * kW2L;                    // [all rows]
-  float* const B1L = B2L + nrows;                           // [5 heads][32]
+  float* const B1L = B2L + ((nrows + 3) & ~3);             // [5 heads][32] (16-byte aligned)
   {
     // head by head, each a contiguous block of the packed parameters: every
     // load of the thread is issued before its first store

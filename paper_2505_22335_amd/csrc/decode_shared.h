@@ -108,9 +108,9 @@ struct DecWork {
 ASGS_DEV int64_t part_index(int64_t p, int64_t b, int64_t nblk) { return (p >> 6) * (nblk << 6) + (b << 6) + (p & 63); }
 
 int64_t dec_bwd_blocks(int64_t n_anchors);
-void launch_dec_fwd_heads(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
-                          const float* feat, const float* off, const float* params, const asgs_gaussians& out,
-                          hipStream_t s);
+void launch_dec_fwd(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
+                    const float* feat, const float* off, const float* params, const asgs_gaussians& out,
+                    hipStream_t s);
 void launch_dec_bwd(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
                     const float* feat, const float* params, const asgs_gaussians& dg, int view, const DecWork& w,
                     float* d_xyz, float* d_feat, bool want_params, hipStream_t s);
