@@ -36,7 +36,7 @@ in ``tests/test_oracle_*.py``.
 from .readings import (RenderOpts, READINGS, RESIDUAL_READINGS, FEATURE_READINGS, ANCHOR_READINGS,  # noqa: F401
                        MAPPING_READINGS)
 from .geometry import quat_to_rotmat, se3_exp, pose_cw, camera_center  # noqa: F401
-from .decode import decode, bf16_hidden_margin, HEAD_ORDER  # noqa: F401
+from .decode import decode, bf16_hidden_margin, bf16_flip_bound, HEAD_ORDER  # noqa: F401
 from .project import project  # noqa: F401
 from .binning import bin_and_sort  # noqa: F401
 from .composite import composite_tile, composite_bruteforce  # noqa: F401

@@ -94,15 +94,11 @@ def decode(xyz: torch.Tensor, feat: torch.Tensor, off: torch.Tensor,
     return g
 
 
-def bf16_hidden_margin(xyz: torch.Tensor, feat: torch.Tensor, weights: Dict[str, Dict[str, torch.Tensor]],
-                       cam_center: torch.Tensor, t: float = 0.0):
-    """Guard band of the bfloat16 variant's one computed operand: the hidden
-    activations H are rounded to bfloat16 after a single-precision first
-    layer, so an H within that layer's rounding of a bfloat16 rounding
-    midpoint may round either way. Per head, per anchor: the minimum over
-    the 32 hidden units of |H - nearest midpoint| / (sum of |terms| of Z),
-    with H and Z as in the bf16 mode above (inf where H = 0). Returns
-    {head: (A,) float64 numpy array}."""
+def _bf16_hidden(xyz, feat, weights, cam_center, t):
+    """Per head: the bf16 variant's single-precision-exact hidden activations
+    H (A, 32), the margin of each to the nearest bfloat16 rounding midpoint
+    relative to the sum of |terms| of Z (inf where H = 0), and the bfloat16
+    spacing around H."""
     A = xyz.shape[0]
     D = xyz - cam_center[None, :]
     dist = torch.linalg.norm(D, dim=1, keepdim=True)
@@ -123,9 +119,42 @@ def bf16_hidden_margin(xyz: torch.Tensor, feat: torch.Tensor, weights: Dict[str,
         Hn = H.numpy()
         with np.errstate(divide="ignore"):
             e = np.floor(np.log2(np.abs(Hn)))
-        ulp = np.exp2(e - 7)  # spacing of bfloat16 values around H (8 significant bits)
+        ulp = np.where(Hn != 0, np.exp2(e - 7), 0.0)  # spacing of bfloat16 values around H (8 significant bits)
         q = np.abs(Hn) / np.where(Hn != 0, ulp, 1.0)
         d = np.abs((q - np.floor(q)) - 0.5) * ulp
         marg = np.where(Hn != 0, d / np.maximum(scale.numpy(), 1e-300), np.inf)
-        out[name] = marg.min(axis=1)
+        out[name] = (Hn, marg, ulp)
+    return out
+
+
+def bf16_hidden_margin(xyz: torch.Tensor, feat: torch.Tensor, weights: Dict[str, Dict[str, torch.Tensor]],
+                       cam_center: torch.Tensor, t: float = 0.0):
+    """Guard band of the bfloat16 variant's one computed operand: the hidden
+    activations H are rounded to bfloat16 after a single-precision first
+    layer, so an H within that layer's rounding of a bfloat16 rounding
+    midpoint may round either way. Per head, per anchor: the minimum over
+    the 32 hidden units of |H - nearest midpoint| / (sum of |terms| of Z),
+    with H and Z as in the bf16 mode above (inf where H = 0). Returns
+    {head: (A,) float64 numpy array}."""
+    return {name: marg.min(axis=1) for name, (_, marg, _) in _bf16_hidden(xyz, feat, weights, cam_center, t).items()}
+
+
+def bf16_flip_bound(xyz: torch.Tensor, feat: torch.Tensor, weights: Dict[str, Dict[str, torch.Tensor]],
+                    cam_center: torch.Tensor, k: int, l_s: float = 0.02, t: float = 0.0, band: float = 2.0 ** -20):
+    """Largest change of each decoded value of the bf16 variant that hidden
+    units within the guard band (margin < band, see bf16_hidden_margin) can
+    cause by rounding the other way: such a unit's bfloat16 operand moves by
+    one bfloat16 spacing, which moves the row's pre-activation by that spacing
+    times |bf16(W2)| (the products are exact), summed over the unit's
+    in-band neighbours of the anchor; the output activations scale it by at
+    most their largest slope (1/4 for sigmoid, l_s/4 for the scale head, 1 for
+    the raw heads). Returns {head: (A * k, m) float64 numpy array}."""
+    slope = dict(opacity=0.25, rgb=0.25, scale=0.25 * l_s, rot=1.0, feat=1.0)
+    out = {}
+    for name, (_, marg, ulp) in _bf16_hidden(xyz, feat, weights, cam_center, t).items():
+        dH = np.where(marg < band, ulp, 0.0)
+        W2 = _bf16(weights[name]["W2"].detach()).numpy()
+        by = dH @ np.abs(W2).T  # (A, k m)
+        m = W2.shape[0] // k
+        out[name] = slope[name] * by.reshape(-1, m)
     return out

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libasgs.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "project.hip", "sort.hip", "blend.hip", "decode.hip", "decode_mfma.hip", "decode_fwd.hip", "decode_bwd.hip", "loss.hip", "serve.hip", "residual.hip", "feature.hip", "anchor.hip", "mapping.hip", "uncertainty.hip", "colgemm.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "blend.hip", "decode.hip", "decode_fwd.hip", "decode_bwd.hip", "loss.hip", "serve.hip", "residual.hip", "feature.hip", "anchor.hip", "mapping.hip", "uncertainty.hip", "colgemm.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -9,14 +9,15 @@
 // (ReLU for the first four, SoftPlus for the feature head), then the output
 // activations: sigmoid (opacity, rgb), l_s * sigmoid (scale), raw (rot, feat).
 //
-// FP32 path: forward and backward run on the matrix cores with FP32
-// 16x16x4 MFMAs, one 16-anchor tile at a time (forward: decode_fwd.hip,
-// backward: decode_bwd.hip). The BF16 path runs the forward on the matrix
-// cores in BF16 (decode_mfma.hip). The backward recomputes the forward, forms
-// dL/dH from the second-layer weights, dL/dZ through the activations, dL/dX
-// from the first layer and from it the anchor gradients, and the weight
-// gradients as per-workgroup sums reduced here in a fixed order
-// (deterministic, no atomics). This file holds the reductions around them.
+// Forward and backward run on the matrix cores with FP32 16x16x4 MFMAs, one
+// 16-anchor tile at a time (forward: decode_fwd.hip, backward:
+// decode_bwd.hip); the BF16 variant of the forward rounds the operands of
+// the feature columns and of the second layer to bfloat16. The backward
+// recomputes the forward, forms dL/dH from the second-layer weights, dL/dZ
+// through the activations, dL/dX from the first layer and from it the anchor
+// gradients, and the weight gradients as per-workgroup sums reduced here in
+// a fixed order (deterministic, no atomics). This file holds the reductions
+// around them.
 #include <math.h>
 
 #include "decode_shared.h"
@@ -186,11 +187,7 @@ void launch_decode(const DecodeConst& dc, const float* xyz, const float* feat, c
                    const float* params, const ViewDev* host_views, const asgs_gaussians& out, hipStream_t s) {
   const HeadTable ht = head_table(dc);
   const DecodeViews dv = decode_views(host_views, dc.n_views);
-  if (dc.precision == 1) {
-    launch_decode_mfma(dc, ht, dv, xyz, feat, off, params, out, s);
-    return;
-  }
-  launch_dec_fwd(dc, ht, dv, xyz, feat, off, params, out, s);
+  launch_dec_fwd(dc, ht, dv, xyz, feat, off, params, out, s);  // FP32 or BF16 by dc.precision
 }
 
 void launch_decode_backward(const DecodeConst& dc, const float* xyz, const float* feat, const float* off,

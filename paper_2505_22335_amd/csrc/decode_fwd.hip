@@ -1,4 +1,5 @@
-// Decoder forward on the matrix cores (UP-SLAM Eq. 8 and Eq. 9). One
+// Decoder forward on the matrix cores (UP-SLAM Eq. 8 and Eq. 9), FP32 or
+// BF16. One
 // workgroup of eight waves takes (16-anchor tile, view) items in turn: waves
 // 0..3 each own one of the opacity, colour, scale and rotation heads, waves
 // 4..7 share the feature head's output rows. Per item and head, with X the
@@ -46,7 +47,27 @@ static_assert(FwdLds<3>::kFloats * 4 <= 80 * 1024, "two workgroups per compute u
 
 ASGS_DEV f4v mfma(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-template <int kR>
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// bfloat16 bits of a finite float, rounded to nearest even
+ASGS_DEV unsigned f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+// eight floats as the bfloat16 operand of v_mfma_f32_16x16x32_bf16 (element j = K index 8 g + j)
+ASGS_DEV bf8v pack_bf8(const float (&v)[8]) {
+  u4v p;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) p[i] = f2bf(v[2 * i]) | (f2bf(v[2 * i + 1]) << 16);
+  return __builtin_bit_cast(bf8v, p);
+}
+
+// kBf: the BF16 decoder (operands of the feature columns of the first layer
+// and of the second layer rounded to bfloat16, FP32 accumulation; the
+// direction and distance columns, biases and activations in FP32)
+template <int kR, bool kBf>
 __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))) k_dec_fwd(DecodeConst dc, HeadTable ht, DecodeViews dv,
                                                     const float* __restrict__ xyz, const float* __restrict__ feat,
                                                     const float* __restrict__ off, const float* __restrict__ params,
@@ -60,6 +81,13 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
   float (*const HF)[kHB] = reinterpret_cast<float (*)[kHB]>(smem + kOffHF);
   float* const OB = smem + kOffOB;
   float* const TW = smem + kOffTW;
+  // BF16: the feature columns 8 g .. 8 g + 7 of anchor f as the B operand of Z^T
+  auto xbf = [&](int buf) {
+    const f4v a = *reinterpret_cast<const f4v*>(&XB[buf][fl][8 * fg]);
+    const f4v b = *reinterpret_cast<const f4v*>(&XB[buf][fl][8 * fg + 4]);
+    const float v8[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    return pack_bf8(v8);
+  };
   constexpr int kOB = FwdLds<kR>::kOB;
   const int A = (int)dc.A;
   const int k = dc.k;
@@ -155,6 +183,12 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
   // feature waves 0 and 1 form one unit block each
   float w1a[2][9], b1r[2][4];
   float w2y[kR][2][4], b2r[kR];
+  // BF16: the feature columns as bfloat16 A operands (unit 16 b + f, inputs
+  // 8 g .. 8 g + 7), the other four columns as FP32 (input 32 + g), and the
+  // second layer as bfloat16 B operands with K index 8 g + j taken as unit
+  // 4 g + j (j < 4) or 16 + 4 g + j - 4, the units the lane holds of H
+  bf8v w1b[2], w2b[kR];
+  float w1x[2];
   const int pb0 = hd == 0 ? 0 : hd == 1 ? 1 : hd == 2 ? 4 : hd == 3 ? 7 : 11;  // first plane of the head
   const int hr0 = ht.row0[hd];
   const int minv = (65536 + m - 1) / (m > 0 ? m : 1);  // o / m = (o * minv) >> 16, exact for o <= 256
@@ -164,8 +198,17 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int ub = wv < 4 ? 0 : (q & 1) * 16;  // unit offset of block 0
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
+      const float* wrow = &W1L[(hd * kHid + ub + 16 * b + fl) * kWL];
+      if constexpr (kBf) {
+        float v8[8];
 #pragma unroll
-      for (int s = 0; s < 9; ++s) w1a[b][s] = W1L[(hd * kHid + ub + 16 * b + fl) * kWL + 4 * s + fg];
+        for (int jj = 0; jj < 8; ++jj) v8[jj] = wrow[8 * fg + jj];
+        w1b[b] = pack_bf8(v8);
+        w1x[b] = wrow[32 + fg];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 9; ++s) w1a[b][s] = wrow[4 * s + fg];
+      }
       const f4v v = *reinterpret_cast<const f4v*>(&B1L[hd * kHid + (ub + 16 * b + 4 * fg) % kHid]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) b1r[b][r] = v[r];
@@ -183,6 +226,12 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
       const f4v v = *reinterpret_cast<const f4v*>(&W2L[(hr0 + oc) * kWL + 16 * b + 4 * fg]);
 #pragma unroll
       for (int r = 0; r < 4; ++r) w2y[i][b][r] = ok ? v[r] : 0.f;
+    }
+    if constexpr (kBf) {
+      float v8[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) v8[jj] = w2y[i][jj >> 2][jj & 3];
+      w2b[i] = pack_bf8(v8);
     }
     b2r[i] = ok ? B2L[hr0 + oc] : 0.f;
     const int gi = (oc * minv) >> 16, gc = oc - gi * m;
@@ -262,11 +311,18 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
     if (wv < 4) {
       // Z^T (units x anchors) = W1 X^T, K = inputs
       f4v z0 = {0.f, 0.f, 0.f, 0.f}, z1 = z0;
+      if constexpr (kBf) {
+        const bf8v xb = xbf(buf);
+        const float xr = XB[buf][fl][32 + fg];
+        z0 = mfma(w1x[0], xr, __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1b[0], xb, z0, 0, 0, 0));
+        z1 = mfma(w1x[1], xr, __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1b[1], xb, z1, 0, 0, 0));
+      } else {
 #pragma unroll
-      for (int s = 0; s < 9; ++s) {
-        const float xb = XB[buf][fl][4 * s + fg];
-        z0 = mfma(w1a[0][s], xb, z0);
-        z1 = mfma(w1a[1][s], xb, z1);
+        for (int s = 0; s < 9; ++s) {
+          const float xb = XB[buf][fl][4 * s + fg];
+          z0 = mfma(w1a[0][s], xb, z0);
+          z1 = mfma(w1a[1][s], xb, z1);
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -276,8 +332,12 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
     } else if (has_feat && q < 2) {
       // the feature head's hidden layer once: unit block q on feature wave q
       f4v z = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (kBf) {
+        z = mfma(w1x[0], XB[buf][fl][32 + fg], __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1b[0], xbf(buf), z, 0, 0, 0));
+      } else {
 #pragma unroll
-      for (int s = 0; s < 9; ++s) z = mfma(w1a[0][s], XB[buf][fl][4 * s + fg], z);
+        for (int s = 0; s < 9; ++s) z = mfma(w1a[0][s], XB[buf][fl][4 * s + fg], z);
+      }
       f4v hq;
 #pragma unroll
       for (int r = 0; r < 4; ++r) hq[r] = fsoftplus(z[r] + bv[0][r]);
@@ -289,16 +349,27 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
       for (int b = 0; b < 2; ++b) h[b] = *reinterpret_cast<const f4v*>(&HF[fl][16 * b + 4 * fg]);
     }
     float* const ob = OB + buf * kOB;
+    bf8v hb;  // BF16: H as the A operand of the second layer
+    if constexpr (kBf) {
+      float v8[8];
+#pragma unroll
+      for (int jj = 0; jj < 8; ++jj) v8[jj] = h[jj >> 2][jj & 3];
+      hb = pack_bf8(v8);
+    }
     if (active) {
 #pragma unroll
       for (int i = 0; i < kR; ++i) {
         if (i >= nt) break;
         // Y (anchors x rows) = H W2^T, K = units; lane (f, g) holds Y[anchor 4 g + r][row 16 i + f]
         f4v y = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (kBf) {
+          y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hb, w2b[i], y, 0, 0, 0);
+        } else {
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < 2; ++b)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) y = mfma(h[b][r], w2y[i][b][r], y);
+            for (int r = 0; r < 4; ++r) y = mfma(h[b][r], w2y[i][b][r], y);
+        }
         if (rok[i]) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) ob[ooff[i] + (4 * fg + r) * k] = fout_act(hd, y[r] + b2r[i], dc.l_s);
@@ -342,19 +413,19 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
   }
 }
 
-template <int kR>
+template <int kR, bool kBf>
 void launch_k(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz, const float* feat,
               const float* off, const float* params, const asgs_gaussians& out, hipStream_t s) {
   static bool attr_set = false;  // more than 64 KiB of dynamic LDS
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_dec_fwd<kR>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_dec_fwd<kR, kBf>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, FwdLds<kR>::kFloats * (int)sizeof(float));
     attr_set = true;
   }
   // two workgroups per compute unit
   const int64_t tiles = (dc.A + 15) / 16;
   const unsigned nblk = (unsigned)(tiles < 512 ? tiles : 512);
-  hipLaunchKernelGGL(k_dec_fwd<kR>, dim3(nblk), dim3(kBT), FwdLds<kR>::kFloats * sizeof(float), s, dc, ht, dv, xyz,
+  hipLaunchKernelGGL((k_dec_fwd<kR, kBf>), dim3(nblk), dim3(kBT), FwdLds<kR>::kFloats * sizeof(float), s, dc, ht, dv, xyz,
                      feat, off, params, out);
 }
 
@@ -365,10 +436,14 @@ void launch_dec_fwd(const DecodeConst& dc, const HeadTable& ht, const DecodeView
                     hipStream_t s) {
   // second-layer row tiles per wave: the rotation head has ceil(4 k / 16),
   // each feature wave ceil(k / 4)
-  if (dc.k <= 12)
-    launch_k<3>(dc, ht, dv, xyz, feat, off, params, out, s);
-  else
-    launch_k<4>(dc, ht, dv, xyz, feat, off, params, out, s);
+  const bool bf = dc.precision == 1;
+  if (dc.k <= 12) {
+    if (bf) launch_k<3, true>(dc, ht, dv, xyz, feat, off, params, out, s);
+    else launch_k<3, false>(dc, ht, dv, xyz, feat, off, params, out, s);
+  } else {
+    if (bf) launch_k<4, true>(dc, ht, dv, xyz, feat, off, params, out, s);
+    else launch_k<4, false>(dc, ht, dv, xyz, feat, off, params, out, s);
+  }
 }
 
 }  // namespace asgs

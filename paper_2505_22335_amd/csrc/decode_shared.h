@@ -116,8 +116,6 @@ void launch_dec_bwd(const DecodeConst& dc, const HeadTable& ht, const DecodeView
                     float* d_xyz, float* d_feat, bool want_params, hipStream_t s);
 
 
-void launch_decode_mfma(const DecodeConst& dc, const HeadTable& ht, const DecodeViews& dv, const float* xyz,
-                        const float* feat, const float* off, const float* params, const asgs_gaussians& out,
-                        hipStream_t s);
+
 
 }  // namespace asgs

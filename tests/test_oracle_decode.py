@@ -242,3 +242,35 @@ def test_bf16_hidden_margin_hand_cases():
     w["opacity"]["b1"][0] = 2.0 ** -8
     mg = bf16_hidden_margin(xyz, feat, w, torch.zeros(3, dtype=F64))
     assert mg["opacity"][1] == 0.0 and mg["opacity"][2] == 2.0 ** -8
+
+
+def test_bf16_flip_bound_hand_case():
+    """A hidden unit on a bfloat16 rounding midpoint (z = 1 + 2^-8 with the
+    feature 1 and b1 = 2^-8) may round to 1 or to 1 + 2^-7: the second layer
+    (W2 = 1/2 on that unit, bf16 exact) then moves the pre-activation by
+    2^-8, which the raw rotation head passes on and the sigmoid heads
+    scale by at most 1/4 (the scale head by l_s / 4). Units off the band
+    (z = 2^-8, margin 2^-8 relative to |b1|) contribute nothing. Both
+    roundings are formed explicitly and their difference equals the bound."""
+    from oracle import bf16_flip_bound
+    xyz = torch.tensor([[0.0, 0.0, 2.0], [0.0, 0.0, 3.0]], dtype=F64)
+    feat = torch.zeros((2, 32), dtype=F64)
+    feat[:, 0] = torch.tensor([1.0, 0.0])
+    k, l_s = 1, 0.02
+    w = {}
+    for name, m, _ in HEAD_ORDER[:4]:
+        W1 = torch.zeros((32, 35), dtype=F64)
+        W1[0, 0] = 1.0
+        b1 = torch.zeros(32, dtype=F64)
+        b1[0] = 2.0 ** -8
+        W2 = torch.zeros((m, 32), dtype=F64)
+        W2[:, 0] = 0.5
+        w[name] = dict(W1=W1, b1=b1, W2=W2, b2=torch.zeros(m, dtype=F64))
+    fb = bf16_flip_bound(xyz, feat, w, torch.zeros(3, dtype=F64), k, l_s=l_s)
+    dy = 0.5 * ((1.0 + 2.0 ** -7) - 1.0)  # the two roundings of H through W2
+    assert np.all(fb["rot"][0] == dy) and np.all(fb["rot"][1] == 0.0)
+    assert np.all(fb["rgb"][0] == 0.25 * dy) and fb["opacity"][0, 0] == 0.25 * dy
+    assert np.all(fb["scale"][0] == 0.25 * l_s * dy)
+    # the sigmoid's largest slope bounds the change of the decoded value
+    s = lambda y: 1.0 / (1.0 + np.exp(-y))
+    assert abs(s(0.5 * (1.0 + 2.0 ** -7)) - s(0.5)) <= fb["opacity"][0, 0]
