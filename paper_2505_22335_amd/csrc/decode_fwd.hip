@@ -381,14 +381,6 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
     // ---- the tile's contiguous runs of every plane: wave w takes planes
     // w, w + 8, w + 16, w + 24 ----
     const int g0 = a0 * k;
-    float ov[4][kR];  // every read before the first store
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int c = 0; c < kR; ++c) {
-        const int p = wv + 8 * i, idx = lane + 64 * c;
-        ov[i][c] = ob[(p < nplanes ? p : 0) * gstride + (idx < run ? idx : 0)];
-      }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int p = wv + 8 * i;
@@ -399,7 +391,7 @@ __global__ void __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
       for (int c = 0; c < kR; ++c) {
         const int idx = lane + 64 * c;
-        if (idx < run && g0 + idx < n) dst[idx] = ov[i][c];
+        if (idx < run && g0 + idx < n) dst[idx] = ob[p * gstride + idx];
       }
     }
     if (view == 0) {
