@@ -467,19 +467,17 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       const float dq = L.floored ? 0.f : -0.5f * gp * L.cos / L.q;
       const int pr = wv * 16 + n;  // pixel of the round
       if (g == 0 && L.valid) a.dqpix[(int64_t)view * HW + L.p] = dq;
-      __builtin_amdgcn_sched_barrier(0);
-      // dL/dz at the lane's units into the table; dL/dx summed over the pixel's four lanes
-      float dxp[kFIn];
+      if (g == 0) {
 #pragma unroll
-      for (int c = 0; c < kFIn; ++c) dxp[c] = 0.f;
+        for (int c = 0; c < kFIn; ++c) S.X[c][pr] = L.x[c];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      // dL/dz at the lane's units into the table (dL/dx follows on the matrix cores)
 #pragma unroll
       for (int u = 0; u < 32; ++u) {
         const int k = 32 * g + u;
         const float dh = fmaf(al, corner_sum(S.F, L, k), 2.f * dq * (L.mh[u] + S.F.m[hpos(k)]));
         const float dz = L.h[u] > 0.f ? dh : 0.f;
-        const float* w = &S.F.w1[hpos(k) * kFIn];
-#pragma unroll
-        for (int c = 0; c < kFIn; ++c) dxp[c] = fmaf(w[c], dz, dxp[c]);
         uint16_t hi, lo;
         bf_split(dz, hi, lo);
         S.Ghi[rp_index(k, pr)] = hi;
@@ -489,16 +487,35 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
         S.Hlo[rp_index(k, pr)] = lo;
         if ((u & 7) == 7) __builtin_amdgcn_sched_barrier(0);
       }
+      // dL/dx (channels x the wave's 16 pixels) = W1^T dL/dz, K = hidden units:
+      // A = W1^T split on the fly (channel n, units 32 kb + 8 g .. + 7), B =
+      // the dL/dz table (the same units, pixel n of the wave); lane (n, g)
+      // receives channels 4 g + j of its own pixel
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      {
+        f4v dxa = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int c = 0; c < kFIn; ++c) dxp[c] = col_sum(dxp[c]);
-      if (g == 0 && L.valid) {
-        float* dfx = a.dfeat + (int64_t)view * kFIn * HW + L.p;
+        for (int kb = 0; kb < 4; ++kb) {
+          uint16_t wh[8], wl[8], zh[8], zl[8];
 #pragma unroll
-        for (int c = 0; c < kFIn; ++c) dfx[c * HW] = dxp[c];
-      }
-      if (g == 0) {
+          for (int i = 0; i < 8; ++i) {
+            const int k = 32 * kb + 8 * g + i;
+            bf_split(S.F.w1[hpos(k) * kFIn + n], wh[i], wl[i]);
+            zh[i] = S.Ghi[rp_index(k, wv * 16 + n)];
+            zl[i] = S.Glo[rp_index(k, wv * 16 + n)];
+          }
+          const bf8v ah = as_bf8(wh), alo = as_bf8(wl), bh = as_bf8(zh), bl = as_bf8(zl);
+          dxa = mfma_bf(ah, bh, dxa);
+          dxa = mfma_bf(ah, bl, dxa);
+          dxa = mfma_bf(alo, bh, dxa);
+        }
+        if (L.valid) {
+          float* dfx = a.dfeat + (int64_t)view * kFIn * HW + L.p;
 #pragma unroll
-        for (int c = 0; c < kFIn; ++c) S.X[c][pr] = L.x[c];
+          for (int j = 0; j < 4; ++j) dfx[(4 * g + j) * HW] = dxa[j];
+        }
       }
       if (g == 1) {
         float wc[kSlots];
