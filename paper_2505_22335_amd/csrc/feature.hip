@@ -117,7 +117,6 @@ struct LanePix {
   int64_t p;           // pixel index in the view
   float x[kFIn];
   float h[32];         // hidden units 32 g + u of the lane's group g
-  float mh[32];        // (M h) at the same units
   float cw[4];         // corner weights
   int cs[4];           // corner slots in the tile's patch table
   float q, a, nF, den, cos;
@@ -158,13 +157,6 @@ ASGS_DEV void stage_cells(const FeatArgs& a, FeatShared& S, int view, const Tile
   }
 }
 
-ASGS_DEV float corner_sum(const FeatShared& S, const LanePix& L, int k) {
-  float r = 0.f;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) r = fmaf(L.cw[c], S.cell[L.cs[c]][k], r);
-  return r;
-}
-
 // G_c . G_c' of two patches of the tile (at most one row and one column
 // apart): the record of the upper-left patch of the pair holds it (self,
 // right, lower, lower-right, or right-with-lower for the anti-diagonal).
@@ -190,14 +182,18 @@ ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCel
   for (int c = 0; c < kFIn; ++c) L.x[c] = L.valid ? fx[c * HW] : 0.f;
   // hidden units 32 g + u, u = 8 kb + i: B operands of M h (K = hidden)
   bf8v bh[4], bl[4];
+  // unit 32 g + u sits at hpos = 4 u + g: per-lane bases with constant offsets
+  const float* const w1g = S.w1 + g * kFIn;
+  const float* const b1g = S.b1 + g;
+  const float* const mg = S.m + g;
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
     uint16_t hi[8], lo[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int u = 8 * kb + i, k = 32 * g + u;
-      const float* w = &S.w1[hpos(k) * kFIn];
-      float z = S.b1[hpos(k)];
+      const int u = 8 * kb + i;
+      const float* w = w1g + 4 * u * kFIn;
+      float z = b1g[4 * u];
 #pragma unroll
       for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], L.x[c], z);
       L.h[u] = fmaxf(z, 0.f);
@@ -208,8 +204,10 @@ ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCel
     bl[kb] = as_bf8(lo);
   }
   __builtin_amdgcn_sched_barrier(0);
-  // M h: row block mb holds units 32 g' + 4 mb + j for lane group g'
+  // M h: row block mb holds units 32 g' + 4 mb + j for lane group g', used
+  // at once for h^T (M h + 2 m)
   const uint16_t* fr = S.frag + lane * 8;
+  float qp = 0.f, ap = 0.f;
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
     f4v d = {0.f, 0.f, 0.f, 0.f};
@@ -222,7 +220,10 @@ ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCel
       d = mfma_bf(al, bh[kb], d);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) L.mh[4 * mb + j] = d[j];
+    for (int j = 0; j < 4; ++j) {
+      const int u = 4 * mb + j;
+      qp = fmaf(L.h[u], d[j] + 2.f * mg[4 * u], qp);
+    }
     // keep the fragment loads of one row block together (hoisting all 64 of
     // them would take every register)
     __builtin_amdgcn_sched_barrier(0);
@@ -239,12 +240,18 @@ ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCel
   L.cw[3] = wy * wx;
 #pragma unroll
   for (int c = 0; c < 4; ++c) L.cs[c] = (ys[c] - tc.cy0) * tc.ncx + (xs[c] - tc.cx0);
-  float qp = 0.f, ap = 0.f;
+  {
+    const float* cb[4];
 #pragma unroll
-  for (int u = 0; u < 32; ++u) {
-    const int k = 32 * g + u;
-    qp = fmaf(L.h[u], L.mh[u] + 2.f * S.m[hpos(k)], qp);
-    ap = fmaf(corner_sum(S, L, k), L.h[u], ap);
+    for (int c = 0; c < 4; ++c) cb[c] = &S.cell[L.cs[c]][32 * g];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      float cs = 0.f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cs = fmaf(L.cw[c], cb[c][u], cs);
+      ap = fmaf(cs, L.h[u], ap);
+      if ((u & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four units' corner reads at a time
+    }
   }
   L.q = fmaxf(col_sum(qp) + a.mvec[kFHid], 0.f);
   float beta = 0.f, nF = 0.f;
@@ -459,33 +466,144 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
     for (int round = 0; round < kFT / kBwdWaves; ++round) {
       __syncthreads();  // patches staged; the previous round's tables are no longer read
       const int row = round * kBwdWaves + wv;
-      LanePix L;
-      lane_forward(a, S.F, tc, view, tx * kFT + n, ty * kFT + row, L);
-      const float gp = L.valid ? a.dcos[(int64_t)view * HW + L.p] : 0.f;
-      const float s1 = 1.f / L.den;
-      const float al = gp * s1;
-      const float dq = L.floored ? 0.f : -0.5f * gp * L.cos / L.q;
+      // The forward of the lane's pixel and its 32 hidden units again (as in
+      // lane_forward), then dL/dz. M h is formed twice, block by block, so
+      // that no lane holds it for all its units: once for |F^|^2, once for
+      // dL/dh (after the cosine's scalars are known).
+      const int px = tx * kFT + n, py = ty * kFT + row;
+      const bool valid = px < a.W && py < a.H;
+      const int cpx = min(px, a.W - 1), cpy = min(py, a.H - 1);
+      const int64_t p = (int64_t)cpy * a.W + cpx;
       const int pr = wv * 16 + n;  // pixel of the round
-      if (g == 0 && L.valid) a.dqpix[(int64_t)view * HW + L.p] = dq;
-      if (g == 0) {
+      // unit 32 g + u sits at hpos = 4 u + g: per-lane bases with constant offsets
+      const float* const w1g = S.F.w1 + g * kFIn;
+      const float* const b1g = S.F.b1 + g;
+      const float* const mg = S.F.m + g;
+      float h[32];
+      bf8v bh[4], bl[4];
+      {
+        float x[kFIn];
+        const float* fx = a.feat + (int64_t)view * kFIn * HW + p;
 #pragma unroll
-        for (int c = 0; c < kFIn; ++c) S.X[c][pr] = L.x[c];
+        for (int c = 0; c < kFIn; ++c) x[c] = valid ? fx[c * HW] : 0.f;
+        if (g == 0) {
+#pragma unroll
+          for (int c = 0; c < kFIn; ++c) S.X[c][pr] = x[c];
+        }
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          uint16_t hi[8], lo[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int u = 8 * kb + i, k = 32 * g + u;
+            const float* w = w1g + 4 * u * kFIn;
+            float z = b1g[4 * u];
+#pragma unroll
+            for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], x[c], z);
+            h[u] = fmaxf(z, 0.f);
+            bf_split(h[u], hi[i], lo[i]);
+            S.Hhi[rp_index(k, pr)] = hi[i];
+            S.Hlo[rp_index(k, pr)] = lo[i];
+            if (i & 1) __builtin_amdgcn_sched_barrier(0);
+          }
+          bh[kb] = as_bf8(hi);
+          bl[kb] = as_bf8(lo);
+        }
       }
+      __builtin_amdgcn_sched_barrier(0);
+      // bilinear corners of the pixel in the tile's patch table
+      LanePix L;  // corners only
+      int ys[4], xs[4];
+      {
+        int y0, y1, x0, x1;
+        float wy, wx;
+        bilin(cpy, a.Hp, a.sy, y0, y1, wy);
+        bilin(cpx, a.Wp, a.sx, x0, x1, wx);
+        ys[0] = ys[1] = y0;
+        ys[2] = ys[3] = y1;
+        xs[0] = xs[2] = x0;
+        xs[1] = xs[3] = x1;
+        L.cw[0] = (1.f - wy) * (1.f - wx);
+        L.cw[1] = (1.f - wy) * wx;
+        L.cw[2] = wy * (1.f - wx);
+        L.cw[3] = wy * wx;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) L.cs[c] = (ys[c] - tc.cy0) * tc.ncx + (xs[c] - tc.cx0);
+      }
+      const uint16_t* fr = S.F.frag + lane * 8;
+      // row block mb of M h: units 32 g + 4 mb + j of the lane's pixel
+      auto mh_block = [&](int mb) {
+        f4v d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+          const bf8v ah = *reinterpret_cast<const bf8v*>(fr + ((mb * 4 + kb) * 2 + 0) * 512);
+          const bf8v alo = *reinterpret_cast<const bf8v*>(fr + ((mb * 4 + kb) * 2 + 1) * 512);
+          d = mfma_bf(ah, bh[kb], d);
+          d = mfma_bf(ah, bl[kb], d);
+          d = mfma_bf(alo, bh[kb], d);
+        }
+        return d;
+      };
+      float qp = 0.f, ap = 0.f;
+#pragma unroll
+      for (int mb = 0; mb < 8; ++mb) {
+        const f4v d = mh_block(mb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = 4 * mb + j;
+          qp = fmaf(h[u], d[j] + 2.f * mg[4 * u], qp);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      const float* cb[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cb[c] = &S.F.cell[L.cs[c]][32 * g];
+      auto csum = [&](int u) {
+        float r = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) r = fmaf(L.cw[c], cb[c][u], r);
+        return r;
+      };
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        ap = fmaf(csum(u), h[u], ap);
+        if ((u & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // four units' corner reads at a time
+      }
+      const float q = fmaxf(col_sum(qp) + a.mvec[kFHid], 0.f);
+      float beta = 0.f, nF = 0.f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        beta = fmaf(L.cw[c], S.F.cell[L.cs[c]][128], beta);
+        nF = fmaf(L.cw[c] * L.cw[c], patch_dot(S.F, tc, ys[c], xs[c], ys[c], xs[c]), nF);
+#pragma unroll
+        for (int e = c + 1; e < 4; ++e)
+          nF = fmaf(2.f * L.cw[c] * L.cw[e], patch_dot(S.F, tc, ys[c], xs[c], ys[e], xs[e]), nF);
+      }
+      const float av = col_sum(ap) + beta;
+      const float den0 = sqrtf(fmaxf(nF, 0.f)) * sqrtf(q);
+      const bool floored = !(den0 >= 1e-12f);
+      const float den = floored ? 1e-12f : den0;
+      const float cosv = av / den;
+      const float gp = valid ? a.dcos[(int64_t)view * HW + p] : 0.f;
+      const float al = gp / den;
+      const float dq = floored ? 0.f : -0.5f * gp * cosv / q;
+      if (g == 0 && valid) a.dqpix[(int64_t)view * HW + p] = dq;
       __builtin_amdgcn_sched_barrier(0);
       // dL/dz at the lane's units into the table (dL/dx follows on the matrix cores)
 #pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const int k = 32 * g + u;
-        const float dh = fmaf(al, corner_sum(S.F, L, k), 2.f * dq * (L.mh[u] + S.F.m[hpos(k)]));
-        const float dz = L.h[u] > 0.f ? dh : 0.f;
-        uint16_t hi, lo;
-        bf_split(dz, hi, lo);
-        S.Ghi[rp_index(k, pr)] = hi;
-        S.Glo[rp_index(k, pr)] = lo;
-        bf_split(L.h[u], hi, lo);
-        S.Hhi[rp_index(k, pr)] = hi;
-        S.Hlo[rp_index(k, pr)] = lo;
-        if ((u & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      for (int mb = 0; mb < 8; ++mb) {
+        const f4v d = mh_block(mb);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int u = 4 * mb + j, k = 32 * g + u;
+          const float dh = fmaf(al, csum(u), 2.f * dq * (d[j] + mg[4 * u]));
+          const float dz = h[u] > 0.f ? dh : 0.f;
+          uint16_t hi, lo;
+          bf_split(dz, hi, lo);
+          S.Ghi[rp_index(k, pr)] = hi;
+          S.Glo[rp_index(k, pr)] = lo;
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
       // dL/dx (channels x the wave's 16 pixels) = W1^T dL/dz, K = hidden units:
       // A = W1^T split on the fly (channel n, units 32 kb + 8 g .. + 7), B =
@@ -495,6 +613,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       {
+        const float* const w1n = S.F.w1 + 32 * g * kFIn + n;
         f4v dxa = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
@@ -502,7 +621,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const int k = 32 * kb + 8 * g + i;
-            bf_split(S.F.w1[hpos(k) * kFIn + n], wh[i], wl[i]);
+            bf_split(w1n[(4 * i + kb) * kFIn], wh[i], wl[i]);  // unit k at hpos 4 (8 g + i) + kb
             zh[i] = S.Ghi[rp_index(k, wv * 16 + n)];
             zl[i] = S.Glo[rp_index(k, wv * 16 + n)];
           }
@@ -511,8 +630,8 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
           dxa = mfma_bf(ah, bl, dxa);
           dxa = mfma_bf(alo, bh, dxa);
         }
-        if (L.valid) {
-          float* dfx = a.dfeat + (int64_t)view * kFIn * HW + L.p;
+        if (valid) {
+          float* dfx = a.dfeat + (int64_t)view * kFIn * HW + p;
 #pragma unroll
           for (int j = 0; j < 4; ++j) dfx[(4 * g + j) * HW] = dxa[j];
         }
