@@ -834,26 +834,59 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd_s(FeatArgs a) {
   if (threadIdx.x == 0) part[16384 + 2048 + 256] = (S.red[0][0] + S.red[0][1]) + (S.red[0][2] + S.red[0][3]);
 }
 
-// Sums of the workgroup partials: S, dW1^T, db1, dm, dmu (fixed order).
+// Sums of the workgroup partials: S, dW1^T, db1, dm, dmu (fixed order): 64
+// elements per workgroup, four threads per element (workgroups b = q mod 4,
+// sixteen loads in flight per round, summed in a fixed tree), combined in LDS.
 __global__ void __launch_bounds__(256) k_feat_reduce(const float* __restrict__ part, int nwg, float* out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kPart) return;
-  float s = 0.f;
-  for (int b = 0; b < nwg; ++b) s += part[(int64_t)b * kPartStride + e];
-  out[e] = s;
+  __shared__ float red[4][64];
+  const int el = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
+  float acc = 0.f;
+  if (e < kPart) {
+    for (int b0 = q; b0 < nwg; b0 += 64) {
+      float v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int b = b0 + 4 * i;
+        v[i] = b < nwg ? part[(int64_t)b * kPartStride + e] : 0.f;
+      }
+#pragma unroll
+      for (int st = 8; st > 0; st >>= 1)
+#pragma unroll
+        for (int i = 0; i < st; ++i) v[i] += v[i + st];
+      acc += v[0];
+    }
+  }
+  red[q][el] = acc;
+  __syncthreads();
+  if (q == 0 && e < kPart) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
 }
 
 // Per patch: dQ and dbeta summed over the tiles that reach it (fixed order).
 __global__ void __launch_bounds__(kDQ) k_feat_cell_reduce(FeatArgs a, float* dqc) {
   const int cell = blockIdx.x, view = blockIdx.y, k = threadIdx.x;
   const int cy = cell / a.Wp, cx = cell - cy * a.Wp;
-  float s = 0.f;
+  // the tile rows and the tile columns that reach the patch (a tile's patch
+  // rows depend on its row only, its patch columns on its column only)
+  int ty0 = a.tiles_y, ty1 = -1, tx0 = a.tiles_x, tx1 = -1;
   for (int ty = 0; ty < a.tiles_y; ++ty) {
-    const TileCells ry = tile_cells(a, 0, ty);
-    if (cy < ry.cy0 || cy >= ry.cy0 + ry.ncy) continue;
-    for (int tx = 0; tx < a.tiles_x; ++tx) {
+    const TileCells r = tile_cells(a, 0, ty);
+    if (cy >= r.cy0 && cy < r.cy0 + r.ncy) {
+      ty0 = min(ty0, ty);
+      ty1 = ty;
+    }
+  }
+  for (int tx = 0; tx < a.tiles_x; ++tx) {
+    const TileCells r = tile_cells(a, tx, 0);
+    if (cx >= r.cx0 && cx < r.cx0 + r.ncx) {
+      tx0 = min(tx0, tx);
+      tx1 = tx;
+    }
+  }
+  float s = 0.f;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    for (int tx = tx0; tx <= tx1; ++tx) {
       const TileCells tc = tile_cells(a, tx, ty);
-      if (cx < tc.cx0 || cx >= tc.cx0 + tc.ncx) continue;
       const int64_t t = (int64_t)view * a.tiles + ty * a.tiles_x + tx;
       s += a.dqt[(t * kSlots + (cy - tc.cy0) * tc.ncx + (cx - tc.cx0)) * kDQ + k];
     }
@@ -1030,7 +1063,7 @@ void launch_feature_backward(const FeatCall& c, const FeatLayout& L, char* work,
   hipLaunchKernelGGL(k_feat_bwd, dim3((unsigned)nwg), dim3(64 * kBwdWaves), 0, s, a);
   hipLaunchKernelGGL(k_feat_bwd_s, dim3((unsigned)nwg), dim3(64 * kBwdWaves), 0, s, a);
   float* red = reinterpret_cast<float*>(work + L.red);
-  hipLaunchKernelGGL(k_feat_reduce, dim3((kPart + 255) / 256), dim3(256), 0, s, a.part, nwg, red);
+  hipLaunchKernelGGL(k_feat_reduce, dim3((kPart + 63) / 64), dim3(256), 0, s, a.part, nwg, red);
   float* dqc = reinterpret_cast<float*>(work + L.dqc);
   hipLaunchKernelGGL(k_feat_cell_reduce, dim3((unsigned)(a.Hp * a.Wp), (unsigned)a.V), dim3(kDQ), 0, s, a, dqc);
   ColGemm g = dq_gemm(a, dqc);

@@ -229,13 +229,27 @@ __global__ void __launch_bounds__(256) k_fu_pix(UncArgs a) {
 __global__ void __launch_bounds__(kHid) k_fu_cell_reduce(UncArgs a) {
   const int cell = blockIdx.x, v = blockIdx.y, u = threadIdx.x;
   const int cy = cell / a.Wp, cx = cell - cy * a.Wp;
-  float s = 0.f;
+  // the tile rows and the tile columns that reach the patch (a tile's patch
+  // rows depend on its row only, its patch columns on its column only)
+  int ty0 = a.tiles_y, ty1 = -1, tx0 = a.tiles_x, tx1 = -1;
   for (int ty = 0; ty < a.tiles_y; ++ty) {
-    const TileCells ry = tile_cells(a, 0, ty);
-    if (cy < ry.cy0 || cy >= ry.cy0 + ry.ncy) continue;
-    for (int tx = 0; tx < a.tiles_x; ++tx) {
+    const TileCells r = tile_cells(a, 0, ty);
+    if (cy >= r.cy0 && cy < r.cy0 + r.ncy) {
+      ty0 = min(ty0, ty);
+      ty1 = ty;
+    }
+  }
+  for (int tx = 0; tx < a.tiles_x; ++tx) {
+    const TileCells r = tile_cells(a, tx, 0);
+    if (cx >= r.cx0 && cx < r.cx0 + r.ncx) {
+      tx0 = min(tx0, tx);
+      tx1 = tx;
+    }
+  }
+  float s = 0.f;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    for (int tx = tx0; tx <= tx1; ++tx) {
       const TileCells tc = tile_cells(a, tx, ty);
-      if (cx < tc.cx0 || cx >= tc.cx0 + tc.ncx) continue;
       const int64_t tile = (int64_t)v * a.tiles + ty * a.tiles_x + tx;
       s += a.dzt[(tile * kSlots + (cy - tc.cy0) * tc.ncx + (cx - tc.cx0)) * kHid + u];
     }
