@@ -766,11 +766,14 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd_s(FeatArgs a) {
       for (int c = 0; c < kFIn; ++c) x[c] = valid ? fx[c * HW] : 0.f;
       if (g == 0) admu += dq;
       const int pr = wv * 16 + n;
+      // unit 32 g + u sits at hpos = 4 u + g: per-lane bases with constant offsets
+      const float* const w1g = S.w1 + g * kFIn;
+      const float* const b1g = S.b1 + g;
 #pragma unroll
       for (int u = 0; u < 32; ++u) {
         const int k = 32 * g + u;
-        const float* w = &S.w1[hpos(k) * kFIn];
-        float z = S.b1[hpos(k)];
+        const float* w = w1g + 4 * u * kFIn;
+        float z = b1g[4 * u];
 #pragma unroll
         for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], x[c], z);
         const float h = fmaxf(z, 0.f);
