@@ -705,136 +705,211 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
   }
 }
 
-// Backward, second pass: S = sum_p dq h h^T (symmetric: the 36 blocks on and
-// above the diagonal of 16 x 16, nine per wave), dm = 2 sum_p dq h and
-// dmu = sum_p dq, from the first layer recomputed per pixel and dq of the
-// first pass. The partial holds T with T + T^T = S + S^T: off-diagonal
-// blocks doubled, diagonal blocks once, blocks below the diagonal zero.
-ASGS_DEV void sblock(int q, int& bi, int& bj) {
-  // q-th block (bi <= bj) of the upper triangle of an 8 x 8 block grid
-  bi = 0;
-  int left = q;
-  while (left >= 8 - bi) {
-    left -= 8 - bi;
-    ++bi;
-  }
-  bj = bi + left;
-}
+// Backward, second pass: S = sum_p dq h h^T, dm = 2 sum_p dq h, dmu = sum_p dq,
+// from dq of the first pass. Each wave takes 32 pixels of one view at a time
+// and keeps all of S in registers. h^T (pixels x units) comes from the matrix
+// cores: A = the 16 features of a pixel as [high | low] bfloat16 parts (K 32),
+// B = W1^T high parts over both halves, then W1^T low parts over the high
+// half, the bias in the accumulator (products good to ~2^-16 relative, FP32
+// sums). A lane then holds eight pixels of one unit, which is its operand in
+// S = (dq h) h^T with K = the 32 pixels (rows: units of dq h, columns: units
+// of h), so h never goes through LDS. S is symmetric: the 36 blocks of 16 x 16
+// on and above the diagonal are formed; the partial holds T with
+// T + T^T = S + S^T (off-diagonal blocks doubled, diagonal blocks once, blocks
+// below the diagonal zero). The four waves' sums are added in a fixed order.
+constexpr int kSPix = 32;  // pixels per wave step
+constexpr int kSBlk = 36;  // blocks of S on and above the diagonal
 
 struct SShared {
-  float w1[kFHid * kFIn];
-  float b1[kFHid];
-  uint16_t Hhi[kFHid * kRP], Hlo[kFHid * kRP];  // h
-  uint16_t Ghi[kFHid * kRP], Glo[kFHid * kRP];  // dq h
-  float red[kBwdWaves][kFHid];
+  uint4 wfrag[8][2][64];                  // first-layer B fragments: unit block, (high, low), lane
+  float red[2][kSBlk * 4 * 64];           // cross-wave sums of S
+  float dm[kBwdWaves][kFHid];
+  float dmu[kBwdWaves];
 };
+
+// the lane's 8 values of the first-layer accumulators as high and low bfloat16
+// operands (element j: pixel 4 g + j of the first 16, then of the second 16)
+ASGS_DEV void split8(const float (&v)[8], bf8v& hi, bf8v& lo) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int j = 0; j < 8; j += 2) {
+    const bf2v h = __builtin_convertvector((f2v{v[j], v[j + 1]}), bf2v);
+    const uint32_t u = __builtin_bit_cast(uint32_t, h);
+    const bf2v l = __builtin_convertvector(
+        (f2v{v[j] - __uint_as_float(u << 16), v[j + 1] - __uint_as_float(u & 0xffff0000u)}), bf2v);
+    hi[j] = h[0];
+    hi[j + 1] = h[1];
+    lo[j] = l[0];
+    lo[j + 1] = l[1];
+  }
+}
+// max(z, 0) on the bits: negative floats (and -0) are negative integers
+ASGS_DEV float relu_bits(float z) { return __int_as_float(max(__float_as_int(z), 0)); }
 
 __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd_s(FeatArgs a) {
   __shared__ __attribute__((aligned(16))) SShared S;
-  for (int q = threadIdx.x; q < kFHid * kFIn; q += blockDim.x) {
-    const int k = q / kFIn, c = q - k * kFIn;
-    S.w1[hpos(k) * kFIn + c] = a.params[q];
-  }
-  for (int k = threadIdx.x; k < kFHid; k += blockDim.x) S.b1[hpos(k)] = a.params[kFHid * kFIn + k];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
-  f4v accS[9], accM[2];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) accS[i] = f4v{0.f, 0.f, 0.f, 0.f};
-  accM[0] = accM[1] = f4v{0.f, 0.f, 0.f, 0.f};
-  float admu = 0.f;
-  bf8v ones;
-  {
+  // B fragment of unit block b for lane (lg, ln): unit 16 b + ln, features
+  // 8 (lg & 1) .. + 7; high parts, or low parts in lane groups 0, 1 and zero in 2, 3
+  for (int e = threadIdx.x; e < 8 * 2 * 64; e += blockDim.x) {
+    const int b = e >> 7, lo = (e >> 6) & 1, l = e & 63, lg = l >> 4, ln = l & 15;
+    const float* w = a.params + (16 * b + ln) * kFIn + 8 * (lg & 1);
     uint16_t o[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) o[e] = n == 0 ? bf_rne(1.f) : (uint16_t)0;
-    ones = as_bf8(o);
+    for (int j = 0; j < 8; ++j) {
+      const uint16_t hi = bf_rne(w[j]);
+      o[j] = lo == 0 ? hi : lg < 2 ? bf_rne(w[j] - bf_val(hi)) : (uint16_t)0;
+    }
+    S.wfrag[b][lo][l] = make_uint4(o[0] | (uint32_t)o[1] << 16, o[2] | (uint32_t)o[3] << 16,
+                                   o[4] | (uint32_t)o[5] << 16, o[6] | (uint32_t)o[7] << 16);
   }
-  const int total = a.tiles * a.V;
-  const int64_t HW = (int64_t)a.W * a.H;
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    const int view = t / a.tiles, lt = t - view * a.tiles;
-    const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
-    for (int round = 0; round < kFT / kBwdWaves; ++round) {
-      __syncthreads();  // weights staged; the previous round's tables are no longer read
-      const int px = tx * kFT + n, py = ty * kFT + round * kBwdWaves + wv;
-      const bool valid = px < a.W && py < a.H;
-      const int64_t p = (int64_t)min(py, a.H - 1) * a.W + min(px, a.W - 1);
-      const float dq = valid ? a.dqpix[(int64_t)view * HW + p] : 0.f;
-      float x[kFIn];
-      const float* fx = a.feat + (int64_t)view * kFIn * HW + p;
+  float b1r[8];
 #pragma unroll
-      for (int c = 0; c < kFIn; ++c) x[c] = valid ? fx[c * HW] : 0.f;
-      if (g == 0) admu += dq;
-      const int pr = wv * 16 + n;
-      // unit 32 g + u sits at hpos = 4 u + g: per-lane bases with constant offsets
-      const float* const w1g = S.w1 + g * kFIn;
-      const float* const b1g = S.b1 + g;
+  for (int b = 0; b < 8; ++b) b1r[b] = a.params[kFHid * kFIn + 16 * b + n];
+  f4v acc[kSBlk];
 #pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const int k = 32 * g + u;
-        const float* w = w1g + 4 * u * kFIn;
-        float z = b1g[4 * u];
+  for (int i = 0; i < kSBlk; ++i) acc[i] = f4v{0.f, 0.f, 0.f, 0.f};
+  float dmacc[8];
 #pragma unroll
-        for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], x[c], z);
-        const float h = fmaxf(z, 0.f);
-        uint16_t hi, lo;
-        bf_split(h, hi, lo);
-        S.Hhi[rp_index(k, pr)] = hi;
-        S.Hlo[rp_index(k, pr)] = lo;
-        bf_split(dq * h, hi, lo);
-        S.Ghi[rp_index(k, pr)] = hi;
-        S.Glo[rp_index(k, pr)] = lo;
-        if ((u & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+  for (int b = 0; b < 8; ++b) dmacc[b] = 0.f;
+  float dmuacc = 0.f;
+  const int HW = a.W * a.H;
+  const int cpv = (HW + kSPix - 1) / kSPix;
+  const int nchunk = a.V * cpv;
+  const int stride = gridDim.x * kBwdWaves;
+  // features and dq of one chunk, loads clamped into the view (the pixels
+  // past its end are masked where they are used: their dq is zero)
+  float xn[2][8], dqn[8];
+  int limn = 0;
+  auto fetch = [&](int cc) {
+    const int v = cc / cpv, base = (cc - v * cpv) * kSPix;
+    const float* fv = a.feat + (int64_t)v * kFIn * HW + (int64_t)(8 * (g & 1)) * HW;
+    const float* dv = a.dqpix + (int64_t)v * HW;
+#pragma unroll
+    for (int P = 0; P < 2; ++P) {
+      const int px = min(base + 16 * P + n, HW - 1);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xn[P][j] = fv[(int64_t)j * HW + px];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dqn[4 * P + r] = dv[min(base + 16 * P + 4 * g + r, HW - 1)];
+    }
+    limn = HW - base;
+  };
+  int c = blockIdx.x * kBwdWaves + wv;
+  if (c < nchunk) fetch(c);
+  for (; c < nchunk; c += stride) {
+    float x[2][8], dq[8];
+#pragma unroll
+    for (int P = 0; P < 2; ++P)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[P][j] = xn[P][j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dq[j] = dqn[j];
+    const int lim = limn;
+    fetch(min(c + stride, nchunk - 1));
+    // A: the pixel's features, high parts in lane groups 0, 1 and low parts in 2, 3
+    bf8v A[2];
+#pragma unroll
+    for (int P = 0; P < 2; ++P) {
+      bf8v hi, lo;
+      split8(x[P], hi, lo);
+      A[P] = g < 2 ? hi : lo;
+    }
+    float sdq = 0.f;
+#pragma unroll
+    for (int P = 0; P < 2; ++P)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        dq[4 * P + r] = 16 * P + 4 * g + r < lim ? dq[4 * P + r] : 0.f;
+        sdq += dq[4 * P + r];
       }
-      __syncthreads();
+    if (n == 0) dmuacc += sdq;
+    bf8v Ghi[8], Glo[8];
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb) {
+    for (int b = 0; b < 8; ++b) {
+      const bf8v whi = __builtin_bit_cast(bf8v, S.wfrag[b][0][lane]);
+      const bf8v wlo = __builtin_bit_cast(bf8v, S.wfrag[b][1][lane]);
+      f4v z0 = f4v{b1r[b], b1r[b], b1r[b], b1r[b]}, z1 = z0;
+      z0 = mfma_bf(A[0], whi, z0);
+      z1 = mfma_bf(A[1], whi, z1);
+      z0 = mfma_bf(A[0], wlo, z0);
+      z1 = mfma_bf(A[1], wlo, z1);
+      float h[8], gh[8];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          int bi, bj;
-          sblock(9 * wv + i, bi, bj);
-          const bf8v gh = tab_frag(S.Ghi, 16 * bi + n, kb, lane), gl = tab_frag(S.Glo, 16 * bi + n, kb, lane);
-          const bf8v hh = tab_frag(S.Hhi, 16 * bj + n, kb, lane), hl = tab_frag(S.Hlo, 16 * bj + n, kb, lane);
-          accS[i] = mfma_bf(gh, hh, accS[i]);
-          accS[i] = mfma_bf(gh, hl, accS[i]);
-          accS[i] = mfma_bf(gl, hh, accS[i]);
-          if (i & 1) __builtin_amdgcn_sched_barrier(0);
-        }
-        // dm over the row blocks 2 wv, 2 wv + 1: (dq h) times a column of ones
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int rb = 2 * wv + i;
-          const bf8v gh = tab_frag(S.Ghi, 16 * rb + n, kb, lane), gl = tab_frag(S.Glo, 16 * rb + n, kb, lane);
-          accM[i] = mfma_bf(gh, ones, accM[i]);
-          accM[i] = mfma_bf(gl, ones, accM[i]);
-        }
+      for (int r = 0; r < 4; ++r) {
+        h[r] = relu_bits(z0[r]);
+        h[4 + r] = relu_bits(z1[r]);
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        gh[j] = dq[j] * h[j];
+        dmacc[b] += gh[j];
+      }
+      bf8v Hhi, Hlo;
+      split8(h, Hhi, Hlo);
+      split8(gh, Ghi[b], Glo[b]);
+      // the blocks of column b: rows bi <= b
+#pragma unroll
+      for (int bi = 0; bi <= b; ++bi) acc[b * (b + 1) / 2 + bi] = mfma_bf(Ghi[bi], Hhi, acc[b * (b + 1) / 2 + bi]);
+#pragma unroll
+      for (int bi = 0; bi <= b; ++bi) acc[b * (b + 1) / 2 + bi] = mfma_bf(Ghi[bi], Hlo, acc[b * (b + 1) / 2 + bi]);
+#pragma unroll
+      for (int bi = 0; bi <= b; ++bi) acc[b * (b + 1) / 2 + bi] = mfma_bf(Glo[bi], Hhi, acc[b * (b + 1) / 2 + bi]);
     }
   }
+  // dm per unit 16 b + n (the four lane groups held different pixels); dmu
+#pragma unroll
+  for (int b = 0; b < 8; ++b) dmacc[b] = col_sum(dmacc[b]);
+  for (int o = 32; o > 0; o >>= 1) dmuacc += __shfl_xor(dmuacc, o);
+  if (g == 0) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) S.dm[wv][16 * b + n] = dmacc[b];
+  }
+  if (lane == 0) S.dmu[wv] = dmuacc;
+  // S over the waves: (w0 + w1) + (w2 + w3)
+  if (wv & 1) {
+#pragma unroll
+    for (int i = 0; i < kSBlk; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) S.red[wv >> 1][(4 * i + j) * 64 + lane] = acc[i][j];
+  }
+  __syncthreads();
+  if (!(wv & 1)) {
+#pragma unroll
+    for (int i = 0; i < kSBlk; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += S.red[wv >> 1][(4 * i + j) * 64 + lane];
+  }
+  __syncthreads();
+  if (wv == 2) {
+#pragma unroll
+    for (int i = 0; i < kSBlk; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) S.red[0][(4 * i + j) * 64 + lane] = acc[i][j];
+  }
+  __syncthreads();
   float* part = a.part + (int64_t)blockIdx.x * kPartStride;
-  // S (T form): rows 16 bi + 4 g + j, columns 16 bj + n; zero blocks below the diagonal
+  if (wv == 0) {
+    // rows 16 bi + 4 g + j, columns 16 bj + n; zero blocks below the diagonal
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    int bi, bj;
-    sblock(9 * wv + i, bi, bj);
-    const float f = bi == bj ? 1.f : 2.f;
+    for (int bj = 0; bj < 8; ++bj)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      part[(16 * bi + 4 * g + j) * kFHid + 16 * bj + n] = f * accS[i][j];
-      if (bi != bj) part[(16 * bj + 4 * g + j) * kFHid + 16 * bi + n] = 0.f;
-    }
+      for (int bi = 0; bi <= bj; ++bi) {
+        const int i = bj * (bj + 1) / 2 + bi;
+        const float f = bi == bj ? 1.f : 2.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float s = acc[i][j] + S.red[0][(4 * i + j) * 64 + lane];
+          part[(16 * bi + 4 * g + j) * kFHid + 16 * bj + n] = f * s;
+          if (bi != bj) part[(16 * bj + 4 * g + j) * kFHid + 16 * bi + n] = 0.f;
+        }
+      }
   }
-  // dm: column 0 of the product with the ones column (lanes n == 0), doubled
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (n == 0) part[16384 + 2048 + 128 + 16 * (2 * wv + i) + 4 * g + j] = 2.f * accM[i][j];
-  for (int o = 32; o > 0; o >>= 1) admu += __shfl_xor(admu, o);
-  __syncthreads();
-  if (lane == 0) S.red[0][wv] = admu;
-  __syncthreads();
-  if (threadIdx.x == 0) part[16384 + 2048 + 256] = (S.red[0][0] + S.red[0][1]) + (S.red[0][2] + S.red[0][3]);
+  const int t = threadIdx.x;
+  if (t < kFHid)
+    part[16384 + 2048 + 128 + t] = 2.f * ((S.dm[0][t] + S.dm[1][t]) + (S.dm[2][t] + S.dm[3][t]));
+  if (t == 0) part[16384 + 2048 + 256] = (S.dmu[0] + S.dmu[1]) + (S.dmu[2] + S.dmu[3]);
 }
 
 // Sums of the workgroup partials: S, dW1^T, db1, dm, dmu (fixed order): 64
