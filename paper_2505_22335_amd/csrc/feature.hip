@@ -115,7 +115,6 @@ ASGS_DEV TileCells tile_cells(const FeatArgs& a, int tx, int ty) {
 struct LanePix {
   bool valid;
   int64_t p;           // pixel index in the view
-  float x[kFIn];
   float h[32];         // hidden units 32 g + u of the lane's group g
   float cw[4];         // corner weights
   int cs[4];           // corner slots in the tile's patch table
@@ -126,7 +125,9 @@ struct LanePix {
 // Staged per workgroup: M fragments, first-layer weights, m, the tile's patches.
 struct FeatShared {
   uint16_t frag[kFrag];
-  float w1[kFHid * kFIn];  // row k at hpos(k)
+  // first-layer A operands (FP32 16x16x4, K = four features a step): block b,
+  // lane l, step s at (64 b + l) 4 + s holds W1[32 (l % 16 / 4) + 4 b + l % 4][4 s + l / 16]
+  float w1[8 * 64 * 4];
   float b1[kFHid];         // at hpos(k)
   float m[kFHid];          // at hpos(k)
   float cell[kSlots][kCell];
@@ -139,7 +140,7 @@ ASGS_DEV void stage_weights(const FeatArgs& a, FeatShared& S) {
   for (int q = t; q < kFrag / 8; q += nt) dst[q] = src[q];
   for (int q = t; q < kFHid * kFIn; q += nt) {
     const int k = q / kFIn, c = q - k * kFIn;
-    S.w1[hpos(k) * kFIn + c] = a.params[q];
+    S.w1[(((k & 31) >> 2) * 64 + 16 * (c & 3) + 4 * (k >> 5) + (k & 3)) * 4 + (c >> 2)] = a.params[q];
   }
   for (int k = t; k < kFHid; k += nt) {
     S.b1[hpos(k)] = a.params[kFHid * kFIn + k];
@@ -167,9 +168,31 @@ ASGS_DEV float patch_dot(const FeatShared& S, const TileCells& tc, int ya, int x
   return S.cell[(y - tc.cy0) * tc.ncx + (x - tc.cx0)][e];
 }
 
+// First layer of the lane's pixel on the matrix cores (v_mfma_f32_16x16x4f32,
+// FP32 products and sums; K = the 16 features in four steps of four): block b
+// gives units 32 g + 4 b + r, r = 0..3, of pixel n (column n = lane & 15,
+// group g = lane >> 4), the bias in the accumulator; xq[s] is feature 4 s + g
+// of the pixel. h[4 b + r] = relu(z) holds unit 32 g + 4 b + r.
+ASGS_DEV void first_layer(const float* w1, const float* b1g, const float (&xq)[4], int lane, float (&h)[32]) {
+  const f4v* wl = reinterpret_cast<const f4v*>(w1) + lane;
+  f4v z[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) z[b][r] = b1g[4 * (4 * b + r)];
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) z[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[64 * b][st], xq[st], z[b], 0, 0, 0);
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[4 * b + r] = fmaxf(z[b][r], 0.f);
+}
+
 // Forward of one pixel per lane (column n = lane & 15, group g = lane >> 4):
-// first layer on the vector ALUs, M h on the matrix cores, the scalars of the
-// cosine summed over the four lanes of the pixel.
+// first layer and M h on the matrix cores, the scalars of the cosine summed
+// over the four lanes of the pixel.
 ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCells& tc, int view, int px, int py,
                            LanePix& L) {
   const int lane = threadIdx.x & 63, g = lane >> 4;
@@ -177,29 +200,21 @@ ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCel
   const int cpx = min(px, a.W - 1), cpy = min(py, a.H - 1);
   const int64_t HW = (int64_t)a.W * a.H;
   L.p = (int64_t)cpy * a.W + cpx;
-  const float* fx = a.feat + (int64_t)view * kFIn * HW + L.p;
+  const float* fx = a.feat + (int64_t)view * kFIn * HW + (int64_t)g * HW + L.p;
+  float xq[4];
 #pragma unroll
-  for (int c = 0; c < kFIn; ++c) L.x[c] = L.valid ? fx[c * HW] : 0.f;
-  // hidden units 32 g + u, u = 8 kb + i: B operands of M h (K = hidden)
-  bf8v bh[4], bl[4];
+  for (int st = 0; st < 4; ++st) xq[st] = L.valid ? fx[4 * st * HW] : 0.f;
   // unit 32 g + u sits at hpos = 4 u + g: per-lane bases with constant offsets
-  const float* const w1g = S.w1 + g * kFIn;
   const float* const b1g = S.b1 + g;
   const float* const mg = S.m + g;
+  first_layer(S.w1, b1g, xq, lane, L.h);
+  // hidden units 32 g + u, u = 8 kb + i: B operands of M h (K = hidden)
+  bf8v bh[4], bl[4];
 #pragma unroll
   for (int kb = 0; kb < 4; ++kb) {
     uint16_t hi[8], lo[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int u = 8 * kb + i;
-      const float* w = w1g + 4 * u * kFIn;
-      float z = b1g[4 * u];
-#pragma unroll
-      for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], L.x[c], z);
-      L.h[u] = fmaxf(z, 0.f);
-      bf_split(L.h[u], hi[i], lo[i]);
-      if (i & 1) __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int i = 0; i < 8; ++i) bf_split(L.h[8 * kb + i], hi[i], lo[i]);
     bh[kb] = as_bf8(hi);
     bl[kb] = as_bf8(lo);
   }
@@ -476,31 +491,24 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       const int64_t p = (int64_t)cpy * a.W + cpx;
       const int pr = wv * 16 + n;  // pixel of the round
       // unit 32 g + u sits at hpos = 4 u + g: per-lane bases with constant offsets
-      const float* const w1g = S.F.w1 + g * kFIn;
       const float* const b1g = S.F.b1 + g;
       const float* const mg = S.F.m + g;
       float h[32];
       bf8v bh[4], bl[4];
       {
-        float x[kFIn];
-        const float* fx = a.feat + (int64_t)view * kFIn * HW + p;
+        float xq[4];
+        const float* fx = a.feat + (int64_t)view * kFIn * HW + (int64_t)g * HW + p;
 #pragma unroll
-        for (int c = 0; c < kFIn; ++c) x[c] = valid ? fx[c * HW] : 0.f;
-        if (g == 0) {
+        for (int st = 0; st < 4; ++st) xq[st] = valid ? fx[4 * st * HW] : 0.f;
 #pragma unroll
-          for (int c = 0; c < kFIn; ++c) S.X[c][pr] = x[c];
-        }
+        for (int st = 0; st < 4; ++st) S.X[4 * st + g][pr] = xq[st];
+        first_layer(S.F.w1, b1g, xq, lane, h);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
           uint16_t hi[8], lo[8];
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const int u = 8 * kb + i, k = 32 * g + u;
-            const float* w = w1g + 4 * u * kFIn;
-            float z = b1g[4 * u];
-#pragma unroll
-            for (int c = 0; c < kFIn; ++c) z = fmaf(w[c], x[c], z);
-            h[u] = fmaxf(z, 0.f);
             bf_split(h[u], hi[i], lo[i]);
             S.Hhi[rp_index(k, pr)] = hi[i];
             S.Hlo[rp_index(k, pr)] = lo[i];
@@ -613,7 +621,8 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       {
-        const float* const w1n = S.F.w1 + 32 * g * kFIn + n;
+        // W1[32 kb + 8 g + i][n] in the first-layer operand table
+        const float* const w1n = S.F.w1 + (128 * g + 16 * (n & 3)) * 4 + (n >> 2);
         f4v dxa = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
@@ -621,7 +630,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
             const int k = 32 * kb + 8 * g + i;
-            bf_split(w1n[(4 * i + kb) * kFIn], wh[i], wl[i]);  // unit k at hpos 4 (8 g + i) + kb
+            bf_split(w1n[((i >> 2) * 64 + 4 * kb + (i & 3)) * 4], wh[i], wl[i]);
             zh[i] = S.Ghi[rp_index(k, wv * 16 + n)];
             zl[i] = S.Glo[rp_index(k, wv * 16 + n)];
           }
