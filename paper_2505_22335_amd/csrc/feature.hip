@@ -470,6 +470,16 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
     for (int e = 0; e < 8; ++e) o[e] = n == 0 ? bf_rne(1.f) : (uint16_t)0;
     ones = as_bf8(o);
   }
+  // A operands of dL/dx = W1^T dL/dz: lane (g, n) supplies W1[32 g + 8 kb + i][n]
+  bf8v dxh[4], dxl[4];
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    uint16_t wh[8], wl[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) bf_split(a.params[(32 * g + 8 * kb + i) * kFIn + n], wh[i], wl[i]);
+    dxh[kb] = as_bf8(wh);
+    dxl[kb] = as_bf8(wl);
+  }
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     const int view = t / a.tiles, lt = t - view * a.tiles;
     const int ty = lt / a.tiles_x, tx = lt - ty * a.tiles_x;
@@ -482,8 +492,7 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       __syncthreads();  // patches staged; the previous round's tables are no longer read
       const int row = round * kBwdWaves + wv;
       // The forward of the lane's pixel and its 32 hidden units again (as in
-      // lane_forward), then dL/dz. M h is formed twice, block by block, so
-      // that no lane holds it for all its units: once for |F^|^2, once for
+      // lane_forward), then dL/dz; M h + m is kept at the lane's units for
       // dL/dh (after the cosine's scalars are known).
       const int px = tx * kFT + n, py = ty * kFT + row;
       const bool valid = px < a.W && py < a.H;
@@ -553,13 +562,15 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
         return d;
       };
       float qp = 0.f, ap = 0.f;
+      float mh[32];  // (M h + m) at the lane's units
 #pragma unroll
       for (int mb = 0; mb < 8; ++mb) {
         const f4v d = mh_block(mb);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int u = 4 * mb + j;
-          qp = fmaf(h[u], d[j] + 2.f * mg[4 * u], qp);
+          mh[u] = d[j] + mg[4 * u];
+          qp = fmaf(h[u], mh[u] + mg[4 * u], qp);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -597,47 +608,34 @@ __global__ void __launch_bounds__(64 * kBwdWaves) k_feat_bwd(FeatArgs a) {
       const float dq = floored ? 0.f : -0.5f * gp * cosv / q;
       if (g == 0 && valid) a.dqpix[(int64_t)view * HW + p] = dq;
       __builtin_amdgcn_sched_barrier(0);
-      // dL/dz at the lane's units into the table (dL/dx follows on the matrix cores)
+      // dL/dz at the lane's units: into the table (dW1, db1 below) and, as
+      // they are, the B operand of dL/dx
+      uint16_t zh[32], zl[32];
 #pragma unroll
       for (int mb = 0; mb < 8; ++mb) {
-        const f4v d = mh_block(mb);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int u = 4 * mb + j, k = 32 * g + u;
-          const float dh = fmaf(al, csum(u), 2.f * dq * (d[j] + mg[4 * u]));
+          const float dh = fmaf(al, csum(u), 2.f * dq * mh[u]);
           const float dz = h[u] > 0.f ? dh : 0.f;
-          uint16_t hi, lo;
-          bf_split(dz, hi, lo);
-          S.Ghi[rp_index(k, pr)] = hi;
-          S.Glo[rp_index(k, pr)] = lo;
+          bf_split(dz, zh[u], zl[u]);
+          S.Ghi[rp_index(k, pr)] = zh[u];
+          S.Glo[rp_index(k, pr)] = zl[u];
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      // dL/dx (channels x the wave's 16 pixels) = W1^T dL/dz, K = hidden units:
-      // A = W1^T split on the fly (channel n, units 32 kb + 8 g .. + 7), B =
-      // the dL/dz table (the same units, pixel n of the wave); lane (n, g)
-      // receives channels 4 g + j of its own pixel
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // dL/dx (channels x the wave's 16 pixels) = W1^T dL/dz, K = the lane
+      // group's own units 32 g + 8 kb .. + 7: A = W1^T (channel n, those
+      // units), B = dL/dz at pixel n; lane (n, g) receives channels 4 g + j
+      // of its own pixel
       {
-        // W1[32 kb + 8 g + i][n] in the first-layer operand table
-        const float* const w1n = S.F.w1 + (128 * g + 16 * (n & 3)) * 4 + (n >> 2);
         f4v dxa = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
-          uint16_t wh[8], wl[8], zh[8], zl[8];
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            const int k = 32 * kb + 8 * g + i;
-            bf_split(w1n[((i >> 2) * 64 + 4 * kb + (i & 3)) * 4], wh[i], wl[i]);
-            zh[i] = S.Ghi[rp_index(k, wv * 16 + n)];
-            zl[i] = S.Glo[rp_index(k, wv * 16 + n)];
-          }
-          const bf8v ah = as_bf8(wh), alo = as_bf8(wl), bh = as_bf8(zh), bl = as_bf8(zl);
-          dxa = mfma_bf(ah, bh, dxa);
-          dxa = mfma_bf(ah, bl, dxa);
-          dxa = mfma_bf(alo, bh, dxa);
+          const bf8v bh = as_bf8(&zh[8 * kb]), bl = as_bf8(&zl[8 * kb]);
+          dxa = mfma_bf(dxh[kb], bh, dxa);
+          dxa = mfma_bf(dxh[kb], bl, dxa);
+          dxa = mfma_bf(dxl[kb], bh, dxa);
         }
         if (valid) {
           float* dfx = a.dfeat + (int64_t)view * kFIn * HW + p;
