@@ -15,11 +15,11 @@
 //   dW1 = sum_c dZ_c F_c^T,  db1 = sum_c dZ_c,
 //   dw2 = sum_p dy_p relu(z_p),  db2 = sum_p dy_p
 // with dy_p = dL_u/dsigma_p * sigmoid(y_p). k_fu_pix handles one 16 x 16
-// pixel tile per workgroup: a first phase, one pixel per thread, forms y_p,
-// sigma, the mask and dy_p; a second phase, one hidden unit (and half of the
-// pixels) per thread, recomputes z_p[u] and accumulates the tile's dZ for the
-// (at most 4 x 4) patches the tile reaches and its dw2 partial. Patch and
-// parameter sums follow in fixed order (deterministic, no atomics).
+// pixel tile per workgroup: the interpolation z = Wbil Z over the (at most
+// 4 x 4) patches the tile reaches and the tile's dZ = Wbil^T G are products
+// on the matrix cores (FP32); y_p, sigma, the mask and dy_p are formed in
+// between, and the tile's dw2 partial alongside. Patch and parameter sums
+// follow in fixed order (deterministic, no atomics).
 #include <math.h>
 
 #include "internal.h"
@@ -35,6 +35,15 @@ constexpr int kZS = kHid + 1; // LDS row of one patch's 128 values (padded)
 constexpr int kGC = 16;       // patches per workgroup of the grid contraction
 constexpr int kGU = 16;       // hidden units per workgroup of the grid contraction
 constexpr int kKC = 64;       // input channels per staged block
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// sum over the four lanes of one column (lanes l, l ^ 16, l ^ 32, l ^ 48)
+ASGS_DEV float col_sum4(float v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
 
 struct TileCells {
   int cy0, ncy, cx0, ncx;
@@ -100,125 +109,225 @@ __global__ void __launch_bounds__(256) k_fu_grid(UncArgs a) {
   if (c0 + pc < plane) a.zg[((int64_t)v * plane + c0 + pc) * kHid + u0 + uu] = acc + a.params[(int64_t)kHid * a.nh + u0 + uu];
 }
 
+// One 16 x 16 tile per workgroup; wave w takes the pixel rows 4 w .. 4 w + 3,
+// one row of 16 pixels at a time, on the matrix cores (v_mfma_f32_16x16x4f32,
+// FP32 products and sums):
+//   z (16 pixels x 16 units) = Wbil (16 pixels x 16 patch slots) Z_slots,
+// A = the bilinear weights (K = slots, four steps of four), B = the staged
+// patch values; lane (g, n) receives pixels 4 g + r of unit 16 b + n. y sums
+// w2 relu(z) over the units (the lanes of a row group). With dy known,
+//   dZ (16 slots x 16 units) += Wbil^T G,  G = dy w2 [z > 0],
+// takes the row's pixels as K: the accumulator rows 4 g + r are directly the
+// B operand of step r, A = the weight of slot n at pixel 4 g + r. The four
+// waves' dZ are added in a fixed order.
 struct PixShared {
-  float z[kSlots][kZS];       // Z of the tile's patches
+  float z[kSlots][kZS];          // Z of the tile's patches (zero past the last)
   float w2[kHid];
-  float cw[kT * kT][4];       // bilinear corner weights of each pixel
-  int cs[kT * kT][4];         // corner slots
-  float dy[kT * kT];          // dL_u/dy per pixel (0 outside the image)
-  float dz[2][kSlots][kZS];   // the tile's dZ, one copy per pixel half
-  float red[2][kHid];
+  float dzw[4][kSlots][kHid];    // each wave's dZ
+  float red[4][kHid];
   double lred[4];
   float bred[4];
 };
 
-__global__ void __launch_bounds__(256) k_fu_pix(UncArgs a) {
+// weight of patch slot sl at a pixel whose corners are (cs, cw)
+ASGS_DEV float slot_weight(const int (&cs)[4], const float (&cw)[4], int sl) {
+  float w = 0.f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) w += cs[c] == sl ? cw[c] : 0.f;
+  return w;
+}
+
+// corners (cs, cw) of pixel column px in a row whose patch rows are r0, r1
+// (slot offsets) with weight wy
+ASGS_DEV void col_corners(const UncArgs& a, const TileCells& tc, int px, int r0, int r1, float wy, int (&cs)[4],
+                          float (&cw)[4]) {
+  int x0, x1;
+  float wx;
+  bilin(px, a.Wp, a.sx, x0, x1, wx);
+  cs[0] = r0 + x0 - tc.cx0;
+  cs[1] = r0 + x1 - tc.cx0;
+  cs[2] = r1 + x0 - tc.cx0;
+  cs[3] = r1 + x1 - tc.cx0;
+  cw[0] = (1.f - wy) * (1.f - wx);
+  cw[1] = (1.f - wy) * wx;
+  cw[2] = wy * (1.f - wx);
+  cw[3] = wy * wx;
+}
+
+template <int kCtrl>
+ASGS_DEV float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), kCtrl, 0xf, 0xf, false));
+}
+// sum over the 16 lanes of a row (rotations by 8 and 4, then within quads);
+// every lane of the row gets the same bits (each step adds the same two
+// partial sums, in either order)
+ASGS_DEV float row_sum16(float v) {
+  v += dpp<0x128>(v);
+  v += dpp<0x124>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0xB1>(v);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_fu_pix(UncArgs a) {
   __shared__ PixShared S;
   const int tx = blockIdx.x, ty = blockIdx.y, v = blockIdx.z;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, g = lane >> 4, n = lane & 15;
   const int64_t HW = (int64_t)a.W * a.H;
   const int plane = a.Hp * a.Wp;
   const TileCells tc = tile_cells(a, tx, ty);
   const int nslots = tc.ncy * tc.ncx;
-  // ---- stage the patches' Z and w2 ----
-  for (int q = t; q < nslots * kHid; q += 256) {
+  // R at the lane's pixel (column 4 g + n % 4) of the wave's four rows,
+  // requested first (clamped into the view; pixels outside it are masked
+  // where used)
+  const int rr = n & 3;
+  float Rq[4];
+  if (a.R) {
+#pragma unroll
+    for (int pb = 0; pb < 4; ++pb) {
+      const int px = min(tx * kT + 4 * g + rr, a.W - 1), py = min(ty * kT + 4 * wv + pb, a.H - 1);
+      Rq[pb] = a.R[v * HW + (int64_t)py * a.W + px];
+    }
+  }
+  // ---- stage the patches' Z (zero past the tile's patches) and w2 ----
+  for (int q = t; q < kSlots * kHid; q += 256) {
     const int sl = q / kHid, u = q - sl * kHid;
     const int cy = tc.cy0 + sl / tc.ncx, cx = tc.cx0 + sl % tc.ncx;
-    S.z[sl][u] = a.zg[((int64_t)v * plane + cy * a.Wp + cx) * kHid + u];
+    S.z[sl][u] = sl < nslots ? a.zg[((int64_t)v * plane + cy * a.Wp + cx) * kHid + u] : 0.f;
   }
   if (t < kHid) S.w2[t] = a.params[(int64_t)kHid * a.nh + kHid + t];
   const float b2 = a.params[(int64_t)kHid * a.nh + 2 * kHid];
-  // ---- phase 1: one pixel per thread ----
-  const int px = tx * kT + (t & (kT - 1)), py = ty * kT + (t >> 4);
-  const bool in = px < a.W && py < a.H;
-  {
-    int x0, x1, y0, y1;
-    float wx, wy;
-    bilin(in ? px : 0, a.Wp, a.sx, x0, x1, wx);
-    bilin(in ? py : 0, a.Hp, a.sy, y0, y1, wy);
-    const int r0 = (y0 - tc.cy0) * tc.ncx, r1 = (y1 - tc.cy0) * tc.ncx;
-    S.cs[t][0] = in ? r0 + x0 - tc.cx0 : 0;
-    S.cs[t][1] = in ? r0 + x1 - tc.cx0 : 0;
-    S.cs[t][2] = in ? r1 + x0 - tc.cx0 : 0;
-    S.cs[t][3] = in ? r1 + x1 - tc.cx0 : 0;
-    S.cw[t][0] = (1.f - wy) * (1.f - wx);
-    S.cw[t][1] = (1.f - wy) * wx;
-    S.cw[t][2] = wy * (1.f - wx);
-    S.cw[t][3] = wy * wx;
-  }
   __syncthreads();
-  float y = b2;
-  {
-    const int s0 = S.cs[t][0], s1 = S.cs[t][1], s2 = S.cs[t][2], s3 = S.cs[t][3];
-    const float w0 = S.cw[t][0], w1 = S.cw[t][1], w2 = S.cw[t][2], w3 = S.cw[t][3];
-#pragma unroll 8
-    for (int u = 0; u < kHid; ++u) {
-      const float z = w0 * S.z[s0][u] + w1 * S.z[s1][u] + w2 * S.z[s2][u] + w3 * S.z[s3][u];
-      y = fmaf(S.w2[u], fmaxf(z, 0.f), y);
+  // B operands of z: slot 4 s + g, unit 16 b + n
+  float zb[4][8], w2n[8];
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) zb[st][b] = S.z[4 * st + g][16 * b + n];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) w2n[b] = S.w2[16 * b + n];
+  const bool grad = a.dzt != nullptr;
+  f4v dz[8];
+  float aw2[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    dz[b] = f4v{0.f, 0.f, 0.f, 0.f};
+    aw2[b] = 0.f;
+  }
+  double lsum = 0.0;
+  float dbs = 0.f;
+#pragma unroll
+  for (int pb = 0; pb < 4; ++pb) {
+    const int py = ty * kT + 4 * wv + pb;
+    int y0, y1;
+    float wy;
+    bilin(py < a.H ? py : 0, a.Hp, a.sy, y0, y1, wy);
+    const int r0 = (y0 - tc.cy0) * tc.ncx, r1 = (y1 - tc.cy0) * tc.ncx;
+    // A of z: the weights of slots 4 s + g at pixel n of the row
+    f4v z[8];
+    {
+      int cs[4];
+      float cw[4];
+      const int pxa = tx * kT + n;
+      col_corners(a, tc, pxa < a.W ? pxa : 0, r0, r1, wy, cs, cw);
+      float wA[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) wA[st] = slot_weight(cs, cw, 4 * st + g);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) z[b] = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) z[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(wA[st], zb[st][b], z[b], 0, 0, 0);
     }
-  }
-  const float sp = fmaxf(y, 0.f) + log1pf(expf(-fabsf(y)));
-  const float sig = a.sigma_min + sp;
-  const int64_t q = v * HW + (int64_t)py * a.W + px;
-  if (in) {
-    if (a.sigma) a.sigma[q] = sig;
-    if (a.dynamic) a.dynamic[q] = 2.f * sig * sig > 1.f ? 1u : 0u;
-  }
-  double l = 0.0;
-  float dy = 0.f;
-  if (a.R && in) {
-    const float R = a.R[q];
-    const double sd = (double)sig;
-    l = (double)R / (2.0 * sd * sd) + (double)a.lam3 * log(sd);
-    // dL_u/dsigma = (-R / sigma^3 + lam3 / sigma) / HW, dsigma/dy = sigmoid(y)
-    const float dsig = (-R / (sig * sig * sig) + a.lam3 / sig) * a.inv_hw;
-    dy = dsig / (1.f + expf(-y));
+    // y at pixels 4 g + r: w2 . relu(z) over the units, summed over the row group's lanes
+    float yr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc = fmaf(w2n[b], fmaxf(z[b][r], 0.f), acc);
+      yr[r] = b2 + row_sum16(acc);
+    }
+    // sigma, the mask, the loss term and dy of the lane's pixel, column
+    // 4 g + n % 4 (four lanes per pixel; lanes n < 4 write)
+    const float y = rr == 0 ? yr[0] : rr == 1 ? yr[1] : rr == 2 ? yr[2] : yr[3];
+    const int px = tx * kT + 4 * g + rr;
+    const bool in = px < a.W && py < a.H;
+    const float sp = fmaxf(y, 0.f) + log1pf(expf(-fabsf(y)));
+    const float sig = a.sigma_min + sp;
+    float dy = 0.f;
+    if (a.R && in) {
+      const float R = Rq[pb];
+      // dL_u/dsigma = (-R / sigma^3 + lam3 / sigma) / HW, dsigma/dy = sigmoid(y)
+      const float dsig = (-R / (sig * sig * sig) + a.lam3 / sig) * a.inv_hw;
+      dy = dsig / (1.f + expf(-y));
+    }
+    if (n < 4 && in) {
+      const int64_t q = v * HW + (int64_t)py * a.W + px;
+      if (a.sigma) a.sigma[q] = sig;
+      if (a.dynamic) a.dynamic[q] = 2.f * sig * sig > 1.f ? 1u : 0u;
+      if (a.R) {
+        const double sd = (double)sig;
+        lsum += (double)Rq[pb] / (2.0 * sd * sd) + (double)a.lam3 * log(sd);
+      }
+    }
+    if (grad) {
+      // dy of pixels 4 g + r in every lane of the quad
+      float dyr[4];
+      dyr[0] = dpp<0x00>(dy);
+      dyr[1] = dpp<0x55>(dy);
+      dyr[2] = dpp<0xAA>(dy);
+      dyr[3] = dpp<0xFF>(dy);
+      // A of dZ, step r: the weight of slot n at pixel 4 g + r
+      float wB[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int cs[4];
+        float cw[4];
+        const int pxr = tx * kT + 4 * g + r;
+        col_corners(a, tc, pxr < a.W ? pxr : 0, r0, r1, wy, cs, cw);
+        wB[r] = slot_weight(cs, cw, n);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const float zz = z[b][r];
+          aw2[b] = fmaf(dyr[r], fmaxf(zz, 0.f), aw2[b]);
+          const float G = zz > 0.f ? dyr[r] * w2n[b] : 0.f;
+          dz[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(wB[r], G, dz[b], 0, 0, 0);
+        }
+      if (n < 4) dbs += dy;
+    }
   }
   if (a.partial) {
-    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o);
-    if ((t & 63) == 0) S.lred[t >> 6] = l;
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+    if (lane == 0) S.lred[wv] = lsum;
   }
-  if (!a.dzt) {
-    if (a.partial) {
-      __syncthreads();
-      if (t == 0)
-        a.partial[(int64_t)v * a.tiles + ty * a.tiles_x + tx] = (S.lred[0] + S.lred[1]) + (S.lred[2] + S.lred[3]);
+  if (grad) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const float s = col_sum4(aw2[b]);
+      if (g == 0) S.red[wv][16 * b + n] = s;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S.dzw[wv][4 * g + r][16 * b + n] = dz[b][r];
     }
-    return;
+    for (int o = 32; o > 0; o >>= 1) dbs += __shfl_xor(dbs, o);
+    if (lane == 0) S.bred[wv] = dbs;
   }
-  S.dy[t] = dy;
-  float db = dy;
-  for (int o = 32; o > 0; o >>= 1) db += __shfl_xor(db, o);
-  if ((t & 63) == 0) S.bred[t >> 6] = db;
-  for (int e = t; e < 2 * kSlots * kZS; e += 256) (&S.dz[0][0][0])[e] = 0.f;
-  __syncthreads();
-  // ---- phase 2: one hidden unit and half of the pixels per thread ----
-  const int u = t & (kHid - 1), ph = t >> 7;
-  const float w2u = S.w2[u];
-  float aw2 = 0.f;
-  for (int p = ph * 128; p < ph * 128 + 128; ++p) {
-    const float d = S.dy[p];  // uniform over the wave
-    if (d == 0.f) continue;
-    const int s0 = S.cs[p][0], s1 = S.cs[p][1], s2 = S.cs[p][2], s3 = S.cs[p][3];
-    const float w0 = S.cw[p][0], w1 = S.cw[p][1], w2 = S.cw[p][2], w3 = S.cw[p][3];
-    const float z = w0 * S.z[s0][u] + w1 * S.z[s1][u] + w2 * S.z[s2][u] + w3 * S.z[s3][u];
-    aw2 = fmaf(d, fmaxf(z, 0.f), aw2);
-    if (z > 0.f) {
-      const float g = d * w2u;
-      S.dz[ph][s0][u] += g * w0;
-      S.dz[ph][s1][u] += g * w1;
-      S.dz[ph][s2][u] += g * w2;
-      S.dz[ph][s3][u] += g * w3;
-    }
-  }
-  S.red[ph][u] = aw2;
   __syncthreads();
   const int64_t tile = (int64_t)v * a.tiles + ty * a.tiles_x + tx;
+  if (!grad) {
+    if (a.partial && t == 0) a.partial[tile] = (S.lred[0] + S.lred[1]) + (S.lred[2] + S.lred[3]);
+    return;
+  }
   for (int e = t; e < nslots * kHid; e += 256) {
     const int sl = e / kHid, uu = e - sl * kHid;
-    a.dzt[(tile * kSlots + sl) * kHid + uu] = S.dz[0][sl][uu] + S.dz[1][sl][uu];
+    a.dzt[(tile * kSlots + sl) * kHid + uu] =
+        (S.dzw[0][sl][uu] + S.dzw[1][sl][uu]) + (S.dzw[2][sl][uu] + S.dzw[3][sl][uu]);
   }
-  if (t < kHid) a.w2t[tile * (kHid + 1) + t] = S.red[0][t] + S.red[1][t];
+  if (t < kHid) a.w2t[tile * (kHid + 1) + t] = (S.red[0][t] + S.red[1][t]) + (S.red[2][t] + S.red[3][t]);
   if (t == 0) {
     a.w2t[tile * (kHid + 1) + kHid] = (S.bred[0] + S.bred[1]) + (S.bred[2] + S.bred[3]);
     if (a.partial) a.partial[tile] = (S.lred[0] + S.lred[1]) + (S.lred[2] + S.lred[3]);
