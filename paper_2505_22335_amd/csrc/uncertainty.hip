@@ -340,21 +340,47 @@ __global__ void __launch_bounds__(kHid) k_fu_cell_reduce(UncArgs a) {
   const int cy = cell / a.Wp, cx = cell - cy * a.Wp;
   // the tile rows and the tile columns that reach the patch (a tile's patch
   // rows depend on its row only, its patch columns on its column only)
-  int ty0 = a.tiles_y, ty1 = -1, tx0 = a.tiles_x, tx1 = -1;
-  for (int ty = 0; ty < a.tiles_y; ++ty) {
-    const TileCells r = tile_cells(a, 0, ty);
-    if (cy >= r.cy0 && cy < r.cy0 + r.ncy) {
-      ty0 = min(ty0, ty);
-      ty1 = ty;
+  // (the first wave: one tile row or column per lane, 64 at a time, then a
+  // ballot; the bounds reach the other threads through LDS)
+  __shared__ int bounds[4];
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    int ty0 = a.tiles_y, ty1 = -1, tx0 = a.tiles_x, tx1 = -1;
+    for (int base = 0; base < a.tiles_y; base += 64) {
+      const int ty = base + lane;
+      bool reach = false;
+      if (ty < a.tiles_y) {
+        const TileCells r = tile_cells(a, 0, ty);
+        reach = cy >= r.cy0 && cy < r.cy0 + r.ncy;
+      }
+      const uint64_t m = __ballot(reach);
+      if (m) {
+        ty0 = min(ty0, base + __builtin_ctzll(m));
+        ty1 = base + 63 - __builtin_clzll(m);
+      }
+    }
+    for (int base = 0; base < a.tiles_x; base += 64) {
+      const int tx = base + lane;
+      bool reach = false;
+      if (tx < a.tiles_x) {
+        const TileCells r = tile_cells(a, tx, 0);
+        reach = cx >= r.cx0 && cx < r.cx0 + r.ncx;
+      }
+      const uint64_t m = __ballot(reach);
+      if (m) {
+        tx0 = min(tx0, base + __builtin_ctzll(m));
+        tx1 = base + 63 - __builtin_clzll(m);
+      }
+    }
+    if (lane == 0) {
+      bounds[0] = ty0;
+      bounds[1] = ty1;
+      bounds[2] = tx0;
+      bounds[3] = tx1;
     }
   }
-  for (int tx = 0; tx < a.tiles_x; ++tx) {
-    const TileCells r = tile_cells(a, tx, 0);
-    if (cx >= r.cx0 && cx < r.cx0 + r.ncx) {
-      tx0 = min(tx0, tx);
-      tx1 = tx;
-    }
-  }
+  __syncthreads();
+  const int ty0 = bounds[0], ty1 = bounds[1], tx0 = bounds[2], tx1 = bounds[3];
   float s = 0.f;
   for (int ty = ty0; ty <= ty1; ++ty) {
     for (int tx = tx0; tx <= tx1; ++tx) {
