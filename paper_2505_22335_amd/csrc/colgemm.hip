@@ -37,19 +37,38 @@ __global__ void __launch_bounds__(256) k_colgemm_part(ColGemm g) {
   float acc[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  // the next block's values are requested before the current block is used
+  constexpr int kDP = kRB * kCT / 256, kFP = kKT * kRB / 256;
+  float dn[kDP], fn[kFP];
+  auto fetch = [&](int64_t rb) {
+#pragma unroll
+    for (int i = 0; i < kDP; ++i) {
+      const int q = t + 256 * i, rr = q / kCT, cc = q - rr * kCT;
+      const int64_t r = rb + rr;
+      dn[i] = r < r1 && c0 + cc < g.ncol ? g.D[r * g.dstride + c0 + cc] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < kFP; ++i) {
+      const int q = t + 256 * i, kk = q / kRB, rr = q - kk * kRB;
+      const int64_t r = rb + rr;
+      fn[i] = r < r1 && k0 + kk < nkt ? fval(g, k0 + kk, r) : 0.f;
+    }
+  };
+  fetch(r0);
   for (int64_t rb = r0; rb < r1; rb += kRB) {
     __syncthreads();
-    for (int q = t; q < kRB * kCT; q += 256) {
-      const int rr = q / kCT, cc = q - rr * kCT;
-      const int64_t r = rb + rr;
-      ds[rr][cc] = r < r1 && c0 + cc < g.ncol ? g.D[r * g.dstride + c0 + cc] : 0.f;
+#pragma unroll
+    for (int i = 0; i < kDP; ++i) {
+      const int q = t + 256 * i;
+      ds[q / kCT][q % kCT] = dn[i];
     }
-    for (int q = t; q < kKT * kRB; q += 256) {
-      const int kk = q / kRB, rr = q - kk * kRB;
-      const int64_t r = rb + rr;
-      fs[kk][rr] = r < r1 && k0 + kk < nkt ? fval(g, k0 + kk, r) : 0.f;
+#pragma unroll
+    for (int i = 0; i < kFP; ++i) {
+      const int q = t + 256 * i;
+      fs[q / kRB][q % kRB] = fn[i];
     }
     __syncthreads();
+    fetch(rb + kRB);  // rows past the chunk read as zero
 #pragma unroll 4
     for (int rr = 0; rr < kRB; ++rr) {
       const float d = ds[rr][t & (kCT - 1)];
@@ -70,8 +89,16 @@ __global__ void __launch_bounds__(256) k_colgemm_reduce(ColGemm g, float* out) {
   const int64_t n = (int64_t)g.ncol * nkt;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
+  // chunk order, sixteen loads in flight
   float s = 0.f;
-  for (int b = 0; b < g.nsplit; ++b) s += g.part[(int64_t)b * n + e];
+  for (int b0 = 0; b0 < g.nsplit; b0 += 16) {
+    float v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = b0 + i < g.nsplit ? g.part[(int64_t)(b0 + i) * n + e] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (b0 + i < g.nsplit) s += v[i];
+  }
   out[e] = s;
 }
 
