@@ -37,6 +37,7 @@ constexpr int kTW = 32, kTH = 16;  // output pixels of one workgroup
 constexpr int kR = 5;              // window radius
 constexpr int kXW = kTW + 2 * kR, kXH = kTH + 2 * kR;
 constexpr int kThreads = 256;      // pixel (tx, ty) and (tx, ty + 8) per thread
+constexpr int kStage = (kXH * kXW + kThreads - 1) / kThreads;  // halo values per thread
 constexpr double kC1 = 0.01 * 0.01, kC2 = 0.03 * 0.03;
 
 __global__ void __launch_bounds__(kThreads) k_map_fwd(MappingArgs a) {
@@ -62,18 +63,35 @@ __global__ void __launch_bounds__(kThreads) k_map_fwd(MappingArgs a) {
   }
   // dL/dS of one channel's SSIM at a pixel of weight 1
   const double gS = -(double)a.lam1 * (1.0 - (double)a.lam) / 3.0 * inv_hw;
-  for (int c = 0; c < 3; ++c) {
+  // a channel's halo tile (zero outside the image), every load of a thread
+  // issued before any store; the next channel's loads are in flight while the
+  // current one is filtered
+  float vx[kStage], vy[kStage];
+  auto fetch = [&](int c) {
     const float* X = a.rgb + ((int64_t)v * 3 + c) * HW;
     const float* Y = a.obs_rgb + ((int64_t)v * 3 + c) * HW;
-    for (int q = t; q < kXH * kXW; q += kThreads) {
-      const int r = q / kXW, j = q - r * kXW;
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int q = t + kThreads * k, r = q / kXW, j = q - r * kXW;
       const int gy = y0 + r - kR, gx = x0 + j - kR;
-      const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      const bool ok = q < kXH * kXW && gy >= 0 && gy < H && gx >= 0 && gx < W;
       const int64_t o = ok ? (int64_t)gy * W + gx : 0;
-      sx[r][j] = ok ? X[o] : 0.f;
-      sy[r][j] = ok ? Y[o] : 0.f;
+      vx[k] = ok ? X[o] : 0.f;
+      vy[k] = ok ? Y[o] : 0.f;
+    }
+  };
+  fetch(0);
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int q = t + kThreads * k;
+      if (q < kXH * kXW) {
+        sx[q / kXW][q % kXW] = vx[k];
+        sy[q / kXW][q % kXW] = vy[k];
+      }
     }
     __syncthreads();
+    fetch(c < 2 ? c + 1 : 2);
     for (int q = t; q < kXH * kTW; q += kThreads) {
       const int r = q / kTW, j = q - r * kTW;
       double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0;
@@ -160,18 +178,32 @@ __global__ void __launch_bounds__(kThreads) k_map_bwd(MappingArgs a) {
   const int t = threadIdx.x;
   const int tx = t & (kTW - 1), ty = t / kTW;
   const float l2c = (float)(2.0 * (double)a.lam1 * (double)a.lam / ((double)HW));
-  for (int c = 0; c < 3; ++c) {
+  // a channel's three halo tiles, loaded as in the forward (next channel in flight)
+  float va[3][kStage];
+  auto fetch = [&](int c) {
     const float* A = a.abc + ((int64_t)v * 9 + 3 * c) * HW;
-    for (int q = t; q < kXH * kXW; q += kThreads) {
-      const int r = q / kXW, j = q - r * kXW;
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int q = t + kThreads * k, r = q / kXW, j = q - r * kXW;
       const int gy = y0 + r - kR, gx = x0 + j - kR;
-      const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      const bool ok = q < kXH * kXW && gy >= 0 && gy < H && gx >= 0 && gx < W;
       const int64_t o = ok ? (int64_t)gy * W + gx : 0;
-      sa[0][r][j] = ok ? A[o] : 0.f;
-      sa[1][r][j] = ok ? A[HW + o] : 0.f;
-      sa[2][r][j] = ok ? A[2 * HW + o] : 0.f;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) va[m][k] = ok ? A[m * HW + o] : 0.f;
+    }
+  };
+  fetch(0);
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int q = t + kThreads * k;
+      if (q < kXH * kXW) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sa[m][q / kXW][q % kXW] = va[m][k];
+      }
     }
     __syncthreads();
+    fetch(c < 2 ? c + 1 : 2);
     for (int q = t; q < kXH * kTW; q += kThreads) {
       const int r = q / kTW, j = q - r * kTW;
       float m0 = 0.f, m1 = 0.f, m2 = 0.f;
