@@ -263,6 +263,8 @@ CtxLayout ctx_layout(int64_t n, int n_views, int total_tiles, int total_pix, int
   L.toff = take((size_t)nv * 4);
   L.bsum = take((size_t)scan_blocks(n, n_views) * 4);
   L.vsum = take((size_t)scan_blocks(n, n_views) * 4);
+  L.bpre = take((size_t)scan_blocks(n, n_views) * 4);
+  L.vpre = take((size_t)scan_blocks(n, n_views) * 4);
   L.vlist = take((size_t)nv * 4);
   L.vcount = take((size_t)n_views * 4);
   L.tcur = take((size_t)total_tiles * 4);

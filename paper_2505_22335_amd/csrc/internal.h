@@ -65,6 +65,7 @@ struct CtxHeader {
 //                      the footprint
 //  ntiles, dkey, toff  per (view, Gaussian): tile count, depth bits, first gradient slot
 //  bsum, vsum          per scan block: tile-count sum, visible count
+//  bpre, vpre          per scan block: exclusive prefixes of bsum and vsum over all blocks
 //  vlist, vcount       per view: its visible Gaussians in index order (region of n), their number
 //  tcur                per tile: intersection count, then the emission cursor
 //  ukey, tkey          per intersection: (depth << 32 | gid) in emission order; merge scratch
@@ -78,7 +79,8 @@ struct CtxHeader {
 //                      transmittance and channels at each segment boundary, and the
 //                      final channels
 struct CtxLayout {
-  size_t hdr, views, geom, chan, rad, rect, ntiles, dkey, toff, bsum, vsum, vlist, vcount, tcur, ukey, tkey, pairgid, pslot,
+  size_t hdr, views, geom, chan, rad, rect, ntiles, dkey, toff, bsum, vsum, bpre, vpre, vlist, vcount, tcur, ukey, tkey,
+      pairgid, pslot,
       ptile, pmask, ranges, binfo, lpart, bslot, sinfo, split, tfinal, ncontrib, gslot, posepart;
   size_t total;
   int64_t nv, cap;

@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
   __shared__ unsigned long long wtot[kTileScanThreads / 64];
   __shared__ uint32_t wbin[kTileScanThreads / 64];
   __shared__ unsigned long long wvis[kTileScanThreads / 64];
+  __shared__ unsigned long long wpb[kTileScanThreads / 64], wpv[kTileScanThreads / 64];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   constexpr int NW = kTileScanThreads / 64;
   const int T = rc.total_tiles;
@@ -99,6 +100,40 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
       // band j: kSplitLen + j kSplitStep < c <= kSplitLen + (j + 1) kSplitStep (the last open)
       const uint32_t j = (c - kSplitLen - 1) / kSplitStep;
       atomicAdd(&scount[find_view(views, rc.n_views, i)][j < kSplitThresholds ? j : kSplitThresholds - 1], 1u);
+    }
+  }
+  // per-block exclusive prefixes for the emission: of the tile-count sums and
+  // of the visible counts, over all blocks (a view's own visible prefix is the
+  // difference to its first block's); thread t takes consecutive blocks
+  {
+    const int64_t nbk = scan_blocks(rc.n, rc.n_views);
+    const int64_t perb = (nbk + kTileScanThreads - 1) / kTileScanThreads;
+    const int64_t b0 = min(nbk, (int64_t)t * perb), b1 = min(nbk, b0 + perb);
+    const uint32_t* bs = ctx_ptr<const uint32_t>(ctx, L.bsum);
+    const uint32_t* vs = ctx_ptr<const uint32_t>(ctx, L.vsum);
+    uint32_t* bp = ctx_ptr<uint32_t>(ctx, L.bpre);
+    uint32_t* vp = ctx_ptr<uint32_t>(ctx, L.vpre);
+    unsigned long long sb = 0, sv = 0;
+    for (int64_t b = b0; b < b1; ++b) {
+      sb += bs[b];
+      sv += vs[b];
+    }
+    const unsigned long long ib = wave_incl_scan(sb, lane), iv = wave_incl_scan(sv, lane);
+    if (lane == 63) {
+      wpb[wv] = ib;
+      wpv[wv] = iv;
+    }
+    __syncthreads();
+    unsigned long long eb = ib - sb, ev = iv - sv;
+    for (int w = 0; w < wv; ++w) {
+      eb += wpb[w];
+      ev += wpv[w];
+    }
+    for (int64_t b = b0; b < b1; ++b) {
+      bp[b] = (uint32_t)eb;
+      vp[b] = (uint32_t)ev;
+      eb += bs[b];
+      ev += vs[b];
     }
   }
   // visible pairs: sum of the per-block counts
@@ -192,26 +227,22 @@ __global__ void __launch_bounds__(kScanThreads) k_dup_emit(RenderConst rc, const
   const ViewDev& V = views[sb.view];
   const uint32_t cnt = sb.valid ? ctx_ptr<const uint32_t>(ctx, L.ntiles)[sb.j] : 0u;
   const short4 r = cnt > 0u ? ctx_ptr<const short4>(ctx, L.rect)[sb.j] : make_short4(1, 0, 1, 0);
-  const uint32_t* bsum = ctx_ptr<const uint32_t>(ctx, L.bsum);
   uint32_t* tcur = ctx_ptr<uint32_t>(ctx, L.tcur);
   unsigned long long* ukey = ctx_ptr<unsigned long long>(ctx, L.ukey);
-  // first gradient slot: sum of the blocks before this one + the prefix in it
-  unsigned long long pre = 0;
-  for (uint32_t bb = t; bb < blockIdx.x; bb += kScanThreads) pre += bsum[bb];
-  for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
+  // first gradient slot: sum of the blocks before this one (the scan's
+  // prefix) + the prefix in it
+  const unsigned long long pre = ctx_ptr<const uint32_t>(ctx, L.bpre)[blockIdx.x];
   const uint32_t incl = wave_incl_scan(cnt, lane);
-  if (lane == 0) wred[wv] = pre;
+  if (lane == 0) wred[wv] = wv == 0 ? pre : 0ull;
   if (lane == 63) wsum[wv] = incl;
   // place in the view's visible list: visible Gaussians of the view's earlier
   // blocks, of the earlier waves, of the earlier lanes
   const int64_t nbx = (rc.n + kScanThreads - 1) / kScanThreads;
-  uint32_t vpre = 0;
-  for (int64_t bb = (int64_t)sb.view * nbx + t; bb < (int64_t)blockIdx.x; bb += kScanThreads)
-    vpre += ctx_ptr<const uint32_t>(ctx, L.vsum)[bb];
-  for (int o = 32; o > 0; o >>= 1) vpre += __shfl_xor(vpre, o);
+  const uint32_t* vpg = ctx_ptr<const uint32_t>(ctx, L.vpre);
+  const uint32_t vpre = vpg[blockIdx.x] - vpg[(int64_t)sb.view * nbx];
   const uint64_t vbits = __ballot(cnt > 0u);
   if (lane == 0) {
-    wvp[wv] = vpre;
+    wvp[wv] = wv == 0 ? vpre : 0u;
     wvc[wv] = (uint32_t)__popcll(vbits);
   }
   const bool small = cnt > 0u && cnt <= (uint32_t)kBoxRect;
