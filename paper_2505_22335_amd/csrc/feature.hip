@@ -8,10 +8,11 @@
 //   |F|^2  = sum_{c,c'} w_c w_c' G_c . G_c'
 // over the four bilinear corners c of the pixel. Q_c, beta_c and the dot
 // products of neighbouring patches are prepared once per patch, M once per
-// call; per pixel the work is the 16 -> 128 first layer (vector ALUs, FP32)
-// and the 128 x 128 product M h on the matrix cores (v_mfma_f32_16x16x32_bf16,
-// both operands split into high and low bfloat16 parts, three products per
-// pair: FP32 sums of products good to ~2^-16 relative).
+// call; per pixel the work is the 16 -> 128 first layer (matrix cores,
+// v_mfma_f32_16x16x4f32: FP32 products and sums) and the 128 x 128 product
+// M h (v_mfma_f32_16x16x32_bf16, both operands split into high and low
+// bfloat16 parts, three products per pair: FP32 sums of products good to
+// ~2^-16 relative).
 //
 // The backward is the same identities differentiated: with g = dL/dcos,
 //   s1 = 1 / (|F||F^|),  dq = -g cos / (2 |F^|^2),
@@ -21,9 +22,10 @@
 //   dL/dQ_c = sum_p g s1 w_c h,  dL/dbeta_c = sum_p g s1 w_c,
 //   dW2 = sum_c G_c dQ_c^T + W2 (S + S^T) + b2 dm^T,
 //   db2 = sum_c dbeta_c G_c + W2 dm + 2 dmu b2.
-// The pixel sums S, dQ and dW1 are matrix products with K = pixels, taken on
-// the matrix cores from per-round LDS tiles of h, dq h, the corner weights,
-// x and dL/dz. Every sum has a fixed order (deterministic).
+// The pixel sums dQ and dW1 are matrix products with K = pixels, taken on
+// the matrix cores from per-round LDS tiles of h, the corner weights, x and
+// dL/dz; S comes from a second pass whose register layout needs no tiles.
+// Every sum has a fixed order (deterministic).
 #include "internal.h"
 
 namespace asgs {
@@ -428,7 +430,7 @@ ASGS_DEV int rp_index(int k, int pxl) { return k * kRP + ((((pxl >> 3) ^ (k & 7)
 struct BwdShared {
   FeatShared F;
   uint16_t Hhi[kFHid * kRP], Hlo[kFHid * kRP];    // h
-  uint16_t Ghi[kFHid * kRP], Glo[kFHid * kRP];    // dq h, then dL/dz
+  uint16_t Ghi[kFHid * kRP], Glo[kFHid * kRP];    // dL/dz
   float X[kFIn][kRP];                             // x
   float Wc[kSlots][kRP];                          // g s1 w_c at each pixel's corner slots
 };
