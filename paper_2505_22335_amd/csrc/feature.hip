@@ -292,8 +292,9 @@ ASGS_DEV void lane_forward(const FeatArgs& a, const FeatShared& S, const TileCel
 // Preparation: M = W2^T W2 and m = W2^T b2 come from the split-K product
 // (colgemm.hip) as gm = [128][129]; here M becomes bfloat16 hi/lo A
 // fragments, and mu = b2 . b2 is summed (one workgroup, fixed order). Per
-// patch (k_feat_cells): Q, beta and the dot products with its right, lower
-// and lower-right neighbours and of its right and lower neighbours.
+// patch (k_feat_cells, 16 patches per workgroup): Q, beta and the dot
+// products with its right, lower and lower-right neighbours and of its right
+// and lower neighbours.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_feat_frag(FeatArgs a, const float* __restrict__ gm, uint16_t* mfrag,
                                                    float* mvec) {
@@ -323,46 +324,119 @@ __global__ void __launch_bounds__(256) k_feat_frag(FeatArgs a, const float* __re
   }
 }
 
-constexpr int kMaxHigh = 1024;
+constexpr int kQC = 16;  // patches per workgroup (the M side of the product)
 
-__global__ void __launch_bounds__(128) k_feat_cells(FeatArgs a, float* cells) {
-  __shared__ float sg[4][kMaxHigh];
-  __shared__ float red[6][2];
-  const int cell = blockIdx.x, view = blockIdx.y;
-  const int gy = cell / a.Wp, gx = cell - gy * a.Wp;
-  const int64_t plane = (int64_t)a.Hp * a.Wp;
+// Per run of 16 consecutive patches (flat index): Q = W2^T G for all 16 on
+// the matrix cores (v_mfma_f32_16x16x4f32, FP32; M = patches, N = units,
+// K = channels four at a time; wave w takes the unit blocks 2 (w % 4),
+// 2 (w % 4) + 1 over one half of the channels, the halves added in a fixed
+// order), so W2 is read once per run; then beta and the neighbour dot
+// products, one patch per lane column and the channels split over the 32
+// lane groups of the workgroup, summed in a fixed order.
+__global__ void __launch_bounds__(512) k_feat_cells(FeatArgs a, float* cells) {
+  __shared__ float qh[kQC][kFHid];
+  __shared__ float red[8][kQC][6];
+  const int c0 = blockIdx.x * kQC, view = blockIdx.y;
+  const int plane = a.Hp * a.Wp;
   const float* G = a.dino + (int64_t)view * a.nh * plane;
   const float* W2 = a.params + kFHid * kFIn + kFHid;
   const float* b2 = W2 + (int64_t)a.nh * kFHid;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, g = lane >> 4, f = lane & 15;
+  const int ub = wv & 3, kh = wv >> 2;
+  const int half = ((a.nh + 63) / 64) * 32;  // channels of the first half (a multiple of 32)
+  f4v q0 = {0.f, 0.f, 0.f, 0.f}, q1 = q0;
+  {
+    // A: channel 4 s + g of patch c0 + f; B: W2 rows 4 s + g, units 32 ub + f (+ 16)
+    const float* Ga = G + min(c0 + f, plane - 1);
+    const float* Wb = W2 + 32 * ub + f;
+    const int cb = kh * half, ce = min(a.nh, cb + half);
+    for (int c = cb + g; c < ce + g; c += 32) {
+      float av[8], b0[8], b1[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int ch = c + 4 * i;
+        const bool ok = ch < ce;
+        av[i] = ok ? Ga[(int64_t)ch * plane] : 0.f;
+        b0[i] = ok ? Wb[(int64_t)ch * kFHid] : 0.f;
+        b1[i] = ok ? Wb[(int64_t)ch * kFHid + 16] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        q0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], b0[i], q0, 0, 0, 0);
+        q1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], b1[i], q1, 0, 0, 0);
+      }
+    }
+    if (kh == 1) {
+      // rows: patches 4 g + r; columns: units 32 ub + f (+ 16)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        qh[4 * g + r][32 * ub + f] = q0[r];
+        qh[4 * g + r][32 * ub + 16 + f] = q1[r];
+      }
+    }
+  }
+  // beta, |G|^2 and the neighbour products of patch c0 + i, i = t % 16,
+  // channels t / 16 + 32 k, four at a time
+  const int i = t & (kQC - 1), cg = t >> 4;
+  const int cell = min(c0 + i, plane - 1);
+  const int gy = cell / a.Wp, gx = cell - gy * a.Wp;
   const bool rx = gx + 1 < a.Wp, dy = gy + 1 < a.Hp;
-  const int nb[4] = {cell, rx ? cell + 1 : -1, dy ? cell + a.Wp : -1, (rx && dy) ? cell + a.Wp + 1 : -1};
-  for (int q = threadIdx.x; q < 4 * a.nh; q += 128) {
-    const int k = q / a.nh, c = q - k * a.nh;
-    sg[k][c] = nb[k] >= 0 ? G[c * plane + nb[k]] : 0.f;
-  }
-  __syncthreads();
-  const int j = threadIdx.x;
-  float qj = 0.f;
-  for (int c = 0; c < a.nh; ++c) qj = fmaf(W2[(int64_t)c * kFHid + j], sg[0][c], qj);
+  const int i1 = rx ? cell + 1 : cell, i2 = dy ? cell + a.Wp : cell, i3 = rx && dy ? cell + a.Wp + 1 : cell;
+  const float f1 = rx ? 1.f : 0.f, f2 = dy ? 1.f : 0.f, f3 = rx && dy ? 1.f : 0.f;
   float p[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int c = j; c < a.nh; c += 128) {
-    const float g0 = sg[0][c], g1 = sg[1][c], g2 = sg[2][c], g3 = sg[3][c];
-    p[0] = fmaf(b2[c], g0, p[0]);
-    p[1] = fmaf(g0, g0, p[1]);
-    p[2] = fmaf(g0, g1, p[2]);
-    p[3] = fmaf(g0, g2, p[3]);
-    p[4] = fmaf(g0, g3, p[4]);
-    p[5] = fmaf(g1, g2, p[5]);
+  for (int c = cg; c < a.nh; c += 128) {
+    float v0[4], v1[4], v2[4], v3[4], vb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int ch = min(c + 32 * k, a.nh - 1);
+      const float* Gc = G + (int64_t)ch * plane;
+      const float m = c + 32 * k < a.nh ? 1.f : 0.f;
+      v0[k] = m * Gc[cell];
+      v1[k] = f1 * Gc[i1];
+      v2[k] = f2 * Gc[i2];
+      v3[k] = f3 * Gc[i3];
+      vb[k] = b2[ch];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      p[0] = fmaf(vb[k], v0[k], p[0]);
+      p[1] = fmaf(v0[k], v0[k], p[1]);
+      p[2] = fmaf(v0[k], v1[k], p[2]);
+      p[3] = fmaf(v0[k], v2[k], p[3]);
+      p[4] = fmaf(v0[k], v3[k], p[4]);
+      p[5] = fmaf(v1[k] * (c + 32 * k < a.nh ? 1.f : 0.f), v2[k], p[5]);
+    }
   }
+  // lanes i, i + 16, i + 32, i + 48 of the wave, then the eight waves
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    for (int o = 32; o > 0; o >>= 1) p[k] += __shfl_xor(p[k], o);
-    if ((j & 63) == 0) red[k][j >> 6] = p[k];
+    p[k] += __shfl_xor(p[k], 16);
+    p[k] += __shfl_xor(p[k], 32);
+  }
+  if (lane < kQC) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[wv][i][k] = p[k];
   }
   __syncthreads();
-  float* out = cells + ((int64_t)view * plane + cell) * kCell;
-  out[j] = qj;
-  if (j < 6) out[kFHid + j] = red[j][0] + red[j][1];
+  if (kh == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cl = c0 + 4 * g + r;
+      if (cl < plane) {
+        float* out = cells + ((int64_t)view * plane + cl) * kCell + 32 * ub + f;
+        out[0] = q0[r] + qh[4 * g + r][32 * ub + f];
+        out[16] = q1[r] + qh[4 * g + r][32 * ub + 16 + f];
+      }
+    }
+  }
+  if (t < kQC * 6) {
+    const int ii = t / 6, k = t - ii * 6;
+    if (c0 + ii < plane) {
+      float sum = 0.f;
+      for (int w = 0; w < 8; ++w) sum += red[w][ii][k];
+      cells[((int64_t)view * plane + c0 + ii) * kCell + kFHid + k] = sum;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1155,7 +1229,7 @@ void launch_prep(const FeatArgs& a, const FeatLayout& L, char* work, hipStream_t
   launch_colgemm(g, gm, s);
   hipLaunchKernelGGL(k_feat_frag, dim3((kFrag / 2 + 255) / 256), dim3(256), 0, s, a, (const float*)gm,
                      reinterpret_cast<uint16_t*>(work + L.mfrag), reinterpret_cast<float*>(work + L.mvec));
-  hipLaunchKernelGGL(k_feat_cells, dim3((unsigned)(a.Hp * a.Wp), (unsigned)a.V), dim3(128), 0, s, a,
+  hipLaunchKernelGGL(k_feat_cells, dim3((unsigned)((a.Hp * a.Wp + kQC - 1) / kQC), (unsigned)a.V), dim3(512), 0, s, a,
                      reinterpret_cast<float*>(work + L.cells));
 }
 }  // namespace
