@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
       atomicAdd(&scount[find_view(views, rc.n_views, i)][j < kSplitThresholds ? j : kSplitThresholds - 1], 1u);
     }
   }
+  unsigned long long vis = 0;
   // per-block exclusive prefixes for the emission: of the tile-count sums and
   // of the visible counts, over all blocks (a view's own visible prefix is the
   // difference to its first block's); thread t takes consecutive blocks
@@ -113,11 +114,16 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
     const uint32_t* vs = ctx_ptr<const uint32_t>(ctx, L.vsum);
     uint32_t* bp = ctx_ptr<uint32_t>(ctx, L.bpre);
     uint32_t* vp = ctx_ptr<uint32_t>(ctx, L.vpre);
+    const int64_t nbx = (rc.n + kScanThreads - 1) / kScanThreads;
     unsigned long long sb = 0, sv = 0;
     for (int64_t b = b0; b < b1; ++b) {
       sb += bs[b];
       sv += vs[b];
+      atomicAdd(&vcnt[b / nbx], vs[b]);  // visible Gaussians per view
     }
+    // visible pairs of the whole batch
+    vis = sv;
+    for (int o = 32; o > 0; o >>= 1) vis += __shfl_xor(vis, o);
     const unsigned long long ib = wave_incl_scan(sb, lane), iv = wave_incl_scan(sv, lane);
     if (lane == 63) {
       wpb[wv] = ib;
@@ -135,18 +141,6 @@ __global__ void __launch_bounds__(kTileScanThreads) k_tile_scan(RenderConst rc, 
       eb += bs[b];
       ev += vs[b];
     }
-  }
-  // visible pairs: sum of the per-block counts
-  unsigned long long vis = 0;
-  {
-    const uint64_t nb = (uint64_t)scan_blocks(rc.n, rc.n_views);
-    const uint32_t* vsum = ctx_ptr<const uint32_t>(ctx, L.vsum);
-    const uint64_t nbx = (uint64_t)((rc.n + kScanThreads - 1) / kScanThreads);
-    for (uint64_t bb = t; bb < nb; bb += kTileScanThreads) {
-      vis += vsum[bb];
-      atomicAdd(&vcnt[bb / nbx], vsum[bb]);  // visible Gaussians per view
-    }
-    for (int o = 32; o > 0; o >>= 1) vis += __shfl_xor(vis, o);
   }
   const unsigned long long incl = wave_incl_scan(mine, lane);
   if (lane == 63) wtot[wv] = incl;
