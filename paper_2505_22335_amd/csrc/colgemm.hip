@@ -5,9 +5,10 @@
 // r) and F_k(r) a strided view of the DINO grid or of a weight matrix, with an
 // optional extra row from a vector (tail) and an optional row of ones (so that
 // out[col][.] also holds sum_r D[r][col]). The rows are cut into nsplit
-// contiguous chunks; each workgroup forms a 64-column x 32-row tile of one
-// chunk's partial product from LDS-staged blocks of D and F, and a second
-// kernel adds the chunks' partials in chunk order (deterministic).
+// contiguous chunks; each workgroup forms a 64-column x 32-k tile of one
+// chunk's partial product from LDS-staged blocks of D and F on the matrix
+// cores (FP32), and a second kernel adds the chunks' partials in chunk order
+// (deterministic).
 #include "internal.h"
 
 namespace asgs {
@@ -17,6 +18,8 @@ namespace {
 constexpr int kCT = 64;   // columns per workgroup
 constexpr int kKT = 32;   // k per workgroup
 constexpr int kRB = 32;   // rows per staged block
+
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 ASGS_DEV float fval(const ColGemm& g, int k, int64_t r) {
   const int64_t v = r / g.rows, c = r - v * g.rows;
@@ -30,13 +33,13 @@ __global__ void __launch_bounds__(256) k_colgemm_part(ColGemm g) {
   __shared__ float fs[kKT][kRB + 1];
   const int t = threadIdx.x;
   const int c0 = blockIdx.x * kCT, k0 = blockIdx.y * kKT, s = blockIdx.z;
-  const int col = c0 + (t & (kCT - 1)), kq = t >> 6;
+  const int lane = t & 63, wv = t >> 6, gq = lane >> 4, f = lane & 15;
   const int nkt = g.nk + (g.tail ? 1 : 0) + (g.ones ? 1 : 0);
   const int64_t R = (int64_t)g.V * g.rows;
   const int64_t r0 = R * s / g.nsplit, r1 = R * (s + 1) / g.nsplit;
-  float acc[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  // wave w: columns 16 w .. + 15 of the tile against both 16-wide k blocks,
+  // on v_mfma_f32_16x16x4f32 (M = columns, N = k, K = four rows a step)
+  f4v acc[2] = {f4v{0.f, 0.f, 0.f, 0.f}, f4v{0.f, 0.f, 0.f, 0.f}};
   // the next block's values are requested before the current block is used
   constexpr int kDP = kRB * kCT / 256, kFP = kKT * kRB / 256;
   float dn[kDP], fn[kFP];
@@ -69,18 +72,23 @@ __global__ void __launch_bounds__(256) k_colgemm_part(ColGemm g) {
     }
     __syncthreads();
     fetch(rb + kRB);  // rows past the chunk read as zero
-#pragma unroll 4
-    for (int rr = 0; rr < kRB; ++rr) {
-      const float d = ds[rr][t & (kCT - 1)];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) acc[i] = fmaf(d, fs[kq * 8 + i][rr], acc[i]);
+    for (int st = 0; st < kRB / 4; ++st) {
+      const float a = ds[4 * st + gq][16 * wv + f];
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+        acc[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, fs[16 * kb + f][4 * st + gq], acc[kb], 0, 0, 0);
     }
   }
-  if (col >= g.ncol) return;
+  // rows: columns c0 + 16 w + 4 (l / 16) + j; columns: k0 + 16 kb + l % 16
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int k = k0 + kq * 8 + i;
-    if (k < nkt) g.part[((int64_t)s * g.ncol + col) * nkt + k] = acc[i];
+  for (int kb = 0; kb < 2; ++kb) {
+    const int k = k0 + 16 * kb + f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + 16 * wv + 4 * gq + j;
+      if (col < g.ncol && k < nkt) g.part[((int64_t)s * g.ncol + col) * nkt + k] = acc[kb][j];
+    }
   }
 }
 
