@@ -112,8 +112,16 @@ __global__ void __launch_bounds__(256) k_colgemm_reduce(ColGemm g, float* out) {
 
 }  // namespace
 
-int colgemm_splits(int64_t rows) {
-  const int64_t s = rows / 48;
+// One chunk per 48 rows (at most 64); products with few tiles take chunks
+// down to 24 rows, up to about 256 workgroups (measured: the Gram matrix
+// gains from the extra chunks, the patch products lose from them).
+int colgemm_splits(int64_t rows, int ncol, int nkt) {
+  const int64_t tiles = (int64_t)((ncol + kCT - 1) / kCT) * ((nkt + kKT - 1) / kKT);
+  int64_t s = rows / 48;
+  if (tiles * s < 256) {
+    const int64_t more = min(rows / 24, 256 / tiles);
+    if (more > s) s = more;
+  }
   return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
 }
 

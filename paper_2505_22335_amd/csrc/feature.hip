@@ -1129,7 +1129,7 @@ ColGemm gram_gemm(const FeatArgs& a) {
   g.tail = W2 + (int64_t)a.nh * kFHid;  // b2: the column m = W2^T b2
   g.V = 1;
   g.rows = a.nh;
-  g.nsplit = colgemm_splits(a.nh);
+  g.nsplit = colgemm_splits(a.nh, kFHid, kFHid + 1);
   return g;
 }
 
@@ -1145,7 +1145,7 @@ ColGemm dq_gemm(const FeatArgs& a, const float* dqc) {
   g.nk = a.nh;
   g.V = a.V;
   g.rows = a.Hp * a.Wp;
-  g.nsplit = colgemm_splits((int64_t)a.V * a.Hp * a.Wp);
+  g.nsplit = colgemm_splits((int64_t)a.V * a.Hp * a.Wp, kDQ, a.nh);
   return g;
 }
 

@@ -212,7 +212,7 @@ struct ColGemm {
   int32_t nsplit;
   float* part;  // work: colgemm_part_floats
 };
-int colgemm_splits(int64_t rows);
+int colgemm_splits(int64_t rows, int ncol, int nkt);
 size_t colgemm_part_floats(const ColGemm& g);
 void launch_colgemm(const ColGemm& g, float* out, hipStream_t s);
 

@@ -450,7 +450,7 @@ ColGemm dw1_gemm(const UncArgs& a) {
   g.ones = 1;
   g.V = a.V;
   g.rows = a.Hp * a.Wp;
-  g.nsplit = colgemm_splits((int64_t)a.V * a.Hp * a.Wp);
+  g.nsplit = colgemm_splits((int64_t)a.V * a.Hp * a.Wp, kHid, a.nh + 1);
   return g;
 }
 
