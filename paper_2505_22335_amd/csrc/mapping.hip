@@ -130,15 +130,17 @@ __global__ void __launch_bounds__(kThreads) k_map_fwd(MappingArgs a) {
       const double sxx = exx - mx * mx, syy = eyy - my * my, sxy = exy - mx * my;
       const double l1 = 2.0 * mx * my + kC1, m1 = mx * mx + my * my + kC1;
       const double l2 = 2.0 * sxy + kC2, m2 = sxx + syy + kC2;
-      const double S = (l1 * l2) / (m1 * m2);
+      // four reciprocals instead of seven divisions
+      const double il1 = 1.0 / l1, im1 = 1.0 / m1, il2 = 1.0 / l2, im2 = 1.0 / m2;
+      const double S = (l1 * l2) * (im1 * im2);
       ssum[i] += S;
       const double g = gS * wgt[i];
-      const double dmx = S * (2.0 * my / l1 - 2.0 * mx / m1 - 2.0 * my / l2 + 2.0 * mx / m2);
+      const double dmx = S * (2.0 * my * il1 - 2.0 * mx * im1 - 2.0 * my * il2 + 2.0 * mx * im2);
       if (a.abc) {
         float* abc = a.abc + ((int64_t)v * 9 + 3 * c) * HW + p[i];
         abc[0] = (float)(g * dmx);
-        abc[HW] = (float)(g * (-S / m2));
-        abc[2 * HW] = (float)(g * (2.0 * S / l2));
+        abc[HW] = (float)(g * (-S * im2));
+        abc[2 * HW] = (float)(g * (2.0 * S * il2));
       }
       const double dc = (double)sx[r + kR][tx + kR] - (double)sy[r + kR][tx + kR];
       col[i] += dc * dc;
