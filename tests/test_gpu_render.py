@@ -247,6 +247,40 @@ def test_multiview_batch_equals_single():
         np.testing.assert_allclose(batch["dpose"][v], one["dpose"][0], rtol=1e-6, atol=1e-9)
 
 
+def test_largest_view_batch_equals_single():
+    """The largest batch one call takes (64 views, uploaded to the device in
+    chunks of 16): the views at the chunk edges give the same images and
+    gradients bitwise as one call per view, the batch's tile lists are
+    self-consistent, and one view more is refused."""
+    nf = 16
+    sc = synth.tiny_scene(64, 300, n_feat=nf, logs_mu=-2.6)
+    base = np.eye(3, 4, dtype=np.float32)
+    cams = [synth.Camera(32, 24, 30.0, 30.0, 15.5, 11.5,
+                         synth.perturb_pose(base, [0.01 * (v % 8), -0.01 * (v // 8), 0.0],
+                                            [0.0, 0.004 * (v % 5), 0.003 * (v % 3)]))
+            for v in range(L.MAX_VIEWS)]
+    log("case largest view batch", len(cams))
+    rng = np.random.default_rng(64)
+    G = dict(rgb=[rng.normal(size=(3, 24, 32)).astype(np.float32) for _ in cams],
+             depth=[rng.normal(size=(24, 32)).astype(np.float32) for _ in cams],
+             alpha=[rng.normal(size=(24, 32)).astype(np.float32) for _ in cams],
+             feat=[rng.normal(size=(nf, 24, 32)).astype(np.float32) for _ in cams])
+    batch = _gpu_render(sc, cams, nf, G=G)
+    check_binning_self_consistent(batch["rc"], "largest view batch")
+    assert np.any(batch["out"]["alpha"][L.MAX_VIEWS - 1] > 0)
+    for v in (0, 15, 16, 17, 47, 48, L.MAX_VIEWS - 1):
+        Gv = {k: G[k][v] for k in G}
+        one = _gpu_render(sc, [cams[v]], nf, G=Gv)
+        for k in ("rgb", "depth", "alpha", "feat"):
+            assert np.array_equal(batch["out"][k][v], one["out"][k][0]), (v, k)
+        for k in ("mean", "scale", "rot", "opacity", "rgb", "feat"):
+            assert np.array_equal(batch["dg"][k][v], one["dg"][k][0]), (v, k)
+        np.testing.assert_allclose(batch["dpose"][v], one["dpose"][0], rtol=1e-6, atol=1e-9)
+    with pytest.raises(L.AsgsError) as ei:
+        P.RenderContext(cams + cams[:1], sc.n, n_feat=nf)
+    assert ei.value.status == L.E_INVALID
+
+
 def test_split_lists_batch_invariant_and_deterministic():
     """Lists long enough for the segmented backward (~300-450 entries over a
     32x32 view), three views in one call vs one call per view: images and
