@@ -58,11 +58,12 @@ def _cams_tiny(nv):
 @pytest.mark.parametrize("k,nf,nv,A,in_dim", [(10, 16, 1, 77, 35), (3, 16, 2, 77, 35), (7, 0, 3, 77, 35),
                                                (16, 16, 2, 77, 35), (1, 16, 1, 77, 35), (10, 16, 2, 5, 35),
                                                (10, 16, 2, 77, 36), (10, 16, 3, 77, 38), (4, 0, 2, 40, 38),
-                                               (16, 16, 1, 33, 38)])
+                                               (16, 16, 1, 33, 38), (10, 16, 64, 77, 38)])
 def test_decode_forward_backward(k, nf, nv, A, in_dim):
     """FP32 decode and its backward, including the scene-variant inputs
     (distance, and distance plus temporal embedding, at distinct frame times
-    per view: the temporal weights' gradient sums over the views)."""
+    per view: the temporal weights' gradient sums over the views), up to the
+    largest view batch a call takes (64)."""
     sc = synth.tiny_anchor_scene(50 + k, A, k=k, n_feat=nf, in_dim=in_dim)
     cams = _cams_tiny(nv)
     log("case decode", k, nf, nv, A, in_dim)
