@@ -90,11 +90,12 @@ def _run(V, H, W, Hp, Wp, nh, seed, backward=True):
 
 
 @pytest.mark.parametrize("V,H,W,Hp,Wp,nh", [(1, 37, 53, 3, 4, 48), (2, 64, 80, 5, 6, 384), (1, 16, 16, 1, 1, 40),
-                                             (1, 40, 130, 3, 9, 17), (2, 256, 320, 17, 23, 64)])
+                                             (1, 40, 130, 3, 9, 17), (2, 256, 320, 17, 23, 64),
+                                             (64, 16, 16, 1, 1, 40)])
 def test_feature_lift_matches_oracle(V, H, W, Hp, Wp, nh):
     """Ragged tiles, two views, a single patch, a wide strip with an odd
-    channel count, and more tiles than the backward's workgroups (each
-    walks several)."""
+    channel count, more tiles than the backward's workgroups (each walks
+    several), and the largest view batch a call takes (64 views)."""
     _run(V, H, W, Hp, Wp, nh, seed=10 + H + W)
 
 

@@ -46,7 +46,7 @@ def _run(m, use_cos=True, use_dyn=True, weights=None, **kw):
 
 
 @pytest.mark.parametrize("V,H,W", [(1, 37, 53), (2, 48, 64), (1, 16, 32), (1, 480, 640), (1, 1, 1), (1, 3, 12),
-                                   (1, 40, 7)])
+                                   (1, 40, 7), (64, 4, 6)])
 def test_mapping_loss_matches_oracle(V, H, W):
     """Ragged tiles (53 x 37 against 32 x 16), several views, the full frame,
     and images smaller than the 11 x 11 window (zero padding everywhere)."""

@@ -57,7 +57,8 @@ def _compare(g, ref, label):
         assert r["band"].sum() <= 1e-4 * r["band"].size + 2
 
 
-@pytest.mark.parametrize("V,H,W", [(1, 53, 75), (3, 48, 64), (1, 480, 640), (2, 1, 1), (1, 2, 3), (1, 5, 130)])
+@pytest.mark.parametrize("V,H,W", [(1, 53, 75), (3, 48, 64), (1, 480, 640), (2, 1, 1), (1, 2, 3), (1, 5, 130),
+                                   (64, 5, 7)])
 def test_residual_matches_oracle(V, H, W):
     """Ragged tiles (75 x 53 against 64 x 4 tiles), several views, the full
     640x480 frame, and degenerate images where the 3x3 box has 1 to 6

@@ -32,10 +32,12 @@ def _pack(m):
 
 
 @pytest.mark.parametrize("V,H,W,gh,gw,nh", [(1, 37, 53, 3, 4, 48), (2, 64, 80, 5, 6, 384), (1, 16, 16, 1, 1, 16),
-                                            (1, 40, 130, 3, 9, 32), (1, 480, 640, 34, 46, 384)])
+                                            (1, 40, 130, 3, 9, 32), (1, 480, 640, 34, 46, 384),
+                                            (64, 16, 16, 1, 1, 16)])
 def test_uncertainty_matches_oracle(V, H, W, gh, gw, nh):
     """Ragged tiles, several views, one patch, a grid near the finest allowed,
-    and the full frame with the 34 x 46 DINO grid."""
+    the full frame with the 34 x 46 DINO grid, and 64 views (the most a
+    call takes)."""
     log("case uncertainty", V, H, W, gh, gw, nh)
     m = synth.uncertainty_inputs(700 + V * H + W, V, H, W, gh, gw, nh)
     u = UncertaintyMLP(V, W, H, nh, gh, gw)
